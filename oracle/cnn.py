@@ -1,0 +1,433 @@
+"""FP64 CPU oracle of the encoder-solver network with the implicit layer, its
+analytic backward pass, the MSE loss and Adam.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/helmholtz.py``): the GPU library never
+imports this package.
+
+Feature maps are float64 arrays of shape (batch, channels, rows, cols).
+Readings of the paper used here:
+* Architecture (Sec. 4.1, Sec. 5.3) with 3x3 convolutions and ReLU in place of
+  the inverted-bottleneck/BatchNorm/softplus blocks.  Each level: a strided
+  (linear) convolution, the encoder features added, then two conv+ReLU
+  modules; four solver levels; the coarsest keeps stride 1 below n = 512
+  (Sec. 5.3); up modules are a strided transposed convolution, the same-level
+  down features added (sum skip, Sec. 4.4), then two conv+ReLU modules; a
+  linear 3x3 projection to 2 channels (real, imaginary) at n/2 and the
+  multigrid's bilinear prolongation back to n (Sec. 5.3, non-learned bilinear
+  upsampling).
+* Implicit layer (Sec. 4.2, eqs. 16-17): the 64 real coarsest channels are
+  paired (2c, 2c+1) into 32 complex channels, each convolved with the cropped
+  Green's function of its own learned complex 3x3 kernel K_c.  The Green's
+  function uses conj(F(K))/(|F(K)|^2 + eps) (the least-squares form) on an
+  N_G x N_G grid, N_G = next power of two >= 3 * (2 n_c), with the point source
+  at (N_G/2, N_G/2); the crop keeps offsets [-n_c, n_c)^2.
+* Residual scaling: the network sees r_hat = h^2 r / s with s = rms(h^2 r) and
+  the preconditioner returns s * Net(r_hat).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import helmholtz as H
+
+EPS_GREEN = 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Convolutions (3x3, zero padding 1)
+# ---------------------------------------------------------------------------
+
+def conv2d(x, w, b, stride=1):
+    """out[b,o,I,J] = bias[o] + sum_{c,a,e} w[o,c,a,e] x[b,c, s*I+a-1, s*J+e-1]."""
+    B, C, Hh, W = x.shape
+    Ho, Wo = Hh // stride, W // stride
+    xp = np.zeros((B, C, Hh + 2, W + 2))
+    xp[:, :, 1:-1, 1:-1] = x
+    out = np.zeros((B, w.shape[0], Ho, Wo))
+    for a in range(3):
+        for e in range(3):
+            patch = xp[:, :, a:a + stride * Ho:stride, e:e + stride * Wo:stride]
+            out += np.einsum("oc,bchw->bohw", w[:, :, a, e], patch)
+    return out + b[None, :, None, None]
+
+
+def conv2d_backward(x, w, gout, stride=1):
+    """Gradients (gx, gw, gb) of conv2d for the upstream gradient gout."""
+    B, C, Hh, W = x.shape
+    Ho, Wo = gout.shape[2], gout.shape[3]
+    xp = np.zeros((B, C, Hh + 2, W + 2))
+    xp[:, :, 1:-1, 1:-1] = x
+    gxp = np.zeros_like(xp)
+    gw = np.zeros_like(w)
+    for a in range(3):
+        for e in range(3):
+            patch = xp[:, :, a:a + stride * Ho:stride, e:e + stride * Wo:stride]
+            gw[:, :, a, e] = np.einsum("bohw,bchw->oc", gout, patch)
+            gxp[:, :, a:a + stride * Ho:stride, e:e + stride * Wo:stride] += np.einsum(
+                "oc,bohw->bchw", w[:, :, a, e], gout)
+    return gxp[:, :, 1:-1, 1:-1].copy(), gw, gout.sum(axis=(0, 2, 3))
+
+
+def conv_transpose2d(x, w, b, stride=2):
+    """Transposed 3x3 convolution (padding 1, output = stride * input size);
+    w has shape (cin, cout, 3, 3): out[b,o, s*I+a-1, s*J+e-1] += w[c,o,a,e] x[b,c,I,J]."""
+    B, C, Hh, W = x.shape
+    Ho, Wo = stride * Hh, stride * W
+    op = np.zeros((B, w.shape[1], Ho + 2, Wo + 2))
+    for a in range(3):
+        for e in range(3):
+            op[:, :, a:a + stride * Hh:stride, e:e + stride * W:stride] += np.einsum(
+                "co,bchw->bohw", w[:, :, a, e], x)
+    return op[:, :, 1:Ho + 1, 1:Wo + 1] + b[None, :, None, None]
+
+
+def conv_transpose2d_backward(x, w, gout, stride=2):
+    B, C, Hh, W = x.shape
+    Ho, Wo = gout.shape[2], gout.shape[3]
+    gp = np.zeros((B, gout.shape[1], Ho + 2, Wo + 2))
+    gp[:, :, 1:Ho + 1, 1:Wo + 1] = gout
+    gx = np.zeros_like(x)
+    gw = np.zeros_like(w)
+    for a in range(3):
+        for e in range(3):
+            sl = gp[:, :, a:a + stride * Hh:stride, e:e + stride * W:stride]
+            gx += np.einsum("co,bohw->bchw", w[:, :, a, e], sl)
+            gw[:, :, a, e] = np.einsum("bchw,bohw->co", x, sl)
+    return gx, gw, gout.sum(axis=(0, 2, 3))
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Implicit layer (Sec. 4.2, eqs. 16-17)
+# ---------------------------------------------------------------------------
+
+def green_grid_size(nc: int) -> int:
+    return 1 << int(math.ceil(math.log2(3 * 2 * nc)))
+
+
+def green_hat(K: np.ndarray, nc: int, eps: float = EPS_GREEN):
+    """Fourier transform (size 2 n_c) of the cropped Green's function of each
+    complex 3x3 kernel K[c] (eq. 17).  Returns (Ghat [nk, 2nc, 2nc], aux)."""
+    N = green_grid_size(nc)
+    nk = K.shape[0]
+    Kpad = np.zeros((nk, N, N), dtype=np.complex128)
+    for a in range(3):
+        for e in range(3):
+            Kpad[:, (a - 1) % N, (e - 1) % N] = K[:, a, e]
+    Khat = np.fft.fft2(Kpad)
+    f = np.conj(Khat) / (np.abs(Khat) ** 2 + eps)
+    delta = np.zeros((N, N))
+    delta[N // 2, N // 2] = 1.0
+    dhat = np.fft.fft2(delta)
+    G = np.fft.ifft2(f * dhat[None])
+    Gc = G[:, N // 2 - nc:N // 2 + nc, N // 2 - nc:N // 2 + nc]
+    Ghat = np.fft.fft2(np.fft.ifftshift(Gc, axes=(1, 2)))
+    return Ghat, dict(N=N, Khat=Khat, dhat=dhat, eps=eps, Gc=Gc)
+
+
+def green_hat_backward(K, nc, gGhat, aux):
+    """dL/dK (complex, d/dRe + i d/dIm) from dL/dGhat in the same convention."""
+    N, Khat, dhat, eps = aux["N"], aux["Khat"], aux["dhat"], aux["eps"]
+    m = 2 * nc
+    gGs = (m * m) * np.fft.ifft2(gGhat)
+    gGc = np.fft.fftshift(gGs, axes=(1, 2))
+    gG = np.zeros((K.shape[0], N, N), dtype=np.complex128)
+    gG[:, N // 2 - nc:N // 2 + nc, N // 2 - nc:N // 2 + nc] = gGc
+    gfd = np.fft.fft2(gG) / (N * N)
+    gf = np.conj(dhat)[None] * gfd
+    a, bb = Khat.real, Khat.imag
+    d = a * a + bb * bb + eps
+    dfr_da = 1.0 / d - 2 * a * a / d ** 2
+    dfr_db = -2 * a * bb / d ** 2
+    dfi_da = 2 * a * bb / d ** 2
+    dfi_db = -1.0 / d + 2 * bb * bb / d ** 2
+    ga = gf.real * dfr_da + gf.imag * dfi_da
+    gb = gf.real * dfr_db + gf.imag * dfi_db
+    gKhat = ga + 1j * gb
+    gKpad = (N * N) * np.fft.ifft2(gKhat)
+    gK = np.zeros_like(K)
+    for ai in range(3):
+        for e in range(3):
+            gK[:, ai, e] = gKpad[:, (ai - 1) % N, (e - 1) % N]
+    return gK
+
+
+def pair(x):
+    """(B, 2k, h, w) real -> (B, k, h, w) complex, channel 2c + i * channel 2c+1."""
+    return x[:, 0::2] + 1j * x[:, 1::2]
+
+
+def unpair(z):
+    B, k, hh, ww = z.shape
+    out = np.zeros((B, 2 * k, hh, ww))
+    out[:, 0::2] = z.real
+    out[:, 1::2] = z.imag
+    return out
+
+
+def implicit_apply(Ghat, z):
+    """y = crop(IFFT(Ghat * FFT(zero-pad(z)))): linear convolution of each complex
+    channel with its cropped Green's function (eq. 16)."""
+    B, k, nc, _ = z.shape
+    zp = np.zeros((B, k, 2 * nc, 2 * nc), dtype=np.complex128)
+    zp[:, :, :nc, :nc] = z
+    Z = np.fft.fft2(zp)
+    y = np.fft.ifft2(Ghat[None] * Z)[:, :, :nc, :nc]
+    return y, Z
+
+
+def implicit_backward(Ghat, Z, gy):
+    """(gz, gGhat) for y = implicit_apply(Ghat, z) and upstream gradient gy."""
+    B, k, nc, _ = gy.shape
+    m = 2 * nc
+    gyp = np.zeros((B, k, m, m), dtype=np.complex128)
+    gyp[:, :, :nc, :nc] = gy
+    gY = np.fft.fft2(gyp) / (m * m)
+    gZ = np.conj(Ghat)[None] * gY
+    gGhat = np.sum(np.conj(Z) * gY, axis=0)
+    gz = (m * m) * np.fft.ifft2(gZ)[:, :, :nc, :nc]
+    return gz, gGhat
+
+
+def implicit_direct(Gc, z):
+    """Brute-force linear convolution y[i] = sum_j Gc[i - j] z[j] (Gc indexed by
+    offset + n_c), used only to pin the FFT route on small maps."""
+    B, k, nc, _ = z.shape
+    y = np.zeros_like(z, dtype=np.complex128)
+    for i1 in range(nc):
+        for i2 in range(nc):
+            for j1 in range(nc):
+                for j2 in range(nc):
+                    y[:, :, i1, i2] += Gc[None, :, i1 - j1 + nc, i2 - j2 + nc] * z[:, :, j1, j2]
+    return y
+
+
+# ---------------------------------------------------------------------------
+# Network
+# ---------------------------------------------------------------------------
+
+def coarse_stride(n: int) -> int:
+    """The coarsest down/up pair keeps the map size when n < 512 (Sec. 5.3)."""
+    return 2 if n >= 512 else 1
+
+
+def coarsest_size(n: int) -> int:
+    return n // 16 if n >= 512 else n // 8
+
+
+def kappa_features(k2w2: np.ndarray, gamma: np.ndarray, h: float) -> np.ndarray:
+    """Encoder input: (omega h)^2 kappa^2 and (omega h)^2 kappa^2 gamma, shape (1, 2, n, n)."""
+    m = k2w2 * h * h
+    return np.stack([m, m * gamma])[None]
+
+
+class Net:
+    """Encoder-solver network with its FP64 parameters ``p`` (see inputs.net_layers)."""
+
+    def __init__(self, params: dict[str, np.ndarray]):
+        self.p = {k: np.array(v, copy=True) for k, v in params.items()}
+
+    # ---- encoder --------------------------------------------------------
+    def encode(self, kin):
+        """kin (B, 2, n, n) -> (E1, E2, E3) and a cache for the backward pass."""
+        p = self.p
+        c = {}
+        acts = []
+        x = kin
+        for lvl in (1, 2, 3):
+            pre = f"enc{lvl}"
+            h0 = conv2d(x, p[pre + "_d.w"], p[pre + "_d.b"], 2)
+            h1p = conv2d(h0, p[pre + "_c1.w"], p[pre + "_c1.b"])
+            h1 = relu(h1p)
+            h2p = conv2d(h1, p[pre + "_c2.w"], p[pre + "_c2.b"])
+            h2 = relu(h2p)
+            c[lvl] = (x, h0, h1p, h1, h2p)
+            acts.append(h2)
+            x = h2
+        return tuple(acts), c
+
+    def encode_backward(self, cache, gE):
+        p = self.p
+        g = {}
+        gx_next = None
+        for lvl in (3, 2, 1):
+            pre = f"enc{lvl}"
+            x, h0, h1p, h1, h2p = cache[lvl]
+            gh2 = gE[lvl - 1] + (gx_next if gx_next is not None else 0.0)
+            gh2p = gh2 * (h2p > 0)
+            gh1, g[pre + "_c2.w"], g[pre + "_c2.b"] = conv2d_backward(h1, p[pre + "_c2.w"], gh2p)
+            gh1p = gh1 * (h1p > 0)
+            gh0, g[pre + "_c1.w"], g[pre + "_c1.b"] = conv2d_backward(h0, p[pre + "_c1.w"], gh1p)
+            gx, g[pre + "_d.w"], g[pre + "_d.b"] = conv2d_backward(x, p[pre + "_d.w"], gh0, 2)
+            gx_next = gx
+        return g
+
+    # ---- solver ---------------------------------------------------------
+    def solve(self, rin, enc, Ghat):
+        """rin (B, 2, n, n) real input, enc = (E1, E2, E3) each (B or 1, C, ., .),
+        Ghat from green_hat.  Returns (out (B, 2, n, n), cache)."""
+        p = self.p
+        n = rin.shape[2]
+        s4 = coarse_stride(n)
+        c = {"rin": rin}
+        x = rin
+        downs = []
+        for lvl in (1, 2, 3, 4):
+            pre = f"s{lvl}"
+            st = 2 if lvl < 4 else s4
+            h0 = conv2d(x, p[pre + "_d.w"], p[pre + "_d.b"], st)
+            if lvl < 4:
+                h0 = h0 + enc[lvl - 1]
+            h1p = conv2d(h0, p[pre + "_c1.w"], p[pre + "_c1.b"])
+            h1 = relu(h1p)
+            h2p = conv2d(h1, p[pre + "_c2.w"], p[pre + "_c2.b"])
+            h2 = relu(h2p)
+            c[pre] = (x, st, h0, h1p, h1, h2p)
+            downs.append(h2)
+            x = h2
+        z = pair(x)
+        y, Z = implicit_apply(Ghat, z)
+        c["imp"] = (Z,)
+        x = unpair(y)
+        for lvl, skip in ((3, downs[2]), (2, downs[1]), (1, downs[0])):
+            pre = f"u{lvl}"
+            st = s4 if lvl == 3 else 2
+            h0 = conv_transpose2d(x, p[pre + "_t.w"], p[pre + "_t.b"], st) + skip
+            h1p = conv2d(h0, p[pre + "_c1.w"], p[pre + "_c1.b"])
+            h1 = relu(h1p)
+            h2p = conv2d(h1, p[pre + "_c2.w"], p[pre + "_c2.b"])
+            h2 = relu(h2p)
+            c[pre] = (x, st, h0, h1p, h1, h2p)
+            x = h2
+        o = conv2d(x, p["out.w"], p["out.b"])
+        c["out"] = x
+        up = np.stack([np.stack([H.prolong(o[b, ch]) for ch in range(2)]) for b in range(o.shape[0])])
+        return up, c
+
+    def solve_backward(self, cache, gup, Ghat):
+        """Gradients of the solver's parameters, of Ghat and of the encodings."""
+        p = self.p
+        g = {}
+        B = gup.shape[0]
+        # prolongation = 4 R^T, so its adjoint is 4 R
+        go = np.stack([np.stack([4.0 * H.restrict_fw(gup[b, ch]) for ch in range(2)]) for b in range(B)])
+        gx, g["out.w"], g["out.b"] = conv2d_backward(cache["out"], p["out.w"], go)
+        gskip = {}
+        for lvl in (1, 2, 3):
+            pre = f"u{lvl}"
+            x, st, h0, h1p, h1, h2p = cache[pre]
+            gh2p = gx * (h2p > 0)
+            gh1, g[pre + "_c2.w"], g[pre + "_c2.b"] = conv2d_backward(h1, p[pre + "_c2.w"], gh2p)
+            gh1p = gh1 * (h1p > 0)
+            gh0, g[pre + "_c1.w"], g[pre + "_c1.b"] = conv2d_backward(h0, p[pre + "_c1.w"], gh1p)
+            gskip[lvl] = gh0
+            gx, g[pre + "_t.w"], g[pre + "_t.b"] = conv_transpose2d_backward(x, p[pre + "_t.w"], gh0, st)
+        (Z,) = cache["imp"]
+        gz, gGhat = implicit_backward(Ghat, Z, pair(gx))
+        gx = unpair(gz)
+        gE = [None, None, None]
+        for lvl in (4, 3, 2, 1):
+            pre = f"s{lvl}"
+            x, st, h0, h1p, h1, h2p = cache[pre]
+            if lvl < 4:
+                gx = gx + gskip[lvl]
+            gh2p = gx * (h2p > 0)
+            gh1, g[pre + "_c2.w"], g[pre + "_c2.b"] = conv2d_backward(h1, p[pre + "_c2.w"], gh2p)
+            gh1p = gh1 * (h1p > 0)
+            gh0, g[pre + "_c1.w"], g[pre + "_c1.b"] = conv2d_backward(h0, p[pre + "_c1.w"], gh1p)
+            if lvl < 4:
+                gE[lvl - 1] = gh0
+            gx, g[pre + "_d.w"], g[pre + "_d.b"] = conv2d_backward(x, p[pre + "_d.w"], gh0, st)
+        return g, gGhat, gE
+
+    # ---- whole network ----------------------------------------------------
+    def forward(self, rin, kin):
+        """Encoder + solver on a batch (each sample with its own kappa features)."""
+        n = rin.shape[2]
+        nc = coarsest_size(n)
+        Ghat, gaux = green_hat(self.p["implicit_K"], nc)
+        enc, ecache = self.encode(kin)
+        out, scache = self.solve(rin, enc, Ghat)
+        return out, (Ghat, gaux, ecache, scache, nc)
+
+    def backward(self, cache, gout):
+        Ghat, gaux, ecache, scache, nc = cache
+        g, gGhat, gE = self.solve_backward(scache, gout, Ghat)
+        g.update(self.encode_backward(ecache, gE))
+        g["implicit_K"] = green_hat_backward(self.p["implicit_K"], nc, gGhat, gaux)
+        return g
+
+
+def to_channels(z: np.ndarray) -> np.ndarray:
+    """complex (B, n, n) -> real (B, 2, n, n)."""
+    return np.stack([z.real, z.imag], axis=1)
+
+
+def from_channels(x: np.ndarray) -> np.ndarray:
+    return x[:, 0] + 1j * x[:, 1]
+
+
+def residual_scale(r: np.ndarray, h: float) -> np.ndarray:
+    """s = rms(h^2 r) per sample, r complex (B, n, n)."""
+    return np.sqrt(np.mean(np.abs(h * h * r) ** 2, axis=(1, 2)))
+
+
+def mse_loss(out, target):
+    """Eq. 19: (1/m) sum_i ||out_i - target_i||^2 over real and imaginary channels."""
+    B = out.shape[0]
+    d = out - target
+    return float(np.sum(d * d) / B), 2.0 * d / B
+
+
+def preconditioner_net(net: Net, r: np.ndarray, kin: np.ndarray, h: float) -> np.ndarray:
+    """e = s * Net(h^2 r / s), s = rms(h^2 r): the network part of the preconditioner."""
+    s = residual_scale(r, h)
+    rin = to_channels(h * h * r / s[:, None, None])
+    out, _ = net.forward(rin, kin)
+    return s[:, None, None] * from_channels(out)
+
+
+# ---------------------------------------------------------------------------
+# Adam (Kingma & Ba; defaults as in Sec. 5.3)
+# ---------------------------------------------------------------------------
+
+class Adam:
+    def __init__(self, params, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.t = 0
+        self.m = {k: np.zeros_like(v) for k, v in params.items()}
+        self.v = {k: np.zeros(np.shape(v)) if not np.iscomplexobj(v) else np.zeros_like(v)
+                  for k, v in params.items()}
+
+    def step(self, params, grads):
+        """Complex parameters are updated as pairs of real parameters."""
+        self.t += 1
+        for k, g in grads.items():
+            if np.iscomplexobj(params[k]):
+                for part in ("real", "imag"):
+                    gp = getattr(g, part)
+                    mp = self.b1 * getattr(self.m[k], part) + (1 - self.b1) * gp
+                    vp = self.b2 * getattr(self.v[k], part) + (1 - self.b2) * gp * gp
+                    mh = mp / (1 - self.b1 ** self.t)
+                    vh = vp / (1 - self.b2 ** self.t)
+                    upd = self.lr * mh / (np.sqrt(vh) + self.eps)
+                    if part == "real":
+                        self.m[k] = mp + 1j * self.m[k].imag
+                        self.v[k] = vp + 1j * self.v[k].imag
+                        params[k] = (params[k].real - upd) + 1j * params[k].imag
+                    else:
+                        self.m[k] = self.m[k].real + 1j * mp
+                        self.v[k] = self.v[k].real + 1j * vp
+                        params[k] = params[k].real + 1j * (params[k].imag - upd)
+            else:
+                self.m[k] = self.b1 * self.m[k] + (1 - self.b1) * g
+                self.v[k] = self.b2 * self.v[k] + (1 - self.b2) * g * g
+                mh = self.m[k] / (1 - self.b1 ** self.t)
+                vh = self.v[k] / (1 - self.b2 ** self.t)
+                params[k] = params[k] - self.lr * mh / (np.sqrt(vh) + self.eps)
+        return params

@@ -1,0 +1,61 @@
+"""FP64 CPU oracle of the preconditioner composition, the two-phase solve and the
+method-generated training data.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/helmholtz.py``).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import cnn as C
+from . import helmholtz as H
+
+
+class NetPrecond:
+    """Network part of the preconditioner for one slowness model: the encoder is
+    applied once and its features reused for every application (Sec. 4.1)."""
+
+    def __init__(self, net: C.Net, prob: H.Problem):
+        self.net, self.prob = net, prob
+        self.h = prob.h
+        kin = C.kappa_features(prob.k2w2, prob.gamma, prob.h)
+        self.enc, _ = net.encode(kin)
+        self.nc = C.coarsest_size(prob.n)
+        self.Ghat, _ = C.green_hat(net.p["implicit_K"], self.nc)
+
+    def __call__(self, r: np.ndarray) -> np.ndarray:
+        """e = s * Net(h^2 r / s), s = rms(h^2 r) (single right-hand side)."""
+        s = C.residual_scale(r[None], self.h)[0]
+        if s == 0.0:
+            return np.zeros_like(r)
+        rin = C.to_channels(self.h * self.h * r[None] / s)
+        out, _ = self.net.solve(rin, self.enc, self.Ghat)
+        return s * C.from_channels(out)[0]
+
+
+def cnn_mg_precond(prob: H.Problem, netp: NetPrecond, v: np.ndarray) -> np.ndarray:
+    """CNN+MG preconditioner: the network's error estimate is the initial guess of
+    the shifted-Laplacian V-cycle on the same right-hand side (Sec. 4.1)."""
+    return prob.hier.vcycle(v, netp(v))
+
+
+def solve_two_phase(prob: H.Problem, netp: NetPrecond, b: np.ndarray, rtol=1e-6, max_iters=2000,
+                    warm_iters=3, restart=10):
+    """Sec. 4.1: a few MG-only FGMRES iterations, then FGMRES(restart) with the
+    CNN+MG preconditioner from that iterate.  Iterations of both phases count."""
+    x, its, hist, rel = H.fgmres(prob.A, b, prob.mg, None, restart, rtol, warm_iters)
+    if rel <= rtol:
+        return x, its, hist, rel
+    x, its2, hist2, rel = H.fgmres(prob.A, b, lambda v: cnn_mg_precond(prob, netp, v), x, restart,
+                                   rtol, max_iters, iters_done=its)
+    return x, its2, hist + hist2[1:], rel
+
+
+def training_pair(prob: H.Problem, x: np.ndarray, k: int):
+    """Eq. 20: b = A x, x~ = k iterations of MG-preconditioned FGMRES from 0,
+    e = x - x~, r = b - A x~ (= A e).  ``x`` is the random vector (an input)."""
+    b = prob.A(x)
+    xt, its, _, _ = H.fgmres(prob.A, b, prob.mg, None, 10, 0.0, k)
+    e = x - xt
+    r = b - prob.A(xt)
+    return e, r

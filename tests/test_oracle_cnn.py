@@ -1,0 +1,236 @@
+"""Pins of the FP64 oracle's network parts: brute-force convolution loops,
+adjointness, the implicit layer's closed forms, the Green's function against a
+sparse direct solve, central finite differences, Adam's first step and the
+training-pair identity r = A e."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import cnn as C
+from oracle import helmholtz as H
+from oracle import solver as S
+from paper_2306_17486_amd import inputs
+
+
+def _rng(s=0):
+    return np.random.default_rng(s)
+
+
+# --- convolutions (Sec. 3.3, eq. 9) ---------------------------------------
+
+def _conv_loops(x, w, b, stride):
+    B, Cin, n, _ = x.shape
+    Cout = w.shape[0]
+    m = n // stride
+    out = np.zeros((B, Cout, m, m))
+    for bb in range(B):
+        for o in range(Cout):
+            for I in range(m):
+                for J in range(m):
+                    acc = b[o]
+                    for c in range(Cin):
+                        for a in range(3):
+                            for e in range(3):
+                                yy, xx = stride * I + a - 1, stride * J + e - 1
+                                if 0 <= yy < n and 0 <= xx < n:
+                                    acc += w[o, c, a, e] * x[bb, c, yy, xx]
+                    out[bb, o, I, J] = acc
+    return out
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_conv_brute_force(stride):
+    r = _rng(1)
+    x = r.standard_normal((2, 3, 6, 6))
+    w = r.standard_normal((4, 3, 3, 3))
+    b = r.standard_normal(4)
+    assert np.allclose(C.conv2d(x, w, b, stride), _conv_loops(x, w, b, stride), atol=1e-12)
+
+
+def test_transposed_conv_brute_force_and_adjoint():
+    r = _rng(2)
+    x = r.standard_normal((2, 3, 4, 4))
+    w = r.standard_normal((3, 5, 3, 3))  # (cin, cout, 3, 3)
+    b = np.zeros(5)
+    y = C.conv_transpose2d(x, w, b, 2)
+    # scatter definition written as loops
+    ref = np.zeros((2, 5, 8, 8))
+    for bb in range(2):
+        for c in range(3):
+            for o in range(5):
+                for I in range(4):
+                    for J in range(4):
+                        for a in range(3):
+                            for e in range(3):
+                                yy, xx = 2 * I + a - 1, 2 * J + e - 1
+                                if 0 <= yy < 8 and 0 <= xx < 8:
+                                    ref[bb, o, yy, xx] += w[c, o, a, e] * x[bb, c, I, J]
+    assert np.allclose(y, ref, atol=1e-12)
+    # adjoint of the stride-2 convolution that uses the same weight array
+    z = r.standard_normal((2, 5, 8, 8))
+    lhs = np.sum(C.conv2d(z, w, np.zeros(3), 2) * x)
+    rhs = np.sum(z * C.conv_transpose2d(x, w, b, 2))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    # stride-1 transposed conv is the adjoint of the stride-1 conv
+    x1 = r.standard_normal((2, 3, 5, 5))
+    z1 = r.standard_normal((2, 5, 5, 5))
+    assert np.sum(C.conv2d(z1, w, np.zeros(3), 1) * x1) == pytest.approx(
+        np.sum(z1 * C.conv_transpose2d(x1, w, b, 1)), rel=1e-12)
+
+
+# --- implicit layer (eqs. 16-17) -------------------------------------------
+
+def test_implicit_identity_kernel_closed_form():
+    nc = 8
+    K = np.zeros((2, 3, 3), dtype=complex)
+    K[:, 1, 1] = 1.0
+    Ghat, _ = C.green_hat(K, nc)
+    z = inputs.random_complex((3, 2, nc, nc), 1)
+    y, _ = C.implicit_apply(Ghat, z)
+    assert np.abs(y - z / (1 + C.EPS_GREEN)).max() <= 1e-12
+
+
+def test_implicit_fft_route_equals_linear_convolution():
+    nc = 4
+    K = inputs.random_complex((2, 3, 3), 3)
+    K[:, 1, 1] += 6.0
+    Ghat, aux = C.green_hat(K, nc)
+    z = inputs.random_complex((2, 2, nc, nc), 4)
+    y, _ = C.implicit_apply(Ghat, z)
+    yd = C.implicit_direct(aux["Gc"], z)
+    assert np.abs(y - yd).max() <= 1e-12 * np.abs(yd).max()
+
+
+def test_green_function_matches_sparse_direct_solve():
+    # K = L + iI (the initial kernel, Sec. 5.3): the cropped G must equal the
+    # response of (L + iI) to a centred point source on a large Dirichlet grid,
+    # up to the Tikhonov term eps / |F(K)|^2 <= 1e-5.
+    nc = 8
+    p = inputs.init_net_params(0, (4, 4, 8, 8))
+    K = p["implicit_K"][:1]
+    _, aux = C.green_hat(K, nc)
+    Gc = aux["Gc"][0]
+    M = 96
+    e = np.ones(M)
+    T = sp.diags([-e[:-1], 2 * e, -e[:-1]], [-1, 0, 1])
+    A = (sp.kron(sp.identity(M), T) + sp.kron(T, sp.identity(M)) + 1j * sp.identity(M * M)).tocsc()
+    rhs = np.zeros((M, M), dtype=complex)
+    rhs[M // 2, M // 2] = 1.0
+    u = spla.spsolve(A, rhs.ravel()).reshape(M, M)
+    ref = u[M // 2 - nc:M // 2 + nc, M // 2 - nc:M // 2 + nc]
+    assert np.abs(Gc - ref).max() <= 2e-5 * np.abs(ref).max()
+    # the kernel applied to G gives back the point source (away from the crop edge)
+    conv = np.zeros_like(Gc)
+    for a in range(3):
+        for b in range(3):
+            conv[1:-1, 1:-1] += K[0, a, b] * Gc[1 - (a - 1):2 * nc - 1 - (a - 1), 1 - (b - 1):2 * nc - 1 - (b - 1)]
+    dl = np.zeros_like(Gc)
+    dl[nc, nc] = 1.0
+    assert np.abs(conv[2:-2, 2:-2] - dl[2:-2, 2:-2]).max() <= 2e-5
+
+
+def test_implicit_adjoint_dot_product():
+    nc = 4
+    K = inputs.random_complex((2, 3, 3), 5)
+    K[:, 1, 1] += 5
+    Ghat, _ = C.green_hat(K, nc)
+    z = inputs.random_complex((1, 2, nc, nc), 6)
+    w = inputs.random_complex((1, 2, nc, nc), 7)
+    y, Z = C.implicit_apply(Ghat, z)
+    gz, _ = C.implicit_backward(Ghat, Z, w)
+    # real inner product <w, T z> = <T^H w, z>
+    assert np.sum((np.conj(w) * y).real) == pytest.approx(np.sum((np.conj(gz) * z).real), rel=1e-12)
+
+
+# --- network gradients ------------------------------------------------------
+
+def test_network_gradients_match_central_differences():
+    ch = (4, 4, 8, 8)
+    p = inputs.init_net_params(0, ch)
+    for k in p:
+        if k.endswith(".w"):
+            p[k] = 2.0 * p[k]  # keeps every layer's gradient well above round-off
+    net = C.Net(p)
+    n = 32
+    r = _rng(1)
+    rin = r.standard_normal((2, 2, n, n))
+    kin = r.standard_normal((2, 2, n, n))
+    tgt = r.standard_normal((2, 2, n, n))
+
+    def loss(params):
+        net.p = params
+        return C.mse_loss(net.forward(rin, kin)[0], tgt)[0]
+
+    net.p = {k: v.copy() for k, v in p.items()}
+    out, cache = net.forward(rin, kin)
+    _, gout = C.mse_loss(out, tgt)
+    g = net.backward(cache, gout)
+    assert set(g) == set(p)
+    for k in sorted(p):
+        v = p[k]
+        d = r.standard_normal(v.shape) + (1j * r.standard_normal(v.shape) if np.iscomplexobj(v) else 0)
+        d = d / np.linalg.norm(d) * np.linalg.norm(v)
+        an = np.sum(g[k].real * d.real) + (np.sum(g[k].imag * d.imag) if np.iscomplexobj(v) else 0.0)
+        best = np.inf
+        for h in (1e-5, 1e-6, 1e-7):
+            pp = {kk: vv.copy() for kk, vv in p.items()}
+            pm = {kk: vv.copy() for kk, vv in p.items()}
+            pp[k] = pp[k] + h * d
+            pm[k] = pm[k] - h * d
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            best = min(best, abs(fd - an) / abs(an))
+        assert best <= 1e-6, (k, best)
+
+
+def test_adam_first_step_closed_form():
+    p = {"w": np.array([0.5, -1.0, 2.0]), "K": np.array([1 + 2j])}
+    g = {"w": np.array([0.1, -3.0, 0.0]), "K": np.array([-0.5 + 0.25j])}
+    opt = C.Adam(p, lr=1e-3)
+    q = opt.step({k: v.copy() for k, v in p.items()}, g)
+    exp_w = p["w"] - 1e-3 * g["w"] / (np.abs(g["w"]) + 1e-8)
+    assert np.allclose(q["w"], exp_w, atol=1e-15)
+    exp_K = (1 + 1e-3 * 0.5 / (0.5 + 1e-8)) + 1j * (2 - 1e-3 * 0.25 / (0.25 + 1e-8))
+    assert q["K"][0] == pytest.approx(exp_K, abs=1e-15)
+
+
+def test_network_shapes_and_skip_rule():
+    p = inputs.init_net_params(1, (4, 4, 8, 8))
+    net = C.Net(p)
+    for n, nc in ((64, 8), (512, 32)):
+        assert C.coarsest_size(n) == nc
+    n = 64
+    rin = _rng(3).standard_normal((1, 2, n, n))
+    kin = _rng(4).standard_normal((1, 2, n, n))
+    out, cache = net.forward(rin, kin)
+    assert out.shape == (1, 2, n, n)
+    assert cache[2][1][3].shape == (1, 4, n // 2, n // 2)  # level-1 encoder features
+    assert cache[3]["s4"][5].shape == (1, 8, n // 8, n // 8)  # stride-1 coarsest level below 512
+
+
+# --- training data (eq. 20) --------------------------------------------------
+
+def test_training_pair_residual_is_operator_times_error():
+    n = 32
+    k = inputs.layered_slowness(n, 5)
+    prob = H.Problem(k, inputs.omega_for(n, k), gamma0=0.05)
+    x = inputs.random_complex((n, n), 9)
+    e, r = S.training_pair(prob, x, 3)
+    assert np.abs(r - prob.A(e)).max() <= 1e-9 * np.abs(r).max()
+    # three MG-preconditioned iterations reduce the residual of b = A x
+    b = prob.A(x)
+    assert np.linalg.norm(r) < 0.5 * np.linalg.norm(b)
+
+
+def test_net_preconditioner_scale_invariance():
+    n = 32
+    k = inputs.grf_slowness(n, 2)
+    prob = H.Problem(k, inputs.omega_for(n, k))
+    net = C.Net(inputs.init_net_params(2, (4, 4, 8, 8)))
+    netp = S.NetPrecond(net, prob)
+    v = inputs.random_complex((n, n), 3)
+    e1 = netp(v)
+    e2 = netp(7.5 * v)
+    assert np.abs(e2 - 7.5 * e1).max() <= 1e-12 * np.abs(e2).max()
