@@ -1,0 +1,188 @@
+/*
+ * hh.h - C ABI of libhh, an MI355X (gfx950) solver for the 2D heterogeneous
+ * Helmholtz equation with a multigrid-augmented CNN preconditioner.
+ *
+ * Method: Lerer, Ben-Yair and Treister, "Multigrid-Augmented Deep Learning
+ * Preconditioners for the Helmholtz Equation using Compact Implicit Layers"
+ * (arXiv 2306.17486).  Section / equation numbers below refer to that paper.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Grid: n x n unknowns u[i][j] (i = row, j = column), row-major, spacing
+ *   h = 1/n, homogeneous Dirichlet ghosts one cell outside the grid (Sec. 3.4:
+ *   the zero padding of the 3x3 stencil is the Dirichlet condition).
+ * - Complex single precision ("c64") is two interleaved floats (re, im);
+ *   complex double ("c128") two interleaved doubles.  Batches are stored
+ *   right-hand side major: element (r, i, j) at offset (r*n + i)*n + j.
+ * - Pointers named *_dev are device pointers on the context's device; the
+ *   caller owns them and must keep them alive until the call returns.
+ *   Pointers named *_host are host memory.
+ * - All device work is ordered on the context's HIP stream.  Calls that write
+ *   host outputs synchronise that stream before returning; the others are
+ *   asynchronous with respect to the host.
+ * - Library workspaces are allocated through the context's allocator
+ *   callbacks (or hipMalloc when none are given) and freed by the matching
+ *   destroy call.
+ * - Return value: HH_OK (0) on success, HH_NOT_CONVERGED (1) when a solve hit
+ *   its iteration cap, a negative HH_ERR_* code on failure.  On failure
+ *   hh_last_error() returns a thread-local description.  Nothing throws.
+ */
+#ifndef HH_H_
+#define HH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hh_status;
+enum {
+    HH_OK = 0,
+    HH_NOT_CONVERGED = 1,
+    HH_ERR_ARG = -1,       /* bad argument (sizes, null pointers, unsupported n) */
+    HH_ERR_HIP = -2,       /* a HIP runtime call or kernel launch failed */
+    HH_ERR_NOMEM = -3,     /* the allocator returned NULL */
+    HH_ERR_STATE = -4,     /* call not valid in the object's current state */
+    HH_ERR_BREAKDOWN = -5  /* NaN or Inf met in a solve */
+};
+
+enum { HH_MAX_LEVELS = 4, HH_MAX_RESTART = 16 };
+
+typedef struct hh_ctx hh_ctx;
+typedef struct hh_model hh_model;
+typedef struct hh_net hh_net;
+
+/* Device allocator callbacks.  alloc returns a device pointer (or NULL on
+ * failure) of at least `bytes` bytes, aligned to 256 bytes, usable on the
+ * context's stream; free releases it.  `user` is passed through unchanged. */
+typedef void* (*hh_alloc_fn)(size_t bytes, void* user);
+typedef void (*hh_free_fn)(void* ptr, void* user);
+
+/* Library version string (static storage). */
+const char* hh_version(void);
+
+/* Thread-local description of the last error returned on this thread
+ * (static storage until the next failing call on the same thread). */
+const char* hh_last_error(void);
+
+/* Create a context bound to HIP device `device` and HIP stream `stream`
+ * (a hipStream_t; NULL = the device's null stream).  alloc/free may both be
+ * NULL (hipMalloc / hipFree are used).  *out receives the new context. */
+hh_status hh_ctx_create(int device, void* stream, hh_alloc_fn alloc, hh_free_fn free_fn, void* user,
+                        hh_ctx** out);
+hh_status hh_ctx_destroy(hh_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Problem model: one or more slowness models on the same n x n grid.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int n;                 /* grid points per dimension; n % 4 == 0, n >= 16 */
+    double omega;          /* angular frequency (eq. 1) */
+    int abl_width;         /* absorbing-layer width in cells (Sec. 3.1), default 16 */
+    double abl_gamma_max;  /* attenuation at the edge cell, default 1 */
+    double gamma0;         /* constant global attenuation gamma of eq. 1, default 0 */
+    double sl_beta;        /* shifted-Laplacian imaginary shift beta (eq. 4), default 0.5 */
+    int levels;            /* multigrid levels (Sec. 3.2), default 3, 2..HH_MAX_LEVELS */
+    int nu_pre, nu_post;   /* damped-Jacobi sweeps before/after the coarse correction, 1/1 */
+    double jacobi_w;       /* Jacobi damping, default 0.8 */
+} hh_model_desc;
+
+/* Fill *d with the defaults listed above (n and omega are set to 0). */
+void hh_model_desc_default(hh_model_desc* d);
+
+/* Build the model for `ninst` slowness models kappa_dev (float32
+ * [ninst][n][n], device, read during the call only).  The operator is eqs.
+ * 1-3 with gamma = gamma0 + ((w - d)/w)^2 * gamma_max on cells at distance
+ * d < w = abl_width from the nearest edge.  Builds every multigrid level
+ * (coefficients restricted by full weighting, eq. 8) and the exact
+ * block-tridiagonal factorisation of the coarsest shifted operator.
+ * Synchronises the stream.  Errors: HH_ERR_ARG for unsupported sizes. */
+hh_status hh_model_create(hh_ctx* ctx, const hh_model_desc* d, int ninst, const float* kappa_dev,
+                          hh_model** out);
+hh_status hh_model_destroy(hh_model* m);
+
+/* ------------------------------------------------------------------------
+ * Flexible GMRES solve (Saad 1993; the Krylov method of Sec. 1 and Sec. 5).
+ * ---------------------------------------------------------------------- */
+enum { HH_PRECOND_MG = 0, HH_PRECOND_CNN_MG = 1 };
+
+typedef struct {
+    int restart;        /* FGMRES restart length m, default 10, <= HH_MAX_RESTART */
+    int max_iters;      /* cap on preconditioner applications per RHS, default 2000 */
+    double rtol;        /* stop when ||b - A x|| / ||b|| <= rtol (FP64), default 1e-6 */
+    int precond;        /* HH_PRECOND_MG or HH_PRECOND_CNN_MG */
+    int warm_mg_iters;  /* CNN_MG only: MG-only iterations before the network (Sec. 4.1), default 3 */
+    int use_x0;         /* 1: x_dev holds the initial guess; 0: start from zero */
+    int fixed_iters;    /* >0: run exactly this many iterations (single cycle, no
+                           convergence test); used to generate training data (eq. 20) */
+} hh_solve_opts;
+
+void hh_solve_opts_default(hh_solve_opts* o);
+
+/* Solve A x = b for `nrhs` right-hand sides.
+ *   inst_host: host int[nrhs], slowness model index of each RHS (NULL = all 0)
+ *   b_dev:     c64 [nrhs][n][n] right-hand sides
+ *   x_dev:     c128 [nrhs][n][n] solutions (initial guess when o->use_x0)
+ *   res_hist_host: optional double [nrhs][o->max_iters + 1]; entry k = relative
+ *              residual estimate after k iterations (entry 0 = initial true
+ *              value); entries past the last iteration are set to -1
+ *   iters_host, converged_host: optional int [nrhs]
+ *   final_res_host: optional double [nrhs]: ||b - A x|| / ||b|| recomputed in FP64
+ * The stencil, V-cycle and network run in single precision / BF16; the
+ * Gram-Schmidt sums, the Hessenberg least-squares problem, x and the restart
+ * residual are FP64.  Returns HH_NOT_CONVERGED if any RHS stopped at
+ * max_iters above rtol.  Synchronises the stream. */
+hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
+                   void* x_dev, const hh_solve_opts* o, double* res_hist_host, int* iters_host,
+                   int* converged_host, double* final_res_host);
+
+/* ------------------------------------------------------------------------
+ * Building blocks exposed for parity tests (same kernels as the solve).
+ * ---------------------------------------------------------------------- */
+
+/* y = A_l x on multigrid level l (0 = finest, size n >> l) with the damping
+ * shifted by `shift` (0 = Helmholtz operator of eqs. 1-3, sl_beta = the
+ * shifted Laplacian of eq. 4).  x, y: c64 [nrhs][n_l][n_l]. */
+hh_status hh_apply_operator(hh_model* m, int level, double shift, int nrhs, const int* inst_host,
+                            const void* x_dev, void* y_dev);
+
+/* One shifted-Laplacian V-cycle (Alg. 1 applied recursively, direct coarsest
+ * solve): x = V(b; x0).  x0_dev may be NULL (zero initial guess).
+ * b, x0, x: c64 [nrhs][n][n]. */
+hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
+                          const void* x0_dev, void* x_dev);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (HIP events on the context's stream).
+ * ---------------------------------------------------------------------- */
+enum {
+    HH_K_OPERATOR = 0,     /* operator application (test entry point) */
+    HH_K_VC_DOWN = 1,      /* V-cycle: relax + residual + restriction, finest level */
+    HH_K_VC_UP = 2,        /* V-cycle: prolongation + correction + relax, finest level */
+    HH_K_VC_COARSE = 3,    /* V-cycle: exact coarsest solve */
+    HH_K_VC_MID = 4,       /* V-cycle: down/up kernels of the intermediate levels */
+    HH_K_OP_DOTS = 5,      /* FGMRES: w = A z with the Gram-Schmidt inner products */
+    HH_K_ORTHO = 6,        /* FGMRES: w -= sum h v, ||w|| */
+    HH_K_SMALL = 7,        /* FGMRES: reductions, Givens, least squares */
+    HH_K_RESTART = 8,      /* FGMRES: x update and FP64 residual */
+    HH_K_CONV = 9,         /* network: convolutions */
+    HH_K_NET_OTHER = 10,   /* network: implicit layer, scaling, upsampling */
+    HH_K_NUM_CLASSES = 11
+};
+
+/* Start timing every launch of kernel class `cls` on this context, or of every
+ * class when cls == HH_K_NUM_CLASSES (replaces a previous selection and clears
+ * its records).  Each timed launch is bracketed by two events on the stream. */
+hh_status hh_profile_begin(hh_ctx* ctx, int cls);
+/* Stop timing; synchronises the stream and writes, per class, the summed
+ * kernel time in milliseconds (total_ms[HH_K_NUM_CLASSES]) and the number of
+ * timed launches (launches[HH_K_NUM_CLASSES]). */
+hh_status hh_profile_end(hh_ctx* ctx, double* total_ms, long long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HH_H_ */

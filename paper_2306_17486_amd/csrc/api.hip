@@ -1,0 +1,310 @@
+// C ABI of libhh: contexts, models, solves and the parity-test entry points.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "hh_internal.h"
+#include "krylov.h"
+#include "net.h"
+
+namespace hh {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+hh_status dalloc(hh_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return HH_OK;
+    if (c->alloc) {
+        *p = c->alloc(bytes, c->user);
+        if (!*p) {
+            set_error("allocator callback returned NULL for %zu bytes", bytes);
+            return HH_ERR_NOMEM;
+        }
+        return HH_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return HH_ERR_NOMEM;
+    }
+    return HH_OK;
+}
+
+void dfree(hh_ctx* c, void* p) {
+    if (!p) return;
+    if (c->dealloc)
+        c->dealloc(p, c->user);
+    else
+        (void)hipFree(p);
+}
+
+// Copy a host int[nrhs] RHS -> instance map to the device (NULL = all zeros).
+static hh_status upload_inst(hh_model* m, Buf& buf, int nrhs, const int* inst_host, const int** out) {
+    *out = nullptr;
+    if (!inst_host) {
+        if (m->ninst > 1) {
+            HH_TRY(buf.ensure(m->ctx, (size_t)nrhs * sizeof(int)));
+            HH_HIP(hipMemsetAsync(buf.ptr, 0, (size_t)nrhs * sizeof(int), m->ctx->stream));
+            *out = buf.as<int>();
+        }
+        return HH_OK;
+    }
+    for (int r = 0; r < nrhs; ++r)
+        HH_ARG(inst_host[r] >= 0 && inst_host[r] < m->ninst, "instance index out of range");
+    HH_TRY(buf.ensure(m->ctx, (size_t)nrhs * sizeof(int)));
+    HH_HIP(hipMemcpyAsync(buf.ptr, inst_host, (size_t)nrhs * sizeof(int), hipMemcpyHostToDevice, m->ctx->stream));
+    HH_HIP(hipStreamSynchronize(m->ctx->stream));  // inst_host may be freed by the caller afterwards
+    *out = buf.as<int>();
+    return HH_OK;
+}
+
+}  // namespace hh
+
+using namespace hh;
+
+extern "C" {
+
+const char* hh_version(void) { return "libhh 0.1 (gfx950)"; }
+
+const char* hh_last_error(void) { return g_err; }
+
+hh_status hh_ctx_create(int device, void* stream, hh_alloc_fn alloc, hh_free_fn free_fn, void* user, hh_ctx** out) {
+    HH_ARG(out != nullptr, "out is NULL");
+    *out = nullptr;
+    HH_ARG((alloc == nullptr) == (free_fn == nullptr), "alloc and free must be given together");
+    int count = 0;
+    HH_HIP(hipGetDeviceCount(&count));
+    HH_ARG(device >= 0 && device < count, "device index out of range");
+    HH_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HH_HIP(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_error("libhh is built for gfx950 only; device %d is %s", device, prop.gcnArchName);
+        return HH_ERR_ARG;
+    }
+    hh_ctx* c = new (std::nothrow) hh_ctx();
+    if (!c) {
+        set_error("out of host memory");
+        return HH_ERR_NOMEM;
+    }
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->alloc = alloc;
+    c->dealloc = free_fn;
+    c->user = user;
+    c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return HH_OK;
+}
+
+hh_status hh_ctx_destroy(hh_ctx* ctx) {
+    if (!ctx) return HH_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx->work;
+    delete ctx;
+    return HH_OK;
+}
+
+void hh_model_desc_default(hh_model_desc* d) {
+    if (!d) return;
+    memset(d, 0, sizeof(*d));
+    d->abl_width = 16;
+    d->abl_gamma_max = 1.0;
+    d->gamma0 = 0.0;
+    d->sl_beta = 0.5;
+    d->levels = 3;
+    d->nu_pre = 1;
+    d->nu_post = 1;
+    d->jacobi_w = 0.8;
+}
+
+hh_status hh_model_create(hh_ctx* ctx, const hh_model_desc* d, int ninst, const float* kappa_dev, hh_model** out) {
+    HH_ARG(ctx && d && kappa_dev && out, "null pointer");
+    *out = nullptr;
+    HH_ARG(ninst >= 1, "ninst >= 1");
+    HH_ARG(d->levels >= 2 && d->levels <= HH_MAX_LEVELS, "levels in 2..HH_MAX_LEVELS");
+    HH_ARG(d->n >= 16 && d->n % (1 << (d->levels - 1)) == 0, "n >= 16 and divisible by 2^(levels-1)");
+    HH_ARG(d->nu_pre == 1 && d->nu_post == 1, "one pre- and one post-relaxation sweep");
+    HH_ARG((d->n >> (d->levels - 1)) <= 1024, "coarsest grid at most 1024 x 1024");
+    HH_ARG(d->omega >= 0.0 && d->abl_width >= 0 && d->sl_beta > 0.0, "omega >= 0, abl_width >= 0, sl_beta > 0");
+    HH_HIP(hipSetDevice(ctx->device));
+    hh_model* m = new (std::nothrow) hh_model();
+    if (!m) {
+        set_error("out of host memory");
+        return HH_ERR_NOMEM;
+    }
+    m->ctx = ctx;
+    m->d = *d;
+    m->ninst = ninst;
+    m->nlev = d->levels;
+    for (int l = 0; l < m->nlev; ++l) {
+        m->lev[l].n = d->n >> l;
+        m->lev[l].h = (double)(1 << l) / d->n;
+        hh_status s = m->lev[l].coef.ensure(ctx, (size_t)ninst * m->lev[l].n * m->lev[l].n * sizeof(float2));
+        if (s < 0) {
+            delete m;
+            return s;
+        }
+    }
+    hh_status s = setup_coefficients(m, kappa_dev);
+    if (s >= 0) s = setup_coarse_factors(m);
+    if (s < 0) {
+        delete m;
+        return s;
+    }
+    *out = m;
+    return HH_OK;
+}
+
+hh_status hh_model_destroy(hh_model* m) {
+    if (!m) return HH_OK;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    net_model_release(m);
+    delete m;
+    return HH_OK;
+}
+
+void hh_solve_opts_default(hh_solve_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->restart = 10;
+    o->max_iters = 2000;
+    o->rtol = 1e-6;
+    o->precond = HH_PRECOND_MG;
+    o->warm_mg_iters = 3;
+    o->use_x0 = 0;
+    o->fixed_iters = 0;
+}
+
+hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev, void* x_dev,
+                   const hh_solve_opts* o, double* res_hist_host, int* iters_host, int* converged_host,
+                   double* final_res_host) {
+    HH_ARG(ctx && m && b_dev && x_dev && o, "null pointer");
+    HH_ARG(m->ctx == ctx, "model belongs to another context");
+    HH_ARG(nrhs >= 1, "nrhs >= 1");
+    HH_ARG(o->restart >= 1 && o->restart <= HH_MAX_RESTART, "restart in 1..HH_MAX_RESTART");
+    HH_ARG(o->max_iters >= 1 && o->rtol >= 0.0, "max_iters >= 1, rtol >= 0");
+    HH_ARG(o->precond == HH_PRECOND_MG || o->precond == HH_PRECOND_CNN_MG, "precond");
+    HH_ARG(o->fixed_iters >= 0 && o->fixed_iters <= o->restart, "0 <= fixed_iters <= restart");
+    HH_ARG(o->precond == HH_PRECOND_MG || m->net != nullptr, "CNN_MG needs a network attached to the model");
+    HH_HIP(hipSetDevice(ctx->device));
+    if (!ctx->work) {
+        ctx->work = new (std::nothrow) SolveWork();
+        if (!ctx->work) {
+            set_error("out of host memory");
+            return HH_ERR_NOMEM;
+        }
+    }
+    SolveWork& W = *ctx->work;
+    const bool cnn = o->precond == HH_PRECOND_CNN_MG;
+    const int max_it = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+    const int hist_len = max_it + 1;
+    HH_TRY(W.prepare(ctx, m, nrhs, o->restart, hist_len, cnn));
+    const int* inst_dev = nullptr;
+    HH_TRY(upload_inst(m, W.inst, nrhs, inst_host, &inst_dev));
+    hh_status s = fgmres_solve(m, W, inst_dev, (const float2*)b_dev, (double2*)x_dev, *o,
+                               cnn ? net_precond : nullptr, cnn ? (void*)m : nullptr);
+    if (s < 0) return s;
+    // results
+    std::vector<KState> hs(nrhs);
+    HH_HIP(hipMemcpyAsync(hs.data(), W.state.ptr, (size_t)nrhs * sizeof(KState), hipMemcpyDeviceToHost, ctx->stream));
+    if (res_hist_host)
+        HH_HIP(hipMemcpyAsync(res_hist_host, W.hist.ptr, (size_t)nrhs * hist_len * sizeof(double),
+                              hipMemcpyDeviceToHost, ctx->stream));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    bool all_conv = true, broke = false;
+    for (int r = 0; r < nrhs; ++r) {
+        if (iters_host) iters_host[r] = hs[r].iters;
+        if (converged_host) converged_host[r] = hs[r].converged;
+        if (final_res_host) final_res_host[r] = hs[r].res_true;
+        all_conv = all_conv && hs[r].converged;
+        broke = broke || hs[r].breakdown;
+    }
+    if (broke) {
+        set_error("NaN or Inf met in the solve");
+        return HH_ERR_BREAKDOWN;
+    }
+    if (o->fixed_iters > 0) return HH_OK;
+    return all_conv ? HH_OK : HH_NOT_CONVERGED;
+}
+
+hh_status hh_apply_operator(hh_model* m, int level, double shift, int nrhs, const int* inst_host, const void* x_dev,
+                            void* y_dev) {
+    HH_ARG(m && x_dev && y_dev, "null pointer");
+    HH_ARG(level >= 0 && level < m->nlev, "level");
+    HH_ARG(nrhs >= 1, "nrhs >= 1");
+    HH_HIP(hipSetDevice(m->ctx->device));
+    Buf ib;
+    const int* inst_dev = nullptr;
+    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &inst_dev));
+    HH_TRY(launch_apply_op(m, level, (float)shift, nrhs, inst_dev, (const float2*)x_dev, (float2*)y_dev, nullptr));
+    HH_HIP(hipStreamSynchronize(m->ctx->stream));
+    return HH_OK;
+}
+
+hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const void* b_dev, const void* x0_dev,
+                          void* x_dev) {
+    HH_ARG(m && b_dev && x_dev, "null pointer");
+    HH_ARG(nrhs >= 1, "nrhs >= 1");
+    HH_HIP(hipSetDevice(m->ctx->device));
+    Buf ib, work;
+    const int* inst_dev = nullptr;
+    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &inst_dev));
+    HH_TRY(work.ensure(m->ctx, vcycle_workspace_bytes(m, nrhs, x0_dev != nullptr) + 256));
+    HH_TRY(launch_vcycle(m, nrhs, inst_dev, (const float2*)b_dev, nullptr, 0, (const float2*)x0_dev, (float2*)x_dev,
+                         work.ptr, nullptr));
+    HH_HIP(hipStreamSynchronize(m->ctx->stream));
+    return HH_OK;
+}
+
+hh_status hh_profile_begin(hh_ctx* ctx, int cls) {
+    HH_ARG(ctx, "null pointer");
+    HH_ARG(cls >= 0 && cls <= HH_K_NUM_CLASSES, "kernel class");
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& e : ctx->prof_events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    ctx->prof_events.clear();
+    ctx->prof_class = cls;
+    return HH_OK;
+}
+
+hh_status hh_profile_end(hh_ctx* ctx, double* total_ms, long long* launches) {
+    HH_ARG(ctx && total_ms && launches, "null pointer");
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < HH_K_NUM_CLASSES; ++k) {
+        total_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    hipError_t err = hipSuccess;
+    for (auto& e : ctx->prof_events) {
+        float ms = 0.f;
+        hipError_t q = hipEventElapsedTime(&ms, e.a, e.b);
+        if (q != hipSuccess && err == hipSuccess) err = q;
+        total_ms[e.cls] += ms;
+        launches[e.cls] += 1;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    ctx->prof_events.clear();
+    ctx->prof_class = -1;
+    if (err != hipSuccess) {
+        set_error("hipEventElapsedTime failed: %s", hipGetErrorString(err));
+        return HH_ERR_HIP;
+    }
+    return HH_OK;
+}
+
+}  // extern "C"

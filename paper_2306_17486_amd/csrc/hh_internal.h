@@ -1,0 +1,232 @@
+// Internal declarations shared by the HIP translation units of libhh.
+// Not part of the public C ABI (see include/hh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hh.h"
+
+// ---------------------------------------------------------------------------
+// error plumbing: no exception crosses the ABI; every failing call records a
+// thread-local message and returns a negative status.
+// ---------------------------------------------------------------------------
+namespace hh {
+
+void set_error(const char* fmt, ...);
+
+#define HH_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::hh::set_error("%s failed at %s:%d: %s", #call, __FILE__, __LINE__,     \
+                            hipGetErrorString(e_));                                    \
+            return HH_ERR_HIP;                                                         \
+        }                                                                              \
+    } while (0)
+
+#define HH_TRY(call)                       \
+    do {                                   \
+        hh_status s_ = (call);             \
+        if (s_ < 0) return s_;             \
+    } while (0)
+
+#define HH_ARG(cond, msg)                                               \
+    do {                                                                \
+        if (!(cond)) {                                                  \
+            ::hh::set_error("invalid argument: %s (%s)", msg, #cond);   \
+            return HH_ERR_ARG;                                          \
+        }                                                               \
+    } while (0)
+
+#define HH_LAUNCH_CHECK()                                                               \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess) {                                                        \
+            ::hh::set_error("kernel launch failed at %s:%d: %s", __FILE__, __LINE__,  \
+                            hipGetErrorString(e_));                                    \
+            return HH_ERR_HIP;                                                         \
+        }                                                                              \
+    } while (0)
+
+}  // namespace hh
+
+// ---------------------------------------------------------------------------
+// opaque handle contents
+// ---------------------------------------------------------------------------
+namespace hh { struct SolveWork; }
+
+struct hh_ctx {
+    hh::SolveWork* work = nullptr;  // solve workspace, reused across calls
+    // event timing of kernel classes (hh_profile_begin / hh_profile_end):
+    // prof_class = -1 off, HH_K_NUM_CLASSES = every class, else one class
+    int prof_class = -1;
+    struct ProfRec { int cls; hipEvent_t a, b; };
+    std::vector<ProfRec> prof_events;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hh_alloc_fn alloc = nullptr;
+    hh_free_fn dealloc = nullptr;
+    void* user = nullptr;
+    int num_cus = 256;
+};
+
+namespace hh {
+
+// Device allocation through the caller's allocator (or hipMalloc).
+hh_status dalloc(hh_ctx* c, void** p, size_t bytes);
+void dfree(hh_ctx* c, void* p);
+
+// A device buffer that frees itself through the context's allocator.
+struct Buf {
+    hh_ctx* ctx = nullptr;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    Buf() = default;
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+    ~Buf() { release(); }
+    void release() {
+        if (ptr && ctx) dfree(ctx, ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    hh_status ensure(hh_ctx* c, size_t want) {
+        if (ptr && bytes >= want) return HH_OK;
+        release();
+        ctx = c;
+        if (want == 0) return HH_OK;
+        hh_status s = dalloc(c, &ptr, want);
+        if (s == HH_OK) bytes = want;
+        return s;
+    }
+    template <class T> T* as() const { return reinterpret_cast<T*>(ptr); }
+};
+
+// One multigrid level of a model (all instances share n).
+struct Level {
+    int n = 0;       // points per dimension
+    double h = 0;    // spacing
+    Buf coef;        // float2 [ninst][n][n] = {omega^2 kappa^2, gamma}
+};
+
+}  // namespace hh
+
+struct hh_model {
+    hh_ctx* ctx = nullptr;
+    hh_model_desc d{};
+    int ninst = 0;
+    int nlev = 0;
+    hh::Level lev[HH_MAX_LEVELS];
+    hh::Buf coarseQT;      // float2 [ninst][m][m][m]: block-LU Schur inverses, transposed
+    int m = 0;             // coarsest points per dimension
+    hh::Buf kfeat;         // encoder input features (bf16 NHWC, 2 channels) when a net is attached
+    hh_net* net = nullptr; // attached network (not owned)
+    void* netcache = nullptr;  // per-model network state (encodings, Green's transforms)
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+namespace hh {
+
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// a / b
+__host__ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
+    float den = b.x * b.x + b.y * b.y;
+    return make_float2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+__host__ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+    double den = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+__host__ __device__ __forceinline__ double zabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// Zeroth-order term omega^2 kappa^2 (1 - i (gamma + shift)) from the stored
+// coefficient pair {omega^2 kappa^2, gamma}.
+__device__ __forceinline__ float2 mass_of(float2 c, float shift) {
+    return make_float2(c.x, -c.x * (c.y + shift));
+}
+
+// FP32 <-> BF16 (round to nearest even; NaN stays NaN)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// Wavefront (64 lanes) sum of a double.
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace hh
+
+// ---------------------------------------------------------------------------
+// Per-kernel-class timing: brackets the launches of the selected class with
+// HIP events recorded on the context's stream.
+// ---------------------------------------------------------------------------
+namespace hh {
+struct ProfScope {
+    hh_ctx* c;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(hh_ctx* ctx, int k) : c(ctx), cls(k) {
+        if (c->prof_class != cls && c->prof_class != HH_K_NUM_CLASSES) return;
+        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, c->stream);
+    }
+    ~ProfScope() {
+        if (!b) return;
+        (void)hipEventRecord(b, c->stream);
+        c->prof_events.push_back({cls, a, b});
+    }
+};
+}  // namespace hh
+
+// ---------------------------------------------------------------------------
+// internal launchers (host functions, defined in the .hip files)
+// ---------------------------------------------------------------------------
+namespace hh {
+
+// setup.hip
+hh_status setup_coefficients(hh_model* m, const float* kappa_dev);
+hh_status setup_coarse_factors(hh_model* m);
+
+// mg.hip
+hh_status launch_apply_op(hh_model* m, int level, float shift, int nrhs, const int* inst_dev,
+                          const float2* x, float2* y, const int* active);
+// V-cycle on level 0: b (optionally scaled per RHS by sig[r*sig_stride]), optional
+// initial guess x0, result z.  work: scratch laid out by vcycle_workspace_bytes.
+size_t vcycle_workspace_bytes(const hh_model* m, int nrhs, bool with_x0);
+hh_status launch_vcycle(hh_model* m, int nrhs, const int* inst_dev, const float2* b, const double* sig,
+                        int sig_stride, const float2* x0, float2* z, void* work, const int* active);
+// Same with explicit element strides between consecutive right-hand sides.
+hh_status launch_vcycle_strided(hh_model* m, int nrhs, const int* inst_dev, const float2* b, size_t bstride,
+                                const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
+                                size_t zstride, void* work, const int* active);
+
+}  // namespace hh

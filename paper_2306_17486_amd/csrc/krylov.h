@@ -1,0 +1,38 @@
+// Internal FGMRES state shared by the solver translation units.
+#pragma once
+#include "hh_internal.h"
+
+namespace hh {
+
+// Per right-hand-side Arnoldi / least-squares state (device memory, FP64).
+struct KState {
+    double2 H[HH_MAX_RESTART + 1][HH_MAX_RESTART];  // Hessenberg, rotated in place
+    double cs[HH_MAX_RESTART];                      // Givens cosines (real)
+    double2 sn[HH_MAX_RESTART];                     // Givens sines
+    double2 g[HH_MAX_RESTART + 1];                  // rotated beta e1
+    double2 y[HH_MAX_RESTART];                      // current least-squares solution
+    double sig[HH_MAX_RESTART + 1];                 // 1/||v_i|| of the stored basis vectors
+    float2 oc[HH_MAX_RESTART + 1];                  // single-precision projection coefficients
+    double bnorm, res_est, res_true;
+    int k, iters, converged, breakdown;
+};
+static_assert(sizeof(KState) % 8 == 0, "KState must be a whole number of doubles");
+
+// Device workspace of one solve (grown on demand, reused across calls).
+struct SolveWork {
+    int nrhs = 0, restart = 0, hist_len = 0, n = 0, npart = 0;
+    Buf V, Z, state, flags, parts, inst, hist, vwork, x0net;
+    hh_status prepare(hh_ctx* c, hh_model* md, int nrhs, int restart, int hist_len, bool cnn);
+};
+
+// Network part of the CNN+MG preconditioner: z_j = V(v_j; Net(v_j)).
+typedef hh_status (*PrecondFn)(void* user, hh_model* md, SolveWork& W, const int* inst_dev, const float2* v,
+                               size_t vstride, const double* sig, int sig_stride, float2* z, size_t zstride,
+                               const int* act);
+
+hh_status fgmres_solve(hh_model* md, SolveWork& W, const int* inst_dev, const float2* b, double2* x,
+                       const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user);
+hh_status precond_mg_strided(hh_model* md, SolveWork& W, const int* inst_dev, const float2* v, size_t vstride,
+                             const double* sig, int sig_stride, float2* z, size_t zstride, const int* act);
+
+}  // namespace hh

@@ -1,0 +1,555 @@
+// Flexible GMRES(m) on gfx950 (Saad 1993; the outer Krylov method of the paper).
+//
+// Mixed precision: the basis V and the preconditioned vectors Z are complex
+// single precision; every inner product and norm is accumulated in FP64; the
+// Hessenberg matrix, the Givens rotations and the small triangular solve are
+// FP64; x is complex double and the residual b - A x is recomputed in FP64 at
+// every restart, which is what the stopping test uses.
+//
+// Every right-hand side of a batch advances in lock step; per-RHS flags in
+// device memory switch finished ones off, so a whole restart cycle is enqueued
+// without host round trips.  The host reads one flag per RHS per cycle.
+//
+// Lazy normalisation: v_{j+1} is stored as the orthogonalised w and its scale
+// sigma_{j+1} = 1/||w|| is applied by every reader, which saves one full pass
+// over the vector per iteration.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "hh_internal.h"
+#include "krylov.h"
+
+namespace hh {
+
+constexpr int KT_X = 64, KT_Y = 16, KT_ROWS = 4;  // 64 x 16 tile, 256 threads
+constexpr int MAXV = HH_MAX_RESTART + 1;
+
+static inline int kblocks(int n) { return ((n + KT_X - 1) / KT_X) * ((n + KT_Y - 1) / KT_Y); }
+
+// Block-wide sum of NV double2 values per thread; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum2(double2 (&v)[NV], int nact, double2* s_red /* [4][NV] */) {
+    const int lane = threadIdx.x + threadIdx.y * blockDim.x;
+    const int wid = lane >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i < nact) {
+            v[i].x = wave_sum(v[i].x);
+            v[i].y = wave_sum(v[i].y);
+        }
+    }
+    if ((lane & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nact) s_red[wid * NV + i] = v[i];
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nact) {
+                double2 a = s_red[i];
+                for (int w = 1; w < 4; ++w) a = zadd(a, s_red[w * NV + i]);
+                v[i] = a;
+            }
+        }
+    }
+}
+
+// ||b||^2 partials (FP64) of a complex-single vector
+__global__ void __launch_bounds__(256) k_norm2(const float2* __restrict__ b, int n, double2* __restrict__ parts) {
+    __shared__ double2 s_red[4];
+    const int r = blockIdx.z;
+    const size_t nn = (size_t)n * n;
+    const int j = blockIdx.x * KT_X + threadIdx.x;
+    const int i0 = blockIdx.y * KT_Y + threadIdx.y * KT_ROWS;
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    if (j < n)
+        for (int t = 0; t < KT_ROWS; ++t) {
+            int i = i0 + t;
+            if (i < n) {
+                float2 v = b[r * nn + (size_t)i * n + j];
+                acc[0].x += (double)v.x * v.x + (double)v.y * v.y;
+            }
+        }
+    block_sum2<1>(acc, 1, s_red);
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        parts[(size_t)r * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
+}
+
+// r = b - A x in FP64 (x complex double); r stored single into V[r][0]; ||r||^2 partials.
+__global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ x, const float2* __restrict__ b,
+                                                    float2* __restrict__ Vbase, size_t vstride,
+                                                    const float2* __restrict__ coef, const int* __restrict__ inst,
+                                                    int n, double inv_h2, double2* __restrict__ parts,
+                                                    const int* __restrict__ done) {
+    __shared__ double2 s_red[4];
+    const int r = blockIdx.z;
+    const bool skip = done && done[r];
+    const size_t nn = (size_t)n * n;
+    const int j = blockIdx.x * KT_X + threadIdx.x;
+    const int i0 = blockIdx.y * KT_Y + threadIdx.y * KT_ROWS;
+    const double2* xr = x + r * nn;
+    const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    if (!skip && j < n) {
+        const double2 z = make_double2(0.0, 0.0);
+        for (int t = 0; t < KT_ROWS; ++t) {
+            int i = i0 + t;
+            if (i >= n) break;
+            size_t o = (size_t)i * n + j;
+            double2 c = xr[o];
+            double2 up = i > 0 ? xr[o - n] : z, dn = i + 1 < n ? xr[o + n] : z;
+            double2 lf = j > 0 ? xr[o - 1] : z, rt = j + 1 < n ? xr[o + 1] : z;
+            float2 cc = cf[o];
+            double w2k2 = cc.x, g = cc.y;
+            // A x = (4c - nb)/h^2 - w2k2 (1 - i g) c
+            double2 m = make_double2(w2k2, -w2k2 * g);
+            double2 Ax = make_double2((4.0 * c.x - up.x - dn.x - lf.x - rt.x) * inv_h2,
+                                      (4.0 * c.y - up.y - dn.y - lf.y - rt.y) * inv_h2);
+            Ax = zsub(Ax, zmul(m, c));
+            float2 bv = b[r * nn + o];
+            double2 rv = make_double2((double)bv.x - Ax.x, (double)bv.y - Ax.y);
+            Vbase[r * vstride + o] = make_float2((float)rv.x, (float)rv.y);
+            acc[0].x += zabs2(rv);
+        }
+    }
+    block_sum2<1>(acc, 1, s_red);
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        parts[(size_t)r * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
+}
+
+// w = A z (FP32) written to V[j+1]; partial FP64 dots <v~_i, w>, i = 0..j
+template <int NJ>
+__global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, size_t zstride, float2* __restrict__ V,
+                                                 size_t vstride, int j, const float2* __restrict__ coef,
+                                                 const int* __restrict__ inst, int n, float inv_h2,
+                                                 double2* __restrict__ parts, int npart,
+                                                 const int* __restrict__ active) {
+    __shared__ double2 s_red[4 * NJ];
+    const int r = blockIdx.z;
+    if (!active[r]) return;
+    const size_t nn = (size_t)n * n;
+    const int jj = blockIdx.x * KT_X + threadIdx.x;
+    const int i0 = blockIdx.y * KT_Y + threadIdx.y * KT_ROWS;
+    const float2* zr = Z + r * zstride;
+    const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
+    const int nact = j + 1;
+    double2 acc[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc[i] = make_double2(0.0, 0.0);
+    const float2 zero = make_float2(0.f, 0.f);
+    float2* wout = V + r * vstride + (size_t)(j + 1) * nn;
+    if (jj < n) {
+        float2 up = (i0 > 0 && i0 - 1 < n) ? zr[(size_t)(i0 - 1) * n + jj] : zero;
+        float2 cur = (i0 < n) ? zr[(size_t)i0 * n + jj] : zero;
+        for (int t = 0; t < KT_ROWS; ++t) {
+            const int i = i0 + t;
+            if (i >= n) break;
+            size_t o = (size_t)i * n + jj;
+            float2 dn = (i + 1 < n) ? zr[o + n] : zero;
+            float2 lf = (jj > 0) ? zr[o - 1] : zero;
+            float2 rt = (jj + 1 < n) ? zr[o + 1] : zero;
+            float2 m = mass_of(cf[o], 0.f);
+            float2 w = csub(make_float2((4.f * cur.x - up.x - dn.x - lf.x - rt.x) * inv_h2,
+                                        (4.f * cur.y - up.y - dn.y - lf.y - rt.y) * inv_h2),
+                            cmul(m, cur));
+            wout[o] = w;
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) {
+                if (q < nact) {
+                    float2 v = V[r * vstride + (size_t)q * nn + o];
+                    // conj(v) * w
+                    acc[q].x += (double)v.x * w.x + (double)v.y * w.y;
+                    acc[q].y += (double)v.x * w.y - (double)v.y * w.x;
+                }
+            }
+            up = cur;
+            cur = dn;
+        }
+    }
+    block_sum2<NJ>(acc, nact, s_red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        double2* p = parts + ((size_t)r * npart + blockIdx.y * gridDim.x + blockIdx.x) * MAXV;
+        for (int q = 0; q < nact; ++q) p[q] = acc[q];
+    }
+}
+
+// w <- w - sum_i oc_i v~_i  (w = V[j+1]); partial ||w||^2
+template <int NJ>
+__global__ void __launch_bounds__(256) k_ortho(float2* __restrict__ V, size_t vstride, int j, const KState* __restrict__ st,
+                                               int n, double2* __restrict__ parts, int npart,
+                                               const int* __restrict__ active) {
+    __shared__ double2 s_red[4];
+    __shared__ float2 s_oc[NJ];
+    const int r = blockIdx.z;
+    if (!active[r]) return;
+    const size_t nn = (size_t)n * n;
+    const int lane = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nact = j + 1;
+    if (lane < nact) s_oc[lane] = st[r].oc[lane];
+    __syncthreads();
+    const int jj = blockIdx.x * KT_X + threadIdx.x;
+    const int i0 = blockIdx.y * KT_Y + threadIdx.y * KT_ROWS;
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    float2* Vr = V + r * vstride;
+    if (jj < n) {
+        for (int t = 0; t < KT_ROWS; ++t) {
+            const int i = i0 + t;
+            if (i >= n) break;
+            size_t o = (size_t)i * n + jj;
+            float2 w = Vr[(size_t)(j + 1) * nn + o];
+#pragma unroll
+            for (int q = 0; q < NJ; ++q)
+                if (q < nact) w = csub(w, cmul(s_oc[q], Vr[(size_t)q * nn + o]));
+            Vr[(size_t)(j + 1) * nn + o] = w;
+            acc[0].x += (double)w.x * w.x + (double)w.y * w.y;
+        }
+    }
+    block_sum2<1>(acc, 1, s_red);
+    if (lane == 0) parts[(size_t)r * npart + blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
+}
+
+// Sum the dot partials into column j of H (h_ij = sigma_i <v~_i, w>) and set the
+// single-precision orthogonalisation coefficients oc_i = h_ij sigma_i.
+__global__ void __launch_bounds__(256) k_arnoldi_col(const double2* __restrict__ parts, int npart, int j,
+                                                     KState* __restrict__ st, const int* __restrict__ active) {
+    __shared__ double2 s_red[4 * MAXV];
+    const int r = blockIdx.x;
+    if (!active[r]) return;
+    const int nact = j + 1;
+    double2 acc[MAXV];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int p = threadIdx.x; p < npart; p += 256) {
+        const double2* pp = parts + ((size_t)r * npart + p) * MAXV;
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nact) acc[q] = zadd(acc[q], pp[q]);
+    }
+    block_sum2<MAXV>(acc, nact, s_red);
+    if (threadIdx.x == 0) {
+        KState& S = st[r];
+        for (int q = 0; q < nact; ++q) {
+            double sg = S.sig[q];
+            double2 h = make_double2(acc[q].x * sg, acc[q].y * sg);
+            S.H[q][j] = h;
+            S.oc[q] = make_float2((float)(h.x * sg), (float)(h.y * sg));
+        }
+    }
+}
+
+// Norm of the orthogonalised w, Givens update of column j, residual estimate,
+// small triangular solve, per-RHS flags.
+__global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ parts, int npart, int j,
+                                                KState* __restrict__ st, int* __restrict__ active,
+                                                double* __restrict__ hist, int hist_len, double rtol, int max_iters) {
+    __shared__ double2 s_red[4];
+    const int r = blockIdx.x;
+    if (!active[r]) return;
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int p = threadIdx.x; p < npart; p += 256) acc[0] = zadd(acc[0], parts[(size_t)r * npart + p]);
+    block_sum2<1>(acc, 1, s_red);
+    if (threadIdx.x != 0) return;
+    KState& S = st[r];
+    const double hn = sqrt(acc[0].x);
+    S.H[j + 1][j] = make_double2(hn, 0.0);
+    S.sig[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    // apply the previous rotations to column j
+    double2 col[MAXV];
+    for (int i = 0; i <= j + 1; ++i) col[i] = S.H[i][j];
+    for (int i = 0; i < j; ++i) {
+        double c = S.cs[i];
+        double2 s = S.sn[i];
+        double2 a = col[i], b = col[i + 1];
+        col[i] = zadd(make_double2(c * a.x, c * a.y), zmul(s, b));
+        col[i + 1] = zsub(make_double2(c * b.x, c * b.y), zmul(zconj(s), a));
+    }
+    // new rotation zeroing col[j+1]
+    double2 a = col[j], b = col[j + 1];
+    double na = sqrt(zabs2(a)), nb = sqrt(zabs2(b));
+    double c;
+    double2 s;
+    if (nb == 0.0) {
+        c = 1.0;
+        s = make_double2(0.0, 0.0);
+    } else if (na == 0.0) {
+        c = 0.0;
+        s = make_double2(1.0, 0.0);
+    } else {
+        double t = sqrt(na * na + nb * nb);
+        c = na / t;
+        double2 ph = make_double2(a.x / na, a.y / na);
+        s = zmul(ph, make_double2(b.x / t, -b.y / t));
+    }
+    col[j] = zadd(make_double2(c * a.x, c * a.y), zmul(s, b));
+    col[j + 1] = make_double2(0.0, 0.0);
+    S.cs[j] = c;
+    S.sn[j] = s;
+    for (int i = 0; i <= j + 1; ++i) S.H[i][j] = col[i];
+    double2 gj = S.g[j];
+    S.g[j + 1] = zmul(make_double2(-s.x, s.y), gj);  // -conj(s) g_j
+    S.g[j] = make_double2(c * gj.x, c * gj.y);
+    // y = R^{-1} g (upper triangular, size j+1)
+    for (int i = j; i >= 0; --i) {
+        double2 t = S.g[i];
+        for (int q = i + 1; q <= j; ++q) t = zsub(t, zmul(S.H[i][q], S.y[q]));
+        S.y[i] = zdiv(t, S.H[i][i]);
+    }
+    S.k = j + 1;
+    S.iters += 1;
+    const double est = sqrt(zabs2(S.g[j + 1])) / S.bnorm;
+    S.res_est = est;
+    if (hist && S.iters < hist_len) hist[(size_t)r * hist_len + S.iters] = est;
+    bool bad = !(est == est) || !(hn == hn);
+    if (bad) S.breakdown = 1;
+    if (bad || est <= rtol || S.iters >= max_iters || hn == 0.0) active[r] = 0;
+}
+
+// x += sum_{q<k} y_q z_q  (x complex double)
+__global__ void __launch_bounds__(256) k_xupdate(double2* __restrict__ x, const float2* __restrict__ Z, size_t zstride,
+                                                 const KState* __restrict__ st, int n) {
+    __shared__ double2 s_y[HH_MAX_RESTART];
+    __shared__ int s_k;
+    const int r = blockIdx.z;
+    const int lane = threadIdx.x + threadIdx.y * blockDim.x;
+    if (lane == 0) s_k = st[r].breakdown ? 0 : st[r].k;
+    if (lane < HH_MAX_RESTART) s_y[lane] = st[r].y[lane];
+    __syncthreads();
+    const int k = s_k;
+    if (k == 0) return;
+    const size_t nn = (size_t)n * n;
+    const int jj = blockIdx.x * KT_X + threadIdx.x;
+    const int i0 = blockIdx.y * KT_Y + threadIdx.y * KT_ROWS;
+    if (jj >= n) return;
+    for (int t = 0; t < KT_ROWS; ++t) {
+        const int i = i0 + t;
+        if (i >= n) break;
+        size_t o = (size_t)i * n + jj;
+        double2 acc = x[r * nn + o];
+        for (int q = 0; q < k; ++q) {
+            float2 z = Z[r * zstride + (size_t)q * nn + o];
+            acc = zadd(acc, zmul(s_y[q], make_double2(z.x, z.y)));
+        }
+        x[r * nn + o] = acc;
+    }
+}
+
+// ||b|| from partials; zero right-hand sides are finished at once (x = 0).
+__global__ void k_init_state(const double2* __restrict__ parts, int npart, KState* __restrict__ st, int* done,
+                             int* active, double* hist, int hist_len) {
+    __shared__ double2 s_red[4];
+    const int r = blockIdx.x;
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int p = threadIdx.x; p < npart; p += 256) acc[0] = zadd(acc[0], parts[(size_t)r * npart + p]);
+    block_sum2<1>(acc, 1, s_red);
+    if (threadIdx.x != 0) return;
+    KState& S = st[r];
+    {
+        uint64_t* w = reinterpret_cast<uint64_t*>(&S);
+        for (size_t q = 0; q < sizeof(KState) / 8; ++q) w[q] = 0;
+    }
+    S.bnorm = sqrt(acc[0].x);
+    done[r] = S.bnorm == 0.0 ? 1 : 0;
+    if (S.bnorm == 0.0) S.converged = 1;
+    active[r] = 0;
+    if (hist)
+        for (int q = 0; q < hist_len; ++q) hist[(size_t)r * hist_len + q] = -1.0;
+}
+
+// Start of a restart cycle: beta = ||r||, true relative residual, stopping test.
+__global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KState* __restrict__ st, int* done,
+                              int* active, double* hist, int hist_len, double rtol, int max_iters, int fixed) {
+    __shared__ double2 s_red[4];
+    const int r = blockIdx.x;
+    if (done[r]) {
+        if (threadIdx.x == 0) active[r] = 0;
+        return;
+    }
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int p = threadIdx.x; p < npart; p += 256) acc[0] = zadd(acc[0], parts[(size_t)r * npart + p]);
+    block_sum2<1>(acc, 1, s_red);
+    if (threadIdx.x != 0) return;
+    KState& S = st[r];
+    const double beta = sqrt(acc[0].x);
+    S.res_true = beta / S.bnorm;
+    if (hist && S.iters < hist_len) hist[(size_t)r * hist_len + S.iters] = S.res_true;
+    const bool bad = !(beta == beta);
+    if (bad) S.breakdown = 1;
+    if (!fixed && S.res_true <= rtol) S.converged = 1;
+    if (bad || S.converged || S.iters >= max_iters || beta == 0.0) {
+        done[r] = 1;
+        active[r] = 0;
+        return;
+    }
+    S.sig[0] = 1.0 / beta;
+    for (int q = 0; q < MAXV; ++q) S.g[q] = make_double2(0.0, 0.0);
+    S.g[0] = make_double2(beta, 0.0);
+    S.k = 0;
+    active[r] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+template <int NJ>
+static void launch_op_dots_t(dim3 g, dim3 b, hipStream_t s, const float2* Z, size_t zs, float2* V, size_t vs, int j,
+                             const float2* cf, const int* inst, int n, float ih2, double2* parts, int np,
+                             const int* act) {
+    hipLaunchKernelGGL(k_op_dots<NJ>, g, b, 0, s, Z, zs, V, vs, j, cf, inst, n, ih2, parts, np, act);
+}
+template <int NJ>
+static void launch_ortho_t(dim3 g, dim3 b, hipStream_t s, float2* V, size_t vs, int j, const KState* st, int n,
+                           double2* parts, int np, const int* act) {
+    hipLaunchKernelGGL(k_ortho<NJ>, g, b, 0, s, V, vs, j, st, n, parts, np, act);
+}
+
+hh_status SolveWork::prepare(hh_ctx* c, hh_model* md, int nrhs_, int restart_, int hist_len_, bool cnn) {
+    nrhs = nrhs_;
+    restart = restart_;
+    hist_len = hist_len_;
+    n = md->lev[0].n;
+    npart = kblocks(n);
+    const size_t nn = (size_t)n * n;
+    HH_TRY(V.ensure(c, (size_t)nrhs * (restart + 1) * nn * sizeof(float2)));
+    HH_TRY(Z.ensure(c, (size_t)nrhs * restart * nn * sizeof(float2)));
+    HH_TRY(state.ensure(c, (size_t)nrhs * sizeof(KState)));
+    HH_TRY(flags.ensure(c, (size_t)2 * nrhs * sizeof(int)));
+    HH_TRY(parts.ensure(c, (size_t)nrhs * npart * MAXV * sizeof(double2)));
+    HH_TRY(inst.ensure(c, (size_t)nrhs * sizeof(int)));
+    HH_TRY(hist.ensure(c, (size_t)nrhs * hist_len * sizeof(double) + 8));
+    HH_TRY(vwork.ensure(c, vcycle_workspace_bytes(md, nrhs, cnn) + 256));
+    if (cnn) HH_TRY(x0net.ensure(c, (size_t)nrhs * nn * sizeof(float2)));
+    return HH_OK;
+}
+
+hh_status fgmres_solve(hh_model* md, SolveWork& W, const int* inst_dev, const float2* b, double2* x,
+                       const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user) {
+    hh_ctx* ctx = md->ctx;
+    hipStream_t st = ctx->stream;
+    const int n = W.n, nrhs = W.nrhs;
+    const size_t nn = (size_t)n * n;
+    const size_t vstride = (size_t)(W.restart + 1) * nn, zstride = (size_t)W.restart * nn;
+    const dim3 blk(KT_X, KT_Y / KT_ROWS);
+    const dim3 grd((n + KT_X - 1) / KT_X, (n + KT_Y - 1) / KT_Y, nrhs);
+    const int np = W.npart;
+    const Level& L0 = md->lev[0];
+    const float ih2 = (float)(1.0 / (L0.h * L0.h));
+    float2* V = W.V.as<float2>();
+    float2* Z = W.Z.as<float2>();
+    KState* S = W.state.as<KState>();
+    int* done = W.flags.as<int>();
+    int* act = done + nrhs;
+    double2* parts = W.parts.as<double2>();
+    double* hist = W.hist.as<double>();
+    const int sig_stride = (int)(sizeof(KState) / sizeof(double));
+    const bool fixed = o.fixed_iters > 0;
+    const double rtol = fixed ? 0.0 : o.rtol;
+    const int max_iters = fixed ? o.fixed_iters : o.max_iters;
+
+    // ||b||
+    hipLaunchKernelGGL(k_norm2, grd, blk, 0, st, b, n, parts);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_init_state, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist, W.hist_len);
+    HH_LAUNCH_CHECK();
+    if (!o.use_x0) HH_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * nn * sizeof(double2), st));
+
+    std::vector<int> hdone(nrhs);
+    int cycle = 0;
+    for (;;) {
+        {
+            ProfScope ps(ctx, HH_K_RESTART);
+            hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
+                               1.0 / (L0.h * L0.h), parts, done);
+        }
+        HH_LAUNCH_CHECK();
+        {
+            ProfScope ps(ctx, HH_K_SMALL);
+            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist,
+                               W.hist_len, rtol, max_iters, fixed ? 1 : 0);
+        }
+        HH_LAUNCH_CHECK();
+        HH_HIP(hipMemcpyAsync(hdone.data(), done, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+        HH_HIP(hipStreamSynchronize(st));
+        bool all = true;
+        for (int r = 0; r < nrhs; ++r) all = all && hdone[r];
+        if (all) break;
+        const bool use_cnn = precond_cnn && !(cycle == 0 && o.warm_mg_iters > 0);
+        int len = W.restart;
+        if (precond_cnn && cycle == 0 && o.warm_mg_iters > 0) len = std::min(len, o.warm_mg_iters);
+        if (fixed) len = std::min(len, o.fixed_iters);
+        for (int j = 0; j < len; ++j) {
+            const float2* vj = V + (size_t)j * nn;
+            const double* sg = reinterpret_cast<const double*>(reinterpret_cast<const char*>(S) + offsetof(KState, sig)) + j;
+            float2* zj = Z + (size_t)j * nn;
+            // z_j = M(v_j): the preconditioner works on [rhs] vectors with strides; use per-RHS views
+            if (use_cnn) {
+                HH_TRY(precond_cnn(precond_user, md, W, inst_dev, vj, vstride, sg, sig_stride, zj, zstride, act));
+            } else {
+                HH_TRY(precond_mg_strided(md, W, inst_dev, vj, vstride, sg, sig_stride, zj, zstride, act));
+            }
+            // w = A z_j, dots with v_0..v_j
+            {
+            ProfScope ps(ctx, HH_K_OP_DOTS);
+            switch (j + 1) {
+#define HH_OPD(NJ) case NJ: launch_op_dots_t<NJ>(grd, blk, st, zj, zstride, V, vstride, j, L0.coef.as<float2>(), inst_dev, n, ih2, parts, np, act); break;
+                HH_OPD(1) HH_OPD(2) HH_OPD(3) HH_OPD(4) HH_OPD(5) HH_OPD(6) HH_OPD(7) HH_OPD(8)
+                HH_OPD(9) HH_OPD(10) HH_OPD(11) HH_OPD(12) HH_OPD(13) HH_OPD(14) HH_OPD(15) HH_OPD(16)
+#undef HH_OPD
+                default: set_error("restart too long"); return HH_ERR_ARG;
+            }
+            }
+            HH_LAUNCH_CHECK();
+            {
+                ProfScope ps(ctx, HH_K_SMALL);
+                hipLaunchKernelGGL(k_arnoldi_col, dim3(nrhs), dim3(256), 0, st, parts, np, j, S, act);
+            }
+            HH_LAUNCH_CHECK();
+            {
+            ProfScope ps(ctx, HH_K_ORTHO);
+            switch (j + 1) {
+#define HH_ORT(NJ) case NJ: launch_ortho_t<NJ>(grd, blk, st, V, vstride, j, S, n, parts, np, act); break;
+                HH_ORT(1) HH_ORT(2) HH_ORT(3) HH_ORT(4) HH_ORT(5) HH_ORT(6) HH_ORT(7) HH_ORT(8)
+                HH_ORT(9) HH_ORT(10) HH_ORT(11) HH_ORT(12) HH_ORT(13) HH_ORT(14) HH_ORT(15) HH_ORT(16)
+#undef HH_ORT
+                default: set_error("restart too long"); return HH_ERR_ARG;
+            }
+            }
+            HH_LAUNCH_CHECK();
+            {
+                ProfScope ps(ctx, HH_K_SMALL);
+                hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(256), 0, st, parts, np, j, S, act, hist, W.hist_len,
+                                   rtol, max_iters);
+            }
+            HH_LAUNCH_CHECK();
+        }
+        {
+            ProfScope ps(ctx, HH_K_RESTART);
+            hipLaunchKernelGGL(k_xupdate, grd, blk, 0, st, x, Z, zstride, S, n);
+        }
+        HH_LAUNCH_CHECK();
+        ++cycle;
+        if (fixed) {
+            // one cycle only: mark everything done after the final residual
+            hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
+                               1.0 / (L0.h * L0.h), parts, nullptr);
+            HH_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist,
+                               W.hist_len, rtol, 0, 1);
+            HH_LAUNCH_CHECK();
+            break;
+        }
+    }
+    return HH_OK;
+}
+
+// MG-only preconditioner on strided [rhs] views of V and Z
+hh_status precond_mg_strided(hh_model* md, SolveWork& W, const int* inst_dev, const float2* v, size_t vstride,
+                             const double* sig, int sig_stride, float2* z, size_t zstride, const int* act) {
+    return launch_vcycle_strided(md, W.nrhs, inst_dev, v, vstride, sig, sig_stride, nullptr, 0, z, zstride,
+                                 W.vwork.ptr, act);
+}
+
+}  // namespace hh

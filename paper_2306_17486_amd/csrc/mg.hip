@@ -1,0 +1,436 @@
+// Shifted-Laplacian multigrid on gfx950: operator application and one V-cycle
+// (Sec. 3.2, Alg. 1 applied recursively; transfers of eq. 8).
+//
+// Data: complex single precision, [rhs][n][n]; coefficients {omega^2 kappa^2,
+// gamma} per point and level, shared by all right-hand sides of one slowness
+// model.  Each V-cycle level is two fused kernels:
+//   down: x1 = relax(x0) (x0 = 0: x1 = w b / diag); r = b - A_SL x1; b_c = R r
+//   up:   x = x1 + P e_c; z = x + w (b - A_SL x) / diag
+// so the level reads b once in each direction and writes only the coarse
+// right-hand side and the level's result.  The tiles are staged in LDS with the
+// halo the stencil chain needs (2 fine cells for down, 1 for up).
+#include "hh_internal.h"
+
+namespace hh {
+
+// ---------------------------------------------------------------------------
+// y = A x   (A = -Delta_h - omega^2 kappa^2 (1 - i (gamma + shift)))
+// 64 x 16 tile per 256-thread block; each thread walks 4 rows of one column.
+// ---------------------------------------------------------------------------
+constexpr int OP_TX = 64, OP_TY = 16, OP_ROWS = 4;
+
+__global__ void __launch_bounds__(256) k_apply_op(const float2* __restrict__ x, float2* __restrict__ y,
+                                                  const float2* __restrict__ coef, const int* __restrict__ inst,
+                                                  int n, float inv_h2, float shift, const int* __restrict__ active) {
+    const int r = blockIdx.z;
+    if (active && !active[r]) return;
+    const int j = blockIdx.x * OP_TX + threadIdx.x;
+    const int i0 = blockIdx.y * OP_TY + threadIdx.y * OP_ROWS;
+    if (j >= n) return;
+    const size_t nn = (size_t)n * n;
+    const float2* xr = x + r * nn;
+    float2* yr = y + r * nn;
+    const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
+    const float2 zero = make_float2(0.f, 0.f);
+    float2 up = (i0 > 0 && i0 - 1 < n) ? xr[(size_t)(i0 - 1) * n + j] : zero;
+    float2 cur = (i0 < n) ? xr[(size_t)i0 * n + j] : zero;
+#pragma unroll
+    for (int t = 0; t < OP_ROWS; ++t) {
+        const int i = i0 + t;
+        if (i >= n) break;
+        float2 dn = (i + 1 < n) ? xr[(size_t)(i + 1) * n + j] : zero;
+        float2 lf = (j > 0) ? xr[(size_t)i * n + j - 1] : zero;
+        float2 rt = (j + 1 < n) ? xr[(size_t)i * n + j + 1] : zero;
+        float2 m = mass_of(cf[(size_t)i * n + j], shift);
+        float2 lap = make_float2((4.f * cur.x - up.x - dn.x - lf.x - rt.x) * inv_h2,
+                                 (4.f * cur.y - up.y - dn.y - lf.y - rt.y) * inv_h2);
+        yr[(size_t)i * n + j] = csub(lap, cmul(m, cur));
+        up = cur;
+        cur = dn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle down kernel on one level.
+// Block = 256 threads computes a TCY x TCX tile of the coarse right-hand side.
+// HAS_X0: the level has a nonzero initial guess x0 (level 0 of the CNN+MG
+// preconditioner); the relaxed x1 is then also written out for the up kernel.
+// ---------------------------------------------------------------------------
+constexpr int DN_TCX = 32, DN_TCY = 8;
+
+template <bool HAS_X0>
+__global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, size_t bstride,
+                                                 const double* __restrict__ sig, int sig_stride,
+                                                 const float2* __restrict__ x0, size_t x0stride,
+                                                 float2* __restrict__ x1out, float2* __restrict__ bc,
+                                                 const float2* __restrict__ coef, const int* __restrict__ inst,
+                                                 int n, float inv_h2, float beta, float wj,
+                                                 const int* __restrict__ active) {
+    constexpr int HALO = HAS_X0 ? 3 : 2;
+    constexpr int PH = 2 * DN_TCY + 2 * HALO - 1;  // fine rows 2I0-HALO .. 2I0+2TCY+HALO-2
+    constexpr int PW = 2 * DN_TCX + 2 * HALO - 1;
+    __shared__ float2 s_b[PH][PW];   // b, later r
+    __shared__ float2 s_x[PH][PW];   // x1 (relaxed)
+    __shared__ float2 s_m[PH][PW];   // shifted mass
+    __shared__ float2 s_x0[HAS_X0 ? PH : 1][HAS_X0 ? PW : 1];
+
+    const int r = blockIdx.z;
+    if (active && !active[r]) return;
+    const int tid = threadIdx.x;
+    const int nc = n >> 1;
+    const int I0 = blockIdx.y * DN_TCY, J0 = blockIdx.x * DN_TCX;
+    const int fy0 = 2 * I0 - HALO, fx0 = 2 * J0 - HALO;
+    const size_t nn = (size_t)n * n;
+    const float2* br = b + r * bstride;
+    const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
+    const float s = sig ? (float)sig[(size_t)r * sig_stride] : 1.0f;
+    const float dgv = 4.f * inv_h2;
+    const float2 zero = make_float2(0.f, 0.f);
+
+    // stage b (scaled), the shifted mass and x0
+    for (int e = tid; e < PH * PW; e += 256) {
+        int py = e / PW, px = e - py * PW;
+        int gi = fy0 + py, gj = fx0 + px;
+        bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
+        size_t o = (size_t)gi * n + gj;
+        float2 bv = in ? cscale(br[o], s) : zero;
+        float2 mv = in ? mass_of(cf[o], beta) : zero;
+        s_b[py][px] = bv;
+        s_m[py][px] = mv;
+        if (HAS_X0) {
+            s_x0[py][px] = in ? x0[r * x0stride + o] : zero;
+        } else {
+            // x1 = w b / diag with diag = 4/h^2 - mass
+            float2 d = make_float2(dgv - mv.x, -mv.y);
+            s_x[py][px] = in ? cscale(cdiv(bv, d), wj) : zero;
+        }
+    }
+    __syncthreads();
+    if (HAS_X0) {
+        // x1 = x0 + w (b - A_SL x0)/diag on rows/cols 1..P-2
+        for (int e = tid; e < PH * PW; e += 256) {
+            int py = e / PW, px = e - py * PW;
+            int gi = fy0 + py, gj = fx0 + px;
+            bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
+            float2 v = zero;
+            if (in && py > 0 && py < PH - 1 && px > 0 && px < PW - 1) {
+                float2 c = s_x0[py][px];
+                float2 nb = cadd(cadd(s_x0[py - 1][px], s_x0[py + 1][px]), cadd(s_x0[py][px - 1], s_x0[py][px + 1]));
+                float2 mv = s_m[py][px];
+                float2 Ax = csub(make_float2((4.f * c.x - nb.x) * inv_h2, (4.f * c.y - nb.y) * inv_h2), cmul(mv, c));
+                float2 d = make_float2(dgv - mv.x, -mv.y);
+                v = cadd(c, cscale(cdiv(csub(s_b[py][px], Ax), d), wj));
+            }
+            s_x[py][px] = v;
+        }
+        __syncthreads();
+        // write x1 on the fine cells this tile owns: rows 2I0 .. 2I0+2TCY-1
+        for (int e = tid; e < 4 * DN_TCY * DN_TCX; e += 256) {
+            int ly = e / (2 * DN_TCX), lx = e - ly * (2 * DN_TCX);
+            int gi = 2 * I0 + ly, gj = 2 * J0 + lx;
+            if (gi < n && gj < n) x1out[r * nn + (size_t)gi * n + gj] = s_x[ly + HALO][lx + HALO];
+        }
+    }
+    // residual r = b - A_SL x1 on rows/cols R0 .. P-1-R0 (the FW support)
+    constexpr int R0 = HALO - 1;
+    for (int e = tid; e < PH * PW; e += 256) {
+        int py = e / PW, px = e - py * PW;
+        if (py < R0 || py > PH - 1 - R0 || px < R0 || px > PW - 1 - R0) continue;
+        int gi = fy0 + py, gj = fx0 + px;
+        bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
+        float2 rv = zero;
+        if (in) {
+            float2 c = s_x[py][px];
+            float2 nb = cadd(cadd(s_x[py - 1][px], s_x[py + 1][px]), cadd(s_x[py][px - 1], s_x[py][px + 1]));
+            float2 Ax = csub(make_float2((4.f * c.x - nb.x) * inv_h2, (4.f * c.y - nb.y) * inv_h2), cmul(s_m[py][px], c));
+            rv = csub(s_b[py][px], Ax);
+        }
+        s_b[py][px] = rv;  // only this thread reads s_b at (py, px) in this phase
+    }
+    __syncthreads();
+    // full-weighting restriction: coarse (I, J) <- fine 2I + a - 1, 2J + c - 1
+    {
+        int cy = tid / DN_TCX, cx = tid - cy * DN_TCX;
+        int I = I0 + cy, J = J0 + cx;
+        if (I < nc && J < nc) {
+            int py = 2 * cy + HALO - 1, px = 2 * cx + HALO - 1;
+            const float w1[3] = {0.25f, 0.5f, 0.25f};
+            float2 acc = zero;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc = cadd(acc, cscale(s_b[py + a][px + c], w1[a] * w1[c]));
+            bc[(size_t)r * nc * nc + (size_t)I * nc + J] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle up kernel on one level: prolong + correct + post-relaxation.
+// Block = 256 threads computes a TY x TX fine tile.  HAS_X1: the relaxed x1 was
+// stored by the down kernel; otherwise x1 = w b / diag is recomputed.
+// ---------------------------------------------------------------------------
+constexpr int UP_TX = 64, UP_TY = 16;
+
+template <bool HAS_X1>
+__global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, size_t bstride,
+                                               const double* __restrict__ sig, int sig_stride,
+                                               const float2* __restrict__ x1, const float2* __restrict__ ec,
+                                               float2* __restrict__ z, size_t zstride,
+                                               const float2* __restrict__ coef, const int* __restrict__ inst,
+                                               int n, float inv_h2, float beta, float wj,
+                                               const int* __restrict__ active) {
+    constexpr int PH = UP_TY + 2, PW = UP_TX + 2;
+    constexpr int CH = UP_TY / 2 + 2, CW = UP_TX / 2 + 2;
+    __shared__ float2 s_b[PH][PW];
+    __shared__ float2 s_x[PH][PW];
+    __shared__ float2 s_m[PH][PW];
+    __shared__ float2 s_e[CH][CW];
+
+    const int r = blockIdx.z;
+    if (active && !active[r]) return;
+    const int tid = threadIdx.x;
+    const int nc = n >> 1;
+    const int y0 = blockIdx.y * UP_TY, x0 = blockIdx.x * UP_TX;
+    const int cy0 = y0 / 2 - 1, cx0 = x0 / 2 - 1;
+    const size_t nn = (size_t)n * n;
+    const float2* br = b + r * bstride;
+    const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
+    const float2* er = ec + (size_t)r * nc * nc;
+    const float s = sig ? (float)sig[(size_t)r * sig_stride] : 1.0f;
+    const float dg = 4.f * inv_h2;
+    const float2 zero = make_float2(0.f, 0.f);
+
+    for (int e = tid; e < CH * CW; e += 256) {
+        int py = e / CW, px = e - py * CW;
+        int I = cy0 + py, J = cx0 + px;
+        s_e[py][px] = (I >= 0 && I < nc && J >= 0 && J < nc) ? er[(size_t)I * nc + J] : zero;
+    }
+    __syncthreads();
+    for (int e = tid; e < PH * PW; e += 256) {
+        int py = e / PW, px = e - py * PW;
+        int gi = y0 - 1 + py, gj = x0 - 1 + px;
+        bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
+        float2 bv = zero, mv = zero, xv = zero;
+        if (in) {
+            size_t o = (size_t)gi * n + gj;
+            bv = cscale(br[o], s);
+            mv = mass_of(cf[o], beta);
+            if (HAS_X1) {
+                xv = x1[r * nn + o];
+            } else {
+                xv = cscale(cdiv(bv, make_float2(dg - mv.x, -mv.y)), wj);
+            }
+            // bilinear prolongation: even index -> coarse i/2; odd -> mean of (i-1)/2, (i+1)/2
+            int ly = (gi >> 1) - cy0, lx = (gj >> 1) - cx0;
+            float2 pe;
+            if (!(gi & 1) && !(gj & 1)) {
+                pe = s_e[ly][lx];
+            } else if (!(gi & 1)) {
+                pe = cscale(cadd(s_e[ly][lx], s_e[ly][lx + 1]), 0.5f);
+            } else if (!(gj & 1)) {
+                pe = cscale(cadd(s_e[ly][lx], s_e[ly + 1][lx]), 0.5f);
+            } else {
+                pe = cscale(cadd(cadd(s_e[ly][lx], s_e[ly][lx + 1]), cadd(s_e[ly + 1][lx], s_e[ly + 1][lx + 1])), 0.25f);
+            }
+            xv = cadd(xv, pe);
+        }
+        s_b[py][px] = bv;
+        s_m[py][px] = mv;
+        s_x[py][px] = xv;
+    }
+    __syncthreads();
+    for (int e = tid; e < UP_TY * UP_TX; e += 256) {
+        int ly = e / UP_TX, lx = e - ly * UP_TX;
+        int gi = y0 + ly, gj = x0 + lx;
+        if (gi >= n || gj >= n) continue;
+        int py = ly + 1, px = lx + 1;
+        float2 c = s_x[py][px];
+        float2 nb = cadd(cadd(s_x[py - 1][px], s_x[py + 1][px]), cadd(s_x[py][px - 1], s_x[py][px + 1]));
+        float2 mv = s_m[py][px];
+        float2 Ax = csub(make_float2((4.f * c.x - nb.x) * inv_h2, (4.f * c.y - nb.y) * inv_h2), cmul(mv, c));
+        float2 d = make_float2(dg - mv.x, -mv.y);
+        z[r * zstride + (size_t)gi * n + gj] = cadd(c, cscale(cdiv(csub(s_b[py][px], Ax), d), wj));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest-level exact solve with the stored Schur inverses (see setup.hip):
+//   forward  w_k = b_k + c y_{k-1},  y_k = Q_k w_k
+//   backward x_{m-1} = y_{m-1},      x_k = y_k + c Q_k x_{k+1}
+// One 256-thread block per right-hand side; thread i owns grid column i (and
+// i + 256, ...).  QT is stored transposed so that the reads of one step are
+// contiguous across threads.
+// ---------------------------------------------------------------------------
+constexpr int CS_MAXM = 1024;
+
+__global__ void __launch_bounds__(256) k_coarse_solve(const float2* __restrict__ bcs, float2* __restrict__ x,
+                                                      const float2* __restrict__ QT, const int* __restrict__ inst,
+                                                      int m, float c, const int* __restrict__ active) {
+    __shared__ float2 s_v[CS_MAXM];
+    const int r = blockIdx.x;
+    if (active && !active[r]) return;
+    const int tid = threadIdx.x;
+    const size_t mm = (size_t)m * m;
+    const float2* Q = QT + (size_t)(inst ? inst[r] : 0) * mm * m;
+    const float2* br = bcs + r * mm;
+    float2* xr = x + r * mm;
+    const float2 zero = make_float2(0.f, 0.f);
+    // forward sweep; y_k is written to x (row k) and kept in LDS for the next step
+    for (int k = 0; k < m; ++k) {
+        for (int i = tid; i < m; i += 256) {
+            float2 w = br[(size_t)k * m + i];
+            if (k > 0) w = cadd(w, cscale(s_v[i], c));
+            s_v[i] = w;  // safe: each thread only touches its own entries until the barrier
+        }
+        __syncthreads();
+        float2 acc[CS_MAXM / 256];
+#pragma unroll
+        for (int t = 0; t < CS_MAXM / 256; ++t) acc[t] = zero;
+        const float2* Qk = Q + (size_t)k * mm;
+        for (int jj = 0; jj < m; ++jj) {
+            float2 wj = s_v[jj];
+#pragma unroll
+            for (int t = 0; t < CS_MAXM / 256; ++t) {
+                int i = tid + 256 * t;
+                if (i < m) acc[t] = cadd(acc[t], cmul(Qk[(size_t)jj * m + i], wj));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < CS_MAXM / 256; ++t) {
+            int i = tid + 256 * t;
+            if (i < m) {
+                s_v[i] = acc[t];
+                xr[(size_t)k * m + i] = acc[t];
+            }
+        }
+        __syncthreads();
+    }
+    // backward sweep; s_v holds x_{k+1}
+    for (int k = m - 2; k >= 0; --k) {
+        float2 acc[CS_MAXM / 256];
+#pragma unroll
+        for (int t = 0; t < CS_MAXM / 256; ++t) acc[t] = zero;
+        const float2* Qk = Q + (size_t)k * mm;
+        for (int jj = 0; jj < m; ++jj) {
+            float2 tj = s_v[jj];
+#pragma unroll
+            for (int t = 0; t < CS_MAXM / 256; ++t) {
+                int i = tid + 256 * t;
+                if (i < m) acc[t] = cadd(acc[t], cmul(Qk[(size_t)jj * m + i], tj));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < CS_MAXM / 256; ++t) {
+            int i = tid + 256 * t;
+            if (i < m) {
+                float2 v = cadd(xr[(size_t)k * m + i], cscale(acc[t], c));
+                s_v[i] = v;
+                xr[(size_t)k * m + i] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hh_status launch_apply_op(hh_model* md, int level, float shift, int nrhs, const int* inst_dev,
+                          const float2* x, float2* y, const int* active) {
+    const Level& L = md->lev[level];
+    ProfScope ps(md->ctx, HH_K_OPERATOR);
+    dim3 blk(OP_TX, OP_TY / OP_ROWS), grd((L.n + OP_TX - 1) / OP_TX, (L.n + OP_TY - 1) / OP_TY, nrhs);
+    hipLaunchKernelGGL(k_apply_op, grd, blk, 0, md->ctx->stream, x, y, L.coef.as<float2>(), inst_dev, L.n,
+                       (float)(1.0 / (L.h * L.h)), shift, active);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+// workspace: per level l >= 1: b_l and e_l [nrhs][n_l][n_l]; plus x1 [nrhs][n][n] if with_x0
+size_t vcycle_workspace_bytes(const hh_model* md, int nrhs, bool with_x0) {
+    size_t bytes = 0;
+    for (int l = 1; l < md->nlev; ++l) bytes += 2 * (size_t)nrhs * md->lev[l].n * md->lev[l].n * sizeof(float2);
+    if (with_x0) bytes += (size_t)nrhs * md->lev[0].n * md->lev[0].n * sizeof(float2);
+    return bytes;
+}
+
+hh_status launch_vcycle_strided(hh_model* md, int nrhs, const int* inst_dev, const float2* b, size_t bstride,
+                                const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
+                                size_t zstride, void* work, const int* active) {
+    hipStream_t st = md->ctx->stream;
+    const float beta = (float)md->d.sl_beta, wj = (float)md->d.jacobi_w;
+    const int L = md->nlev;
+    float2* bl[HH_MAX_LEVELS] = {nullptr};
+    float2* el[HH_MAX_LEVELS] = {nullptr};
+    char* p = (char*)work;
+    for (int l = 1; l < L; ++l) {
+        size_t sz = (size_t)nrhs * md->lev[l].n * md->lev[l].n * sizeof(float2);
+        bl[l] = (float2*)p;
+        p += sz;
+        el[l] = (float2*)p;
+        p += sz;
+    }
+    float2* x1 = x0 ? (float2*)p : nullptr;
+    // down sweep
+    for (int l = 0; l < L - 1; ++l) {
+        const Level& lv = md->lev[l];
+        const int nc = lv.n / 2;
+        const size_t nl = (size_t)lv.n * lv.n;
+        dim3 grd((nc + DN_TCX - 1) / DN_TCX, (nc + DN_TCY - 1) / DN_TCY, nrhs);
+        const float2* bin = (l == 0) ? b : bl[l];
+        const size_t bs = (l == 0) ? bstride : nl;
+        const double* sg = (l == 0) ? sig : nullptr;
+        const float ih2 = (float)(1.0 / (lv.h * lv.h));
+        ProfScope ps(md->ctx, l == 0 ? HH_K_VC_DOWN : HH_K_VC_MID);
+        if (l == 0 && x0) {
+            hipLaunchKernelGGL(k_vc_down<true>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x0, x0stride, x1,
+                               bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active);
+        } else {
+            hipLaunchKernelGGL(k_vc_down<false>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
+                               (size_t)0, nullptr, bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta,
+                               wj, active);
+        }
+        HH_LAUNCH_CHECK();
+    }
+    // coarsest exact solve
+    {
+        const Level& lc = md->lev[L - 1];
+        ProfScope ps(md->ctx, HH_K_VC_COARSE);
+        hipLaunchKernelGGL(k_coarse_solve, dim3(nrhs), dim3(256), 0, st, bl[L - 1], el[L - 1],
+                           md->coarseQT.as<float2>(), inst_dev, lc.n, (float)(1.0 / (lc.h * lc.h)), active);
+        HH_LAUNCH_CHECK();
+    }
+    // up sweep
+    for (int l = L - 2; l >= 0; --l) {
+        const Level& lv = md->lev[l];
+        const size_t nl = (size_t)lv.n * lv.n;
+        dim3 grd((lv.n + UP_TX - 1) / UP_TX, (lv.n + UP_TY - 1) / UP_TY, nrhs);
+        const float2* bin = (l == 0) ? b : bl[l];
+        const size_t bs = (l == 0) ? bstride : nl;
+        const double* sg = (l == 0) ? sig : nullptr;
+        float2* out = (l == 0) ? z : el[l];
+        const size_t os = (l == 0) ? zstride : nl;
+        const float ih2 = (float)(1.0 / (lv.h * lv.h));
+        ProfScope ps(md->ctx, l == 0 ? HH_K_VC_UP : HH_K_VC_MID);
+        if (l == 0 && x0) {
+            hipLaunchKernelGGL(k_vc_up<true>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x1, el[l + 1], out,
+                               os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active);
+        } else {
+            hipLaunchKernelGGL(k_vc_up<false>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
+                               el[l + 1], out, os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active);
+        }
+        HH_LAUNCH_CHECK();
+    }
+    return HH_OK;
+}
+
+hh_status launch_vcycle(hh_model* md, int nrhs, const int* inst_dev, const float2* b, const double* sig,
+                        int sig_stride, const float2* x0, float2* z, void* work, const int* active) {
+    const size_t nn = (size_t)md->lev[0].n * md->lev[0].n;
+    return launch_vcycle_strided(md, nrhs, inst_dev, b, nn, sig, sig_stride, x0, nn, z, nn, work, active);
+}
+
+}  // namespace hh

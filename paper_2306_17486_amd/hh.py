@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libhh (include/hh.h).
+
+Functions named ``hh_*`` mirror the C entry points one to one and only marshal
+arguments.  The small ``Context`` / ``Model`` / ``Net`` wrappers take torch
+tensors, pass their device pointers and return results; every numerical step
+runs in the library's HIP kernels.  There is no fallback: if ``libhh.so`` is
+missing or cannot be loaded, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhh.so")
+
+HH_OK = 0
+HH_NOT_CONVERGED = 1
+HH_ERR_ARG = -1
+HH_ERR_HIP = -2
+HH_ERR_NOMEM = -3
+HH_ERR_STATE = -4
+HH_ERR_BREAKDOWN = -5
+HH_PRECOND_MG = 0
+HH_PRECOND_CNN_MG = 1
+
+
+class HHError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libhh error {status}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_17486_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+
+class hh_model_desc(C.Structure):
+    _fields_ = [("n", C.c_int), ("omega", C.c_double), ("abl_width", C.c_int), ("abl_gamma_max", C.c_double),
+                ("gamma0", C.c_double), ("sl_beta", C.c_double), ("levels", C.c_int), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("jacobi_w", C.c_double)]
+
+
+class hh_solve_opts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("rtol", C.c_double), ("precond", C.c_int),
+                ("warm_mg_iters", C.c_int), ("use_x0", C.c_int), ("fixed_iters", C.c_int)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_P = C.c_void_p
+_I = C.c_int
+_D = C.c_double
+_IP = C.POINTER(C.c_int)
+_DP = C.POINTER(C.c_double)
+
+
+def _sig(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+hh_version = _sig("hh_version", C.c_char_p)
+hh_last_error = _sig("hh_last_error", C.c_char_p)
+hh_ctx_create = _sig("hh_ctx_create", _I, _I, _P, ALLOC_FN, FREE_FN, _P, C.POINTER(_P))
+hh_ctx_destroy = _sig("hh_ctx_destroy", _I, _P)
+hh_model_desc_default = _sig("hh_model_desc_default", None, C.POINTER(hh_model_desc))
+hh_model_create = _sig("hh_model_create", _I, _P, C.POINTER(hh_model_desc), _I, _P, C.POINTER(_P))
+hh_model_destroy = _sig("hh_model_destroy", _I, _P)
+hh_solve_opts_default = _sig("hh_solve_opts_default", None, C.POINTER(hh_solve_opts))
+hh_solve = _sig("hh_solve", _I, _P, _P, _I, _IP, _P, _P, C.POINTER(hh_solve_opts), _DP, _IP, _IP, _DP)
+hh_apply_operator = _sig("hh_apply_operator", _I, _P, _I, _D, _I, _IP, _P, _P)
+hh_apply_vcycle = _sig("hh_apply_vcycle", _I, _P, _I, _IP, _P, _P, _P)
+hh_profile_begin = _sig("hh_profile_begin", _I, _P, _I)
+hh_profile_end = _sig("hh_profile_end", _I, _P, _DP, C.POINTER(C.c_longlong))
+HH_K_NUM_CLASSES = 11
+
+# kernel classes for hh_profile_begin
+HH_K_OPERATOR, HH_K_VC_DOWN, HH_K_VC_UP, HH_K_VC_COARSE, HH_K_VC_MID, HH_K_OP_DOTS, HH_K_ORTHO, HH_K_SMALL, \
+    HH_K_RESTART, HH_K_CONV, HH_K_NET_OTHER = range(11)
+KERNEL_CLASS_NAMES = ["operator", "vc_down", "vc_up", "vc_coarse", "vc_mid", "op_dots", "ortho", "small",
+                      "restart", "conv", "net_other"]
+
+
+def check(status: int, allow=(HH_OK,)) -> int:
+    if status in allow:
+        return status
+    raise HHError(status, (hh_last_error() or b"").decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous and on the GPU"
+    return C.c_void_p(t.data_ptr())
+
+
+def _int_array(vals):
+    if vals is None:
+        return None
+    a = (C.c_int * len(vals))(*[int(v) for v in vals])
+    return a
+
+
+# ---------------------------------------------------------------------------
+# torch-facing wrappers
+# ---------------------------------------------------------------------------
+
+class Context:
+    """A libhh context on one device and torch's current stream; device memory
+    comes from torch's caching allocator through the allocator callbacks."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = device
+        self.stream = stream or torch.cuda.current_stream(device)
+        dev = device
+
+        def _alloc(nbytes, user):
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self.stream)
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        h = C.c_void_p()
+        check(hh_ctx_create(device, C.c_void_p(self.stream.cuda_stream), self._alloc, self._free, None, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            hh_ctx_destroy(self.handle)
+            self.handle = None
+
+    def profile_begin(self, cls: int = HH_K_NUM_CLASSES):
+        check(hh_profile_begin(self.handle, cls))
+
+    def profile_end(self):
+        """{class name: (total kernel ms, timed launches)} since profile_begin."""
+        ms = (C.c_double * HH_K_NUM_CLASSES)()
+        cnt = (C.c_longlong * HH_K_NUM_CLASSES)()
+        check(hh_profile_end(self.handle, ms, cnt))
+        return {KERNEL_CLASS_NAMES[k]: (ms[k], cnt[k]) for k in range(HH_K_NUM_CLASSES) if cnt[k]}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def model_desc(n: int, omega: float, **kw) -> hh_model_desc:
+    d = hh_model_desc()
+    hh_model_desc_default(C.byref(d))
+    d.n = n
+    d.omega = omega
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+class Model:
+    """Slowness model(s) on an n x n grid: kappa is a (ninst, n, n) or (n, n) tensor."""
+
+    def __init__(self, ctx: Context, kappa: torch.Tensor, omega: float, **desc_kw):
+        k = kappa.to(device=f"cuda:{ctx.device}", dtype=torch.float32).contiguous()
+        if k.dim() == 2:
+            k = k[None]
+        self.ctx, self.n, self.ninst = ctx, k.shape[-1], k.shape[0]
+        self.desc = model_desc(self.n, omega, **desc_kw)
+        h = C.c_void_p()
+        check(hh_model_create(ctx.handle, C.byref(self.desc), self.ninst, _ptr(k), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            hh_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- parity-test building blocks --------------------------------------
+    def apply_operator(self, x: torch.Tensor, level: int = 0, shift: float = 0.0, inst=None) -> torch.Tensor:
+        x = x.to(torch.complex64).contiguous()
+        y = torch.empty_like(x)
+        nrhs = x.shape[0]
+        check(hh_apply_operator(self.handle, level, shift, nrhs, _int_array(inst), _ptr(x), _ptr(y)))
+        return y
+
+    def apply_vcycle(self, b: torch.Tensor, x0: torch.Tensor | None = None, inst=None) -> torch.Tensor:
+        b = b.to(torch.complex64).contiguous()
+        x0 = None if x0 is None else x0.to(torch.complex64).contiguous()
+        x = torch.empty_like(b)
+        check(hh_apply_vcycle(self.handle, b.shape[0], _int_array(inst), _ptr(b), _ptr(x0), _ptr(x)))
+        return x
+
+    # -- solve --------------------------------------------------------------
+    def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, inst=None, restart=10, max_iters=2000,
+              rtol=1e-6, precond=HH_PRECOND_MG, warm_mg_iters=3, fixed_iters=0, want_hist=True):
+        """Returns (x complex128 tensor, info dict with iters, converged, final_res, hist)."""
+        b = b.to(torch.complex64).contiguous()
+        nrhs = b.shape[0]
+        if x0 is not None:
+            x = x0.to(torch.complex128).contiguous().clone()
+        else:
+            x = torch.empty(b.shape, dtype=torch.complex128, device=b.device)
+        o = hh_solve_opts()
+        hh_solve_opts_default(C.byref(o))
+        o.restart, o.max_iters, o.rtol, o.precond = restart, max_iters, rtol, precond
+        o.warm_mg_iters, o.use_x0, o.fixed_iters = warm_mg_iters, int(x0 is not None), fixed_iters
+        hl = (fixed_iters if fixed_iters > 0 else max_iters) + 1
+        hist = np.zeros((nrhs, hl)) if want_hist else None
+        iters = np.zeros(nrhs, dtype=np.int32)
+        conv = np.zeros(nrhs, dtype=np.int32)
+        fres = np.zeros(nrhs)
+        st = hh_solve(self.ctx.handle, self.handle, nrhs, _int_array(inst), _ptr(b), _ptr(x), C.byref(o),
+                      hist.ctypes.data_as(_DP) if hist is not None else None, iters.ctypes.data_as(_IP),
+                      conv.ctypes.data_as(_IP), fres.ctypes.data_as(_DP))
+        check(st, allow=(HH_OK, HH_NOT_CONVERGED))
+        return x, dict(iters=iters, converged=conv.astype(bool), final_res=fres, hist=hist, status=st)

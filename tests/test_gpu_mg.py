@@ -1,0 +1,171 @@
+"""GPU parity of the operator, the V-cycle and MG-only FGMRES against the FP64 oracle.
+
+Called through the C ABI (ctypes binding).  Sizes span several tiles and a
+ragged tail (n = 100 is not a multiple of the 64 x 16 tiles)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import helmholtz as H
+from paper_2306_17486_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hh():
+    from paper_2306_17486_amd import hh as _hh
+    return _hh
+
+
+@pytest.fixture(scope="module")
+def ctx(hh):
+    return hh.Context(0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _dev(a, dtype=torch.complex64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda:0", dtype=dtype)
+
+
+@pytest.mark.parametrize("n,family", [(128, "grf"), (100, "layered")])
+def test_operator_all_levels(hh, ctx, n, family):
+    _say(f"operator parity n={n} {family}")
+    k = inputs.slowness(n, 11, family)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    for lvl, L in enumerate(prob.hier.levels):
+        x = inputs.random_complex((2, L.n, L.n), 20 + lvl)
+        for shift in (0.0, 0.5):
+            y = m.apply_operator(_dev(x), level=lvl, shift=shift).cpu().numpy()
+            ref = np.stack([H.apply_op(x[i], L.k2w2, L.gamma, L.h, shift) for i in range(2)])
+            assert _rel(y, ref) <= 2e-6, (lvl, shift, _rel(y, ref))
+
+
+def test_operator_complex_symmetry(hh, ctx):
+    n = 96
+    _say("operator bilinear symmetry")
+    k = inputs.grf_slowness(n, 3)
+    m = hh.Model(ctx, torch.from_numpy(k), inputs.omega_for(n, k))
+    x = inputs.random_complex((1, n, n), 1)
+    y = inputs.random_complex((1, n, n), 2)
+    Ax = m.apply_operator(_dev(x)).cpu().numpy().astype(np.complex128)
+    Ay = m.apply_operator(_dev(y)).cpu().numpy().astype(np.complex128)
+    lhs, rhs = np.sum(y * Ax), np.sum(x * Ay)
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
+
+
+@pytest.mark.parametrize("n,family,with_x0", [(128, "grf", False), (100, "layered", False),
+                                              (128, "layered", True), (100, "grf", True)])
+def test_vcycle_parity(hh, ctx, n, family, with_x0):
+    _say(f"vcycle parity n={n} {family} x0={with_x0}")
+    k = inputs.slowness(n, 12, family)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    b = inputs.random_complex((3, n, n), 5)
+    x0 = inputs.random_complex((3, n, n), 6) * 1e-4 if with_x0 else None
+    z = m.apply_vcycle(_dev(b), None if x0 is None else _dev(x0)).cpu().numpy()
+    ref = np.stack([prob.hier.vcycle(b[i], None if x0 is None else x0[i]) for i in range(3)])
+    assert _rel(z, ref) <= 2e-5, _rel(z, ref)
+
+
+def test_vcycle_multi_instance(hh, ctx):
+    n = 64
+    _say("vcycle two slowness models")
+    ks = [inputs.grf_slowness(n, 1), inputs.layered_slowness(n, 2)]
+    om = inputs.omega_for(n)
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om)
+    b = inputs.random_complex((4, n, n), 7)
+    inst = [1, 0, 0, 1]
+    z = m.apply_vcycle(_dev(b), inst=inst).cpu().numpy()
+    for r in range(4):
+        prob = H.Problem(ks[inst[r]], om)
+        assert _rel(z[r], prob.hier.vcycle(b[r])) <= 2e-5
+
+
+def test_fgmres_mg_config1(hh, ctx):
+    """128^2 GRF (seed 1000), one unit point source (seed 3000), FGMRES(10) + SL V-cycle,
+    rtol 1e-6: iteration count within 2 of the oracle, solution within 1e-5 of the
+    exact discrete solution, FP64 residual <= 1e-6 recomputed here."""
+    n = 128
+    _say("fgmres config 1")
+    k = inputs.grf_slowness(n, 1000)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    b = inputs.point_source(n, 3000)
+    xo, its_o, _, _ = H.solve_mg(prob, b)
+    xs = H.exact_solve(prob, b)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    x, info = m.solve(_dev(b[None]))
+    x = x.cpu().numpy()[0]
+    _say("gpu iters", info["iters"][0], "oracle", its_o, "final", info["final_res"][0])
+    assert info["converged"][0]
+    assert abs(int(info["iters"][0]) - its_o) <= 2
+    assert np.linalg.norm(b - prob.A(x)) / np.linalg.norm(b) <= 1e-6
+    assert _rel(x, xs) <= 1e-5
+    h = info["hist"][0]
+    assert h[0] == pytest.approx(1.0) and h[info["iters"][0] + 1:].max() == -1.0
+
+
+def test_fgmres_batch_instances_and_edge_cases(hh, ctx):
+    n = 64
+    _say("fgmres batch with two models, a zero rhs and an iteration cap")
+    ks = [inputs.grf_slowness(n, 4), inputs.layered_slowness(n, 5)]
+    om = inputs.omega_for(n)
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om)
+    b = np.stack([inputs.point_source(n, 30), inputs.point_source(n, 31), np.zeros((n, n)),
+                  inputs.random_complex((n, n), 32)])
+    inst = [0, 1, 0, 1]
+    x, info = m.solve(_dev(b), inst=inst)
+    x = x.cpu().numpy()
+    for r in (0, 1, 3):
+        prob = H.Problem(ks[inst[r]], om)
+        assert info["converged"][r]
+        assert np.linalg.norm(b[r] - prob.A(x[r])) / np.linalg.norm(b[r]) <= 1e-6
+        _, its_o, _, _ = H.solve_mg(prob, b[r])
+        assert abs(int(info["iters"][r]) - its_o) <= 2
+    assert info["converged"][2] and info["iters"][2] == 0 and np.abs(x[2]).max() == 0.0
+    # iteration cap
+    x, info = m.solve(_dev(b[:2]), inst=inst[:2], max_iters=5)
+    assert info["status"] == hh.HH_NOT_CONVERGED
+    assert list(info["iters"]) == [5, 5] and not info["converged"].any()
+
+
+def test_fgmres_fixed_iterations_match_oracle(hh, ctx):
+    """fixed_iters = k reproduces eq. 20's x~ (k MG-preconditioned iterations from 0)."""
+    n = 64
+    _say("fgmres fixed iterations")
+    k = inputs.layered_slowness(n, 8)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om, gamma0=0.05)
+    m = hh.Model(ctx, torch.from_numpy(k), om, gamma0=0.05)
+    xr = inputs.random_complex((n, n), 9)
+    b = prob.A(xr)
+    for kk in (2, 5, 8):
+        xo, _, _, _ = H.fgmres(prob.A, b, prob.mg, None, 10, 0.0, kk)
+        x, info = m.solve(_dev(b[None]), fixed_iters=kk)
+        assert info["iters"][0] == kk
+        assert _rel(x.cpu().numpy()[0], xo) <= 1e-4
+
+
+def test_bad_arguments_raise(hh, ctx):
+    with pytest.raises(hh.HHError):
+        hh.Model(ctx, torch.ones(30, 30), 10.0)  # 30 not divisible by 4
+    k = torch.from_numpy(inputs.grf_slowness(32, 1))
+    m = hh.Model(ctx, k, 20.0)
+    with pytest.raises(hh.HHError):
+        m.solve(_dev(np.zeros((1, 32, 32))), restart=40)
+    with pytest.raises(hh.HHError):
+        m.solve(_dev(np.zeros((1, 32, 32))), precond=hh.HH_PRECOND_CNN_MG)
