@@ -48,23 +48,39 @@ void dfree(hh_ctx* c, void* p) {
         (void)hipFree(p);
 }
 
-// Copy a host int[nrhs] RHS -> instance map to the device (NULL = all zeros).
-static hh_status upload_inst(hh_model* m, Buf& buf, int nrhs, const int* inst_host, const int** out) {
-    *out = nullptr;
-    if (!inst_host) {
-        if (m->ninst > 1) {
-            HH_TRY(buf.ensure(m->ctx, (size_t)nrhs * sizeof(int)));
-            HH_HIP(hipMemsetAsync(buf.ptr, 0, (size_t)nrhs * sizeof(int), m->ctx->stream));
-            *out = buf.as<int>();
+// Copy a host int[nrhs] RHS -> instance map to the device (NULL = all zeros)
+// together with the grouping order of the coarse solve (see BatchMap).
+static hh_status upload_inst(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out) {
+    *out = BatchMap();
+    if (inst_host)
+        for (int r = 0; r < nrhs; ++r)
+            HH_ARG(inst_host[r] >= 0 && inst_host[r] < m->ninst, "instance index out of range");
+    if (m->ninst == 1) return HH_OK;  // one model: no map needed
+    const int G = coarse_group();
+    std::vector<int> inst(nrhs, 0);
+    if (inst_host)
+        for (int r = 0; r < nrhs; ++r) inst[r] = inst_host[r];
+    std::vector<int> order;
+    for (int k = 0; k < m->ninst; ++k) {
+        int cnt = 0;
+        for (int r = 0; r < nrhs; ++r)
+            if (inst[r] == k) {
+                order.push_back(r);
+                ++cnt;
+            }
+        while (cnt % G) {
+            order.push_back(-1);
+            ++cnt;
         }
-        return HH_OK;
     }
-    for (int r = 0; r < nrhs; ++r)
-        HH_ARG(inst_host[r] >= 0 && inst_host[r] < m->ninst, "instance index out of range");
-    HH_TRY(buf.ensure(m->ctx, (size_t)nrhs * sizeof(int)));
-    HH_HIP(hipMemcpyAsync(buf.ptr, inst_host, (size_t)nrhs * sizeof(int), hipMemcpyHostToDevice, m->ctx->stream));
-    HH_HIP(hipStreamSynchronize(m->ctx->stream));  // inst_host may be freed by the caller afterwards
-    *out = buf.as<int>();
+    std::vector<int> packed(inst);
+    packed.insert(packed.end(), order.begin(), order.end());
+    HH_TRY(buf.ensure(m->ctx, packed.size() * sizeof(int)));
+    HH_HIP(hipMemcpyAsync(buf.ptr, packed.data(), packed.size() * sizeof(int), hipMemcpyHostToDevice, m->ctx->stream));
+    HH_HIP(hipStreamSynchronize(m->ctx->stream));  // the host vectors go out of scope
+    out->inst = buf.as<int>();
+    out->order = buf.as<int>() + nrhs;
+    out->nslots = (int)order.size();
     return HH_OK;
 }
 
@@ -211,9 +227,9 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
     const int max_it = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
     const int hist_len = max_it + 1;
     HH_TRY(W.prepare(ctx, m, nrhs, o->restart, hist_len, cnn));
-    const int* inst_dev = nullptr;
-    HH_TRY(upload_inst(m, W.inst, nrhs, inst_host, &inst_dev));
-    hh_status s = fgmres_solve(m, W, inst_dev, (const float2*)b_dev, (double2*)x_dev, *o,
+    BatchMap bm;
+    HH_TRY(upload_inst(m, W.inst, nrhs, inst_host, &bm));
+    hh_status s = fgmres_solve(m, W, bm, (const float2*)b_dev, (double2*)x_dev, *o,
                                cnn ? net_precond : nullptr, cnn ? (void*)m : nullptr);
     if (s < 0) return s;
     // results
@@ -246,9 +262,9 @@ hh_status hh_apply_operator(hh_model* m, int level, double shift, int nrhs, cons
     HH_ARG(nrhs >= 1, "nrhs >= 1");
     HH_HIP(hipSetDevice(m->ctx->device));
     Buf ib;
-    const int* inst_dev = nullptr;
-    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &inst_dev));
-    HH_TRY(launch_apply_op(m, level, (float)shift, nrhs, inst_dev, (const float2*)x_dev, (float2*)y_dev, nullptr));
+    BatchMap bm;
+    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &bm));
+    HH_TRY(launch_apply_op(m, level, (float)shift, nrhs, bm.inst, (const float2*)x_dev, (float2*)y_dev, nullptr));
     HH_HIP(hipStreamSynchronize(m->ctx->stream));
     return HH_OK;
 }
@@ -259,10 +275,10 @@ hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const voi
     HH_ARG(nrhs >= 1, "nrhs >= 1");
     HH_HIP(hipSetDevice(m->ctx->device));
     Buf ib, work;
-    const int* inst_dev = nullptr;
-    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &inst_dev));
+    BatchMap bm;
+    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &bm));
     HH_TRY(work.ensure(m->ctx, vcycle_workspace_bytes(m, nrhs, x0_dev != nullptr) + 256));
-    HH_TRY(launch_vcycle(m, nrhs, inst_dev, (const float2*)b_dev, nullptr, 0, (const float2*)x0_dev, (float2*)x_dev,
+    HH_TRY(launch_vcycle(m, nrhs, bm, (const float2*)b_dev, nullptr, 0, (const float2*)x0_dev, (float2*)x_dev,
                          work.ptr, nullptr));
     HH_HIP(hipStreamSynchronize(m->ctx->stream));
     return HH_OK;

@@ -107,6 +107,15 @@ struct Buf {
     template <class T> T* as() const { return reinterpret_cast<T*>(ptr); }
 };
 
+// Right-hand-side -> slowness-model map of one batch on the device.  `order`
+// lists RHS indices grouped by model and padded with -1 so that consecutive
+// groups of `group` entries never mix models (NULL when there is one model).
+struct BatchMap {
+    const int* inst = nullptr;
+    const int* order = nullptr;
+    int nslots = 0;
+};
+
 // One multigrid level of a model (all instances share n).
 struct Level {
     int n = 0;       // points per dimension
@@ -222,11 +231,13 @@ hh_status launch_apply_op(hh_model* m, int level, float shift, int nrhs, const i
 // V-cycle on level 0: b (optionally scaled per RHS by sig[r*sig_stride]), optional
 // initial guess x0, result z.  work: scratch laid out by vcycle_workspace_bytes.
 size_t vcycle_workspace_bytes(const hh_model* m, int nrhs, bool with_x0);
-hh_status launch_vcycle(hh_model* m, int nrhs, const int* inst_dev, const float2* b, const double* sig,
+hh_status launch_vcycle(hh_model* m, int nrhs, const BatchMap& bm, const float2* b, const double* sig,
                         int sig_stride, const float2* x0, float2* z, void* work, const int* active);
 // Same with explicit element strides between consecutive right-hand sides.
-hh_status launch_vcycle_strided(hh_model* m, int nrhs, const int* inst_dev, const float2* b, size_t bstride,
+hh_status launch_vcycle_strided(hh_model* m, int nrhs, const BatchMap& bm, const float2* b, size_t bstride,
                                 const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
                                 size_t zstride, void* work, const int* active);
+// RHS per workgroup of the coarsest solve (the grouping unit of BatchMap::order)
+int coarse_group();
 
 }  // namespace hh

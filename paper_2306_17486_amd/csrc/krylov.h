@@ -14,7 +14,9 @@ struct KState {
     double sig[HH_MAX_RESTART + 1];                 // 1/||v_i|| of the stored basis vectors
     float2 oc[HH_MAX_RESTART + 1];                  // single-precision projection coefficients
     double bnorm, res_est, res_true;
+    double tol_scale;  // inner-cycle target = rtol * tol_scale (tightened when the FP64 residual refutes it)
     int k, iters, converged, breakdown;
+    int ended_by_est, pad_;
 };
 static_assert(sizeof(KState) % 8 == 0, "KState must be a whole number of doubles");
 
@@ -26,13 +28,13 @@ struct SolveWork {
 };
 
 // Network part of the CNN+MG preconditioner: z_j = V(v_j; Net(v_j)).
-typedef hh_status (*PrecondFn)(void* user, hh_model* md, SolveWork& W, const int* inst_dev, const float2* v,
+typedef hh_status (*PrecondFn)(void* user, hh_model* md, SolveWork& W, const BatchMap& bm, const float2* v,
                                size_t vstride, const double* sig, int sig_stride, float2* z, size_t zstride,
                                const int* act);
 
-hh_status fgmres_solve(hh_model* md, SolveWork& W, const int* inst_dev, const float2* b, double2* x,
+hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* b, double2* x,
                        const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user);
-hh_status precond_mg_strided(hh_model* md, SolveWork& W, const int* inst_dev, const float2* v, size_t vstride,
+hh_status precond_mg_strided(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* v, size_t vstride,
                              const double* sig, int sig_stride, float2* z, size_t zstride, const int* act);
 
 }  // namespace hh

@@ -121,9 +121,12 @@ __global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ 
         parts[(size_t)r * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
 }
 
-// w = A z (FP32) written to V[j+1]; partial FP64 dots <v~_i, w>, i = 0..j
+// w = A z (FP32) written to V[j+1]; partial dots <v~_i, w>, i = 0..j: each
+// thread sums its 4 points in FP32, the block and grid sums are FP64.  The
+// read set (z, v_0..v_j) and the write set (v_{j+1}) do not overlap.
 template <int NJ>
-__global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, size_t zstride, float2* __restrict__ V,
+__global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, size_t zstride,
+                                                 const float2* __restrict__ Vin, float2* __restrict__ Vout,
                                                  size_t vstride, int j, const float2* __restrict__ coef,
                                                  const int* __restrict__ inst, int n, float inv_h2,
                                                  double2* __restrict__ parts, int npart,
@@ -135,41 +138,47 @@ __global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, s
     const int jj = blockIdx.x * KT_X + threadIdx.x;
     const int i0 = blockIdx.y * KT_Y + threadIdx.y * KT_ROWS;
     const float2* zr = Z + r * zstride;
+    const float2* Vr = Vin + r * vstride;
     const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
     const int nact = j + 1;
-    double2 acc[NJ];
+    float2 pacc[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int q = 0; q < NJ; ++q) pacc[q] = make_float2(0.f, 0.f);
     const float2 zero = make_float2(0.f, 0.f);
-    float2* wout = V + r * vstride + (size_t)(j + 1) * nn;
+    float2* wout = Vout + r * vstride + (size_t)(j + 1) * nn;
     if (jj < n) {
         float2 up = (i0 > 0 && i0 - 1 < n) ? zr[(size_t)(i0 - 1) * n + jj] : zero;
         float2 cur = (i0 < n) ? zr[(size_t)i0 * n + jj] : zero;
+#pragma unroll
         for (int t = 0; t < KT_ROWS; ++t) {
             const int i = i0 + t;
             if (i >= n) break;
-            size_t o = (size_t)i * n + jj;
-            float2 dn = (i + 1 < n) ? zr[o + n] : zero;
-            float2 lf = (jj > 0) ? zr[o - 1] : zero;
-            float2 rt = (jj + 1 < n) ? zr[o + 1] : zero;
-            float2 m = mass_of(cf[o], 0.f);
-            float2 w = csub(make_float2((4.f * cur.x - up.x - dn.x - lf.x - rt.x) * inv_h2,
-                                        (4.f * cur.y - up.y - dn.y - lf.y - rt.y) * inv_h2),
-                            cmul(m, cur));
+            const size_t o = (size_t)i * n + jj;
+            const float2 dn = (i + 1 < n) ? zr[o + n] : zero;
+            const float2 lf = (jj > 0) ? zr[o - 1] : zero;
+            const float2 rt = (jj + 1 < n) ? zr[o + 1] : zero;
+            const float2 m = mass_of(cf[o], 0.f);
+            // sum of neighbour differences: far less cancellation in FP32 than 4c - sum
+            const float2 lap = make_float2(((cur.x - up.x) + (cur.x - dn.x)) + ((cur.x - lf.x) + (cur.x - rt.x)),
+                                           ((cur.y - up.y) + (cur.y - dn.y)) + ((cur.y - lf.y) + (cur.y - rt.y)));
+            const float2 w = csub(cscale(lap, inv_h2), cmul(m, cur));
             wout[o] = w;
 #pragma unroll
             for (int q = 0; q < NJ; ++q) {
                 if (q < nact) {
-                    float2 v = V[r * vstride + (size_t)q * nn + o];
+                    const float2 v = Vr[(size_t)q * nn + o];
                     // conj(v) * w
-                    acc[q].x += (double)v.x * w.x + (double)v.y * w.y;
-                    acc[q].y += (double)v.x * w.y - (double)v.y * w.x;
+                    pacc[q].x += v.x * w.x + v.y * w.y;
+                    pacc[q].y += v.x * w.y - v.y * w.x;
                 }
             }
             up = cur;
             cur = dn;
         }
     }
+    double2 acc[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) acc[q] = make_double2((double)pacc[q].x, (double)pacc[q].y);
     block_sum2<NJ>(acc, nact, s_red);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         double2* p = parts + ((size_t)r * npart + blockIdx.y * gridDim.x + blockIdx.x) * MAXV;
@@ -305,7 +314,9 @@ __global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ part
     if (hist && S.iters < hist_len) hist[(size_t)r * hist_len + S.iters] = est;
     bool bad = !(est == est) || !(hn == hn);
     if (bad) S.breakdown = 1;
-    if (bad || est <= rtol || S.iters >= max_iters || hn == 0.0) active[r] = 0;
+    const bool by_est = est <= rtol * S.tol_scale;
+    if (by_est) S.ended_by_est = 1;
+    if (bad || by_est || S.iters >= max_iters || hn == 0.0) active[r] = 0;
 }
 
 // x += sum_{q<k} y_q z_q  (x complex double)
@@ -352,6 +363,7 @@ __global__ void k_init_state(const double2* __restrict__ parts, int npart, KStat
         for (size_t q = 0; q < sizeof(KState) / 8; ++q) w[q] = 0;
     }
     S.bnorm = sqrt(acc[0].x);
+    S.tol_scale = 1.0;
     done[r] = S.bnorm == 0.0 ? 1 : 0;
     if (S.bnorm == 0.0) S.converged = 1;
     active[r] = 0;
@@ -379,6 +391,10 @@ __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KSta
     const bool bad = !(beta == beta);
     if (bad) S.breakdown = 1;
     if (!fixed && S.res_true <= rtol) S.converged = 1;
+    // the previous cycle stopped on its residual estimate but the FP64 residual
+    // says otherwise: ask the next cycles for a 10x deeper reduction
+    if (S.ended_by_est && !S.converged) S.tol_scale = fmax(S.tol_scale * 0.1, 1e-4);
+    S.ended_by_est = 0;
     if (bad || S.converged || S.iters >= max_iters || beta == 0.0) {
         done[r] = 1;
         active[r] = 0;
@@ -398,7 +414,8 @@ template <int NJ>
 static void launch_op_dots_t(dim3 g, dim3 b, hipStream_t s, const float2* Z, size_t zs, float2* V, size_t vs, int j,
                              const float2* cf, const int* inst, int n, float ih2, double2* parts, int np,
                              const int* act) {
-    hipLaunchKernelGGL(k_op_dots<NJ>, g, b, 0, s, Z, zs, V, vs, j, cf, inst, n, ih2, parts, np, act);
+    hipLaunchKernelGGL(k_op_dots<NJ>, g, b, 0, s, Z, zs, (const float2*)V, V, vs, j, cf, inst, n, ih2, parts, np,
+                       act);
 }
 template <int NJ>
 static void launch_ortho_t(dim3 g, dim3 b, hipStream_t s, float2* V, size_t vs, int j, const KState* st, int n,
@@ -425,8 +442,9 @@ hh_status SolveWork::prepare(hh_ctx* c, hh_model* md, int nrhs_, int restart_, i
     return HH_OK;
 }
 
-hh_status fgmres_solve(hh_model* md, SolveWork& W, const int* inst_dev, const float2* b, double2* x,
+hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* b, double2* x,
                        const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user) {
+    const int* inst_dev = bm.inst;
     hh_ctx* ctx = md->ctx;
     hipStream_t st = ctx->stream;
     const int n = W.n, nrhs = W.nrhs;
@@ -486,9 +504,9 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const int* inst_dev, const fl
             float2* zj = Z + (size_t)j * nn;
             // z_j = M(v_j): the preconditioner works on [rhs] vectors with strides; use per-RHS views
             if (use_cnn) {
-                HH_TRY(precond_cnn(precond_user, md, W, inst_dev, vj, vstride, sg, sig_stride, zj, zstride, act));
+                HH_TRY(precond_cnn(precond_user, md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, act));
             } else {
-                HH_TRY(precond_mg_strided(md, W, inst_dev, vj, vstride, sg, sig_stride, zj, zstride, act));
+                HH_TRY(precond_mg_strided(md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, act));
             }
             // w = A z_j, dots with v_0..v_j
             {
@@ -546,10 +564,10 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const int* inst_dev, const fl
 }
 
 // MG-only preconditioner on strided [rhs] views of V and Z
-hh_status precond_mg_strided(hh_model* md, SolveWork& W, const int* inst_dev, const float2* v, size_t vstride,
+hh_status precond_mg_strided(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* v, size_t vstride,
                              const double* sig, int sig_stride, float2* z, size_t zstride, const int* act) {
-    return launch_vcycle_strided(md, W.nrhs, inst_dev, v, vstride, sig, sig_stride, nullptr, 0, z, zstride,
-                                 W.vwork.ptr, act);
+    return launch_vcycle_strided(md, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, 0, z, zstride, W.vwork.ptr,
+                                 act);
 }
 
 }  // namespace hh

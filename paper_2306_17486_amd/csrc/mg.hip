@@ -255,80 +255,247 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
 }
 
 // ---------------------------------------------------------------------------
-// Coarsest-level exact solve with the stored Schur inverses (see setup.hip):
-//   forward  w_k = b_k + c y_{k-1},  y_k = Q_k w_k
-//   backward x_{m-1} = y_{m-1},      x_k = y_k + c Q_k x_{k+1}
-// One 256-thread block per right-hand side; thread i owns grid column i (and
-// i + 256, ...).  QT is stored transposed so that the reads of one step are
-// contiguous across threads.
+// Coarsest-level exact solve with the stored Schur inverses (see setup.hip),
+// eliminating from both ends towards the middle row p:
+//   forward (top)     w_k = b_k + c y_{k-1},  y_k = Q_k w_k       k = 0 .. p-1
+//   forward (bottom)  w_k = b_k + c y_{k+1},  y_k = Q_k w_k       k = m-1 .. p+1
+//   middle            x_p = Q_p (b_p + c y_{p-1} + c y_{p+1})
+//   backward (top)    x_k = y_k + c Q_k x_{k+1}                   k = p-1 .. 0
+//   backward (bottom) x_k = y_k + c Q_k x_{k-1}                   k = p+1 .. m-1
+// Two launches (forward, then middle + backward); each launch has two
+// workgroups per right-hand side (blockIdx.y = 0 top, 1 bottom), so the kernel
+// boundary is the only synchronisation.  A step is a dense m x m complex
+// matrix-vector product; QT is stored transposed so that the threads of a
+// wave read consecutive rows of one column.  For m < 256 the column range is
+// split over JP thread groups whose partial sums meet in LDS.
 // ---------------------------------------------------------------------------
 constexpr int CS_MAXM = 1024;
+constexpr int CS_NT = 1024;  // threads per workgroup: every row, columns split JP = 1024/m ways
+constexpr int CS_R = 2;      // right-hand sides per workgroup (each Q_k read is shared by CS_R solves)
 
-__global__ void __launch_bounds__(256) k_coarse_solve(const float2* __restrict__ bcs, float2* __restrict__ x,
-                                                      const float2* __restrict__ QT, const int* __restrict__ inst,
-                                                      int m, float c, const int* __restrict__ active) {
-    __shared__ float2 s_v[CS_MAXM];
-    const int r = blockIdx.x;
-    if (active && !active[r]) return;
-    const int tid = threadIdx.x;
-    const size_t mm = (size_t)m * m;
-    const float2* Q = QT + (size_t)(inst ? inst[r] : 0) * mm * m;
-    const float2* br = bcs + r * mm;
-    float2* xr = x + r * mm;
-    const float2 zero = make_float2(0.f, 0.f);
-    // forward sweep; y_k is written to x (row k) and kept in LDS for the next step
-    for (int k = 0; k < m; ++k) {
-        for (int i = tid; i < m; i += 256) {
-            float2 w = br[(size_t)k * m + i];
-            if (k > 0) w = cadd(w, cscale(s_v[i], c));
-            s_v[i] = w;  // safe: each thread only touches its own entries until the barrier
+struct CoarseMV {
+    int m, JP, jlen, row, jp;
+    __device__ CoarseMV(int m_) : m(m_) {
+        JP = CS_NT / m;  // >= 1 since m <= 1024
+        jlen = (m + JP - 1) / JP;
+        row = threadIdx.x % m;
+        jp = threadIdx.x / m;
+    }
+    // out[q] = sum_j Qk[j][row] v[q][j] for the CS_R vectors; the JP partial
+    // sums meet in s_part.  Valid in the owner threads (jp == 0).
+    __device__ void apply(const float2* __restrict__ Qk, const float2 (*s_v)[CS_MAXM], float2 (*s_part)[CS_NT],
+                          float2 (&out)[CS_R]) const {
+        constexpr int CH = 16;  // loads per chunk; the next chunk is loaded while one is used
+        float2 acc[CS_R];
+#pragma unroll
+        for (int q = 0; q < CS_R; ++q) acc[q] = make_float2(0.f, 0.f);
+        if (jp < JP) {
+            const int j0 = jp * jlen, j1 = min(m, j0 + jlen);
+            const float2* qp = Qk + row;
+            float2 qa[CH], qb[CH];
+            int j = j0;
+            if (j + CH <= j1) {
+#pragma unroll
+                for (int u = 0; u < CH; ++u) qa[u] = qp[(size_t)(j + u) * m];
+                for (;;) {
+                    const int jb = j + CH;
+                    const bool hb = jb + CH <= j1;
+                    if (hb) {
+#pragma unroll
+                        for (int u = 0; u < CH; ++u) qb[u] = qp[(size_t)(jb + u) * m];
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u)
+#pragma unroll
+                        for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], cmul(qa[u], s_v[q][j + u]));
+                    j = jb;
+                    if (!hb) break;
+                    const int ja = j + CH;
+                    const bool ha = ja + CH <= j1;
+                    if (ha) {
+#pragma unroll
+                        for (int u = 0; u < CH; ++u) qa[u] = qp[(size_t)(ja + u) * m];
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u)
+#pragma unroll
+                        for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], cmul(qb[u], s_v[q][j + u]));
+                    j = ja;
+                    if (!ha) break;
+                }
+            }
+            for (; j < j1; ++j) {
+                const float2 qv = qp[(size_t)j * m];
+#pragma unroll
+                for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], cmul(qv, s_v[q][j]));
+            }
         }
-        __syncthreads();
-        float2 acc[CS_MAXM / 256];
+        if (JP > 1) {
+            if (jp < JP)
 #pragma unroll
-        for (int t = 0; t < CS_MAXM / 256; ++t) acc[t] = zero;
-        const float2* Qk = Q + (size_t)k * mm;
-        for (int jj = 0; jj < m; ++jj) {
-            float2 wj = s_v[jj];
+                for (int q = 0; q < CS_R; ++q) s_part[q][threadIdx.x] = acc[q];
+            __syncthreads();
+            if (jp == 0)
+                for (int t = 1; t < JP; ++t)
 #pragma unroll
-            for (int t = 0; t < CS_MAXM / 256; ++t) {
-                int i = tid + 256 * t;
-                if (i < m) acc[t] = cadd(acc[t], cmul(Qk[(size_t)jj * m + i], wj));
+                    for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], s_part[q][t * m + row]);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < CS_R; ++q) out[q] = acc[q];
+    }
+    __device__ bool owner() const { return jp == 0; }
+};
+
+// Right-hand sides r = blockIdx.x * CS_R + q (q < CS_R) that exist and are
+// active; all of them must use the same slowness model (the host groups them).
+struct CoarseGroup {
+    int r[CS_R];
+    bool on[CS_R];
+    bool any;
+    __device__ CoarseGroup(int nrhs, const int* active) {
+        any = false;
+#pragma unroll
+        for (int q = 0; q < CS_R; ++q) {
+            r[q] = blockIdx.x * CS_R + q;
+            on[q] = r[q] < nrhs && (!active || active[r[q]]);
+            any = any || on[q];
+        }
+    }
+};
+
+// ends: [rhs][2][m], the last forward results y_{p-1} (slot 0) and y_{p+1}
+// (slot 1), kept apart from x because the backward sweep overwrites x rows.
+// rhs_order: RHS indices grouped so that each block's CS_R entries share a
+// slowness model (entries < 0 are padding).
+__global__ void __launch_bounds__(CS_NT) k_coarse_fwd(const float2* __restrict__ bcs, float2* __restrict__ x,
+                                                      float2* __restrict__ ends, const float2* __restrict__ QT,
+                                                      const int* __restrict__ inst, const int* __restrict__ order,
+                                                      int nslots, int m, int p, float c,
+                                                      const int* __restrict__ active) {
+    __shared__ float2 s_v[CS_R][CS_MAXM];
+    __shared__ float2 s_part[CS_R][CS_NT];
+    const bool top = blockIdx.y == 0;
+    int rr[CS_R];
+    bool on[CS_R];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < CS_R; ++q) {
+        const int slot = blockIdx.x * CS_R + q;
+        rr[q] = (slot < nslots) ? (order ? order[slot] : slot) : -1;
+        on[q] = rr[q] >= 0 && (!active || active[rr[q]]);
+        any = any || on[q];
+    }
+    if (!any) return;
+    int r0 = 0;
+#pragma unroll
+    for (int q = CS_R - 1; q >= 0; --q)
+        if (on[q]) r0 = rr[q];
+    const size_t mm = (size_t)m * m;
+    const float2* Q = QT + (size_t)(inst ? inst[r0] : 0) * mm * m;
+    const CoarseMV mv(m);
+    const int nsteps = top ? p : (m - 1 - p);
+    for (int s = 0; s < nsteps; ++s) {
+        const int k = top ? s : (m - 1 - s);
+        // w_k = b_k + c y_prev  (y_prev is in s_v from the previous step)
+        if (mv.owner()) {
+            const int i = mv.row;
+#pragma unroll
+            for (int q = 0; q < CS_R; ++q) {
+                float2 w = on[q] ? bcs[(size_t)rr[q] * mm + (size_t)k * m + i] : make_float2(0.f, 0.f);
+                if (s > 0) w = cadd(w, cscale(s_v[q][i], c));
+                s_v[q][i] = w;
             }
         }
         __syncthreads();
+        float2 out[CS_R];
+        mv.apply(Q + (size_t)k * mm, s_v, s_part, out);
+        __syncthreads();
+        if (mv.owner()) {
+            const int i = mv.row;
 #pragma unroll
-        for (int t = 0; t < CS_MAXM / 256; ++t) {
-            int i = tid + 256 * t;
-            if (i < m) {
-                s_v[i] = acc[t];
-                xr[(size_t)k * m + i] = acc[t];
+            for (int q = 0; q < CS_R; ++q) {
+                s_v[q][i] = out[q];
+                if (on[q]) {
+                    x[(size_t)rr[q] * mm + (size_t)k * m + i] = out[q];
+                    if (s == nsteps - 1) ends[((size_t)rr[q] * 2 + (top ? 0 : 1)) * m + i] = out[q];
+                }
             }
         }
         __syncthreads();
     }
-    // backward sweep; s_v holds x_{k+1}
-    for (int k = m - 2; k >= 0; --k) {
-        float2 acc[CS_MAXM / 256];
+}
+
+__global__ void __launch_bounds__(CS_NT) k_coarse_bwd(const float2* __restrict__ bcs, float2* __restrict__ x,
+                                                      const float2* __restrict__ ends, const float2* __restrict__ QT,
+                                                      const int* __restrict__ inst, const int* __restrict__ order,
+                                                      int nslots, int m, int p, float c,
+                                                      const int* __restrict__ active) {
+    __shared__ float2 s_v[CS_R][CS_MAXM];
+    __shared__ float2 s_part[CS_R][CS_NT];
+    const bool top = blockIdx.y == 0;
+    int rr[CS_R];
+    bool on[CS_R];
+    bool any = false;
 #pragma unroll
-        for (int t = 0; t < CS_MAXM / 256; ++t) acc[t] = zero;
-        const float2* Qk = Q + (size_t)k * mm;
-        for (int jj = 0; jj < m; ++jj) {
-            float2 tj = s_v[jj];
+    for (int q = 0; q < CS_R; ++q) {
+        const int slot = blockIdx.x * CS_R + q;
+        rr[q] = (slot < nslots) ? (order ? order[slot] : slot) : -1;
+        on[q] = rr[q] >= 0 && (!active || active[rr[q]]);
+        any = any || on[q];
+    }
+    if (!any) return;
+    int r0 = 0;
 #pragma unroll
-            for (int t = 0; t < CS_MAXM / 256; ++t) {
-                int i = tid + 256 * t;
-                if (i < m) acc[t] = cadd(acc[t], cmul(Qk[(size_t)jj * m + i], tj));
+    for (int q = CS_R - 1; q >= 0; --q)
+        if (on[q]) r0 = rr[q];
+    const size_t mm = (size_t)m * m;
+    const float2* Q = QT + (size_t)(inst ? inst[r0] : 0) * mm * m;
+    const CoarseMV mv(m);
+    // middle row: x_p = Q_p (b_p + c y_{p-1} + c y_{p+1}); both workgroups compute it
+    if (mv.owner()) {
+        const int i = mv.row;
+#pragma unroll
+        for (int q = 0; q < CS_R; ++q) {
+            float2 w = make_float2(0.f, 0.f);
+            if (on[q]) {
+                w = bcs[(size_t)rr[q] * mm + (size_t)p * m + i];
+                if (p > 0) w = cadd(w, cscale(ends[((size_t)rr[q] * 2 + 0) * m + i], c));
+                if (p < m - 1) w = cadd(w, cscale(ends[((size_t)rr[q] * 2 + 1) * m + i], c));
+            }
+            s_v[q][i] = w;
+        }
+    }
+    __syncthreads();
+    {
+        float2 out[CS_R];
+        mv.apply(Q + (size_t)p * mm, s_v, s_part, out);
+        __syncthreads();
+        if (mv.owner()) {
+#pragma unroll
+            for (int q = 0; q < CS_R; ++q) {
+                s_v[q][mv.row] = out[q];
+                if (top && on[q]) x[(size_t)rr[q] * mm + (size_t)p * m + mv.row] = out[q];
             }
         }
         __syncthreads();
+    }
+    const int nsteps = top ? p : (m - 1 - p);
+    for (int s = 0; s < nsteps; ++s) {
+        const int k = top ? (p - 1 - s) : (p + 1 + s);
+        float2 out[CS_R];
+        mv.apply(Q + (size_t)k * mm, s_v, s_part, out);
+        __syncthreads();
+        if (mv.owner()) {
+            const int i = mv.row;
 #pragma unroll
-        for (int t = 0; t < CS_MAXM / 256; ++t) {
-            int i = tid + 256 * t;
-            if (i < m) {
-                float2 v = cadd(xr[(size_t)k * m + i], cscale(acc[t], c));
-                s_v[i] = v;
-                xr[(size_t)k * m + i] = v;
+            for (int q = 0; q < CS_R; ++q) {
+                float2 v = make_float2(0.f, 0.f);
+                if (on[q]) {
+                    v = cadd(x[(size_t)rr[q] * mm + (size_t)k * m + i], cscale(out[q], c));
+                    x[(size_t)rr[q] * mm + (size_t)k * m + i] = v;
+                }
+                s_v[q][i] = v;
             }
         }
         __syncthreads();
@@ -349,31 +516,38 @@ hh_status launch_apply_op(hh_model* md, int level, float shift, int nrhs, const 
     return HH_OK;
 }
 
-// workspace: per level l >= 1: b_l and e_l [nrhs][n_l][n_l]; plus x1 [nrhs][n][n] if with_x0
+// workspace: per level l >= 1: b_l and e_l [nrhs][n_l][n_l]; the coarse solve's
+// [nrhs][2][m] exchange rows; plus x1 [nrhs][n][n] if with_x0
 size_t vcycle_workspace_bytes(const hh_model* md, int nrhs, bool with_x0) {
     size_t bytes = 0;
     for (int l = 1; l < md->nlev; ++l) bytes += 2 * (size_t)nrhs * md->lev[l].n * md->lev[l].n * sizeof(float2);
+    bytes += 2 * (size_t)nrhs * md->lev[md->nlev - 1].n * sizeof(float2);
     if (with_x0) bytes += (size_t)nrhs * md->lev[0].n * md->lev[0].n * sizeof(float2);
     return bytes;
 }
 
-hh_status launch_vcycle_strided(hh_model* md, int nrhs, const int* inst_dev, const float2* b, size_t bstride,
+int coarse_group() { return CS_R; }
+
+hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, const float2* b, size_t bstride,
                                 const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
                                 size_t zstride, void* work, const int* active) {
+    const int* inst_dev = bm.inst;
     hipStream_t st = md->ctx->stream;
     const float beta = (float)md->d.sl_beta, wj = (float)md->d.jacobi_w;
     const int L = md->nlev;
     float2* bl[HH_MAX_LEVELS] = {nullptr};
     float2* el[HH_MAX_LEVELS] = {nullptr};
-    char* p = (char*)work;
+    char* wp = (char*)work;
     for (int l = 1; l < L; ++l) {
         size_t sz = (size_t)nrhs * md->lev[l].n * md->lev[l].n * sizeof(float2);
-        bl[l] = (float2*)p;
-        p += sz;
-        el[l] = (float2*)p;
-        p += sz;
+        bl[l] = (float2*)wp;
+        wp += sz;
+        el[l] = (float2*)wp;
+        wp += sz;
     }
-    float2* x1 = x0 ? (float2*)p : nullptr;
+    float2* ends = (float2*)wp;
+    wp += 2 * (size_t)nrhs * md->lev[L - 1].n * sizeof(float2);
+    float2* x1 = x0 ? (float2*)wp : nullptr;
     // down sweep
     for (int l = 0; l < L - 1; ++l) {
         const Level& lv = md->lev[l];
@@ -399,8 +573,18 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const int* inst_dev, con
     {
         const Level& lc = md->lev[L - 1];
         ProfScope ps(md->ctx, HH_K_VC_COARSE);
-        hipLaunchKernelGGL(k_coarse_solve, dim3(nrhs), dim3(256), 0, st, bl[L - 1], el[L - 1],
-                           md->coarseQT.as<float2>(), inst_dev, lc.n, (float)(1.0 / (lc.h * lc.h)), active);
+        const int m = lc.n, p = m / 2;
+        const float c = (float)(1.0 / (lc.h * lc.h));
+        // every block serves CS_R right-hand sides of one slowness model; with a
+        // single model the natural order already groups them
+        const int* order = bm.order;
+        const int nslots = bm.order ? bm.nslots : nrhs;
+        dim3 grd((nslots + CS_R - 1) / CS_R, 2);
+        hipLaunchKernelGGL(k_coarse_fwd, grd, dim3(CS_NT), 0, st, bl[L - 1], el[L - 1], ends,
+                           md->coarseQT.as<float2>(), inst_dev, order, nslots, m, p, c, active);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_coarse_bwd, grd, dim3(CS_NT), 0, st, bl[L - 1], el[L - 1], ends,
+                           md->coarseQT.as<float2>(), inst_dev, order, nslots, m, p, c, active);
         HH_LAUNCH_CHECK();
     }
     // up sweep
@@ -427,10 +611,10 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const int* inst_dev, con
     return HH_OK;
 }
 
-hh_status launch_vcycle(hh_model* md, int nrhs, const int* inst_dev, const float2* b, const double* sig,
+hh_status launch_vcycle(hh_model* md, int nrhs, const BatchMap& bm, const float2* b, const double* sig,
                         int sig_stride, const float2* x0, float2* z, void* work, const int* active) {
     const size_t nn = (size_t)md->lev[0].n * md->lev[0].n;
-    return launch_vcycle_strided(md, nrhs, inst_dev, b, nn, sig, sig_stride, x0, nn, z, nn, work, active);
+    return launch_vcycle_strided(md, nrhs, bm, b, nn, sig, sig_stride, x0, nn, z, nn, work, active);
 }
 
 }  // namespace hh

@@ -52,77 +52,115 @@ __global__ void k_coef_restrict(const float2* __restrict__ fine, float2* __restr
 // Coarsest-level direct solver.  The shifted operator on an m x m grid is block
 // tridiagonal in grid rows: diagonal blocks T_k (tridiagonal, 4/H^2 - mass on
 // the diagonal, -1/H^2 off it) and off-diagonal blocks -c I with c = 1/H^2.
-// Block LU without pivoting: S_0 = T_0, S_k = T_k - c^2 S_{k-1}^{-1}.  The
-// Schur inverses Q_k = S_k^{-1} are formed in FP64 and stored transposed in
-// complex single precision: QT[k][j][i] = Q_k[i][j].  -i A_SL has a positive
-// definite Hermitian part (omega^2 kappa^2 (gamma + beta) > 0 on the diagonal),
-// which keeps every Schur complement nonsingular without pivoting.
-// One workgroup per slowness model; rows are processed sequentially.
+// The rows are eliminated from both ends towards the middle row p = m/2
+// ("burn at both ends"), which halves the sequential chain:
+//   top:    S_0 = T_0,         S_k = T_k - c^2 S_{k-1}^{-1}   (k = 0 .. p-1)
+//   bottom: S_{m-1} = T_{m-1}, S_k = T_k - c^2 S_{k+1}^{-1}   (k = m-1 .. p+1)
+//   middle: S_p = T_p - c^2 S_{p-1}^{-1} - c^2 S_{p+1}^{-1}
+// The inverses Q_k = S_k^{-1} are formed in FP64 (in-place Gauss-Jordan without
+// pivoting) and stored transposed in complex single precision:
+// QT[k][j][i] = Q_k[i][j].  -i A_SL has a positive definite Hermitian part
+// (omega^2 kappa^2 (gamma + beta) > 0 on the diagonal), which keeps every Schur
+// complement nonsingular without pivoting.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_coarse_factor(const float2* __restrict__ coef, double2* __restrict__ S,
-                                                        float2* __restrict__ QT, int m, double H, double beta) {
-    const int inst = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x;
-    const double c = 1.0 / (H * H);
-    const float2* cf = coef + (size_t)inst * m * m;
-    double2* A = S + (size_t)inst * m * m;
-    float2* Q = QT + (size_t)inst * m * m * m;
-    __shared__ double2 piv_s;
 
-    for (int k = 0; k < m; ++k) {
-        // S = T_k - c^2 Q_{k-1}   (A holds Q_{k-1} from the previous step)
-        for (int e = tid; e < m * m; e += nt) {
-            int i = e / m, j = e - i * m;
-            double2 prev = (k > 0) ? A[e] : make_double2(0.0, 0.0);
-            double2 v = make_double2(-c * c * prev.x, -c * c * prev.y);
-            if (i == j) {
-                float2 cc = cf[(size_t)k * m + i];
-                double w2k2 = cc.x, g = cc.y;
-                // diagonal: 4c - omega^2 kappa^2 (1 - i (gamma + beta))
-                v.x += 4.0 * c - w2k2;
-                v.y += w2k2 * (g + beta);
-            } else if (j == i - 1 || j == i + 1) {
-                v.x += -c;
-            }
-            A[e] = v;
+// A <- T_k - c^2 (P1 + P2)   (P1, P2 may be null)
+__device__ void build_schur(double2* A, const double2* P1, const double2* P2, const float2* cf, int k, int m,
+                            double c, double beta) {
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        int i = e / m, j = e - i * m;
+        double2 v = make_double2(0.0, 0.0);
+        if (P1) v = zadd(v, P1[e]);
+        if (P2) v = zadd(v, P2[e]);
+        v = make_double2(-c * c * v.x, -c * c * v.y);
+        if (i == j) {
+            float2 cc = cf[(size_t)k * m + i];
+            double w2k2 = cc.x, g = cc.y;
+            // diagonal: 4c - omega^2 kappa^2 (1 - i (gamma + beta))
+            v.x += 4.0 * c - w2k2;
+            v.y += w2k2 * (g + beta);
+        } else if (j == i - 1 || j == i + 1) {
+            v.x += -c;
+        }
+        A[e] = v;
+    }
+    __syncthreads();
+}
+
+// In-place Gauss-Jordan inversion without pivoting (one workgroup), then store
+// the transpose in single precision.
+__device__ void invert_store(double2* A, float2* Qk, int m) {
+    __shared__ double2 piv_s;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int p = 0; p < m; ++p) {
+        if (tid == 0) {
+            double2 a = A[(size_t)p * m + p];
+            double den = a.x * a.x + a.y * a.y;
+            piv_s = make_double2(a.x / den, -a.y / den);
         }
         __syncthreads();
-        // in-place Gauss-Jordan inversion, no pivoting
-        for (int p = 0; p < m; ++p) {
-            if (tid == 0) {
-                double2 a = A[(size_t)p * m + p];
-                double den = a.x * a.x + a.y * a.y;
-                piv_s = make_double2(a.x / den, -a.y / den);
-            }
-            __syncthreads();
-            const double2 piv = piv_s;
-            for (int j = tid; j < m; j += nt)
-                if (j != p) A[(size_t)p * m + j] = zmul(A[(size_t)p * m + j], piv);
-            __syncthreads();
-            for (int e = tid; e < m * m; e += nt) {
-                int i = e / m, j = e - i * m;
-                if (i == p || j == p) continue;
-                A[e] = zsub(A[e], zmul(A[(size_t)i * m + p], A[(size_t)p * m + j]));
-            }
-            __syncthreads();
-            for (int i = tid; i < m; i += nt) {
-                if (i != p) {
-                    double2 a = A[(size_t)i * m + p];
-                    A[(size_t)i * m + p] = zmul(make_double2(-a.x, -a.y), piv);
-                }
-            }
-            if (tid == 0) A[(size_t)p * m + p] = piv;
-            __syncthreads();
-        }
-        // store Q_k transposed
+        const double2 piv = piv_s;
+        for (int j = tid; j < m; j += nt)
+            if (j != p) A[(size_t)p * m + j] = zmul(A[(size_t)p * m + j], piv);
+        __syncthreads();
         for (int e = tid; e < m * m; e += nt) {
             int i = e / m, j = e - i * m;
-            double2 v = A[e];
-            Q[((size_t)k * m + j) * m + i] = make_float2((float)v.x, (float)v.y);
+            if (i == p || j == p) continue;
+            A[e] = zsub(A[e], zmul(A[(size_t)i * m + p], A[(size_t)p * m + j]));
         }
+        __syncthreads();
+        for (int i = tid; i < m; i += nt) {
+            if (i != p) {
+                double2 a = A[(size_t)i * m + p];
+                A[(size_t)i * m + p] = zmul(make_double2(-a.x, -a.y), piv);
+            }
+        }
+        if (tid == 0) A[(size_t)p * m + p] = piv;
         __syncthreads();
     }
+    for (int e = tid; e < m * m; e += nt) {
+        int i = e / m, j = e - i * m;
+        double2 v = A[e];
+        Qk[(size_t)j * m + i] = make_float2((float)v.x, (float)v.y);
+    }
+    __syncthreads();
+}
+
+// blockIdx.x = instance, blockIdx.y = 0 (top chain) or 1 (bottom chain).
+// Scratch S per instance: [3][m][m] FP64 (top, bottom, middle).
+__global__ void __launch_bounds__(1024) k_coarse_factor_ends(const float2* __restrict__ coef, double2* __restrict__ S,
+                                                             float2* __restrict__ QT, int m, int p, double H,
+                                                             double beta) {
+    const int inst = blockIdx.x;
+    const bool top = blockIdx.y == 0;
+    const double c = 1.0 / (H * H);
+    const size_t mm = (size_t)m * m;
+    const float2* cf = coef + (size_t)inst * mm;
+    double2* A = S + (size_t)inst * 3 * mm + (top ? 0 : mm);
+    float2* Q = QT + (size_t)inst * mm * m;
+    if (top) {
+        for (int k = 0; k < p; ++k) {
+            build_schur(A, k > 0 ? A : nullptr, nullptr, cf, k, m, c, beta);
+            invert_store(A, Q + (size_t)k * mm, m);
+        }
+    } else {
+        for (int k = m - 1; k > p; --k) {
+            build_schur(A, k < m - 1 ? A : nullptr, nullptr, cf, k, m, c, beta);
+            invert_store(A, Q + (size_t)k * mm, m);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_coarse_factor_mid(const float2* __restrict__ coef, double2* __restrict__ S,
+                                                            float2* __restrict__ QT, int m, int p, double H,
+                                                            double beta) {
+    const int inst = blockIdx.x;
+    const double c = 1.0 / (H * H);
+    const size_t mm = (size_t)m * m;
+    double2* base = S + (size_t)inst * 3 * mm;
+    double2* A = base + 2 * mm;
+    build_schur(A, p > 0 ? base : nullptr, p < m - 1 ? base + mm : nullptr, coef + (size_t)inst * mm, p, m, c, beta);
+    invert_store(A, QT + (size_t)inst * mm * m + (size_t)p * mm, m);
 }
 
 hh_status setup_coefficients(hh_model* md, const float* kappa_dev) {
@@ -149,14 +187,18 @@ hh_status setup_coarse_factors(hh_model* md) {
     hh_ctx* ctx = md->ctx;
     const Level& C = md->lev[md->nlev - 1];
     const int m = C.n;
+    const int p = m / 2;
     md->m = m;
     HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * m * m * m * sizeof(float2)));
     Buf S;
-    HH_TRY(S.ensure(ctx, (size_t)md->ninst * m * m * sizeof(double2)));
-    hipLaunchKernelGGL(k_coarse_factor, dim3(md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
-                       S.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
+    HH_TRY(S.ensure(ctx, (size_t)md->ninst * 3 * m * m * sizeof(double2)));
+    hipLaunchKernelGGL(k_coarse_factor_ends, dim3(md->ninst, 2), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
+                       S.as<double2>(), md->coarseQT.as<float2>(), m, p, C.h, md->d.sl_beta);
     HH_LAUNCH_CHECK();
-    // S is released when this function returns: order the free after the kernel.
+    hipLaunchKernelGGL(k_coarse_factor_mid, dim3(md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
+                       S.as<double2>(), md->coarseQT.as<float2>(), m, p, C.h, md->d.sl_beta);
+    HH_LAUNCH_CHECK();
+    // S is released when this function returns: order the free after the kernels.
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
 }
