@@ -155,6 +155,61 @@ hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const voi
                           const void* x0_dev, void* x_dev);
 
 /* ------------------------------------------------------------------------
+ * Encoder-solver network with the implicit coarsest layer (Sec. 4.1-4.4,
+ * Sec. 5.3).  Parameters are one flat FP32 vector, layer by layer in the order
+ *   encoder  enc1_d enc1_c1 enc1_c2 enc2_d enc2_c1 enc2_c2 enc3_d enc3_c1 enc3_c2
+ *   solver   s1_d s1_c1 s1_c2 s2_d s2_c1 s2_c2 s3_d s3_c1 s3_c2 s4_d s4_c1 s4_c2
+ *            u3_t u3_c1 u3_c2 u2_t u2_c1 u2_c2 u1_t u1_c1 u1_c2 out
+ * each as the weights then the biases; convolution weights are (cout, cin, 3,
+ * 3), transposed-convolution weights (the *_t layers) (cin, cout, 3, 3); then
+ * the implicit kernels K[c][3][3] as (re, im) pairs, c < ch[3]/2.  Channels
+ * per level (ch) must be (16, 32, 64, 64).  *_d layers are stride-2
+ * convolutions (s4_d stride 1 when n < 512), *_t stride-2 transposed
+ * convolutions (u3_t stride 1 when n < 512); ReLU follows every *_c* layer.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int ch[4];
+} hh_net_desc;
+
+/* Create a network; params_host (host, nparams floats) may be NULL (zeros). */
+hh_status hh_net_create(hh_ctx* ctx, const hh_net_desc* d, const float* params_host, hh_net** out);
+hh_status hh_net_destroy(hh_net* net);
+/* Number of FP32 parameters. */
+size_t hh_net_num_params(const hh_net* net);
+/* Copy the FP32 master parameters to / from host memory (synchronous). */
+hh_status hh_net_get_params(hh_net* net, float* host);
+hh_status hh_net_set_params(hh_net* net, const float* host);
+/* Binary checkpoint: parameters, optimizer moments (when present) and step. */
+hh_status hh_net_save(hh_net* net, const char* path);
+hh_status hh_net_load(hh_ctx* ctx, const char* path, hh_net** out);
+
+/* Attach a network to a model (NULL detaches).  Runs the encoder on every
+ * slowness model of the model and builds the implicit layer's transformed
+ * Green's functions for the model's coarsest map (eq. 17); both are redone
+ * automatically when the parameters change.  The network is not owned. */
+hh_status hh_model_attach_net(hh_model* m, hh_net* net);
+
+/* Network part of the CNN+MG preconditioner (Sec. 4.1): for every r_b,
+ *   e_b = s_b P(Net(r_b / rms(r_b))),  s_b = h^2 rms(r_b),
+ * P the bilinear prolongation; r, e c64 [nrhs][n][n]. */
+hh_status hh_net_forward(hh_model* m, int nrhs, const int* inst_host, const void* r_dev, void* e_dev);
+
+/* Parity-test entry points (same kernels as the network).
+ * hh_conv_test: one 3x3 convolution of BF16 NHWC x [B][Hin][Win][cin] with FP32
+ *   weights w_dev; mode 0 = stride 1, 1 = stride 2, 2 = transposed stride 2;
+ *   flipped = 0: w is (cout, cin, 3, 3) and the layer is a convolution;
+ *   flipped = 1: w is (cin, cout, 3, 3) and the layer is a transposed convolution
+ *   (mode 2 or, with mode 0, the stride-1 transposed convolution);
+ *   bias (FP32, may be NULL), skip (BF16, output shape, may be NULL), relu;
+ *   y_dev BF16 output, yf_dev optional FP32 output.
+ * hh_implicit_test: the implicit layer for coarsest size nc on BF16 NHWC
+ *   [B][nc][nc][ch[3]] (adjoint = 1 multiplies by conj(Ghat)). */
+hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
+                       const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int relu,
+                       void* y_dev, float* yf_dev);
+hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (HIP events on the context's stream).
  * ---------------------------------------------------------------------- */
 enum {

@@ -50,7 +50,7 @@ void dfree(hh_ctx* c, void* p) {
 
 // Copy a host int[nrhs] RHS -> instance map to the device (NULL = all zeros)
 // together with the grouping order of the coarse solve (see BatchMap).
-static hh_status upload_inst(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out) {
+hh_status upload_inst_map(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out) {
     *out = BatchMap();
     if (inst_host)
         for (int r = 0; r < nrhs; ++r)
@@ -228,7 +228,7 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
     const int hist_len = max_it + 1;
     HH_TRY(W.prepare(ctx, m, nrhs, o->restart, hist_len, cnn));
     BatchMap bm;
-    HH_TRY(upload_inst(m, W.inst, nrhs, inst_host, &bm));
+    HH_TRY(upload_inst_map(m, W.inst, nrhs, inst_host, &bm));
     hh_status s = fgmres_solve(m, W, bm, (const float2*)b_dev, (double2*)x_dev, *o,
                                cnn ? net_precond : nullptr, cnn ? (void*)m : nullptr);
     if (s < 0) return s;
@@ -263,7 +263,7 @@ hh_status hh_apply_operator(hh_model* m, int level, double shift, int nrhs, cons
     HH_HIP(hipSetDevice(m->ctx->device));
     Buf ib;
     BatchMap bm;
-    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &bm));
+    HH_TRY(upload_inst_map(m, ib, nrhs, inst_host, &bm));
     HH_TRY(launch_apply_op(m, level, (float)shift, nrhs, bm.inst, (const float2*)x_dev, (float2*)y_dev, nullptr));
     HH_HIP(hipStreamSynchronize(m->ctx->stream));
     return HH_OK;
@@ -276,7 +276,7 @@ hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const voi
     HH_HIP(hipSetDevice(m->ctx->device));
     Buf ib, work;
     BatchMap bm;
-    HH_TRY(upload_inst(m, ib, nrhs, inst_host, &bm));
+    HH_TRY(upload_inst_map(m, ib, nrhs, inst_host, &bm));
     HH_TRY(work.ensure(m->ctx, vcycle_workspace_bytes(m, nrhs, x0_dev != nullptr) + 256));
     HH_TRY(launch_vcycle(m, nrhs, bm, (const float2*)b_dev, nullptr, 0, (const float2*)x0_dev, (float2*)x_dev,
                          work.ptr, nullptr));

@@ -239,5 +239,7 @@ hh_status launch_vcycle_strided(hh_model* m, int nrhs, const BatchMap& bm, const
                                 size_t zstride, void* work, const int* active);
 // RHS per workgroup of the coarsest solve (the grouping unit of BatchMap::order)
 int coarse_group();
+// copy a host RHS -> slowness-model map to the device (api.hip)
+hh_status upload_inst_map(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out);
 
 }  // namespace hh

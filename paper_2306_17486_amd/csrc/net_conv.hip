@@ -1,0 +1,232 @@
+// Convolutions of the encoder-solver network on gfx950 (Sec. 3.3, eq. 9; the
+// 3x3 layers of Sec. 4.1 / 5.3).  Activations are BF16 NHWC [b][y][x][c].
+//
+// Every 16/32/64-channel 3x3 convolution -- forward and input gradient -- is
+// one implicit GEMM on the matrix cores: out[p][o] = sum_k Wg[k][o] * in[src(p,k)],
+// k = tap * CIN + ci, with v_mfma_f32_16x16x32_bf16 (FP32 accumulation):
+//   A operand = 16 output channels x 32 k   (the packed weights, held in VGPRs)
+//   B operand = 32 k x 16 output pixels      (8 consecutive channels per lane from LDS)
+//   D         = 16 channels x 16 pixels      (each lane owns 4 consecutive channels of one pixel)
+// Modes: S1 (stride 1), S2 (stride 2, the downsampling layers), T2 (stride-2
+// transposed convolution, evaluated as a stride-1 convolution over the
+// zero-interleaved input with flipped weights).  The input gradients of the
+// three layer kinds are again S1/S2/T2 convolutions with repacked weights.
+// The epilogue fuses bias, a sum skip connection, ReLU, and (backward) the
+// ReLU mask of the tensor whose gradient is produced.
+#include "net.h"
+
+namespace hh {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Weight packing: FP32 layer weights -> BF16 chunks Wp[ch][o][32] of the
+// gather form Wg[tap][o][i] (k = tap * CIN + i, zero beyond tap 8).
+//   direct:   Wg[t][o][i] = W[o][i][t]       (W's first index is the output channel)
+//   flipped:  Wg[t][o][i] = W[i][o][8 - t]   (W's first index is the input channel)
+// ---------------------------------------------------------------------------
+__global__ void k_pack_weights(const float* __restrict__ W, uint16_t* __restrict__ Wp, int cin, int cout, int flipped,
+                               int nch) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = nch * cout * 32;
+    if (e >= total) return;
+    const int kk = e % 32, o = (e / 32) % cout, ch = e / (32 * cout);
+    const int k = ch * 32 + kk;
+    const int t = k / cin, i = k % cin;
+    float v = 0.f;
+    if (t < 9) v = flipped ? W[((size_t)i * cout + o) * 9 + (8 - t)] : W[((size_t)o * cin + i) * 9 + t];
+    Wp[e] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// The MFMA convolution.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int MODE>
+struct ConvCfg {
+    static constexpr int TC = 32;                                               // output tile columns
+    static constexpr int TR = (MODE == CM_S2) ? (CIN >= 64 ? 2 : 4) : (CIN >= 64 ? 4 : 8);  // output tile rows
+    static constexpr int NT = COUT / 16;                                        // channel tiles
+    static constexpr int WPT = 4 / NT;                                          // waves per channel tile
+    static constexpr int PB = TR * (TC / 16);                                   // 16-pixel blocks per tile
+    static constexpr int PBW = PB / WPT;                                        // pixel blocks per wave
+    static constexpr int NCH = (9 * CIN + 31) / 32;                             // k chunks
+    static constexpr int PH = (MODE == CM_S2) ? 2 * TR + 1 : TR + 2;            // staged input rows
+    static constexpr int PW = (MODE == CM_S2) ? 2 * TC + 1 : TC + 2;            // staged input cols
+    static constexpr int CP = CIN + 8;                                          // LDS channel pitch (bf16)
+    static constexpr int LDS_BYTES = PH * PW * CP * 2;
+};
+
+template <int CIN, int COUT, int MODE>
+__global__ void __launch_bounds__(256) k_conv_mfma(ConvArgs a) {
+    using C = ConvCfg<CIN, COUT, MODE>;
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[C::PH * C::PW * C::CP];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ct = wave % C::NT;           // channel tile of this wave
+    const int wsub = wave / C::NT;         // which share of the pixel blocks
+    const int lp = lane & 15, lg = lane >> 4;
+
+    // this wave's weights stay in VGPRs for all tiles
+    bf16x8 wreg[C::NCH];
+    {
+        const uint4* wp4 = reinterpret_cast<const uint4*>(a.wp);
+#pragma unroll
+        for (int ch = 0; ch < C::NCH; ++ch) {
+            uint4 v = wp4[((size_t)ch * COUT + ct * 16 + lp) * 4 + lg];
+            wreg[ch] = *reinterpret_cast<bf16x8*>(&v);
+        }
+    }
+    float bias4[4] = {0.f, 0.f, 0.f, 0.f};
+    if (a.bias)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias4[i] = a.bias[ct * 16 + 4 * lg + i];
+
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int b = tile / (a.tiles_x * a.tiles_y);
+        const int rem = tile - b * a.tiles_x * a.tiles_y;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        if (a.active && !a.active[b]) continue;  // uniform over the block
+        const int y0 = ty * C::TR, x0 = tx * C::TC;
+        __syncthreads();  // previous tile's readers are done with s_in
+        // ---- stage the input patch (zero padding / zero interleaving) ----
+        const uint16_t* xb = a.x + (size_t)b * a.Hin * a.Win * CIN;
+        constexpr int VEC = CIN / 8;
+        for (int e = tid; e < C::PH * C::PW * VEC; e += 256) {
+            const int v = e % VEC, pix = e / VEC;
+            const int py = pix / C::PW, px = pix - py * C::PW;
+            int iy, ix;
+            bool in;
+            if (MODE == CM_S1) {
+                iy = y0 - 1 + py;
+                ix = x0 - 1 + px;
+                in = iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+            } else if (MODE == CM_S2) {
+                iy = 2 * y0 - 1 + py;
+                ix = 2 * x0 - 1 + px;
+                in = iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+            } else {  // T2: u[2i][2j] = x[i][j]
+                const int uy = y0 - 1 + py, ux = x0 - 1 + px;
+                in = uy >= 0 && ux >= 0 && !(uy & 1) && !(ux & 1) && (uy >> 1) < a.Hin && (ux >> 1) < a.Win;
+                iy = uy >> 1;
+                ix = ux >> 1;
+            }
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (in) val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
+            *reinterpret_cast<uint4*>(&s_in[(py * C::PW + px) * C::CP + 8 * v]) = val;
+        }
+        __syncthreads();
+        // ---- MFMA over the k chunks ----
+        f32x4 acc[C::PBW];
+#pragma unroll
+        for (int q = 0; q < C::PBW; ++q) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < C::NCH; ++ch) {
+            const int k0 = ch * 32 + 8 * lg;
+            const int tap = k0 / CIN, ci = k0 % CIN;
+            const int ky = tap / 3, kx = tap - 3 * ky;
+#pragma unroll
+            for (int q = 0; q < C::PBW; ++q) {
+                const int pbk = wsub * C::PBW + q;          // pixel block in the tile
+                const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
+                bf16x8 bv;
+                if (tap < 9) {
+                    int sy, sx;
+                    if (MODE == CM_S2) {
+                        sy = 2 * ry + ky;
+                        sx = 2 * rx + kx;
+                    } else {
+                        sy = ry + ky;
+                        sx = rx + kx;
+                    }
+                    uint4 raw = *reinterpret_cast<const uint4*>(&s_in[(sy * C::PW + sx) * C::CP + ci]);
+                    bv = *reinterpret_cast<bf16x8*>(&raw);
+                } else {
+                    uint4 z = make_uint4(0, 0, 0, 0);
+                    bv = *reinterpret_cast<bf16x8*>(&z);
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[ch], bv, acc[q], 0, 0, 0);
+            }
+        }
+        // ---- epilogue: lane owns channels ct*16 + 4 lg .. +3 of one pixel per block ----
+        const int co = ct * 16 + 4 * lg;
+        const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
+#pragma unroll
+        for (int q = 0; q < C::PBW; ++q) {
+            const int pbk = wsub * C::PBW + q;
+            const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
+            const int oy = y0 + ry, ox = x0 + rx;
+            if (oy >= a.Hout || ox >= a.Wout) continue;
+            const size_t po = (((size_t)b * a.Hout + oy) * a.Wout + ox) * COUT + co;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = acc[q][i] + bias4[i];
+            if (a.skip) {
+                const size_t so = (((size_t)sb * a.Hout + oy) * a.Wout + ox) * COUT + co;
+                uint2 s2 = *reinterpret_cast<const uint2*>(a.skip + so);
+                v[0] += bf2f((uint16_t)(s2.x & 0xffff));
+                v[1] += bf2f((uint16_t)(s2.x >> 16));
+                v[2] += bf2f((uint16_t)(s2.y & 0xffff));
+                v[3] += bf2f((uint16_t)(s2.y >> 16));
+            }
+            if (a.relu)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
+            if (a.mask) {
+                uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
+                if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
+                if (!(bf2f((uint16_t)(m2.x >> 16)) > 0.f)) v[1] = 0.f;
+                if (!(bf2f((uint16_t)(m2.y & 0xffff)) > 0.f)) v[2] = 0.f;
+                if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
+            }
+            uint2 o2;
+            o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+            o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+            *reinterpret_cast<uint2*>(a.y + po) = o2;
+            if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+template <int CIN, int COUT, int MODE>
+static hh_status launch_conv_t(hipStream_t st, ConvArgs a, int num_cus) {
+    using C = ConvCfg<CIN, COUT, MODE>;
+    a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
+    a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
+    a.ntiles = a.B * a.tiles_x * a.tiles_y;
+    if (a.ntiles == 0) return HH_OK;
+    const int grid = std::min(a.ntiles, 8 * num_cus);
+    hipLaunchKernelGGL((k_conv_mfma<CIN, COUT, MODE>), dim3(grid), dim3(256), 0, st, a);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a) {
+#define HH_CONV_CASE(CI, CO, MD) \
+    if (cin == CI && cout == CO && mode == MD) return launch_conv_t<CI, CO, MD>(st, a, num_cus);
+    HH_CONV_CASE(16, 16, CM_S1)
+    HH_CONV_CASE(32, 32, CM_S1)
+    HH_CONV_CASE(64, 64, CM_S1)
+    HH_CONV_CASE(16, 32, CM_S2)
+    HH_CONV_CASE(32, 64, CM_S2)
+    HH_CONV_CASE(64, 64, CM_S2)
+    HH_CONV_CASE(64, 64, CM_T2)
+    HH_CONV_CASE(64, 32, CM_T2)
+    HH_CONV_CASE(32, 16, CM_T2)
+#undef HH_CONV_CASE
+    set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
+    return HH_ERR_ARG;
+}
+
+hh_status pack_weights(hipStream_t st, const float* W, uint16_t* Wp, int cin, int cout, bool flipped) {
+    const int nch = (9 * cin + 31) / 32;
+    const int total = nch * cout * 32;
+    hipLaunchKernelGGL(k_pack_weights, dim3((total + 255) / 256), dim3(256), 0, st, W, Wp, cin, cout,
+                       flipped ? 1 : 0, nch);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+size_t packed_weight_elems(int cin, int cout) { return (size_t)((9 * cin + 31) / 32) * cout * 32; }
+
+}  // namespace hh

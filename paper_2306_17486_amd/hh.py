@@ -78,6 +78,22 @@ hh_solve_opts_default = _sig("hh_solve_opts_default", None, C.POINTER(hh_solve_o
 hh_solve = _sig("hh_solve", _I, _P, _P, _I, _IP, _P, _P, C.POINTER(hh_solve_opts), _DP, _IP, _IP, _DP)
 hh_apply_operator = _sig("hh_apply_operator", _I, _P, _I, _D, _I, _IP, _P, _P)
 hh_apply_vcycle = _sig("hh_apply_vcycle", _I, _P, _I, _IP, _P, _P, _P)
+class hh_net_desc(C.Structure):
+    _fields_ = [("ch", C.c_int * 4)]
+
+
+_FP = C.POINTER(C.c_float)
+hh_net_create = _sig("hh_net_create", _I, _P, C.POINTER(hh_net_desc), _FP, C.POINTER(_P))
+hh_net_destroy = _sig("hh_net_destroy", _I, _P)
+hh_net_num_params = _sig("hh_net_num_params", C.c_size_t, _P)
+hh_net_get_params = _sig("hh_net_get_params", _I, _P, _FP)
+hh_net_set_params = _sig("hh_net_set_params", _I, _P, _FP)
+hh_net_save = _sig("hh_net_save", _I, _P, C.c_char_p)
+hh_net_load = _sig("hh_net_load", _I, _P, C.c_char_p, C.POINTER(_P))
+hh_model_attach_net = _sig("hh_model_attach_net", _I, _P, _P)
+hh_net_forward = _sig("hh_net_forward", _I, _P, _I, _IP, _P, _P)
+hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P)
+hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
 hh_profile_begin = _sig("hh_profile_begin", _I, _P, _I)
 hh_profile_end = _sig("hh_profile_end", _I, _P, _DP, C.POINTER(C.c_longlong))
 HH_K_NUM_CLASSES = 11
@@ -205,6 +221,16 @@ class Model:
         check(hh_apply_vcycle(self.handle, b.shape[0], _int_array(inst), _ptr(b), _ptr(x0), _ptr(x)))
         return x
 
+    def attach_net(self, net: "Net | None"):
+        check(hh_model_attach_net(self.handle, net.handle if net is not None else None))
+        self.net = net
+
+    def net_forward(self, r: torch.Tensor, inst=None) -> torch.Tensor:
+        r = r.to(torch.complex64).contiguous()
+        e = torch.empty_like(r)
+        check(hh_net_forward(self.handle, r.shape[0], _int_array(inst), _ptr(r), _ptr(e)))
+        return e
+
     # -- solve --------------------------------------------------------------
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, inst=None, restart=10, max_iters=2000,
               rtol=1e-6, precond=HH_PRECOND_MG, warm_mg_iters=3, fixed_iters=0, want_hist=True):
@@ -229,3 +255,123 @@ class Model:
                       conv.ctypes.data_as(_IP), fres.ctypes.data_as(_DP))
         check(st, allow=(HH_OK, HH_NOT_CONVERGED))
         return x, dict(iters=iters, converged=conv.astype(bool), final_res=fres, hist=hist, status=st)
+
+
+# ---------------------------------------------------------------------------
+# network
+# ---------------------------------------------------------------------------
+
+NET_LAYER_NAMES = ["enc1_d", "enc1_c1", "enc1_c2", "enc2_d", "enc2_c1", "enc2_c2", "enc3_d", "enc3_c1", "enc3_c2",
+                   "s1_d", "s1_c1", "s1_c2", "s2_d", "s2_c1", "s2_c2", "s3_d", "s3_c1", "s3_c2",
+                   "s4_d", "s4_c1", "s4_c2", "u3_t", "u3_c1", "u3_c2", "u2_t", "u2_c1", "u2_c2",
+                   "u1_t", "u1_c1", "u1_c2", "out"]
+
+
+def flatten_params(p: dict, ch=(16, 32, 64, 64)) -> np.ndarray:
+    """Named parameters (weights, biases, complex implicit kernels) -> the flat
+    FP32 vector of include/hh.h (layer order, weights then biases, then K as re/im)."""
+    parts = []
+    for name in NET_LAYER_NAMES:
+        parts.append(np.asarray(p[name + ".w"], dtype=np.float64).ravel())
+        parts.append(np.asarray(p[name + ".b"], dtype=np.float64).ravel())
+    K = np.asarray(p["implicit_K"])
+    parts.append(np.stack([K.real, K.imag], axis=-1).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unflatten_params(flat: np.ndarray, ch=(16, 32, 64, 64)) -> dict:
+    from . import inputs
+    out = {}
+    off = 0
+    for name, kind, cin, cout in inputs.net_layers(ch):
+        shape = (cin, cout, 3, 3) if kind in ("t", "t4") else (cout, cin, 3, 3)
+        sz = int(np.prod(shape))
+        out[name + ".w"] = flat[off:off + sz].reshape(shape).astype(np.float64)
+        off += sz
+        out[name + ".b"] = flat[off:off + cout].astype(np.float64)
+        off += cout
+    nk = ch[3] // 2
+    k = flat[off:off + nk * 18].reshape(nk, 3, 3, 2).astype(np.float64)
+    out["implicit_K"] = k[..., 0] + 1j * k[..., 1]
+    return out
+
+
+class Net:
+    """Encoder-solver network on the device (FP32 master parameters)."""
+
+    def __init__(self, ctx: Context, params: dict | np.ndarray | None = None, ch=(16, 32, 64, 64), _handle=None):
+        self.ctx = ctx
+        self.ch = tuple(ch)
+        if _handle is not None:
+            self.handle = _handle
+            return
+        d = hh_net_desc()
+        for i in range(4):
+            d.ch[i] = ch[i]
+        flat = None
+        if params is not None:
+            flat = params if isinstance(params, np.ndarray) else flatten_params(params, ch)
+            flat = np.ascontiguousarray(flat, dtype=np.float32)
+        h = C.c_void_p()
+        check(hh_net_create(ctx.handle, C.byref(d), flat.ctypes.data_as(_FP) if flat is not None else None,
+                            C.byref(h)))
+        self.handle = h
+        if flat is not None:
+            assert flat.size == self.num_params(), (flat.size, self.num_params())
+
+    @classmethod
+    def load(cls, ctx: Context, path: str) -> "Net":
+        h = C.c_void_p()
+        check(hh_net_load(ctx.handle, path.encode(), C.byref(h)))
+        return cls(ctx, _handle=h)
+
+    def save(self, path: str):
+        check(hh_net_save(self.handle, path.encode()))
+
+    def num_params(self) -> int:
+        return int(hh_net_num_params(self.handle))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.num_params(), dtype=np.float32)
+        check(hh_net_get_params(self.handle, a.ctypes.data_as(_FP)))
+        return a
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.num_params()
+        check(hh_net_set_params(self.handle, a.ctypes.data_as(_FP)))
+
+    def implicit_test(self, x_bf16: torch.Tensor, nc: int, adjoint=False) -> torch.Tensor:
+        y = torch.empty_like(x_bf16)
+        check(hh_implicit_test(self.handle, nc, x_bf16.shape[0], _ptr(x_bf16), _ptr(y), int(adjoint)))
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            hh_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, flipped: bool, bias=None, skip=None,
+              relu=False):
+    """One convolution through the library's MFMA kernel; returns (y bf16, y fp32)."""
+    B, H, W_, cin = x_bf16.shape
+    cout = w.shape[1] if flipped else w.shape[0]
+    Ho = H // 2 if mode == 1 else (2 * H if mode == 2 else H)
+    Wo = W_ // 2 if mode == 1 else (2 * W_ if mode == 2 else W_)
+    y = torch.empty((B, Ho, Wo, cout), dtype=torch.bfloat16, device=x_bf16.device)
+    yf = torch.empty((B, Ho, Wo, cout), dtype=torch.float32, device=x_bf16.device)
+    # keep every converted tensor referenced until the call returns: the library
+    # allocates through torch's caching allocator and could otherwise reuse them
+    w = w.to(torch.float32).contiguous()
+    bias = bias.to(torch.float32).contiguous() if bias is not None else None
+    skip = skip.contiguous() if skip is not None else None
+    check(hh_conv_test(ctx.handle, cin, cout, mode, B, H, W_, _ptr(x_bf16), _ptr(w), int(flipped), _ptr(bias),
+                       _ptr(skip), int(relu), _ptr(y), _ptr(yf)))
+    return y, yf

@@ -1,0 +1,149 @@
+"""GPU parity of the network kernels against the FP64 oracle, through the C ABI.
+
+* every MFMA convolution instantiation on BF16-representable inputs and weights
+  (products are exact, so the FP32 outputs agree to FP32 summation error);
+* the LDS-resident implicit layer (and its adjoint) against the FFT definition;
+* the whole encoder-solver network (random initial weights) below and above
+  n = 512, where the coarsest pair changes stride;
+* the two-phase CNN+MG FGMRES solve against the oracle's."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn as C
+from oracle import helmholtz as H
+from oracle import solver as S
+from paper_2306_17486_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hh():
+    from paper_2306_17486_amd import hh as _hh
+    return _hh
+
+
+@pytest.fixture(scope="module")
+def ctx(hh):
+    return hh.Context(0)
+
+
+def _bf16_round(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+
+
+def _nhwc_dev(x_nchw):
+    return torch.from_numpy(np.ascontiguousarray(x_nchw.transpose(0, 2, 3, 1))).to("cuda:0", torch.bfloat16)
+
+
+CONV_CASES = [
+    # (cin, cout, mode, flipped, H)   mode 0 = S1, 1 = S2, 2 = T2; flipped = transposed-conv weights
+    (16, 16, 0, False, 20), (32, 32, 0, False, 20), (64, 64, 0, False, 12),
+    (16, 32, 1, False, 20), (32, 64, 1, False, 20), (64, 64, 1, False, 12),
+    (64, 64, 2, True, 6), (64, 32, 2, True, 10), (32, 16, 2, True, 10),
+    (64, 64, 0, True, 12),
+]
+
+
+@pytest.mark.parametrize("cin,cout,mode,flipped,Hs", CONV_CASES)
+def test_conv_kernel(hh, ctx, cin, cout, mode, flipped, Hs):
+    _say(f"conv cin={cin} cout={cout} mode={mode} flipped={flipped} H={Hs}")
+    rng = np.random.default_rng(cin * 100 + cout + 7 * mode)
+    B = 2
+    x = _bf16_round(rng.standard_normal((B, cin, Hs, Hs)))
+    wshape = (cin, cout, 3, 3) if flipped else (cout, cin, 3, 3)
+    w = _bf16_round(rng.standard_normal(wshape) / np.sqrt(9 * cin))
+    b = rng.standard_normal(cout)
+    if flipped:
+        stride = 2 if mode == 2 else 1
+        ref = C.conv_transpose2d(x, w, b, stride)
+    else:
+        ref = C.conv2d(x, w, b, 2 if mode == 1 else 1)
+    skip = _bf16_round(rng.standard_normal(ref.shape))
+    for use_skip, relu in ((False, False), (True, True)):
+        r = ref + skip if use_skip else ref
+        if relu:
+            r = np.maximum(r, 0.0)
+        y, yf = hh.conv_test(ctx, _nhwc_dev(x), torch.from_numpy(w).cuda(), mode, flipped,
+                             bias=torch.from_numpy(b).cuda(), skip=_nhwc_dev(skip) if use_skip else None, relu=relu)
+        got = yf.cpu().numpy().transpose(0, 3, 1, 2)
+        assert got.shape == r.shape
+        err = np.abs(got - r).max() / np.abs(r).max()
+        assert err <= 2e-6, (use_skip, relu, err)
+        # BF16 output = round-to-nearest-even of the FP32 result
+        yb = y.to(torch.float32).cpu().numpy().transpose(0, 3, 1, 2)
+        assert np.array_equal(yb, _bf16_round(got))
+
+
+@pytest.mark.parametrize("nc", [8, 16, 32])
+def test_implicit_layer(hh, ctx, nc):
+    _say(f"implicit layer nc={nc}")
+    p = inputs.init_net_params(3)
+    rng = np.random.default_rng(nc)
+    K = p["implicit_K"] + 0.3 * (rng.standard_normal((32, 3, 3)) + 1j * rng.standard_normal((32, 3, 3)))
+    p["implicit_K"] = K
+    net = hh.Net(ctx, p)
+    B = 2
+    x = _bf16_round(rng.standard_normal((B, 64, nc, nc)))
+    Ghat, _ = C.green_hat(K, nc)
+    for adjoint in (False, True):
+        y = net.implicit_test(_nhwc_dev(x), nc, adjoint=adjoint).to(torch.float32).cpu().numpy().transpose(0, 3, 1, 2)
+        z = C.pair(x)
+        if adjoint:
+            _, Z = C.implicit_apply(Ghat, z)
+            ref = C.unpair(C.implicit_backward(Ghat, Z, z)[0])
+        else:
+            ref = C.unpair(C.implicit_apply(Ghat, z)[0])
+        tol = 2.0 ** -8 * np.abs(ref) + 2e-5 * np.abs(ref).max()
+        assert np.all(np.abs(y - ref) <= tol), (adjoint, np.abs(y - ref).max() / np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,family", [(64, "grf"), (128, "layered"), (512, "grf")])
+def test_network_forward(hh, ctx, n, family):
+    _say(f"network forward n={n}")
+    k = inputs.slowness(n, 21, family)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    p = inputs.init_net_params(5)
+    net = hh.Net(ctx, p)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.attach_net(net)
+    nr = 2 if n <= 128 else 1
+    r = inputs.random_complex((nr, n, n), 8)
+    e = m.net_forward(torch.from_numpy(r).to("cuda:0", torch.complex64)).cpu().numpy()
+    netp = S.NetPrecond(C.Net(p), prob)
+    for i in range(nr):
+        ref = netp(r[i])
+        err = np.linalg.norm(e[i] - ref) / np.linalg.norm(ref)
+        _say(f"  rhs {i}: relative error {err:.3e}")
+        assert err <= 3e-2
+
+
+def test_cnn_mg_two_phase_solve(hh, ctx):
+    n = 64
+    _say("cnn+mg two-phase solve")
+    k = inputs.grf_slowness(n, 30)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    p = inputs.init_net_params(6)
+    net = hh.Net(ctx, p)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.attach_net(net)
+    b = np.stack([inputs.point_source(n, 40), inputs.point_source(n, 41)])
+    x, info = m.solve(torch.from_numpy(b).to("cuda:0", torch.complex64), precond=hh.HH_PRECOND_CNN_MG)
+    x = x.cpu().numpy()
+    netp = S.NetPrecond(C.Net(p), prob)
+    for r in range(2):
+        rel = np.linalg.norm(b[r] - prob.A(x[r])) / np.linalg.norm(b[r])
+        assert info["converged"][r] and rel <= 1e-6
+        _, its_o, _, _ = S.solve_two_phase(prob, netp, b[r])
+        _say(f"  rhs {r}: gpu {info['iters'][r]} oracle {its_o}")
+        assert abs(int(info["iters"][r]) - its_o) <= max(3, int(0.25 * its_o))
