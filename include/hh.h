@@ -194,6 +194,28 @@ hh_status hh_model_attach_net(hh_model* m, hh_net* net);
  * P the bilinear prolongation; r, e c64 [nrhs][n][n]. */
 hh_status hh_net_forward(hh_model* m, int nrhs, const int* inst_host, const void* r_dev, void* e_dev);
 
+/* Method-generated training pairs (Sec. 4.3, eq. 20) for nb samples on the
+ * model's (training) operator, sample b using slowness model b (or the single
+ * model when the model holds one):
+ *   b_i = A x_i,  x~_i = kiters_host[i] iterations of MG-preconditioned FGMRES from 0,
+ *   e_i = x_i - x~_i,  r_i = A e_i.
+ * x_dev: c64 [nb][n][n] random vectors (an input); e_dev, r_dev: c64 outputs;
+ * kiters_host: host int[nb], each in 1..HH_MAX_RESTART. */
+hh_status hh_gen_training_pairs(hh_ctx* ctx, hh_model* m, int nb, const void* x_dev, const int* kiters_host,
+                                void* e_dev, void* r_dev);
+
+/* One training step on B pairs (r, e) (c64 [B][n][n]), sample b on slowness
+ * model b of md (md->ninst == B), n < 512: BF16 forward and backward through
+ * encoder, solver and implicit layer, loss (eq. 19)
+ *   L = (1/B) sum_b || P(Net(r_b / rms(r_b))) - e_b / s_b ||^2,  s_b = h^2 rms(r_b),
+ * FP32 gradients (hh_net_get_grads), then one Adam step with learning rate lr
+ * (betas 0.9, 0.999, eps 1e-8; lr = 0 computes the gradients only).
+ * *loss_out receives L before the update.  Synchronises the stream. */
+hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev, double lr,
+                        double* loss_out);
+/* FP32 gradients of the last training step, same layout as the parameters. */
+hh_status hh_net_get_grads(hh_net* net, float* host);
+
 /* Parity-test entry points (same kernels as the network).
  * hh_conv_test: one 3x3 convolution of BF16 NHWC x [B][Hin][Win][cin] with FP32
  *   weights w_dev; mode 0 = stride 1, 1 = stride 2, 2 = transposed stride 2;
@@ -203,11 +225,20 @@ hh_status hh_net_forward(hh_model* m, int nrhs, const int* inst_host, const void
  *   bias (FP32, may be NULL), skip (BF16, output shape, may be NULL), relu;
  *   y_dev BF16 output, yf_dev optional FP32 output.
  * hh_implicit_test: the implicit layer for coarsest size nc on BF16 NHWC
- *   [B][nc][nc][ch[3]] (adjoint = 1 multiplies by conj(Ghat)). */
+ *   [B][nc][nc][ch[3]] (adjoint = 1 multiplies by conj(Ghat)).
+ * hh_wgrad_test: the weight-gradient kernel of the training pass,
+ *   out[oo][ii][t] = sum over b and output pixels p of
+ *   a[b][p][oo] * x[b][s*p + (t/3 - 1, t%3 - 1)][ii]   (zero outside x),
+ *   a BF16 NHWC [B][Ho][Wo][ca], x BF16 NHWC [B][Hi][Wi][cx], s = 1 (mode 0,
+ *   Hi = Ho) or 2 (mode 1, Hi = 2 Ho); out FP32 [ca][cx][9], overwritten.
+ *   (ca, cx, mode) in {(16,16,0), (32,32,0), (64,64,0), (32,16,1), (64,32,1),
+ *   (64,64,1)}, otherwise HH_ERR_ARG. */
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
                        const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int relu,
                        void* y_dev, float* yf_dev);
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint);
+hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, int Wo, int Hi, int Wi,
+                        const void* a_dev, const void* x_dev, float* out_dev);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (HIP events on the context's stream).

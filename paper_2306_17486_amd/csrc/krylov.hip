@@ -254,7 +254,8 @@ __global__ void __launch_bounds__(256) k_arnoldi_col(const double2* __restrict__
 // small triangular solve, per-RHS flags.
 __global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ parts, int npart, int j,
                                                 KState* __restrict__ st, int* __restrict__ active,
-                                                double* __restrict__ hist, int hist_len, double rtol, int max_iters) {
+                                                double* __restrict__ hist, int hist_len, double rtol, int max_iters,
+                                                const int* __restrict__ caps) {
     __shared__ double2 s_red[4];
     const int r = blockIdx.x;
     if (!active[r]) return;
@@ -316,7 +317,8 @@ __global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ part
     if (bad) S.breakdown = 1;
     const bool by_est = est <= rtol * S.tol_scale;
     if (by_est) S.ended_by_est = 1;
-    if (bad || by_est || S.iters >= max_iters || hn == 0.0) active[r] = 0;
+    const int cap = caps ? min(caps[r], max_iters) : max_iters;
+    if (bad || by_est || S.iters >= cap || hn == 0.0) active[r] = 0;
 }
 
 // x += sum_{q<k} y_q z_q  (x complex double)
@@ -373,7 +375,8 @@ __global__ void k_init_state(const double2* __restrict__ parts, int npart, KStat
 
 // Start of a restart cycle: beta = ||r||, true relative residual, stopping test.
 __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KState* __restrict__ st, int* done,
-                              int* active, double* hist, int hist_len, double rtol, int max_iters, int fixed) {
+                              int* active, double* hist, int hist_len, double rtol, int max_iters, int fixed,
+                              const int* __restrict__ caps) {
     __shared__ double2 s_red[4];
     const int r = blockIdx.x;
     if (done[r]) {
@@ -395,7 +398,8 @@ __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KSta
     // says otherwise: ask the next cycles for a 10x deeper reduction
     if (S.ended_by_est && !S.converged) S.tol_scale = fmax(S.tol_scale * 0.1, 1e-4);
     S.ended_by_est = 0;
-    if (bad || S.converged || S.iters >= max_iters || beta == 0.0) {
+    const int cap = caps ? min(caps[r], max_iters) : max_iters;
+    if (bad || S.converged || S.iters >= cap || beta == 0.0) {
         done[r] = 1;
         active[r] = 0;
         return;
@@ -486,7 +490,7 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
         {
             ProfScope ps(ctx, HH_K_SMALL);
             hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist,
-                               W.hist_len, rtol, max_iters, fixed ? 1 : 0);
+                               W.hist_len, rtol, max_iters, fixed ? 1 : 0, W.caps_dev);
         }
         HH_LAUNCH_CHECK();
         HH_HIP(hipMemcpyAsync(hdone.data(), done, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -539,7 +543,7 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
             {
                 ProfScope ps(ctx, HH_K_SMALL);
                 hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(256), 0, st, parts, np, j, S, act, hist, W.hist_len,
-                                   rtol, max_iters);
+                                   rtol, max_iters, W.caps_dev);
             }
             HH_LAUNCH_CHECK();
         }
@@ -555,7 +559,7 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
                                1.0 / (L0.h * L0.h), parts, nullptr);
             HH_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist,
-                               W.hist_len, rtol, 0, 1);
+                               W.hist_len, rtol, 0, 1, W.caps_dev);
             HH_LAUNCH_CHECK();
             break;
         }

@@ -57,4 +57,6 @@ struct hh_net {
     bool packed_valid = false;
     long long step = 0;
     unsigned long long version = 1;         // bumped whenever the parameters change
+    void* train_work = nullptr;             // training workspace (net.hip)
+    ~hh_net();
 };

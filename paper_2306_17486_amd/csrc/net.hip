@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_prolong_x0(const float2* __restrict__ o
 template <int M, int NT>
 __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xin, uint16_t* __restrict__ yout,
                                                  const float2* __restrict__ Gbr, int nc, int nk, int conjG,
-                                                 const int* __restrict__ active) {
+                                                 const uint16_t* __restrict__ mask, const int* __restrict__ active) {
     extern __shared__ float2 s_dyn[];
     constexpr int P = M + 1;
     float2* s = s_dyn;
@@ -318,16 +318,21 @@ __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xi
     }
     for (int e = tid; e < nc * nc; e += NT) {
         const int y = e / nc, x = e - y * nc;
-        const float2 v = s[y * P + x];
-        uint16_t* py = yout + (((size_t)b * nc + y) * nc + x) * CH + 2 * c;
-        *reinterpret_cast<uint32_t*>(py) = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+        float2 v = s[y * P + x];
+        const size_t o = (((size_t)b * nc + y) * nc + x) * CH + 2 * c;
+        if (mask) {
+            const uint32_t mr = *reinterpret_cast<const uint32_t*>(mask + o);
+            if (!(bf2f((uint16_t)(mr & 0xffff)) > 0.f)) v.x = 0.f;
+            if (!(bf2f((uint16_t)(mr >> 16)) > 0.f)) v.y = 0.f;
+        }
+        *reinterpret_cast<uint32_t*>(yout + o) = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
     }
 }
 
 static size_t implicit_lds_bytes(int M) { return ((size_t)M * (M + 1) + M / 2) * sizeof(float2); }
 
 hh_status launch_implicit(hipStream_t st, int M, const uint16_t* x, uint16_t* y, const float2* Gbr, int nc, int nk,
-                          int B, bool conjG, const int* active) {
+                          int B, bool conjG, const int* active, const uint16_t* mask = nullptr) {
     const size_t lds = implicit_lds_bytes(M);
     dim3 grd(nk, B);
 #define HH_IMP(MM, NTT)                                                                                  \
@@ -339,7 +344,7 @@ hh_status launch_implicit(hipStream_t st, int M, const uint16_t* x, uint16_t* y,
             attr_set = true;                                                                             \
         }                                                                                                \
         hipLaunchKernelGGL((k_implicit<MM, NTT>), grd, dim3(NTT), lds, st, x, y, Gbr, nc, nk, conjG ? 1 : 0, \
-                           active);                                                                      \
+                           mask, active);                                                                \
         HH_LAUNCH_CHECK();                                                                               \
         return HH_OK;                                                                                    \
     }
@@ -544,8 +549,7 @@ struct NetCache {
     hh_net* net = nullptr;
     unsigned long long version = 0;
     int n = 0, nc = 0, M = 0;
-    Buf E[3];      // BF16 encodings per instance
-    Buf tmp[2];    // encoder temporaries
+    Buf enc[9];    // BF16 outputs of the 9 encoder layers per instance (E1, E2, E3 = enc[2], enc[5], enc[8])
     Buf Gbr;       // bit-reversed, scaled Ghat [nk][M][M]
     NetActs acts;  // forward activations of the solves on this model
 };
@@ -579,47 +583,32 @@ static hh_status conv_layer(hh_net* net, int l, int mode, const uint16_t* x, int
 }
 
 // Encoder (Sec. 5.3): three levels of (strided conv, conv+ReLU, conv+ReLU) on
-// the dimensionless mass term of every slowness model of the model.
-static hh_status run_encoder(hh_net* net, hh_model* md, NetCache* nc) {
+// the dimensionless mass term of every slowness model of the model; every layer
+// output is kept (the training pass needs them).
+hh_status encoder_forward(hh_net* net, hh_model* md, Buf* enc) {
     hipStream_t st = net->ctx->stream;
     const int n = md->lev[0].n, B = md->ninst;
     const double h = md->lev[0].h;
-    const int c[3] = {net->ch[0], net->ch[1], net->ch[2]};
-    size_t tmax = 0;
-    for (int l = 0; l < 3; ++l) {
-        const size_t sz = (size_t)B * (n >> (l + 1)) * (n >> (l + 1)) * c[l] * sizeof(uint16_t);
-        HH_TRY(nc->E[l].ensure(net->ctx, sz));
-        tmax = std::max(tmax, sz);
+    for (int l = 0; l < 9; ++l) {
+        const int lev = l / 3 + 1;
+        HH_TRY(enc[l].ensure(net->ctx, (size_t)B * (n >> lev) * (n >> lev) * net->L[l].cout * sizeof(uint16_t)));
     }
-    HH_TRY(nc->tmp[0].ensure(net->ctx, tmax));
-    HH_TRY(nc->tmp[1].ensure(net->ctx, tmax));
-    uint16_t* t0 = nc->tmp[0].as<uint16_t>();
-    uint16_t* t1 = nc->tmp[1].as<uint16_t>();
+    auto E = [&](int l) { return enc[l].as<uint16_t>(); };
     const float* P = net->params.as<float>();
-    {
-        const int m = n / 2;
-        dim3 grd((m * m + 255) / 256, B);
-        if (c[0] != 16) {
-            set_error("first-level channel count must be 16");
-            return HH_ERR_ARG;
-        }
-        hipLaunchKernelGGL((k_conv_in<1, 16>), grd, dim3(256), 0, st, md->lev[0].coef.as<float2>(), (size_t)n * n,
-                           nullptr, nullptr, (float)(h * h), P + net->L[L_ENC1_D].woff, P + net->L[L_ENC1_D].boff,
-                           nullptr, nullptr, t0, n, nullptr);
-        HH_LAUNCH_CHECK();
-        HH_TRY(conv_layer(net, L_ENC1_C1, CM_S1, t0, B, m, m, t1, m, m, nullptr, nullptr, true, nullptr));
-        HH_TRY(conv_layer(net, L_ENC1_C2, CM_S1, t1, B, m, m, nc->E[0].as<uint16_t>(), m, m, nullptr, nullptr, true,
-                          nullptr));
-    }
-    const int ld[2] = {L_ENC2_D, L_ENC3_D};
+    const int m1 = n / 2;
+    hipLaunchKernelGGL((k_conv_in<1, 16>), dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st,
+                       md->lev[0].coef.as<float2>(), (size_t)n * n, nullptr, nullptr, (float)(h * h),
+                       P + net->L[L_ENC1_D].woff, P + net->L[L_ENC1_D].boff, nullptr, nullptr, E(L_ENC1_D), n,
+                       nullptr);
+    HH_LAUNCH_CHECK();
+    HH_TRY(conv_layer(net, L_ENC1_C1, CM_S1, E(L_ENC1_D), B, m1, m1, E(L_ENC1_C1), m1, m1, nullptr, nullptr, true, nullptr));
+    HH_TRY(conv_layer(net, L_ENC1_C2, CM_S1, E(L_ENC1_C1), B, m1, m1, E(L_ENC1_C2), m1, m1, nullptr, nullptr, true, nullptr));
     for (int k = 0; k < 2; ++k) {
         const int mi = n >> (k + 1), mo = mi / 2;
-        const int l = ld[k];
-        HH_TRY(conv_layer(net, l, CM_S2, nc->E[k].as<uint16_t>(), B, mi, mi, t0, mo, mo, nullptr, nullptr, false,
-                          nullptr));
-        HH_TRY(conv_layer(net, l + 1, CM_S1, t0, B, mo, mo, t1, mo, mo, nullptr, nullptr, true, nullptr));
-        HH_TRY(conv_layer(net, l + 2, CM_S1, t1, B, mo, mo, nc->E[k + 1].as<uint16_t>(), mo, mo, nullptr, nullptr,
-                          true, nullptr));
+        const int l = (k == 0) ? L_ENC2_D : L_ENC3_D;
+        HH_TRY(conv_layer(net, l, CM_S2, E(l - 1), B, mi, mi, E(l), mo, mo, nullptr, nullptr, false, nullptr));
+        HH_TRY(conv_layer(net, l + 1, CM_S1, E(l), B, mo, mo, E(l + 1), mo, mo, nullptr, nullptr, true, nullptr));
+        HH_TRY(conv_layer(net, l + 2, CM_S1, E(l + 1), B, mo, mo, E(l + 2), mo, mo, nullptr, nullptr, true, nullptr));
     }
     return HH_OK;
 }
@@ -648,7 +637,11 @@ hh_status net_prepare_model(hh_model* md) {
     nc->M = 2 * nc->nc;
     HH_TRY(nc->Gbr.ensure(net->ctx, (size_t)net->nk * nc->M * nc->M * sizeof(float2)));
     HH_TRY(green_forward(net, nc->nc, nc->Gbr.as<float2>(), 1e-5));
-    HH_TRY(run_encoder(net, md, nc));
+    if (net->ch[0] != 16) {
+        set_error("first-level channel count must be 16");
+        return HH_ERR_ARG;
+    }
+    HH_TRY(encoder_forward(net, md, nc->enc));
     nc->net = net;
     nc->version = net->version;
     return HH_OK;
@@ -656,14 +649,14 @@ hh_status net_prepare_model(hh_model* md) {
 
 // e = out_scale * P(Net(v * in_scale)) for the B vectors v (stride vstride);
 // writes x0 (complex single, [B][n][n]).  Encodings come from the model cache.
-hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const BatchMap& bm, const float2* v,
-                            size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active) {
+// Forward pass on B vectors v.  E1..E3: encodings ([.][m][m][c] BF16) indexed
+// through smap (null: identity); Gbr: transformed Green's functions.  Keeps
+// every activation in A; writes x0 = out_scale * P(o) when x0 is not null.
+hh_status net_forward_core(hh_net* net, int n, double h, NetActs& A, int B, const int* smap, const uint16_t* E1,
+                           const uint16_t* E2, const uint16_t* E3, const float2* Gbr, const float2* v, size_t vstride,
+                           const double* sig, int sig_stride, float2* x0, const int* active) {
     hipStream_t st = net->ctx->stream;
-    NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
-    const int n = md->lev[0].n;
-    const double h = md->lev[0].h;
     HH_TRY(A.ensure(net, B, n));
-    const int* smap = md->ninst > 1 ? bm.inst : A.zeros.as<int>();
     float* in_scale = A.scales.as<float>();
     float* out_scale = in_scale + B;
     // rms scaling (C9 reading of Sec. 4.3: the network works on a unit-rms residual)
@@ -682,7 +675,7 @@ hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const 
     {
         ProfScope ps(net->ctx, HH_K_CONV);
         hipLaunchKernelGGL((k_conv_in<0, 16>), dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, v, vstride, in_scale,
-                           nullptr, 0.f, P + net->L[L_S1_D].woff, P + net->L[L_S1_D].boff, nc->E[0].as<uint16_t>(),
+                           nullptr, 0.f, P + net->L[L_S1_D].woff, P + net->L[L_S1_D].boff, E1,
                            smap, act(L_S1_D), n, active);
         HH_LAUNCH_CHECK();
     }
@@ -692,11 +685,11 @@ hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const 
         HH_TRY(conv_layer(net, L_S1_C1, CM_S1, act(L_S1_D), B, m1, m1, act(L_S1_C1), m1, m1, nullptr, nullptr, true, active));
         HH_TRY(conv_layer(net, L_S1_C2, CM_S1, act(L_S1_C1), B, m1, m1, act(L_S1_C2), m1, m1, nullptr, nullptr, true, active));
         // level 2
-        HH_TRY(conv_layer(net, L_S2_D, CM_S2, act(L_S1_C2), B, m1, m1, act(L_S2_D), m2, m2, nc->E[1].as<uint16_t>(), smap, false, active));
+        HH_TRY(conv_layer(net, L_S2_D, CM_S2, act(L_S1_C2), B, m1, m1, act(L_S2_D), m2, m2, E2, smap, false, active));
         HH_TRY(conv_layer(net, L_S2_C1, CM_S1, act(L_S2_D), B, m2, m2, act(L_S2_C1), m2, m2, nullptr, nullptr, true, active));
         HH_TRY(conv_layer(net, L_S2_C2, CM_S1, act(L_S2_C1), B, m2, m2, act(L_S2_C2), m2, m2, nullptr, nullptr, true, active));
         // level 3
-        HH_TRY(conv_layer(net, L_S3_D, CM_S2, act(L_S2_C2), B, m2, m2, act(L_S3_D), m3, m3, nc->E[2].as<uint16_t>(), smap, false, active));
+        HH_TRY(conv_layer(net, L_S3_D, CM_S2, act(L_S2_C2), B, m2, m2, act(L_S3_D), m3, m3, E3, smap, false, active));
         HH_TRY(conv_layer(net, L_S3_C1, CM_S1, act(L_S3_D), B, m3, m3, act(L_S3_C1), m3, m3, nullptr, nullptr, true, active));
         HH_TRY(conv_layer(net, L_S3_C2, CM_S1, act(L_S3_C1), B, m3, m3, act(L_S3_C2), m3, m3, nullptr, nullptr, true, active));
         // level 4 (stride 1 below n = 512)
@@ -706,8 +699,7 @@ hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const 
     }
     {
         ProfScope ps(net->ctx, HH_K_NET_OTHER);
-        HH_TRY(launch_implicit(st, 2 * m4, act(L_S4_C2), A.imp.as<uint16_t>(), nc->Gbr.as<float2>(), m4, net->nk, B,
-                               false, active));
+        HH_TRY(launch_implicit(st, 2 * m4, act(L_S4_C2), A.imp.as<uint16_t>(), Gbr, m4, net->nk, B, false, active));
     }
     {
         ProfScope ps(net->ctx, HH_K_CONV);
@@ -728,10 +720,23 @@ hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const 
         hipLaunchKernelGGL((k_conv_out<16>), dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, act(L_U1_C2),
                            P + net->L[L_OUT].woff, P + net->L[L_OUT].boff, o, m1, active);
         HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_prolong_x0, dim3((n * n + 255) / 256, B), dim3(256), 0, st, o, out_scale, x0, n, active);
-        HH_LAUNCH_CHECK();
+        if (x0) {
+            hipLaunchKernelGGL(k_prolong_x0, dim3((n * n + 255) / 256, B), dim3(256), 0, st, o, out_scale, x0, n,
+                               active);
+            HH_LAUNCH_CHECK();
+        }
     }
     return HH_OK;
+}
+
+hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const BatchMap& bm, const float2* v,
+                            size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active) {
+    NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
+    HH_TRY(A.ensure(net, B, md->lev[0].n));
+    const int* smap = md->ninst > 1 ? bm.inst : A.zeros.as<int>();
+    return net_forward_core(net, md->lev[0].n, md->lev[0].h, A, B, smap, nc->enc[L_ENC1_C2].as<uint16_t>(),
+                            nc->enc[L_ENC2_C2].as<uint16_t>(), nc->enc[L_ENC3_C2].as<uint16_t>(),
+                            nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active);
 }
 
 // ---------------------------------------------------------------------------
@@ -752,6 +757,889 @@ hh_status net_precond(void* user, hh_model* md, SolveWork& W, const BatchMap& bm
     const size_t nn = (size_t)md->lev[0].n * md->lev[0].n;
     return launch_vcycle_strided(md, W.nrhs, bm, v, vstride, sig, sig_stride, x0, nn, z, zstride, W.vwork.ptr, act);
 }
+
+// ===========================================================================
+// Training (Sec. 4.3, Sec. 5.3): MSE loss (eq. 19) on method-generated pairs
+// (eq. 20), backward pass through every layer, Adam on the FP32 masters.
+// ===========================================================================
+
+// ---- weight gradients of the 16/32/64-channel layers -----------------------
+// part[blk][oo][ii][t] = sum over the block's output pixels p of
+//   A[b][p][oo] * X[b][src(p, t)][ii],   src = p + (ky-1, kx-1) (S1) or 2p + (ky-1, kx-1) (S2).
+// Convolutions: A = output gradient, X = layer input -> dW (cout, cin, 3, 3).
+// Transposed convolutions: A = layer input, X = output gradient -> dW (cin, cout, 3, 3).
+template <int CA, int CX, int MODE>
+struct WgCfg {
+    static constexpr int TC = 32;
+    static constexpr int TR = (MODE == CM_S2) ? (CX >= 64 ? 2 : 4) : 4;
+    static constexpr int PH = (MODE == CM_S2) ? 2 * TR + 1 : TR + 2;
+    static constexpr int PW = (MODE == CM_S2) ? 2 * TC + 1 : TC + 2;
+};
+
+template <int CA, int CX, int MODE>
+__global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ A, const uint16_t* __restrict__ X,
+                                               float* __restrict__ part, int Ho, int Wo, int Hi, int Wi, int tiles_x,
+                                               int tiles_y) {
+    using Cf = WgCfg<CA, CX, MODE>;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[Cf::TR * Cf::TC * CA];
+    __shared__ __attribute__((aligned(16))) uint16_t sX[Cf::PH * Cf::PW * CX];
+    const int blk = blockIdx.x;
+    const int b = blk / (tiles_x * tiles_y);
+    const int rem = blk - b * tiles_x * tiles_y;
+    const int ty = rem / tiles_x, tx = rem - ty * tiles_x;
+    const int y0 = ty * Cf::TR, x0 = tx * Cf::TC;
+    const int tid = threadIdx.x;
+    const uint16_t* Ab = A + (size_t)b * Ho * Wo * CA;
+    const uint16_t* Xb = X + (size_t)b * Hi * Wi * CX;
+    for (int e = tid; e < Cf::TR * Cf::TC * (CA / 8); e += 256) {
+        const int v = e % (CA / 8), pix = e / (CA / 8);
+        const int r = pix / Cf::TC, c = pix - r * Cf::TC;
+        const int oy = y0 + r, ox = x0 + c;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (oy < Ho && ox < Wo) val = *reinterpret_cast<const uint4*>(Ab + ((size_t)oy * Wo + ox) * CA + 8 * v);
+        *reinterpret_cast<uint4*>(&sA[pix * CA + 8 * v]) = val;
+    }
+    for (int e = tid; e < Cf::PH * Cf::PW * (CX / 8); e += 256) {
+        const int v = e % (CX / 8), pix = e / (CX / 8);
+        const int py = pix / Cf::PW, px = pix - py * Cf::PW;
+        const int iy = (MODE == CM_S2 ? 2 * y0 : y0) - 1 + py, ix = (MODE == CM_S2 ? 2 * x0 : x0) - 1 + px;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
+            val = *reinterpret_cast<const uint4*>(Xb + ((size_t)iy * Wi + ix) * CX + 8 * v);
+        *reinterpret_cast<uint4*>(&sX[pix * CX + 8 * v]) = val;
+    }
+    __syncthreads();
+    constexpr int NOB = CA / 4, NIB = CX / 4;
+    for (int it = tid; it < 9 * NOB * NIB; it += 256) {
+        const int t = it / (NOB * NIB);
+        const int r2 = it - t * NOB * NIB;
+        const int ob = r2 / NIB, ib = r2 - ob * NIB;
+        const int ky = t / 3, kx = t - 3 * ky;
+        float acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+        for (int p = 0; p < Cf::TR * Cf::TC; ++p) {
+            const int r = p / Cf::TC, c = p - r * Cf::TC;
+            const uint2 ar = *reinterpret_cast<const uint2*>(&sA[p * CA + 4 * ob]);
+            const int sy = (MODE == CM_S2 ? 2 * r : r) + ky, sx = (MODE == CM_S2 ? 2 * c : c) + kx;
+            const uint2 xr = *reinterpret_cast<const uint2*>(&sX[(sy * Cf::PW + sx) * CX + 4 * ib]);
+            const float a[4] = {bf2f((uint16_t)(ar.x & 0xffff)), bf2f((uint16_t)(ar.x >> 16)),
+                                bf2f((uint16_t)(ar.y & 0xffff)), bf2f((uint16_t)(ar.y >> 16))};
+            const float x[4] = {bf2f((uint16_t)(xr.x & 0xffff)), bf2f((uint16_t)(xr.x >> 16)),
+                                bf2f((uint16_t)(xr.y & 0xffff)), bf2f((uint16_t)(xr.y >> 16))};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * x[j];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) part[(((size_t)blk * CA + 4 * ob + i) * CX + 4 * ib + j) * 9 + t] = acc[i][j];
+    }
+}
+
+// out[e] = scale * sum_b part[b][e]   (deterministic two-stage reduction)
+__global__ void k_reduce_part(const float* __restrict__ part, int nblk, int count, float* __restrict__ out,
+                              float scale) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    float acc = 0.f;
+    for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * count + e];
+    out[e] = acc * scale;
+}
+
+template <int CA, int CX, int MODE>
+static hh_status launch_wgrad_t(hipStream_t st, const uint16_t* A, const uint16_t* X, int B, int Ho, int Wo, int Hi,
+                                int Wi, Buf& part, hh_ctx* ctx, float* out) {
+    using Cf = WgCfg<CA, CX, MODE>;
+    const int tx = (Wo + Cf::TC - 1) / Cf::TC, ty = (Ho + Cf::TR - 1) / Cf::TR;
+    const int nblk = B * tx * ty;
+    const int count = CA * CX * 9;
+    HH_TRY(part.ensure(ctx, (size_t)nblk * count * sizeof(float)));
+    hipLaunchKernelGGL((k_wgrad<CA, CX, MODE>), dim3(nblk), dim3(256), 0, st, A, X, part.as<float>(), Ho, Wo, Hi, Wi,
+                       tx, ty);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, part.as<float>(), nblk, count, out,
+                       1.f);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+static hh_status launch_wgrad(hipStream_t st, int ca, int cx, int mode, const uint16_t* A, const uint16_t* X, int B,
+                              int Ho, int Wo, int Hi, int Wi, Buf& part, hh_ctx* ctx, float* out) {
+#define HH_WG(CA_, CX_, MD)                      \
+    if (ca == CA_ && cx == CX_ && mode == MD) \
+        return launch_wgrad_t<CA_, CX_, MD>(st, A, X, B, Ho, Wo, Hi, Wi, part, ctx, out);
+    HH_WG(16, 16, CM_S1)
+    HH_WG(32, 32, CM_S1)
+    HH_WG(64, 64, CM_S1)
+    HH_WG(32, 16, CM_S2)
+    HH_WG(64, 32, CM_S2)
+    HH_WG(64, 64, CM_S2)
+#undef HH_WG
+    set_error("no weight-gradient kernel for %d x %d mode %d", ca, cx, mode);
+    return HH_ERR_ARG;
+}
+
+// channel sums of a BF16 NHWC tensor over all pixels: part[blk][c]
+template <int C>
+__global__ void __launch_bounds__(256) k_chsum(const uint16_t* __restrict__ A, size_t npix, float* __restrict__ part) {
+    __shared__ float s[256];
+    constexpr int PPB = 256 / C;  // pixels handled concurrently
+    const int c = threadIdx.x % C, lane_p = threadIdx.x / C;
+    float acc = 0.f;
+    for (size_t p = (size_t)blockIdx.x * PPB + lane_p; p < npix; p += (size_t)gridDim.x * PPB)
+        acc += bf2f(A[p * C + c]);
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.f;
+        for (int q = 0; q < PPB; ++q) t += s[q * C + threadIdx.x];
+        part[(size_t)blockIdx.x * C + threadIdx.x] = t;
+    }
+}
+
+static hh_status launch_bgrad(hipStream_t st, int C, const uint16_t* A, size_t npix, Buf& part, hh_ctx* ctx,
+                              float* out) {
+    const int nblk = 512;
+    HH_TRY(part.ensure(ctx, (size_t)nblk * C * sizeof(float)));
+    if (C == 16)
+        hipLaunchKernelGGL(k_chsum<16>, dim3(nblk), dim3(256), 0, st, A, npix, part.as<float>());
+    else if (C == 32)
+        hipLaunchKernelGGL(k_chsum<32>, dim3(nblk), dim3(256), 0, st, A, npix, part.as<float>());
+    else if (C == 64)
+        hipLaunchKernelGGL(k_chsum<64>, dim3(nblk), dim3(256), 0, st, A, npix, part.as<float>());
+    else {
+        set_error("channel sum for %d channels", C);
+        return HH_ERR_ARG;
+    }
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_reduce_part, dim3((C + 255) / 256), dim3(256), 0, st, part.as<float>(), nblk, C, out, 1.f);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+// ---- projection layer (CIN -> 2) backward --------------------------------
+// input gradient: g[q][c] = sum_{o,t} W[o][c][t] go[q - off(t)][o], masked by (x > 0)
+template <int CIN>
+__global__ void __launch_bounds__(256) k_out_dgrad(const float2* __restrict__ go, const float* __restrict__ W,
+                                                   const uint16_t* __restrict__ mask, uint16_t* __restrict__ g, int m) {
+    __shared__ float s_w[2 * CIN * 9];
+    for (int e = threadIdx.x; e < 2 * CIN * 9; e += 256) s_w[e] = W[e];
+    __syncthreads();
+    const int b = blockIdx.y;
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= m * m) return;
+    const int qy = q / m, qx = q - qy * m;
+    float acc[CIN];
+#pragma unroll
+    for (int c = 0; c < CIN; ++c) acc[c] = 0.f;
+    for (int t = 0; t < 9; ++t) {
+        const int py = qy - (t / 3 - 1), px = qx - (t % 3 - 1);
+        if (py < 0 || py >= m || px < 0 || px >= m) continue;
+        const float2 gv = go[(size_t)b * m * m + (size_t)py * m + px];
+#pragma unroll
+        for (int c = 0; c < CIN; ++c) acc[c] += s_w[(0 * CIN + c) * 9 + t] * gv.x + s_w[(1 * CIN + c) * 9 + t] * gv.y;
+    }
+    const size_t o = ((size_t)b * m * m + q) * CIN;
+#pragma unroll
+    for (int c0 = 0; c0 < CIN; c0 += 8) {
+        uint4 mr = *reinterpret_cast<const uint4*>(mask + o + c0);
+        const uint16_t* mh = reinterpret_cast<const uint16_t*>(&mr);
+        uint16_t out[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) out[u] = f2bf(bf2f(mh[u]) > 0.f ? acc[c0 + u] : 0.f);
+        *reinterpret_cast<uint4*>(g + o + c0) = *reinterpret_cast<uint4*>(out);
+    }
+}
+
+// weight gradient: part[blk][o][c][t] = sum_p go[p][o] x[p + off(t)][c];  bias: part[blk][2*CIN*9 + o]
+template <int CIN>
+__global__ void __launch_bounds__(256) k_out_wgrad(const float2* __restrict__ go, const uint16_t* __restrict__ x,
+                                                   float* __restrict__ part, int m, int chunk) {
+    const int blk = blockIdx.x;
+    const int b = blockIdx.y;
+    const int nb = gridDim.x;
+    const int count = 2 * CIN * 9 + 2;
+    for (int it = threadIdx.x; it < count; it += 256) {
+        float acc = 0.f;
+        const int p0 = blk * chunk, p1 = min(m * m, p0 + chunk);
+        if (it < 2 * CIN * 9) {
+            const int o = it / (CIN * 9), c = (it / 9) % CIN, t = it % 9;
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            for (int p = p0; p < p1; ++p) {
+                const int py = p / m, px = p - py * m;
+                const int sy = py + dy, sx = px + dx;
+                if (sy < 0 || sy >= m || sx < 0 || sx >= m) continue;
+                const float2 gv = go[(size_t)b * m * m + p];
+                acc += (o == 0 ? gv.x : gv.y) * bf2f(x[(((size_t)b * m + sy) * m + sx) * CIN + c]);
+            }
+        } else {
+            const int o = it - 2 * CIN * 9;
+            for (int p = p0; p < p1; ++p) {
+                const float2 gv = go[(size_t)b * m * m + p];
+                acc += (o == 0 ? gv.x : gv.y);
+            }
+        }
+        part[((size_t)b * nb + blk) * count + it] = acc;
+    }
+}
+
+// ---- first layer (2 -> COUT, stride 2) weight + bias gradient --------------
+template <int SRC, int COUT>
+__global__ void __launch_bounds__(256) k_in_wgrad(const uint16_t* __restrict__ g, const float2* __restrict__ src,
+                                                  size_t src_bstride, const float* __restrict__ in_scale, float h2,
+                                                  float* __restrict__ part, int n, int chunk) {
+    const int blk = blockIdx.x, b = blockIdx.y, nb = gridDim.x;
+    const int m = n / 2;
+    const int count = COUT * 18 + COUT;
+    const float sc = (SRC == 0) ? in_scale[b] : 1.f;
+    const float2* sb = src + (size_t)b * src_bstride;
+    const int p0 = blk * chunk, p1 = min(m * m, p0 + chunk);
+    for (int it = threadIdx.x; it < count; it += 256) {
+        float acc = 0.f;
+        if (it < COUT * 18) {
+            const int co = it / 18, ci = (it / 9) % 2, t = it % 9;
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            for (int p = p0; p < p1; ++p) {
+                const int oy = p / m, ox = p - oy * m;
+                const int iy = 2 * oy + dy, ix = 2 * ox + dx;
+                if (iy < 0 || iy >= n || ix < 0 || ix >= n) continue;
+                const float2 v = sb[(size_t)iy * n + ix];
+                float a;
+                if (SRC == 0) {
+                    a = (ci == 0 ? v.x : v.y) * sc;
+                } else {
+                    const float m0 = v.x * h2;
+                    a = ci == 0 ? m0 : m0 * v.y;
+                }
+                a = bf2f(f2bf(a));
+                acc += bf2f(g[((size_t)b * m * m + p) * COUT + co]) * a;
+            }
+        } else {
+            const int co = it - COUT * 18;
+            for (int p = p0; p < p1; ++p) acc += bf2f(g[((size_t)b * m * m + p) * COUT + co]);
+        }
+        part[((size_t)b * nb + blk) * count + it] = acc;
+    }
+}
+
+// ---- implicit layer: gradient of the transformed Green's functions --------
+// part[b][c][k1][k2] = conj(FFT(pad z))[k] * FFT(pad gy)[k] / M^2 (natural order)
+template <int M, int NT>
+__global__ void __launch_bounds__(NT) k_implicit_ggrad(const uint16_t* __restrict__ z, const uint16_t* __restrict__ gy,
+                                                       float2* __restrict__ part, int nc, int nk) {
+    extern __shared__ float2 s_dyn[];
+    constexpr int P = M + 1;
+    float2* s0 = s_dyn;
+    float2* s1 = s_dyn + M * P;
+    float2* tw = s_dyn + 2 * M * P;
+    const int c = blockIdx.x, b = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int CH = 2 * nk;
+    for (int t = tid; t < M / 2; t += NT) {
+        float sn, cs;
+        sincospif(-2.0f * (float)t / (float)M, &sn, &cs);
+        tw[t] = make_float2(cs, sn);
+    }
+    for (int e = tid; e < 2 * M * P; e += NT) s_dyn[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (int e = tid; e < nc * nc; e += NT) {
+        const int y = e / nc, x = e - y * nc;
+        const size_t o = (((size_t)b * nc + y) * nc + x) * CH + 2 * c;
+        const uint32_t r0 = *reinterpret_cast<const uint32_t*>(z + o);
+        const uint32_t r1 = *reinterpret_cast<const uint32_t*>(gy + o);
+        s0[y * P + x] = make_float2(bf2f((uint16_t)(r0 & 0xffff)), bf2f((uint16_t)(r0 >> 16)));
+        s1[y * P + x] = make_float2(bf2f((uint16_t)(r1 & 0xffff)), bf2f((uint16_t)(r1 >> 16)));
+    }
+    __syncthreads();
+    for (int len = M; len >= 2; len >>= 1) {
+        const int half = len >> 1, tws = M / len;
+        for (int t = tid; t < 2 * nc * (M / 2); t += NT) {
+            float2* s = (t < nc * (M / 2)) ? s0 : s1;
+            const int tt = t % (nc * (M / 2));
+            const int row = tt / (M / 2), bf = tt - row * (M / 2);
+            const int blk = bf / half, j = bf - blk * half;
+            const int i0 = row * P + blk * len + j, i1 = i0 + half;
+            const float2 a = s[i0], bb = s[i1];
+            s[i0] = cadd(a, bb);
+            s[i1] = cmul(csub(a, bb), tw[j * tws]);
+        }
+        __syncthreads();
+    }
+    for (int len = M; len >= 2; len >>= 1) {
+        const int half = len >> 1, tws = M / len;
+        for (int t = tid; t < 2 * M * (M / 2); t += NT) {
+            float2* s = (t < M * (M / 2)) ? s0 : s1;
+            const int tt = t % (M * (M / 2));
+            const int col = tt % M, bf = tt / M;
+            const int blk = bf / half, j = bf - blk * half;
+            const int i0 = (blk * len + j) * P + col, i1 = i0 + half * P;
+            const float2 a = s[i0], bb = s[i1];
+            s[i0] = cadd(a, bb);
+            s[i1] = cmul(csub(a, bb), tw[j * tws]);
+        }
+        __syncthreads();
+    }
+    int bits = 0;
+    while ((1 << bits) < M) ++bits;
+    const float sc = 1.f / ((float)M * M);
+    for (int e = tid; e < M * M; e += NT) {
+        const int r = e / M, col = e - r * M;
+        const float2 a = s0[r * P + col], g = s1[r * P + col];
+        // conj(a) * g
+        const float2 pr = make_float2((a.x * g.x + a.y * g.y) * sc, (a.x * g.y - a.y * g.x) * sc);
+        const int k1 = (int)(__brev((unsigned)r) >> (32 - bits)), k2 = (int)(__brev((unsigned)col) >> (32 - bits));
+        part[(((size_t)b * nk + c) * M + k1) * M + k2] = pr;
+    }
+}
+
+// gG[c][e] = sum_b part[b][c][e]  (FP64)
+__global__ void k_reduce_ggrad(const float2* __restrict__ part, int B, int count, double2* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const float2 v = part[(size_t)b * count + e];
+        re += v.x;
+        im += v.y;
+    }
+    out[e] = make_double2(re, im);
+}
+
+// ---- Green's function backward -------------------------------------------
+// gS -> gKhat: gf = conj(F(delta)) gS, then the real Jacobian of
+// f(z) = conj(z)/(|z|^2 + eps) at z = Khat.
+__global__ void k_green_gkhat(const double2* __restrict__ gS, const float* __restrict__ K, double2* __restrict__ gKh,
+                              int N, double eps) {
+    const int c = blockIdx.y;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= N * N) return;
+    const int p = idx / N, q = idx - p * N;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int bb = 0; bb < 3; ++bb) {
+            const double kr = K[((size_t)c * 9 + a * 3 + bb) * 2], ki = K[((size_t)c * 9 + a * 3 + bb) * 2 + 1];
+            long t = ((long)p * (a - 1) + (long)q * (bb - 1)) % N;
+            if (t < 0) t += N;
+            double sn, cs;
+            sincospi(-2.0 * (double)t / (double)N, &sn, &cs);
+            re += kr * cs - ki * sn;
+            im += kr * sn + ki * cs;
+        }
+    const double sign = ((p + q) & 1) ? -1.0 : 1.0;
+    const double2 g = gS[(size_t)c * N * N + idx];
+    const double gfr = sign * g.x, gfi = sign * g.y;
+    const double d = re * re + im * im + eps;
+    const double dfr_da = 1.0 / d - 2 * re * re / (d * d), dfr_db = -2 * re * im / (d * d);
+    const double dfi_da = 2 * re * im / (d * d), dfi_db = -1.0 / d + 2 * im * im / (d * d);
+    gKh[(size_t)c * N * N + idx] = make_double2(gfr * dfr_da + gfi * dfi_da, gfr * dfr_db + gfi * dfi_db);
+}
+
+// gK[c][a][b] = sum_{p,q} gKhat[p][q] exp(+2 pi i (p (a-1) + q (b-1)) / N), written as (re, im) floats
+__global__ void __launch_bounds__(256) k_green_gK(const double2* __restrict__ gKh, float* __restrict__ gK, int N) {
+    __shared__ double s_re[256], s_im[256];
+    const int c = blockIdx.y, tap = blockIdx.x;
+    const int a = tap / 3, bb = tap % 3;
+    double re = 0.0, im = 0.0;
+    for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+        const int p = idx / N, q = idx - p * N;
+        long t = ((long)p * (a - 1) + (long)q * (bb - 1)) % N;
+        if (t < 0) t += N;
+        double sn, cs;
+        sincospi(2.0 * (double)t / (double)N, &sn, &cs);
+        const double2 g = gKh[(size_t)c * N * N + idx];
+        re += g.x * cs - g.y * sn;
+        im += g.x * sn + g.y * cs;
+    }
+    s_re[threadIdx.x] = re;
+    s_im[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_re[threadIdx.x] += s_re[threadIdx.x + w];
+            s_im[threadIdx.x] += s_im[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        gK[((size_t)c * 9 + tap) * 2] = (float)s_re[0];
+        gK[((size_t)c * 9 + tap) * 2 + 1] = (float)s_im[0];
+    }
+}
+
+// dL/dK from dL/dGhat (natural order, FP64), eq. 17 backward
+static hh_status green_backward(hh_net* net, int nc, const double2* gGh, float* gK, double eps) {
+    hipStream_t st = net->ctx->stream;
+    const int M = 2 * nc, N = nextpow2(3 * M), nk = net->nk;
+    Buf A, Bt, S, Kh;
+    HH_TRY(A.ensure(net->ctx, (size_t)nk * M * M * sizeof(double2)));
+    HH_TRY(Bt.ensure(net->ctx, (size_t)nk * M * N * sizeof(double2)));
+    HH_TRY(S.ensure(net->ctx, (size_t)nk * N * N * sizeof(double2)));
+    HH_TRY(Kh.ensure(net->ctx, (size_t)nk * N * N * sizeof(double2)));
+    // gG[g1][g2] = sum_k gGhat[k1][k2] exp(+2 pi i (k1 (g1 - nc) + k2 (g2 - nc)) / M)
+    HH_TRY(dft_pass(st, gGh, A.as<double2>(), nk, M, M, M, M, 0, -nc, +1, 1.0, 1));
+    HH_TRY(dft_pass(st, A.as<double2>(), S.as<double2>(), nk, M, M, M, M, 0, -nc, +1, 1.0, 0));
+    // gS[p][q] = (1/N^2) sum_g gG[g1][g2] exp(-2 pi i (p y(g1) + q x(g2)) / N), y = N/2 - nc + g
+    HH_TRY(dft_pass(st, S.as<double2>(), Bt.as<double2>(), nk, M, M, N, N, N / 2 - nc, 0, -1, 1.0, 1));
+    HH_TRY(dft_pass(st, Bt.as<double2>(), S.as<double2>(), nk, N, M, N, N, N / 2 - nc, 0, -1, 1.0 / ((double)N * N), 0));
+    const float* K = net->params.as<float>() + net->koff;
+    hipLaunchKernelGGL(k_green_gkhat, dim3((N * N + 255) / 256, nk), dim3(256), 0, st, S.as<double2>(), K,
+                       Kh.as<double2>(), N, eps);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_green_gK, dim3(9, nk), dim3(256), 0, st, Kh.as<double2>(), gK, N);
+    HH_LAUNCH_CHECK();
+    HH_HIP(hipStreamSynchronize(st));  // scratch released on return
+    return HH_OK;
+}
+
+// ---- loss (eq. 19) and its gradient at the projection layer --------------
+// d = P(o) - e / s per fine point (s = h^2 rms(r)); loss partials sum |d|^2;
+// gfull = (2 / B) d
+__global__ void __launch_bounds__(256) k_loss(const float2* __restrict__ o, const float2* __restrict__ e,
+                                              const float* __restrict__ s, float2* __restrict__ gfull,
+                                              double* __restrict__ parts, int n, float inv_b) {
+    __shared__ double s_red[4];
+    const int b = blockIdx.y;
+    const int m = n / 2;
+    const float sc = s[b] > 0.f ? 1.f / s[b] : 0.f;
+    double acc = 0.0;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < n * n; p += gridDim.x * 256) {
+        const int i = p / n, j = p - i * n;
+        const float2* ob = o + (size_t)b * m * m;
+        auto at = [&](int I, int J) -> float2 {
+            return (I < m && J < m) ? ob[(size_t)I * m + J] : make_float2(0.f, 0.f);
+        };
+        const int I = i >> 1, J = j >> 1;
+        float2 v;
+        if (!(i & 1) && !(j & 1)) v = at(I, J);
+        else if (!(i & 1)) v = cscale(cadd(at(I, J), at(I, J + 1)), 0.5f);
+        else if (!(j & 1)) v = cscale(cadd(at(I, J), at(I + 1, J)), 0.5f);
+        else v = cscale(cadd(cadd(at(I, J), at(I, J + 1)), cadd(at(I + 1, J), at(I + 1, J + 1))), 0.25f);
+        const float2 t = cscale(e[(size_t)b * n * n + p], sc);
+        const float2 d = csub(v, t);
+        acc += (double)d.x * d.x + (double)d.y * d.y;
+        gfull[(size_t)b * n * n + p] = cscale(d, 2.f * inv_b);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) parts[(size_t)b * gridDim.x + blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+// go = P^T gfull = 4 R gfull  (full weighting, zero ghosts)
+__global__ void __launch_bounds__(256) k_restrict4(const float2* __restrict__ gfull, float2* __restrict__ go, int n) {
+    const int b = blockIdx.y;
+    const int m = n / 2;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= m * m) return;
+    const int I = p / m, J = p - I * m;
+    const float w1[3] = {0.25f, 0.5f, 0.25f};
+    float2 acc = make_float2(0.f, 0.f);
+    for (int a = 0; a < 3; ++a) {
+        const int y = 2 * I + a - 1;
+        if (y < 0 || y >= n) continue;
+        for (int c = 0; c < 3; ++c) {
+            const int x = 2 * J + c - 1;
+            if (x < 0 || x >= n) continue;
+            acc = cadd(acc, cscale(gfull[(size_t)b * n * n + (size_t)y * n + x], 4.f * w1[a] * w1[c]));
+        }
+    }
+    go[(size_t)b * m * m + p] = acc;
+}
+
+// ---- elementwise: g = (g_in + add) masked by (mask > 0), BF16 -------------
+__global__ void k_mask_add(const uint16_t* __restrict__ gin, const uint16_t* __restrict__ add,
+                           const uint16_t* __restrict__ mask, uint16_t* __restrict__ g, size_t count) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    float v = bf2f(gin[e]) + (add ? bf2f(add[e]) : 0.f);
+    if (!(bf2f(mask[e]) > 0.f)) v = 0.f;
+    g[e] = f2bf(v);
+}
+
+// ---- Adam (Kingma & Ba), FP32 masters ------------------------------------
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t N, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// training step
+// ---------------------------------------------------------------------------
+struct TrainWork {
+    NetActs acts;         // solver activations
+    Buf enc[9];           // encoder activations
+    Buf G[NET_LAYERS];    // gradients w.r.t. each layer's output (pre-activation for ReLU layers)
+    Buf gimp;             // gradient w.r.t. the implicit layer's output
+    Buf gfull, go;        // loss gradient at full / half resolution
+    Buf lparts;           // loss partials
+    Buf part, part2;      // reduction scratch
+    Buf gGh_part, gGh;    // implicit-layer kernel gradients
+    Buf Gbr;              // transformed Green's functions of this step
+};
+
+static hh_status ensure_grads(hh_net* net, TrainWork& T, int B, int n) {
+    const int ncs = coarsest_of(n);
+    for (int l = 0; l < NET_LAYERS; ++l) {
+        int m;
+        if (l < L_S1_D) m = n >> (l / 3 + 1);
+        else if (l <= L_S1_C2 || (l >= L_U1_T && l <= L_U1_C2) || l == L_OUT) m = n / 2;
+        else if (l <= L_S2_C2 || (l >= L_U2_T && l <= L_U2_C2)) m = n / 4;
+        else if (l <= L_S3_C2 || (l >= L_U3_T && l <= L_U3_C2)) m = n / 8;
+        else m = ncs;
+        if (l == L_OUT) continue;
+        HH_TRY(T.G[l].ensure(net->ctx, (size_t)B * m * m * net->L[l].cout * sizeof(uint16_t)));
+    }
+    HH_TRY(T.gimp.ensure(net->ctx, (size_t)B * ncs * ncs * net->ch[3] * sizeof(uint16_t)));
+    HH_TRY(T.gfull.ensure(net->ctx, (size_t)B * n * n * sizeof(float2)));
+    HH_TRY(T.go.ensure(net->ctx, (size_t)B * (n / 2) * (n / 2) * sizeof(float2)));
+    HH_TRY(T.lparts.ensure(net->ctx, (size_t)B * 64 * sizeof(double)));
+    return HH_OK;
+}
+
+// dgrad of layer l: g_in = conv_l^T (gout), + add, masked by `mask`
+static hh_status dgrad_layer(hh_net* net, int l, int mode, const uint16_t* gout, int B, int Hout, int Wout,
+                             uint16_t* gin, int Hin, int Win, const uint16_t* add, const uint16_t* mask) {
+    const LayerInfo& L = net->L[l];
+    ConvArgs a{};
+    a.x = gout;
+    a.y = gin;
+    a.wp = net->packed.as<uint16_t>() + net->pk_bwd[l];
+    a.bias = nullptr;
+    a.skip = add;
+    a.mask = mask;
+    a.relu = 0;
+    a.B = B;
+    a.Hin = Hout;
+    a.Win = Wout;
+    a.Hout = Hin;
+    a.Wout = Win;
+    return launch_conv(net->ctx->stream, net->ctx->num_cus, L.cout, L.cin, mode, a);
+}
+
+}  // namespace hh
+
+using namespace hh;
+
+extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev,
+                                   const void* e_dev, double lr, double* loss_out) {
+    HH_ARG(ctx && net && md && r_dev && e_dev, "null pointer");
+    HH_ARG(net->ctx == ctx && md->ctx == ctx, "objects of another context");
+    HH_ARG(B >= 1 && (md->ninst == B || md->ninst == 1), "model must hold one slowness model per sample (or one)");
+    const int n = md->lev[0].n;
+    HH_ARG(n % 16 == 0 && n < 512, "training sizes: n divisible by 16 and below 512");
+    HH_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (!net->train_work) {
+        net->train_work = new (std::nothrow) TrainWork();
+        if (!net->train_work) {
+            set_error("out of host memory");
+            return HH_ERR_NOMEM;
+        }
+    }
+    TrainWork& T = *reinterpret_cast<TrainWork*>(net->train_work);
+    HH_TRY(net_pack(net));
+    const double h = md->lev[0].h;
+    const int nc = coarsest_of(n), M = 2 * nc;
+    HH_TRY(T.Gbr.ensure(ctx, (size_t)net->nk * M * M * sizeof(float2)));
+    HH_TRY(green_forward(net, nc, T.Gbr.as<float2>(), 1e-5));
+    HH_TRY(encoder_forward(net, md, T.enc));
+    NetActs& A = T.acts;
+    HH_TRY(A.ensure(net, B, n));
+    const int* smap = md->ninst == 1 ? A.zeros.as<int>() : nullptr;  // sample b uses slowness model b
+    HH_TRY(net_forward_core(net, n, h, A, B, smap, T.enc[L_ENC1_C2].as<uint16_t>(), T.enc[L_ENC2_C2].as<uint16_t>(),
+                            T.enc[L_ENC3_C2].as<uint16_t>(), T.Gbr.as<float2>(), (const float2*)r_dev, (size_t)n * n,
+                            nullptr, 0, nullptr, nullptr));
+    HH_TRY(ensure_grads(net, T, B, n));
+    float* out_scale = A.scales.as<float>() + B;
+    // ---- loss and gradient at the projection layer
+    const int m1 = n / 2, m2 = n / 4, m3 = n / 8, m4 = nc;
+    hipLaunchKernelGGL(k_loss, dim3(64, B), dim3(256), 0, st, A.a[L_OUT].as<float2>(), (const float2*)e_dev, out_scale,
+                       T.gfull.as<float2>(), T.lparts.as<double>(), n, 1.f / B);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_restrict4, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.gfull.as<float2>(),
+                       T.go.as<float2>(), n);
+    HH_LAUNCH_CHECK();
+    HH_TRY(net->grads.ensure(ctx, net->nparams * sizeof(float)));
+    float* GR = net->grads.as<float>();
+    const float* P = net->params.as<float>();
+    auto act = [&](int l) { return A.a[l].as<uint16_t>(); };
+    auto G = [&](int l) { return T.G[l].as<uint16_t>(); };
+    auto enc = [&](int l) { return T.enc[l].as<uint16_t>(); };
+    // ---- projection layer
+    {
+        const int chunk = 1024;
+        const int nb = (m1 * m1 + chunk - 1) / chunk;
+        const int count = 2 * 16 * 9 + 2;
+        HH_TRY(T.part.ensure(ctx, (size_t)B * nb * count * sizeof(float)));
+        hipLaunchKernelGGL(k_out_wgrad<16>, dim3(nb, B), dim3(256), 0, st, T.go.as<float2>(), act(L_U1_C2),
+                           T.part.as<float>(), m1, chunk);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
+                           count, GR + net->L[L_OUT].woff, 1.f);  // weights and the 2 biases are contiguous
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_out_dgrad<16>, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.go.as<float2>(),
+                           P + net->L[L_OUT].woff, act(L_U1_C2), G(L_U1_C2), m1);
+        HH_LAUNCH_CHECK();
+    }
+    // generic helpers for a 16/32/64-channel layer l whose pre-activation gradient is G(l)
+    auto wgrad_conv = [&](int l, int mode, const uint16_t* x, int Hin, int Win, int Hout, int Wout) -> hh_status {
+        const LayerInfo& L = net->L[l];
+        HH_TRY(launch_wgrad(st, L.cout, L.cin, mode, G(l), x, B, Hout, Wout, Hin, Win, T.part, ctx, GR + L.woff));
+        return launch_bgrad(st, L.cout, G(l), (size_t)B * Hout * Wout, T.part2, ctx, GR + L.boff);
+    };
+    // transposed convolution l (input x at Hin, output gradient G(l) at Hout): dW (cin, cout)
+    auto wgrad_convT = [&](int l, int mode, const uint16_t* x, int Hin, int Hout) -> hh_status {
+        const LayerInfo& L = net->L[l];
+        HH_TRY(launch_wgrad(st, L.cin, L.cout, mode, x, G(l), B, Hin, Hin, Hout, Hout, T.part, ctx, GR + L.woff));
+        return launch_bgrad(st, L.cout, G(l), (size_t)B * Hout * Hout, T.part2, ctx, GR + L.boff);
+    };
+    const int s4 = coarse_stride_of(n);
+    // ---- up path, level 1
+    HH_TRY(wgrad_conv(L_U1_C2, CM_S1, act(L_U1_C1), m1, m1, m1, m1));
+    HH_TRY(dgrad_layer(net, L_U1_C2, CM_S1, G(L_U1_C2), B, m1, m1, G(L_U1_C1), m1, m1, nullptr, act(L_U1_C1)));
+    HH_TRY(wgrad_conv(L_U1_C1, CM_S1, act(L_U1_T), m1, m1, m1, m1));
+    HH_TRY(dgrad_layer(net, L_U1_C1, CM_S1, G(L_U1_C1), B, m1, m1, G(L_U1_T), m1, m1, nullptr, nullptr));
+    HH_TRY(wgrad_convT(L_U1_T, CM_S2, act(L_U2_C2), m2, m1));
+    HH_TRY(dgrad_layer(net, L_U1_T, CM_S2, G(L_U1_T), B, m1, m1, G(L_U2_C2), m2, m2, nullptr, act(L_U2_C2)));
+    // ---- up path, level 2
+    HH_TRY(wgrad_conv(L_U2_C2, CM_S1, act(L_U2_C1), m2, m2, m2, m2));
+    HH_TRY(dgrad_layer(net, L_U2_C2, CM_S1, G(L_U2_C2), B, m2, m2, G(L_U2_C1), m2, m2, nullptr, act(L_U2_C1)));
+    HH_TRY(wgrad_conv(L_U2_C1, CM_S1, act(L_U2_T), m2, m2, m2, m2));
+    HH_TRY(dgrad_layer(net, L_U2_C1, CM_S1, G(L_U2_C1), B, m2, m2, G(L_U2_T), m2, m2, nullptr, nullptr));
+    HH_TRY(wgrad_convT(L_U2_T, CM_S2, act(L_U3_C2), m3, m2));
+    HH_TRY(dgrad_layer(net, L_U2_T, CM_S2, G(L_U2_T), B, m2, m2, G(L_U3_C2), m3, m3, nullptr, act(L_U3_C2)));
+    // ---- up path, level 3
+    HH_TRY(wgrad_conv(L_U3_C2, CM_S1, act(L_U3_C1), m3, m3, m3, m3));
+    HH_TRY(dgrad_layer(net, L_U3_C2, CM_S1, G(L_U3_C2), B, m3, m3, G(L_U3_C1), m3, m3, nullptr, act(L_U3_C1)));
+    HH_TRY(wgrad_conv(L_U3_C1, CM_S1, act(L_U3_T), m3, m3, m3, m3));
+    HH_TRY(dgrad_layer(net, L_U3_C1, CM_S1, G(L_U3_C1), B, m3, m3, G(L_U3_T), m3, m3, nullptr, nullptr));
+    HH_TRY(wgrad_convT(L_U3_T, s4 == 2 ? CM_S2 : CM_S1, A.imp.as<uint16_t>(), m4, m3));
+    HH_TRY(dgrad_layer(net, L_U3_T, s4 == 2 ? CM_S2 : CM_S1, G(L_U3_T), B, m3, m3, T.gimp.as<uint16_t>(), m4, m4,
+                       nullptr, nullptr));
+    // ---- implicit layer: input gradient (adjoint, masked) and kernel gradient
+    HH_TRY(launch_implicit(st, M, T.gimp.as<uint16_t>(), G(L_S4_C2), T.Gbr.as<float2>(), m4, net->nk, B, true,
+                           nullptr, act(L_S4_C2)));
+    {
+        HH_TRY(T.gGh_part.ensure(ctx, (size_t)B * net->nk * M * M * sizeof(float2)));
+        HH_TRY(T.gGh.ensure(ctx, (size_t)net->nk * M * M * sizeof(double2)));
+        const size_t lds = ((size_t)2 * M * (M + 1) + M / 2) * sizeof(float2);
+        dim3 grd(net->nk, B);
+        if (M == 32) {
+            hipLaunchKernelGGL((k_implicit_ggrad<32, 256>), grd, dim3(256), lds, st, act(L_S4_C2), T.gimp.as<uint16_t>(),
+                               T.gGh_part.as<float2>(), m4, net->nk);
+        } else if (M == 64) {
+            static bool attr = false;
+            if (!attr) {
+                HH_HIP(hipFuncSetAttribute((const void*)k_implicit_ggrad<64, 512>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                attr = true;
+            }
+            hipLaunchKernelGGL((k_implicit_ggrad<64, 512>), grd, dim3(512), lds, st, act(L_S4_C2),
+                               T.gimp.as<uint16_t>(), T.gGh_part.as<float2>(), m4, net->nk);
+        } else if (M == 16) {
+            hipLaunchKernelGGL((k_implicit_ggrad<16, 256>), grd, dim3(256), lds, st, act(L_S4_C2), T.gimp.as<uint16_t>(),
+                               T.gGh_part.as<float2>(), m4, net->nk);
+        } else {
+            set_error("implicit-layer gradient: transform size %d not supported", M);
+            return HH_ERR_ARG;
+        }
+        HH_LAUNCH_CHECK();
+        const int count = net->nk * M * M;
+        hipLaunchKernelGGL(k_reduce_ggrad, dim3((count + 255) / 256), dim3(256), 0, st, T.gGh_part.as<float2>(), B,
+                           count, T.gGh.as<double2>());
+        HH_LAUNCH_CHECK();
+        HH_TRY(green_backward(net, nc, T.gGh.as<double2>(), GR + net->koff, 1e-5));
+    }
+    // ---- down path, level 4
+    HH_TRY(wgrad_conv(L_S4_C2, CM_S1, act(L_S4_C1), m4, m4, m4, m4));
+    HH_TRY(dgrad_layer(net, L_S4_C2, CM_S1, G(L_S4_C2), B, m4, m4, G(L_S4_C1), m4, m4, nullptr, act(L_S4_C1)));
+    HH_TRY(wgrad_conv(L_S4_C1, CM_S1, act(L_S4_D), m4, m4, m4, m4));
+    HH_TRY(dgrad_layer(net, L_S4_C1, CM_S1, G(L_S4_C1), B, m4, m4, G(L_S4_D), m4, m4, nullptr, nullptr));
+    HH_TRY(wgrad_conv(L_S4_D, s4 == 2 ? CM_S2 : CM_S1, act(L_S3_C2), m3, m3, m4, m4));
+    HH_TRY(dgrad_layer(net, L_S4_D, s4 == 2 ? CM_T2 : CM_S1, G(L_S4_D), B, m4, m4, G(L_S3_C2), m3, m3, G(L_U3_T),
+                       act(L_S3_C2)));
+    // ---- down path, levels 3 .. 1 (G(L_Sk_D) is also the gradient of the encodings Ek)
+    const int lvl_d[3] = {L_S3_D, L_S2_D, L_S1_D};
+    const int lvl_m[3] = {m3, m2, m1};
+    const int up_t[3] = {L_U2_T, L_U1_T, -1};
+    for (int k = 0; k < 3; ++k) {
+        const int ld = lvl_d[k], mm = lvl_m[k];
+        HH_TRY(wgrad_conv(ld + 2, CM_S1, act(ld + 1), mm, mm, mm, mm));
+        HH_TRY(dgrad_layer(net, ld + 2, CM_S1, G(ld + 2), B, mm, mm, G(ld + 1), mm, mm, nullptr, act(ld + 1)));
+        HH_TRY(wgrad_conv(ld + 1, CM_S1, act(ld), mm, mm, mm, mm));
+        HH_TRY(dgrad_layer(net, ld + 1, CM_S1, G(ld + 1), B, mm, mm, G(ld), mm, mm, nullptr, nullptr));
+        if (k < 2) {
+            HH_TRY(wgrad_conv(ld, CM_S2, act(ld - 1), 2 * mm, 2 * mm, mm, mm));
+            HH_TRY(dgrad_layer(net, ld, CM_T2, G(ld), B, mm, mm, G(ld - 1), 2 * mm, 2 * mm, G(up_t[k]),
+                               act(ld - 1)));
+        }
+    }
+    {   // first solver layer (2 -> 16, stride 2) from the scaled residual
+        const int chunk = 1024;
+        const int nb = (m1 * m1 + chunk - 1) / chunk;
+        const int count = 16 * 18 + 16;
+        HH_TRY(T.part.ensure(ctx, (size_t)B * nb * count * sizeof(float)));
+        hipLaunchKernelGGL((k_in_wgrad<0, 16>), dim3(nb, B), dim3(256), 0, st, G(L_S1_D), (const float2*)r_dev,
+                           (size_t)n * n, A.scales.as<float>(), 0.f, T.part.as<float>(), n, chunk);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
+                           count, GR + net->L[L_S1_D].woff, 1.f);
+        HH_LAUNCH_CHECK();
+    }
+    // ---- encoder (the encodings' gradients are G(L_S1_D), G(L_S2_D), G(L_S3_D))
+    {
+        const int EB = md->ninst;
+        if (EB != B) {
+            set_error("training with one slowness model shared by the batch is not supported");
+            return HH_ERR_ARG;
+        }
+        const int lvl_c2[3] = {L_ENC3_C2, L_ENC2_C2, L_ENC1_C2};
+        const int lvl_gs[3] = {L_S3_D, L_S2_D, L_S1_D};
+        const uint16_t* add = nullptr;  // gradient reaching E_k from the next encoder level
+        for (int k = 0; k < 3; ++k) {
+            const int l2 = lvl_c2[k], mm = lvl_m[k];
+            const size_t cnt = (size_t)B * mm * mm * net->L[l2].cout;
+            if (k == 0) {
+                hipLaunchKernelGGL(k_mask_add, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, G(lvl_gs[k]),
+                                   nullptr, enc(l2), G(l2), cnt);
+                HH_LAUNCH_CHECK();
+            }
+            (void)add;
+            HH_TRY(wgrad_conv(l2, CM_S1, enc(l2 - 1), mm, mm, mm, mm));
+            HH_TRY(dgrad_layer(net, l2, CM_S1, G(l2), B, mm, mm, G(l2 - 1), mm, mm, nullptr, enc(l2 - 1)));
+            HH_TRY(wgrad_conv(l2 - 1, CM_S1, enc(l2 - 2), mm, mm, mm, mm));
+            HH_TRY(dgrad_layer(net, l2 - 1, CM_S1, G(l2 - 1), B, mm, mm, G(l2 - 2), mm, mm, nullptr, nullptr));
+            if (k < 2) {
+                // strided conv of this level: input E_{k-1} (at 2 mm); its gradient adds the solver's
+                HH_TRY(wgrad_conv(l2 - 2, CM_S2, enc(l2 - 3), 2 * mm, 2 * mm, mm, mm));
+                HH_TRY(dgrad_layer(net, l2 - 2, CM_T2, G(l2 - 2), B, mm, mm, G(l2 - 3), 2 * mm, 2 * mm,
+                                   G(lvl_gs[k + 1]), enc(l2 - 3)));
+            }
+        }
+        const int chunk = 1024;
+        const int nb = (m1 * m1 + chunk - 1) / chunk;
+        const int count = 16 * 18 + 16;
+        HH_TRY(T.part.ensure(ctx, (size_t)B * nb * count * sizeof(float)));
+        hipLaunchKernelGGL((k_in_wgrad<1, 16>), dim3(nb, B), dim3(256), 0, st, G(L_ENC1_D),
+                           md->lev[0].coef.as<float2>(), (size_t)n * n, nullptr, (float)(h * h), T.part.as<float>(), n,
+                           chunk);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
+                           count, GR + net->L[L_ENC1_D].woff, 1.f);
+        HH_LAUNCH_CHECK();
+    }
+    // ---- Adam
+    if (lr > 0.0) {
+        if (!net->adam_m.ptr) {
+            HH_TRY(net->adam_m.ensure(ctx, net->nparams * sizeof(float)));
+            HH_TRY(net->adam_v.ensure(ctx, net->nparams * sizeof(float)));
+            HH_HIP(hipMemsetAsync(net->adam_m.ptr, 0, net->nparams * sizeof(float), st));
+            HH_HIP(hipMemsetAsync(net->adam_v.ptr, 0, net->nparams * sizeof(float), st));
+        }
+        net->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float bc1 = (float)(1.0 - pow(0.9, (double)net->step)), bc2 = (float)(1.0 - pow(0.999, (double)net->step));
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->nparams + 255) / 256)), dim3(256), 0, st,
+                           net->params.as<float>(), GR, net->adam_m.as<float>(), net->adam_v.as<float>(),
+                           net->nparams, (float)lr, b1, b2, 1e-8f, bc1, bc2);
+        HH_LAUNCH_CHECK();
+        net->packed_valid = false;
+        net->version++;
+    }
+    // ---- loss value
+    std::vector<double> lp((size_t)B * 64);
+    HH_HIP(hipMemcpyAsync(lp.data(), T.lparts.ptr, lp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HH_HIP(hipStreamSynchronize(st));
+    double L = 0.0;
+    for (double v : lp) L += v;
+    if (loss_out) *loss_out = L / B;
+    return HH_OK;
+}
+
+// e = x - xt (xt complex double), single precision
+__global__ void k_err_pair(const float2* __restrict__ x, const double2* __restrict__ xt, float2* __restrict__ e,
+                           size_t count) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const float2 a = x[i];
+    const double2 b = xt[i];
+    e[i] = make_float2((float)((double)a.x - b.x), (float)((double)a.y - b.y));
+}
+
+extern "C" hh_status hh_gen_training_pairs(hh_ctx* ctx, hh_model* m, int nb, const void* x_dev, const int* kiters_host,
+                                           void* e_dev, void* r_dev) {
+    HH_ARG(ctx && m && x_dev && kiters_host && e_dev && r_dev, "null pointer");
+    HH_ARG(m->ctx == ctx, "model of another context");
+    HH_ARG(nb >= 1 && (m->ninst == nb || m->ninst == 1), "one slowness model per sample (or one)");
+    int kmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        HH_ARG(kiters_host[b] >= 1 && kiters_host[b] <= HH_MAX_RESTART, "iterations per sample in 1..HH_MAX_RESTART");
+        kmax = std::max(kmax, kiters_host[b]);
+    }
+    HH_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int n = m->lev[0].n;
+    const size_t nn = (size_t)n * n;
+    Buf ib, bb, xt, caps;
+    BatchMap bm;
+    std::vector<int> ident(nb);
+    for (int b = 0; b < nb; ++b) ident[b] = m->ninst == 1 ? 0 : b;
+    HH_TRY(upload_inst_map(m, ib, nb, ident.data(), &bm));
+    HH_TRY(bb.ensure(ctx, (size_t)nb * nn * sizeof(float2)));
+    HH_TRY(xt.ensure(ctx, (size_t)nb * nn * sizeof(double2)));
+    HH_TRY(caps.ensure(ctx, (size_t)nb * sizeof(int)));
+    HH_HIP(hipMemcpyAsync(caps.ptr, kiters_host, (size_t)nb * sizeof(int), hipMemcpyHostToDevice, st));
+    // b = A x (training operator of the model), x~ = k FGMRES-MG iterations from 0 (eq. 20)
+    HH_TRY(launch_apply_op(m, 0, 0.f, nb, bm.inst, (const float2*)x_dev, bb.as<float2>(), nullptr));
+    if (!ctx->work) {
+        ctx->work = new (std::nothrow) SolveWork();
+        if (!ctx->work) {
+            set_error("out of host memory");
+            return HH_ERR_NOMEM;
+        }
+    }
+    SolveWork& W = *ctx->work;
+    hh_solve_opts o;
+    hh_solve_opts_default(&o);
+    o.fixed_iters = kmax;
+    o.restart = std::max(kmax, 1);
+    HH_TRY(W.prepare(ctx, m, nb, o.restart, kmax + 1, false));
+    W.caps_dev = caps.as<int>();
+    hh_status s = fgmres_solve(m, W, bm, bb.as<float2>(), xt.as<double2>(), o, nullptr, nullptr);
+    W.caps_dev = nullptr;
+    if (s < 0) return s;
+    // e = x - x~, r = A e
+    hipLaunchKernelGGL(k_err_pair, dim3((unsigned)(((size_t)nb * nn + 255) / 256)), dim3(256), 0, st,
+                       (const float2*)x_dev, xt.as<double2>(), (float2*)e_dev, (size_t)nb * nn);
+    HH_LAUNCH_CHECK();
+    HH_TRY(launch_apply_op(m, 0, 0.f, nb, bm.inst, (const float2*)e_dev, (float2*)r_dev, nullptr));
+    HH_HIP(hipStreamSynchronize(st));
+    return HH_OK;
+}
+
+hh_net::~hh_net() { delete reinterpret_cast<hh::TrainWork*>(train_work); }
+
+extern "C" hh_status hh_net_get_grads(hh_net* net, float* host) {
+    HH_ARG(net && host, "null pointer");
+    HH_ARG(net->grads.ptr, "no gradients computed yet");
+    HH_HIP(hipStreamSynchronize(net->ctx->stream));
+    HH_HIP(hipMemcpy(host, net->grads.ptr, net->nparams * sizeof(float), hipMemcpyDeviceToHost));
+    return HH_OK;
+}
+
+namespace hh {
 
 }  // namespace hh
 
@@ -955,6 +1843,20 @@ hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin,
     a.Hout = mode == CM_S2 ? Hin / 2 : (mode == CM_T2 ? 2 * Hin : Hin);
     a.Wout = mode == CM_S2 ? Win / 2 : (mode == CM_T2 ? 2 * Win : Win);
     HH_TRY(launch_conv(ctx->stream, ctx->num_cus, cin, cout, mode, a));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+}
+
+hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, int Wo, int Hi, int Wi,
+                        const void* a_dev, const void* x_dev, float* out_dev) {
+    HH_ARG(ctx && a_dev && x_dev && out_dev, "null pointer");
+    HH_ARG(mode == CM_S1 || mode == CM_S2, "mode");
+    HH_ARG(B > 0 && Ho > 0 && Wo > 0 && Hi > 0 && Wi > 0, "sizes");
+    HH_ARG(mode == CM_S1 ? (Hi == Ho && Wi == Wo) : (Hi == 2 * Ho && Wi == 2 * Wo), "input/output sizes");
+    HH_HIP(hipSetDevice(ctx->device));
+    Buf part;
+    HH_TRY(launch_wgrad(ctx->stream, ca, cx, mode, (const uint16_t*)a_dev, (const uint16_t*)x_dev, B, Ho, Wo, Hi, Wi,
+                        part, ctx, out_dev));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
 }

@@ -94,6 +94,10 @@ hh_model_attach_net = _sig("hh_model_attach_net", _I, _P, _P)
 hh_net_forward = _sig("hh_net_forward", _I, _P, _I, _IP, _P, _P)
 hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P)
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
+hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
+hh_gen_training_pairs = _sig("hh_gen_training_pairs", _I, _P, _P, _I, _P, _IP, _P, _P)
+hh_train_step = _sig("hh_train_step", _I, _P, _P, _P, _I, _P, _P, _D, _DP)
+hh_net_get_grads = _sig("hh_net_get_grads", _I, _P, _FP)
 hh_profile_begin = _sig("hh_profile_begin", _I, _P, _I)
 hh_profile_end = _sig("hh_profile_end", _I, _P, _DP, C.POINTER(C.c_longlong))
 HH_K_NUM_CLASSES = 11
@@ -225,6 +229,15 @@ class Model:
         check(hh_model_attach_net(self.handle, net.handle if net is not None else None))
         self.net = net
 
+    def training_pairs(self, x: torch.Tensor, kiters):
+        """(e, r) of eq. 20 for random vectors x (one per slowness model of the model)."""
+        x = x.to(torch.complex64).contiguous()
+        e = torch.empty_like(x)
+        r = torch.empty_like(x)
+        check(hh_gen_training_pairs(self.ctx.handle, self.handle, x.shape[0], _ptr(x), _int_array(kiters), _ptr(e),
+                                    _ptr(r)))
+        return e, r
+
     def net_forward(self, r: torch.Tensor, inst=None) -> torch.Tensor:
         r = r.to(torch.complex64).contiguous()
         e = torch.empty_like(r)
@@ -341,6 +354,19 @@ class Net:
         assert a.size == self.num_params()
         check(hh_net_set_params(self.handle, a.ctypes.data_as(_FP)))
 
+    def get_grads(self) -> np.ndarray:
+        a = np.zeros(self.num_params(), dtype=np.float32)
+        check(hh_net_get_grads(self.handle, a.ctypes.data_as(_FP)))
+        return a
+
+    def train_step(self, model: "Model", r: torch.Tensor, e: torch.Tensor, lr: float) -> float:
+        r = r.to(torch.complex64).contiguous()
+        e = e.to(torch.complex64).contiguous()
+        loss = C.c_double()
+        check(hh_train_step(self.ctx.handle, self.handle, model.handle, r.shape[0], _ptr(r), _ptr(e), lr,
+                            C.byref(loss)))
+        return loss.value
+
     def implicit_test(self, x_bf16: torch.Tensor, nc: int, adjoint=False) -> torch.Tensor:
         y = torch.empty_like(x_bf16)
         check(hh_implicit_test(self.handle, nc, x_bf16.shape[0], _ptr(x_bf16), _ptr(y), int(adjoint)))
@@ -375,3 +401,13 @@ def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, fl
     check(hh_conv_test(ctx.handle, cin, cout, mode, B, H, W_, _ptr(x_bf16), _ptr(w), int(flipped), _ptr(bias),
                        _ptr(skip), int(relu), _ptr(y), _ptr(yf)))
     return y, yf
+
+
+def wgrad_test(ctx: Context, a_bf16: torch.Tensor, x_bf16: torch.Tensor, mode: int) -> torch.Tensor:
+    """Weight-gradient kernel: (ca, cx, 3, 3) FP32 sums of a (x) shifted x over pixels."""
+    B, Ho, Wo, ca = a_bf16.shape
+    _, Hi, Wi, cx = x_bf16.shape
+    a_bf16, x_bf16 = a_bf16.contiguous(), x_bf16.contiguous()
+    out = torch.empty((ca, cx, 3, 3), dtype=torch.float32, device=a_bf16.device)
+    check(hh_wgrad_test(ctx.handle, ca, cx, mode, B, Ho, Wo, Hi, Wi, _ptr(a_bf16), _ptr(x_bf16), _ptr(out)))
+    return out

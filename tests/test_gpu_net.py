@@ -83,6 +83,29 @@ def test_conv_kernel(hh, ctx, cin, cout, mode, flipped, Hs):
         assert np.array_equal(yb, _bf16_round(got))
 
 
+WGRAD_CASES = [
+    # (ca, cx, mode, Ho): conv layers take a = output gradient, x = layer input;
+    # stride-2 transposed layers take a = layer input, x = output gradient
+    (16, 16, 0, 20), (32, 32, 0, 13), (64, 64, 0, 9), (32, 16, 1, 10), (64, 32, 1, 7), (64, 64, 1, 5),
+]
+
+
+@pytest.mark.parametrize("ca,cx,mode,Ho", WGRAD_CASES)
+def test_wgrad_kernel(hh, ctx, ca, cx, mode, Ho):
+    _say(f"wgrad ca={ca} cx={cx} mode={mode} Ho={Ho}")
+    rng = np.random.default_rng(ca * 1000 + cx * 10 + mode)
+    B, s = 2, 1 + mode
+    a = _bf16_round(rng.standard_normal((B, ca, Ho, Ho + 3)))
+    x = _bf16_round(rng.standard_normal((B, cx, s * Ho, s * (Ho + 3))))
+    w0 = np.zeros((ca, cx, 3, 3))
+    # the weight gradient of a convolution y = conv(x) with output gradient a
+    _, ref, _ = C.conv2d_backward(x, w0, a, s)
+    _, scale, _ = C.conv2d_backward(np.abs(x), w0, np.abs(a), s)
+    got = hh.wgrad_test(ctx, _nhwc_dev(a), _nhwc_dev(x), mode).cpu().numpy()
+    # BF16 x BF16 products are exact in FP32: only the FP32 summation rounds
+    assert np.all(np.abs(got - ref) <= 2e-6 * scale + 1e-30), np.abs(got - ref).max() / scale.max()
+
+
 @pytest.mark.parametrize("nc", [8, 16, 32])
 def test_implicit_layer(hh, ctx, nc):
     _say(f"implicit layer nc={nc}")

@@ -1,0 +1,181 @@
+"""GPU training path against the FP64 oracle, through the C ABI:
+method-generated pairs (eq. 20), the loss (eq. 19) and every parameter
+gradient of the BF16 backward pass, Adam's first step, and a fixed batch
+whose loss must drop."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn as C
+from oracle import helmholtz as H
+from oracle import solver as S
+from paper_2306_17486_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hh():
+    from paper_2306_17486_amd import hh as _hh
+    return _hh
+
+
+@pytest.fixture(scope="module")
+def ctx(hh):
+    return hh.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.complex64)
+
+
+def _kappas(n, B, seed):
+    return [inputs.slowness(n, seed + i, "grf" if i % 2 == 0 else "layered") for i in range(B)]
+
+
+def test_training_pairs_match_oracle(hh, ctx):
+    n, B = 64, 3
+    _say("training pairs")
+    ks = _kappas(n, B, 50)
+    om = inputs.omega_for(n)
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om, gamma0=0.05)
+    x = inputs.random_complex((B, n, n), 60)
+    kit = [2, 5, 8]
+    e, r = m.training_pairs(_dev(x), kit)
+    e, r = e.cpu().numpy(), r.cpu().numpy()
+    for b in range(B):
+        prob = H.Problem(ks[b], om, gamma0=0.05)
+        eo, ro = S.training_pair(prob, x[b], kit[b])
+        assert np.linalg.norm(e[b] - eo) / np.linalg.norm(eo) <= 1e-4
+        # r = A e: e is smooth, so A strongly amplifies e's rounding-level
+        # differences; check the GPU's r against the FP64 operator on the GPU's e
+        ra = prob.A(e[b].astype(np.complex128))
+        assert np.linalg.norm(r[b] - ra) / np.linalg.norm(ra) <= 1e-4
+        assert np.linalg.norm(r[b] - ro) / np.linalg.norm(ro) <= 1e-3
+
+
+def _oracle_loss_grads(p, ks, om, r, e, n):
+    h = 1.0 / n
+    net = C.Net(p)
+    rms = np.sqrt(np.mean(np.abs(r) ** 2, axis=(1, 2)))
+    rin = C.to_channels(r / rms[:, None, None])
+    # the GPU rounds the network input to BF16
+    rin = _bf16(rin)
+    kin = np.concatenate([C.kappa_features(*(lambda P: (P.k2w2, P.gamma))(H.Problem(k, om, gamma0=0.05)), h)
+                          for k in ks])
+    s = h * h * rms
+    tgt = C.to_channels(e / s[:, None, None])
+    out, cache = net.forward(rin, kin)
+    L, gout = C.mse_loss(out, tgt)
+    return L, net.backward(cache, gout)
+
+
+def _bf16(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float32).numpy().astype(
+        np.float64)
+
+
+def _bf16_storage(monkeypatch):
+    """Make the oracle's layer primitives round what they hand on (activations
+    and activation gradients) to BF16, as the GPU stores them; parameter
+    gradients stay FP64.  The gap between this run and the plain FP64 run is
+    the rounding noise the GPU's gradients are expected to carry."""
+    conv, convt = C.conv2d, C.conv_transpose2d
+    convb, convtb = C.conv2d_backward, C.conv_transpose2d_backward
+    imp, impb = C.implicit_apply, C.implicit_backward
+
+    def cb(*a, **k):
+        gx, gw, gb = convb(*a, **k)
+        return _bf16(gx), gw, gb
+
+    def ctb(*a, **k):
+        gx, gw, gb = convtb(*a, **k)
+        return _bf16(gx), gw, gb
+
+    def ia(G, z):
+        y, Z = imp(G, z)
+        return C.pair(_bf16(C.unpair(y))), Z
+
+    def ib(G, Z, gy):
+        gz, gG = impb(G, Z, gy)
+        return C.pair(_bf16(C.unpair(gz))), gG
+
+    monkeypatch.setattr(C, "conv2d", lambda *a, **k: _bf16(conv(*a, **k)))
+    monkeypatch.setattr(C, "conv_transpose2d", lambda *a, **k: _bf16(convt(*a, **k)))
+    monkeypatch.setattr(C, "conv2d_backward", cb)
+    monkeypatch.setattr(C, "conv_transpose2d_backward", ctb)
+    monkeypatch.setattr(C, "implicit_apply", ia)
+    monkeypatch.setattr(C, "implicit_backward", ib)
+
+
+def test_loss_and_gradients_match_oracle(hh, ctx, monkeypatch):
+    n, B = 64, 2
+    _say("loss and gradients")
+    ks = _kappas(n, B, 70)
+    om = inputs.omega_for(n)
+    p = inputs.init_net_params(11)
+    for k in p:
+        if k.endswith(".w"):
+            p[k] = 2.0 * p[k]  # keeps every layer's gradient well away from zero
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om, gamma0=0.05)
+    x = inputs.random_complex((B, n, n), 80)
+    e, r = m.training_pairs(_dev(x), [3, 6])
+    e64, r64 = e.cpu().numpy().astype(np.complex128), r.cpu().numpy().astype(np.complex128)
+    net = hh.Net(ctx, p)
+    loss = net.train_step(m, r, e, lr=0.0)
+    g = hh.unflatten_params(net.get_grads())
+    L, go = _oracle_loss_grads(p, ks, om, r64, e64, n)
+    with monkeypatch.context() as mp:
+        _bf16_storage(mp)
+        _, gq = _oracle_loss_grads(p, ks, om, r64, e64, n)
+    _say(f"  loss gpu {loss:.6e} oracle {L:.6e}")
+    assert abs(loss - L) <= 1e-3 * L
+    bad = []
+    for name in sorted(go):
+        ref = np.asarray(go[name]).ravel()
+        err = np.linalg.norm(g[name].ravel() - ref) / np.linalg.norm(ref)
+        noise = np.linalg.norm(np.asarray(gq[name]).ravel() - ref) / np.linalg.norm(ref)
+        _say(f"  {name:12s} rel {err:.3e}  bf16-storage noise {noise:.3e}")
+        # a wrong term, operand or mask in a layer's backward gives O(1) errors;
+        # rounding noise stays within a small multiple of the emulated one
+        if err > 3.0 * noise + 2e-3:
+            bad.append((name, err, noise))
+    assert not bad, bad
+
+
+def test_adam_first_step_closed_form(hh, ctx):
+    n, B = 64, 2
+    _say("adam first step")
+    ks = _kappas(n, B, 90)
+    om = inputs.omega_for(n)
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om, gamma0=0.05)
+    e, r = m.training_pairs(_dev(inputs.random_complex((B, n, n), 91)), [4, 4])
+    net = hh.Net(ctx, inputs.init_net_params(12))
+    p0 = net.get_params().astype(np.float64)
+    lr = 1e-3
+    net.train_step(m, r, e, lr=lr)
+    g = net.get_grads().astype(np.float64)
+    p1 = net.get_params().astype(np.float64)
+    expect = p0 - lr * g / (np.abs(g) + 1e-8)
+    assert np.abs(p1 - expect).max() <= 2e-6
+
+
+def test_fixed_batch_loss_decreases(hh, ctx):
+    n, B = 64, 8
+    _say("fixed batch training")
+    ks = _kappas(n, B, 100)
+    om = inputs.omega_for(n)
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om, gamma0=0.05)
+    e, r = m.training_pairs(_dev(inputs.random_complex((B, n, n), 101)), [2, 3, 4, 5, 6, 7, 8, 2])
+    net = hh.Net(ctx, inputs.init_net_params(13))
+    losses = [net.train_step(m, r, e, lr=1e-3) for _ in range(40)]
+    _say(f"  loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.8 * losses[0]
