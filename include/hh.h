@@ -117,6 +117,12 @@ typedef struct {
     int use_x0;         /* 1: x_dev holds the initial guess; 0: start from zero */
     int fixed_iters;    /* >0: run exactly this many iterations (single cycle, no
                            convergence test); used to generate training data (eq. 20) */
+    int fallback;       /* CNN_MG only, default 1: MG-only FGMRES judges the network per
+                           RHS.  A restart cycle that cuts the FP64 residual by less than
+                           probe_ratio is followed by one MG-only cycle; if that cycle cuts
+                           it more, the RHS finishes with MG-only, otherwise it returns to
+                           CNN+MG and the wait before its next probe doubles. */
+    double probe_ratio; /* default 0.5 */
 } hh_solve_opts;
 
 void hh_solve_opts_default(hh_solve_opts* o);
@@ -130,13 +136,14 @@ void hh_solve_opts_default(hh_solve_opts* o);
  *              value); entries past the last iteration are set to -1
  *   iters_host, converged_host: optional int [nrhs]
  *   final_res_host: optional double [nrhs]: ||b - A x|| / ||b|| recomputed in FP64
+ *   fellback_host: optional int [nrhs]: 1 where a CNN_MG solve switched to MG-only
  * The stencil, V-cycle and network run in single precision / BF16; the
  * Gram-Schmidt sums, the Hessenberg least-squares problem, x and the restart
  * residual are FP64.  Returns HH_NOT_CONVERGED if any RHS stopped at
  * max_iters above rtol.  Synchronises the stream. */
 hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
                    void* x_dev, const hh_solve_opts* o, double* res_hist_host, int* iters_host,
-                   int* converged_host, double* final_res_host);
+                   int* converged_host, double* final_res_host, int* fellback_host);
 
 /* ------------------------------------------------------------------------
  * Building blocks exposed for parity tests (same kernels as the solve).
@@ -205,7 +212,7 @@ hh_status hh_gen_training_pairs(hh_ctx* ctx, hh_model* m, int nb, const void* x_
                                 void* e_dev, void* r_dev);
 
 /* One training step on B pairs (r, e) (c64 [B][n][n]), sample b on slowness
- * model b of md (md->ninst == B), n < 512: BF16 forward and backward through
+ * model b of md (md->ninst == B), n a power of two from 64 to 512: BF16 forward and backward through
  * encoder, solver and implicit layer, loss (eq. 19)
  *   L = (1/B) sum_b || P(Net(r_b / rms(r_b))) - e_b / s_b ||^2,  s_b = h^2 rms(r_b),
  * FP32 gradients (hh_net_get_grads), then one Adam step with learning rate lr
@@ -213,6 +220,10 @@ hh_status hh_gen_training_pairs(hh_ctx* ctx, hh_model* m, int nb, const void* x_
  * *loss_out receives L before the update.  Synchronises the stream. */
 hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev, double lr,
                         double* loss_out);
+/* The loss L of hh_train_step (same arguments and rules) without the backward
+ * pass: no gradient, parameter or optimiser state changes.  For validation. */
+hh_status hh_eval_loss(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev,
+                       double* loss_out);
 /* FP32 gradients of the last training step, same layout as the parameters. */
 hh_status hh_net_get_grads(hh_net* net, float* host);
 

@@ -212,7 +212,7 @@ def _norm(a):
 
 
 def fgmres(A, b, M, x0=None, restart: int = 10, rtol: float = 1e-6, max_iters: int = 2000,
-           iters_done: int = 0):
+           iters_done: int = 0, cycles: int | None = None):
     """Right-preconditioned flexible GMRES(restart).
 
     The preconditioner M may change from one application to the next (the
@@ -224,6 +224,8 @@ def fgmres(A, b, M, x0=None, restart: int = 10, rtol: float = 1e-6, max_iters: i
     recomputed; the solve stops only when that true relative residual is
     <= rtol, or when ``max_iters`` preconditioner applications are reached.
 
+    ``cycles`` (optional) stops after that many restart cycles.
+
     Returns (x, iterations, history, true_rel): history[k] is the relative
     residual estimate after k total iterations (history[0] = initial true
     relative residual).
@@ -234,9 +236,11 @@ def fgmres(A, b, M, x0=None, restart: int = 10, rtol: float = 1e-6, max_iters: i
     r = b - A(x)
     beta = _norm(r)
     hist = [beta / bnorm]
+    ncyc = 0
     while True:
-        if beta / bnorm <= rtol or its >= max_iters:
+        if beta / bnorm <= rtol or its >= max_iters or (cycles is not None and ncyc >= cycles):
             break
+        ncyc += 1
         V = [r / beta]
         Z = []
         H = np.zeros((restart + 1, restart), dtype=np.complex128)

@@ -40,15 +40,47 @@ def cnn_mg_precond(prob: H.Problem, netp: NetPrecond, v: np.ndarray) -> np.ndarr
 
 
 def solve_two_phase(prob: H.Problem, netp: NetPrecond, b: np.ndarray, rtol=1e-6, max_iters=2000,
-                    warm_iters=3, restart=10):
+                    warm_iters=3, restart=10, fallback=True, probe_ratio=0.5, stats=None):
     """Sec. 4.1: a few MG-only FGMRES iterations, then FGMRES(restart) with the
-    CNN+MG preconditioner from that iterate.  Iterations of both phases count."""
+    CNN+MG preconditioner from that iterate.  Iterations of both phases count.
+
+    With ``fallback``, MG-only FGMRES judges the network, one restart cycle at a
+    time (the reading of the method used here; the paper gives no rule): a
+    CNN+MG cycle whose true residual ratio (end / start) exceeds probe_ratio is
+    followed by one MG-only cycle.  If that probe cycle reduces the residual
+    more than the CNN+MG cycle did, the solve finishes with MG-only; otherwise
+    it returns to CNN+MG, and the number of CNN+MG cycles before the next
+    probe may run doubles (2, 4, 8, ...).  ``stats`` (a dict, optional)
+    receives ``fell_back`` and ``probes``."""
     x, its, hist, rel = H.fgmres(prob.A, b, prob.mg, None, restart, rtol, warm_iters)
-    if rel <= rtol:
-        return x, its, hist, rel
-    x, its2, hist2, rel = H.fgmres(prob.A, b, lambda v: cnn_mg_precond(prob, netp, v), x, restart,
-                                   rtol, max_iters, iters_done=its)
-    return x, its2, hist + hist2[1:], rel
+    mode, q_cnn, wait, gap, probes = "cnn", None, 0, 0, 0
+    while rel > rtol and its < max_iters:
+        if mode == "cnn":
+            M = lambda v: cnn_mg_precond(prob, netp, v)  # noqa: E731
+        else:
+            M = prob.mg
+        rel0 = rel
+        x, its, h, rel = H.fgmres(prob.A, b, M, x, restart, rtol, max_iters, iters_done=its, cycles=1)
+        hist = hist + h[1:]
+        q = rel / rel0
+        if mode == "cnn":
+            q_cnn = q
+            if fallback and q > probe_ratio and wait <= 0:
+                mode = "probe"
+                probes += 1
+            elif wait > 0:
+                wait -= 1
+        elif mode == "probe":
+            if q < q_cnn:
+                mode = "mg"
+            else:
+                gap = 2 * gap if gap > 0 else 2
+                wait = gap
+                mode = "cnn"
+    if stats is not None:
+        stats["fell_back"] = mode == "mg"
+        stats["probes"] = probes
+    return x, its, hist, rel
 
 
 def training_pair(prob: H.Problem, x: np.ndarray, k: int):

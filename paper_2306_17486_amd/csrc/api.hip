@@ -201,11 +201,13 @@ void hh_solve_opts_default(hh_solve_opts* o) {
     o->warm_mg_iters = 3;
     o->use_x0 = 0;
     o->fixed_iters = 0;
+    o->fallback = 1;
+    o->probe_ratio = 0.5;
 }
 
 hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev, void* x_dev,
                    const hh_solve_opts* o, double* res_hist_host, int* iters_host, int* converged_host,
-                   double* final_res_host) {
+                   double* final_res_host, int* fellback_host) {
     HH_ARG(ctx && m && b_dev && x_dev && o, "null pointer");
     HH_ARG(m->ctx == ctx, "model belongs to another context");
     HH_ARG(nrhs >= 1, "nrhs >= 1");
@@ -213,6 +215,7 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
     HH_ARG(o->max_iters >= 1 && o->rtol >= 0.0, "max_iters >= 1, rtol >= 0");
     HH_ARG(o->precond == HH_PRECOND_MG || o->precond == HH_PRECOND_CNN_MG, "precond");
     HH_ARG(o->fixed_iters >= 0 && o->fixed_iters <= o->restart, "0 <= fixed_iters <= restart");
+    HH_ARG(o->probe_ratio >= 0.0 && o->probe_ratio <= 1.0, "0 <= probe_ratio <= 1");
     HH_ARG(o->precond == HH_PRECOND_MG || m->net != nullptr, "CNN_MG needs a network attached to the model");
     HH_HIP(hipSetDevice(ctx->device));
     if (!ctx->work) {
@@ -244,6 +247,7 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
         if (iters_host) iters_host[r] = hs[r].iters;
         if (converged_host) converged_host[r] = hs[r].converged;
         if (final_res_host) final_res_host[r] = hs[r].res_true;
+        if (fellback_host) fellback_host[r] = hs[r].fellback;
         all_conv = all_conv && hs[r].converged;
         broke = broke || hs[r].breakdown;
     }

@@ -16,8 +16,15 @@ struct KState {
     double bnorm, res_est, res_true;
     double tol_scale;  // inner-cycle target = rtol * tol_scale (tightened when the FP64 residual refutes it)
     int k, iters, converged, breakdown;
-    int ended_by_est, pad_;
+    int ended_by_est;
+    int mode;                   // preconditioner of the current cycle (PM_*)
+    int probe_wait, probe_gap;  // CNN+MG cycles before the next MG probe may run, and the next wait
+    int fellback, pad_;         // 1 once the RHS has switched to MG-only for good
+    double res_cycle0;          // true relative residual at the start of the current cycle
+    double q_cnn;               // residual reduction of the last CNN+MG cycle
 };
+// Preconditioner of a restart cycle of a CNN+MG solve (per RHS).
+enum { PM_WARM = 0, PM_CNN = 1, PM_PROBE = 2, PM_MG = 3 };
 static_assert(sizeof(KState) % 8 == 0, "KState must be a whole number of doubles");
 
 // Device workspace of one solve (grown on demand, reused across calls).

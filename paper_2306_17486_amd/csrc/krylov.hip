@@ -254,6 +254,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_col(const double2* __restrict__
 // small triangular solve, per-RHS flags.
 __global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ parts, int npart, int j,
                                                 KState* __restrict__ st, int* __restrict__ active,
+                                                int* __restrict__ actc, int* __restrict__ actm,
                                                 double* __restrict__ hist, int hist_len, double rtol, int max_iters,
                                                 const int* __restrict__ caps) {
     __shared__ double2 s_red[4];
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ part
     const bool by_est = est <= rtol * S.tol_scale;
     if (by_est) S.ended_by_est = 1;
     const int cap = caps ? min(caps[r], max_iters) : max_iters;
-    if (bad || by_est || S.iters >= cap || hn == 0.0) active[r] = 0;
+    if (bad || by_est || S.iters >= cap || hn == 0.0) active[r] = actc[r] = actm[r] = 0;
 }
 
 // x += sum_{q<k} y_q z_q  (x complex double)
@@ -373,14 +374,46 @@ __global__ void k_init_state(const double2* __restrict__ parts, int npart, KStat
         for (int q = 0; q < hist_len; ++q) hist[(size_t)r * hist_len + q] = -1.0;
 }
 
-// Start of a restart cycle: beta = ||r||, true relative residual, stopping test.
+// Preconditioner of the next restart cycle of a CNN+MG solve, with MG-only
+// FGMRES as the judge: a CNN+MG cycle that reduces the FP64 residual by less
+// than probe_ratio is followed by one MG-only probe cycle; if the probe reduces
+// the residual more than the CNN+MG cycle did, the RHS stays on MG-only for the
+// rest of the solve, otherwise it returns to CNN+MG and waits twice as many
+// cycles before it may be probed again.
+__device__ static int next_mode(KState& S, int warm, int fallback, double probe_ratio) {
+    if (warm) return PM_WARM;
+    const double q = S.res_cycle0 > 0.0 ? S.res_true / S.res_cycle0 : 0.0;
+    switch (S.mode) {
+        case PM_WARM:
+            return PM_CNN;
+        case PM_CNN:
+            S.q_cnn = q;
+            if (fallback && q > probe_ratio && S.probe_wait <= 0) return PM_PROBE;
+            if (S.probe_wait > 0) S.probe_wait--;
+            return PM_CNN;
+        case PM_PROBE:
+            if (q < S.q_cnn) {
+                S.fellback = 1;
+                return PM_MG;
+            }
+            S.probe_gap = S.probe_gap > 0 ? 2 * S.probe_gap : 2;
+            S.probe_wait = S.probe_gap;
+            return PM_CNN;
+        default:
+            return PM_MG;
+    }
+}
+
+// Start of a restart cycle: beta = ||r||, true relative residual, stopping test,
+// and the masks of the RHS that use CNN+MG (actc) and MG-only (actm) in it.
 __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KState* __restrict__ st, int* done,
-                              int* active, double* hist, int hist_len, double rtol, int max_iters, int fixed,
-                              const int* __restrict__ caps) {
+                              int* active, int* actc, int* actm, double* hist, int hist_len, double rtol,
+                              int max_iters, int fixed, const int* __restrict__ caps, int cnn, int warm, int fallback,
+                              double probe_ratio) {
     __shared__ double2 s_red[4];
     const int r = blockIdx.x;
     if (done[r]) {
-        if (threadIdx.x == 0) active[r] = 0;
+        if (threadIdx.x == 0) active[r] = actc[r] = actm[r] = 0;
         return;
     }
     double2 acc[1] = {make_double2(0.0, 0.0)};
@@ -401,14 +434,19 @@ __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KSta
     const int cap = caps ? min(caps[r], max_iters) : max_iters;
     if (bad || S.converged || S.iters >= cap || beta == 0.0) {
         done[r] = 1;
-        active[r] = 0;
+        active[r] = actc[r] = actm[r] = 0;
         return;
     }
     S.sig[0] = 1.0 / beta;
     for (int q = 0; q < MAXV; ++q) S.g[q] = make_double2(0.0, 0.0);
     S.g[0] = make_double2(beta, 0.0);
     S.k = 0;
+    if (cnn) S.mode = next_mode(S, warm, fallback, probe_ratio);
+    S.res_cycle0 = S.res_true;
+    const int c = cnn && S.mode == PM_CNN;
     active[r] = 1;
+    actc[r] = c;
+    actm[r] = !c;
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +475,7 @@ hh_status SolveWork::prepare(hh_ctx* c, hh_model* md, int nrhs_, int restart_, i
     HH_TRY(V.ensure(c, (size_t)nrhs * (restart + 1) * nn * sizeof(float2)));
     HH_TRY(Z.ensure(c, (size_t)nrhs * restart * nn * sizeof(float2)));
     HH_TRY(state.ensure(c, (size_t)nrhs * sizeof(KState)));
-    HH_TRY(flags.ensure(c, (size_t)2 * nrhs * sizeof(int)));
+    HH_TRY(flags.ensure(c, (size_t)4 * nrhs * sizeof(int)));
     HH_TRY(parts.ensure(c, (size_t)nrhs * npart * MAXV * sizeof(double2)));
     HH_TRY(inst.ensure(c, (size_t)nrhs * sizeof(int)));
     HH_TRY(hist.ensure(c, (size_t)nrhs * hist_len * sizeof(double) + 8));
@@ -462,8 +500,10 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
     float2* V = W.V.as<float2>();
     float2* Z = W.Z.as<float2>();
     KState* S = W.state.as<KState>();
-    int* done = W.flags.as<int>();
-    int* act = done + nrhs;
+    int* done = W.flags.as<int>();  // [done | actc | actm | active]
+    int* actc = done + nrhs;
+    int* actm = done + 2 * nrhs;
+    int* act = done + 3 * nrhs;
     double2* parts = W.parts.as<double2>();
     double* hist = W.hist.as<double>();
     const int sig_stride = (int)(sizeof(KState) / sizeof(double));
@@ -478,9 +518,11 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
     HH_LAUNCH_CHECK();
     if (!o.use_x0) HH_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * nn * sizeof(double2), st));
 
-    std::vector<int> hdone(nrhs);
+    std::vector<int> hflags((size_t)3 * nrhs);
     int cycle = 0;
+    const bool cnn = precond_cnn != nullptr;
     for (;;) {
+        const bool warm = cnn && cycle == 0 && o.warm_mg_iters > 0;
         {
             ProfScope ps(ctx, HH_K_RESTART);
             hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
@@ -489,29 +531,31 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
         HH_LAUNCH_CHECK();
         {
             ProfScope ps(ctx, HH_K_SMALL);
-            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist,
-                               W.hist_len, rtol, max_iters, fixed ? 1 : 0, W.caps_dev);
+            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, actc, actm,
+                               hist, W.hist_len, rtol, max_iters, fixed ? 1 : 0, W.caps_dev, cnn ? 1 : 0,
+                               warm ? 1 : 0, o.fallback, o.probe_ratio);
         }
         HH_LAUNCH_CHECK();
-        HH_HIP(hipMemcpyAsync(hdone.data(), done, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+        HH_HIP(hipMemcpyAsync(hflags.data(), done, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, st));
         HH_HIP(hipStreamSynchronize(st));
-        bool all = true;
-        for (int r = 0; r < nrhs; ++r) all = all && hdone[r];
+        bool all = true, any_c = false, any_m = false;
+        for (int r = 0; r < nrhs; ++r) {
+            all = all && hflags[r];
+            any_c = any_c || hflags[nrhs + r];
+            any_m = any_m || hflags[2 * nrhs + r];
+        }
         if (all) break;
-        const bool use_cnn = precond_cnn && !(cycle == 0 && o.warm_mg_iters > 0);
         int len = W.restart;
-        if (precond_cnn && cycle == 0 && o.warm_mg_iters > 0) len = std::min(len, o.warm_mg_iters);
+        if (warm) len = std::min(len, o.warm_mg_iters);
         if (fixed) len = std::min(len, o.fixed_iters);
         for (int j = 0; j < len; ++j) {
             const float2* vj = V + (size_t)j * nn;
             const double* sg = reinterpret_cast<const double*>(reinterpret_cast<const char*>(S) + offsetof(KState, sig)) + j;
             float2* zj = Z + (size_t)j * nn;
-            // z_j = M(v_j): the preconditioner works on [rhs] vectors with strides; use per-RHS views
-            if (use_cnn) {
-                HH_TRY(precond_cnn(precond_user, md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, act));
-            } else {
-                HH_TRY(precond_mg_strided(md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, act));
-            }
+            // z_j = M(v_j) on strided [rhs] views: CNN+MG for the RHS in actc,
+            // MG-only for those in actm (warm start, probes, fallback)
+            if (any_c) HH_TRY(precond_cnn(precond_user, md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, actc));
+            if (any_m) HH_TRY(precond_mg_strided(md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, actm));
             // w = A z_j, dots with v_0..v_j
             {
             ProfScope ps(ctx, HH_K_OP_DOTS);
@@ -542,8 +586,8 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
             HH_LAUNCH_CHECK();
             {
                 ProfScope ps(ctx, HH_K_SMALL);
-                hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(256), 0, st, parts, np, j, S, act, hist, W.hist_len,
-                                   rtol, max_iters, W.caps_dev);
+                hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(256), 0, st, parts, np, j, S, act, actc, actm, hist,
+                                   W.hist_len, rtol, max_iters, W.caps_dev);
             }
             HH_LAUNCH_CHECK();
         }
@@ -558,8 +602,8 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
             hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
                                1.0 / (L0.h * L0.h), parts, nullptr);
             HH_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist,
-                               W.hist_len, rtol, 0, 1, W.caps_dev);
+            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, actc, actm,
+                               hist, W.hist_len, rtol, 0, 1, W.caps_dev, 0, 0, 0, 0.0);
             HH_LAUNCH_CHECK();
             break;
         }

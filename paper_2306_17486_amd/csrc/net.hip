@@ -1332,13 +1332,27 @@ static hh_status dgrad_layer(hh_net* net, int l, int mode, const uint16_t* gout,
 
 using namespace hh;
 
-extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev,
-                                   const void* e_dev, double lr, double* loss_out) {
+// sum of the per-block loss partials written by k_loss, divided by B
+static hh_status read_loss(hh_ctx* ctx, const Buf& lparts, int B, double* loss_out) {
+    std::vector<double> lp((size_t)B * 64);
+    HH_HIP(hipMemcpyAsync(lp.data(), lparts.ptr, lp.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    double L = 0.0;
+    for (double v : lp) L += v;
+    if (loss_out) *loss_out = L / B;
+    return HH_OK;
+}
+
+// forward pass and loss on B pairs; with backward set, also every gradient and
+// (lr > 0) one Adam step
+static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev,
+                            double lr, double* loss_out, bool backward) {
     HH_ARG(ctx && net && md && r_dev && e_dev, "null pointer");
     HH_ARG(net->ctx == ctx && md->ctx == ctx, "objects of another context");
     HH_ARG(B >= 1 && (md->ninst == B || md->ninst == 1), "model must hold one slowness model per sample (or one)");
     const int n = md->lev[0].n;
-    HH_ARG(n % 16 == 0 && n < 512, "training sizes: n divisible by 16 and below 512");
+    HH_ARG(n % 16 == 0 && n >= 64 && n <= 512 && (n & (n - 1)) == 0,
+           "training sizes: n a power of two from 64 to 512 (implicit-layer gradient transforms up to 64)");
     HH_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     if (!net->train_work) {
@@ -1368,6 +1382,7 @@ extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B
     hipLaunchKernelGGL(k_loss, dim3(64, B), dim3(256), 0, st, A.a[L_OUT].as<float2>(), (const float2*)e_dev, out_scale,
                        T.gfull.as<float2>(), T.lparts.as<double>(), n, 1.f / B);
     HH_LAUNCH_CHECK();
+    if (!backward) return read_loss(ctx, T.lparts, B, loss_out);
     hipLaunchKernelGGL(k_restrict4, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.gfull.as<float2>(),
                        T.go.as<float2>(), n);
     HH_LAUNCH_CHECK();
@@ -1507,7 +1522,6 @@ extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B
         }
         const int lvl_c2[3] = {L_ENC3_C2, L_ENC2_C2, L_ENC1_C2};
         const int lvl_gs[3] = {L_S3_D, L_S2_D, L_S1_D};
-        const uint16_t* add = nullptr;  // gradient reaching E_k from the next encoder level
         for (int k = 0; k < 3; ++k) {
             const int l2 = lvl_c2[k], mm = lvl_m[k];
             const size_t cnt = (size_t)B * mm * mm * net->L[l2].cout;
@@ -1516,7 +1530,6 @@ extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B
                                    nullptr, enc(l2), G(l2), cnt);
                 HH_LAUNCH_CHECK();
             }
-            (void)add;
             HH_TRY(wgrad_conv(l2, CM_S1, enc(l2 - 1), mm, mm, mm, mm));
             HH_TRY(dgrad_layer(net, l2, CM_S1, G(l2), B, mm, mm, G(l2 - 1), mm, mm, nullptr, enc(l2 - 1)));
             HH_TRY(wgrad_conv(l2 - 1, CM_S1, enc(l2 - 2), mm, mm, mm, mm));
@@ -1558,14 +1571,17 @@ extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B
         net->packed_valid = false;
         net->version++;
     }
-    // ---- loss value
-    std::vector<double> lp((size_t)B * 64);
-    HH_HIP(hipMemcpyAsync(lp.data(), T.lparts.ptr, lp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HH_HIP(hipStreamSynchronize(st));
-    double L = 0.0;
-    for (double v : lp) L += v;
-    if (loss_out) *loss_out = L / B;
-    return HH_OK;
+    return read_loss(ctx, T.lparts, B, loss_out);
+}
+
+extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev,
+                                   const void* e_dev, double lr, double* loss_out) {
+    return train_core(ctx, net, md, B, r_dev, e_dev, lr, loss_out, true);
+}
+
+extern "C" hh_status hh_eval_loss(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev,
+                                  const void* e_dev, double* loss_out) {
+    return train_core(ctx, net, md, B, r_dev, e_dev, 0.0, loss_out, false);
 }
 
 // e = x - xt (xt complex double), single precision

@@ -47,7 +47,8 @@ class hh_model_desc(C.Structure):
 
 class hh_solve_opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("rtol", C.c_double), ("precond", C.c_int),
-                ("warm_mg_iters", C.c_int), ("use_x0", C.c_int), ("fixed_iters", C.c_int)]
+                ("warm_mg_iters", C.c_int), ("use_x0", C.c_int), ("fixed_iters", C.c_int), ("fallback", C.c_int),
+                ("probe_ratio", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -75,7 +76,7 @@ hh_model_desc_default = _sig("hh_model_desc_default", None, C.POINTER(hh_model_d
 hh_model_create = _sig("hh_model_create", _I, _P, C.POINTER(hh_model_desc), _I, _P, C.POINTER(_P))
 hh_model_destroy = _sig("hh_model_destroy", _I, _P)
 hh_solve_opts_default = _sig("hh_solve_opts_default", None, C.POINTER(hh_solve_opts))
-hh_solve = _sig("hh_solve", _I, _P, _P, _I, _IP, _P, _P, C.POINTER(hh_solve_opts), _DP, _IP, _IP, _DP)
+hh_solve = _sig("hh_solve", _I, _P, _P, _I, _IP, _P, _P, C.POINTER(hh_solve_opts), _DP, _IP, _IP, _DP, _IP)
 hh_apply_operator = _sig("hh_apply_operator", _I, _P, _I, _D, _I, _IP, _P, _P)
 hh_apply_vcycle = _sig("hh_apply_vcycle", _I, _P, _I, _IP, _P, _P, _P)
 class hh_net_desc(C.Structure):
@@ -97,6 +98,7 @@ hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
 hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
 hh_gen_training_pairs = _sig("hh_gen_training_pairs", _I, _P, _P, _I, _P, _IP, _P, _P)
 hh_train_step = _sig("hh_train_step", _I, _P, _P, _P, _I, _P, _P, _D, _DP)
+hh_eval_loss = _sig("hh_eval_loss", _I, _P, _P, _P, _I, _P, _P, _DP)
 hh_net_get_grads = _sig("hh_net_get_grads", _I, _P, _FP)
 hh_profile_begin = _sig("hh_profile_begin", _I, _P, _I)
 hh_profile_end = _sig("hh_profile_end", _I, _P, _DP, C.POINTER(C.c_longlong))
@@ -246,7 +248,8 @@ class Model:
 
     # -- solve --------------------------------------------------------------
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, inst=None, restart=10, max_iters=2000,
-              rtol=1e-6, precond=HH_PRECOND_MG, warm_mg_iters=3, fixed_iters=0, want_hist=True):
+              rtol=1e-6, precond=HH_PRECOND_MG, warm_mg_iters=3, fixed_iters=0, want_hist=True, fallback=True,
+              probe_ratio=0.5):
         """Returns (x complex128 tensor, info dict with iters, converged, final_res, hist)."""
         b = b.to(torch.complex64).contiguous()
         nrhs = b.shape[0]
@@ -258,16 +261,19 @@ class Model:
         hh_solve_opts_default(C.byref(o))
         o.restart, o.max_iters, o.rtol, o.precond = restart, max_iters, rtol, precond
         o.warm_mg_iters, o.use_x0, o.fixed_iters = warm_mg_iters, int(x0 is not None), fixed_iters
+        o.fallback, o.probe_ratio = int(fallback), probe_ratio
         hl = (fixed_iters if fixed_iters > 0 else max_iters) + 1
         hist = np.zeros((nrhs, hl)) if want_hist else None
         iters = np.zeros(nrhs, dtype=np.int32)
         conv = np.zeros(nrhs, dtype=np.int32)
         fres = np.zeros(nrhs)
+        fb = np.zeros(nrhs, dtype=np.int32)
         st = hh_solve(self.ctx.handle, self.handle, nrhs, _int_array(inst), _ptr(b), _ptr(x), C.byref(o),
                       hist.ctypes.data_as(_DP) if hist is not None else None, iters.ctypes.data_as(_IP),
-                      conv.ctypes.data_as(_IP), fres.ctypes.data_as(_DP))
+                      conv.ctypes.data_as(_IP), fres.ctypes.data_as(_DP), fb.ctypes.data_as(_IP))
         check(st, allow=(HH_OK, HH_NOT_CONVERGED))
-        return x, dict(iters=iters, converged=conv.astype(bool), final_res=fres, hist=hist, status=st)
+        return x, dict(iters=iters, converged=conv.astype(bool), final_res=fres, hist=hist, status=st,
+                       fell_back=fb.astype(bool))
 
 
 # ---------------------------------------------------------------------------
@@ -365,6 +371,14 @@ class Net:
         loss = C.c_double()
         check(hh_train_step(self.ctx.handle, self.handle, model.handle, r.shape[0], _ptr(r), _ptr(e), lr,
                             C.byref(loss)))
+        return loss.value
+
+    def eval_loss(self, model: "Model", r: torch.Tensor, e: torch.Tensor) -> float:
+        """Loss of hh_train_step without the backward pass or an update."""
+        r = r.to(torch.complex64).contiguous()
+        e = e.to(torch.complex64).contiguous()
+        loss = C.c_double()
+        check(hh_eval_loss(self.ctx.handle, self.handle, model.handle, r.shape[0], _ptr(r), _ptr(e), C.byref(loss)))
         return loss.value
 
     def implicit_test(self, x_bf16: torch.Tensor, nc: int, adjoint=False) -> torch.Tensor:

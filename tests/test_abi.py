@@ -44,6 +44,7 @@ def test_defaults_without_gpu():
     o = hh.hh_solve_opts()
     hh.hh_solve_opts_default(C.byref(o))
     assert (o.restart, o.max_iters, o.warm_mg_iters) == (10, 2000, 3) and o.rtol == 1e-6
+    assert o.fallback == 1 and o.probe_ratio == 0.5
 
 
 def test_argument_errors_are_reported_without_gpu():

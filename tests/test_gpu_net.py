@@ -106,7 +106,7 @@ def test_wgrad_kernel(hh, ctx, ca, cx, mode, Ho):
     assert np.all(np.abs(got - ref) <= 2e-6 * scale + 1e-30), np.abs(got - ref).max() / scale.max()
 
 
-@pytest.mark.parametrize("nc", [8, 16, 32])
+@pytest.mark.parametrize("nc", [8, 16, 32, 64])
 def test_implicit_layer(hh, ctx, nc):
     _say(f"implicit layer nc={nc}")
     p = inputs.init_net_params(3)
@@ -129,7 +129,8 @@ def test_implicit_layer(hh, ctx, nc):
         assert np.all(np.abs(y - ref) <= tol), (adjoint, np.abs(y - ref).max() / np.abs(ref).max())
 
 
-@pytest.mark.parametrize("n,family", [(64, "grf"), (128, "layered"), (512, "grf")])
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("n,family", [(64, "grf"), (128, "layered"), (512, "grf"), (1024, "layered")])
 def test_network_forward(hh, ctx, n, family):
     _say(f"network forward n={n}")
     k = inputs.slowness(n, 21, family)
@@ -170,3 +171,34 @@ def test_cnn_mg_two_phase_solve(hh, ctx):
         _, its_o, _, _ = S.solve_two_phase(prob, netp, b[r])
         _say(f"  rhs {r}: gpu {info['iters'][r]} oracle {its_o}")
         assert abs(int(info["iters"][r]) - its_o) <= max(3, int(0.25 * its_o))
+
+
+def test_cnn_mg_judge_falls_back_for_a_bad_network(hh, ctx):
+    # a projection layer scaled by 1e4 makes the network's output swamp the
+    # V-cycle: the CNN+MG cycle stalls, one MG-only probe wins, the RHS ends on MG
+    n = 64
+    _say("cnn+mg judge, bad network")
+    k = inputs.grf_slowness(n, 31)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    p = inputs.init_net_params(7)
+    p["out.w"] = 1e4 * p["out.w"]
+    p["out.b"] = 1e4 * p["out.b"]
+    net = hh.Net(ctx, p)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.attach_net(net)
+    b = np.stack([inputs.point_source(n, 50), inputs.point_source(n, 51)])
+    x, info = m.solve(torch.from_numpy(b).to("cuda:0", torch.complex64), precond=hh.HH_PRECOND_CNN_MG)
+    x = x.cpu().numpy()
+    netp = S.NetPrecond(C.Net(p), prob)
+    for r in range(2):
+        rel = np.linalg.norm(b[r] - prob.A(x[r])) / np.linalg.norm(b[r])
+        assert info["converged"][r] and rel <= 1e-6
+        st = {}
+        _, its_o, _, _ = S.solve_two_phase(prob, netp, b[r], stats=st)
+        _, its_mg, _, _ = H.solve_mg(prob, b[r])
+        _say(f"  rhs {r}: gpu {info['iters'][r]} (fell back {info['fell_back'][r]}) oracle {its_o} {st} "
+             f"mg-only {its_mg}")
+        assert st["fell_back"] and info["fell_back"][r]
+        assert abs(int(info["iters"][r]) - its_o) <= max(3, int(0.25 * its_o))
+        assert info["iters"][r] <= its_mg + 2 * 10

@@ -1,0 +1,72 @@
+"""The oracle's two-phase solve with MG-only FGMRES judging the network
+(restart-cycle probes, permanent fallback), pinned by three cases whose outcome
+follows from the method itself:
+
+* an exact network (the direct solve) makes CNN+MG a strong preconditioner
+  (the V-cycle that follows relaxes on the shifted operator, so it is not
+  exact): every CNN+MG cycle cuts the residual far below the probe ratio, the
+  judge never probes and the solve needs a fraction of MG-only's iterations;
+* a network that returns large noise cannot reduce the residual (FGMRES picks
+  the best combination, so the cycle stalls): the judge probes once, MG-only
+  wins and the solve costs at most one wasted cycle more than MG-only;
+* without the judge the same noisy network needs far more iterations."""
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from oracle import helmholtz as H
+from oracle import solver as S
+from paper_2306_17486_amd import inputs
+
+N = 64
+
+
+def _problem():
+    k = inputs.grf_slowness(N, 5)
+    return H.Problem(k, inputs.omega_for(N, k))
+
+
+class _Exact:
+    def __init__(self, prob):
+        self.lu = spla.splu(prob.matrix(0.0).tocsc())
+
+    def __call__(self, r):
+        return self.lu.solve(r.ravel()).reshape(r.shape)
+
+
+class _Noise:
+    def __init__(self, seed):
+        self.rng = np.random.default_rng(seed)
+
+    def __call__(self, r):
+        return 1e3 * np.abs(r).max() * (self.rng.standard_normal(r.shape) + 1j * self.rng.standard_normal(r.shape))
+
+
+def test_exact_network_never_probes():
+    prob = _problem()
+    b = inputs.point_source(N, 3)
+    _, its_mg, _, _ = H.solve_mg(prob, b)
+    st = {}
+    x, its, _, rel = S.solve_two_phase(prob, _Exact(prob), b, stats=st)
+    assert rel <= 1e-6 and its < its_mg / 2
+    assert st == {"fell_back": False, "probes": 0}
+    assert np.linalg.norm(b - prob.A(x)) / np.linalg.norm(b) <= 1e-6
+
+
+def test_noisy_network_falls_back_to_mg_after_one_probe():
+    prob = _problem()
+    b = inputs.point_source(N, 4)
+    _, its_mg, _, rel_mg = H.solve_mg(prob, b)
+    st = {}
+    _, its, _, rel = S.solve_two_phase(prob, _Noise(1), b, stats=st)
+    assert rel <= 1e-6 and rel_mg <= 1e-6
+    assert st["fell_back"] and st["probes"] == 1
+    # 3 warm + one stalled CNN+MG cycle, then MG-only from (about) where it was
+    assert its <= its_mg + 2 * 10
+
+
+def test_without_the_judge_the_noisy_network_costs_far_more():
+    prob = _problem()
+    b = inputs.point_source(N, 4)
+    _, its_fb, _, _ = S.solve_two_phase(prob, _Noise(1), b)
+    _, its_no, _, _ = S.solve_two_phase(prob, _Noise(1), b, fallback=False, max_iters=4 * its_fb)
+    assert its_no >= 2 * its_fb
