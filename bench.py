@@ -12,7 +12,9 @@ right-hand sides already resident in HBM.
 Prints one JSON line.  Options:
   --gpus N (only 1 is supported: the path runs on one GPU), --steps K, --warmup W
   --precond {auto,mg,cnn_mg}: auto = CNN+MG when a trained network file exists
+  --mg-steps M: timed MG-only solves of the same workload for the comparison (default 1, 0 = skip)
   --no-cpu-baseline: skip the bounded CPU oracle timing
+  --copy-mib S: first copy an S MiB buffer once (a plain-copy reference for HBM counters)
 """
 from __future__ import annotations
 
@@ -29,9 +31,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Helmholtz solves/s to rel. residual 1e-6 at 1024², CNN+MG vs MG-only FGMRES"
-NET_FILE = os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256.bin")
+NET_FILE = os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256_512.bin")
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix, published
 
 # Algorithmic HBM bytes per grid point and right-hand side of one launch of the
 # single-kernel classes (complex single = 8 B; coefficients shared by all RHS
@@ -47,47 +50,86 @@ _THREAD_VARS = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "B
 
 
 def _cpu_worker(args):
-    n, seed_k, seed_b, iters = args
+    """Seconds per FGMRES iteration of the FP64 oracle on this workload: MG-only
+    iterations and (with a network file) CNN+MG iterations, one RHS."""
+    n, seed_k, seed_b, mg_iters, net_file = args
     for v in _THREAD_VARS:
         os.environ[v] = "1"
-    import numpy as np  # noqa: F401
+    from oracle import cnn as C
     from oracle import helmholtz as H
-    from paper_2306_17486_amd import inputs
+    from oracle import solver as S
+    from paper_2306_17486_amd import inputs, netfile
     k = inputs.layered_slowness(n, seed_k)
     prob = H.Problem(k, inputs.omega_for(n, k))
     b = inputs.point_source(n, seed_b)
     t = time.perf_counter()
-    H.fgmres(prob.A, b, prob.mg, None, 10, 1e-6, iters)
-    return (time.perf_counter() - t) / iters
+    x, _, _, _ = H.fgmres(prob.A, b, prob.mg, None, 10, 1e-6, mg_iters)
+    s_mg = (time.perf_counter() - t) / mg_iters
+    s_cnn = None
+    if net_file:
+        flat, ch = netfile.read_params(net_file)
+        netp = S.NetPrecond(C.Net(netfile.unflatten_params(flat, ch)), prob)  # encoder: once per medium
+        t = time.perf_counter()
+        H.fgmres(prob.A, b, lambda v: S.cnn_mg_precond(prob, netp, v), x, 10, 1e-6, mg_iters + 1,
+                 iters_done=mg_iters)
+        s_cnn = time.perf_counter() - t
+    return s_mg, s_cnn
 
 
-def cpu_sample(n, nrhs, sample_iters):
-    """Time the FP64 oracle (MG-only FGMRES) on the host cores, one RHS per
-    process, `sample_iters` iterations each.  Runs before the GPU is touched
-    (child processes are started from a process without GPU state)."""
+def cpu_sample(n, nrhs, mg_iters, net_file):
+    """Time the FP64 oracle on the host cores, one RHS per single-threaded
+    process: `mg_iters` MG-only iterations and, with a network, one CNN+MG
+    iteration.  Runs before the GPU is touched (child processes are started
+    from a process without GPU state)."""
     cores = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1), 16, nrhs)
-    # one single-threaded process per core (children inherit this environment)
     for v in _THREAD_VARS:
         os.environ[v] = "1"
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    per_it = []
+    res = []
     with ctx.Pool(cores) as pool:
-        for v in pool.imap_unordered(_cpu_worker, [(n, 2000, 3000 + i, sample_iters) for i in range(cores)]):
-            per_it.append(v)
-            print(f"bench: cpu sample {len(per_it)}/{cores}: {v:.3f} s/iteration", file=sys.stderr, flush=True)
+        for v in pool.imap_unordered(_cpu_worker, [(n, 2000, 3000 + i, mg_iters, net_file) for i in range(cores)]):
+            res.append(v)
+            print(f"bench: cpu sample {len(res)}/{cores}: MG-only {v[0]:.3f} s/iteration"
+                  + (f", CNN+MG {v[1]:.2f} s/iteration" if v[1] is not None else ""), file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
-    return cores, sum(per_it) / len(per_it), wall
+    s_mg = sum(r[0] for r in res) / len(res)
+    s_cnn = sum(r[1] for r in res) / len(res) if res[0][1] is not None else None
+    return cores, s_mg, s_cnn, wall
 
 
-def cpu_baseline(sample, n, sample_iters, iters_per_solve):
-    """solves/s of the oracle, extrapolated as cores / (s per iteration * iterations per solve)."""
-    cores, s_it, wall = sample
-    value = cores / (s_it * iters_per_solve)
-    return {"value": value, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{cores} RHS x {sample_iters} MG-only FGMRES iterations of the {n}^2 workload "
-                      f"(one process per core, FP64 NumPy/SciPy oracle); {s_it:.3f} s/iteration, extrapolated "
-                      f"to {iters_per_solve:.0f} iterations per solve; wall {wall:.1f} s"}
+def cpu_baseline(sample, n, mg_iters, iters_mg, iters_cnn):
+    """solves/s of the oracle on the same workload: cores / (seconds per solve),
+    a solve costing the GPU run's mean iteration counts (MG-only iterations at
+    the MG-only rate, CNN+MG iterations at the CNN+MG rate)."""
+    cores, s_mg, s_cnn, wall = sample
+    per_solve = iters_mg * s_mg + (iters_cnn * s_cnn if iters_cnn else 0.0)
+    what = f"{mg_iters} MG-only FGMRES iterations" + (" and 1 CNN+MG iteration" if s_cnn is not None else "")
+    return {"value": cores / per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} RHS x ({what}) of the {n}^2 workload, one single-threaded process per core, FP64 "
+                      f"NumPy/SciPy oracle: {s_mg:.3f} s per MG-only iteration"
+                      + (f", {s_cnn:.1f} s per CNN+MG iteration" if s_cnn is not None else "")
+                      + f"; extrapolated to {iters_mg:.0f} MG-only + {iters_cnn or 0:.0f} CNN+MG iterations per "
+                        f"solve (the GPU run's means); wall {wall:.1f} s"}
+
+
+def network_flops(n: int) -> float:
+    """FLOPs of the BF16 MFMA convolutions of one solver-network application
+    (encoder excluded: it runs once per slowness model).  A convolution costs
+    2 * 9 * cin * cout per output pixel, a transposed one per input pixel; the
+    FP32 input (2 -> 16) and projection (16 -> 2) layers are not counted."""
+    from paper_2306_17486_amd import inputs
+    nc = n // 16 if n >= 512 else n // 8
+    out_size = {"s1": n // 2, "s2": n // 4, "s3": n // 8, "s4": nc, "u3": n // 8, "u2": n // 4, "u1": n // 2}
+    tin_size = {"u3": nc, "u2": n // 8, "u1": n // 4}
+    f = 0.0
+    for name, kind, cin, cout in inputs.net_layers((16, 32, 64, 64)):
+        lvl = name.split("_")[0]
+        if lvl.startswith("enc") or name in ("s1_d", "out"):
+            continue
+        pix = tin_size[lvl] ** 2 if kind in ("t", "t4") else out_size[lvl] ** 2
+        f += 2.0 * 9 * cin * cout * pix
+    return f
 
 
 def main():
@@ -101,16 +143,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--max-iters", type=int, default=10000)
+    ap.add_argument("--mg-steps", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=0)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {a.gpus} is not supported "
               f"(the right-hand sides shard across GPUs with no communication, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
+    use_cnn = a.precond == "cnn_mg" or (a.precond == "auto" and os.path.exists(NET_FILE))
     sample = None
     if not a.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        sample = cpu_sample(a.n, a.nrhs, a.cpu_iters)
+        sample = cpu_sample(a.n, a.nrhs, a.cpu_iters, NET_FILE if use_cnn else None)
 
     import numpy as np
     import torch
@@ -124,46 +169,59 @@ def main():
     model = hh.Model(ctx, torch.from_numpy(k), omega)
     b = torch.from_numpy(np.stack([inputs.point_source(n, 3000 + i) for i in range(nrhs)])).to(dev, torch.complex64)
     precond = hh.HH_PRECOND_MG
-    use_cnn = a.precond == "cnn_mg" or (a.precond == "auto" and os.path.exists(NET_FILE))
     if use_cnn:
         net = hh.Net.load(ctx, NET_FILE)
         model.attach_net(net)
         precond = hh.HH_PRECOND_CNN_MG
 
-    def one_solve():
-        # a cap far above the need, so that every right-hand side reaches 1e-6
-        return model.solve(b, precond=precond, max_iters=a.max_iters, want_hist=False)
-
     def say(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    if a.copy_mib > 0:
+        # reference for the HBM traffic counters: one plain device copy of known size
+        src = torch.empty(a.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def timed(prec, steps, warmup, label):
+        def one_solve():
+            # a cap far above the need, so that every right-hand side reaches 1e-6
+            return model.solve(b, precond=prec, max_iters=a.max_iters, want_hist=False)
+
+        for w in range(warmup):
+            t = time.perf_counter()
+            _, info = one_solve()
+            say(f"bench: {label} warmup {w} done in {time.perf_counter() - t:.2f} s, "
+                f"iterations {int(info['iters'].max())}")
+        torch.cuda.synchronize()
+        ctx.profile_begin()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for st in range(steps):
+            _, info = one_solve()
+            infos.append(info)
+            say(f"bench: {label} step {st} done at {time.perf_counter() - t0:.2f} s")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = ctx.profile_end()
+        cat = {k: np.concatenate([i[k] for i in infos]) for k in ("iters", "converged", "final_res", "cnn_iters",
+                                                                 "mg_cycles")}
+        return elapsed, prof, cat
+
     say(f"bench: n={n} nrhs={nrhs} precond={'cnn_mg' if use_cnn else 'mg'}")
-    for w in range(a.warmup):
-        t = time.perf_counter()
-        _, info = one_solve()
-        say(f"bench: warmup {w} done in {time.perf_counter() - t:.2f} s, iterations {int(info['iters'].max())}")
-    torch.cuda.synchronize()
-    ctx.profile_begin()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for st in range(a.steps):
-        x, info = one_solve()
-        infos.append(info)
-        say(f"bench: step {st} done at {time.perf_counter() - t0:.2f} s")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile_end()
-    iters = np.concatenate([i["iters"] for i in infos])
-    conv = np.concatenate([i["converged"] for i in infos])
-    fres = np.concatenate([i["final_res"] for i in infos])
+    elapsed, prof, res = timed(precond, a.steps, a.warmup, "cnn_mg" if use_cnn else "mg")
+    iters, conv, fres = res["iters"], res["converged"], res["final_res"]
     # only right-hand sides whose FP64 residual reached 1e-6 count as solves
     value = float(conv.sum()) / elapsed
 
-    # roofline of the dominant single-kernel class (largest summed time).
-    # Algorithmic bytes = (sum over RHS of their iterations) x N x bytes per point
-    # and RHS, plus the shared coefficients (8 B per point) once per launch.
-    # Inactive right-hand sides exit at once and are not counted.
+    # per kernel class: algorithmic bytes (HBM-bound classes) or FLOPs (MFMA
+    # convolutions) over the class's summed HIP-event time.  Bytes = (sum over
+    # RHS of their iterations) x N x bytes per point and RHS, plus the shared
+    # coefficients once per launch; inactive right-hand sides exit at once and
+    # are not counted.
     N = n * n
     mean_it = float(iters.mean())
     rhs_iters = float(iters.sum())
@@ -172,22 +230,41 @@ def main():
     per_pt = {"op_dots": 16 + 8 * mean_jp1, "ortho": 16 + 8 * mean_jp1, "vc_down": 8 + 2, "vc_up": 8 + 2 + 8,
               # coarse solve per RHS: b read twice, y written and read, x written (5 coarse vectors)
               "vc_coarse": 5 * 8 * mc * mc / N}
+    # with the network's initial guess the down kernel also reads x0 and writes the
+    # relaxed x1, and the up kernel reads x1 back
+    per_pt_cnn = dict(per_pt, vc_down=8 + 8 + 8 + 2, vc_up=8 + 2 + 8 + 8)
+    cnn_rhs_iters = float(res["cnn_iters"].sum())
     # per launch, shared by all RHS: coefficients; for the coarse solve the m
     # Schur inverses (m^2 complex each) streamed once per sweep
     coef_pt = {"op_dots": 8, "ortho": 0, "vc_down": 8, "vc_up": 8, "vc_coarse": 2 * mc ** 3 * 8 / N}
+    cnn_apps = float(res["cnn_iters"].sum())
+    net_flops = network_flops(n)
+    classes = {}
+    for kname, (ms, cnt) in prof.items():
+        if cnt == 0 or ms <= 0:
+            continue
+        if kname in per_pt:
+            total = ((rhs_iters - cnn_rhs_iters) * per_pt[kname] + cnn_rhs_iters * per_pt_cnn[kname]) * N \
+                + cnt * N * coef_pt[kname]
+            ach = total / (ms / 1e3) / 1e9
+            classes[kname] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                              "avg_launch_us": round(ms / cnt * 1e3, 1),
+                              "algorithmic_bytes_per_launch": int(total / cnt), "ms": round(ms, 2),
+                              "launches": cnt}
+        elif kname == "conv" and cnn_apps > 0:
+            total = cnn_apps * net_flops
+            ach = total / (ms / 1e3) / 1e12
+            classes[kname] = {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                              "avg_launch_us": round(ms / cnt * 1e3, 1),
+                              "algorithmic_flops_per_launch": int(total / cnt), "ms": round(ms, 2),
+                              "launches": cnt}
+        else:
+            classes[kname] = {"ms": round(ms, 2), "launches": cnt}
     ranked = sorted(((v[0], kname) for kname, v in prof.items()), reverse=True)
-    dom = next((kname for _, kname in ranked if kname in per_pt), None)
-    roof = None
-    if dom:
-        ms, cnt = prof[dom]
-        total_bytes = rhs_iters * N * per_pt[dom] + cnt * N * coef_pt[dom]
-        ach = total_bytes / (ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": round(ms / cnt * 1e3, 1),
-                "algorithmic_bytes_per_launch": int(total_bytes / cnt),
-                "bytes_per_point_per_rhs": per_pt[dom]}
-    kt = {kname: {"ms": round(v[0], 2), "launches": v[1]} for kname, v in prof.items()}
+    dom = next((kname for _, kname in ranked if "bound" in classes.get(kname, {})), None)
+    roof = dict(classes[dom], kernel=dom) if dom else None
 
     out = {
         "metric": METRIC,
@@ -210,10 +287,31 @@ def main():
         "converged": f"{int(conv.sum())}/{conv.size}",
         "max_final_rel_residual": float(fres.max()),
         "roofline": roof,
-        "kernel_ms": kt,
+        "kernels": classes,
     }
+    if use_cnn:
+        out["cnn_iterations_mean"] = float(res["cnn_iters"].mean())
+        out["mg_only_cycles_mean"] = float(res["mg_cycles"].mean())
+        if a.mg_steps > 0:
+            say("bench: MG-only comparison")
+            el_mg, _, rmg = timed(hh.HH_PRECOND_MG, a.mg_steps, 0, "mg")
+            v_mg = float(rmg["converged"].sum()) / el_mg
+            out["mg_only"] = {"value": round(v_mg, 4), "unit": "solves/s", "steps": a.mg_steps,
+                              "ms_per_step": round(1e3 * el_mg / a.mg_steps, 2),
+                              "iterations": {"mean": float(rmg["iters"].mean()), "min": int(rmg["iters"].min()),
+                                             "max": int(rmg["iters"].max())},
+                              "converged": f"{int(rmg['converged'].sum())}/{rmg['converged'].size}",
+                              "max_iters_cap": a.max_iters}
+            out["speedup_vs_mg_only"] = round(value / v_mg, 3) if v_mg > 0 else None
     if sample is not None:
-        out["cpu_baseline"] = cpu_baseline(sample, n, a.cpu_iters, mean_it)
+        if use_cnn:
+            cnn_it = float(res["cnn_iters"].mean())
+            out["cpu_baseline"] = cpu_baseline(sample, n, a.cpu_iters, mean_it - cnn_it, cnn_it)
+            if "mg_only" in out:
+                out["mg_only"]["cpu_baseline"] = cpu_baseline(sample, n, a.cpu_iters,
+                                                              out["mg_only"]["iterations"]["mean"], 0.0)
+        else:
+            out["cpu_baseline"] = cpu_baseline(sample, n, a.cpu_iters, mean_it, 0.0)
     print(json.dumps(out), flush=True)
 
 

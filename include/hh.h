@@ -117,11 +117,14 @@ typedef struct {
     int use_x0;         /* 1: x_dev holds the initial guess; 0: start from zero */
     int fixed_iters;    /* >0: run exactly this many iterations (single cycle, no
                            convergence test); used to generate training data (eq. 20) */
-    int fallback;       /* CNN_MG only, default 1: MG-only FGMRES judges the network per
-                           RHS.  A restart cycle that cuts the FP64 residual by less than
-                           probe_ratio is followed by one MG-only cycle; if that cycle cuts
-                           it more, the RHS finishes with MG-only, otherwise it returns to
-                           CNN+MG and the wait before its next probe doubles. */
+    int fallback;       /* CNN_MG only, default 1: per RHS, MG-only FGMRES judges the
+                           network and the network judges MG-only.  A restart cycle that
+                           cuts the FP64 residual by less than probe_ratio (end / start
+                           above it) is followed by one cycle with the other preconditioner;
+                           that one takes over if its cycle cut the residual more, otherwise
+                           the previous one resumes and the wait before the next probe
+                           doubles (2, 4, 8, ... cycles; a switch resets it).  0: CNN+MG
+                           in every cycle after the warm start. */
     double probe_ratio; /* default 0.5 */
 } hh_solve_opts;
 
@@ -136,14 +139,16 @@ void hh_solve_opts_default(hh_solve_opts* o);
  *              value); entries past the last iteration are set to -1
  *   iters_host, converged_host: optional int [nrhs]
  *   final_res_host: optional double [nrhs]: ||b - A x|| / ||b|| recomputed in FP64
- *   fellback_host: optional int [nrhs]: 1 where a CNN_MG solve switched to MG-only
+ *   mg_cycles_host: optional int [nrhs]: restart cycles after the warm start that a
+ *              CNN_MG solve ran with MG-only (judge probes and switches)
+ *   cnn_iters_host: optional int [nrhs]: iterations preconditioned by CNN+MG
  * The stencil, V-cycle and network run in single precision / BF16; the
  * Gram-Schmidt sums, the Hessenberg least-squares problem, x and the restart
  * residual are FP64.  Returns HH_NOT_CONVERGED if any RHS stopped at
  * max_iters above rtol.  Synchronises the stream. */
 hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
                    void* x_dev, const hh_solve_opts* o, double* res_hist_host, int* iters_host,
-                   int* converged_host, double* final_res_host, int* fellback_host);
+                   int* converged_host, double* final_res_host, int* mg_cycles_host, int* cnn_iters_host);
 
 /* ------------------------------------------------------------------------
  * Building blocks exposed for parity tests (same kernels as the solve).
@@ -213,13 +218,15 @@ hh_status hh_gen_training_pairs(hh_ctx* ctx, hh_model* m, int nb, const void* x_
 
 /* One training step on B pairs (r, e) (c64 [B][n][n]), sample b on slowness
  * model b of md (md->ninst == B), n a power of two from 64 to 512: BF16 forward and backward through
- * encoder, solver and implicit layer, loss (eq. 19)
- *   L = (1/B) sum_b || P(Net(r_b / rms(r_b))) - e_b / s_b ||^2,  s_b = h^2 rms(r_b),
- * FP32 gradients (hh_net_get_grads), then one Adam step with learning rate lr
- * (betas 0.9, 0.999, eps 1e-8; lr = 0 computes the gradients only).
- * *loss_out receives L before the update.  Synchronises the stream. */
+ * encoder, solver and implicit layer, loss (eq. 19 as a mean over samples and grid points)
+ *   L = 1/(B n^2) sum_b || P(Net(r_b / rms(r_b))) - e_b / s_b ||^2,  s_b = h^2 rms(r_b),
+ * FP32 gradients (hh_net_get_grads, unclipped), then one Adam step with learning
+ * rate lr (betas 0.9, 0.999, eps 1e-8; lr = 0 computes the gradients only) on the
+ * gradient scaled by min(1, max_grad_norm / ||g||) (max_grad_norm = 0: no clipping).
+ * *loss_out receives L before the update, *grad_norm_out (may be NULL) ||g||.
+ * Synchronises the stream. */
 hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev, double lr,
-                        double* loss_out);
+                        double max_grad_norm, double* loss_out, double* grad_norm_out);
 /* The loss L of hh_train_step (same arguments and rules) without the backward
  * pass: no gradient, parameter or optimiser state changes.  For validation. */
 hh_status hh_eval_loss(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev,

@@ -378,10 +378,14 @@ def residual_scale(r: np.ndarray, h: float) -> np.ndarray:
 
 
 def mse_loss(out, target):
-    """Eq. 19: (1/m) sum_i ||out_i - target_i||^2 over real and imaginary channels."""
+    """Eq. 19 as a mean squared error over the m samples and the N grid points:
+    (1 / (m N)) sum_i ||out_i - target_i||^2, summing real and imaginary parts.
+    (Averaging over the points keeps the loss of different grid sizes on one
+    scale for multiscale training.)  Returns the loss and its gradient."""
     B = out.shape[0]
+    N = out.shape[2] * out.shape[3]
     d = out - target
-    return float(np.sum(d * d) / B), 2.0 * d / B
+    return float(np.sum(d * d) / (B * N)), 2.0 * d / (B * N)
 
 
 def preconditioner_net(net: Net, r: np.ndarray, kin: np.ndarray, h: float) -> np.ndarray:

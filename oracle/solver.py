@@ -44,42 +44,46 @@ def solve_two_phase(prob: H.Problem, netp: NetPrecond, b: np.ndarray, rtol=1e-6,
     """Sec. 4.1: a few MG-only FGMRES iterations, then FGMRES(restart) with the
     CNN+MG preconditioner from that iterate.  Iterations of both phases count.
 
-    With ``fallback``, MG-only FGMRES judges the network, one restart cycle at a
-    time (the reading of the method used here; the paper gives no rule): a
-    CNN+MG cycle whose true residual ratio (end / start) exceeds probe_ratio is
-    followed by one MG-only cycle.  If that probe cycle reduces the residual
-    more than the CNN+MG cycle did, the solve finishes with MG-only; otherwise
-    it returns to CNN+MG, and the number of CNN+MG cycles before the next
-    probe may run doubles (2, 4, 8, ...).  ``stats`` (a dict, optional)
-    receives ``fell_back`` and ``probes``."""
+    With ``fallback`` the two preconditioners judge each other, one restart
+    cycle at a time (the reading of the method used here; the paper gives no
+    rule): a cycle whose true residual ratio (end / start) exceeds
+    probe_ratio is followed by one cycle with the other preconditioner
+    (CNN+MG <-> MG-only).  If that probe cycle reduces the residual more, its
+    preconditioner takes over; otherwise the previous one resumes, and the
+    number of cycles before the next probe may run doubles (2, 4, 8, ...; a
+    switch resets it).  ``stats`` (a dict, optional) receives ``probes`` and
+    ``mg_cycles`` (cycles after the warm start run with MG-only)."""
     x, its, hist, rel = H.fgmres(prob.A, b, prob.mg, None, restart, rtol, warm_iters)
-    mode, q_cnn, wait, gap, probes = "cnn", None, 0, 0, 0
+    cnn = lambda v: cnn_mg_precond(prob, netp, v)  # noqa: E731
+    cur, probing, q_base, wait, gap, probes, mg_cycles = "cnn", False, None, 0, 0, 0, 0
     while rel > rtol and its < max_iters:
-        if mode == "cnn":
-            M = lambda v: cnn_mg_precond(prob, netp, v)  # noqa: E731
-        else:
-            M = prob.mg
+        if cur == "mg":
+            mg_cycles += 1
         rel0 = rel
-        x, its, h, rel = H.fgmres(prob.A, b, M, x, restart, rtol, max_iters, iters_done=its, cycles=1)
+        x, its, h, rel = H.fgmres(prob.A, b, cnn if cur == "cnn" else prob.mg, x, restart, rtol, max_iters,
+                                  iters_done=its, cycles=1)
         hist = hist + h[1:]
         q = rel / rel0
-        if mode == "cnn":
-            q_cnn = q
-            if fallback and q > probe_ratio and wait <= 0:
-                mode = "probe"
-                probes += 1
-            elif wait > 0:
-                wait -= 1
-        elif mode == "probe":
-            if q < q_cnn:
-                mode = "mg"
+        other = "mg" if cur == "cnn" else "cnn"
+        if probing:
+            probing = False
+            if q < q_base:
+                gap, wait = 0, 0
             else:
                 gap = 2 * gap if gap > 0 else 2
                 wait = gap
-                mode = "cnn"
+                cur = other
+        else:
+            q_base = q
+            if fallback and q > probe_ratio and wait <= 0:
+                probing = True
+                probes += 1
+                cur = other
+            elif wait > 0:
+                wait -= 1
     if stats is not None:
-        stats["fell_back"] = mode == "mg"
         stats["probes"] = probes
+        stats["mg_cycles"] = mg_cycles
     return x, its, hist, rel
 
 

@@ -207,7 +207,7 @@ void hh_solve_opts_default(hh_solve_opts* o) {
 
 hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev, void* x_dev,
                    const hh_solve_opts* o, double* res_hist_host, int* iters_host, int* converged_host,
-                   double* final_res_host, int* fellback_host) {
+                   double* final_res_host, int* mg_cycles_host, int* cnn_iters_host) {
     HH_ARG(ctx && m && b_dev && x_dev && o, "null pointer");
     HH_ARG(m->ctx == ctx, "model belongs to another context");
     HH_ARG(nrhs >= 1, "nrhs >= 1");
@@ -247,7 +247,8 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
         if (iters_host) iters_host[r] = hs[r].iters;
         if (converged_host) converged_host[r] = hs[r].converged;
         if (final_res_host) final_res_host[r] = hs[r].res_true;
-        if (fellback_host) fellback_host[r] = hs[r].fellback;
+        if (mg_cycles_host) mg_cycles_host[r] = hs[r].mg_cycles;
+        if (cnn_iters_host) cnn_iters_host[r] = hs[r].cnn_iters;
         all_conv = all_conv && hs[r].converged;
         broke = broke || hs[r].breakdown;
     }

@@ -18,13 +18,16 @@ struct KState {
     int k, iters, converged, breakdown;
     int ended_by_est;
     int mode;                   // preconditioner of the current cycle (PM_*)
-    int probe_wait, probe_gap;  // CNN+MG cycles before the next MG probe may run, and the next wait
-    int fellback, pad_;         // 1 once the RHS has switched to MG-only for good
+    int probing;                // 1: the current cycle probes the other preconditioner
+    int probe_wait, probe_gap;  // cycles before the next probe may run, and the next wait
+    int mg_cycles;              // MG-only cycles after the warm start (probes included)
+    int cnn_iters;              // iterations preconditioned by CNN+MG
+    int pad_;
     double res_cycle0;          // true relative residual at the start of the current cycle
-    double q_cnn;               // residual reduction of the last CNN+MG cycle
+    double q_base;              // residual reduction of the last cycle of the preconditioner in use
 };
 // Preconditioner of a restart cycle of a CNN+MG solve (per RHS).
-enum { PM_WARM = 0, PM_CNN = 1, PM_PROBE = 2, PM_MG = 3 };
+enum { PM_WARM = 0, PM_CNN = 1, PM_MG = 2 };
 static_assert(sizeof(KState) % 8 == 0, "KState must be a whole number of doubles");
 
 // Device workspace of one solve (grown on demand, reused across calls).

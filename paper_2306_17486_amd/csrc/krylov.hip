@@ -124,6 +124,8 @@ __global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ 
 // w = A z (FP32) written to V[j+1]; partial dots <v~_i, w>, i = 0..j: each
 // thread sums its 4 points in FP32, the block and grid sums are FP64.  The
 // read set (z, v_0..v_j) and the write set (v_{j+1}) do not overlap.
+// Launched with NJ = j + 1: every per-thread array is indexed by compile-time
+// constants only, so it stays in registers.
 template <int NJ>
 __global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, size_t zstride,
                                                  const float2* __restrict__ Vin, float2* __restrict__ Vout,
@@ -140,7 +142,6 @@ __global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, s
     const float2* zr = Z + r * zstride;
     const float2* Vr = Vin + r * vstride;
     const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
-    const int nact = j + 1;
     float2 pacc[NJ];
 #pragma unroll
     for (int q = 0; q < NJ; ++q) pacc[q] = make_float2(0.f, 0.f);
@@ -165,12 +166,10 @@ __global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, s
             wout[o] = w;
 #pragma unroll
             for (int q = 0; q < NJ; ++q) {
-                if (q < nact) {
-                    const float2 v = Vr[(size_t)q * nn + o];
-                    // conj(v) * w
-                    pacc[q].x += v.x * w.x + v.y * w.y;
-                    pacc[q].y += v.x * w.y - v.y * w.x;
-                }
+                const float2 v = Vr[(size_t)q * nn + o];
+                // conj(v) * w
+                pacc[q].x += v.x * w.x + v.y * w.y;
+                pacc[q].y += v.x * w.y - v.y * w.x;
             }
             up = cur;
             cur = dn;
@@ -179,10 +178,11 @@ __global__ void __launch_bounds__(256) k_op_dots(const float2* __restrict__ Z, s
     double2 acc[NJ];
 #pragma unroll
     for (int q = 0; q < NJ; ++q) acc[q] = make_double2((double)pacc[q].x, (double)pacc[q].y);
-    block_sum2<NJ>(acc, nact, s_red);
+    block_sum2<NJ>(acc, NJ, s_red);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         double2* p = parts + ((size_t)r * npart + blockIdx.y * gridDim.x + blockIdx.x) * MAXV;
-        for (int q = 0; q < nact; ++q) p[q] = acc[q];
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) p[q] = acc[q];
     }
 }
 
@@ -311,6 +311,7 @@ __global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ part
     }
     S.k = j + 1;
     S.iters += 1;
+    if (S.mode == PM_CNN) S.cnn_iters += 1;
     const double est = sqrt(zabs2(S.g[j + 1])) / S.bnorm;
     S.res_est = est;
     if (hist && S.iters < hist_len) hist[(size_t)r * hist_len + S.iters] = est;
@@ -374,34 +375,36 @@ __global__ void k_init_state(const double2* __restrict__ parts, int npart, KStat
         for (int q = 0; q < hist_len; ++q) hist[(size_t)r * hist_len + q] = -1.0;
 }
 
-// Preconditioner of the next restart cycle of a CNN+MG solve, with MG-only
-// FGMRES as the judge: a CNN+MG cycle that reduces the FP64 residual by less
-// than probe_ratio is followed by one MG-only probe cycle; if the probe reduces
-// the residual more than the CNN+MG cycle did, the RHS stays on MG-only for the
-// rest of the solve, otherwise it returns to CNN+MG and waits twice as many
-// cycles before it may be probed again.
-__device__ static int next_mode(KState& S, int warm, int fallback, double probe_ratio) {
+// Preconditioner of the next restart cycle of a CNN+MG solve: MG-only FGMRES
+// judges the network, and the network judges MG-only.  A cycle that reduces
+// the FP64 residual by less than probe_ratio (end / start above it) is
+// followed by one probe cycle of the other preconditioner; the probe's
+// preconditioner takes over if its cycle reduced the residual more, otherwise
+// the previous one resumes and the wait before the next probe doubles
+// (2, 4, 8, ... cycles; a switch resets it).
+__device__ static int next_mode(KState& S, int warm, int judge, double probe_ratio) {
     if (warm) return PM_WARM;
+    if (S.mode == PM_WARM) return PM_CNN;
     const double q = S.res_cycle0 > 0.0 ? S.res_true / S.res_cycle0 : 0.0;
-    switch (S.mode) {
-        case PM_WARM:
-            return PM_CNN;
-        case PM_CNN:
-            S.q_cnn = q;
-            if (fallback && q > probe_ratio && S.probe_wait <= 0) return PM_PROBE;
-            if (S.probe_wait > 0) S.probe_wait--;
-            return PM_CNN;
-        case PM_PROBE:
-            if (q < S.q_cnn) {
-                S.fellback = 1;
-                return PM_MG;
-            }
-            S.probe_gap = S.probe_gap > 0 ? 2 * S.probe_gap : 2;
-            S.probe_wait = S.probe_gap;
-            return PM_CNN;
-        default:
-            return PM_MG;
+    const int cur = S.mode, other = cur == PM_CNN ? PM_MG : PM_CNN;
+    if (S.probing) {
+        S.probing = 0;
+        if (q < S.q_base) {
+            S.probe_gap = 0;
+            S.probe_wait = 0;
+            return cur;
+        }
+        S.probe_gap = S.probe_gap > 0 ? 2 * S.probe_gap : 2;
+        S.probe_wait = S.probe_gap;
+        return other;
     }
+    S.q_base = q;
+    if (judge && q > probe_ratio && S.probe_wait <= 0) {
+        S.probing = 1;
+        return other;
+    }
+    if (S.probe_wait > 0) S.probe_wait--;
+    return cur;
 }
 
 // Start of a restart cycle: beta = ||r||, true relative residual, stopping test,
@@ -441,7 +444,10 @@ __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KSta
     for (int q = 0; q < MAXV; ++q) S.g[q] = make_double2(0.0, 0.0);
     S.g[0] = make_double2(beta, 0.0);
     S.k = 0;
-    if (cnn) S.mode = next_mode(S, warm, fallback, probe_ratio);
+    if (cnn) {
+        S.mode = next_mode(S, warm, fallback, probe_ratio);
+        if (S.mode == PM_MG) S.mg_cycles++;
+    }
     S.res_cycle0 = S.res_true;
     const int c = cnn && S.mode == PM_CNN;
     active[r] = 1;

@@ -1262,11 +1262,42 @@ __global__ void k_mask_add(const uint16_t* __restrict__ gin, const uint16_t* __r
 }
 
 // ---- Adam (Kingma & Ba), FP32 masters ------------------------------------
-__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, size_t N, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+// global gradient norm: per-block FP64 partial sums of g^2 ...
+constexpr int GN_BLOCKS = 256;  // one partial per thread of the single-block final reduction
+__global__ void __launch_bounds__(256) k_grad_norm_parts(const float* __restrict__ g, size_t N,
+                                                         double* __restrict__ parts) {
+    __shared__ double s_red[4];
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (size_t)GN_BLOCKS * 256)
+        acc += (double)g[i] * g[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) parts[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+// ... and out[0] = ||g||, out[1] = clip factor min(1, max_norm / ||g||) (1 when max_norm = 0);
+// the partials sit at out + 2
+__global__ void __launch_bounds__(256) k_grad_norm(double* __restrict__ out, double max_norm) {
+    __shared__ double s_red[4];
+    double acc = threadIdx.x < GN_BLOCKS ? out[2 + threadIdx.x] : 0.0;
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+        out[0] = nrm;
+        out[1] = (max_norm > 0.0 && nrm > max_norm) ? max_norm / nrm : 1.0;
+    }
+}
+
+// Adam on the FP32 masters with the gradient scaled by the clip factor gn[1]
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, const double* __restrict__ gn,
+                       float* __restrict__ m, float* __restrict__ v, size_t N, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2) {
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
-    const float gi = g[i];
+    const float gi = g[i] * (float)gn[1];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
@@ -1279,6 +1310,7 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 // ---------------------------------------------------------------------------
 struct TrainWork {
     NetActs acts;         // solver activations
+    Buf gn;               // gradient norm, clip factor, partial sums
     Buf enc[9];           // encoder activations
     Buf G[NET_LAYERS];    // gradients w.r.t. each layer's output (pre-activation for ReLU layers)
     Buf gimp;             // gradient w.r.t. the implicit layer's output
@@ -1332,21 +1364,27 @@ static hh_status dgrad_layer(hh_net* net, int l, int mode, const uint16_t* gout,
 
 using namespace hh;
 
-// sum of the per-block loss partials written by k_loss, divided by B
-static hh_status read_loss(hh_ctx* ctx, const Buf& lparts, int B, double* loss_out) {
+// loss = sum of the per-block partials written by k_loss / (B n^2); optionally
+// the gradient norm written by k_grad_norm
+static hh_status read_loss(hh_ctx* ctx, const Buf& lparts, int B, int n, const Buf* gn, double* loss_out,
+                           double* grad_norm_out) {
     std::vector<double> lp((size_t)B * 64);
+    double g[2] = {0.0, 1.0};
     HH_HIP(hipMemcpyAsync(lp.data(), lparts.ptr, lp.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (gn) HH_HIP(hipMemcpyAsync(g, gn->ptr, sizeof(g), hipMemcpyDeviceToHost, ctx->stream));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     double L = 0.0;
     for (double v : lp) L += v;
-    if (loss_out) *loss_out = L / B;
+    if (loss_out) *loss_out = L / ((double)B * n * n);
+    if (grad_norm_out) *grad_norm_out = g[0];
     return HH_OK;
 }
 
 // forward pass and loss on B pairs; with backward set, also every gradient and
-// (lr > 0) one Adam step
+// (lr > 0) one Adam step on the gradient clipped to max_grad_norm (0 = no clip)
 static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev,
-                            double lr, double* loss_out, bool backward) {
+                            double lr, double max_grad_norm, double* loss_out, double* grad_norm_out,
+                            bool backward) {
     HH_ARG(ctx && net && md && r_dev && e_dev, "null pointer");
     HH_ARG(net->ctx == ctx && md->ctx == ctx, "objects of another context");
     HH_ARG(B >= 1 && (md->ninst == B || md->ninst == 1), "model must hold one slowness model per sample (or one)");
@@ -1380,9 +1418,9 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
     // ---- loss and gradient at the projection layer
     const int m1 = n / 2, m2 = n / 4, m3 = n / 8, m4 = nc;
     hipLaunchKernelGGL(k_loss, dim3(64, B), dim3(256), 0, st, A.a[L_OUT].as<float2>(), (const float2*)e_dev, out_scale,
-                       T.gfull.as<float2>(), T.lparts.as<double>(), n, 1.f / B);
+                       T.gfull.as<float2>(), T.lparts.as<double>(), n, (float)(1.0 / ((double)B * n * n)));
     HH_LAUNCH_CHECK();
-    if (!backward) return read_loss(ctx, T.lparts, B, loss_out);
+    if (!backward) return read_loss(ctx, T.lparts, B, n, nullptr, loss_out, nullptr);
     hipLaunchKernelGGL(k_restrict4, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.gfull.as<float2>(),
                        T.go.as<float2>(), n);
     HH_LAUNCH_CHECK();
@@ -1553,6 +1591,13 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
                            count, GR + net->L[L_ENC1_D].woff, 1.f);
         HH_LAUNCH_CHECK();
     }
+    // ---- gradient norm and clip factor (device side, no host round trip)
+    HH_TRY(T.gn.ensure(ctx, (GN_BLOCKS + 2) * sizeof(double)));
+    hipLaunchKernelGGL(k_grad_norm_parts, dim3(GN_BLOCKS), dim3(256), 0, st, GR, net->nparams,
+                       T.gn.as<double>() + 2);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_grad_norm, dim3(1), dim3(256), 0, st, T.gn.as<double>(), max_grad_norm);
+    HH_LAUNCH_CHECK();
     // ---- Adam
     if (lr > 0.0) {
         if (!net->adam_m.ptr) {
@@ -1565,23 +1610,25 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
         const float b1 = 0.9f, b2 = 0.999f;
         const float bc1 = (float)(1.0 - pow(0.9, (double)net->step)), bc2 = (float)(1.0 - pow(0.999, (double)net->step));
         hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->nparams + 255) / 256)), dim3(256), 0, st,
-                           net->params.as<float>(), GR, net->adam_m.as<float>(), net->adam_v.as<float>(),
-                           net->nparams, (float)lr, b1, b2, 1e-8f, bc1, bc2);
+                           net->params.as<float>(), GR, T.gn.as<double>(), net->adam_m.as<float>(),
+                           net->adam_v.as<float>(), net->nparams, (float)lr, b1, b2, 1e-8f, bc1, bc2);
         HH_LAUNCH_CHECK();
         net->packed_valid = false;
         net->version++;
     }
-    return read_loss(ctx, T.lparts, B, loss_out);
+    return read_loss(ctx, T.lparts, B, n, &T.gn, loss_out, grad_norm_out);
 }
 
 extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev,
-                                   const void* e_dev, double lr, double* loss_out) {
-    return train_core(ctx, net, md, B, r_dev, e_dev, lr, loss_out, true);
+                                   const void* e_dev, double lr, double max_grad_norm, double* loss_out,
+                                   double* grad_norm_out) {
+    HH_ARG(max_grad_norm >= 0.0, "max_grad_norm >= 0");
+    return train_core(ctx, net, md, B, r_dev, e_dev, lr, max_grad_norm, loss_out, grad_norm_out, true);
 }
 
 extern "C" hh_status hh_eval_loss(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev,
                                   const void* e_dev, double* loss_out) {
-    return train_core(ctx, net, md, B, r_dev, e_dev, 0.0, loss_out, false);
+    return train_core(ctx, net, md, B, r_dev, e_dev, 0.0, 0.0, loss_out, nullptr, false);
 }
 
 // e = x - xt (xt complex double), single precision

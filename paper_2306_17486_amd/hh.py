@@ -76,7 +76,7 @@ hh_model_desc_default = _sig("hh_model_desc_default", None, C.POINTER(hh_model_d
 hh_model_create = _sig("hh_model_create", _I, _P, C.POINTER(hh_model_desc), _I, _P, C.POINTER(_P))
 hh_model_destroy = _sig("hh_model_destroy", _I, _P)
 hh_solve_opts_default = _sig("hh_solve_opts_default", None, C.POINTER(hh_solve_opts))
-hh_solve = _sig("hh_solve", _I, _P, _P, _I, _IP, _P, _P, C.POINTER(hh_solve_opts), _DP, _IP, _IP, _DP, _IP)
+hh_solve = _sig("hh_solve", _I, _P, _P, _I, _IP, _P, _P, C.POINTER(hh_solve_opts), _DP, _IP, _IP, _DP, _IP, _IP)
 hh_apply_operator = _sig("hh_apply_operator", _I, _P, _I, _D, _I, _IP, _P, _P)
 hh_apply_vcycle = _sig("hh_apply_vcycle", _I, _P, _I, _IP, _P, _P, _P)
 class hh_net_desc(C.Structure):
@@ -97,7 +97,7 @@ hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, 
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
 hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
 hh_gen_training_pairs = _sig("hh_gen_training_pairs", _I, _P, _P, _I, _P, _IP, _P, _P)
-hh_train_step = _sig("hh_train_step", _I, _P, _P, _P, _I, _P, _P, _D, _DP)
+hh_train_step = _sig("hh_train_step", _I, _P, _P, _P, _I, _P, _P, _D, _D, _DP, _DP)
 hh_eval_loss = _sig("hh_eval_loss", _I, _P, _P, _P, _I, _P, _P, _DP)
 hh_net_get_grads = _sig("hh_net_get_grads", _I, _P, _FP)
 hh_profile_begin = _sig("hh_profile_begin", _I, _P, _I)
@@ -267,52 +267,22 @@ class Model:
         iters = np.zeros(nrhs, dtype=np.int32)
         conv = np.zeros(nrhs, dtype=np.int32)
         fres = np.zeros(nrhs)
-        fb = np.zeros(nrhs, dtype=np.int32)
+        mgc = np.zeros(nrhs, dtype=np.int32)
+        cnnit = np.zeros(nrhs, dtype=np.int32)
         st = hh_solve(self.ctx.handle, self.handle, nrhs, _int_array(inst), _ptr(b), _ptr(x), C.byref(o),
                       hist.ctypes.data_as(_DP) if hist is not None else None, iters.ctypes.data_as(_IP),
-                      conv.ctypes.data_as(_IP), fres.ctypes.data_as(_DP), fb.ctypes.data_as(_IP))
+                      conv.ctypes.data_as(_IP), fres.ctypes.data_as(_DP), mgc.ctypes.data_as(_IP),
+                      cnnit.ctypes.data_as(_IP))
         check(st, allow=(HH_OK, HH_NOT_CONVERGED))
         return x, dict(iters=iters, converged=conv.astype(bool), final_res=fres, hist=hist, status=st,
-                       fell_back=fb.astype(bool))
+                       mg_cycles=mgc, cnn_iters=cnnit)
 
 
 # ---------------------------------------------------------------------------
 # network
 # ---------------------------------------------------------------------------
 
-NET_LAYER_NAMES = ["enc1_d", "enc1_c1", "enc1_c2", "enc2_d", "enc2_c1", "enc2_c2", "enc3_d", "enc3_c1", "enc3_c2",
-                   "s1_d", "s1_c1", "s1_c2", "s2_d", "s2_c1", "s2_c2", "s3_d", "s3_c1", "s3_c2",
-                   "s4_d", "s4_c1", "s4_c2", "u3_t", "u3_c1", "u3_c2", "u2_t", "u2_c1", "u2_c2",
-                   "u1_t", "u1_c1", "u1_c2", "out"]
-
-
-def flatten_params(p: dict, ch=(16, 32, 64, 64)) -> np.ndarray:
-    """Named parameters (weights, biases, complex implicit kernels) -> the flat
-    FP32 vector of include/hh.h (layer order, weights then biases, then K as re/im)."""
-    parts = []
-    for name in NET_LAYER_NAMES:
-        parts.append(np.asarray(p[name + ".w"], dtype=np.float64).ravel())
-        parts.append(np.asarray(p[name + ".b"], dtype=np.float64).ravel())
-    K = np.asarray(p["implicit_K"])
-    parts.append(np.stack([K.real, K.imag], axis=-1).ravel())
-    return np.concatenate(parts).astype(np.float32)
-
-
-def unflatten_params(flat: np.ndarray, ch=(16, 32, 64, 64)) -> dict:
-    from . import inputs
-    out = {}
-    off = 0
-    for name, kind, cin, cout in inputs.net_layers(ch):
-        shape = (cin, cout, 3, 3) if kind in ("t", "t4") else (cout, cin, 3, 3)
-        sz = int(np.prod(shape))
-        out[name + ".w"] = flat[off:off + sz].reshape(shape).astype(np.float64)
-        off += sz
-        out[name + ".b"] = flat[off:off + cout].astype(np.float64)
-        off += cout
-    nk = ch[3] // 2
-    k = flat[off:off + nk * 18].reshape(nk, 3, 3, 2).astype(np.float64)
-    out["implicit_K"] = k[..., 0] + 1j * k[..., 1]
-    return out
+from .netfile import NET_LAYER_NAMES, flatten_params, read_params, unflatten_params  # noqa: E402,F401
 
 
 class Net:
@@ -365,12 +335,15 @@ class Net:
         check(hh_net_get_grads(self.handle, a.ctypes.data_as(_FP)))
         return a
 
-    def train_step(self, model: "Model", r: torch.Tensor, e: torch.Tensor, lr: float) -> float:
+    def train_step(self, model: "Model", r: torch.Tensor, e: torch.Tensor, lr: float,
+                   max_grad_norm: float = 0.0) -> float:
+        """One training step; returns the loss (the gradient norm is kept in last_grad_norm)."""
         r = r.to(torch.complex64).contiguous()
         e = e.to(torch.complex64).contiguous()
-        loss = C.c_double()
+        loss, gnorm = C.c_double(), C.c_double()
         check(hh_train_step(self.ctx.handle, self.handle, model.handle, r.shape[0], _ptr(r), _ptr(e), lr,
-                            C.byref(loss)))
+                            max_grad_norm, C.byref(loss), C.byref(gnorm)))
+        self.last_grad_norm = gnorm.value
         return loss.value
 
     def eval_loss(self, model: "Model", r: torch.Tensor, e: torch.Tensor) -> float:

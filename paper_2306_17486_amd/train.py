@@ -14,6 +14,9 @@ library kernel).
   last quarter of the steps.  Below n = 512 the coarsest level keeps the size
   of the level above it, so only 512 trains the stride-2 coarsest layers that
   larger grids use.
+* Gradient clipping: the global gradient norm is clipped to `clip` times the
+  median of the recent norms, so one outlier batch (the switch to a new grid
+  size, a rare hard medium) cannot undo what the network has learned.
 * Validation: fixed held-out pairs per size, evaluated without updates.
 * Evaluation: FGMRES iterations to 1e-6 with MG-only, with the untrained
   network and with the trained one, on held-out media at several sizes.
@@ -111,8 +114,25 @@ def val_loss(net, items) -> float:
     return float(np.mean([net.eval_loss(m, r, e) for m, r, e in items]))
 
 
+class GradClip:
+    """Clip threshold = factor x the median of the last `window` gradient norms
+    (no clipping until `warmup` norms have been seen, or with factor 0)."""
+
+    def __init__(self, factor: float, window: int = 200, warmup: int = 20):
+        self.factor, self.window, self.warmup = factor, window, warmup
+        self.norms: list[float] = []
+
+    def threshold(self) -> float:
+        if self.factor <= 0 or len(self.norms) < self.warmup:
+            return 0.0
+        return self.factor * float(np.median(self.norms[-self.window:]))
+
+    def record(self, norm: float):
+        self.norms.append(norm)
+
+
 def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: int, nval: int, seed: int,
-          sizes=(128, 256)):
+          sizes=(128, 256), clip: float = 2.0):
     dev = f"cuda:{ctx.device}"
     plan_blocks = schedule(steps, block, sizes)
     plan = [plan_blocks[s // block] for s in range(steps)]
@@ -122,7 +142,9 @@ def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: in
     t0 = time.time()
     val = make_val_set(ctx, sizes, nval, batch, dev)
     _log(f"[train] validation set ({nval} pairs per size) in {time.time() - t0:.1f} s")
-    hist = {"step": [], "size": [], "loss": [], "lr": [], "val_step": [], "val": {str(n): [] for n in sizes}}
+    hist = {"step": [], "size": [], "loss": [], "lr": [], "grad_norm": [], "clipped": [], "val_step": [],
+            "val": {str(n): [] for n in sizes}}
+    clipper = GradClip(clip)
 
     def do_val(step):
         hist["val_step"].append(step)
@@ -146,7 +168,9 @@ def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: in
         x = torch.view_as_complex(torch.randn((batch, n, n, 2), generator=gen, device=dev))
         e, r = m.training_pairs(x, rng.integers(2, 9, batch).tolist())
         cur_lr = learning_rate(step, steps, lr)
-        loss = net.train_step(m, r, e, lr=cur_lr)
+        thr = clipper.threshold()
+        loss = net.train_step(m, r, e, lr=cur_lr, max_grad_norm=thr)
+        clipper.record(net.last_grad_norm)
         m.close()
         if not np.isfinite(loss):
             raise RuntimeError(f"training loss is not finite at step {step}")
@@ -154,11 +178,14 @@ def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: in
         hist["size"].append(n)
         hist["loss"].append(loss)
         hist["lr"].append(cur_lr)
+        hist["grad_norm"].append(net.last_grad_norm)
+        hist["clipped"].append(bool(thr > 0 and net.last_grad_norm > thr))
         run[n].append(loss)
         if (step + 1) % 50 == 0:
             el = time.time() - t0
             _log(f"[train] step {step + 1}/{steps} {n}^2 lr {cur_lr:.0e} loss(50) "
-                 f"{np.mean(hist['loss'][-50:]):.4e}  {el:.0f} s ({el / (step + 1) * 1e3:.0f} ms/step)")
+                 f"{np.mean(hist['loss'][-50:]):.4e} |g| {np.median(hist['grad_norm'][-50:]):.3e} "
+                 f"clipped {sum(hist['clipped'][-50:])}  {el:.0f} s ({el / (step + 1) * 1e3:.0f} ms/step)")
         if (step + 1) % val_every == 0 or step + 1 == steps:
             do_val(step + 1)
     hist["seconds"] = time.time() - t0
@@ -204,6 +231,7 @@ def main(argv=None):
     ap.add_argument("--val-every", type=int, default=250)
     ap.add_argument("--nval", type=int, default=256, help="validation pairs per size")
     ap.add_argument("--seed", type=int, default=4000)
+    ap.add_argument("--clip", type=float, default=2.0, help="clip at this multiple of the median gradient norm")
     ap.add_argument("--init-seed", type=int, default=0, help="seed of the initial parameters")
     ap.add_argument("--sizes", type=str, default="128,256", help="training grid sizes (128, 256, 512)")
     ap.add_argument("--eval-sizes", type=str, default="128,256,512")
@@ -223,7 +251,7 @@ def main(argv=None):
     if any(s not in SIZE_WEIGHT for s in sizes):
         sys.exit(f"training sizes must be among {sorted(SIZE_WEIGHT)}")
     hist = train(ctx, net, args.steps, args.batch, args.lr, args.block, args.val_every, args.nval, args.seed,
-                 sizes=sizes)
+                 sizes=sizes, clip=args.clip)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
     _log(f"[train] saved {args.out} after {hist['seconds']:.0f} s ({hist['steps_per_s']:.2f} steps/s)")

@@ -53,3 +53,24 @@ def test_argument_errors_are_reported_without_gpu():
     st = hh.hh_model_create(None, None, 1, None, None)
     assert st == hh.HH_ERR_ARG
     assert b"null pointer" in hh.hh_last_error()
+
+
+def test_parameter_vector_round_trip_and_size():
+    import numpy as np
+    from paper_2306_17486_amd import inputs, netfile
+    p = inputs.init_net_params(3)
+    flat = netfile.flatten_params(p)
+    assert flat.dtype == np.float32 and flat.size == 509522
+    q = netfile.unflatten_params(flat)
+    assert set(q) == set(p)
+    for k in p:
+        assert np.allclose(q[k], np.asarray(p[k]).astype(np.complex64 if np.iscomplexobj(p[k]) else np.float32))
+
+
+def test_shipped_network_file_reads_without_gpu():
+    import numpy as np
+    from paper_2306_17486_amd import netfile
+    path = os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256_512.bin")
+    flat, ch = netfile.read_params(path)
+    assert ch == (16, 32, 64, 64) and flat.size == 509522
+    assert np.isfinite(flat).all()

@@ -213,3 +213,38 @@ def test_eval_loss_matches_train_step_and_changes_nothing(hh, ctx):
     assert lv == lt
     assert not np.array_equal(net.get_params(), p0)
     assert net.eval_loss(m, r, e) < lt
+
+
+def test_gradient_norm_and_clipped_adam_step(hh, ctx):
+    n, B = 64, 2
+    _say("gradient norm and clipping")
+    ks = _kappas(n, B, 120)
+    om = inputs.omega_for(n)
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om, gamma0=0.05)
+    e, r = m.training_pairs(_dev(inputs.random_complex((B, n, n), 121)), [3, 5])
+    net = hh.Net(ctx, inputs.init_net_params(15))
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    p0 = net.get_params().astype(np.float64)
+    net.train_step(m, r, e, lr=lr)  # unclipped first step
+    g1 = net.get_grads().astype(np.float64)
+    assert abs(net.last_grad_norm - np.linalg.norm(g1)) <= 1e-6 * np.linalg.norm(g1)
+    p1 = net.get_params().astype(np.float64)
+    clip = 0.25 * np.linalg.norm(g1)
+    net.train_step(m, r, e, lr=lr, max_grad_norm=clip)  # second step, clipped
+    g2 = net.get_grads().astype(np.float64)  # stored unclipped
+    n2 = np.linalg.norm(g2)
+    assert abs(net.last_grad_norm - n2) <= 1e-6 * n2
+    f2 = min(1.0, clip / n2)
+    assert f2 < 0.5
+    m1, v1 = (1 - b1) * g1, (1 - b2) * g1 * g1
+    m2 = b1 * m1 + (1 - b1) * f2 * g2
+    v2 = b2 * v1 + (1 - b2) * (f2 * g2) ** 2
+    expect = p1 - lr * (m2 / (1 - b1 ** 2)) / (np.sqrt(v2 / (1 - b2 ** 2)) + eps)
+    p2 = net.get_params().astype(np.float64)
+    assert np.abs(p2 - expect).max() <= 2e-6
+    # the unclipped update would differ visibly
+    m2u = b1 * m1 + (1 - b1) * g2
+    v2u = b2 * v1 + (1 - b2) * g2 * g2
+    unclipped = p1 - lr * (m2u / (1 - b1 ** 2)) / (np.sqrt(v2u / (1 - b2 ** 2)) + eps)
+    assert np.abs(unclipped - expect).max() > 1e-4
+    assert np.abs(p1 - p0).max() > 0

@@ -1,5 +1,5 @@
-"""The oracle's two-phase solve with MG-only FGMRES judging the network
-(restart-cycle probes, permanent fallback), pinned by three cases whose outcome
+"""The oracle's two-phase solve with the CNN+MG and MG-only preconditioners
+judging each other (restart-cycle probes), pinned by three cases whose outcome
 follows from the method itself:
 
 * an exact network (the direct solve) makes CNN+MG a strong preconditioner
@@ -8,7 +8,9 @@ follows from the method itself:
   judge never probes and the solve needs a fraction of MG-only's iterations;
 * a network that returns large noise cannot reduce the residual (FGMRES picks
   the best combination, so the cycle stalls): the judge probes once, MG-only
-  wins and the solve costs at most one wasted cycle more than MG-only;
+  wins and keeps every later cycle (its cycles reduce the residual far below
+  the probe ratio on this small grid), so the solve costs at most about one
+  wasted cycle more than MG-only;
 * without the judge the same noisy network needs far more iterations."""
 import numpy as np
 import scipy.sparse.linalg as spla
@@ -48,7 +50,7 @@ def test_exact_network_never_probes():
     st = {}
     x, its, _, rel = S.solve_two_phase(prob, _Exact(prob), b, stats=st)
     assert rel <= 1e-6 and its < its_mg / 2
-    assert st == {"fell_back": False, "probes": 0}
+    assert st == {"probes": 0, "mg_cycles": 0}
     assert np.linalg.norm(b - prob.A(x)) / np.linalg.norm(b) <= 1e-6
 
 
@@ -59,7 +61,8 @@ def test_noisy_network_falls_back_to_mg_after_one_probe():
     st = {}
     _, its, _, rel = S.solve_two_phase(prob, _Noise(1), b, stats=st)
     assert rel <= 1e-6 and rel_mg <= 1e-6
-    assert st["fell_back"] and st["probes"] == 1
+    assert st["probes"] == 1 and st["mg_cycles"] >= 1
+    assert st["mg_cycles"] == -(-(its - 3 - 10) // 10)  # every cycle after the stalled one
     # 3 warm + one stalled CNN+MG cycle, then MG-only from (about) where it was
     assert its <= its_mg + 2 * 10
 

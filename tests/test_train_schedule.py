@@ -25,3 +25,15 @@ def test_training_media_alternate_families():
 def test_three_size_schedule_follows_the_16_10_4_epoch_lengths():
     s = train.schedule(3000, 100, sizes=(128, 256, 512))
     assert (s.count(128), s.count(256), s.count(512)) == (16, 10, 4)
+
+
+def test_gradient_clip_threshold_follows_the_median():
+    c = train.GradClip(2.0, window=5, warmup=3)
+    assert c.threshold() == 0.0
+    for v in (1.0, 3.0, 2.0):
+        c.record(v)
+    assert c.threshold() == 4.0
+    for v in (100.0, 2.0, 2.0, 2.0):
+        c.record(v)
+    assert c.threshold() == 4.0  # one outlier does not move the median
+    assert train.GradClip(0.0, warmup=0).threshold() == 0.0
