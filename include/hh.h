@@ -150,6 +150,30 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
                    void* x_dev, const hh_solve_opts* o, double* res_hist_host, int* iters_host,
                    int* converged_host, double* final_res_host, int* mg_cycles_host, int* cnn_iters_host);
 
+/* Autotuner of the coarsest exact solve (the two-ended block-tridiagonal
+ * elimination).  Variants: the chain, one workgroup per end for every R
+ * right-hand sides (code R = 1, 2, 4, 8; each Schur inverse read serves R
+ * solves), and the split solve, where the rows of every Schur inverse are
+ * shared by ceil(m / RS) workgroups that meet after each step (code
+ * 100 RS + R, RS = 8, 16, 32; cooperative launch, offered only when every
+ * workgroup can be resident).  By default the variant is tuned per model and
+ * per bucket of active right-hand sides (1, 2, 3-4, 5-8, ...): on the first
+ * coarse solve of a bucket every variant is timed on that call's data and the
+ * fastest kept (that call synchronises the stream).
+ * hh_model_set_coarse_group fixes a variant or returns to tuning (0, which
+ * also forgets earlier choices); hh_model_coarse_group returns the variant in
+ * use for nact active right-hand sides (0: not tuned yet, -1: bad arguments).
+ * A split-solve step wait that times out makes the solve return HH_ERR_HIP. */
+hh_status hh_model_set_coarse_group(hh_model* m, int R);
+int hh_model_coarse_group(const hh_model* m, int nact);
+
+/* rel_host[r] = ||b_r - A x_r|| / ||b_r|| in FP64 (A of eqs. 1-3 with the
+ * model's coefficients) for solutions x_dev (c128 [nrhs][n][n], e.g. those
+ * hh_solve returned) and right-hand sides b_dev (c64 [nrhs][n][n]); inst_host
+ * as in hh_solve.  Synchronises the stream. */
+hh_status hh_residual_norms(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
+                            const void* x_dev, double* rel_host);
+
 /* ------------------------------------------------------------------------
  * Building blocks exposed for parity tests (same kernels as the solve).
  * ---------------------------------------------------------------------- */

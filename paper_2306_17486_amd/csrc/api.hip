@@ -175,6 +175,15 @@ hh_status hh_model_create(hh_ctx* ctx, const hh_model_desc* d, int ninst, const 
     }
     hh_status s = setup_coefficients(m, kappa_dev);
     if (s >= 0) s = setup_coarse_factors(m);
+    if (s >= 0) s = m->coarse_err.ensure(ctx, 256);
+    if (s >= 0 && hipMemsetAsync(m->coarse_err.ptr, 0, sizeof(int), ctx->stream) != hipSuccess) {
+        set_error("hipMemsetAsync failed");
+        s = HH_ERR_HIP;
+    }
+    if (s >= 0 && hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        set_error("hipStreamSynchronize failed");
+        s = HH_ERR_HIP;
+    }
     if (s < 0) {
         delete m;
         return s;
@@ -235,6 +244,7 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
     hh_status s = fgmres_solve(m, W, bm, (const float2*)b_dev, (double2*)x_dev, *o,
                                cnn ? net_precond : nullptr, cnn ? (void*)m : nullptr);
     if (s < 0) return s;
+    HH_TRY(coarse_check_err(m));
     // results
     std::vector<KState> hs(nrhs);
     HH_HIP(hipMemcpyAsync(hs.data(), W.state.ptr, (size_t)nrhs * sizeof(KState), hipMemcpyDeviceToHost, ctx->stream));
@@ -286,7 +296,36 @@ hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const voi
     HH_TRY(launch_vcycle(m, nrhs, bm, (const float2*)b_dev, nullptr, 0, (const float2*)x0_dev, (float2*)x_dev,
                          work.ptr, nullptr));
     HH_HIP(hipStreamSynchronize(m->ctx->stream));
+    return coarse_check_err(m);
+}
+
+hh_status hh_residual_norms(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
+                            const void* x_dev, double* rel_host) {
+    HH_ARG(ctx && m && b_dev && x_dev && rel_host, "null pointer");
+    HH_ARG(m->ctx == ctx, "model belongs to another context");
+    HH_ARG(nrhs >= 1, "nrhs >= 1");
+    HH_HIP(hipSetDevice(ctx->device));
+    Buf ib;
+    BatchMap bm;
+    HH_TRY(upload_inst_map(m, ib, nrhs, inst_host, &bm));
+    return residual_norms(m, nrhs, bm, (const float2*)b_dev, (const double2*)x_dev, rel_host);
+}
+
+hh_status hh_model_set_coarse_group(hh_model* m, int R) {
+    HH_ARG(m, "null pointer");
+    HH_ARG(R == 0 || coarse_choice_valid(R), "variant 0 (autotune), R = 1, 2, 4, 8 or 100 RS + R, RS = 8, 16, 32");
+    m->coarse_R_forced = R;
+    if (R == 0)
+        for (int b = 0; b < HH_COARSE_BUCKETS; ++b) m->coarse_R[b] = 0;
     return HH_OK;
+}
+
+int hh_model_coarse_group(const hh_model* m, int nact) {
+    if (!m || nact < 1) return -1;
+    if (m->coarse_R_forced > 0) return m->coarse_R_forced;
+    int b = 0;
+    while ((1 << b) < nact && b < HH_COARSE_BUCKETS - 1) ++b;
+    return m->coarse_R[b];
 }
 
 hh_status hh_profile_begin(hh_ctx* ctx, int cls) {

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -114,6 +115,7 @@ struct BatchMap {
     const int* inst = nullptr;
     const int* order = nullptr;
     int nslots = 0;
+    int nact = 0;  // upper bound of the right-hand sides active in this call (0 = all)
 };
 
 // One multigrid level of a model (all instances share n).
@@ -124,6 +126,10 @@ struct Level {
 };
 
 }  // namespace hh
+
+// buckets of the coarse-solve autotuner: active right-hand-side counts
+// 1, 2, 3-4, 5-8, ..., with the last bucket open-ended
+#define HH_COARSE_BUCKETS 12
 
 struct hh_model {
     hh_ctx* ctx = nullptr;
@@ -136,6 +142,9 @@ struct hh_model {
     hh::Buf kfeat;         // encoder input features (bf16 NHWC, 2 channels) when a net is attached
     hh_net* net = nullptr; // attached network (not owned)
     void* netcache = nullptr;  // per-model network state (encodings, Green's transforms)
+    int coarse_R[HH_COARSE_BUCKETS] = {0};  // coarse-solve variant per active-count bucket (0 = not tuned)
+    int coarse_R_forced = 0;                // fixed variant (R, or 100 RS + R for the split solve); 0: autotuned
+    hh::Buf coarse_err;                     // device int: a split-solve wait timed out
 };
 
 // ---------------------------------------------------------------------------
@@ -239,6 +248,8 @@ hh_status launch_vcycle_strided(hh_model* m, int nrhs, const BatchMap& bm, const
                                 size_t zstride, void* work, const int* active);
 // RHS per workgroup of the coarsest solve (the grouping unit of BatchMap::order)
 int coarse_group();
+bool coarse_choice_valid(int c);
+hh_status coarse_check_err(hh_model* md);
 // copy a host RHS -> slowness-model map to the device (api.hip)
 hh_status upload_inst_map(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out);
 

@@ -48,4 +48,7 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
 hh_status precond_mg_strided(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* v, size_t vstride,
                              const double* sig, int sig_stride, float2* z, size_t zstride, const int* act);
 
+hh_status residual_norms(hh_model* md, int nrhs, const BatchMap& bm, const float2* b, const double2* x,
+                         double* rel_host);
+
 }  // namespace hh

@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ 
             Ax = zsub(Ax, zmul(m, c));
             float2 bv = b[r * nn + o];
             double2 rv = make_double2((double)bv.x - Ax.x, (double)bv.y - Ax.y);
-            Vbase[r * vstride + o] = make_float2((float)rv.x, (float)rv.y);
+            if (Vbase) Vbase[r * vstride + o] = make_float2((float)rv.x, (float)rv.y);
             acc[0].x += zabs2(rv);
         }
     }
@@ -416,7 +416,10 @@ __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KSta
     __shared__ double2 s_red[4];
     const int r = blockIdx.x;
     if (done[r]) {
-        if (threadIdx.x == 0) active[r] = actc[r] = actm[r] = 0;
+        if (threadIdx.x == 0) {
+            active[r] = actc[r] = actm[r] = 0;
+            st[r].k = 0;  // a finished RHS takes no further x update
+        }
         return;
     }
     double2 acc[1] = {make_double2(0.0, 0.0)};
@@ -438,6 +441,7 @@ __global__ void k_cycle_begin(const double2* __restrict__ parts, int npart, KSta
     if (bad || S.converged || S.iters >= cap || beta == 0.0) {
         done[r] = 1;
         active[r] = actc[r] = actm[r] = 0;
+        S.k = 0;  // the last cycle's correction is already in x
         return;
     }
     S.sig[0] = 1.0 / beta;
@@ -544,13 +548,19 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
         HH_LAUNCH_CHECK();
         HH_HIP(hipMemcpyAsync(hflags.data(), done, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, st));
         HH_HIP(hipStreamSynchronize(st));
-        bool all = true, any_c = false, any_m = false;
+        bool all = true;
+        int cnt_c = 0, cnt_m = 0;
         for (int r = 0; r < nrhs; ++r) {
             all = all && hflags[r];
-            any_c = any_c || hflags[nrhs + r];
-            any_m = any_m || hflags[2 * nrhs + r];
+            cnt_c += hflags[nrhs + r];
+            cnt_m += hflags[2 * nrhs + r];
         }
         if (all) break;
+        const bool any_c = cnt_c > 0, any_m = cnt_m > 0;
+        // the active counts only fall during a cycle: upper bounds for the coarse solves
+        BatchMap bmc = bm, bmm = bm;
+        bmc.nact = cnt_c;
+        bmm.nact = cnt_m;
         int len = W.restart;
         if (warm) len = std::min(len, o.warm_mg_iters);
         if (fixed) len = std::min(len, o.fixed_iters);
@@ -560,8 +570,8 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
             float2* zj = Z + (size_t)j * nn;
             // z_j = M(v_j) on strided [rhs] views: CNN+MG for the RHS in actc,
             // MG-only for those in actm (warm start, probes, fallback)
-            if (any_c) HH_TRY(precond_cnn(precond_user, md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, actc));
-            if (any_m) HH_TRY(precond_mg_strided(md, W, bm, vj, vstride, sg, sig_stride, zj, zstride, actm));
+            if (any_c) HH_TRY(precond_cnn(precond_user, md, W, bmc, vj, vstride, sg, sig_stride, zj, zstride, actc));
+            if (any_m) HH_TRY(precond_mg_strided(md, W, bmm, vj, vstride, sg, sig_stride, zj, zstride, actm));
             // w = A z_j, dots with v_0..v_j
             {
             ProfScope ps(ctx, HH_K_OP_DOTS);
@@ -613,6 +623,38 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
             HH_LAUNCH_CHECK();
             break;
         }
+    }
+    return HH_OK;
+}
+
+// ||b - A x|| / ||b|| in FP64 for complex-double solutions x (the solve's own
+// restart-residual kernel, without storing the residual)
+hh_status residual_norms(hh_model* md, int nrhs, const BatchMap& bm, const float2* b, const double2* x,
+                         double* rel_host) {
+    hh_ctx* ctx = md->ctx;
+    const Level& L0 = md->lev[0];
+    const int n = L0.n, np = kblocks(n);
+    const dim3 blk(KT_X, KT_Y / KT_ROWS);
+    const dim3 grd((n + KT_X - 1) / KT_X, (n + KT_Y - 1) / KT_Y, nrhs);
+    Buf parts;
+    HH_TRY(parts.ensure(ctx, (size_t)2 * nrhs * np * sizeof(double2)));
+    double2* pr = parts.as<double2>();
+    double2* pb = pr + (size_t)nrhs * np;
+    hipLaunchKernelGGL(k_residual64, grd, blk, 0, ctx->stream, x, b, nullptr, (size_t)0, L0.coef.as<float2>(), bm.inst,
+                       n, 1.0 / (L0.h * L0.h), pr, nullptr);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_norm2, grd, blk, 0, ctx->stream, b, n, pb);
+    HH_LAUNCH_CHECK();
+    std::vector<double2> h((size_t)2 * nrhs * np);
+    HH_HIP(hipMemcpyAsync(h.data(), pr, h.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    for (int r = 0; r < nrhs; ++r) {
+        double sr = 0.0, sb = 0.0;
+        for (int q = 0; q < np; ++q) {
+            sr += h[(size_t)r * np + q].x;
+            sb += h[(size_t)(nrhs + r) * np + q].x;
+        }
+        rel_host[r] = sb > 0.0 ? sqrt(sr / sb) : sqrt(sr);
     }
     return HH_OK;
 }

@@ -271,9 +271,11 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
 // ---------------------------------------------------------------------------
 constexpr int CS_MAXM = 1024;
 constexpr int CS_NT = 1024;  // threads per workgroup: every row, columns split JP = 1024/m ways
-constexpr int CS_R = 2;      // right-hand sides per workgroup (each Q_k read is shared by CS_R solves)
+constexpr int CS_RMAX = 8;   // right-hand sides per workgroup: 1, 2, 4 or 8 (each Q_k read serves all of them)
 
+template <int R>
 struct CoarseMV {
+    static constexpr int CH = R >= 4 ? 8 : 16;  // loads per chunk; the next chunk loads while one is used
     int m, JP, jlen, row, jp;
     __device__ CoarseMV(int m_) : m(m_) {
         JP = CS_NT / m;  // >= 1 since m <= 1024
@@ -281,14 +283,12 @@ struct CoarseMV {
         row = threadIdx.x % m;
         jp = threadIdx.x / m;
     }
-    // out[q] = sum_j Qk[j][row] v[q][j] for the CS_R vectors; the JP partial
-    // sums meet in s_part.  Valid in the owner threads (jp == 0).
-    __device__ void apply(const float2* __restrict__ Qk, const float2 (*s_v)[CS_MAXM], float2 (*s_part)[CS_NT],
-                          float2 (&out)[CS_R]) const {
-        constexpr int CH = 16;  // loads per chunk; the next chunk is loaded while one is used
-        float2 acc[CS_R];
+    // out[q] = sum_j Qk[j][row] v[q][j] for the R vectors s_v[q * m + j]; the JP
+    // partial sums meet in s_part[q * CS_NT + t].  Valid in the owner threads (jp == 0).
+    __device__ void apply(const float2* __restrict__ Qk, const float2* s_v, float2* s_part, float2 (&out)[R]) const {
+        float2 acc[R];
 #pragma unroll
-        for (int q = 0; q < CS_R; ++q) acc[q] = make_float2(0.f, 0.f);
+        for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
         if (jp < JP) {
             const int j0 = jp * jlen, j1 = min(m, j0 + jlen);
             const float2* qp = Qk + row;
@@ -307,7 +307,7 @@ struct CoarseMV {
 #pragma unroll
                     for (int u = 0; u < CH; ++u)
 #pragma unroll
-                        for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], cmul(qa[u], s_v[q][j + u]));
+                        for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qa[u], s_v[q * m + j + u]));
                     j = jb;
                     if (!hb) break;
                     const int ja = j + CH;
@@ -319,7 +319,7 @@ struct CoarseMV {
 #pragma unroll
                     for (int u = 0; u < CH; ++u)
 #pragma unroll
-                        for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], cmul(qb[u], s_v[q][j + u]));
+                        for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qb[u], s_v[q * m + j + u]));
                     j = ja;
                     if (!ha) break;
                 }
@@ -327,73 +327,104 @@ struct CoarseMV {
             for (; j < j1; ++j) {
                 const float2 qv = qp[(size_t)j * m];
 #pragma unroll
-                for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], cmul(qv, s_v[q][j]));
+                for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qv, s_v[q * m + j]));
             }
         }
         if (JP > 1) {
             if (jp < JP)
 #pragma unroll
-                for (int q = 0; q < CS_R; ++q) s_part[q][threadIdx.x] = acc[q];
+                for (int q = 0; q < R; ++q) s_part[q * CS_NT + threadIdx.x] = acc[q];
             __syncthreads();
             if (jp == 0)
                 for (int t = 1; t < JP; ++t)
 #pragma unroll
-                    for (int q = 0; q < CS_R; ++q) acc[q] = cadd(acc[q], s_part[q][t * m + row]);
+                    for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], s_part[q * CS_NT + t * m + row]);
             __syncthreads();
         }
 #pragma unroll
-        for (int q = 0; q < CS_R; ++q) out[q] = acc[q];
+        for (int q = 0; q < R; ++q) out[q] = acc[q];
     }
     __device__ bool owner() const { return jp == 0; }
 };
 
-// Right-hand sides r = blockIdx.x * CS_R + q (q < CS_R) that exist and are
-// active; all of them must use the same slowness model (the host groups them).
-struct CoarseGroup {
-    int r[CS_R];
-    bool on[CS_R];
+// dynamic LDS of a chain kernel: s_v [R][m], then s_part [R][CS_NT] when JP > 1
+static inline size_t coarse_lds_bytes(int R, int m) {
+    return (size_t)R * m * sizeof(float2) + (CS_NT / m > 1 ? (size_t)R * CS_NT * sizeof(float2) : 0);
+}
+
+// The R right-hand sides of this workgroup: slot blockIdx.x * R + q of the
+// slot list (slots = NULL: slot s is RHS s); *nslots_dev (if given) bounds it.
+// Entries < 0 are padding; all entries of one workgroup share a slowness model.
+template <int R>
+struct CoarseSlots {
+    int rr[R];
+    bool on[R];
     bool any;
-    __device__ CoarseGroup(int nrhs, const int* active) {
+    int r0;
+    __device__ CoarseSlots(const int* slots, int nslots, const int* nslots_dev, const int* active, int grp) {
+        const int ns = nslots_dev ? *nslots_dev : nslots;
         any = false;
+        r0 = 0;
 #pragma unroll
-        for (int q = 0; q < CS_R; ++q) {
-            r[q] = blockIdx.x * CS_R + q;
-            on[q] = r[q] < nrhs && (!active || active[r[q]]);
+        for (int q = 0; q < R; ++q) {
+            const int slot = grp * R + q;
+            rr[q] = (slot < ns) ? (slots ? slots[slot] : slot) : -1;
+            on[q] = rr[q] >= 0 && (!active || active[rr[q]]);
             any = any || on[q];
         }
+#pragma unroll
+        for (int q = R - 1; q >= 0; --q)
+            if (on[q]) r0 = rr[q];
     }
 };
 
+// Active right-hand sides of a single-model solve packed to the front of
+// `slots` (ascending), their count in *count.  One workgroup.
+__global__ void __launch_bounds__(1024) k_coarse_compact(const int* __restrict__ active, int nrhs,
+                                                         int* __restrict__ slots, int* __restrict__ count) {
+    __shared__ int s_wsum[16];
+    __shared__ int s_base;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int r0 = 0; r0 < nrhs; r0 += 1024) {
+        const int r = r0 + threadIdx.x;
+        const int f = (r < nrhs && active[r]) ? 1 : 0;
+        const unsigned long long bal = __ballot(f);
+        const int below = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wsum[wid] = __popcll(bal);
+        __syncthreads();
+        int off = s_base;
+        for (int w = 0; w < wid; ++w) off += s_wsum[w];
+        if (f) slots[off + below] = r;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int w = 0; w < 16; ++w) t += s_wsum[w];
+            s_base += t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = s_base;
+}
+
 // ends: [rhs][2][m], the last forward results y_{p-1} (slot 0) and y_{p+1}
 // (slot 1), kept apart from x because the backward sweep overwrites x rows.
-// rhs_order: RHS indices grouped so that each block's CS_R entries share a
-// slowness model (entries < 0 are padding).
+template <int R>
 __global__ void __launch_bounds__(CS_NT) k_coarse_fwd(const float2* __restrict__ bcs, float2* __restrict__ x,
                                                       float2* __restrict__ ends, const float2* __restrict__ QT,
-                                                      const int* __restrict__ inst, const int* __restrict__ order,
-                                                      int nslots, int m, int p, float c,
-                                                      const int* __restrict__ active) {
-    __shared__ float2 s_v[CS_R][CS_MAXM];
-    __shared__ float2 s_part[CS_R][CS_NT];
+                                                      const int* __restrict__ inst, const int* __restrict__ slots,
+                                                      int nslots, const int* __restrict__ nslots_dev, int m, int p,
+                                                      float c, const int* __restrict__ active) {
+    extern __shared__ float2 s_lds[];
+    float2* s_v = s_lds;
+    float2* s_part = s_lds + R * m;
     const bool top = blockIdx.y == 0;
-    int rr[CS_R];
-    bool on[CS_R];
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < CS_R; ++q) {
-        const int slot = blockIdx.x * CS_R + q;
-        rr[q] = (slot < nslots) ? (order ? order[slot] : slot) : -1;
-        on[q] = rr[q] >= 0 && (!active || active[rr[q]]);
-        any = any || on[q];
-    }
-    if (!any) return;
-    int r0 = 0;
-#pragma unroll
-    for (int q = CS_R - 1; q >= 0; --q)
-        if (on[q]) r0 = rr[q];
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
+    if (!g.any) return;
     const size_t mm = (size_t)m * m;
-    const float2* Q = QT + (size_t)(inst ? inst[r0] : 0) * mm * m;
-    const CoarseMV mv(m);
+    const float2* Q = QT + (size_t)(inst ? inst[g.r0] : 0) * mm * m;
+    const CoarseMV<R> mv(m);
     const int nsteps = top ? p : (m - 1 - p);
     for (int s = 0; s < nsteps; ++s) {
         const int k = top ? s : (m - 1 - s);
@@ -401,24 +432,24 @@ __global__ void __launch_bounds__(CS_NT) k_coarse_fwd(const float2* __restrict__
         if (mv.owner()) {
             const int i = mv.row;
 #pragma unroll
-            for (int q = 0; q < CS_R; ++q) {
-                float2 w = on[q] ? bcs[(size_t)rr[q] * mm + (size_t)k * m + i] : make_float2(0.f, 0.f);
-                if (s > 0) w = cadd(w, cscale(s_v[q][i], c));
-                s_v[q][i] = w;
+            for (int q = 0; q < R; ++q) {
+                float2 w = g.on[q] ? bcs[(size_t)g.rr[q] * mm + (size_t)k * m + i] : make_float2(0.f, 0.f);
+                if (s > 0) w = cadd(w, cscale(s_v[q * m + i], c));
+                s_v[q * m + i] = w;
             }
         }
         __syncthreads();
-        float2 out[CS_R];
+        float2 out[R];
         mv.apply(Q + (size_t)k * mm, s_v, s_part, out);
         __syncthreads();
         if (mv.owner()) {
             const int i = mv.row;
 #pragma unroll
-            for (int q = 0; q < CS_R; ++q) {
-                s_v[q][i] = out[q];
-                if (on[q]) {
-                    x[(size_t)rr[q] * mm + (size_t)k * m + i] = out[q];
-                    if (s == nsteps - 1) ends[((size_t)rr[q] * 2 + (top ? 0 : 1)) * m + i] = out[q];
+            for (int q = 0; q < R; ++q) {
+                s_v[q * m + i] = out[q];
+                if (g.on[q]) {
+                    x[(size_t)g.rr[q] * mm + (size_t)k * m + i] = out[q];
+                    if (s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + i] = out[q];
                 }
             }
         }
@@ -426,56 +457,45 @@ __global__ void __launch_bounds__(CS_NT) k_coarse_fwd(const float2* __restrict__
     }
 }
 
+template <int R>
 __global__ void __launch_bounds__(CS_NT) k_coarse_bwd(const float2* __restrict__ bcs, float2* __restrict__ x,
                                                       const float2* __restrict__ ends, const float2* __restrict__ QT,
-                                                      const int* __restrict__ inst, const int* __restrict__ order,
-                                                      int nslots, int m, int p, float c,
-                                                      const int* __restrict__ active) {
-    __shared__ float2 s_v[CS_R][CS_MAXM];
-    __shared__ float2 s_part[CS_R][CS_NT];
+                                                      const int* __restrict__ inst, const int* __restrict__ slots,
+                                                      int nslots, const int* __restrict__ nslots_dev, int m, int p,
+                                                      float c, const int* __restrict__ active) {
+    extern __shared__ float2 s_lds[];
+    float2* s_v = s_lds;
+    float2* s_part = s_lds + R * m;
     const bool top = blockIdx.y == 0;
-    int rr[CS_R];
-    bool on[CS_R];
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < CS_R; ++q) {
-        const int slot = blockIdx.x * CS_R + q;
-        rr[q] = (slot < nslots) ? (order ? order[slot] : slot) : -1;
-        on[q] = rr[q] >= 0 && (!active || active[rr[q]]);
-        any = any || on[q];
-    }
-    if (!any) return;
-    int r0 = 0;
-#pragma unroll
-    for (int q = CS_R - 1; q >= 0; --q)
-        if (on[q]) r0 = rr[q];
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
+    if (!g.any) return;
     const size_t mm = (size_t)m * m;
-    const float2* Q = QT + (size_t)(inst ? inst[r0] : 0) * mm * m;
-    const CoarseMV mv(m);
+    const float2* Q = QT + (size_t)(inst ? inst[g.r0] : 0) * mm * m;
+    const CoarseMV<R> mv(m);
     // middle row: x_p = Q_p (b_p + c y_{p-1} + c y_{p+1}); both workgroups compute it
     if (mv.owner()) {
         const int i = mv.row;
 #pragma unroll
-        for (int q = 0; q < CS_R; ++q) {
+        for (int q = 0; q < R; ++q) {
             float2 w = make_float2(0.f, 0.f);
-            if (on[q]) {
-                w = bcs[(size_t)rr[q] * mm + (size_t)p * m + i];
-                if (p > 0) w = cadd(w, cscale(ends[((size_t)rr[q] * 2 + 0) * m + i], c));
-                if (p < m - 1) w = cadd(w, cscale(ends[((size_t)rr[q] * 2 + 1) * m + i], c));
+            if (g.on[q]) {
+                w = bcs[(size_t)g.rr[q] * mm + (size_t)p * m + i];
+                if (p > 0) w = cadd(w, cscale(ends[((size_t)g.rr[q] * 2 + 0) * m + i], c));
+                if (p < m - 1) w = cadd(w, cscale(ends[((size_t)g.rr[q] * 2 + 1) * m + i], c));
             }
-            s_v[q][i] = w;
+            s_v[q * m + i] = w;
         }
     }
     __syncthreads();
     {
-        float2 out[CS_R];
+        float2 out[R];
         mv.apply(Q + (size_t)p * mm, s_v, s_part, out);
         __syncthreads();
         if (mv.owner()) {
 #pragma unroll
-            for (int q = 0; q < CS_R; ++q) {
-                s_v[q][mv.row] = out[q];
-                if (top && on[q]) x[(size_t)rr[q] * mm + (size_t)p * m + mv.row] = out[q];
+            for (int q = 0; q < R; ++q) {
+                s_v[q * m + mv.row] = out[q];
+                if (top && g.on[q]) x[(size_t)g.rr[q] * mm + (size_t)p * m + mv.row] = out[q];
             }
         }
         __syncthreads();
@@ -483,23 +503,258 @@ __global__ void __launch_bounds__(CS_NT) k_coarse_bwd(const float2* __restrict__
     const int nsteps = top ? p : (m - 1 - p);
     for (int s = 0; s < nsteps; ++s) {
         const int k = top ? (p - 1 - s) : (p + 1 + s);
-        float2 out[CS_R];
+        float2 out[R];
         mv.apply(Q + (size_t)k * mm, s_v, s_part, out);
         __syncthreads();
         if (mv.owner()) {
             const int i = mv.row;
 #pragma unroll
-            for (int q = 0; q < CS_R; ++q) {
+            for (int q = 0; q < R; ++q) {
                 float2 v = make_float2(0.f, 0.f);
-                if (on[q]) {
-                    v = cadd(x[(size_t)rr[q] * mm + (size_t)k * m + i], cscale(out[q], c));
-                    x[(size_t)rr[q] * mm + (size_t)k * m + i] = v;
+                if (g.on[q]) {
+                    v = cadd(x[(size_t)g.rr[q] * mm + (size_t)k * m + i], cscale(out[q], c));
+                    x[(size_t)g.rr[q] * mm + (size_t)k * m + i] = v;
                 }
-                s_v[q][i] = v;
+                s_v[q * m + i] = v;
             }
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Split coarse solve.  One chain step streams a whole m x m Schur inverse; a
+// single workgroup cannot pull that faster than one CU's share of the memory
+// system, so here the rows of every Q_k are shared by S workgroups ("slices")
+// that advance through the chain together.  The slices of one (end, RHS
+// group) unit exchange each step's result vector through a double-buffered
+// global buffer and meet at a counter after every step.  All slices of a unit
+// run on one XCD (blockIdx mod 8), the launch is cooperative (every workgroup
+// resident), and every wait is bounded: on a timeout the kernel sets *err and
+// carries on without waiting, so every wave reaches its end.
+// ---------------------------------------------------------------------------
+constexpr int CSP_NT = 256;
+constexpr int CSP_SPIN_LIMIT = 1 << 22;  // ~0.1 s of polling
+
+struct SplitGeom {
+    int G;      // right-hand-side groups of R
+    int S;      // slices per unit (RS rows each)
+    int units;  // 2 G: unit u = group u / 2, end u % 2 (0 = top)
+    int upx;    // units per XCD lane: ceil(units / 8)
+};
+
+__device__ __forceinline__ bool split_decode(const SplitGeom& geo, int& unit, int& slice) {
+    const int b = blockIdx.x;
+    const int xcd = b & 7, rest = b >> 3;
+    const int lu = rest / geo.S;
+    slice = rest - lu * geo.S;
+    unit = lu * 8 + xcd;
+    return unit < geo.units;
+}
+
+// all threads: wait until *cnt >= target (thread 0 polls with acquire loads)
+__device__ __forceinline__ void split_wait(int* cnt, int target, int* err) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (!__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+               __hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > CSP_SPIN_LIMIT) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// all threads: the step's results (stored by wave 0) are released, then counted
+__device__ __forceinline__ void split_arrive(int* cnt) {
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float2 load_agent(const float2* p) {
+    const unsigned long long v =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    float2 r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+
+// rows row0 .. row0 + RS - 1 of Q_k v for the R vectors s_w[q * m + j]; the
+// CSP_NT / RS column parts meet in s_part.  Results in threads t < RS (wave 0).
+template <int R, int RS>
+__device__ __forceinline__ void split_matvec(const float2* __restrict__ Qk, const float2* s_w, float2* s_part, int m,
+                                             int row0, float2 (&out)[R]) {
+    constexpr int JP = CSP_NT / RS;
+    const int t = threadIdx.x, lr = t % RS, jp = t / RS;
+    const int jlen = (m + JP - 1) / JP, j0 = jp * jlen, j1 = min(m, j0 + jlen);
+    float2 acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
+    if (row0 + lr < m) {
+        const float2* qp = Qk + row0 + lr;
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            float2 qv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) qv[u] = qp[(size_t)(j + u) * m];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qv[u], s_w[q * m + j + u]));
+        }
+        for (; j < j1; ++j) {
+            const float2 qv = qp[(size_t)j * m];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qv, s_w[q * m + j]));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) s_part[(jp * RS + lr) * R + q] = acc[q];
+    __syncthreads();
+    if (t < RS) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float2 a = make_float2(0.f, 0.f);
+            for (int u = 0; u < JP; ++u) a = cadd(a, s_part[(u * RS + t) * R + q]);
+            out[q] = a;
+        }
+    }
+}
+
+// xch layout: [unit][parity][R][m]
+template <int R>
+__device__ __forceinline__ float2* xch_at(float2* xch, int unit, int par, int q, int m) {
+    return xch + ((size_t)(unit * 2 + par) * R + q) * m;
+}
+
+template <int R, int RS>
+__global__ void __launch_bounds__(CSP_NT) k_coarse_split_fwd(const float2* __restrict__ bcs, float2* __restrict__ x,
+                                                             float2* __restrict__ ends, const float2* __restrict__ QT,
+                                                             const int* __restrict__ inst, const int* __restrict__ slots,
+                                                             int nslots, const int* __restrict__ nslots_dev, int m,
+                                                             int p, float c, const int* __restrict__ active,
+                                                             SplitGeom geo, float2* __restrict__ xch,
+                                                             int* __restrict__ cnt, int* __restrict__ err) {
+    extern __shared__ float2 s_lds[];
+    float2* s_w = s_lds;
+    float2* s_part = s_lds + R * m;
+    int unit, slice;
+    if (!split_decode(geo, unit, slice)) return;
+    const bool top = (unit & 1) == 0;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
+    if (!g.any) return;  // the same for every slice of the unit
+    const size_t mm = (size_t)m * m;
+    const float2* Q = QT + (size_t)(inst ? inst[g.r0] : 0) * mm * m;
+    const int row0 = slice * RS;
+    const int nsteps = top ? p : (m - 1 - p);
+    for (int s = 0; s < nsteps; ++s) {
+        const int k = top ? s : (m - 1 - s);
+        if (s > 0) split_wait(cnt + unit, geo.S * s, err);
+        // w_k = b_k + c y_prev for every row
+        for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
+            const int q = e / m, j = e - q * m;
+            float2 w = make_float2(0.f, 0.f);
+            if (g.on[q]) {
+                w = bcs[(size_t)g.rr[q] * mm + (size_t)k * m + j];
+                if (s > 0) w = cadd(w, cscale(load_agent(xch_at<R>(xch, unit, (s - 1) & 1, q, m) + j), c));
+            }
+            s_w[e] = w;
+        }
+        __syncthreads();
+        float2 out[R];
+        split_matvec<R, RS>(Q + (size_t)k * mm, s_w, s_part, m, row0, out);
+        const int row = row0 + threadIdx.x;
+        if (threadIdx.x < RS && row < m) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                xch_at<R>(xch, unit, s & 1, q, m)[row] = out[q];
+                if (g.on[q]) {
+                    x[(size_t)g.rr[q] * mm + (size_t)k * m + row] = out[q];
+                    if (s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + row] = out[q];
+                }
+            }
+        }
+        split_arrive(cnt + unit);
+    }
+}
+
+template <int R, int RS>
+__global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __restrict__ bcs, float2* __restrict__ x,
+                                                             const float2* __restrict__ ends,
+                                                             const float2* __restrict__ QT,
+                                                             const int* __restrict__ inst, const int* __restrict__ slots,
+                                                             int nslots, const int* __restrict__ nslots_dev, int m,
+                                                             int p, float c, const int* __restrict__ active,
+                                                             SplitGeom geo, float2* __restrict__ xch,
+                                                             int* __restrict__ cnt, int* __restrict__ err) {
+    extern __shared__ float2 s_lds[];
+    float2* s_w = s_lds;
+    float2* s_part = s_lds + R * m;
+    int unit, slice;
+    if (!split_decode(geo, unit, slice)) return;
+    const bool top = (unit & 1) == 0;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
+    if (!g.any) return;
+    const size_t mm = (size_t)m * m;
+    const float2* Q = QT + (size_t)(inst ? inst[g.r0] : 0) * mm * m;
+    const int row0 = slice * RS;
+    const int row = row0 + threadIdx.x;
+    // middle row (round 0): x_p = Q_p (b_p + c y_{p-1} + c y_{p+1}); both ends compute it
+    for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
+        const int q = e / m, j = e - q * m;
+        float2 w = make_float2(0.f, 0.f);
+        if (g.on[q]) {
+            w = bcs[(size_t)g.rr[q] * mm + (size_t)p * m + j];
+            if (p > 0) w = cadd(w, cscale(ends[((size_t)g.rr[q] * 2 + 0) * m + j], c));
+            if (p < m - 1) w = cadd(w, cscale(ends[((size_t)g.rr[q] * 2 + 1) * m + j], c));
+        }
+        s_w[e] = w;
+    }
+    __syncthreads();
+    {
+        float2 out[R];
+        split_matvec<R, RS>(Q + (size_t)p * mm, s_w, s_part, m, row0, out);
+        if (threadIdx.x < RS && row < m) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                xch_at<R>(xch, unit, 0, q, m)[row] = out[q];
+                if (top && g.on[q]) x[(size_t)g.rr[q] * mm + (size_t)p * m + row] = out[q];
+            }
+        }
+        split_arrive(cnt + unit);
+    }
+    const int nsteps = top ? p : (m - 1 - p);
+    for (int s = 0; s < nsteps; ++s) {
+        const int k = top ? (p - 1 - s) : (p + 1 + s);
+        split_wait(cnt + unit, geo.S * (s + 1), err);
+        for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
+            const int q = e / m, j = e - q * m;
+            s_w[e] = g.on[q] ? load_agent(xch_at<R>(xch, unit, s & 1, q, m) + j) : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        float2 out[R];
+        split_matvec<R, RS>(Q + (size_t)k * mm, s_w, s_part, m, row0, out);
+        if (threadIdx.x < RS && row < m) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                float2 v = make_float2(0.f, 0.f);
+                if (g.on[q]) {
+                    v = cadd(x[(size_t)g.rr[q] * mm + (size_t)k * m + row], cscale(out[q], c));
+                    x[(size_t)g.rr[q] * mm + (size_t)k * m + row] = v;
+                }
+                xch_at<R>(xch, unit, (s + 1) & 1, q, m)[row] = v;
+            }
+        }
+        split_arrive(cnt + unit);
+    }
+}
+
+__global__ void k_zero_ints(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -517,8 +772,9 @@ hh_status launch_apply_op(hh_model* md, int level, float shift, int nrhs, const 
 }
 
 // workspace: per level l >= 1: b_l and e_l [nrhs][n_l][n_l]; the coarse solve's
-// [nrhs][2][m] exchange rows; plus x1 [nrhs][n][n] if with_x0
-size_t vcycle_workspace_bytes(const hh_model* md, int nrhs, bool with_x0) {
+// [nrhs][2][m] exchange rows; x1 [nrhs][n][n] if with_x0; then the coarse
+// solve's compacted slot list (nrhs ints) and its length
+static size_t vcycle_float_bytes(const hh_model* md, int nrhs, bool with_x0) {
     size_t bytes = 0;
     for (int l = 1; l < md->nlev; ++l) bytes += 2 * (size_t)nrhs * md->lev[l].n * md->lev[l].n * sizeof(float2);
     bytes += 2 * (size_t)nrhs * md->lev[md->nlev - 1].n * sizeof(float2);
@@ -526,7 +782,260 @@ size_t vcycle_workspace_bytes(const hh_model* md, int nrhs, bool with_x0) {
     return bytes;
 }
 
-int coarse_group() { return CS_R; }
+// slots of the coarse solve: the RHS list, or the grouping order padded per model
+static int coarse_slot_bound(const hh_model* md, int nrhs) { return nrhs + CS_RMAX * md->ninst; }
+
+// after the float part: slot list, its count, the split solve's step counters
+// (2 sweeps x units) and exchange vectors ([unit][2][R][m], units * R <= 2 (slots + CS_RMAX))
+struct CoarseWork {
+    int* slots;
+    int* count;
+    int* cnt;
+    float2* xch;
+};
+static size_t coarse_work_bytes(const hh_model* md, int nrhs) {
+    const size_t ns = (size_t)coarse_slot_bound(md, nrhs);
+    const int m = md->lev[md->nlev - 1].n;
+    return (ns + 64) * sizeof(int) + 4 * (ns + CS_RMAX) * sizeof(int) + 256 +
+           4 * (ns + CS_RMAX) * (size_t)m * sizeof(float2);
+}
+static CoarseWork coarse_work(const hh_model* md, void* base, int nrhs) {
+    const size_t ns = (size_t)coarse_slot_bound(md, nrhs);
+    CoarseWork w;
+    char* q = (char*)base;
+    w.slots = (int*)q;
+    w.count = w.slots + ns;
+    q += (ns + 64) * sizeof(int);
+    w.cnt = (int*)q;
+    q += 4 * (ns + CS_RMAX) * sizeof(int);
+    q = (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    w.xch = (float2*)q;
+    return w;
+}
+
+size_t vcycle_workspace_bytes(const hh_model* md, int nrhs, bool with_x0) {
+    return vcycle_float_bytes(md, nrhs, with_x0) + coarse_work_bytes(md, nrhs) + 256;
+}
+
+int coarse_group() { return CS_RMAX; }
+
+// ---- coarse block solve: launch with R right-hand sides per workgroup -------
+template <int R>
+static hh_status launch_coarse_t(hh_ctx* ctx, const float2* bcs, float2* x, float2* ends, const float2* QT,
+                                 const int* inst, const int* slots, int nslots, const int* nslots_dev, int m, int p,
+                                 float c, const int* active) {
+    static unsigned attr_devices = 0;  // devices on which the LDS limit was raised
+    const size_t lds = coarse_lds_bytes(R, m);
+    if (lds > 65536 && !(attr_devices & (1u << ctx->device))) {
+        size_t most = 0;  // the largest need over every supported m
+        for (int mm = 4; mm <= CS_MAXM; ++mm) most = std::max(most, coarse_lds_bytes(R, mm));
+        const int want = (int)most;
+        HH_HIP(hipFuncSetAttribute((const void*)k_coarse_fwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+        HH_HIP(hipFuncSetAttribute((const void*)k_coarse_bwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+        attr_devices |= 1u << ctx->device;
+    }
+    const dim3 grd((nslots + R - 1) / R, 2);
+    hipLaunchKernelGGL(k_coarse_fwd<R>, grd, dim3(CS_NT), lds, ctx->stream, bcs, x, ends, QT, inst, slots, nslots,
+                       nslots_dev, m, p, c, active);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_coarse_bwd<R>, grd, dim3(CS_NT), lds, ctx->stream, bcs, x, ends, QT, inst, slots, nslots,
+                       nslots_dev, m, p, c, active);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+static hh_status launch_coarse(int R, hh_ctx* ctx, const float2* bcs, float2* x, float2* ends, const float2* QT,
+                               const int* inst, const int* slots, int nslots, const int* nslots_dev, int m, int p,
+                               float c, const int* active) {
+    switch (R) {
+        case 1: return launch_coarse_t<1>(ctx, bcs, x, ends, QT, inst, slots, nslots, nslots_dev, m, p, c, active);
+        case 2: return launch_coarse_t<2>(ctx, bcs, x, ends, QT, inst, slots, nslots, nslots_dev, m, p, c, active);
+        case 4: return launch_coarse_t<4>(ctx, bcs, x, ends, QT, inst, slots, nslots, nslots_dev, m, p, c, active);
+        case 8: return launch_coarse_t<8>(ctx, bcs, x, ends, QT, inst, slots, nslots, nslots_dev, m, p, c, active);
+        default: set_error("coarse group size %d (1, 2, 4 or 8)", R); return HH_ERR_ARG;
+    }
+}
+
+// ---- split solve: S workgroups per (end, group), cooperative launch ---------
+static size_t split_lds_bytes(int R, int m) { return (size_t)R * m * sizeof(float2) + (size_t)CSP_NT * R * sizeof(float2); }
+
+template <int R, int RS>
+static hh_status launch_split_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
+                                const int* slots, int nslots, const int* nslots_dev, int m, int p, float c,
+                                const int* active, const CoarseWork& cw, bool* fits) {
+    hh_ctx* ctx = md->ctx;
+    static unsigned attr_devices = 0;
+    const size_t lds = split_lds_bytes(R, m);
+    if (split_lds_bytes(R, CS_MAXM) > 65536 && !(attr_devices & (1u << ctx->device))) {
+        const int want = (int)split_lds_bytes(R, CS_MAXM);
+        HH_HIP(hipFuncSetAttribute((const void*)k_coarse_split_fwd<R, RS>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, want));
+        HH_HIP(hipFuncSetAttribute((const void*)k_coarse_split_bwd<R, RS>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, want));
+        attr_devices |= 1u << ctx->device;
+    }
+    SplitGeom geo;
+    geo.G = (nslots + R - 1) / R;
+    geo.S = (m + RS - 1) / RS;
+    geo.units = 2 * geo.G;
+    geo.upx = (geo.units + 7) / 8;
+    const int grid = 8 * geo.upx * geo.S;
+    int per_cu_f = 0, per_cu_b = 0;
+    HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_f, (const void*)k_coarse_split_fwd<R, RS>, CSP_NT,
+                                                        lds));
+    HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, (const void*)k_coarse_split_bwd<R, RS>, CSP_NT,
+                                                        lds));
+    if ((long long)std::min(per_cu_f, per_cu_b) * ctx->num_cus < grid) {
+        *fits = false;  // not every workgroup could be resident: not offered
+        return HH_OK;
+    }
+    *fits = true;
+    hipLaunchKernelGGL(k_zero_ints, dim3((2 * geo.units + 255) / 256), dim3(256), 0, ctx->stream, cw.cnt,
+                       2 * geo.units);
+    HH_LAUNCH_CHECK();
+    const float2* a_bcs = bcs;
+    float2* a_x = x;
+    float2* a_ends = ends;
+    const float2* a_QT = md->coarseQT.as<float2>();
+    const int* a_inst = inst;
+    const int* a_slots = slots;
+    int a_nslots = nslots;
+    const int* a_nsd = nslots_dev;
+    int a_m = m, a_p = p;
+    float a_c = c;
+    const int* a_act = active;
+    float2* a_xch = cw.xch;
+    int* a_cnt = cw.cnt;
+    int* a_err = md->coarse_err.as<int>();
+    void* args[] = {&a_bcs, &a_x, &a_ends, &a_QT, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m,   &a_p,
+                    &a_c,   &a_act, &geo, &a_xch, &a_cnt, &a_err};
+    const hipError_t le = hipLaunchCooperativeKernel((const void*)k_coarse_split_fwd<R, RS>, dim3(grid),
+                                                     dim3(CSP_NT), args, (unsigned)lds, ctx->stream);
+    if (le == hipErrorCooperativeLaunchTooLarge) {  // the runtime's residency bound is tighter: not offered
+        (void)hipGetLastError();
+        *fits = false;
+        return HH_OK;
+    }
+    if (le != hipSuccess) {
+        set_error("cooperative launch failed: %s", hipGetErrorString(le));
+        return HH_ERR_HIP;
+    }
+    const float2* b_ends = ends;
+    int* b_cnt = cw.cnt + geo.units;
+    void* args_b[] = {&a_bcs, &a_x, &b_ends, &a_QT, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m,   &a_p,
+                      &a_c,   &a_act, &geo, &a_xch, &b_cnt, &a_err};
+    HH_HIP(hipLaunchCooperativeKernel((const void*)k_coarse_split_bwd<R, RS>, dim3(grid), dim3(CSP_NT), args_b,
+                                      (unsigned)lds, ctx->stream));
+    return HH_OK;
+}
+
+// choice: R (1, 2, 4, 8) = chain with R right-hand sides per workgroup;
+// 100 RS + R = split with RS rows per workgroup (RS = 8, 16, 32)
+static hh_status launch_coarse_choice(int choice, hh_model* md, const float2* bcs, float2* x, float2* ends,
+                                      const int* inst, const int* slots, int nslots, const int* nslots_dev, int m,
+                                      int p, float c, const int* active, const CoarseWork& cw, bool* fits) {
+    *fits = true;
+    if (choice < 100)
+        return launch_coarse(choice, md->ctx, bcs, x, ends, md->coarseQT.as<float2>(), inst, slots, nslots,
+                             nslots_dev, m, p, c, active);
+#define HH_SPLIT(RS_, R_)                                                                                  \
+    if (choice == 100 * RS_ + R_)                                                                          \
+        return launch_split_t<R_, RS_>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, p, c, active, \
+                                       cw, fits);
+    HH_SPLIT(8, 1) HH_SPLIT(8, 2) HH_SPLIT(8, 4) HH_SPLIT(8, 8)
+    HH_SPLIT(16, 1) HH_SPLIT(16, 2) HH_SPLIT(16, 4) HH_SPLIT(16, 8)
+    HH_SPLIT(32, 1) HH_SPLIT(32, 2) HH_SPLIT(32, 4) HH_SPLIT(32, 8)
+#undef HH_SPLIT
+    set_error("coarse-solve variant %d", choice);
+    return HH_ERR_ARG;
+}
+
+static bool valid_choice(int c) {
+    if (c == 1 || c == 2 || c == 4 || c == 8) return true;
+    const int rs = c / 100, r = c % 100;
+    return (rs == 8 || rs == 16 || rs == 32) && (r == 1 || r == 2 || r == 4 || r == 8);
+}
+
+bool coarse_choice_valid(int c) { return valid_choice(c); }
+
+// the split solve's timeout flag: reported (and cleared) after a solve
+hh_status coarse_check_err(hh_model* md) {
+    int e = 0;
+    HH_HIP(hipMemcpyAsync(&e, md->coarse_err.ptr, sizeof(int), hipMemcpyDeviceToHost, md->ctx->stream));
+    HH_HIP(hipStreamSynchronize(md->ctx->stream));
+    if (e) {
+        HH_HIP(hipMemsetAsync(md->coarse_err.ptr, 0, sizeof(int), md->ctx->stream));
+        HH_HIP(hipStreamSynchronize(md->ctx->stream));
+        set_error("coarse solve: a step wait of the split solve timed out (results invalid)");
+        return HH_ERR_HIP;
+    }
+    return HH_OK;
+}
+
+// bucket of an active right-hand-side count: ceil(log2(n)), n >= 1
+static int coarse_bucket(int n) {
+    int b = 0;
+    while ((1 << b) < n && b < HH_COARSE_BUCKETS - 1) ++b;
+    return b;
+}
+
+// Autotuner of the coarse solve: for each bucket of active right-hand sides,
+// time every variant (chain with R right-hand sides per workgroup, split with
+// RS rows per workgroup; fwd + bwd, second of two runs, HIP events on the
+// context's stream) on the call's own data and keep the fastest.  The timed
+// launches only write the solve's outputs, which the real launch then rewrites.
+static hh_status coarse_pick(hh_model* md, int nact, const float2* bcs, float2* x, float2* ends, const int* slots,
+                             int nslots, const int* nslots_dev, int m, int p, float c, const int* inst,
+                             const int* active, const CoarseWork& cw, int* choice_out) {
+    if (md->coarse_R_forced > 0) {
+        *choice_out = md->coarse_R_forced;
+        return HH_OK;
+    }
+    const int b = coarse_bucket(std::max(nact, 1));
+    if (md->coarse_R[b] > 0) {
+        *choice_out = md->coarse_R[b];
+        return HH_OK;
+    }
+    std::vector<int> cand;
+    for (int R = 1; R <= CS_RMAX; R *= 2) {
+        if (R > 1 && R / 2 >= nact) break;  // groups larger than the work
+        cand.push_back(R);
+        for (int rs = 8; rs <= 32; rs *= 2) cand.push_back(100 * rs + R);
+    }
+    hh_ctx* ctx = md->ctx;
+    hipEvent_t e0, e1;
+    HH_HIP(hipEventCreate(&e0));
+    HH_HIP(hipEventCreate(&e1));
+    int best = 1;
+    float best_ms = 1e30f;
+    hh_status st = HH_OK;
+    for (int cidx = 0; cidx < (int)cand.size() && st == HH_OK; ++cidx) {
+        float ms = 0.f;
+        bool fits = true;
+        for (int rep = 0; rep < 2 && st == HH_OK && fits; ++rep) {
+            if (hipEventRecord(e0, ctx->stream) != hipSuccess) st = HH_ERR_HIP;
+            if (st == HH_OK)
+                st = launch_coarse_choice(cand[cidx], md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, p, c,
+                                          active, cw, &fits);
+            if (st == HH_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = HH_ERR_HIP;
+        }
+        if (st == HH_OK && fits && ms < best_ms) {
+            best_ms = ms;
+            best = cand[cidx];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HH_OK) {
+        if (!hh_last_error()[0]) set_error("coarse-solve autotuning failed");
+        return st;
+    }
+    md->coarse_R[b] = best;
+    *choice_out = best;
+    return HH_OK;
+}
 
 hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, const float2* b, size_t bstride,
                                 const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
@@ -548,6 +1057,7 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
     float2* ends = (float2*)wp;
     wp += 2 * (size_t)nrhs * md->lev[L - 1].n * sizeof(float2);
     float2* x1 = x0 ? (float2*)wp : nullptr;
+    const CoarseWork cw = coarse_work(md, (char*)work + vcycle_float_bytes(md, nrhs, x0 != nullptr), nrhs);
     // down sweep
     for (int l = 0; l < L - 1; ++l) {
         const Level& lv = md->lev[l];
@@ -575,17 +1085,29 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         ProfScope ps(md->ctx, HH_K_VC_COARSE);
         const int m = lc.n, p = m / 2;
         const float c = (float)(1.0 / (lc.h * lc.h));
-        // every block serves CS_R right-hand sides of one slowness model; with a
-        // single model the natural order already groups them
-        const int* order = bm.order;
-        const int nslots = bm.order ? bm.nslots : nrhs;
-        dim3 grd((nslots + CS_R - 1) / CS_R, 2);
-        hipLaunchKernelGGL(k_coarse_fwd, grd, dim3(CS_NT), 0, st, bl[L - 1], el[L - 1], ends,
-                           md->coarseQT.as<float2>(), inst_dev, order, nslots, m, p, c, active);
-        HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_coarse_bwd, grd, dim3(CS_NT), 0, st, bl[L - 1], el[L - 1], ends,
-                           md->coarseQT.as<float2>(), inst_dev, order, nslots, m, p, c, active);
-        HH_LAUNCH_CHECK();
+        // every workgroup serves R right-hand sides of one slowness model: with
+        // several models the host's grouping order (padded per model to
+        // CS_RMAX); with one model the active right-hand sides, packed
+        const int* slots = bm.order;
+        int nslots = bm.order ? bm.nslots : nrhs;
+        const int* nslots_dev = nullptr;
+        if (!bm.order && active) {
+            hipLaunchKernelGGL(k_coarse_compact, dim3(1), dim3(1024), 0, st, active, nrhs, cw.slots, cw.count);
+            HH_LAUNCH_CHECK();
+            slots = cw.slots;
+            nslots_dev = cw.count;
+            if (bm.nact > 0) nslots = std::min(nslots, bm.nact);
+        }
+        const int nact = bm.nact > 0 ? std::min(bm.nact, nrhs) : nrhs;
+        int choice = 1;
+        HH_TRY(coarse_pick(md, nact, bl[L - 1], el[L - 1], ends, slots, nslots, nslots_dev, m, p, c, inst_dev,
+                           active, cw, &choice));
+        bool fits = true;
+        HH_TRY(launch_coarse_choice(choice, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots, nslots_dev, m,
+                                    p, c, active, cw, &fits));
+        if (!fits)  // a forced split variant that cannot be resident here: the chain
+            HH_TRY(launch_coarse_choice(1, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots, nslots_dev, m,
+                                        p, c, active, cw, &fits));
     }
     // up sweep
     for (int l = L - 2; l >= 0; --l) {

@@ -1683,6 +1683,7 @@ extern "C" hh_status hh_gen_training_pairs(hh_ctx* ctx, hh_model* m, int nb, con
     hh_status s = fgmres_solve(m, W, bm, bb.as<float2>(), xt.as<double2>(), o, nullptr, nullptr);
     W.caps_dev = nullptr;
     if (s < 0) return s;
+    HH_TRY(coarse_check_err(m));
     // e = x - x~, r = A e
     hipLaunchKernelGGL(k_err_pair, dim3((unsigned)(((size_t)nb * nn + 255) / 256)), dim3(256), 0, st,
                        (const float2*)x_dev, xt.as<double2>(), (float2*)e_dev, (size_t)nb * nn);

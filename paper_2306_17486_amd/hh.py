@@ -97,6 +97,9 @@ hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, 
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
 hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
 hh_gen_training_pairs = _sig("hh_gen_training_pairs", _I, _P, _P, _I, _P, _IP, _P, _P)
+hh_residual_norms = _sig("hh_residual_norms", _I, _P, _P, _I, _IP, _P, _P, _DP)
+hh_model_set_coarse_group = _sig("hh_model_set_coarse_group", _I, _P, _I)
+hh_model_coarse_group = _sig("hh_model_coarse_group", _I, _P, _I)
 hh_train_step = _sig("hh_train_step", _I, _P, _P, _P, _I, _P, _P, _D, _D, _DP, _DP)
 hh_eval_loss = _sig("hh_eval_loss", _I, _P, _P, _P, _I, _P, _P, _DP)
 hh_net_get_grads = _sig("hh_net_get_grads", _I, _P, _FP)
@@ -226,6 +229,22 @@ class Model:
         x = torch.empty_like(b)
         check(hh_apply_vcycle(self.handle, b.shape[0], _int_array(inst), _ptr(b), _ptr(x0), _ptr(x)))
         return x
+
+    def residual_norms(self, b: torch.Tensor, x: torch.Tensor, inst=None) -> np.ndarray:
+        """||b - A x|| / ||b|| (FP64) of solutions x (complex128) for right-hand sides b."""
+        b = b.to(torch.complex64).contiguous()
+        x = x.to(torch.complex128).contiguous()
+        out = np.zeros(b.shape[0])
+        check(hh_residual_norms(self.ctx.handle, self.handle, b.shape[0], _int_array(inst), _ptr(b), _ptr(x),
+                                out.ctypes.data_as(_DP)))
+        return out
+
+    def set_coarse_group(self, R: int):
+        """Fix the coarse solve's right-hand sides per workgroup (1, 2, 4, 8) or autotune (0)."""
+        check(hh_model_set_coarse_group(self.handle, R))
+
+    def coarse_group(self, nact: int) -> int:
+        return hh_model_coarse_group(self.handle, nact)
 
     def attach_net(self, net: "Net | None"):
         check(hh_model_attach_net(self.handle, net.handle if net is not None else None))

@@ -169,3 +169,69 @@ def test_bad_arguments_raise(hh, ctx):
         m.solve(_dev(np.zeros((1, 32, 32))), restart=40)
     with pytest.raises(hh.HHError):
         m.solve(_dev(np.zeros((1, 32, 32))), precond=hh.HH_PRECOND_CNN_MG)
+
+
+# chain variants R, split variants 100 RS + R (RS rows of each Schur inverse per workgroup)
+COARSE_VARIANTS = [1, 2, 4, 8, 801, 808, 1601, 1604, 3202, 3208]
+
+
+@pytest.mark.parametrize("R", COARSE_VARIANTS)
+def test_coarse_group_sizes_vcycle_parity(hh, ctx, R):
+    # 11 right-hand sides: full groups and a ragged last group for every R; one
+    # and two slowness models (grouping order padded per model); coarse grids of
+    # 32 and 16 points (split slices with and without empty rows)
+    n = 128
+    _say(f"coarse solve variant {R}")
+    k = inputs.slowness(n, 13, "layered")
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.set_coarse_group(R)
+    assert m.coarse_group(11) == R
+    b = inputs.random_complex((11, n, n), 17)
+    z = m.apply_vcycle(_dev(b)).cpu().numpy()
+    ref = np.stack([prob.hier.vcycle(b[i]) for i in range(11)])
+    assert _rel(z, ref) <= 2e-5, _rel(z, ref)
+    ks = [inputs.grf_slowness(64, 1), inputs.layered_slowness(64, 2)]
+    m2 = hh.Model(ctx, torch.from_numpy(np.stack(ks)), inputs.omega_for(64))
+    m2.set_coarse_group(R)
+    inst = [1, 0, 0, 1, 1, 0, 1]
+    b2 = inputs.random_complex((7, 64, 64), 18)
+    z2 = m2.apply_vcycle(_dev(b2), inst=inst).cpu().numpy()
+    for r in range(7):
+        assert _rel(z2[r], H.Problem(ks[inst[r]], inputs.omega_for(64)).hier.vcycle(b2[r])) <= 2e-5
+
+
+def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
+    # right-hand sides that converge at different iterations leave ragged active
+    # sets: the packed coarse solve must still give every RHS the oracle's count.
+    # RHS 2 finishes a restart cycle before the others: its returned solution must
+    # not change after its convergence test (regression: finished RHS once took
+    # their last correction again in every later cycle)
+    n = 64
+    _say("coarse autotuner and active packing")
+    k = inputs.grf_slowness(n, 40)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    b = np.stack([inputs.point_source(n, 60 + i) for i in range(6)] + [inputs.random_complex((n, n), 66)])
+    its_o = [H.solve_mg(prob, b[r])[1] for r in range(7)]
+    bad = []
+    for R in (0, 1, 8, 802, 1608):
+        m = hh.Model(ctx, torch.from_numpy(k), om)
+        m.set_coarse_group(R)
+        xd, info = m.solve(_dev(b))
+        lib = m.residual_norms(_dev(b), xd)
+        x = xd.cpu().numpy()
+        for r in range(7):
+            res = np.linalg.norm(b[r] - prob.A(x[r])) / np.linalg.norm(b[r])
+            # the library applies A with FP32 coefficients: on these solutions that
+            # operator differs from the FP64 one by about 4e-8 of ||b||
+            assert abs(lib[r] - res) <= 1e-7
+            assert abs(info["final_res"][r] - res) <= 1e-7
+            _say(f"  R={R} rhs {r}: iters {info['iters'][r]} (oracle {its_o[r]}) gpu residual "
+                 f"{info['final_res'][r]:.3e} host residual {res:.3e}")
+            if not (info["converged"][r] and res <= 1e-6 and abs(int(info["iters"][r]) - its_o[r]) <= 2):
+                bad.append((R, r))
+        if R == 0:
+            assert m.coarse_group(7) in (1, 2, 4, 8)
+    assert not bad, bad
