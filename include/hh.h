@@ -87,6 +87,11 @@ typedef struct {
     int levels;            /* multigrid levels (Sec. 3.2), default 3, 2..HH_MAX_LEVELS */
     int nu_pre, nu_post;   /* damped-Jacobi sweeps before/after the coarse correction, 1/1 */
     double jacobi_w;       /* Jacobi damping, default 0.8 */
+    int coarse_reduce;     /* coarsest exact solve: 1 (default) eliminates the odd grid rows by
+                              their tridiagonal inverses first (one level of cyclic reduction)
+                              and runs the two-ended block elimination on the even rows (half
+                              the sequential chain, about twice the factor memory); 0 runs the
+                              two-ended elimination on all grid rows */
 } hh_model_desc;
 
 /* Fill *d with the defaults listed above (n and omega are set to 0). */

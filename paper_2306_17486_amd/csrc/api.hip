@@ -143,6 +143,7 @@ void hh_model_desc_default(hh_model_desc* d) {
     d->nu_pre = 1;
     d->nu_post = 1;
     d->jacobi_w = 0.8;
+    d->coarse_reduce = 1;
 }
 
 hh_status hh_model_create(hh_ctx* ctx, const hh_model_desc* d, int ninst, const float* kappa_dev, hh_model** out) {
@@ -313,7 +314,9 @@ hh_status hh_residual_norms(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_
 
 hh_status hh_model_set_coarse_group(hh_model* m, int R) {
     HH_ARG(m, "null pointer");
-    HH_ARG(R == 0 || coarse_choice_valid(R), "variant 0 (autotune), R = 1, 2, 4, 8 or 100 RS + R, RS = 8, 16, 32");
+    HH_ARG(R == 0 || coarse_choice_valid(m, R),
+           "variant 0 (autotune); R = 1, 2, 4, 8 or 100 RS + R (RS = 8, 16, 32) for the plain factorisation; "
+           "1000 + R for the reduced one");
     m->coarse_R_forced = R;
     if (R == 0)
         for (int b = 0; b < HH_COARSE_BUCKETS; ++b) m->coarse_R[b] = 0;

@@ -137,7 +137,8 @@ struct hh_model {
     int ninst = 0;
     int nlev = 0;
     hh::Level lev[HH_MAX_LEVELS];
-    hh::Buf coarseQT;      // float2 [ninst][m][m][m]: block-LU Schur inverses, transposed
+    hh::Buf coarseQT;      // coarse factors, transposed complex singles: [ninst][m][m][m] Schur inverses of the
+                           // two-ended elimination, or (cr1) [ninst][4 ceil(m/2)][m][m] reduced-solve slots
     int m = 0;             // coarsest points per dimension
     hh::Buf kfeat;         // encoder input features (bf16 NHWC, 2 channels) when a net is attached
     hh_net* net = nullptr; // attached network (not owned)
@@ -145,6 +146,7 @@ struct hh_model {
     int coarse_R[HH_COARSE_BUCKETS] = {0};  // coarse-solve variant per active-count bucket (0 = not tuned)
     int coarse_R_forced = 0;                // fixed variant (R, or 100 RS + R for the split solve); 0: autotuned
     hh::Buf coarse_err;                     // device int: a split-solve wait timed out
+    bool cr1 = false;                       // coarseQT holds the reduced factorisation (one level of cyclic reduction)
 };
 
 // ---------------------------------------------------------------------------
@@ -248,7 +250,7 @@ hh_status launch_vcycle_strided(hh_model* m, int nrhs, const BatchMap& bm, const
                                 size_t zstride, void* work, const int* active);
 // RHS per workgroup of the coarsest solve (the grouping unit of BatchMap::order)
 int coarse_group();
-bool coarse_choice_valid(int c);
+bool coarse_choice_valid(const hh_model* md, int c);
 hh_status coarse_check_err(hh_model* md);
 // copy a host RHS -> slowness-model map to the device (api.hip)
 hh_status upload_inst_map(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out);

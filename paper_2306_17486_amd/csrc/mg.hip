@@ -523,6 +523,194 @@ __global__ void __launch_bounds__(CS_NT) k_coarse_bwd(const float2* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Coarse solve after one level of cyclic reduction (factors described in
+// setup.hip): odd grid rows by their tridiagonal inverses V_j, even rows by the
+// two-ended elimination of the reduced system, whose chain is half as long.
+// Per instance the factors are slots of m x m transposed complex singles:
+// j (Q_j), M + j (P_j), 2M + j (R_j), 3M + j (V_j).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int crM(int m) { return (m + 1) / 2; }
+__device__ __forceinline__ int crMo(int m) { return m / 2; }
+
+// PH 1: t_j = V_j b_{2j+1}                         (j < Mo)
+// PH 2: g_j = Q_j (b_{2j} + c (t_{j-1} + t_j))     (j < M; terms beyond the rows vanish)
+// PH 3: x_{2j+1} = V_j (b_{2j+1} + c (x_{2j} + x_{2j+2}))   (j < Mo)
+// blockIdx.x = right-hand-side group, blockIdx.y = reduced row j.
+template <int R, int PH>
+__global__ void __launch_bounds__(CS_NT) k_cr_par(const float2* __restrict__ bcs, float2* __restrict__ x,
+                                                  float2* __restrict__ tw, float2* __restrict__ gw,
+                                                  const float2* __restrict__ F, const int* __restrict__ inst,
+                                                  const int* __restrict__ slots, int nslots,
+                                                  const int* __restrict__ nslots_dev, int m, float c,
+                                                  const int* __restrict__ active) {
+    extern __shared__ float2 s_lds[];
+    float2* s_v = s_lds;
+    float2* s_part = s_lds + R * m;
+    const int M = crM(m), Mo = crMo(m);
+    const int j = blockIdx.y;
+    if (j >= (PH == 2 ? M : Mo)) return;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
+    if (!g.any) return;
+    const size_t mm = (size_t)m * m;
+    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const float2* Mat = Fi + (size_t)(PH == 2 ? j : 3 * M + j) * mm;
+    const CoarseMV<R> mv(m);
+    if (mv.owner()) {
+        const int i = mv.row;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float2 w = make_float2(0.f, 0.f);
+            if (g.on[q]) {
+                const size_t rb = (size_t)g.rr[q] * mm;
+                if (PH == 1) {
+                    w = bcs[rb + (size_t)(2 * j + 1) * m + i];
+                } else if (PH == 2) {
+                    const float2* t = tw + (size_t)g.rr[q] * Mo * m;
+                    w = bcs[rb + (size_t)(2 * j) * m + i];
+                    float2 a = make_float2(0.f, 0.f);
+                    if (j >= 1) a = t[(size_t)(j - 1) * m + i];
+                    if (j < Mo) a = cadd(a, t[(size_t)j * m + i]);
+                    w = cadd(w, cscale(a, c));
+                } else {
+                    float2 a = x[rb + (size_t)(2 * j) * m + i];
+                    if (2 * j + 2 <= m - 1) a = cadd(a, x[rb + (size_t)(2 * j + 2) * m + i]);
+                    w = cadd(bcs[rb + (size_t)(2 * j + 1) * m + i], cscale(a, c));
+                }
+            }
+            s_v[q * m + i] = w;
+        }
+    }
+    __syncthreads();
+    float2 out[R];
+    mv.apply(Mat, s_v, s_part, out);
+    if (mv.owner()) {
+        const int i = mv.row;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (!g.on[q]) continue;
+            if (PH == 1) tw[((size_t)g.rr[q] * Mo + j) * m + i] = out[q];
+            else if (PH == 2) gw[((size_t)g.rr[q] * M + j) * m + i] = out[q];
+            else x[(size_t)g.rr[q] * mm + (size_t)(2 * j + 1) * m + i] = out[q];
+        }
+    }
+}
+
+// forward chains of the reduced system: y_j = g_j + P_j y_{j -/+ 1}; y_j -> x row 2j.
+template <int R>
+__global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw, float2* __restrict__ x,
+                                                  float2* __restrict__ ends, const float2* __restrict__ F,
+                                                  const int* __restrict__ inst, const int* __restrict__ slots,
+                                                  int nslots, const int* __restrict__ nslots_dev, int m,
+                                                  const int* __restrict__ active) {
+    extern __shared__ float2 s_lds[];
+    float2* s_v = s_lds;
+    float2* s_part = s_lds + R * m;
+    const int M = crM(m), p = M / 2;
+    const bool top = blockIdx.y == 0;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
+    if (!g.any) return;
+    const size_t mm = (size_t)m * m;
+    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const CoarseMV<R> mv(m);
+    const int nsteps = top ? p : (M - 1 - p);
+    for (int s = 0; s < nsteps; ++s) {
+        const int j = top ? s : (M - 1 - s);
+        float2 out[R];
+        if (s > 0) mv.apply(Fi + (size_t)(M + j) * mm, s_v, s_part, out);
+        __syncthreads();
+        if (mv.owner()) {
+            const int i = mv.row;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                float2 y = make_float2(0.f, 0.f);
+                if (g.on[q]) {
+                    y = gw[((size_t)g.rr[q] * M + j) * m + i];
+                    if (s > 0) y = cadd(y, out[q]);
+                    x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + i] = y;
+                    if (s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + i] = y;
+                }
+                s_v[q * m + i] = y;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// middle row and backward chains: x_p = g_p + P_p y_{p-1} + R_p y_{p+1};
+// x_j = y_j + R_j x_{j +/- 1} (y_j read from, x_j written to, x row 2j).
+template <int R>
+__global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw, float2* __restrict__ x,
+                                                  const float2* __restrict__ ends, const float2* __restrict__ F,
+                                                  const int* __restrict__ inst, const int* __restrict__ slots,
+                                                  int nslots, const int* __restrict__ nslots_dev, int m,
+                                                  const int* __restrict__ active) {
+    extern __shared__ float2 s_lds[];
+    float2* s_v = s_lds;
+    float2* s_part = s_lds + R * m;
+    const int M = crM(m), p = M / 2;
+    const bool top = blockIdx.y == 0;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
+    if (!g.any) return;
+    const size_t mm = (size_t)m * m;
+    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const CoarseMV<R> mv(m);
+    float2 acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
+    // middle row, computed by both workgroups
+    for (int side = 0; side < 2; ++side) {
+        const bool has = side == 0 ? (p >= 1) : (p + 1 <= M - 1);
+        if (!has) continue;
+        if (mv.owner())
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                s_v[q * m + mv.row] =
+                    g.on[q] ? ends[((size_t)g.rr[q] * 2 + side) * m + mv.row] : make_float2(0.f, 0.f);
+        __syncthreads();
+        float2 out[R];
+        mv.apply(Fi + (size_t)((side == 0 ? M : 2 * M) + p) * mm, s_v, s_part, out);
+        __syncthreads();
+        if (mv.owner())
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], out[q]);
+    }
+    if (mv.owner()) {
+        const int i = mv.row;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float2 v = make_float2(0.f, 0.f);
+            if (g.on[q]) {
+                v = cadd(gw[((size_t)g.rr[q] * M + p) * m + i], acc[q]);
+                if (top) x[(size_t)g.rr[q] * mm + (size_t)(2 * p) * m + i] = v;
+            }
+            s_v[q * m + i] = v;
+        }
+    }
+    __syncthreads();
+    const int nsteps = top ? p : (M - 1 - p);
+    for (int s = 0; s < nsteps; ++s) {
+        const int j = top ? (p - 1 - s) : (p + 1 + s);
+        float2 out[R];
+        mv.apply(Fi + (size_t)(2 * M + j) * mm, s_v, s_part, out);
+        __syncthreads();
+        if (mv.owner()) {
+            const int i = mv.row;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                float2 v = make_float2(0.f, 0.f);
+                if (g.on[q]) {
+                    const size_t o = (size_t)g.rr[q] * mm + (size_t)(2 * j) * m + i;
+                    v = cadd(x[o], out[q]);
+                    x[o] = v;
+                }
+                s_v[q * m + i] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Split coarse solve.  One chain step streams a whole m x m Schur inverse; a
 // single workgroup cannot pull that faster than one CU's share of the memory
 // system, so here the rows of every Q_k are shared by S workgroups ("slices")
@@ -582,33 +770,42 @@ __device__ __forceinline__ float2 load_agent(const float2* p) {
     return r;
 }
 
-// rows row0 .. row0 + RS - 1 of Q_k v for the R vectors s_w[q * m + j]; the
-// CSP_NT / RS column parts meet in s_part.  Results in threads t < RS (wave 0).
-template <int R, int RS>
-__device__ __forceinline__ void split_matvec(const float2* __restrict__ Qk, const float2* s_w, float2* s_part, int m,
-                                             int row0, float2 (&out)[R]) {
+// This thread's share of rows row0 .. row0 + RS - 1 of Q_k: row row0 + t % RS,
+// columns j0 .. j0 + jlen - 1 with jlen = ceil(m / (CSP_NT / RS)) <= CSP_CMAX.
+// Loaded one step ahead (Q_{k+1} does not depend on the chain), so the loads
+// are in flight while the workgroup waits for its partners.
+constexpr int CSP_CMAX = 32;
+
+template <int RS>
+__device__ __forceinline__ void split_load_q(const float2* __restrict__ Qk, int m, int row0,
+                                             float2 (&qr)[CSP_CMAX]) {
     constexpr int JP = CSP_NT / RS;
     const int t = threadIdx.x, lr = t % RS, jp = t / RS;
-    const int jlen = (m + JP - 1) / JP, j0 = jp * jlen, j1 = min(m, j0 + jlen);
+    const int jlen = (m + JP - 1) / JP, j0 = jp * jlen;
+    const bool row_ok = row0 + lr < m;
+    const float2* qp = Qk + row0 + lr;
+#pragma unroll
+    for (int u = 0; u < CSP_CMAX; ++u)
+        qr[u] = (row_ok && u < jlen && j0 + u < m) ? qp[(size_t)(j0 + u) * m] : make_float2(0.f, 0.f);
+}
+
+// rows row0 .. row0 + RS - 1 of Q_k v for the R vectors s_w[q * m + j], Q_k's
+// share in registers; the CSP_NT / RS column parts meet in s_part.  Results
+// in threads t < RS (wave 0).
+template <int R, int RS>
+__device__ __forceinline__ void split_compute(const float2 (&qr)[CSP_CMAX], const float2* s_w, float2* s_part, int m,
+                                              float2 (&out)[R]) {
+    constexpr int JP = CSP_NT / RS;
+    const int t = threadIdx.x, lr = t % RS, jp = t / RS;
+    const int jlen = (m + JP - 1) / JP, j0 = jp * jlen;
     float2 acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
-    if (row0 + lr < m) {
-        const float2* qp = Qk + row0 + lr;
-        int j = j0;
-        for (; j + 4 <= j1; j += 4) {
-            float2 qv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) qv[u] = qp[(size_t)(j + u) * m];
+    for (int u = 0; u < CSP_CMAX; ++u) {
+        if (u < jlen && j0 + u < m) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qv[u], s_w[q * m + j + u]));
-        }
-        for (; j < j1; ++j) {
-            const float2 qv = qp[(size_t)j * m];
-#pragma unroll
-            for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qv, s_w[q * m + j]));
+            for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qr[u], s_w[q * m + j0 + u]));
         }
     }
 #pragma unroll
@@ -650,6 +847,8 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_fwd(const float2* __res
     const float2* Q = QT + (size_t)(inst ? inst[g.r0] : 0) * mm * m;
     const int row0 = slice * RS;
     const int nsteps = top ? p : (m - 1 - p);
+    float2 qr[CSP_CMAX];
+    if (nsteps > 0) split_load_q<RS>(Q + (size_t)(top ? 0 : m - 1) * mm, m, row0, qr);
     for (int s = 0; s < nsteps; ++s) {
         const int k = top ? s : (m - 1 - s);
         if (s > 0) split_wait(cnt + unit, geo.S * s, err);
@@ -665,7 +864,7 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_fwd(const float2* __res
         }
         __syncthreads();
         float2 out[R];
-        split_matvec<R, RS>(Q + (size_t)k * mm, s_w, s_part, m, row0, out);
+        split_compute<R, RS>(qr, s_w, s_part, m, out);
         const int row = row0 + threadIdx.x;
         if (threadIdx.x < RS && row < m) {
 #pragma unroll
@@ -678,6 +877,7 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_fwd(const float2* __res
             }
         }
         split_arrive(cnt + unit);
+        if (s + 1 < nsteps) split_load_q<RS>(Q + (size_t)(top ? k + 1 : k - 1) * mm, m, row0, qr);
     }
 }
 
@@ -702,6 +902,9 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
     const float2* Q = QT + (size_t)(inst ? inst[g.r0] : 0) * mm * m;
     const int row0 = slice * RS;
     const int row = row0 + threadIdx.x;
+    const int nsteps = top ? p : (m - 1 - p);
+    float2 qr[CSP_CMAX];
+    split_load_q<RS>(Q + (size_t)p * mm, m, row0, qr);
     // middle row (round 0): x_p = Q_p (b_p + c y_{p-1} + c y_{p+1}); both ends compute it
     for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
         const int q = e / m, j = e - q * m;
@@ -716,7 +919,7 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
     __syncthreads();
     {
         float2 out[R];
-        split_matvec<R, RS>(Q + (size_t)p * mm, s_w, s_part, m, row0, out);
+        split_compute<R, RS>(qr, s_w, s_part, m, out);
         if (threadIdx.x < RS && row < m) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -725,8 +928,8 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
             }
         }
         split_arrive(cnt + unit);
+        if (nsteps > 0) split_load_q<RS>(Q + (size_t)(top ? p - 1 : p + 1) * mm, m, row0, qr);
     }
-    const int nsteps = top ? p : (m - 1 - p);
     for (int s = 0; s < nsteps; ++s) {
         const int k = top ? (p - 1 - s) : (p + 1 + s);
         split_wait(cnt + unit, geo.S * (s + 1), err);
@@ -736,7 +939,7 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
         }
         __syncthreads();
         float2 out[R];
-        split_matvec<R, RS>(Q + (size_t)k * mm, s_w, s_part, m, row0, out);
+        split_compute<R, RS>(qr, s_w, s_part, m, out);
         if (threadIdx.x < RS && row < m) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -749,6 +952,7 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
             }
         }
         split_arrive(cnt + unit);
+        if (s + 1 < nsteps) split_load_q<RS>(Q + (size_t)(top ? k - 1 : k + 1) * mm, m, row0, qr);
     }
 }
 
@@ -792,15 +996,18 @@ struct CoarseWork {
     int* count;
     int* cnt;
     float2* xch;
+    float2* tw;  // reduced solve: V_j b_{2j+1}, [rhs][Mo][m]
+    float2* gw;  // reduced solve: g_j, [rhs][M][m]
 };
 static size_t coarse_work_bytes(const hh_model* md, int nrhs) {
     const size_t ns = (size_t)coarse_slot_bound(md, nrhs);
     const int m = md->lev[md->nlev - 1].n;
     return (ns + 64) * sizeof(int) + 4 * (ns + CS_RMAX) * sizeof(int) + 256 +
-           4 * (ns + CS_RMAX) * (size_t)m * sizeof(float2);
+           4 * (ns + CS_RMAX) * (size_t)m * sizeof(float2) + 256 + (size_t)nrhs * m * m * sizeof(float2);
 }
 static CoarseWork coarse_work(const hh_model* md, void* base, int nrhs) {
     const size_t ns = (size_t)coarse_slot_bound(md, nrhs);
+    const int m = md->lev[md->nlev - 1].n;
     CoarseWork w;
     char* q = (char*)base;
     w.slots = (int*)q;
@@ -810,6 +1017,10 @@ static CoarseWork coarse_work(const hh_model* md, void* base, int nrhs) {
     q += 4 * (ns + CS_RMAX) * sizeof(int);
     q = (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
     w.xch = (float2*)q;
+    q += 4 * (ns + CS_RMAX) * (size_t)m * sizeof(float2);
+    q = (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    w.tw = (float2*)q;
+    w.gw = w.tw + (size_t)nrhs * (m / 2) * m;
     return w;
 }
 
@@ -874,6 +1085,10 @@ static hh_status launch_split_t(hh_model* md, const float2* bcs, float2* x, floa
                                    hipFuncAttributeMaxDynamicSharedMemorySize, want));
         attr_devices |= 1u << ctx->device;
     }
+    if ((m + CSP_NT / RS - 1) / (CSP_NT / RS) > CSP_CMAX) {  // column share exceeds the registers
+        *fits = false;
+        return HH_OK;
+    }
     SplitGeom geo;
     geo.G = (nslots + R - 1) / R;
     geo.S = (m + RS - 1) / RS;
@@ -929,12 +1144,87 @@ static hh_status launch_split_t(hh_model* md, const float2* bcs, float2* x, floa
     return HH_OK;
 }
 
+// ---- reduced solve (one level of cyclic reduction, then the two-ended chains) ----
+template <int R>
+static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
+                             const int* slots, int nslots, const int* nslots_dev, int m, float c, const int* active,
+                             const CoarseWork& cw) {
+    hh_ctx* ctx = md->ctx;
+    static unsigned attr_devices = 0;
+    // the row-parallel phases serve CS_RMAX right-hand sides per workgroup
+    // whatever R the chains use: their matrices are then read CS_RMAX times
+    // fewer (slot groups of CS_RMAX never mix models: the grouping order is
+    // padded per model to CS_RMAX)
+    constexpr int RP = CS_RMAX;
+    const size_t lds = coarse_lds_bytes(R, m), ldsp = coarse_lds_bytes(RP, m);
+    if (!(attr_devices & (1u << ctx->device))) {
+        size_t most = 0, mostp = 0;
+        for (int mm_ = 4; mm_ <= CS_MAXM; ++mm_) {
+            most = std::max(most, coarse_lds_bytes(R, mm_));
+            mostp = std::max(mostp, coarse_lds_bytes(RP, mm_));
+        }
+        if (mostp > 65536) {
+            const int want = (int)mostp;
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_par<RP, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_par<RP, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_par<RP, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+        }
+        if (most > 65536) {
+            const int want = (int)most;
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_fwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_bwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+        }
+        attr_devices |= 1u << ctx->device;
+    }
+    const int G = (nslots + R - 1) / R, GP = (nslots + RP - 1) / RP;
+    const int M = (m + 1) / 2, Mo = m / 2;
+    const float2* F = md->coarseQT.as<float2>();
+    hipStream_t st = ctx->stream;
+    if (Mo > 0) {
+        hipLaunchKernelGGL((k_cr_par<RP, 1>), dim3(GP, Mo), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst,
+                           slots, nslots, nslots_dev, m, c, active);
+        HH_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL((k_cr_par<RP, 2>), dim3(GP, M), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst, slots,
+                       nslots, nslots_dev, m, c, active);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_cr_fwd<R>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, x, ends, F, inst, slots, nslots,
+                       nslots_dev, m, active);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_cr_bwd<R>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, x, ends, F, inst, slots, nslots,
+                       nslots_dev, m, active);
+    HH_LAUNCH_CHECK();
+    if (Mo > 0) {
+        hipLaunchKernelGGL((k_cr_par<RP, 3>), dim3(GP, Mo), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst,
+                           slots, nslots, nslots_dev, m, c, active);
+        HH_LAUNCH_CHECK();
+    }
+    return HH_OK;
+}
+
 // choice: R (1, 2, 4, 8) = chain with R right-hand sides per workgroup;
-// 100 RS + R = split with RS rows per workgroup (RS = 8, 16, 32)
+// 100 RS + R = split with RS rows per workgroup (RS = 8, 16, 32);
+// 1000 + R = the reduced solve (models factorised with one level of cyclic reduction)
+// the reduced solve's codes (1001..1008) lie between the split codes with RS = 8
+// (801..808) and those with RS = 16 (1601..1608)
+static inline bool reduced_code(int c) { return c > 1000 && c < 1100; }
+
 static hh_status launch_coarse_choice(int choice, hh_model* md, const float2* bcs, float2* x, float2* ends,
                                       const int* inst, const int* slots, int nslots, const int* nslots_dev, int m,
                                       int p, float c, const int* active, const CoarseWork& cw, bool* fits) {
     *fits = true;
+    if (reduced_code(choice)) {
+        const float cc = c;
+        switch (choice - 1000) {
+            case 1: return launch_cr_t<1>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, cc, active, cw);
+            case 2: return launch_cr_t<2>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, cc, active, cw);
+            case 4: return launch_cr_t<4>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, cc, active, cw);
+            case 8: return launch_cr_t<8>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, cc, active, cw);
+            default: break;
+        }
+        set_error("coarse-solve variant %d", choice);
+        return HH_ERR_ARG;
+    }
     if (choice < 100)
         return launch_coarse(choice, md->ctx, bcs, x, ends, md->coarseQT.as<float2>(), inst, slots, nslots,
                              nslots_dev, m, p, c, active);
@@ -952,11 +1242,13 @@ static hh_status launch_coarse_choice(int choice, hh_model* md, const float2* bc
 
 static bool valid_choice(int c) {
     if (c == 1 || c == 2 || c == 4 || c == 8) return true;
+    if (reduced_code(c)) return c == 1001 || c == 1002 || c == 1004 || c == 1008;
     const int rs = c / 100, r = c % 100;
     return (rs == 8 || rs == 16 || rs == 32) && (r == 1 || r == 2 || r == 4 || r == 8);
 }
 
-bool coarse_choice_valid(int c) { return valid_choice(c); }
+// the reduced solve's codes need the reduced factorisation, the others the plain one
+bool coarse_choice_valid(const hh_model* md, int c) { return valid_choice(c) && (reduced_code(c) == md->cr1); }
 
 // the split solve's timeout flag: reported (and cleared) after a solve
 hh_status coarse_check_err(hh_model* md) {
@@ -999,8 +1291,12 @@ static hh_status coarse_pick(hh_model* md, int nact, const float2* bcs, float2* 
     std::vector<int> cand;
     for (int R = 1; R <= CS_RMAX; R *= 2) {
         if (R > 1 && R / 2 >= nact) break;  // groups larger than the work
-        cand.push_back(R);
-        for (int rs = 8; rs <= 32; rs *= 2) cand.push_back(100 * rs + R);
+        if (md->cr1) {
+            cand.push_back(1000 + R);
+        } else {
+            cand.push_back(R);
+            for (int rs = 8; rs <= 32; rs *= 2) cand.push_back(100 * rs + R);
+        }
     }
     hh_ctx* ctx = md->ctx;
     hipEvent_t e0, e1;
@@ -1106,8 +1402,8 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         HH_TRY(launch_coarse_choice(choice, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots, nslots_dev, m,
                                     p, c, active, cw, &fits));
         if (!fits)  // a forced split variant that cannot be resident here: the chain
-            HH_TRY(launch_coarse_choice(1, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots, nslots_dev, m,
-                                        p, c, active, cw, &fits));
+            HH_TRY(launch_coarse_choice(md->cr1 ? 1001 : 1, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots,
+                                        nslots_dev, m, p, c, active, cw, &fits));
     }
     // up sweep
     for (int l = L - 2; l >= 0; --l) {

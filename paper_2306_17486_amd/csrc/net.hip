@@ -97,29 +97,30 @@ __global__ void k_scales(const double* __restrict__ parts, int nblk, size_t N, c
 // channels (BF16-rounded) to COUT channels, + bias, + optional skip.  The input
 // is either a complex vector scaled per RHS (solver: v / rms(v)) or the
 // coefficient field (encoder: (omega h)^2 kappa^2 and (omega h)^2 kappa^2 gamma).
+// A block computes CI_TY x CI_TX outputs (two per thread) from the
+// (2 CI_TY + 1) x (2 CI_TX + 1) input patch staged once in LDS.
+constexpr int CI_TY = 8, CI_TX = 64;
 template <int SRC, int COUT>
 __global__ void __launch_bounds__(256) k_conv_in(const float2* __restrict__ src, size_t src_bstride,
                                                  const float* __restrict__ in_scale, const int* __restrict__ src_map,
                                                  float h2, const float* __restrict__ W, const float* __restrict__ bias,
                                                  const uint16_t* __restrict__ skip, const int* __restrict__ skip_map,
                                                  uint16_t* __restrict__ y, int n, const int* __restrict__ active) {
+    constexpr int PH = 2 * CI_TY + 1, PW = 2 * CI_TX + 1;
     __shared__ float s_w[COUT * 18];
     __shared__ float s_b[COUT];
-    const int b = blockIdx.y;
+    __shared__ float s_a[2][PH][PW + 1];
+    const int b = blockIdx.z;
     if (active && !active[b]) return;
+    const int m = n / 2;
+    const int oy0 = blockIdx.y * CI_TY, ox0 = blockIdx.x * CI_TX;
     for (int e = threadIdx.x; e < COUT * 18; e += 256) s_w[e] = W[e];
     for (int e = threadIdx.x; e < COUT; e += 256) s_b[e] = bias[e];
-    __syncthreads();
-    const int m = n / 2;
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= m * m) return;
-    const int oy = p / m, ox = p - oy * m;
     const float2* sb = src + (size_t)(src_map ? src_map[b] : b) * src_bstride;
     const float sc = (SRC == 0) ? in_scale[b] : 1.f;
-    float in[2][9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+    for (int e = threadIdx.x; e < PH * PW; e += 256) {
+        const int py = e / PW, px = e - py * PW;
+        const int iy = 2 * oy0 - 1 + py, ix = 2 * ox0 - 1 + px;
         float a0 = 0.f, a1 = 0.f;
         if (iy >= 0 && iy < n && ix >= 0 && ix < n) {
             const float2 v = sb[(size_t)iy * n + ix];
@@ -131,25 +132,46 @@ __global__ void __launch_bounds__(256) k_conv_in(const float2* __restrict__ src,
                 a1 = a0 * v.y;
             }
         }
-        in[0][t] = bf2f(f2bf(a0));
-        in[1][t] = bf2f(f2bf(a1));
+        s_a[0][py][px] = bf2f(f2bf(a0));
+        s_a[1][py][px] = bf2f(f2bf(a1));
     }
-    const size_t po = ((size_t)b * m * m + p) * COUT;
-    const uint16_t* sk = skip ? skip + ((size_t)(skip_map ? skip_map[b] : b) * m * m + p) * COUT : nullptr;
+    __syncthreads();
+    const int ly = threadIdx.x / (CI_TX / 2), lx0 = threadIdx.x % (CI_TX / 2);
 #pragma unroll
-    for (int c0 = 0; c0 < COUT; c0 += 8) {
-        uint16_t o[8];
+    for (int half = 0; half < 2; ++half) {
+        const int lx = lx0 + half * (CI_TX / 2);
+        const int oy = oy0 + ly, ox = ox0 + lx;
+        if (oy >= m || ox >= m) continue;
+        float in[2][9];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int co = c0 + u;
-            float acc = s_b[co];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) acc += s_w[(co * 2 + 0) * 9 + t] * in[0][t] + s_w[(co * 2 + 1) * 9 + t] * in[1][t];
-            if (sk) acc += bf2f(sk[co]);
-            o[u] = f2bf(acc);
+        for (int t = 0; t < 9; ++t) {
+            in[0][t] = s_a[0][2 * ly + t / 3][2 * lx + t % 3];
+            in[1][t] = s_a[1][2 * ly + t / 3][2 * lx + t % 3];
         }
-        *reinterpret_cast<uint4*>(y + po + c0) = *reinterpret_cast<uint4*>(o);
+        const size_t pix = (size_t)oy * m + ox;
+        const size_t po = ((size_t)b * m * m + pix) * COUT;
+        const uint16_t* sk = skip ? skip + ((size_t)(skip_map ? skip_map[b] : b) * m * m + pix) * COUT : nullptr;
+#pragma unroll
+        for (int c0 = 0; c0 < COUT; c0 += 8) {
+            uint16_t o[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int co = c0 + u;
+                float acc = s_b[co];
+#pragma unroll
+                for (int t = 0; t < 9; ++t)
+                    acc += s_w[(co * 2 + 0) * 9 + t] * in[0][t] + s_w[(co * 2 + 1) * 9 + t] * in[1][t];
+                if (sk) acc += bf2f(sk[co]);
+                o[u] = f2bf(acc);
+            }
+            *reinterpret_cast<uint4*>(y + po + c0) = *reinterpret_cast<uint4*>(o);
+        }
     }
+}
+
+static inline dim3 conv_in_grid(int n, int B) {
+    const int m = n / 2;
+    return dim3((m + CI_TX - 1) / CI_TX, (m + CI_TY - 1) / CI_TY, B);
 }
 
 // Projection layer: 3x3 stride-1 convolution CIN -> 2 channels + bias, FP32 output
@@ -596,7 +618,7 @@ hh_status encoder_forward(hh_net* net, hh_model* md, Buf* enc) {
     auto E = [&](int l) { return enc[l].as<uint16_t>(); };
     const float* P = net->params.as<float>();
     const int m1 = n / 2;
-    hipLaunchKernelGGL((k_conv_in<1, 16>), dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_conv_in<1, 16>), conv_in_grid(n, B), dim3(256), 0, st,
                        md->lev[0].coef.as<float2>(), (size_t)n * n, nullptr, nullptr, (float)(h * h),
                        P + net->L[L_ENC1_D].woff, P + net->L[L_ENC1_D].boff, nullptr, nullptr, E(L_ENC1_D), n,
                        nullptr);
@@ -674,7 +696,7 @@ hh_status net_forward_core(hh_net* net, int n, double h, NetActs& A, int B, cons
     const int m1 = n / 2, m2 = n / 4, m3 = n / 8, m4 = coarsest_of(n), s4 = coarse_stride_of(n);
     {
         ProfScope ps(net->ctx, HH_K_CONV);
-        hipLaunchKernelGGL((k_conv_in<0, 16>), dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, v, vstride, in_scale,
+        hipLaunchKernelGGL((k_conv_in<0, 16>), conv_in_grid(n, B), dim3(256), 0, st, v, vstride, in_scale,
                            nullptr, 0.f, P + net->L[L_S1_D].woff, P + net->L[L_S1_D].boff, E1,
                            smap, act(L_S1_D), n, active);
         HH_LAUNCH_CHECK();

@@ -188,6 +188,153 @@ __global__ void __launch_bounds__(256) k_conv_mfma(ConvArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Stride-2 transposed convolution by output parity.  With u the zero-interleaved
+// input (u[2i][2j] = x[i][j]), out[oy][ox] = sum_t Wg[t] u[oy + ky - 1][ox + kx - 1]
+// only meets nonzero u where oy + ky - 1 and ox + kx - 1 are even: an even output
+// row uses tap row ky = 1 only, an odd one ky = 0 and 2 (the same for columns).
+// So each 16-pixel block takes 16 outputs of one row with one column parity
+// (ox = x0 + px + 2 l); the four parity classes use 1, 2, 2 and 4 taps, 9 per
+// four outputs instead of 36.  Every chunk is one tap x 32 input channels, so
+// the weights are the same packed chunks as the interleaved form's.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+struct T2Cfg {
+    static constexpr int TC = 32;                        // output tile columns
+    static constexpr int TR = CIN >= 64 ? 4 : 8;         // output tile rows (even)
+    static constexpr int NT = COUT / 16;                 // channel tiles
+    static constexpr int WPT = 4 / NT;                   // waves per channel tile
+    static constexpr int PB = TR * 2;                    // (row, column parity) blocks
+    static constexpr int PBW = PB / WPT;                 // blocks per wave
+    static constexpr int CB = CIN / 32;                  // 32-channel blocks per tap
+    static constexpr int NCH = 9 * CB;                   // weight chunks
+    static constexpr int PH = TR / 2 + 1;                // staged input rows y0/2 .. y0/2 + TR/2
+    static constexpr int PW = TC / 2 + 1;                // staged input cols x0/2 .. x0/2 + TC/2
+    static constexpr int CP = CIN + 8;                   // LDS channel pitch (bf16)
+    static_assert(CIN % 32 == 0, "one tap per weight chunk");
+    static_assert(PBW % 4 == 0, "row and column parity of a block fixed at compile time");
+};
+
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
+    using C = T2Cfg<CIN, COUT>;
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[C::PH * C::PW * C::CP];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ct = wave % C::NT;
+    const int wsub = wave / C::NT;
+    const int lp = lane & 15, lg = lane >> 4;
+
+    bf16x8 wreg[C::NCH];
+    {
+        const uint4* wp4 = reinterpret_cast<const uint4*>(a.wp);
+#pragma unroll
+        for (int ch = 0; ch < C::NCH; ++ch) {
+            uint4 v = wp4[((size_t)ch * COUT + ct * 16 + lp) * 4 + lg];
+            wreg[ch] = *reinterpret_cast<bf16x8*>(&v);
+        }
+    }
+    float bias4[4] = {0.f, 0.f, 0.f, 0.f};
+    if (a.bias)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias4[i] = a.bias[ct * 16 + 4 * lg + i];
+
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int b = tile / (a.tiles_x * a.tiles_y);
+        const int rem = tile - b * a.tiles_x * a.tiles_y;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        if (a.active && !a.active[b]) continue;  // uniform over the block
+        const int y0 = ty * C::TR, x0 = tx * C::TC;
+        __syncthreads();
+        const uint16_t* xb = a.x + (size_t)b * a.Hin * a.Win * CIN;
+        constexpr int VEC = CIN / 8;
+        for (int e = tid; e < C::PH * C::PW * VEC; e += 256) {
+            const int v = e % VEC, pix = e / VEC;
+            const int py = pix / C::PW, px = pix - py * C::PW;
+            const int iy = (y0 >> 1) + py, ix = (x0 >> 1) + px;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (iy < a.Hin && ix < a.Win) val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
+            *reinterpret_cast<uint4*>(&s_in[(py * C::PW + px) * C::CP + 8 * v]) = val;
+        }
+        __syncthreads();
+        f32x4 acc[C::PBW];
+#pragma unroll
+        for (int q = 0; q < C::PBW; ++q) {
+            acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            const int ry = (wsub * C::PBW + q) >> 1;  // parity (q >> 1) & 1, since 4 | PBW
+            const bool odd_row = (q >> 1) & 1, odd_col = q & 1;
+#pragma unroll
+            for (int ty_ = 0; ty_ < 2; ++ty_) {
+                if (!odd_row && ty_ > 0) break;
+                const int ky = odd_row ? 2 * ty_ : 1;
+#pragma unroll
+                for (int tx_ = 0; tx_ < 2; ++tx_) {
+                    if (!odd_col && tx_ > 0) break;
+                    const int kx = odd_col ? 2 * tx_ : 1;
+                    const int tap = ky * 3 + kx;
+                    const int sy = (ry + ky - 1) >> 1;
+                    const int sx = lp + ((odd_col ? kx : kx - 1) >> 1);
+#pragma unroll
+                    for (int cb = 0; cb < C::CB; ++cb) {
+                        const uint4 raw =
+                            *reinterpret_cast<const uint4*>(&s_in[(sy * C::PW + sx) * C::CP + cb * 32 + 8 * lg]);
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&raw);
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[tap * C::CB + cb], bv, acc[q], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        const int co = ct * 16 + 4 * lg;
+        const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
+#pragma unroll
+        for (int q = 0; q < C::PBW; ++q) {
+            const int ry = (wsub * C::PBW + q) >> 1;
+            const int oy = y0 + ry, ox = x0 + (q & 1) + 2 * lp;
+            if (oy >= a.Hout || ox >= a.Wout) continue;
+            const size_t po = (((size_t)b * a.Hout + oy) * a.Wout + ox) * COUT + co;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = acc[q][i] + bias4[i];
+            if (a.skip) {
+                const size_t so = (((size_t)sb * a.Hout + oy) * a.Wout + ox) * COUT + co;
+                uint2 s2 = *reinterpret_cast<const uint2*>(a.skip + so);
+                v[0] += bf2f((uint16_t)(s2.x & 0xffff));
+                v[1] += bf2f((uint16_t)(s2.x >> 16));
+                v[2] += bf2f((uint16_t)(s2.y & 0xffff));
+                v[3] += bf2f((uint16_t)(s2.y >> 16));
+            }
+            if (a.relu)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
+            if (a.mask) {
+                uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
+                if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
+                if (!(bf2f((uint16_t)(m2.x >> 16)) > 0.f)) v[1] = 0.f;
+                if (!(bf2f((uint16_t)(m2.y & 0xffff)) > 0.f)) v[2] = 0.f;
+                if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
+            }
+            uint2 o2;
+            o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+            o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+            *reinterpret_cast<uint2*>(a.y + po) = o2;
+            if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+template <int CIN, int COUT>
+static hh_status launch_t2_t(hipStream_t st, ConvArgs a, int num_cus) {
+    using C = T2Cfg<CIN, COUT>;
+    a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
+    a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
+    a.ntiles = a.B * a.tiles_x * a.tiles_y;
+    if (a.ntiles == 0) return HH_OK;
+    const int grid = std::min(a.ntiles, 8 * num_cus);
+    hipLaunchKernelGGL((k_conv_t2<CIN, COUT>), dim3(grid), dim3(256), 0, st, a);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
 template <int CIN, int COUT, int MODE>
 static hh_status launch_conv_t(hipStream_t st, ConvArgs a, int num_cus) {
     using C = ConvCfg<CIN, COUT, MODE>;
@@ -210,10 +357,12 @@ hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, 
     HH_CONV_CASE(16, 32, CM_S2)
     HH_CONV_CASE(32, 64, CM_S2)
     HH_CONV_CASE(64, 64, CM_S2)
-    HH_CONV_CASE(64, 64, CM_T2)
-    HH_CONV_CASE(64, 32, CM_T2)
-    HH_CONV_CASE(32, 16, CM_T2)
 #undef HH_CONV_CASE
+    if (mode == CM_T2) {
+        if (cin == 64 && cout == 64) return launch_t2_t<64, 64>(st, a, num_cus);
+        if (cin == 64 && cout == 32) return launch_t2_t<64, 32>(st, a, num_cus);
+        if (cin == 32 && cout == 16) return launch_t2_t<32, 16>(st, a, num_cus);
+    }
     set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
     return HH_ERR_ARG;
 }

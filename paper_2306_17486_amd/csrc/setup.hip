@@ -87,9 +87,8 @@ __device__ void build_schur(double2* A, const double2* P1, const double2* P2, co
     __syncthreads();
 }
 
-// In-place Gauss-Jordan inversion without pivoting (one workgroup), then store
-// the transpose in single precision.
-__device__ void invert_store(double2* A, float2* Qk, int m) {
+// In-place Gauss-Jordan inversion without pivoting (one workgroup).
+__device__ void invert_inplace(double2* A, int m) {
     __shared__ double2 piv_s;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int p = 0; p < m; ++p) {
@@ -118,7 +117,12 @@ __device__ void invert_store(double2* A, float2* Qk, int m) {
         if (tid == 0) A[(size_t)p * m + p] = piv;
         __syncthreads();
     }
-    for (int e = tid; e < m * m; e += nt) {
+}
+
+// ... then store the transpose in single precision
+__device__ void invert_store(double2* A, float2* Qk, int m) {
+    invert_inplace(A, m);
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
         int i = e / m, j = e - i * m;
         double2 v = A[e];
         Qk[(size_t)j * m + i] = make_float2((float)v.x, (float)v.y);
@@ -163,6 +167,211 @@ __global__ void __launch_bounds__(1024) k_coarse_factor_mid(const float2* __rest
     invert_store(A, QT + (size_t)inst * mm * m + (size_t)p * mm, m);
 }
 
+// ---------------------------------------------------------------------------
+// One level of cyclic reduction before the two-ended elimination.  With V_j =
+// T_{2j+1}^{-1} (odd grid rows, j < Mo = floor(m/2)), eliminating the odd rows
+// leaves a block-tridiagonal system on the even rows 2j, j < M = ceil(m/2):
+//   D_j = T_{2j} - c^2 ([j >= 1] V_{j-1} + [j < Mo] V_j),  L_j = -c^2 V_{j-1},  U_j = -c^2 V_j,
+//   b'_j = b_{2j} + c ([j >= 1] V_{j-1} b_{2j-1} + [j < Mo] V_j b_{2j+1}),
+// and the odd rows follow from x_{2j+1} = V_j (b_{2j+1} + c x_{2j} + c x_{2j+2}).
+// The reduced system is eliminated from both ends towards p = M/2:
+//   top (j < p):      S_j = D_j - c^4 V_{j-1} Q_{j-1} V_{j-1},  P_j = c^2 Q_j V_{j-1},  R_j = c^2 Q_j V_j
+//   bottom (j > p):   S_j = D_j - c^4 V_j Q_{j+1} V_j,          P_j = c^2 Q_j V_j,      R_j = c^2 Q_j V_{j-1}
+//   middle:           S_p = D_p - c^4 V_{p-1} Q_{p-1} V_{p-1} - c^4 V_p Q_{p+1} V_p,
+//                     P_p = c^2 Q_p V_{p-1},  R_p = c^2 Q_p V_p
+// with Q_j = S_j^{-1}, so that the solve is
+//   g_j = Q_j b'_j;  y_j = g_j + P_j y_{j-/+1} (forward from each end);
+//   x_p = g_p + P_p y_{p-1} + R_p y_{p+1};  x_j = y_j + R_j x_{j+/-1} (backward).
+// Factors per instance, complex single, transposed (slot[c][r] = M[r][c]):
+// slots j (Q_j), M + j (P_j), 2M + j (R_j), 3M + j (V_j).
+// ---------------------------------------------------------------------------
+static inline __device__ __host__ int cr_M(int m) { return (m + 1) / 2; }
+static inline __device__ __host__ int cr_Mo(int m) { return m / 2; }
+
+// A <- T_k (the shifted operator's grid-row block), dense FP64
+__device__ void build_tblock(double2* A, const float2* cf, int k, int m, double c, double beta) {
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int i = e / m, j = e - i * m;
+        double2 v = make_double2(0.0, 0.0);
+        if (i == j) {
+            const float2 cc = cf[(size_t)k * m + i];
+            const double w2k2 = cc.x, g = cc.y;
+            v.x = 4.0 * c - w2k2;
+            v.y = w2k2 * (g + beta);
+        } else if (j == i - 1 || j == i + 1) {
+            v.x = -c;
+        }
+        A[e] = v;
+    }
+    __syncthreads();
+}
+
+// C (+)= alpha A B for m x m FP64 complex matrices (row-major), one workgroup,
+// 32 x 32 output tiles through LDS.  C must not alias A or B.
+__device__ void zgemm_wg(double2* C, const double2* A, const double2* B, int m, double alpha, bool accumulate) {
+    constexpr int T = 32;
+    __shared__ double2 sa[T][T + 1];
+    __shared__ double2 sb[T][T + 1];
+    const int tid = threadIdx.x;  // blockDim.x == 1024: one output entry of the tile per thread
+    const int ty = tid / T, tx = tid % T;
+    const int nt = (m + T - 1) / T;
+    for (int bi = 0; bi < nt; ++bi)
+        for (int bj = 0; bj < nt; ++bj) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int bk = 0; bk < nt; ++bk) {
+                const int ar = bi * T + ty, ac = bk * T + tx;
+                const int br = bk * T + ty, bc = bj * T + tx;
+                sa[ty][tx] = (ar < m && ac < m) ? A[(size_t)ar * m + ac] : make_double2(0.0, 0.0);
+                sb[ty][tx] = (br < m && bc < m) ? B[(size_t)br * m + bc] : make_double2(0.0, 0.0);
+                __syncthreads();
+#pragma unroll 8
+                for (int k = 0; k < T; ++k) acc = zadd(acc, zmul(sa[ty][k], sb[k][tx]));
+                __syncthreads();
+            }
+            const int r = bi * T + ty, cc = bj * T + tx;
+            if (r < m && cc < m) {
+                const double2 v = make_double2(alpha * acc.x, alpha * acc.y);
+                C[(size_t)r * m + cc] = accumulate ? zadd(C[(size_t)r * m + cc], v) : v;
+            }
+        }
+    __syncthreads();
+}
+
+// store alpha * A (FP64, row-major) transposed in single precision
+__device__ void store_slot(const double2* A, float2* slot, int m, double alpha) {
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int i = e / m, j = e - i * m;
+        const double2 v = A[e];
+        slot[(size_t)j * m + i] = make_float2((float)(alpha * v.x), (float)(alpha * v.y));
+    }
+    __syncthreads();
+}
+
+
+// V_j = T_{2j+1}^{-1}: blockIdx.x = j (< Mo), blockIdx.y = instance.
+// Vd: FP64 copies [inst][Mo][m][m] (kept for the chain factorisation).
+__global__ void __launch_bounds__(1024) k_cr_vinv(const float2* __restrict__ coef, double2* __restrict__ Vd,
+                                                  float2* __restrict__ F, int m, double H, double beta) {
+    const int j = blockIdx.x, inst = blockIdx.y;
+    const int M = cr_M(m), Mo = cr_Mo(m);
+    const size_t mm = (size_t)m * m;
+    const double c = 1.0 / (H * H);
+    double2* V = Vd + ((size_t)inst * Mo + j) * mm;
+    build_tblock(V, coef + (size_t)inst * mm, 2 * j + 1, m, c, beta);
+    invert_inplace(V, m);
+    store_slot(V, F + ((size_t)inst * 4 * M + 3 * M + j) * mm, m, 1.0);
+}
+
+// A <- D_j = T_{2j} - c^2 ([j >= 1] V_{j-1} + [j < Mo] V_j)
+__device__ void build_dblock(double2* A, const float2* cf, const double2* Vinst, int j, int m, double c,
+                             double beta) {
+    const int Mo = cr_Mo(m);
+    const size_t mm = (size_t)m * m;
+    build_tblock(A, cf, 2 * j, m, c, beta);
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        double2 v = A[e];
+        if (j >= 1) {
+            const double2 a = Vinst[(size_t)(j - 1) * mm + e];
+            v.x -= c * c * a.x;
+            v.y -= c * c * a.y;
+        }
+        if (j < Mo) {
+            const double2 a = Vinst[(size_t)j * mm + e];
+            v.x -= c * c * a.x;
+            v.y -= c * c * a.y;
+        }
+        A[e] = v;
+    }
+    __syncthreads();
+}
+
+// The two chains of the reduced system: blockIdx.x = instance, blockIdx.y = 0 (top) / 1 (bottom).
+// Scratch W per instance: [6][m][m] FP64: A, Qprev (top), A, Qprev (bottom), T1, T2 (temporaries
+// of the top chain; the bottom chain uses the next two) -- laid out as [chain][3][m][m].
+__global__ void __launch_bounds__(1024) k_cr_chain(const float2* __restrict__ coef, const double2* __restrict__ Vd,
+                                                   double2* __restrict__ W, float2* __restrict__ F, int m,
+                                                   double H, double beta) {
+    const int inst = blockIdx.x;
+    const bool top = blockIdx.y == 0;
+    const int M = cr_M(m), Mo = cr_Mo(m), p = M / 2;
+    const size_t mm = (size_t)m * m;
+    const double c = 1.0 / (H * H), c2 = c * c;
+    const float2* cf = coef + (size_t)inst * mm;
+    const double2* Vi = Vd + (size_t)inst * Mo * mm;
+    double2* base = W + ((size_t)inst * 2 + (top ? 0 : 1)) * 4 * mm;
+    double2* A = base;            // S_j, then Q_j
+    double2* Qp = base + mm;      // Q of the previous step
+    double2* T1 = base + 2 * mm;  // temporaries
+    double2* T2 = base + 3 * mm;
+    float2* Fi = F + (size_t)inst * 4 * M * mm;
+    const int first = top ? 0 : M - 1, last = top ? p - 1 : p + 1, dir = top ? 1 : -1;
+    if (top ? (p < 1) : (M - 1 <= p)) return;  // empty chain
+    for (int j = first;; j += dir) {
+        build_dblock(A, cf, Vi, j, m, c, beta);
+        if (j != first) {
+            // the coupling block between j and the previous row: V_{j-1} (top) or V_j (bottom)
+            const double2* Vc = Vi + (size_t)(top ? j - 1 : j) * mm;
+            zgemm_wg(T1, Qp, Vc, m, 1.0, false);      // Q_prev V
+            zgemm_wg(A, Vc, T1, m, -c2 * c2, true);    // S_j -= c^4 V Q_prev V
+        }
+        invert_inplace(A, m);                          // A = Q_j
+        store_slot(A, Fi + (size_t)j * mm, m, 1.0);
+        // P_j: couples to the previous row (exists unless j is the first of the chain)
+        if (j != first) {
+            const double2* Vc = Vi + (size_t)(top ? j - 1 : j) * mm;
+            zgemm_wg(T2, A, Vc, m, c2, false);
+            store_slot(T2, Fi + (size_t)(M + j) * mm, m, 1.0);
+        }
+        // R_j: couples to the next row towards the middle: V_j (top) or V_{j-1} (bottom)
+        {
+            const double2* Vn = Vi + (size_t)(top ? j : j - 1) * mm;
+            zgemm_wg(T2, A, Vn, m, c2, false);
+            store_slot(T2, Fi + (size_t)(2 * M + j) * mm, m, 1.0);
+        }
+        // keep Q_j for the next step (and for the middle row)
+        for (int e = threadIdx.x; e < m * m; e += blockDim.x) Qp[e] = A[e];
+        __syncthreads();
+        if (j == last) break;
+    }
+}
+
+// middle row: blockIdx.x = instance; uses the chains' last Q (W[.][0|1][1]).
+__global__ void __launch_bounds__(1024) k_cr_mid(const float2* __restrict__ coef, const double2* __restrict__ Vd,
+                                                 double2* __restrict__ W, double2* __restrict__ Wm,
+                                                 float2* __restrict__ F, int m, double H, double beta) {
+    const int inst = blockIdx.x;
+    const int M = cr_M(m), Mo = cr_Mo(m), p = M / 2;
+    const size_t mm = (size_t)m * m;
+    const double c = 1.0 / (H * H), c2 = c * c;
+    const double2* Vi = Vd + (size_t)inst * Mo * mm;
+    const double2* Qtop = W + ((size_t)inst * 2 + 0) * 4 * mm + mm;
+    const double2* Qbot = W + ((size_t)inst * 2 + 1) * 4 * mm + mm;
+    double2* A = Wm + (size_t)inst * 2 * mm;
+    double2* T1 = A + mm;
+    float2* Fi = F + (size_t)inst * 4 * M * mm;
+    build_dblock(A, coef + (size_t)inst * mm, Vi, p, m, c, beta);
+    if (p >= 1) {
+        const double2* Vc = Vi + (size_t)(p - 1) * mm;
+        zgemm_wg(T1, Qtop, Vc, m, 1.0, false);
+        zgemm_wg(A, Vc, T1, m, -c2 * c2, true);
+    }
+    if (p + 1 <= M - 1) {
+        const double2* Vc = Vi + (size_t)p * mm;
+        zgemm_wg(T1, Qbot, Vc, m, 1.0, false);
+        zgemm_wg(A, Vc, T1, m, -c2 * c2, true);
+    }
+    invert_inplace(A, m);
+    store_slot(A, Fi + (size_t)p * mm, m, 1.0);
+    if (p >= 1) {
+        zgemm_wg(T1, A, Vi + (size_t)(p - 1) * mm, m, c2, false);
+        store_slot(T1, Fi + (size_t)(M + p) * mm, m, 1.0);
+    }
+    if (p + 1 <= M - 1) {
+        zgemm_wg(T1, A, Vi + (size_t)p * mm, m, c2, false);
+        store_slot(T1, Fi + (size_t)(2 * M + p) * mm, m, 1.0);
+    }
+}
+
 hh_status setup_coefficients(hh_model* md, const float* kappa_dev) {
     hipStream_t st = md->ctx->stream;
     const hh_model_desc& d = md->d;
@@ -183,12 +392,42 @@ hh_status setup_coefficients(hh_model* md, const float* kappa_dev) {
     return HH_OK;
 }
 
+static hh_status setup_coarse_reduced(hh_model* md) {
+    hh_ctx* ctx = md->ctx;
+    const Level& C = md->lev[md->nlev - 1];
+    const int m = C.n;
+    const int M = cr_M(m), Mo = cr_Mo(m);
+    const size_t mm = (size_t)m * m;
+    md->m = m;
+    md->cr1 = true;
+    HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * 4 * M * mm * sizeof(float2)));
+    Buf Vd, W, Wm;
+    HH_TRY(Vd.ensure(ctx, (size_t)md->ninst * std::max(Mo, 1) * mm * sizeof(double2)));
+    HH_TRY(W.ensure(ctx, (size_t)md->ninst * 8 * mm * sizeof(double2)));
+    HH_TRY(Wm.ensure(ctx, (size_t)md->ninst * 2 * mm * sizeof(double2)));
+    if (Mo > 0) {
+        hipLaunchKernelGGL(k_cr_vinv, dim3(Mo, md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
+                           Vd.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
+        HH_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_cr_chain, dim3(md->ninst, 2), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
+                       Vd.as<double2>(), W.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cr_mid, dim3(md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(), Vd.as<double2>(),
+                       W.as<double2>(), Wm.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
+    HH_LAUNCH_CHECK();
+    HH_HIP(hipStreamSynchronize(ctx->stream));  // scratch released on return
+    return HH_OK;
+}
+
 hh_status setup_coarse_factors(hh_model* md) {
+    if (md->d.coarse_reduce) return setup_coarse_reduced(md);
     hh_ctx* ctx = md->ctx;
     const Level& C = md->lev[md->nlev - 1];
     const int m = C.n;
     const int p = m / 2;
     md->m = m;
+    md->cr1 = false;
     HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * m * m * m * sizeof(float2)));
     Buf S;
     HH_TRY(S.ensure(ctx, (size_t)md->ninst * 3 * m * m * sizeof(double2)));

@@ -66,14 +66,15 @@ def test_operator_complex_symmetry(hh, ctx):
     assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
 
 
-@pytest.mark.parametrize("n,family,with_x0", [(128, "grf", False), (100, "layered", False),
-                                              (128, "layered", True), (100, "grf", True)])
-def test_vcycle_parity(hh, ctx, n, family, with_x0):
-    _say(f"vcycle parity n={n} {family} x0={with_x0}")
+@pytest.mark.parametrize("n,family,with_x0,reduce", [(128, "grf", False, 1), (100, "layered", False, 1),
+                                                     (128, "layered", True, 1), (100, "grf", True, 1),
+                                                     (100, "layered", False, 0), (128, "grf", True, 0)])
+def test_vcycle_parity(hh, ctx, n, family, with_x0, reduce):
+    _say(f"vcycle parity n={n} {family} x0={with_x0} reduced coarse factorisation {reduce}")
     k = inputs.slowness(n, 12, family)
     om = inputs.omega_for(n, k)
     prob = H.Problem(k, om)
-    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m = hh.Model(ctx, torch.from_numpy(k), om, coarse_reduce=reduce)
     b = inputs.random_complex((3, n, n), 5)
     x0 = inputs.random_complex((3, n, n), 6) * 1e-4 if with_x0 else None
     z = m.apply_vcycle(_dev(b), None if x0 is None else _dev(x0)).cpu().numpy()
@@ -171,21 +172,24 @@ def test_bad_arguments_raise(hh, ctx):
         m.solve(_dev(np.zeros((1, 32, 32))), precond=hh.HH_PRECOND_CNN_MG)
 
 
-# chain variants R, split variants 100 RS + R (RS rows of each Schur inverse per workgroup)
-COARSE_VARIANTS = [1, 2, 4, 8, 801, 808, 1601, 1604, 3202, 3208]
+# (reduced factorisation?, variant): plain factorisation -- chain R, split 100 RS + R
+# (RS rows of each Schur inverse per workgroup); reduced factorisation (one level of
+# cyclic reduction) -- 1000 + R
+COARSE_VARIANTS = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 801), (0, 808), (0, 1601), (0, 1604), (0, 3202), (0, 3208),
+                   (1, 1001), (1, 1002), (1, 1004), (1, 1008)]
 
 
-@pytest.mark.parametrize("R", COARSE_VARIANTS)
-def test_coarse_group_sizes_vcycle_parity(hh, ctx, R):
+@pytest.mark.parametrize("reduce,R", COARSE_VARIANTS)
+def test_coarse_group_sizes_vcycle_parity(hh, ctx, reduce, R):
     # 11 right-hand sides: full groups and a ragged last group for every R; one
     # and two slowness models (grouping order padded per model); coarse grids of
     # 32 and 16 points (split slices with and without empty rows)
     n = 128
-    _say(f"coarse solve variant {R}")
+    _say(f"coarse solve variant {R} (reduced factorisation {reduce})")
     k = inputs.slowness(n, 13, "layered")
     om = inputs.omega_for(n, k)
     prob = H.Problem(k, om)
-    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m = hh.Model(ctx, torch.from_numpy(k), om, coarse_reduce=reduce)
     m.set_coarse_group(R)
     assert m.coarse_group(11) == R
     b = inputs.random_complex((11, n, n), 17)
@@ -193,7 +197,7 @@ def test_coarse_group_sizes_vcycle_parity(hh, ctx, R):
     ref = np.stack([prob.hier.vcycle(b[i]) for i in range(11)])
     assert _rel(z, ref) <= 2e-5, _rel(z, ref)
     ks = [inputs.grf_slowness(64, 1), inputs.layered_slowness(64, 2)]
-    m2 = hh.Model(ctx, torch.from_numpy(np.stack(ks)), inputs.omega_for(64))
+    m2 = hh.Model(ctx, torch.from_numpy(np.stack(ks)), inputs.omega_for(64), coarse_reduce=reduce)
     m2.set_coarse_group(R)
     inst = [1, 0, 0, 1, 1, 0, 1]
     b2 = inputs.random_complex((7, 64, 64), 18)
@@ -216,8 +220,8 @@ def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
     b = np.stack([inputs.point_source(n, 60 + i) for i in range(6)] + [inputs.random_complex((n, n), 66)])
     its_o = [H.solve_mg(prob, b[r])[1] for r in range(7)]
     bad = []
-    for R in (0, 1, 8, 802, 1608):
-        m = hh.Model(ctx, torch.from_numpy(k), om)
+    for reduce, R in ((1, 0), (1, 1001), (1, 1008), (0, 0), (0, 1), (0, 802), (0, 1608)):
+        m = hh.Model(ctx, torch.from_numpy(k), om, coarse_reduce=reduce)
         m.set_coarse_group(R)
         xd, info = m.solve(_dev(b))
         lib = m.residual_norms(_dev(b), xd)
@@ -228,10 +232,12 @@ def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
             # operator differs from the FP64 one by about 4e-8 of ||b||
             assert abs(lib[r] - res) <= 1e-7
             assert abs(info["final_res"][r] - res) <= 1e-7
-            _say(f"  R={R} rhs {r}: iters {info['iters'][r]} (oracle {its_o[r]}) gpu residual "
+            _say(f"  reduce={reduce} R={R} rhs {r}: iters {info['iters'][r]} (oracle {its_o[r]}) gpu residual "
                  f"{info['final_res'][r]:.3e} host residual {res:.3e}")
             if not (info["converged"][r] and res <= 1e-6 and abs(int(info["iters"][r]) - its_o[r]) <= 2):
-                bad.append((R, r))
+                bad.append((reduce, R, r))
         if R == 0:
-            assert m.coarse_group(7) in (1, 2, 4, 8)
+            assert m.coarse_group(7) in ((1001, 1002, 1004, 1008) if reduce else
+                                         (1, 2, 4, 8, 801, 802, 804, 808, 1601, 1602, 1604, 1608, 3201, 3202, 3204,
+                                          3208))
     assert not bad, bad
