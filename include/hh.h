@@ -131,6 +131,17 @@ typedef struct {
                            doubles (2, 4, 8, ... cycles; a switch resets it).  0: CNN+MG
                            in every cycle after the warm start. */
     double probe_ratio; /* default 0.5 */
+    int graph;          /* 1 (default): a restart cycle's launch sequence (every kernel
+                           from the first preconditioner application to the update of x)
+                           depends only on the cycle length, the warm start and the
+                           counts of right-hand sides on each preconditioner; the second
+                           cycle with a given configuration is captured into a HIP graph
+                           and every later one replays it (the first runs eagerly, so
+                           that lazy set-up and coarse-solve tuning happen outside a
+                           capture).  Graphs live for one call.  Cycles run eagerly while
+                           kernel-class profiling is on and when the coarse solve uses a
+                           cooperative (split) variant.  0: every cycle eager.  Results are
+                           identical either way (same kernels in the same order). */
 } hh_solve_opts;
 
 void hh_solve_opts_default(hh_solve_opts* o);

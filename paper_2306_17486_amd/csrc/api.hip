@@ -128,6 +128,7 @@ hh_status hh_ctx_destroy(hh_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     delete ctx->work;
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return HH_OK;
 }
@@ -213,6 +214,7 @@ void hh_solve_opts_default(hh_solve_opts* o) {
     o->fixed_iters = 0;
     o->fallback = 1;
     o->probe_ratio = 0.5;
+    o->graph = 1;
 }
 
 hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev, void* x_dev,

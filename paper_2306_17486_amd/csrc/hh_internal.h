@@ -74,6 +74,7 @@ struct hh_ctx {
     hh_free_fn dealloc = nullptr;
     void* user = nullptr;
     int num_cus = 256;
+    hipStream_t cap_stream = nullptr;  // graph capture (the caller's stream may be the null stream)
 };
 
 namespace hh {
@@ -251,6 +252,9 @@ hh_status launch_vcycle_strided(hh_model* m, int nrhs, const BatchMap& bm, const
 // RHS per workgroup of the coarsest solve (the grouping unit of BatchMap::order)
 int coarse_group();
 bool coarse_choice_valid(const hh_model* md, int c);
+bool coarse_capturable(const hh_model* md, int nrhs, int nact);
+// a non-blocking stream of the context for graph capture (created on first use)
+hh_status capture_stream(hh_ctx* c, hipStream_t* out);
 hh_status coarse_check_err(hh_model* md);
 // copy a host RHS -> slowness-model map to the device (api.hip)
 hh_status upload_inst_map(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out);

@@ -494,6 +494,63 @@ hh_status SolveWork::prepare(hh_ctx* c, hh_model* md, int nrhs_, int restart_, i
     return HH_OK;
 }
 
+hh_status capture_stream(hh_ctx* c, hipStream_t* out) {
+    if (!c->cap_stream) HH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    *out = c->cap_stream;
+    return HH_OK;
+}
+
+// Graphs of restart cycles, keyed by the cycle's launch configuration; owned
+// by one solve call.
+struct CycleGraphs {
+    struct Entry {
+        int len, warm, cnt_c, cnt_m, seen;
+        hipGraphExec_t exec;
+    };
+    static constexpr size_t MAX_ENTRIES = 512;
+    std::vector<Entry> v;
+    ~CycleGraphs() {
+        for (auto& e : v)
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    }
+    // the entry of a configuration (created unseen); null once the cache is full
+    Entry* find(int len, int warm, int cnt_c, int cnt_m) {
+        for (auto& e : v)
+            if (e.len == len && e.warm == warm && e.cnt_c == cnt_c && e.cnt_m == cnt_m) return &e;
+        if (v.size() >= MAX_ENTRIES) return nullptr;
+        v.reserve(MAX_ENTRIES);  // entries never move: callers keep pointers
+        v.push_back({len, warm, cnt_c, cnt_m, 0, nullptr});
+        return &v.back();
+    }
+    // record body's launches on the context's capture stream into e->exec
+    template <class F>
+    hh_status capture(hh_ctx* ctx, Entry* e, F&& body) {
+        hipStream_t cs;
+        HH_TRY(capture_stream(ctx, &cs));
+        hipStream_t saved = ctx->stream;
+        ctx->stream = cs;
+        hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        hh_status s = be == hipSuccess ? body() : HH_ERR_HIP;
+        hipGraph_t g = nullptr;
+        const hipError_t ee = be == hipSuccess ? hipStreamEndCapture(cs, &g) : be;
+        ctx->stream = saved;
+        if (s == HH_OK && ee != hipSuccess) {
+            set_error("graph capture of a restart cycle failed: %s", hipGetErrorString(ee));
+            s = HH_ERR_HIP;
+        }
+        if (s == HH_OK) {
+            const hipError_t ie = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                e->exec = nullptr;
+                set_error("graph instantiation of a restart cycle failed: %s", hipGetErrorString(ie));
+                s = HH_ERR_HIP;
+            }
+        }
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+};
+
 hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* b, double2* x,
                        const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user) {
     const int* inst_dev = bm.inst;
@@ -529,6 +586,7 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
     if (!o.use_x0) HH_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * nn * sizeof(double2), st));
 
     std::vector<int> hflags((size_t)3 * nrhs);
+    CycleGraphs graphs;
     int cycle = 0;
     const bool cnn = precond_cnn != nullptr;
     for (;;) {
@@ -564,54 +622,76 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
         int len = W.restart;
         if (warm) len = std::min(len, o.warm_mg_iters);
         if (fixed) len = std::min(len, o.fixed_iters);
-        for (int j = 0; j < len; ++j) {
-            const float2* vj = V + (size_t)j * nn;
-            const double* sg = reinterpret_cast<const double*>(reinterpret_cast<const char*>(S) + offsetof(KState, sig)) + j;
-            float2* zj = Z + (size_t)j * nn;
-            // z_j = M(v_j) on strided [rhs] views: CNN+MG for the RHS in actc,
-            // MG-only for those in actm (warm start, probes, fallback)
-            if (any_c) HH_TRY(precond_cnn(precond_user, md, W, bmc, vj, vstride, sg, sig_stride, zj, zstride, actc));
-            if (any_m) HH_TRY(precond_mg_strided(md, W, bmm, vj, vstride, sg, sig_stride, zj, zstride, actm));
-            // w = A z_j, dots with v_0..v_j
-            {
-            ProfScope ps(ctx, HH_K_OP_DOTS);
-            switch (j + 1) {
-#define HH_OPD(NJ) case NJ: launch_op_dots_t<NJ>(grd, blk, st, zj, zstride, V, vstride, j, L0.coef.as<float2>(), inst_dev, n, ih2, parts, np, act); break;
-                HH_OPD(1) HH_OPD(2) HH_OPD(3) HH_OPD(4) HH_OPD(5) HH_OPD(6) HH_OPD(7) HH_OPD(8)
-                HH_OPD(9) HH_OPD(10) HH_OPD(11) HH_OPD(12) HH_OPD(13) HH_OPD(14) HH_OPD(15) HH_OPD(16)
+        // every launch of the cycle, on the context's current stream (a capture
+        // stream while a graph is recorded)
+        auto body = [&]() -> hh_status {
+            hipStream_t s = ctx->stream;
+            for (int j = 0; j < len; ++j) {
+                const float2* vj = V + (size_t)j * nn;
+                const double* sg =
+                    reinterpret_cast<const double*>(reinterpret_cast<const char*>(S) + offsetof(KState, sig)) + j;
+                float2* zj = Z + (size_t)j * nn;
+                // z_j = M(v_j) on strided [rhs] views: CNN+MG for the RHS in actc,
+                // MG-only for those in actm (warm start, probes, fallback)
+                if (any_c)
+                    HH_TRY(precond_cnn(precond_user, md, W, bmc, vj, vstride, sg, sig_stride, zj, zstride, actc));
+                if (any_m) HH_TRY(precond_mg_strided(md, W, bmm, vj, vstride, sg, sig_stride, zj, zstride, actm));
+                // w = A z_j, dots with v_0..v_j
+                {
+                    ProfScope ps(ctx, HH_K_OP_DOTS);
+                    switch (j + 1) {
+#define HH_OPD(NJ) case NJ: launch_op_dots_t<NJ>(grd, blk, s, zj, zstride, V, vstride, j, L0.coef.as<float2>(), inst_dev, n, ih2, parts, np, act); break;
+                        HH_OPD(1) HH_OPD(2) HH_OPD(3) HH_OPD(4) HH_OPD(5) HH_OPD(6) HH_OPD(7) HH_OPD(8)
+                        HH_OPD(9) HH_OPD(10) HH_OPD(11) HH_OPD(12) HH_OPD(13) HH_OPD(14) HH_OPD(15) HH_OPD(16)
 #undef HH_OPD
-                default: set_error("restart too long"); return HH_ERR_ARG;
-            }
-            }
-            HH_LAUNCH_CHECK();
-            {
-                ProfScope ps(ctx, HH_K_SMALL);
-                hipLaunchKernelGGL(k_arnoldi_col, dim3(nrhs), dim3(256), 0, st, parts, np, j, S, act);
-            }
-            HH_LAUNCH_CHECK();
-            {
-            ProfScope ps(ctx, HH_K_ORTHO);
-            switch (j + 1) {
-#define HH_ORT(NJ) case NJ: launch_ortho_t<NJ>(grd, blk, st, V, vstride, j, S, n, parts, np, act); break;
-                HH_ORT(1) HH_ORT(2) HH_ORT(3) HH_ORT(4) HH_ORT(5) HH_ORT(6) HH_ORT(7) HH_ORT(8)
-                HH_ORT(9) HH_ORT(10) HH_ORT(11) HH_ORT(12) HH_ORT(13) HH_ORT(14) HH_ORT(15) HH_ORT(16)
+                        default: set_error("restart too long"); return HH_ERR_ARG;
+                    }
+                }
+                HH_LAUNCH_CHECK();
+                {
+                    ProfScope ps(ctx, HH_K_SMALL);
+                    hipLaunchKernelGGL(k_arnoldi_col, dim3(nrhs), dim3(256), 0, s, parts, np, j, S, act);
+                }
+                HH_LAUNCH_CHECK();
+                {
+                    ProfScope ps(ctx, HH_K_ORTHO);
+                    switch (j + 1) {
+#define HH_ORT(NJ) case NJ: launch_ortho_t<NJ>(grd, blk, s, V, vstride, j, S, n, parts, np, act); break;
+                        HH_ORT(1) HH_ORT(2) HH_ORT(3) HH_ORT(4) HH_ORT(5) HH_ORT(6) HH_ORT(7) HH_ORT(8)
+                        HH_ORT(9) HH_ORT(10) HH_ORT(11) HH_ORT(12) HH_ORT(13) HH_ORT(14) HH_ORT(15) HH_ORT(16)
 #undef HH_ORT
-                default: set_error("restart too long"); return HH_ERR_ARG;
+                        default: set_error("restart too long"); return HH_ERR_ARG;
+                    }
+                }
+                HH_LAUNCH_CHECK();
+                {
+                    ProfScope ps(ctx, HH_K_SMALL);
+                    hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(256), 0, s, parts, np, j, S, act, actc, actm, hist,
+                                       W.hist_len, rtol, max_iters, W.caps_dev);
+                }
+                HH_LAUNCH_CHECK();
             }
-            }
-            HH_LAUNCH_CHECK();
             {
-                ProfScope ps(ctx, HH_K_SMALL);
-                hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(256), 0, st, parts, np, j, S, act, actc, actm, hist,
-                                   W.hist_len, rtol, max_iters, W.caps_dev);
+                ProfScope ps(ctx, HH_K_RESTART);
+                hipLaunchKernelGGL(k_xupdate, grd, blk, 0, s, x, Z, zstride, S, n);
             }
             HH_LAUNCH_CHECK();
+            return HH_OK;
+        };
+        // graph path: a configuration runs eagerly the first time (lazy set-up and
+        // coarse-solve tuning happen there), is captured the second time and
+        // replayed after that
+        CycleGraphs::Entry* ge = nullptr;
+        if (o.graph && !fixed && ctx->prof_class < 0) ge = graphs.find(len, warm ? 1 : 0, cnt_c, cnt_m);
+        if (ge && !ge->exec && ge->seen >= 1 && (!any_c || coarse_capturable(md, nrhs, cnt_c)) &&
+            (!any_m || coarse_capturable(md, nrhs, cnt_m)))
+            HH_TRY(graphs.capture(ctx, ge, body));
+        if (ge && ge->exec) {
+            HH_HIP(hipGraphLaunch(ge->exec, st));
+        } else {
+            HH_TRY(body());
+            if (ge) ge->seen++;
         }
-        {
-            ProfScope ps(ctx, HH_K_RESTART);
-            hipLaunchKernelGGL(k_xupdate, grd, blk, 0, st, x, Z, zstride, S, n);
-        }
-        HH_LAUNCH_CHECK();
         ++cycle;
         if (fixed) {
             // one cycle only: mark everything done after the final residual

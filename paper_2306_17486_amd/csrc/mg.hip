@@ -1271,6 +1271,15 @@ static int coarse_bucket(int n) {
     return b;
 }
 
+// whether a V-cycle's coarse solve for nact active right-hand sides (of nrhs)
+// is already decided (forced or tuned) and launches no cooperative kernel: then
+// its launch sequence can be captured into a graph
+bool coarse_capturable(const hh_model* md, int nrhs, int nact) {
+    const int na = nact > 0 ? std::min(nact, nrhs) : nrhs;
+    const int c = md->coarse_R_forced > 0 ? md->coarse_R_forced : md->coarse_R[coarse_bucket(std::max(na, 1))];
+    return c > 0 && (c < 100 || reduced_code(c));
+}
+
 // Autotuner of the coarse solve: for each bucket of active right-hand sides,
 // time every variant (chain with R right-hand sides per workgroup, split with
 // RS rows per workgroup; fwd + bwd, second of two runs, HIP events on the

@@ -48,7 +48,7 @@ class hh_model_desc(C.Structure):
 class hh_solve_opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("rtol", C.c_double), ("precond", C.c_int),
                 ("warm_mg_iters", C.c_int), ("use_x0", C.c_int), ("fixed_iters", C.c_int), ("fallback", C.c_int),
-                ("probe_ratio", C.c_double)]
+                ("probe_ratio", C.c_double), ("graph", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -268,7 +268,7 @@ class Model:
     # -- solve --------------------------------------------------------------
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, inst=None, restart=10, max_iters=2000,
               rtol=1e-6, precond=HH_PRECOND_MG, warm_mg_iters=3, fixed_iters=0, want_hist=True, fallback=True,
-              probe_ratio=0.5):
+              probe_ratio=0.5, graph=True):
         """Returns (x complex128 tensor, info dict with iters, converged, final_res, hist)."""
         b = b.to(torch.complex64).contiguous()
         nrhs = b.shape[0]
@@ -280,7 +280,7 @@ class Model:
         hh_solve_opts_default(C.byref(o))
         o.restart, o.max_iters, o.rtol, o.precond = restart, max_iters, rtol, precond
         o.warm_mg_iters, o.use_x0, o.fixed_iters = warm_mg_iters, int(x0 is not None), fixed_iters
-        o.fallback, o.probe_ratio = int(fallback), probe_ratio
+        o.fallback, o.probe_ratio, o.graph = int(fallback), probe_ratio, int(graph)
         hl = (fixed_iters if fixed_iters > 0 else max_iters) + 1
         hist = np.zeros((nrhs, hl)) if want_hist else None
         iters = np.zeros(nrhs, dtype=np.int32)

@@ -1,0 +1,120 @@
+"""Restart cycles replayed from HIP graphs give exactly the eager solve's results
+(the same kernels in the same order): MG-only and two-phase CNN+MG solves with
+right-hand sides that finish at different cycles (many cycle configurations,
+each run eagerly, then captured, then replayed), a batch over two slowness
+models, a split coarse solve (cooperative, so its cycles stay eager), and
+repeated calls on one context."""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2306_17486_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+NET_FILE = os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256_512.bin")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hh():
+    from paper_2306_17486_amd import hh as _hh
+    return _hh
+
+
+@pytest.fixture(scope="module")
+def ctx(hh):
+    return hh.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.complex64)
+
+
+def _same(a, b):
+    (xa, ia), (xb, ib) = a, b
+    assert torch.equal(xa, xb), "solutions differ"
+    for key in ("iters", "converged", "final_res", "mg_cycles", "cnn_iters"):
+        assert np.array_equal(ia[key], ib[key]), key
+    assert np.array_equal(ia["hist"], ib["hist"])
+
+
+def _sources(n, seeds):
+    return np.stack([inputs.point_source(n, s) for s in seeds])
+
+
+def test_graph_mg_only_config1(hh, ctx):
+    n = 128
+    _say("graph vs eager, 128^2 MG-only, one source")
+    k = inputs.grf_slowness(n, 1000)
+    m = hh.Model(ctx, torch.from_numpy(k), inputs.omega_for(n, k))
+    b = _dev(_sources(n, [3000]))
+    eager = m.solve(b, graph=False)
+    graph = m.solve(b, graph=True)
+    _same(eager, graph)
+    assert eager[1]["converged"].all()
+    # per-iteration latency of the two paths (informative)
+    its = int(eager[1]["iters"][0])
+    for g in (False, True, False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.solve(b, graph=g, want_hist=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _say(f"  graph={g}: {its} iterations, {dt * 1e6 / its:.1f} us per iteration")
+
+
+def test_graph_mg_only_uneven_batch(hh, ctx):
+    n = 64
+    _say("graph vs eager, 64^2 MG-only, 5 sources finishing at different cycles")
+    k = inputs.layered_slowness(n, 21)
+    m = hh.Model(ctx, torch.from_numpy(k), inputs.omega_for(n, k))
+    b = np.concatenate([_sources(n, [70, 71]), inputs.random_complex((3, n, n), 72)])
+    b[3] *= 1e-3
+    bd = _dev(b)
+    eager = m.solve(bd, graph=False)
+    graph = m.solve(bd, graph=True)
+    _same(eager, graph)
+    assert len(set(eager[1]["iters"].tolist())) > 1
+    _same(eager, m.solve(bd, graph=True))  # a second call on the same context
+
+
+def test_graph_cnn_mg_two_phase(hh, ctx):
+    n = 128
+    _say("graph vs eager, 128^2 two-phase CNN+MG with the shipped network, 6 sources")
+    k = inputs.grf_slowness(n, 1003)
+    m = hh.Model(ctx, torch.from_numpy(k), inputs.omega_for(n, k))
+    net = hh.Net.load(ctx, NET_FILE)
+    m.attach_net(net)
+    bd = _dev(_sources(n, range(3010, 3016)))
+    eager = m.solve(bd, precond=hh.HH_PRECOND_CNN_MG, graph=False)
+    graph = m.solve(bd, precond=hh.HH_PRECOND_CNN_MG, graph=True)
+    _same(eager, graph)
+    assert eager[1]["converged"].all()
+    _say(f"  iterations {eager[1]['iters'].tolist()}")
+
+
+def test_graph_two_models_and_split_coarse(hh, ctx):
+    n = 64
+    _say("graph vs eager, two slowness models; split coarse solve (eager cycles)")
+    ks = np.stack([inputs.grf_slowness(n, 40), inputs.layered_slowness(n, 41)])
+    om = inputs.omega_for(n)
+    b = np.concatenate([_sources(n, [80, 81, 82]), inputs.random_complex((1, n, n), 83)])
+    inst = [0, 1, 1, 0]
+    m = hh.Model(ctx, torch.from_numpy(ks), om)
+    eager = m.solve(_dev(b), inst=inst, graph=False)
+    _same(eager, m.solve(_dev(b), inst=inst, graph=True))
+    m0 = hh.Model(ctx, torch.from_numpy(ks), om, coarse_reduce=0)
+    m0.set_coarse_group(808)
+    eager0 = m0.solve(_dev(b), inst=inst, graph=False)
+    _same(eager0, m0.solve(_dev(b), inst=inst, graph=True))
+    assert np.array_equal(eager0[1]["converged"], eager[1]["converged"])
