@@ -138,22 +138,45 @@ class Level:
         return 4.0 / (self.h * self.h) - mass(self.k2w2, self.gamma, shift)
 
 
+def gmres_jacobi(lev: Level, b: np.ndarray, iters: int, beta: float = SL_BETA) -> np.ndarray:
+    """The iterative coarsest-grid solve of Sec. 3.4 (after the approach the
+    paper cites there): ``iters`` steps of GMRES on the shifted operator A_SL,
+    right-preconditioned by its diagonal (Jacobi), starting from zero, with no
+    restart and no early stop.  GMRES here is the flexible GMRES below with a
+    fixed preconditioner, which is plain right-preconditioned GMRES."""
+    if not np.any(b):
+        return np.zeros_like(b)
+    d = lev.diag(beta)
+    x, _, _, _ = fgmres(lambda u: lev.op(u, beta), b, lambda v: v / d, None, restart=iters, rtol=0.0,
+                        max_iters=iters)
+    return x
+
+
 class Hierarchy:
-    """Levels 0..L-1 of the shifted-Laplacian V-cycle with a sparse-direct coarsest solve."""
+    """Levels 0..L-1 of the shifted-Laplacian V-cycle.  The coarsest level is
+    solved exactly (sparse direct) when ``coarse_iters`` is 0, else by
+    ``coarse_iters`` steps of Jacobi-preconditioned GMRES (``gmres_jacobi``)."""
 
     def __init__(self, k2w2: np.ndarray, gamma: np.ndarray, levels: int = 3,
-                 beta: float = SL_BETA, nu1: int = 1, nu2: int = 1, wj: float = 0.8):
+                 beta: float = SL_BETA, nu1: int = 1, nu2: int = 1, wj: float = 0.8, coarse_iters: int = 0):
         """k2w2 = omega^2 kappa^2 and gamma on the finest level (h = 1/n)."""
         n = k2w2.shape[0]
         h = 1.0 / n
         self.beta, self.nu1, self.nu2, self.wj = beta, nu1, nu2, wj
+        self.coarse_iters = coarse_iters
         self.levels = [Level(n, h, k2w2, gamma)]
         for _ in range(1, levels):
             prev = self.levels[-1]
             self.levels.append(Level(prev.n // 2, 2.0 * prev.h, restrict_coeff(prev.k2w2),
                                      restrict_coeff(prev.gamma)))
         c = self.levels[-1]
-        self.coarse_lu = spla.splu(assemble(c.k2w2, c.gamma, c.h, beta).tocsc())
+        self.coarse_lu = None if coarse_iters > 0 else spla.splu(assemble(c.k2w2, c.gamma, c.h, beta).tocsc())
+
+    def coarse_solve(self, b: np.ndarray) -> np.ndarray:
+        c = self.levels[-1]
+        if self.coarse_iters > 0:
+            return gmres_jacobi(c, b, self.coarse_iters, self.beta)
+        return self.coarse_lu.solve(b.ravel()).reshape(b.shape)
 
     def jacobi(self, l: int, x: np.ndarray, b: np.ndarray) -> np.ndarray:
         """Damped Jacobi on the shifted operator: x + w (b - A_SL x) / diag(A_SL)."""
@@ -165,7 +188,7 @@ class Hierarchy:
         prolong and correct, relax nu2 times; exact solve on the coarsest level."""
         lev = self.levels[l]
         if l == len(self.levels) - 1:
-            return self.coarse_lu.solve(b.ravel()).reshape(b.shape)
+            return self.coarse_solve(b)
         x = np.zeros_like(b) if x0 is None else x0.copy()
         for _ in range(self.nu1):
             x = self.jacobi(l, x, b)
@@ -181,13 +204,14 @@ class Problem:
     """One slowness model: operator A (eqs. 1-3), shifted-Laplacian hierarchy."""
 
     def __init__(self, kappa: np.ndarray, omega: float, abl_width: int = 16, gamma_max: float = 1.0,
-                 gamma0: float = 0.0, levels: int = 3, beta: float = SL_BETA, wj: float = 0.8):
+                 gamma0: float = 0.0, levels: int = 3, beta: float = SL_BETA, wj: float = 0.8,
+                 coarse_iters: int = 0):
         self.n = kappa.shape[0]
         self.h = 1.0 / self.n
         self.kappa, self.omega = kappa, omega
         self.gamma = abl_gamma(self.n, abl_width, gamma_max, gamma0)
         self.k2w2 = omega ** 2 * kappa ** 2
-        self.hier = Hierarchy(self.k2w2, self.gamma, levels, beta, wj=wj)
+        self.hier = Hierarchy(self.k2w2, self.gamma, levels, beta, wj=wj, coarse_iters=coarse_iters)
 
     def A(self, u):
         return apply_op(u, self.k2w2, self.gamma, self.h, 0.0)

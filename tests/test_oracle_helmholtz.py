@@ -264,3 +264,60 @@ def test_mg_only_iterations_config1_magnitude():
     assert 30 <= its <= 170
     xs = H.exact_solve(P, b)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-4
+
+
+# ---- iterative coarsest-grid solve (GMRES with a Jacobi preconditioner, Sec. 3.4) ----
+
+def _coarse_level(n, seed):
+    k = inputs.grf_slowness(n, seed)
+    prob = H.Problem(k, inputs.omega_for(n, k), coarse_iters=1)
+    return prob.hier.levels[-1]
+
+
+def test_coarse_gmres_jacobi_is_the_minimal_residual_krylov_iterate():
+    # GMRES's defining property, by brute force: with M = diag(A_SL)^-1 on the
+    # right, x_k = M y with y in span{b, (A M) b, ..., (A M)^(k-1) b} minimising
+    # ||b - A M y||.  A left-preconditioned or unpreconditioned variant, a wrong
+    # diagonal or a dropped Givens step gives a different iterate.
+    lev = _coarse_level(32, 11)  # coarsest 8 x 8
+    b = inputs.random_complex((lev.n, lev.n), 12)
+    A = H.assemble(lev.k2w2, lev.gamma, lev.h, H.SL_BETA).toarray()
+    dinv = 1.0 / lev.diag(H.SL_BETA).ravel()
+    AM = A * dinv[None, :]
+    for k in (1, 3, 6):
+        K = np.empty((b.size, k), dtype=np.complex128)
+        K[:, 0] = b.ravel()
+        for j in range(1, k):
+            K[:, j] = AM @ K[:, j - 1]
+        Q, _ = np.linalg.qr(K)
+        c = np.linalg.lstsq(AM @ Q, b.ravel(), rcond=None)[0]
+        x_bf = (dinv * (Q @ c)).reshape(b.shape)
+        x = H.gmres_jacobi(lev, b, k)
+        assert np.linalg.norm(x - x_bf) / np.linalg.norm(x_bf) <= 1e-9
+        # and it is not the unpreconditioned Krylov iterate
+        c0 = np.linalg.lstsq(A @ Q, b.ravel(), rcond=None)[0]
+        if k > 1:
+            assert np.linalg.norm(x - (Q @ c0).reshape(b.shape)) / np.linalg.norm(x_bf) > 1e-3
+
+
+def test_coarse_gmres_jacobi_at_full_dimension_is_the_direct_solve():
+    lev = _coarse_level(16, 13)  # coarsest 4 x 4: 16 unknowns
+    b = inputs.random_complex((lev.n, lev.n), 14)
+    A = H.assemble(lev.k2w2, lev.gamma, lev.h, H.SL_BETA).tocsc()
+    x_ref = spla.spsolve(A, b.ravel()).reshape(b.shape)
+    x = H.gmres_jacobi(lev, b, 16)
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) <= 1e-8
+    assert np.array_equal(H.gmres_jacobi(lev, np.zeros_like(b), 5), np.zeros_like(b))
+
+
+def test_vcycle_with_iterative_coarse_solve():
+    n = 16
+    k = inputs.layered_slowness(n, 15)
+    om = inputs.omega_for(n, k)
+    direct = H.Problem(k, om)
+    it_full = H.Problem(k, om, coarse_iters=16)
+    it_few = H.Problem(k, om, coarse_iters=2)
+    b = inputs.random_complex((n, n), 16)
+    zd = direct.mg(b)
+    assert np.linalg.norm(it_full.mg(b) - zd) / np.linalg.norm(zd) <= 1e-8
+    assert np.linalg.norm(it_few.mg(b) - zd) / np.linalg.norm(zd) > 1e-4
