@@ -92,6 +92,12 @@ typedef struct {
                               and runs the two-ended block elimination on the even rows (half
                               the sequential chain, about twice the factor memory); 0 runs the
                               two-ended elimination on all grid rows */
+    int coarse_iters;      /* 0 (default): the coarsest level is solved exactly (above).  k in
+                              1..16: instead k steps of GMRES on the coarsest shifted operator,
+                              right-preconditioned by its diagonal (Jacobi), from zero, without
+                              restart -- the iterative coarsest-grid solve of Sec. 3.4; no
+                              factorisation is built (the option for coarsest grids where the
+                              sequential elimination is too slow, e.g. 1024 x 1024) */
 } hh_model_desc;
 
 /* Fill *d with the defaults listed above (n and omega are set to 0). */

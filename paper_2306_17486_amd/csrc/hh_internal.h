@@ -253,6 +253,12 @@ hh_status launch_vcycle_strided(hh_model* m, int nrhs, const BatchMap& bm, const
 int coarse_group();
 bool coarse_choice_valid(const hh_model* md, int c);
 bool coarse_capturable(const hh_model* md, int nrhs, int nact);
+// iterative coarsest-grid solve (coarse_gmres.hip): workspace bytes for nrhs
+// right-hand sides (0 with the exact solve), the launcher, the step limit
+size_t coarse_gmres_bytes(const hh_model* md, int nrhs);
+hh_status launch_coarse_gmres(hh_model* md, int nrhs, const int* inst, const float2* bc, float2* xc,
+                              const int* active, void* work);
+int coarse_gmres_max_iters();
 // a non-blocking stream of the context for graph capture (created on first use)
 hh_status capture_stream(hh_ctx* c, hipStream_t* out);
 hh_status coarse_check_err(hh_model* md);

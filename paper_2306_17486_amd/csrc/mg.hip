@@ -1025,7 +1025,8 @@ static CoarseWork coarse_work(const hh_model* md, void* base, int nrhs) {
 }
 
 size_t vcycle_workspace_bytes(const hh_model* md, int nrhs, bool with_x0) {
-    return vcycle_float_bytes(md, nrhs, with_x0) + coarse_work_bytes(md, nrhs) + 256;
+    return vcycle_float_bytes(md, nrhs, with_x0) + coarse_work_bytes(md, nrhs) + 256 + coarse_gmres_bytes(md, nrhs) +
+           256;
 }
 
 int coarse_group() { return CS_RMAX; }
@@ -1248,7 +1249,9 @@ static bool valid_choice(int c) {
 }
 
 // the reduced solve's codes need the reduced factorisation, the others the plain one
-bool coarse_choice_valid(const hh_model* md, int c) { return valid_choice(c) && (reduced_code(c) == md->cr1); }
+bool coarse_choice_valid(const hh_model* md, int c) {
+    return md->d.coarse_iters == 0 && valid_choice(c) && (reduced_code(c) == md->cr1);
+}
 
 // the split solve's timeout flag: reported (and cleared) after a solve
 hh_status coarse_check_err(hh_model* md) {
@@ -1275,6 +1278,7 @@ static int coarse_bucket(int n) {
 // is already decided (forced or tuned) and launches no cooperative kernel: then
 // its launch sequence can be captured into a graph
 bool coarse_capturable(const hh_model* md, int nrhs, int nact) {
+    if (md->d.coarse_iters > 0) return true;
     const int na = nact > 0 ? std::min(nact, nrhs) : nrhs;
     const int c = md->coarse_R_forced > 0 ? md->coarse_R_forced : md->coarse_R[coarse_bucket(std::max(na, 1))];
     return c > 0 && (c < 100 || reduced_code(c));
@@ -1390,29 +1394,35 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         ProfScope ps(md->ctx, HH_K_VC_COARSE);
         const int m = lc.n, p = m / 2;
         const float c = (float)(1.0 / (lc.h * lc.h));
-        // every workgroup serves R right-hand sides of one slowness model: with
-        // several models the host's grouping order (padded per model to
-        // CS_RMAX); with one model the active right-hand sides, packed
-        const int* slots = bm.order;
-        int nslots = bm.order ? bm.nslots : nrhs;
-        const int* nslots_dev = nullptr;
-        if (!bm.order && active) {
-            hipLaunchKernelGGL(k_coarse_compact, dim3(1), dim3(1024), 0, st, active, nrhs, cw.slots, cw.count);
-            HH_LAUNCH_CHECK();
-            slots = cw.slots;
-            nslots_dev = cw.count;
-            if (bm.nact > 0) nslots = std::min(nslots, bm.nact);
+        if (md->d.coarse_iters > 0) {
+            char* gw = (char*)work + vcycle_float_bytes(md, nrhs, x0 != nullptr) + coarse_work_bytes(md, nrhs) + 256;
+            gw = (char*)(((uintptr_t)gw + 255) & ~(uintptr_t)255);
+            HH_TRY(launch_coarse_gmres(md, nrhs, inst_dev, bl[L - 1], el[L - 1], active, gw));
+        } else {
+            // every workgroup serves R right-hand sides of one slowness model: with
+            // several models the host's grouping order (padded per model to
+            // CS_RMAX); with one model the active right-hand sides, packed
+            const int* slots = bm.order;
+            int nslots = bm.order ? bm.nslots : nrhs;
+            const int* nslots_dev = nullptr;
+            if (!bm.order && active) {
+                hipLaunchKernelGGL(k_coarse_compact, dim3(1), dim3(1024), 0, st, active, nrhs, cw.slots, cw.count);
+                HH_LAUNCH_CHECK();
+                slots = cw.slots;
+                nslots_dev = cw.count;
+                if (bm.nact > 0) nslots = std::min(nslots, bm.nact);
+            }
+            const int nact = bm.nact > 0 ? std::min(bm.nact, nrhs) : nrhs;
+            int choice = 1;
+            HH_TRY(coarse_pick(md, nact, bl[L - 1], el[L - 1], ends, slots, nslots, nslots_dev, m, p, c, inst_dev,
+                               active, cw, &choice));
+            bool fits = true;
+            HH_TRY(launch_coarse_choice(choice, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots, nslots_dev, m,
+                                        p, c, active, cw, &fits));
+            if (!fits)  // a forced split variant that cannot be resident here: the chain
+                HH_TRY(launch_coarse_choice(md->cr1 ? 1001 : 1, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots,
+                                            nslots_dev, m, p, c, active, cw, &fits));
         }
-        const int nact = bm.nact > 0 ? std::min(bm.nact, nrhs) : nrhs;
-        int choice = 1;
-        HH_TRY(coarse_pick(md, nact, bl[L - 1], el[L - 1], ends, slots, nslots, nslots_dev, m, p, c, inst_dev,
-                           active, cw, &choice));
-        bool fits = true;
-        HH_TRY(launch_coarse_choice(choice, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots, nslots_dev, m,
-                                    p, c, active, cw, &fits));
-        if (!fits)  // a forced split variant that cannot be resident here: the chain
-            HH_TRY(launch_coarse_choice(md->cr1 ? 1001 : 1, md, bl[L - 1], el[L - 1], ends, inst_dev, slots, nslots,
-                                        nslots_dev, m, p, c, active, cw, &fits));
     }
     // up sweep
     for (int l = L - 2; l >= 0; --l) {

@@ -421,6 +421,11 @@ static hh_status setup_coarse_reduced(hh_model* md) {
 }
 
 hh_status setup_coarse_factors(hh_model* md) {
+    if (md->d.coarse_iters > 0) {  // iterative coarsest-grid solve: nothing to factorise
+        md->m = md->lev[md->nlev - 1].n;
+        md->cr1 = false;
+        return HH_OK;
+    }
     if (md->d.coarse_reduce) return setup_coarse_reduced(md);
     hh_ctx* ctx = md->ctx;
     const Level& C = md->lev[md->nlev - 1];

@@ -42,7 +42,8 @@ _lib = C.CDLL(LIB_PATH)
 class hh_model_desc(C.Structure):
     _fields_ = [("n", C.c_int), ("omega", C.c_double), ("abl_width", C.c_int), ("abl_gamma_max", C.c_double),
                 ("gamma0", C.c_double), ("sl_beta", C.c_double), ("levels", C.c_int), ("nu_pre", C.c_int),
-                ("nu_post", C.c_int), ("jacobi_w", C.c_double), ("coarse_reduce", C.c_int)]
+                ("nu_post", C.c_int), ("jacobi_w", C.c_double), ("coarse_reduce", C.c_int),
+                ("coarse_iters", C.c_int)]
 
 
 class hh_solve_opts(C.Structure):
