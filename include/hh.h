@@ -172,6 +172,27 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
                    void* x_dev, const hh_solve_opts* o, double* res_hist_host, int* iters_host,
                    int* converged_host, double* final_res_host, int* mg_cycles_host, int* cnn_iters_host);
 
+/* Several slowness models of any sizes solved together (the batched
+ * multi-instance solve of Sec. 5: many media, several right-hand sides
+ * each): model i (its own n, one or more slowness instances) gets nrhs[i]
+ * right-hand sides b_dev[i] (c64 [nrhs[i]][n_i][n_i]), solutions x_dev[i]
+ * (c128) and optional RHS -> instance maps inst_host[i] (host; the array or an
+ * entry may be NULL).  Each model's FGMRES runs on its own internal stream
+ * (default priority); the restart cycles of all models are issued in one
+ * interleaved sequence (every model's restart residual, then one wait per
+ * model, then every model's cycle), so the sizes overlap on the device.
+ * Every model runs the kernels a single hh_solve with the same options runs,
+ * so the results are those of separate hh_solve calls.  One options struct
+ * for all (fixed_iters must be 0).  The per-model output arrays
+ * (iters_host[i], ... host int/double [nrhs[i]]) may be NULL as a whole or
+ * per entry.  The context's stream is synchronised before the solves start
+ * and the model streams before the call returns.  Returns HH_NOT_CONVERGED if
+ * any RHS of any model stopped at max_iters. */
+hh_status hh_solve_batch(hh_ctx* ctx, int nmodels, hh_model* const* models, const int* nrhs,
+                         const int* const* inst_host, const void* const* b_dev, void* const* x_dev,
+                         const hh_solve_opts* o, int* const* iters_host, int* const* converged_host,
+                         double* const* final_res_host, int* const* mg_cycles_host, int* const* cnn_iters_host);
+
 /* Autotuner of the coarsest exact solve (the two-ended block-tridiagonal
  * elimination).  Variants: the chain, one workgroup per end for every R
  * right-hand sides (code R = 1, 2, 4, 8; each Schur inverse read serves R

@@ -3,7 +3,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <memory>
 #include <new>
+#include <vector>
 
 #include "hh_internal.h"
 #include "krylov.h"
@@ -219,9 +221,8 @@ void hh_solve_opts_default(hh_solve_opts* o) {
     o->graph = 1;
 }
 
-hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev, void* x_dev,
-                   const hh_solve_opts* o, double* res_hist_host, int* iters_host, int* converged_host,
-                   double* final_res_host, int* mg_cycles_host, int* cnn_iters_host) {
+static hh_status check_solve_args(hh_ctx* ctx, hh_model* m, int nrhs, const void* b_dev, void* x_dev,
+                                  const hh_solve_opts* o) {
     HH_ARG(ctx && m && b_dev && x_dev && o, "null pointer");
     HH_ARG(m->ctx == ctx, "model belongs to another context");
     HH_ARG(nrhs >= 1, "nrhs >= 1");
@@ -231,6 +232,42 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
     HH_ARG(o->fixed_iters >= 0 && o->fixed_iters <= o->restart, "0 <= fixed_iters <= restart");
     HH_ARG(o->probe_ratio >= 0.0 && o->probe_ratio <= 1.0, "0 <= probe_ratio <= 1");
     HH_ARG(o->precond == HH_PRECOND_MG || m->net != nullptr, "CNN_MG needs a network attached to the model");
+    return HH_OK;
+}
+
+// per-RHS results of a finished solve (stream synchronised here)
+static hh_status read_results(hh_ctx* ctx, hipStream_t st, SolveWork& W, int nrhs, int hist_len, bool fixed,
+                              double* res_hist_host, int* iters_host, int* converged_host, double* final_res_host,
+                              int* mg_cycles_host, int* cnn_iters_host) {
+    (void)ctx;
+    std::vector<KState> hs(nrhs);
+    HH_HIP(hipMemcpyAsync(hs.data(), W.state.ptr, (size_t)nrhs * sizeof(KState), hipMemcpyDeviceToHost, st));
+    if (res_hist_host)
+        HH_HIP(hipMemcpyAsync(res_hist_host, W.hist.ptr, (size_t)nrhs * hist_len * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+    HH_HIP(hipStreamSynchronize(st));
+    bool all_conv = true, broke = false;
+    for (int r = 0; r < nrhs; ++r) {
+        if (iters_host) iters_host[r] = hs[r].iters;
+        if (converged_host) converged_host[r] = hs[r].converged;
+        if (final_res_host) final_res_host[r] = hs[r].res_true;
+        if (mg_cycles_host) mg_cycles_host[r] = hs[r].mg_cycles;
+        if (cnn_iters_host) cnn_iters_host[r] = hs[r].cnn_iters;
+        all_conv = all_conv && hs[r].converged;
+        broke = broke || hs[r].breakdown;
+    }
+    if (broke) {
+        set_error("NaN or Inf met in the solve");
+        return HH_ERR_BREAKDOWN;
+    }
+    if (fixed) return HH_OK;
+    return all_conv ? HH_OK : HH_NOT_CONVERGED;
+}
+
+hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev, void* x_dev,
+                   const hh_solve_opts* o, double* res_hist_host, int* iters_host, int* converged_host,
+                   double* final_res_host, int* mg_cycles_host, int* cnn_iters_host) {
+    HH_TRY(check_solve_args(ctx, m, nrhs, b_dev, x_dev, o));
     HH_HIP(hipSetDevice(ctx->device));
     if (!ctx->work) {
         ctx->work = new (std::nothrow) SolveWork();
@@ -250,29 +287,76 @@ hh_status hh_solve(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, con
                                cnn ? net_precond : nullptr, cnn ? (void*)m : nullptr);
     if (s < 0) return s;
     HH_TRY(coarse_check_err(m));
-    // results
-    std::vector<KState> hs(nrhs);
-    HH_HIP(hipMemcpyAsync(hs.data(), W.state.ptr, (size_t)nrhs * sizeof(KState), hipMemcpyDeviceToHost, ctx->stream));
-    if (res_hist_host)
-        HH_HIP(hipMemcpyAsync(res_hist_host, W.hist.ptr, (size_t)nrhs * hist_len * sizeof(double),
-                              hipMemcpyDeviceToHost, ctx->stream));
+    return read_results(ctx, ctx->stream, W, nrhs, hist_len, o->fixed_iters > 0, res_hist_host, iters_host,
+                        converged_host, final_res_host, mg_cycles_host, cnn_iters_host);
+}
+
+hh_status hh_solve_batch(hh_ctx* ctx, int nmodels, hh_model* const* models, const int* nrhs,
+                         const int* const* inst_host, const void* const* b_dev, void* const* x_dev,
+                         const hh_solve_opts* o, int* const* iters_host, int* const* converged_host,
+                         double* const* final_res_host, int* const* mg_cycles_host, int* const* cnn_iters_host) {
+    HH_ARG(ctx && models && nrhs && b_dev && x_dev && o, "null pointer");
+    HH_ARG(nmodels >= 1, "nmodels >= 1");
+    HH_ARG(o->fixed_iters == 0, "fixed_iters must be 0 in a batch");
+    for (int i = 0; i < nmodels; ++i) {
+        HH_TRY(check_solve_args(ctx, models[i], nrhs[i], b_dev[i], x_dev[i], o));
+        for (int k = 0; k < i; ++k) HH_ARG(models[k] != models[i], "a model appears twice in the batch");
+    }
+    HH_HIP(hipSetDevice(ctx->device));
+    const bool cnn = o->precond == HH_PRECOND_CNN_MG;
+    const int hist_len = o->max_iters + 1;
+    std::vector<std::unique_ptr<SolveWork>> work(nmodels);
+    std::vector<SolveWork*> wp(nmodels);
+    std::vector<BatchMap> bm(nmodels);
+    std::vector<hh_model*> mp(models, models + nmodels);
+    std::vector<const float2*> bp(nmodels);
+    std::vector<double2*> xp(nmodels);
+    for (int i = 0; i < nmodels; ++i) {
+        work[i].reset(new (std::nothrow) SolveWork());
+        if (!work[i]) {
+            set_error("out of host memory");
+            return HH_ERR_NOMEM;
+        }
+        wp[i] = work[i].get();
+        HH_TRY(wp[i]->prepare(ctx, models[i], nrhs[i], o->restart, hist_len, cnn));
+        HH_TRY(upload_inst_map(models[i], wp[i]->inst, nrhs[i], inst_host ? inst_host[i] : nullptr, &bm[i]));
+        bp[i] = (const float2*)b_dev[i];
+        xp[i] = (double2*)x_dev[i];
+    }
+    // one stream per model (default priority); inputs are ordered by the
+    // context's stream, which is idle here
     HH_HIP(hipStreamSynchronize(ctx->stream));
-    bool all_conv = true, broke = false;
-    for (int r = 0; r < nrhs; ++r) {
-        if (iters_host) iters_host[r] = hs[r].iters;
-        if (converged_host) converged_host[r] = hs[r].converged;
-        if (final_res_host) final_res_host[r] = hs[r].res_true;
-        if (mg_cycles_host) mg_cycles_host[r] = hs[r].mg_cycles;
-        if (cnn_iters_host) cnn_iters_host[r] = hs[r].cnn_iters;
-        all_conv = all_conv && hs[r].converged;
-        broke = broke || hs[r].breakdown;
+    struct Streams {
+        std::vector<hipStream_t> s;
+        ~Streams() {
+            for (hipStream_t x : s) {
+                (void)hipStreamSynchronize(x);
+                (void)hipStreamDestroy(x);
+            }
+        }
+    } streams;
+    for (int i = 0; i < nmodels; ++i) {
+        hipStream_t x;
+        HH_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        streams.s.push_back(x);
     }
-    if (broke) {
-        set_error("NaN or Inf met in the solve");
-        return HH_ERR_BREAKDOWN;
+    hh_status s = fgmres_solve_many(nmodels, mp.data(), wp.data(), bm.data(), bp.data(), xp.data(), *o,
+                                    cnn ? net_precond : nullptr, streams.s.data());
+    for (hipStream_t x : streams.s) HH_HIP(hipStreamSynchronize(x));
+    if (s < 0) return s;
+    hh_status worst = HH_OK;
+    for (int i = 0; i < nmodels; ++i) {
+        HH_TRY(coarse_check_err(models[i]));
+        const hh_status r = read_results(ctx, ctx->stream, *wp[i], nrhs[i], hist_len, false, nullptr,
+                                         iters_host ? iters_host[i] : nullptr,
+                                         converged_host ? converged_host[i] : nullptr,
+                                         final_res_host ? final_res_host[i] : nullptr,
+                                         mg_cycles_host ? mg_cycles_host[i] : nullptr,
+                                         cnn_iters_host ? cnn_iters_host[i] : nullptr);
+        if (r < 0) return r;
+        if (r == HH_NOT_CONVERGED) worst = HH_NOT_CONVERGED;
     }
-    if (o->fixed_iters > 0) return HH_OK;
-    return all_conv ? HH_OK : HH_NOT_CONVERGED;
+    return worst;
 }
 
 hh_status hh_apply_operator(hh_model* m, int level, double shift, int nrhs, const int* inst_host, const void* x_dev,

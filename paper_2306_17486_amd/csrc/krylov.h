@@ -45,6 +45,11 @@ typedef hh_status (*PrecondFn)(void* user, hh_model* md, SolveWork& W, const Bat
 
 hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* b, double2* x,
                        const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user);
+// Several solves (one per model, any sizes) with interleaved restart cycles,
+// solve i on streams[i]; fixed_iters must be 0.
+hh_status fgmres_solve_many(int nruns, hh_model* const* md, SolveWork* const* W, const BatchMap* bm,
+                            const float2* const* b, double2* const* x, const hh_solve_opts& o, PrecondFn precond_cnn,
+                            const hipStream_t* streams);
 hh_status precond_mg_strided(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* v, size_t vstride,
                              const double* sig, int sig_stride, float2* z, size_t zstride, const int* act);
 

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 
 #include "hh_internal.h"
 #include "krylov.h"
@@ -551,11 +552,124 @@ struct CycleGraphs {
     }
 };
 
-hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* b, double2* x,
-                       const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user) {
+// One FGMRES(m) solve driven in phases, so that several solves (models of
+// different sizes) can interleave their restart cycles on their own streams:
+// start(); then per cycle begin_cycle() (restart residual, per-RHS decisions,
+// flags to the host), wait_cycle() (reads them; tells whether every RHS is
+// done) and run_cycle() (the cycle's launches, eager or from a graph).  Every
+// phase launches on `stream` (the context's stream is switched to it meanwhile).
+class FgmresRun {
+  public:
+    FgmresRun(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* b, double2* x, const hh_solve_opts& o,
+              PrecondFn precond_cnn, void* precond_user, hipStream_t stream)
+        : md_(md), W_(W), bm_(bm), b_(b), x_(x), o_(o), pc_(precond_cnn), pu_(precond_user), stream_(stream) {}
+    ~FgmresRun() {
+        if (hflags_) (void)hipHostFree(hflags_);
+    }
+    hh_status start();
+    hh_status begin_cycle();
+    hh_status wait_cycle(bool* finished);
+    hh_status run_cycle();
+    bool fixed_done() const { return fixed_done_; }
+
+  private:
+    // switches the context's stream to this solve's stream for one phase
+    struct StreamGuard {
+        hh_ctx* c;
+        hipStream_t saved;
+        StreamGuard(hh_ctx* ctx, hipStream_t s) : c(ctx), saved(ctx->stream) { c->stream = s; }
+        ~StreamGuard() { c->stream = saved; }
+    };
+    hh_model* md_;
+    SolveWork& W_;
+    BatchMap bm_;
+    const float2* b_;
+    double2* x_;
+    hh_solve_opts o_;
+    PrecondFn pc_;
+    void* pu_;
+    hipStream_t stream_;
+    int* hflags_ = nullptr;  // pinned host copy of [done | actc | actm]
+    CycleGraphs graphs_;
+    int cycle_ = 0, cnt_c_ = 0, cnt_m_ = 0;
+    bool warm_ = false, fixed_done_ = false;
+};
+
+hh_status FgmresRun::start() {
+    StreamGuard g(md_->ctx, stream_);
+    const int n = W_.n, nrhs = W_.nrhs, np = W_.npart;
+    const dim3 blk(KT_X, KT_Y / KT_ROWS);
+    const dim3 grd((n + KT_X - 1) / KT_X, (n + KT_Y - 1) / KT_Y, nrhs);
+    KState* S = W_.state.as<KState>();
+    int* done = W_.flags.as<int>();
+    if (!hflags_) HH_HIP(hipHostMalloc((void**)&hflags_, (size_t)3 * nrhs * sizeof(int), hipHostMallocDefault));
+    hipLaunchKernelGGL(k_norm2, grd, blk, 0, stream_, b_, n, W_.parts.as<double2>());
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_init_state, dim3(nrhs), dim3(256), 0, stream_, W_.parts.as<double2>(), np, S, done,
+                       done + 3 * nrhs, W_.hist.as<double>(), W_.hist_len);
+    HH_LAUNCH_CHECK();
+    if (!o_.use_x0) HH_HIP(hipMemsetAsync(x_, 0, (size_t)nrhs * n * n * sizeof(double2), stream_));
+    return HH_OK;
+}
+
+hh_status FgmresRun::begin_cycle() {
+    StreamGuard g(md_->ctx, stream_);
+    hh_ctx* ctx = md_->ctx;
+    const int n = W_.n, nrhs = W_.nrhs, np = W_.npart;
+    const size_t vstride = (size_t)(W_.restart + 1) * n * n;
+    const dim3 blk(KT_X, KT_Y / KT_ROWS);
+    const dim3 grd((n + KT_X - 1) / KT_X, (n + KT_Y - 1) / KT_Y, nrhs);
+    const Level& L0 = md_->lev[0];
+    int* done = W_.flags.as<int>();
+    const bool fixed = o_.fixed_iters > 0;
+    const bool cnn = pc_ != nullptr;
+    warm_ = cnn && cycle_ == 0 && o_.warm_mg_iters > 0;
+    {
+        ProfScope ps(ctx, HH_K_RESTART);
+        hipLaunchKernelGGL(k_residual64, grd, blk, 0, stream_, x_, b_, W_.V.as<float2>(), vstride,
+                           L0.coef.as<float2>(), bm_.inst, n, 1.0 / (L0.h * L0.h), W_.parts.as<double2>(), done);
+    }
+    HH_LAUNCH_CHECK();
+    {
+        ProfScope ps(ctx, HH_K_SMALL);
+        hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, stream_, W_.parts.as<double2>(), np,
+                           W_.state.as<KState>(), done, done + 3 * nrhs, done + nrhs, done + 2 * nrhs,
+                           W_.hist.as<double>(), W_.hist_len, fixed ? 0.0 : o_.rtol,
+                           fixed ? o_.fixed_iters : o_.max_iters, fixed ? 1 : 0, W_.caps_dev, cnn ? 1 : 0,
+                           warm_ ? 1 : 0, o_.fallback, o_.probe_ratio);
+    }
+    HH_LAUNCH_CHECK();
+    HH_HIP(hipMemcpyAsync(hflags_, done, (size_t)3 * nrhs * sizeof(int), hipMemcpyDeviceToHost, stream_));
+    return HH_OK;
+}
+
+hh_status FgmresRun::wait_cycle(bool* finished) {
+    HH_HIP(hipStreamSynchronize(stream_));
+    const int nrhs = W_.nrhs;
+    bool all = true;
+    cnt_c_ = cnt_m_ = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        all = all && hflags_[r];
+        cnt_c_ += hflags_[nrhs + r];
+        cnt_m_ += hflags_[2 * nrhs + r];
+    }
+    *finished = all || fixed_done_;
+    return HH_OK;
+}
+
+hh_status FgmresRun::run_cycle() {
+    StreamGuard guard(md_->ctx, stream_);
+    hh_model* md = md_;
+    SolveWork& W = W_;
+    const hh_solve_opts& o = o_;
+    const BatchMap& bm = bm_;
+    PrecondFn precond_cnn = pc_;
+    void* precond_user = pu_;
+    double2* x = x_;
+    const float2* b = b_;
     const int* inst_dev = bm.inst;
     hh_ctx* ctx = md->ctx;
-    hipStream_t st = ctx->stream;
+    hipStream_t st = stream_;
     const int n = W.n, nrhs = W.nrhs;
     const size_t nn = (size_t)n * n;
     const size_t vstride = (size_t)(W.restart + 1) * nn, zstride = (size_t)W.restart * nn;
@@ -577,55 +691,20 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
     const bool fixed = o.fixed_iters > 0;
     const double rtol = fixed ? 0.0 : o.rtol;
     const int max_iters = fixed ? o.fixed_iters : o.max_iters;
-
-    // ||b||
-    hipLaunchKernelGGL(k_norm2, grd, blk, 0, st, b, n, parts);
-    HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_init_state, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, hist, W.hist_len);
-    HH_LAUNCH_CHECK();
-    if (!o.use_x0) HH_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * nn * sizeof(double2), st));
-
-    std::vector<int> hflags((size_t)3 * nrhs);
-    CycleGraphs graphs;
-    int cycle = 0;
-    const bool cnn = precond_cnn != nullptr;
-    for (;;) {
-        const bool warm = cnn && cycle == 0 && o.warm_mg_iters > 0;
-        {
-            ProfScope ps(ctx, HH_K_RESTART);
-            hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
-                               1.0 / (L0.h * L0.h), parts, done);
-        }
-        HH_LAUNCH_CHECK();
-        {
-            ProfScope ps(ctx, HH_K_SMALL);
-            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, actc, actm,
-                               hist, W.hist_len, rtol, max_iters, fixed ? 1 : 0, W.caps_dev, cnn ? 1 : 0,
-                               warm ? 1 : 0, o.fallback, o.probe_ratio);
-        }
-        HH_LAUNCH_CHECK();
-        HH_HIP(hipMemcpyAsync(hflags.data(), done, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-        HH_HIP(hipStreamSynchronize(st));
-        bool all = true;
-        int cnt_c = 0, cnt_m = 0;
-        for (int r = 0; r < nrhs; ++r) {
-            all = all && hflags[r];
-            cnt_c += hflags[nrhs + r];
-            cnt_m += hflags[2 * nrhs + r];
-        }
-        if (all) break;
-        const bool any_c = cnt_c > 0, any_m = cnt_m > 0;
-        // the active counts only fall during a cycle: upper bounds for the coarse solves
-        BatchMap bmc = bm, bmm = bm;
-        bmc.nact = cnt_c;
-        bmm.nact = cnt_m;
-        int len = W.restart;
-        if (warm) len = std::min(len, o.warm_mg_iters);
-        if (fixed) len = std::min(len, o.fixed_iters);
-        // every launch of the cycle, on the context's current stream (a capture
-        // stream while a graph is recorded)
-        auto body = [&]() -> hh_status {
-            hipStream_t s = ctx->stream;
+    const int cnt_c = cnt_c_, cnt_m = cnt_m_;
+    const bool warm = warm_;
+    const bool any_c = cnt_c > 0, any_m = cnt_m > 0;
+    // the active counts only fall during a cycle: upper bounds for the coarse solves
+    BatchMap bmc = bm, bmm = bm;
+    bmc.nact = cnt_c;
+    bmm.nact = cnt_m;
+    int len = W.restart;
+    if (warm) len = std::min(len, o.warm_mg_iters);
+    if (fixed) len = std::min(len, o.fixed_iters);
+    // every launch of the cycle, on the context's current stream (a capture
+    // stream while a graph is recorded)
+    auto body = [&]() -> hh_status {
+        hipStream_t s = ctx->stream;
             for (int j = 0; j < len; ++j) {
                 const float2* vj = V + (size_t)j * nn;
                 const double* sg =
@@ -677,32 +756,77 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
             }
             HH_LAUNCH_CHECK();
             return HH_OK;
-        };
-        // graph path: a configuration runs eagerly the first time (lazy set-up and
-        // coarse-solve tuning happen there), is captured the second time and
-        // replayed after that
-        CycleGraphs::Entry* ge = nullptr;
-        if (o.graph && !fixed && ctx->prof_class < 0) ge = graphs.find(len, warm ? 1 : 0, cnt_c, cnt_m);
-        if (ge && !ge->exec && ge->seen >= 1 && (!any_c || coarse_capturable(md, nrhs, cnt_c)) &&
-            (!any_m || coarse_capturable(md, nrhs, cnt_m)))
-            HH_TRY(graphs.capture(ctx, ge, body));
-        if (ge && ge->exec) {
-            HH_HIP(hipGraphLaunch(ge->exec, st));
-        } else {
-            HH_TRY(body());
-            if (ge) ge->seen++;
+    };
+    // graph path: a configuration runs eagerly the first time (lazy set-up and
+    // coarse-solve tuning happen there), is captured the second time and
+    // replayed after that
+    CycleGraphs::Entry* ge = nullptr;
+    if (o.graph && !fixed && ctx->prof_class < 0) ge = graphs_.find(len, warm ? 1 : 0, cnt_c, cnt_m);
+    if (ge && !ge->exec && ge->seen >= 1 && (!any_c || coarse_capturable(md, nrhs, cnt_c)) &&
+        (!any_m || coarse_capturable(md, nrhs, cnt_m)))
+        HH_TRY(graphs_.capture(ctx, ge, body));
+    if (ge && ge->exec) {
+        HH_HIP(hipGraphLaunch(ge->exec, st));
+    } else {
+        HH_TRY(body());
+        if (ge) ge->seen++;
+    }
+    ++cycle_;
+    if (fixed) {
+        // one cycle only: mark everything done after the final residual
+        hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
+                           1.0 / (L0.h * L0.h), parts, nullptr);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, actc, actm, hist,
+                           W.hist_len, rtol, 0, 1, W.caps_dev, 0, 0, 0, 0.0);
+        HH_LAUNCH_CHECK();
+        fixed_done_ = true;
+    }
+    return HH_OK;
+}
+
+hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const float2* b, double2* x,
+                       const hh_solve_opts& o, PrecondFn precond_cnn, void* precond_user) {
+    FgmresRun run(md, W, bm, b, x, o, precond_cnn, precond_user, md->ctx->stream);
+    HH_TRY(run.start());
+    for (;;) {
+        HH_TRY(run.begin_cycle());
+        bool fin = false;
+        HH_TRY(run.wait_cycle(&fin));
+        if (fin) break;
+        HH_TRY(run.run_cycle());
+        if (run.fixed_done()) break;
+    }
+    return HH_OK;
+}
+
+hh_status fgmres_solve_many(int nruns, hh_model* const* md, SolveWork* const* W, const BatchMap* bm,
+                            const float2* const* b, double2* const* x, const hh_solve_opts& o, PrecondFn precond_cnn,
+                            const hipStream_t* streams) {
+    std::vector<std::unique_ptr<FgmresRun>> runs;
+    for (int i = 0; i < nruns; ++i) {
+        runs.emplace_back(new (std::nothrow) FgmresRun(md[i], *W[i], bm[i], b[i], x[i], o, precond_cnn,
+                                                       precond_cnn ? (void*)md[i] : nullptr, streams[i]));
+        if (!runs.back()) {
+            set_error("out of host memory");
+            return HH_ERR_NOMEM;
         }
-        ++cycle;
-        if (fixed) {
-            // one cycle only: mark everything done after the final residual
-            hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
-                               1.0 / (L0.h * L0.h), parts, nullptr);
-            HH_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, actc, actm,
-                               hist, W.hist_len, rtol, 0, 1, W.caps_dev, 0, 0, 0, 0.0);
-            HH_LAUNCH_CHECK();
-            break;
+        HH_TRY(runs.back()->start());
+    }
+    std::vector<int> live(nruns);
+    for (int i = 0; i < nruns; ++i) live[i] = i;
+    while (!live.empty()) {
+        // all restart residuals and decisions first, then the waits, then the
+        // cycles: the streams overlap each other's work
+        for (int i : live) HH_TRY(runs[i]->begin_cycle());
+        std::vector<int> next;
+        for (int i : live) {
+            bool fin = false;
+            HH_TRY(runs[i]->wait_cycle(&fin));
+            if (!fin) next.push_back(i);
         }
+        live.swap(next);
+        for (int i : live) HH_TRY(runs[i]->run_cycle());
     }
     return HH_OK;
 }

@@ -78,6 +78,8 @@ hh_model_create = _sig("hh_model_create", _I, _P, C.POINTER(hh_model_desc), _I, 
 hh_model_destroy = _sig("hh_model_destroy", _I, _P)
 hh_solve_opts_default = _sig("hh_solve_opts_default", None, C.POINTER(hh_solve_opts))
 hh_solve = _sig("hh_solve", _I, _P, _P, _I, _IP, _P, _P, C.POINTER(hh_solve_opts), _DP, _IP, _IP, _DP, _IP, _IP)
+hh_solve_batch = _sig("hh_solve_batch", _I, _P, _I, _P, _IP, _P, _P, _P, C.POINTER(hh_solve_opts), _P, _P, _P, _P,
+                      _P)
 hh_apply_operator = _sig("hh_apply_operator", _I, _P, _I, _D, _I, _IP, _P, _P)
 hh_apply_vcycle = _sig("hh_apply_vcycle", _I, _P, _I, _IP, _P, _P, _P)
 class hh_net_desc(C.Structure):
@@ -296,6 +298,47 @@ class Model:
         check(st, allow=(HH_OK, HH_NOT_CONVERGED))
         return x, dict(iters=iters, converged=conv.astype(bool), final_res=fres, hist=hist, status=st,
                        mg_cycles=mgc, cnn_iters=cnnit)
+
+
+def _ptr_array(ctype, items):
+    arr = (ctype * len(items))(*items)
+    return arr, C.cast(arr, C.c_void_p)
+
+
+def solve_batch(ctx: Context, models, bs, insts=None, restart=10, max_iters=2000, rtol=1e-6, precond=HH_PRECOND_MG,
+                warm_mg_iters=3, fallback=True, probe_ratio=0.5, graph=True):
+    """Several models (any sizes) solved in one interleaved launch sequence
+    (hh_solve_batch).  bs[i]: right-hand sides of models[i]; insts[i]: optional
+    RHS -> instance map.  Returns [(x complex128 tensor, info dict)] per model."""
+    nm = len(models)
+    bs = [b.to(torch.complex64).contiguous() for b in bs]
+    xs = [torch.empty(b.shape, dtype=torch.complex128, device=b.device) for b in bs]
+    o = hh_solve_opts()
+    hh_solve_opts_default(C.byref(o))
+    o.restart, o.max_iters, o.rtol, o.precond = restart, max_iters, rtol, precond
+    o.warm_mg_iters, o.fallback, o.probe_ratio, o.graph = warm_mg_iters, int(fallback), probe_ratio, int(graph)
+    nr = [b.shape[0] for b in bs]
+    out = {k: [np.zeros(n, dtype=np.int32) for n in nr] for k in ("iters", "converged", "mg_cycles", "cnn_iters")}
+    fres = [np.zeros(n) for n in nr]
+    inst_arrays = [_int_array(insts[i]) if insts is not None and insts[i] is not None else None for i in range(nm)]
+    keep = []
+
+    def ints(lst):
+        a, p = _ptr_array(_IP, [x.ctypes.data_as(_IP) for x in lst])
+        keep.append(a)
+        return p
+
+    ma, mp = _ptr_array(C.c_void_p, [m.handle for m in models])
+    ia, ip = _ptr_array(_IP, [C.cast(a, _IP) if a is not None else None for a in inst_arrays])
+    ba, bp = _ptr_array(C.c_void_p, [b.data_ptr() for b in bs])
+    xa, xp = _ptr_array(C.c_void_p, [x.data_ptr() for x in xs])
+    fa, fp = _ptr_array(_DP, [f.ctypes.data_as(_DP) for f in fres])
+    st = hh_solve_batch(ctx.handle, nm, mp, (C.c_int * nm)(*nr), ip, bp, xp, C.byref(o), ints(out["iters"]),
+                        ints(out["converged"]), fp, ints(out["mg_cycles"]), ints(out["cnn_iters"]))
+    check(st, allow=(HH_OK, HH_NOT_CONVERGED))
+    return [(xs[i], dict(iters=out["iters"][i], converged=out["converged"][i].astype(bool), final_res=fres[i],
+                         status=st, mg_cycles=out["mg_cycles"][i], cnn_iters=out["cnn_iters"][i]))
+            for i in range(nm)]
 
 
 # ---------------------------------------------------------------------------

@@ -41,10 +41,11 @@ def test_defaults_without_gpu():
     hh.hh_model_desc_default(C.byref(d))
     assert (d.abl_width, d.levels, d.nu_pre, d.nu_post) == (16, 3, 1, 1)
     assert d.sl_beta == 0.5 and d.jacobi_w == 0.8 and d.abl_gamma_max == 1.0 and d.coarse_reduce == 1
+    assert d.coarse_iters == 0
     o = hh.hh_solve_opts()
     hh.hh_solve_opts_default(C.byref(o))
     assert (o.restart, o.max_iters, o.warm_mg_iters) == (10, 2000, 3) and o.rtol == 1e-6
-    assert o.fallback == 1 and o.probe_ratio == 0.5
+    assert o.fallback == 1 and o.probe_ratio == 0.5 and o.graph == 1
 
 
 def test_argument_errors_are_reported_without_gpu():
@@ -53,6 +54,10 @@ def test_argument_errors_are_reported_without_gpu():
     st = hh.hh_model_create(None, None, 1, None, None)
     assert st == hh.HH_ERR_ARG
     assert b"null pointer" in hh.hh_last_error()
+    o = hh.hh_solve_opts()
+    hh.hh_solve_opts_default(C.byref(o))
+    assert hh.hh_solve_batch(None, 1, None, None, None, None, None, C.byref(o), None, None, None, None,
+                             None) == hh.HH_ERR_ARG
 
 
 def test_parameter_vector_round_trip_and_size():

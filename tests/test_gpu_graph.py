@@ -118,3 +118,31 @@ def test_graph_two_models_and_split_coarse(hh, ctx):
     eager0 = m0.solve(_dev(b), inst=inst, graph=False)
     _same(eager0, m0.solve(_dev(b), inst=inst, graph=True))
     assert np.array_equal(eager0[1]["converged"], eager[1]["converged"])
+
+
+# ---- several models of different sizes in one interleaved launch sequence ----
+
+def test_batch_of_sizes_equals_separate_solves(hh, ctx):
+    _say("batch of 3 models (64^2 x 2 media, 128^2, 256^2), MG-only and two-phase CNN+MG")
+    net = hh.Net.load(ctx, NET_FILE)
+    specs = [(64, [inputs.grf_slowness(64, 50), inputs.layered_slowness(64, 51)], [0, 1, 1]),
+             (128, [inputs.layered_slowness(128, 52)], None),
+             (256, [inputs.grf_slowness(256, 53)], None)]
+    models, bs, insts = [], [], []
+    for i, (n, ks, inst) in enumerate(specs):
+        m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), inputs.omega_for(n))
+        m.attach_net(net)
+        models.append(m)
+        nr = len(inst) if inst else 2
+        bs.append(_dev(_sources(n, range(100 * i, 100 * i + nr))))
+        insts.append(inst)
+    for precond in (hh.HH_PRECOND_MG, hh.HH_PRECOND_CNN_MG):
+        res = hh.solve_batch(ctx, models, bs, insts, precond=precond)
+        for i, m in enumerate(models):
+            x, info = m.solve(bs[i], inst=insts[i], precond=precond, want_hist=False)
+            xb, ib = res[i]
+            assert torch.equal(x, xb)
+            for key in ("iters", "converged", "final_res", "mg_cycles", "cnn_iters"):
+                assert np.array_equal(info[key], ib[key]), key
+            assert ib["converged"].all()
+            _say(f"  precond {precond} model {i} (n={m.n}): iterations {ib['iters'].tolist()}")
