@@ -353,8 +353,167 @@ __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xi
 
 static size_t implicit_lds_bytes(int M) { return ((size_t)M * (M + 1) + M / 2) * sizeof(float2); }
 
+// ---------------------------------------------------------------------------
+// Implicit layer for transforms too large for LDS (M = 256, 512: coarsest maps
+// of 128^2 and 256^2).  The same transform in three passes through a scratch
+// array W [B][nk][nc][M] in HBM: (1) forward DIF along the nc data rows,
+// (2) per column: forward DIF along the column, the product with Ghat_c,
+// inverse DIT along the column, keeping the nc rows the output needs,
+// (3) inverse DIT along those rows, keeping nc columns.  Forward only.
+// ---------------------------------------------------------------------------
+constexpr int IMPL_RPB = 4;  // rows per workgroup in passes 1 and 3
+constexpr int IMPL_CPB = 8;  // columns per workgroup in pass 2
+
+template <int M>
+__device__ __forceinline__ void impl_twiddles(float2* tw) {
+    for (int t = threadIdx.x; t < M / 2; t += blockDim.x) {
+        float sn, cs;
+        sincospif(-2.0f * (float)t / (float)M, &sn, &cs);
+        tw[t] = make_float2(cs, sn);
+    }
+}
+
+// forward DIF on `cnt` vectors of length M, vector v at s[v * vstride + k * estride]
+template <int M>
+__device__ __forceinline__ void impl_dif(float2* s, int cnt, int vstride, int estride, const float2* tw) {
+    for (int len = M; len >= 2; len >>= 1) {
+        const int half = len >> 1, tws = M / len;
+        for (int t = threadIdx.x; t < cnt * (M / 2); t += blockDim.x) {
+            const int v = t / (M / 2), bf = t - v * (M / 2);
+            const int blk = bf / half, j = bf - blk * half;
+            const int i0 = v * vstride + (blk * len + j) * estride, i1 = i0 + half * estride;
+            const float2 a = s[i0], bb = s[i1];
+            s[i0] = cadd(a, bb);
+            s[i1] = cmul(csub(a, bb), tw[j * tws]);
+        }
+        __syncthreads();
+    }
+}
+
+// inverse DIT (conjugate twiddles, no scaling) on `cnt` vectors of length M
+template <int M>
+__device__ __forceinline__ void impl_dit_inv(float2* s, int cnt, int vstride, int estride, const float2* tw) {
+    for (int len = 2; len <= M; len <<= 1) {
+        const int half = len >> 1, tws = M / len;
+        for (int t = threadIdx.x; t < cnt * (M / 2); t += blockDim.x) {
+            const int v = t / (M / 2), bf = t - v * (M / 2);
+            const int blk = bf / half, j = bf - blk * half;
+            const int i0 = v * vstride + (blk * len + j) * estride, i1 = i0 + half * estride;
+            float2 w = tw[j * tws];
+            w.y = -w.y;
+            const float2 a = s[i0], bb = cmul(s[i1], w);
+            s[i0] = cadd(a, bb);
+            s[i1] = csub(a, bb);
+        }
+        __syncthreads();
+    }
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) k_implicit_rows_fwd(const uint16_t* __restrict__ xin, float2* __restrict__ W,
+                                                           int nc, int nk, const int* __restrict__ active) {
+    __shared__ float2 s[IMPL_RPB * M];
+    __shared__ float2 tw[M / 2];
+    const int c = blockIdx.y, b = blockIdx.z, r0 = blockIdx.x * IMPL_RPB;
+    if (active && !active[b]) return;
+    const int CH = 2 * nk;
+    const int rows = min(IMPL_RPB, nc - r0);
+    impl_twiddles<M>(tw);
+    for (int e = threadIdx.x; e < IMPL_RPB * M; e += blockDim.x) {
+        const int v = e / M, x = e - v * M;
+        float2 val = make_float2(0.f, 0.f);
+        if (v < rows && x < nc) {
+            const uint32_t raw =
+                *reinterpret_cast<const uint32_t*>(xin + (((size_t)b * nc + r0 + v) * nc + x) * CH + 2 * c);
+            val = make_float2(bf2f((uint16_t)(raw & 0xffff)), bf2f((uint16_t)(raw >> 16)));
+        }
+        s[e] = val;
+    }
+    __syncthreads();
+    impl_dif<M>(s, rows, M, 1, tw);
+    float2* Wr = W + (((size_t)b * nk + c) * nc + r0) * M;
+    for (int e = threadIdx.x; e < rows * M; e += blockDim.x) Wr[e] = s[e];
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) k_implicit_cols(float2* __restrict__ W, const float2* __restrict__ Gbr, int nc,
+                                                       int nk, const int* __restrict__ active) {
+    constexpr int P = M + 1;
+    __shared__ float2 s[IMPL_CPB * P];
+    __shared__ float2 tw[M / 2];
+    const int c = blockIdx.y, b = blockIdx.z, k0 = blockIdx.x * IMPL_CPB;
+    if (active && !active[b]) return;
+    impl_twiddles<M>(tw);
+    float2* Wc = W + ((size_t)b * nk + c) * nc * M;
+    // column cl of the tile at s[cl * P + row]; rows >= nc are zero
+    for (int e = threadIdx.x; e < IMPL_CPB * M; e += blockDim.x) {
+        const int row = e / IMPL_CPB, cl = e - row * IMPL_CPB;
+        s[cl * P + row] = row < nc ? Wc[(size_t)row * M + k0 + cl] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    impl_dif<M>(s, IMPL_CPB, P, 1, tw);
+    const float2* G = Gbr + (size_t)c * M * M;
+    for (int e = threadIdx.x; e < IMPL_CPB * M; e += blockDim.x) {
+        const int r = e / IMPL_CPB, cl = e - r * IMPL_CPB;
+        s[cl * P + r] = cmul(s[cl * P + r], G[(size_t)r * M + k0 + cl]);
+    }
+    __syncthreads();
+    impl_dit_inv<M>(s, IMPL_CPB, P, 1, tw);
+    for (int e = threadIdx.x; e < IMPL_CPB * nc; e += blockDim.x) {
+        const int row = e / IMPL_CPB, cl = e - row * IMPL_CPB;
+        Wc[(size_t)row * M + k0 + cl] = s[cl * P + row];
+    }
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) k_implicit_rows_inv(const float2* __restrict__ W, uint16_t* __restrict__ yout,
+                                                           int nc, int nk, const int* __restrict__ active) {
+    __shared__ float2 s[IMPL_RPB * M];
+    __shared__ float2 tw[M / 2];
+    const int c = blockIdx.y, b = blockIdx.z, r0 = blockIdx.x * IMPL_RPB;
+    if (active && !active[b]) return;
+    const int CH = 2 * nk;
+    const int rows = min(IMPL_RPB, nc - r0);
+    impl_twiddles<M>(tw);
+    const float2* Wr = W + (((size_t)b * nk + c) * nc + r0) * M;
+    for (int e = threadIdx.x; e < IMPL_RPB * M; e += blockDim.x) s[e] = e < rows * M ? Wr[e] : make_float2(0.f, 0.f);
+    __syncthreads();
+    impl_dit_inv<M>(s, rows, M, 1, tw);
+    for (int e = threadIdx.x; e < rows * nc; e += blockDim.x) {
+        const int v = e / nc, x = e - v * nc;
+        const float2 val = s[v * M + x];
+        *reinterpret_cast<uint32_t*>(yout + (((size_t)b * nc + r0 + v) * nc + x) * CH + 2 * c) =
+            (uint32_t)f2bf(val.x) | ((uint32_t)f2bf(val.y) << 16);
+    }
+}
+
+template <int M>
+static hh_status launch_implicit_large_t(hipStream_t st, const uint16_t* x, uint16_t* y, const float2* Gbr, int nc,
+                                         int nk, int B, float2* work, const int* active) {
+    const dim3 gr((nc + IMPL_RPB - 1) / IMPL_RPB, nk, B), gc(M / IMPL_CPB, nk, B);
+    hipLaunchKernelGGL(k_implicit_rows_fwd<M>, gr, dim3(256), 0, st, x, work, nc, nk, active);
+    hipLaunchKernelGGL(k_implicit_cols<M>, gc, dim3(256), 0, st, work, Gbr, nc, nk, active);
+    hipLaunchKernelGGL(k_implicit_rows_inv<M>, gr, dim3(256), 0, st, work, y, nc, nk, active);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+// scratch of the large-transform path (0 when the transform fits LDS)
+size_t implicit_work_bytes(int M, int nc, int nk, int B) {
+    return M > 128 ? (size_t)B * nk * nc * M * sizeof(float2) : 0;
+}
+
 hh_status launch_implicit(hipStream_t st, int M, const uint16_t* x, uint16_t* y, const float2* Gbr, int nc, int nk,
-                          int B, bool conjG, const int* active, const uint16_t* mask = nullptr) {
+                          int B, bool conjG, const int* active, const uint16_t* mask = nullptr,
+                          float2* work = nullptr) {
+    if (M == 256 || M == 512) {
+        if (conjG || mask || !work) {
+            set_error("implicit layer: transforms of %d points run forward only (no adjoint, needs scratch)", M);
+            return HH_ERR_ARG;
+        }
+        return M == 256 ? launch_implicit_large_t<256>(st, x, y, Gbr, nc, nk, B, work, active)
+                        : launch_implicit_large_t<512>(st, x, y, Gbr, nc, nk, B, work, active);
+    }
     const size_t lds = implicit_lds_bytes(M);
     dim3 grd(nk, B);
 #define HH_IMP(MM, NTT)                                                                                  \
@@ -375,7 +534,7 @@ hh_status launch_implicit(hipStream_t st, int M, const uint16_t* x, uint16_t* y,
     HH_IMP(64, 512)
     HH_IMP(128, 1024)
 #undef HH_IMP
-    set_error("implicit layer: transform size %d not supported (coarsest map must be at most 64 x 64)", M);
+    set_error("implicit layer: transform size %d not supported (coarsest map must be at most 256 x 256)", M);
     return HH_ERR_ARG;
 }
 
@@ -411,7 +570,7 @@ __global__ void k_green_S(const float* __restrict__ K, double2* __restrict__ S, 
 __global__ void __launch_bounds__(256) k_dft_pass(const double2* __restrict__ in, double2* __restrict__ out, int R,
                                                   int Lin, int Lout, int N, int oin, int oout, int sign,
                                                   double scale, int axis) {
-    __shared__ double2 s_tw[1024];
+    __shared__ double2 s_tw[2048];
     for (int t = threadIdx.x; t < N; t += 256) {
         double sn, cs;
         sincospi(2.0 * sign * (double)t / (double)N, &sn, &cs);
@@ -429,13 +588,14 @@ __global__ void __launch_bounds__(256) k_dft_pass(const double2* __restrict__ in
         k = o / R;
         r = o - k * R;
     }
-    long kk = ((long)(k + oout)) % N;
-    if (kk < 0) kk += N;
+    // N is a power of two: indices mod N by masking; the twiddle index
+    // (i + oin)(k + oout) mod N advances by kk per step
+    const int msk = N - 1;
+    const int kk = (k + oout) & msk;
+    int tix = (int)(((long)(oin & msk) * kk) & msk);
     double re = 0.0, im = 0.0;
-    for (int i = 0; i < Lin; ++i) {
-        long ii = ((long)(i + oin)) % N;
-        if (ii < 0) ii += N;
-        const double2 w = s_tw[(ii * kk) % N];
+    for (int i = 0; i < Lin; ++i, tix = (tix + kk) & msk) {
+        const double2 w = s_tw[tix];
         const double2 v = (axis == 1) ? in[((size_t)b * R + r) * Lin + i] : in[((size_t)b * Lin + i) * R + r];
         re += v.x * w.x - v.y * w.y;
         im += v.x * w.y + v.y * w.x;
@@ -462,8 +622,8 @@ __global__ void k_green_store(const double2* __restrict__ Gh, float2* __restrict
 
 static hh_status dft_pass(hipStream_t st, const double2* in, double2* out, int nb, int R, int Lin, int Lout, int N,
                           int oin, int oout, int sign, double scale, int axis) {
-    if (N > 1024) {
-        set_error("Green's function grid %d too large", N);
+    if (N > 2048 || (N & (N - 1))) {
+        set_error("Green's function grid %d: a power of two up to 2048", N);
         return HH_ERR_ARG;
     }
     dim3 grd((R * Lout + 255) / 256, nb);
@@ -537,6 +697,7 @@ struct NetActs {
     int B = 0, n = 0;
     Buf a[NET_LAYERS];  // output of every layer (BF16 NHWC); a[L_OUT] holds the FP32 (re, im) projection
     Buf imp;            // implicit-layer output
+    Buf impw;           // implicit-layer scratch for transforms larger than LDS
     Buf parts, scales;  // rms partials, in/out scales
     Buf zeros;          // skip map of one slowness model shared by the batch
     hh_status ensure(hh_net* net, int B_, int n_) {
@@ -556,6 +717,8 @@ struct NetActs {
             HH_TRY(a[l].ensure(net->ctx, (size_t)B * m * m * L.cout * esz));
         }
         HH_TRY(imp.ensure(net->ctx, (size_t)B * ncs * ncs * net->ch[3] * sizeof(uint16_t)));
+        if (implicit_work_bytes(2 * ncs, ncs, net->nk, B) > 0)
+            HH_TRY(impw.ensure(net->ctx, implicit_work_bytes(2 * ncs, ncs, net->nk, B)));
         HH_TRY(parts.ensure(net->ctx, (size_t)B * 64 * sizeof(double)));
         HH_TRY(scales.ensure(net->ctx, (size_t)2 * B * sizeof(float)));
         HH_TRY(zeros.ensure(net->ctx, (size_t)B * sizeof(int)));
@@ -721,7 +884,8 @@ hh_status net_forward_core(hh_net* net, int n, double h, NetActs& A, int B, cons
     }
     {
         ProfScope ps(net->ctx, HH_K_NET_OTHER);
-        HH_TRY(launch_implicit(st, 2 * m4, act(L_S4_C2), A.imp.as<uint16_t>(), Gbr, m4, net->nk, B, false, active));
+        HH_TRY(launch_implicit(st, 2 * m4, act(L_S4_C2), A.imp.as<uint16_t>(), Gbr, m4, net->nk, B, false, active,
+                               nullptr, A.impw.as<float2>()));
     }
     {
         ProfScope ps(net->ctx, HH_K_CONV);
@@ -1950,12 +2114,13 @@ hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, in
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint) {
     HH_ARG(net && x_dev && y_dev, "null pointer");
     HH_HIP(hipSetDevice(net->ctx->device));
-    Buf G;
+    Buf G, Wk;
     const int M = 2 * nc;
     HH_TRY(G.ensure(net->ctx, (size_t)net->nk * M * M * sizeof(float2)));
     HH_TRY(green_forward(net, nc, G.as<float2>(), 1e-5));
+    if (implicit_work_bytes(M, nc, net->nk, B) > 0) HH_TRY(Wk.ensure(net->ctx, implicit_work_bytes(M, nc, net->nk, B)));
     HH_TRY(launch_implicit(net->ctx->stream, M, (const uint16_t*)x_dev, (uint16_t*)y_dev, G.as<float2>(), nc, net->nk,
-                           B, adjoint != 0, nullptr));
+                           B, adjoint != 0, nullptr, nullptr, Wk.as<float2>()));
     HH_HIP(hipStreamSynchronize(net->ctx->stream));
     return HH_OK;
 }

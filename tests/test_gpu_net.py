@@ -106,8 +106,11 @@ def test_wgrad_kernel(hh, ctx, ca, cx, mode, Ho):
     assert np.all(np.abs(got - ref) <= 2e-6 * scale + 1e-30), np.abs(got - ref).max() / scale.max()
 
 
-@pytest.mark.parametrize("nc", [8, 16, 32, 64])
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("nc", [8, 16, 32, 64, 128, 256])
 def test_implicit_layer(hh, ctx, nc):
+    # nc = 128, 256 (coarsest maps at 2048^2 and 4096^2): transforms of 256 and
+    # 512 points, larger than LDS, in three passes through HBM; forward only
     _say(f"implicit layer nc={nc}")
     p = inputs.init_net_params(3)
     rng = np.random.default_rng(nc)
@@ -116,10 +119,15 @@ def test_implicit_layer(hh, ctx, nc):
     net = hh.Net(ctx, p)
     B = 2
     x = _bf16_round(rng.standard_normal((B, 64, nc, nc)))
-    Ghat, _ = C.green_hat(K, nc)
-    for adjoint in (False, True):
+    # above nc = 64 the FP64 oracle transforms only two complex channels (its
+    # 2048^2 FFTs of all 32 would take minutes); the GPU computes all of them
+    sel = np.arange(32) if nc <= 64 else np.array([0, 17])
+    rsel = np.stack([2 * sel, 2 * sel + 1], axis=1).ravel()
+    Ghat, _ = C.green_hat(K[sel], nc)
+    for adjoint in ((False, True) if nc <= 64 else (False,)):
         y = net.implicit_test(_nhwc_dev(x), nc, adjoint=adjoint).to(torch.float32).cpu().numpy().transpose(0, 3, 1, 2)
-        z = C.pair(x)
+        y = y[:, rsel]
+        z = C.pair(x)[:, sel]
         if adjoint:
             _, Z = C.implicit_apply(Ghat, z)
             ref = C.unpair(C.implicit_backward(Ghat, Z, z)[0])
