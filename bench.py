@@ -15,6 +15,10 @@ Prints one JSON line.  Options:
   --mg-steps M: timed MG-only solves of the same workload for the comparison (default 1, 0 = skip)
   --no-cpu-baseline: skip the bounded CPU oracle timing
   --copy-mib S: first copy an S MiB buffer once (a plain-copy reference for HBM counters)
+  --workload batch: instead, the batched uneven-size workload (512^2 x 32, 1024^2 x 16,
+      2048^2 x 8 and 4096^2 x 2 slowness models, 4 unit point sources each, 232 RHS) solved
+      in one interleaved launch sequence (hh_solve_batch), MG-only and CNN+MG, iteration
+      cap 2000 (--batch-max-iters); prints its own JSON line
 """
 from __future__ import annotations
 
@@ -132,6 +136,87 @@ def network_flops(n: int) -> float:
     return f
 
 
+# batched uneven-size workload: (n, slowness models), 4 point sources per model;
+# the 4096^2 models use the iterative coarsest-grid solve (10 Jacobi-GMRES steps):
+# their direct elimination would be 1024 sequential block steps per V-cycle
+BATCH_SIZES = ((512, 32), (1024, 16), (2048, 8), (4096, 2))
+BATCH_RHS_PER_MODEL = 4
+
+
+def run_batch(a):
+    import numpy as np
+    import torch
+    from paper_2306_17486_amd import hh, inputs
+
+    def say(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    ctx = hh.Context(0)
+    net = hh.Net.load(ctx, NET_FILE) if os.path.exists(NET_FILE) else None
+    models, bs, insts, setup = [], [], [], {}
+    for si, (n, ninst) in enumerate(BATCH_SIZES):
+        t = time.perf_counter()
+        ks = np.stack([inputs.grf_slowness(n, 1100 + 100 * si + i) if i % 2 == 0 else
+                       inputs.layered_slowness(n, 2100 + 100 * si + i) for i in range(ninst)]).astype(np.float32)
+        coarse_iters = 10 if n >= 4096 else 0
+        m = hh.Model(ctx, torch.from_numpy(ks), inputs.omega_for(n), coarse_iters=coarse_iters)
+        del ks
+        if net is not None:
+            m.attach_net(net)
+        src = [inputs.point_source(n, 3000 + 1000 * si + q) for q in range(ninst * BATCH_RHS_PER_MODEL)]
+        b = torch.from_numpy(np.stack(src)).to("cuda:0", torch.complex64)
+        del src
+        if net is not None:
+            m.net_forward(b[:1])  # encodings and Green's transforms built outside the timing
+        torch.cuda.synchronize()
+        setup[n] = round(time.perf_counter() - t, 2)
+        models.append(m)
+        bs.append(b)
+        insts.append([i for i in range(ninst) for _ in range(BATCH_RHS_PER_MODEL)])
+        say(f"bench batch: {ninst} models at {n}^2 set up in {setup[n]:.1f} s")
+    nrhs = sum(b.shape[0] for b in bs)
+    runs = [("mg", hh.HH_PRECOND_MG)] + ([("cnn_mg", hh.HH_PRECOND_CNN_MG)] if net is not None else [])
+    for label, prec in runs:  # short warm-up: coarse-solve tuning and graph paths at the full counts
+        hh.solve_batch(ctx, models, bs, insts, precond=prec, max_iters=20)
+        torch.cuda.synchronize()
+        say(f"bench batch: {label} warm-up done")
+    out = {}
+    for label, prec in runs:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = hh.solve_batch(ctx, models, bs, insts, precond=prec, max_iters=a.batch_max_iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        per = {}
+        for (n, ninst), (_, info) in zip(BATCH_SIZES, res):
+            it = info["iters"]
+            conv = info["converged"]
+            per[f"{n}x{ninst}"] = {"iterations_mean": round(float(it.mean()), 1), "iterations_max": int(it.max()),
+                                   "converged": f"{int(conv.sum())}/{len(conv)}",
+                                   "max_rel_residual_converged": (float(info["final_res"][conv].max())
+                                                                  if conv.any() else None)}
+        nconv = sum(int(info["converged"].sum()) for _, info in res)
+        out[label] = {"seconds": round(dt, 3), "solves_per_s": round(nrhs / dt, 4), "converged": f"{nconv}/{nrhs}",
+                      "not_converged": nrhs - nconv, "per_size": per}
+        say(f"bench batch: {label} done in {dt:.1f} s, {nconv}/{nrhs} converged")
+    head = out.get("cnn_mg", out["mg"])
+    line = {"metric": "Helmholtz solves/s, batched uneven sizes (512^2 x 32, 1024^2 x 16, 2048^2 x 8, 4096^2 x 2 "
+                      "models, 4 sources each) to rel. residual 1e-6 or the iteration cap",
+            "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": round(1e3 * head["seconds"], 2), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16+c64+f64", "data": "synthetic",
+            "config": {"workload": "batched uneven sizes: 512^2 x 32, 1024^2 x 16, 2048^2 x 8, 4096^2 x 2 slowness "
+                                   "models (GRF seeds 1100+, layered 2100+, alternating), 4 unit point sources each "
+                                   "(232 RHS), omega = 2 pi n / 10, FGMRES(10), iteration cap "
+                                   f"{a.batch_max_iters}; coarsest solve direct up to 2048^2, 10 Jacobi-GMRES steps "
+                                   "at 4096^2", "nrhs": nrhs,
+                       "precond": "cnn_mg" if "cnn_mg" in out else "mg"},
+            "setup_seconds": setup, "runs": out,
+            "cnn_mg_over_mg_only": (round(out["cnn_mg"]["solves_per_s"] / out["mg"]["solves_per_s"], 3)
+                                    if "cnn_mg" in out else None)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,11 +230,16 @@ def main():
     ap.add_argument("--max-iters", type=int, default=10000)
     ap.add_argument("--mg-steps", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--workload", choices=["single", "batch"], default="single")
+    ap.add_argument("--batch-max-iters", type=int, default=2000)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {a.gpus} is not supported "
               f"(the right-hand sides shard across GPUs with no communication, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batch":
+        run_batch(a)
+        return
 
     use_cnn = a.precond == "cnn_mg" or (a.precond == "auto" and os.path.exists(NET_FILE))
     sample = None

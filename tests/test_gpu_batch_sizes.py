@@ -1,0 +1,65 @@
+"""The batched solve over the size classes of the uneven-size workload (512^2 and
+1024^2 with the direct coarsest solve, 2048^2 and 4096^2 with the iterative
+one; one slowness model and one point source each, CNN+MG with the shipped
+network, iteration cap 300): every model's result equals its separate solve,
+and the 512^2 solution is checked against the FP64 oracle's operator and its
+sparse direct solve."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import helmholtz as H
+from paper_2306_17486_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+NET_FILE = os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256_512.bin")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.timeout(400)
+def test_batch_over_the_size_classes():
+    from paper_2306_17486_amd import hh
+    ctx = hh.Context(0)
+    net = hh.Net.load(ctx, NET_FILE)
+    specs = [(512, 0, "grf"), (1024, 0, "layered"), (2048, 10, "grf"), (4096, 10, "layered")]
+    models, bs, ks = [], [], []
+    for i, (n, ci, fam) in enumerate(specs):
+        k = inputs.slowness(n, 4100 + i, fam)
+        m = hh.Model(ctx, torch.from_numpy(k.astype(np.float32)), inputs.omega_for(n), coarse_iters=ci)
+        m.attach_net(net)
+        models.append(m)
+        ks.append(k)
+        bs.append(torch.from_numpy(inputs.point_source(n, 4200 + i)[None]).to("cuda:0", torch.complex64))
+        _say(f"model {n}^2 (coarse_iters {ci}) ready")
+    res = hh.solve_batch(ctx, models, bs, None, precond=hh.HH_PRECOND_CNN_MG, max_iters=300)
+    _say("batch done: iterations", [int(info["iters"][0]) for _, info in res])
+    for i, m in enumerate(models):
+        x, info = m.solve(bs[i], precond=hh.HH_PRECOND_CNN_MG, max_iters=300, want_hist=False)
+        assert torch.equal(x, res[i][0])
+        for key in ("iters", "converged", "final_res", "mg_cycles", "cnn_iters"):
+            assert np.array_equal(info[key], res[i][1][key]), key
+        assert np.isfinite(info["final_res"]).all()
+    # 512^2: converged; FP64 residual with the oracle's operator and the error
+    # against the sparse direct solution (reading C17: at rtol 1e-6 the error is
+    # bounded by the conditioning; the oracle's own FGMRES at the same rtol is the floor)
+    x0, info0 = res[0]
+    assert info0["converged"][0]
+    n = specs[0][0]
+    prob = H.Problem(ks[0], inputs.omega_for(n))
+    b = inputs.point_source(n, 4200)
+    x = x0.cpu().numpy()[0]
+    rel = np.linalg.norm(b - prob.A(x)) / np.linalg.norm(b)
+    xs = H.exact_solve(prob, b)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    _say(f"512^2: FP64 residual {rel:.2e}, error vs direct solve {err:.2e}")
+    assert rel <= 1e-6
+    assert err <= 1e-4
