@@ -75,6 +75,8 @@ struct hh_ctx {
     void* user = nullptr;
     int num_cus = 256;
     hipStream_t cap_stream = nullptr;  // graph capture (the caller's stream may be the null stream)
+    bool concurrent = false;           // several streams of this context run at once (batched solve):
+                                       // no cooperative launches, whose workgroups must all be resident
 };
 
 namespace hh {

@@ -803,6 +803,13 @@ hh_status fgmres_solve(hh_model* md, SolveWork& W, const BatchMap& bm, const flo
 hh_status fgmres_solve_many(int nruns, hh_model* const* md, SolveWork* const* W, const BatchMap* bm,
                             const float2* const* b, double2* const* x, const hh_solve_opts& o, PrecondFn precond_cnn,
                             const hipStream_t* streams) {
+    // several streams at once: no cooperative coarse-solve variants meanwhile
+    struct Concurrent {
+        hh_ctx* c;
+        bool saved;
+        Concurrent(hh_ctx* ctx, bool on) : c(ctx), saved(ctx->concurrent) { c->concurrent = on; }
+        ~Concurrent() { c->concurrent = saved; }
+    } conc(md[0]->ctx, nruns > 1);
     std::vector<std::unique_ptr<FgmresRun>> runs;
     for (int i = 0; i < nruns; ++i) {
         runs.emplace_back(new (std::nothrow) FgmresRun(md[i], *W[i], bm[i], b[i], x[i], o, precond_cnn,

@@ -956,6 +956,146 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
     }
 }
 
+// ---- split form of the reduced solve's chains ------------------------------
+// The same slices, counters and exchange as the split solve above, on the
+// reduced chains: forward y_j = g_j + P_j y_{j -/+ 1} (no product at an end's
+// first row); middle row x_p = g_p + P_p y_{p-1} + R_p y_{p+1}; backward
+// x_j = y_j + R_j x_{j +/- 1}.  Factor slots as in k_cr_fwd / k_cr_bwd.
+template <int R, int RS>
+__global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restrict__ gw, float2* __restrict__ x,
+                                                         float2* __restrict__ ends, const float2* __restrict__ F,
+                                                         const int* __restrict__ inst, const int* __restrict__ slots,
+                                                         int nslots, const int* __restrict__ nslots_dev, int m,
+                                                         const int* __restrict__ active, SplitGeom geo,
+                                                         float2* __restrict__ xch, int* __restrict__ cnt,
+                                                         int* __restrict__ err) {
+    extern __shared__ float2 s_lds[];
+    float2* s_w = s_lds;
+    float2* s_part = s_lds + R * m;
+    int unit, slice;
+    if (!split_decode(geo, unit, slice)) return;
+    const bool top = (unit & 1) == 0;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
+    if (!g.any) return;  // the same for every slice of the unit
+    const int M = crM(m), p = M / 2;
+    const size_t mm = (size_t)m * m;
+    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const int row0 = slice * RS;
+    const int row = row0 + threadIdx.x;
+    const int nsteps = top ? p : (M - 1 - p);
+    float2 qr[CSP_CMAX];
+    for (int s = 0; s < nsteps; ++s) {
+        const int j = top ? s : (M - 1 - s);
+        float2 out[R];
+        if (s > 0) {
+            split_wait(cnt + unit, geo.S * s, err);
+            for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
+                const int q = e / m, i = e - q * m;
+                s_w[e] = g.on[q] ? load_agent(xch_at<R>(xch, unit, (s - 1) & 1, q, m) + i) : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            split_compute<R, RS>(qr, s_w, s_part, m, out);
+        }
+        if (threadIdx.x < RS && row < m) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                float2 y = make_float2(0.f, 0.f);
+                if (g.on[q]) {
+                    y = gw[((size_t)g.rr[q] * M + j) * m + row];
+                    if (s > 0) y = cadd(y, out[q]);
+                    x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + row] = y;
+                    if (s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + row] = y;
+                }
+                xch_at<R>(xch, unit, s & 1, q, m)[row] = y;
+            }
+        }
+        split_arrive(cnt + unit);
+        if (s + 1 < nsteps) split_load_q<RS>(Fi + (size_t)(M + (top ? j + 1 : j - 1)) * mm, m, row0, qr);
+    }
+}
+
+template <int R, int RS>
+__global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restrict__ gw, float2* __restrict__ x,
+                                                         const float2* __restrict__ ends, const float2* __restrict__ F,
+                                                         const int* __restrict__ inst, const int* __restrict__ slots,
+                                                         int nslots, const int* __restrict__ nslots_dev, int m,
+                                                         const int* __restrict__ active, SplitGeom geo,
+                                                         float2* __restrict__ xch, int* __restrict__ cnt,
+                                                         int* __restrict__ err) {
+    extern __shared__ float2 s_lds[];
+    float2* s_w = s_lds;
+    float2* s_part = s_lds + R * m;
+    int unit, slice;
+    if (!split_decode(geo, unit, slice)) return;
+    const bool top = (unit & 1) == 0;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
+    if (!g.any) return;
+    const int M = crM(m), p = M / 2;
+    const size_t mm = (size_t)m * m;
+    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const int row0 = slice * RS;
+    const int row = row0 + threadIdx.x;
+    const int nsteps = top ? p : (M - 1 - p);
+    float2 qr[CSP_CMAX];
+    // middle row (round 0), computed by both ends
+    float2 acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
+    for (int side = 0; side < 2; ++side) {
+        const bool has = side == 0 ? (p >= 1) : (p + 1 <= M - 1);
+        if (!has) continue;
+        split_load_q<RS>(Fi + (size_t)((side == 0 ? M : 2 * M) + p) * mm, m, row0, qr);
+        for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
+            const int q = e / m, i = e - q * m;
+            s_w[e] = g.on[q] ? ends[((size_t)g.rr[q] * 2 + side) * m + i] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        float2 out[R];
+        split_compute<R, RS>(qr, s_w, s_part, m, out);
+        if (threadIdx.x < RS)
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], out[q]);
+    }
+    if (threadIdx.x < RS && row < m) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float2 v = make_float2(0.f, 0.f);
+            if (g.on[q]) {
+                v = cadd(gw[((size_t)g.rr[q] * M + p) * m + row], acc[q]);
+                if (top) x[(size_t)g.rr[q] * mm + (size_t)(2 * p) * m + row] = v;
+            }
+            xch_at<R>(xch, unit, 0, q, m)[row] = v;
+        }
+    }
+    split_arrive(cnt + unit);
+    if (nsteps > 0) split_load_q<RS>(Fi + (size_t)(2 * M + (top ? p - 1 : p + 1)) * mm, m, row0, qr);
+    for (int s = 0; s < nsteps; ++s) {
+        const int j = top ? (p - 1 - s) : (p + 1 + s);
+        split_wait(cnt + unit, geo.S * (s + 1), err);
+        for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
+            const int q = e / m, i = e - q * m;
+            s_w[e] = g.on[q] ? load_agent(xch_at<R>(xch, unit, s & 1, q, m) + i) : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        float2 out[R];
+        split_compute<R, RS>(qr, s_w, s_part, m, out);
+        if (threadIdx.x < RS && row < m) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                float2 v = make_float2(0.f, 0.f);
+                if (g.on[q]) {
+                    const size_t o = (size_t)g.rr[q] * mm + (size_t)(2 * j) * m + row;
+                    v = cadd(x[o], out[q]);
+                    x[o] = v;
+                }
+                xch_at<R>(xch, unit, (s + 1) & 1, q, m)[row] = v;
+            }
+        }
+        split_arrive(cnt + unit);
+        if (s + 1 < nsteps) split_load_q<RS>(Fi + (size_t)(2 * M + (top ? j - 1 : j + 1)) * mm, m, row0, qr);
+    }
+}
+
 __global__ void k_zero_ints(int* __restrict__ p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -1086,8 +1226,8 @@ static hh_status launch_split_t(hh_model* md, const float2* bcs, float2* x, floa
                                    hipFuncAttributeMaxDynamicSharedMemorySize, want));
         attr_devices |= 1u << ctx->device;
     }
-    if ((m + CSP_NT / RS - 1) / (CSP_NT / RS) > CSP_CMAX) {  // column share exceeds the registers
-        *fits = false;
+    if (ctx->concurrent || (m + CSP_NT / RS - 1) / (CSP_NT / RS) > CSP_CMAX) {
+        *fits = false;  // other streams may hold CUs, or the column share exceeds the registers
         return HH_OK;
     }
     SplitGeom geo;
@@ -1146,30 +1286,56 @@ static hh_status launch_split_t(hh_model* md, const float2* bcs, float2* x, floa
 }
 
 // ---- reduced solve (one level of cyclic reduction, then the two-ended chains) ----
-template <int R>
-static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
-                             const int* slots, int nslots, const int* nslots_dev, int m, float c, const int* active,
-                             const CoarseWork& cw) {
+// The row-parallel phases serve CS_RMAX right-hand sides per workgroup whatever
+// the chains use: their blocks are then read CS_RMAX times fewer (slot groups of
+// CS_RMAX never mix models: the grouping order is padded per model to CS_RMAX).
+static hh_status launch_cr_par(hh_model* md, int PH, const float2* bcs, float2* x, const int* inst, const int* slots,
+                               int nslots, const int* nslots_dev, int m, float c, const int* active,
+                               const CoarseWork& cw) {
+    constexpr int RP = CS_RMAX;
     hh_ctx* ctx = md->ctx;
     static unsigned attr_devices = 0;
-    // the row-parallel phases serve CS_RMAX right-hand sides per workgroup
-    // whatever R the chains use: their matrices are then read CS_RMAX times
-    // fewer (slot groups of CS_RMAX never mix models: the grouping order is
-    // padded per model to CS_RMAX)
-    constexpr int RP = CS_RMAX;
-    const size_t lds = coarse_lds_bytes(R, m), ldsp = coarse_lds_bytes(RP, m);
     if (!(attr_devices & (1u << ctx->device))) {
-        size_t most = 0, mostp = 0;
-        for (int mm_ = 4; mm_ <= CS_MAXM; ++mm_) {
-            most = std::max(most, coarse_lds_bytes(R, mm_));
-            mostp = std::max(mostp, coarse_lds_bytes(RP, mm_));
-        }
+        size_t mostp = 0;
+        for (int mm_ = 4; mm_ <= CS_MAXM; ++mm_) mostp = std::max(mostp, coarse_lds_bytes(RP, mm_));
         if (mostp > 65536) {
             const int want = (int)mostp;
             HH_HIP(hipFuncSetAttribute((const void*)k_cr_par<RP, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
             HH_HIP(hipFuncSetAttribute((const void*)k_cr_par<RP, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
             HH_HIP(hipFuncSetAttribute((const void*)k_cr_par<RP, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
         }
+        attr_devices |= 1u << ctx->device;
+    }
+    const size_t ldsp = coarse_lds_bytes(RP, m);
+    const int GP = (nslots + RP - 1) / RP;
+    const int M = (m + 1) / 2, Mo = m / 2;
+    const float2* F = md->coarseQT.as<float2>();
+    hipStream_t st = ctx->stream;
+    const int rows = PH == 2 ? M : Mo;
+    if (rows == 0) return HH_OK;
+    if (PH == 1)
+        hipLaunchKernelGGL((k_cr_par<RP, 1>), dim3(GP, rows), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst,
+                           slots, nslots, nslots_dev, m, c, active);
+    else if (PH == 2)
+        hipLaunchKernelGGL((k_cr_par<RP, 2>), dim3(GP, rows), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst,
+                           slots, nslots, nslots_dev, m, c, active);
+    else
+        hipLaunchKernelGGL((k_cr_par<RP, 3>), dim3(GP, rows), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst,
+                           slots, nslots, nslots_dev, m, c, active);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+template <int R>
+static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
+                             const int* slots, int nslots, const int* nslots_dev, int m, float c, const int* active,
+                             const CoarseWork& cw) {
+    hh_ctx* ctx = md->ctx;
+    static unsigned attr_devices = 0;
+    const size_t lds = coarse_lds_bytes(R, m);
+    if (!(attr_devices & (1u << ctx->device))) {
+        size_t most = 0;
+        for (int mm_ = 4; mm_ <= CS_MAXM; ++mm_) most = std::max(most, coarse_lds_bytes(R, mm_));
         if (most > 65536) {
             const int want = (int)most;
             HH_HIP(hipFuncSetAttribute((const void*)k_cr_fwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
@@ -1177,43 +1343,115 @@ static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2*
         }
         attr_devices |= 1u << ctx->device;
     }
-    const int G = (nslots + R - 1) / R, GP = (nslots + RP - 1) / RP;
-    const int M = (m + 1) / 2, Mo = m / 2;
+    const int G = (nslots + R - 1) / R;
     const float2* F = md->coarseQT.as<float2>();
     hipStream_t st = ctx->stream;
-    if (Mo > 0) {
-        hipLaunchKernelGGL((k_cr_par<RP, 1>), dim3(GP, Mo), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst,
-                           slots, nslots, nslots_dev, m, c, active);
-        HH_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL((k_cr_par<RP, 2>), dim3(GP, M), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst, slots,
-                       nslots, nslots_dev, m, c, active);
-    HH_LAUNCH_CHECK();
+    HH_TRY(launch_cr_par(md, 1, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
+    HH_TRY(launch_cr_par(md, 2, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
     hipLaunchKernelGGL((k_cr_fwd<R>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, x, ends, F, inst, slots, nslots,
                        nslots_dev, m, active);
     HH_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_cr_bwd<R>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, x, ends, F, inst, slots, nslots,
                        nslots_dev, m, active);
     HH_LAUNCH_CHECK();
-    if (Mo > 0) {
-        hipLaunchKernelGGL((k_cr_par<RP, 3>), dim3(GP, Mo), dim3(CS_NT), ldsp, st, bcs, x, cw.tw, cw.gw, F, inst,
-                           slots, nslots, nslots_dev, m, c, active);
-        HH_LAUNCH_CHECK();
+    return launch_cr_par(md, 3, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw);
+}
+
+// the reduced solve with split chains (cooperative; offered when every
+// workgroup can be resident and no other stream of the process may hold CUs)
+template <int R, int RS>
+static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
+                                   const int* slots, int nslots, const int* nslots_dev, int m, float c,
+                                   const int* active, const CoarseWork& cw, bool* fits) {
+    hh_ctx* ctx = md->ctx;
+    *fits = false;
+    if (ctx->concurrent) return HH_OK;
+    static unsigned attr_devices = 0;
+    const size_t lds = split_lds_bytes(R, m);
+    if (split_lds_bytes(R, CS_MAXM) > 65536 && !(attr_devices & (1u << ctx->device))) {
+        const int want = (int)split_lds_bytes(R, CS_MAXM);
+        HH_HIP(hipFuncSetAttribute((const void*)k_cr_split_fwd<R, RS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   want));
+        HH_HIP(hipFuncSetAttribute((const void*)k_cr_split_bwd<R, RS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   want));
+        attr_devices |= 1u << ctx->device;
     }
-    return HH_OK;
+    if ((m + CSP_NT / RS - 1) / (CSP_NT / RS) > CSP_CMAX) return HH_OK;  // column share exceeds the registers
+    SplitGeom geo;
+    geo.G = (nslots + R - 1) / R;
+    geo.S = (m + RS - 1) / RS;
+    geo.units = 2 * geo.G;
+    geo.upx = (geo.units + 7) / 8;
+    const int grid = 8 * geo.upx * geo.S;
+    int per_cu_f = 0, per_cu_b = 0;
+    HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_f, (const void*)k_cr_split_fwd<R, RS>, CSP_NT, lds));
+    HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, (const void*)k_cr_split_bwd<R, RS>, CSP_NT, lds));
+    if ((long long)std::min(per_cu_f, per_cu_b) * ctx->num_cus < grid) return HH_OK;  // not offered
+    HH_TRY(launch_cr_par(md, 1, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
+    HH_TRY(launch_cr_par(md, 2, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
+    hipLaunchKernelGGL(k_zero_ints, dim3((2 * geo.units + 255) / 256), dim3(256), 0, ctx->stream, cw.cnt,
+                       2 * geo.units);
+    HH_LAUNCH_CHECK();
+    const float2* a_gw = cw.gw;
+    float2* a_x = x;
+    float2* a_ends = ends;
+    const float2* a_F = md->coarseQT.as<float2>();
+    const int* a_inst = inst;
+    const int* a_slots = slots;
+    int a_nslots = nslots;
+    const int* a_nsd = nslots_dev;
+    int a_m = m;
+    const int* a_act = active;
+    float2* a_xch = cw.xch;
+    int* a_cnt = cw.cnt;
+    int* a_err = md->coarse_err.as<int>();
+    void* args[] = {&a_gw, &a_x, &a_ends, &a_F, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
+                    &geo,  &a_xch, &a_cnt, &a_err};
+    const hipError_t le = hipLaunchCooperativeKernel((const void*)k_cr_split_fwd<R, RS>, dim3(grid), dim3(CSP_NT),
+                                                     args, (unsigned)lds, ctx->stream);
+    if (le == hipErrorCooperativeLaunchTooLarge) {  // the runtime's residency bound is tighter: not offered
+        (void)hipGetLastError();
+        return HH_OK;  // the phases launched so far are redone by the fallback
+    }
+    if (le != hipSuccess) {
+        set_error("cooperative launch failed: %s", hipGetErrorString(le));
+        return HH_ERR_HIP;
+    }
+    const float2* b_ends = ends;
+    int* b_cnt = cw.cnt + geo.units;
+    void* args_b[] = {&a_gw, &a_x, &b_ends, &a_F, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
+                      &geo,  &a_xch, &b_cnt, &a_err};
+    HH_HIP(hipLaunchCooperativeKernel((const void*)k_cr_split_bwd<R, RS>, dim3(grid), dim3(CSP_NT), args_b,
+                                      (unsigned)lds, ctx->stream));
+    *fits = true;
+    return launch_cr_par(md, 3, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw);
 }
 
 // choice: R (1, 2, 4, 8) = chain with R right-hand sides per workgroup;
 // 100 RS + R = split with RS rows per workgroup (RS = 8, 16, 32);
-// 1000 + R = the reduced solve (models factorised with one level of cyclic reduction)
-// the reduced solve's codes (1001..1008) lie between the split codes with RS = 8
-// (801..808) and those with RS = 16 (1601..1608)
-static inline bool reduced_code(int c) { return c > 1000 && c < 1100; }
+// 1000 + R = the reduced solve (models factorised with one level of cyclic reduction);
+// 10000 + 100 RS + R = the reduced solve with split chains.
+// The reduced chain codes (1001..1008) lie between the split codes with RS = 8
+// (801..808) and those with RS = 16 (1601..1608).
+static inline bool reduced_code(int c) { return (c > 1000 && c < 1100) || c > 10000; }
+static inline bool cooperative_code(int c) { return (c >= 100 && c < 1000) || (c > 1100 && c < 10000) || c > 10000; }
 
 static hh_status launch_coarse_choice(int choice, hh_model* md, const float2* bcs, float2* x, float2* ends,
                                       const int* inst, const int* slots, int nslots, const int* nslots_dev, int m,
                                       int p, float c, const int* active, const CoarseWork& cw, bool* fits) {
     *fits = true;
+    if (choice > 10000) {
+#define HH_CRSPLIT(RS_, R_)                                                                                \
+    if (choice == 10000 + 100 * RS_ + R_)                                                                  \
+        return launch_cr_split_t<R_, RS_>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw, \
+                                          fits);
+        HH_CRSPLIT(8, 1) HH_CRSPLIT(8, 2) HH_CRSPLIT(8, 4) HH_CRSPLIT(8, 8)
+        HH_CRSPLIT(16, 1) HH_CRSPLIT(16, 2) HH_CRSPLIT(16, 4) HH_CRSPLIT(16, 8)
+        HH_CRSPLIT(32, 1) HH_CRSPLIT(32, 2) HH_CRSPLIT(32, 4) HH_CRSPLIT(32, 8)
+#undef HH_CRSPLIT
+        set_error("coarse-solve variant %d", choice);
+        return HH_ERR_ARG;
+    }
     if (reduced_code(choice)) {
         const float cc = c;
         switch (choice - 1000) {
@@ -1243,7 +1481,8 @@ static hh_status launch_coarse_choice(int choice, hh_model* md, const float2* bc
 
 static bool valid_choice(int c) {
     if (c == 1 || c == 2 || c == 4 || c == 8) return true;
-    if (reduced_code(c)) return c == 1001 || c == 1002 || c == 1004 || c == 1008;
+    if (c > 10000) c -= 10000;  // reduced split: the same RS / R pairs as the split
+    else if (reduced_code(c)) return c == 1001 || c == 1002 || c == 1004 || c == 1008;
     const int rs = c / 100, r = c % 100;
     return (rs == 8 || rs == 16 || rs == 32) && (r == 1 || r == 2 || r == 4 || r == 8);
 }
@@ -1281,7 +1520,7 @@ bool coarse_capturable(const hh_model* md, int nrhs, int nact) {
     if (md->d.coarse_iters > 0) return true;
     const int na = nact > 0 ? std::min(nact, nrhs) : nrhs;
     const int c = md->coarse_R_forced > 0 ? md->coarse_R_forced : md->coarse_R[coarse_bucket(std::max(na, 1))];
-    return c > 0 && (c < 100 || reduced_code(c));
+    return c > 0 && !cooperative_code(c);
 }
 
 // Autotuner of the coarse solve: for each bucket of active right-hand sides,
@@ -1306,9 +1545,12 @@ static hh_status coarse_pick(hh_model* md, int nact, const float2* bcs, float2* 
         if (R > 1 && R / 2 >= nact) break;  // groups larger than the work
         if (md->cr1) {
             cand.push_back(1000 + R);
+            if (!md->ctx->concurrent)
+                for (int rs = 8; rs <= 32; rs *= 2) cand.push_back(10000 + 100 * rs + R);
         } else {
             cand.push_back(R);
-            for (int rs = 8; rs <= 32; rs *= 2) cand.push_back(100 * rs + R);
+            if (!md->ctx->concurrent)
+                for (int rs = 8; rs <= 32; rs *= 2) cand.push_back(100 * rs + R);
         }
     }
     hh_ctx* ctx = md->ctx;

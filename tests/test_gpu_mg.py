@@ -174,9 +174,10 @@ def test_bad_arguments_raise(hh, ctx):
 
 # (reduced factorisation?, variant): plain factorisation -- chain R, split 100 RS + R
 # (RS rows of each Schur inverse per workgroup); reduced factorisation (one level of
-# cyclic reduction) -- 1000 + R
+# cyclic reduction) -- 1000 + R, and with split chains 10000 + 100 RS + R
 COARSE_VARIANTS = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 801), (0, 808), (0, 1601), (0, 1604), (0, 3202), (0, 3208),
-                   (1, 1001), (1, 1002), (1, 1004), (1, 1008)]
+                   (1, 1001), (1, 1002), (1, 1004), (1, 1008), (1, 10801), (1, 10808), (1, 11602), (1, 13201),
+                   (1, 13208)]
 
 
 @pytest.mark.parametrize("reduce,R", COARSE_VARIANTS)
@@ -220,7 +221,7 @@ def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
     b = np.stack([inputs.point_source(n, 60 + i) for i in range(6)] + [inputs.random_complex((n, n), 66)])
     its_o = [H.solve_mg(prob, b[r])[1] for r in range(7)]
     bad = []
-    for reduce, R in ((1, 0), (1, 1001), (1, 1008), (0, 0), (0, 1), (0, 802), (0, 1608)):
+    for reduce, R in ((1, 0), (1, 1001), (1, 1008), (1, 11601), (0, 0), (0, 1), (0, 802), (0, 1608)):
         m = hh.Model(ctx, torch.from_numpy(k), om, coarse_reduce=reduce)
         m.set_coarse_group(R)
         xd, info = m.solve(_dev(b))
@@ -237,7 +238,8 @@ def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
             if not (info["converged"][r] and res <= 1e-6 and abs(int(info["iters"][r]) - its_o[r]) <= 2):
                 bad.append((reduce, R, r))
         if R == 0:
-            assert m.coarse_group(7) in ((1001, 1002, 1004, 1008) if reduce else
+            split = tuple(100 * rs + r for rs in (8, 16, 32) for r in (1, 2, 4, 8))
+            assert m.coarse_group(7) in ((1001, 1002, 1004, 1008) + tuple(10000 + c for c in split) if reduce else
                                          (1, 2, 4, 8, 801, 802, 804, 808, 1601, 1602, 1604, 1608, 3201, 3202, 3204,
                                           3208))
     assert not bad, bad
