@@ -273,6 +273,12 @@ hh_status hh_model_attach_net(hh_model* m, hh_net* net);
  * P the bilinear prolongation; r, e c64 [nrhs][n][n]. */
 hh_status hh_net_forward(hh_model* m, int nrhs, const int* inst_host, const void* r_dev, void* e_dev);
 
+/* One application of the CNN+MG preconditioner (Sec. 4.1), as the solve
+ * applies it: z = V(v; x0) with x0 = hh_net_forward(v), the network's output
+ * interpolated inside the V-cycle's first kernels.  v, z c64 [nrhs][n][n];
+ * inst_host as in hh_solve.  Synchronises the stream. */
+hh_status hh_apply_cnn_precond(hh_model* m, int nrhs, const int* inst_host, const void* v_dev, void* z_dev);
+
 /* Method-generated training pairs (Sec. 4.3, eq. 20) for nb samples on the
  * model's (training) operator, sample b using slowness model b (or the single
  * model when the model holds one):

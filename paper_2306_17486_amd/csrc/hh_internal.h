@@ -168,6 +168,12 @@ __host__ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
     float den = b.x * b.x + b.y * b.y;
     return make_float2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
 }
+// a / b with one hardware reciprocal of |b|^2 (about 1 ulp; the relaxation
+// sweeps divide by the shifted diagonal at every point and sweep)
+__device__ __forceinline__ float2 cdiv_rcp(float2 a, float2 b) {
+    const float inv = __builtin_amdgcn_rcpf(b.x * b.x + b.y * b.y);
+    return make_float2((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);
+}
 __host__ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -248,9 +254,12 @@ size_t vcycle_workspace_bytes(const hh_model* m, int nrhs, bool with_x0);
 hh_status launch_vcycle(hh_model* m, int nrhs, const BatchMap& bm, const float2* b, const double* sig,
                         int sig_stride, const float2* x0, float2* z, void* work, const int* active);
 // Same with explicit element strides between consecutive right-hand sides.
+// x0h (with x0s): the initial guess given as the network's half-resolution
+// output [nrhs][n/2][n/2] and its per-RHS scale, x0 = x0s P(x0h) (x0 unused).
 hh_status launch_vcycle_strided(hh_model* m, int nrhs, const BatchMap& bm, const float2* b, size_t bstride,
                                 const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
-                                size_t zstride, void* work, const int* active);
+                                size_t zstride, void* work, const int* active, const float2* x0h = nullptr,
+                                const float* x0s = nullptr);
 // RHS per workgroup of the coarsest solve (the grouping unit of BatchMap::order)
 int coarse_group();
 bool coarse_choice_valid(const hh_model* md, int c);

@@ -33,7 +33,7 @@ static_assert(sizeof(KState) % 8 == 0, "KState must be a whole number of doubles
 // Device workspace of one solve (grown on demand, reused across calls).
 struct SolveWork {
     int nrhs = 0, restart = 0, hist_len = 0, n = 0, npart = 0;
-    Buf V, Z, state, flags, parts, inst, hist, vwork, x0net;
+    Buf V, Z, state, flags, parts, inst, hist, vwork;
     const int* caps_dev = nullptr;  // optional per-RHS iteration caps (training-data generation)
     hh_status prepare(hh_ctx* c, hh_model* md, int nrhs, int restart, int hist_len, bool cnn);
 };

@@ -491,7 +491,6 @@ hh_status SolveWork::prepare(hh_ctx* c, hh_model* md, int nrhs_, int restart_, i
     HH_TRY(inst.ensure(c, (size_t)nrhs * sizeof(int)));
     HH_TRY(hist.ensure(c, (size_t)nrhs * hist_len * sizeof(double) + 8));
     HH_TRY(vwork.ensure(c, vcycle_workspace_bytes(md, nrhs, cnn) + 256));
-    if (cnn) HH_TRY(x0net.ensure(c, (size_t)nrhs * nn * sizeof(float2)));
     return HH_OK;
 }
 

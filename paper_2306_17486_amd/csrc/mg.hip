@@ -51,21 +51,62 @@ __global__ void __launch_bounds__(256) k_apply_op(const float2* __restrict__ x, 
 }
 
 // ---------------------------------------------------------------------------
+// Initial guess of the CNN+MG V-cycle straight from the network's
+// half-resolution output o ([n/2][n/2] (re, im)): x0 = s P(o) at fine (i, j),
+// with P the multigrid prolongation of eq. 8 (coarse I on fine 2I; odd fine
+// indices average their two coarse neighbours) and s the network's output
+// scale.  Reading o instead of a stored fine x0 saves the full-resolution
+// vector's write and reads.
+// ---------------------------------------------------------------------------
+// The blocks stage the coarse tile they need, s_o[I - cy0][J - cx0] (zero
+// outside the grid), and interpolate from LDS; i, j >= 0 are fine indices
+// inside the grid.
+template <int CPW>
+__device__ __forceinline__ void stage_half(float2* s_o, int rows, const float2* __restrict__ ob, int m, int cy0,
+                                           int cx0) {
+    for (int e = threadIdx.x; e < rows * CPW; e += blockDim.x) {
+        const int py = e / CPW, px = e - py * CPW;
+        const int I = cy0 + py, J = cx0 + px;
+        s_o[e] = (I >= 0 && I < m && J >= 0 && J < m) ? ob[(size_t)I * m + J] : make_float2(0.f, 0.f);
+    }
+}
+
+template <int CPW>
+__device__ __forceinline__ float2 x0_from_half(const float2* s_o, int cy0, int cx0, int i, int j, float s) {
+    auto at = [&](int I, int J) -> float2 { return s_o[(I - cy0) * CPW + (J - cx0)]; };
+    const int I = i >> 1, J = j >> 1;
+    float2 v;
+    if (!(i & 1) && !(j & 1)) {
+        v = at(I, J);
+    } else if (!(i & 1)) {
+        v = cscale(cadd(at(I, J), at(I, J + 1)), 0.5f);
+    } else if (!(j & 1)) {
+        v = cscale(cadd(at(I, J), at(I + 1, J)), 0.5f);
+    } else {
+        v = cscale(cadd(cadd(at(I, J), at(I, J + 1)), cadd(at(I + 1, J), at(I + 1, J + 1))), 0.25f);
+    }
+    return cscale(v, s);
+}
+
+// ---------------------------------------------------------------------------
 // V-cycle down kernel on one level.
 // Block = 256 threads computes a TCY x TCX tile of the coarse right-hand side.
-// HAS_X0: the level has a nonzero initial guess x0 (level 0 of the CNN+MG
-// preconditioner); the relaxed x1 is then also written out for the up kernel.
+// X0M: the level's initial guess -- 0 none; 1 a fine x0 (the relaxed x1 is then
+// also written out for the up kernel); 2 the network's half-resolution output
+// (x0h, scale x0s per RHS), from which the up kernel recomputes x1 itself.
 // ---------------------------------------------------------------------------
 constexpr int DN_TCX = 32, DN_TCY = 8;
 
-template <bool HAS_X0>
+template <int X0M>
 __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, size_t bstride,
                                                  const double* __restrict__ sig, int sig_stride,
                                                  const float2* __restrict__ x0, size_t x0stride,
                                                  float2* __restrict__ x1out, float2* __restrict__ bc,
                                                  const float2* __restrict__ coef, const int* __restrict__ inst,
                                                  int n, float inv_h2, float beta, float wj,
-                                                 const int* __restrict__ active) {
+                                                 const int* __restrict__ active, const float2* __restrict__ x0h,
+                                                 const float* __restrict__ x0s) {
+    constexpr bool HAS_X0 = X0M != 0;
     constexpr int HALO = HAS_X0 ? 3 : 2;
     constexpr int PH = 2 * DN_TCY + 2 * HALO - 1;  // fine rows 2I0-HALO .. 2I0+2TCY+HALO-2
     constexpr int PW = 2 * DN_TCX + 2 * HALO - 1;
@@ -73,6 +114,9 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
     __shared__ float2 s_x[PH][PW];   // x1 (relaxed)
     __shared__ float2 s_m[PH][PW];   // shifted mass
     __shared__ float2 s_x0[HAS_X0 ? PH : 1][HAS_X0 ? PW : 1];
+    // mode 2: the coarse tile of the network output under the fine patch
+    constexpr int OPH = X0M == 2 ? PH / 2 + 2 : 1, OPW = X0M == 2 ? PW / 2 + 2 : 1;
+    __shared__ float2 s_o[OPH * OPW];
 
     const int r = blockIdx.z;
     if (active && !active[r]) return;
@@ -86,6 +130,11 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
     const float s = sig ? (float)sig[(size_t)r * sig_stride] : 1.0f;
     const float dgv = 4.f * inv_h2;
     const float2 zero = make_float2(0.f, 0.f);
+    const int ocy0 = fy0 >> 1, ocx0 = fx0 >> 1;  // floor halves (fy0, fx0 may be negative)
+    if (X0M == 2) {
+        stage_half<OPW>(s_o, OPH, x0h + (size_t)r * (n >> 1) * (n >> 1), n >> 1, ocy0, ocx0);
+        __syncthreads();
+    }
 
     // stage b (scaled), the shifted mass and x0
     for (int e = tid; e < PH * PW; e += 256) {
@@ -97,12 +146,14 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
         float2 mv = in ? mass_of(cf[o], beta) : zero;
         s_b[py][px] = bv;
         s_m[py][px] = mv;
-        if (HAS_X0) {
+        if (X0M == 1) {
             s_x0[py][px] = in ? x0[r * x0stride + o] : zero;
+        } else if (X0M == 2) {
+            s_x0[py][px] = in ? x0_from_half<OPW>(s_o, ocy0, ocx0, gi, gj, x0s[r]) : zero;
         } else {
             // x1 = w b / diag with diag = 4/h^2 - mass
             float2 d = make_float2(dgv - mv.x, -mv.y);
-            s_x[py][px] = in ? cscale(cdiv(bv, d), wj) : zero;
+            s_x[py][px] = in ? cscale(cdiv_rcp(bv, d), wj) : zero;
         }
     }
     __syncthreads();
@@ -119,13 +170,13 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
                 float2 mv = s_m[py][px];
                 float2 Ax = csub(make_float2((4.f * c.x - nb.x) * inv_h2, (4.f * c.y - nb.y) * inv_h2), cmul(mv, c));
                 float2 d = make_float2(dgv - mv.x, -mv.y);
-                v = cadd(c, cscale(cdiv(csub(s_b[py][px], Ax), d), wj));
+                v = cadd(c, cscale(cdiv_rcp(csub(s_b[py][px], Ax), d), wj));
             }
             s_x[py][px] = v;
         }
         __syncthreads();
         // write x1 on the fine cells this tile owns: rows 2I0 .. 2I0+2TCY-1
-        for (int e = tid; e < 4 * DN_TCY * DN_TCX; e += 256) {
+        for (int e = tid; X0M == 1 && e < 4 * DN_TCY * DN_TCX; e += 256) {
             int ly = e / (2 * DN_TCX), lx = e - ly * (2 * DN_TCX);
             int gi = 2 * I0 + ly, gj = 2 * J0 + lx;
             if (gi < n && gj < n) x1out[r * nn + (size_t)gi * n + gj] = s_x[ly + HALO][lx + HALO];
@@ -167,25 +218,32 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
 
 // ---------------------------------------------------------------------------
 // V-cycle up kernel on one level: prolong + correct + post-relaxation.
-// Block = 256 threads computes a TY x TX fine tile.  HAS_X1: the relaxed x1 was
-// stored by the down kernel; otherwise x1 = w b / diag is recomputed.
+// Block = 256 threads computes a TY x TX fine tile.  X1M: where the relaxed x1
+// comes from -- 0 recomputed as w b / diag (zero initial guess); 1 stored by
+// the down kernel; 2 recomputed from the network's half-resolution output,
+// x1 = x0 + w (b - A_SL x0) / diag with x0 = s P(o), the down kernel's formula.
 // ---------------------------------------------------------------------------
 constexpr int UP_TX = 64, UP_TY = 16;
 
-template <bool HAS_X1>
+template <int X1M>
 __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, size_t bstride,
                                                const double* __restrict__ sig, int sig_stride,
                                                const float2* __restrict__ x1, const float2* __restrict__ ec,
                                                float2* __restrict__ z, size_t zstride,
                                                const float2* __restrict__ coef, const int* __restrict__ inst,
                                                int n, float inv_h2, float beta, float wj,
-                                               const int* __restrict__ active) {
+                                               const int* __restrict__ active, const float2* __restrict__ x0h,
+                                               const float* __restrict__ x0s) {
     constexpr int PH = UP_TY + 2, PW = UP_TX + 2;
     constexpr int CH = UP_TY / 2 + 2, CW = UP_TX / 2 + 2;
+    constexpr int XH = X1M == 2 ? PH + 2 : 1, XW = X1M == 2 ? PW + 2 : 1;
     __shared__ float2 s_b[PH][PW];
     __shared__ float2 s_x[PH][PW];
     __shared__ float2 s_m[PH][PW];
     __shared__ float2 s_e[CH][CW];
+    __shared__ float2 s_x0[XH][XW];  // x0 on fine rows y0-2 .. y0+TY+1 (mode 2)
+    constexpr int OPH = X1M == 2 ? XH / 2 + 2 : 1, OPW = X1M == 2 ? XW / 2 + 2 : 1;
+    __shared__ float2 s_o[OPH * OPW];  // the network output's coarse tile under s_x0
 
     const int r = blockIdx.z;
     if (active && !active[r]) return;
@@ -206,6 +264,18 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
         int I = cy0 + py, J = cx0 + px;
         s_e[py][px] = (I >= 0 && I < nc && J >= 0 && J < nc) ? er[(size_t)I * nc + J] : zero;
     }
+    const int ocy0 = (y0 - 2) >> 1, ocx0 = (x0 - 2) >> 1;
+    if (X1M == 2) {
+        stage_half<OPW>(s_o, OPH, x0h + (size_t)r * nc * nc, nc, ocy0, ocx0);
+        __syncthreads();
+        const float os = x0s[r];
+        for (int e = tid; e < XH * XW; e += 256) {
+            int py = e / XW, px = e - py * XW;
+            int gi = y0 - 2 + py, gj = x0 - 2 + px;
+            s_x0[py][px] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? x0_from_half<OPW>(s_o, ocy0, ocx0, gi, gj, os)
+                                                                   : zero;
+        }
+    }
     __syncthreads();
     for (int e = tid; e < PH * PW; e += 256) {
         int py = e / PW, px = e - py * PW;
@@ -216,10 +286,17 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
             size_t o = (size_t)gi * n + gj;
             bv = cscale(br[o], s);
             mv = mass_of(cf[o], beta);
-            if (HAS_X1) {
+            if (X1M == 1) {
                 xv = x1[r * nn + o];
+            } else if (X1M == 2) {
+                const int qy = py + 1, qx = px + 1;  // s_x0 starts one row / column further out
+                float2 c = s_x0[qy][qx];
+                float2 nb = cadd(cadd(s_x0[qy - 1][qx], s_x0[qy + 1][qx]), cadd(s_x0[qy][qx - 1], s_x0[qy][qx + 1]));
+                float2 Ax = csub(make_float2((4.f * c.x - nb.x) * inv_h2, (4.f * c.y - nb.y) * inv_h2), cmul(mv, c));
+                float2 d = make_float2(dg - mv.x, -mv.y);
+                xv = cadd(c, cscale(cdiv_rcp(csub(bv, Ax), d), wj));
             } else {
-                xv = cscale(cdiv(bv, make_float2(dg - mv.x, -mv.y)), wj);
+                xv = cscale(cdiv_rcp(bv, make_float2(dg - mv.x, -mv.y)), wj);
             }
             // bilinear prolongation: even index -> coarse i/2; odd -> mean of (i-1)/2, (i+1)/2
             int ly = (gi >> 1) - cy0, lx = (gj >> 1) - cx0;
@@ -250,7 +327,7 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
         float2 mv = s_m[py][px];
         float2 Ax = csub(make_float2((4.f * c.x - nb.x) * inv_h2, (4.f * c.y - nb.y) * inv_h2), cmul(mv, c));
         float2 d = make_float2(dg - mv.x, -mv.y);
-        z[r * zstride + (size_t)gi * n + gj] = cadd(c, cscale(cdiv(csub(s_b[py][px], Ax), d), wj));
+        z[r * zstride + (size_t)gi * n + gj] = cadd(c, cscale(cdiv_rcp(csub(s_b[py][px], Ax), d), wj));
     }
 }
 
@@ -1590,7 +1667,8 @@ static hh_status coarse_pick(hh_model* md, int nact, const float2* bcs, float2* 
 
 hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, const float2* b, size_t bstride,
                                 const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
-                                size_t zstride, void* work, const int* active) {
+                                size_t zstride, void* work, const int* active, const float2* x0h,
+                                const float* x0s) {
     const int* inst_dev = bm.inst;
     hipStream_t st = md->ctx->stream;
     const float beta = (float)md->d.sl_beta, wj = (float)md->d.jacobi_w;
@@ -1620,13 +1698,18 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         const double* sg = (l == 0) ? sig : nullptr;
         const float ih2 = (float)(1.0 / (lv.h * lv.h));
         ProfScope ps(md->ctx, l == 0 ? HH_K_VC_DOWN : HH_K_VC_MID);
-        if (l == 0 && x0) {
-            hipLaunchKernelGGL(k_vc_down<true>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x0, x0stride, x1,
-                               bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active);
+        if (l == 0 && x0h) {
+            hipLaunchKernelGGL(k_vc_down<2>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr, (size_t)0,
+                               nullptr, bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, x0h,
+                               x0s);
+        } else if (l == 0 && x0) {
+            hipLaunchKernelGGL(k_vc_down<1>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x0, x0stride, x1,
+                               bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, nullptr,
+                               nullptr);
         } else {
-            hipLaunchKernelGGL(k_vc_down<false>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
+            hipLaunchKernelGGL(k_vc_down<0>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
                                (size_t)0, nullptr, bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta,
-                               wj, active);
+                               wj, active, nullptr, nullptr);
         }
         HH_LAUNCH_CHECK();
     }
@@ -1678,12 +1761,16 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         const size_t os = (l == 0) ? zstride : nl;
         const float ih2 = (float)(1.0 / (lv.h * lv.h));
         ProfScope ps(md->ctx, l == 0 ? HH_K_VC_UP : HH_K_VC_MID);
-        if (l == 0 && x0) {
-            hipLaunchKernelGGL(k_vc_up<true>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x1, el[l + 1], out,
-                               os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active);
+        if (l == 0 && x0h) {
+            hipLaunchKernelGGL(k_vc_up<2>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr, el[l + 1], out,
+                               os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, x0h, x0s);
+        } else if (l == 0 && x0) {
+            hipLaunchKernelGGL(k_vc_up<1>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x1, el[l + 1], out,
+                               os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, nullptr, nullptr);
         } else {
-            hipLaunchKernelGGL(k_vc_up<false>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
-                               el[l + 1], out, os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active);
+            hipLaunchKernelGGL(k_vc_up<0>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
+                               el[l + 1], out, os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active,
+                               nullptr, nullptr);
         }
         HH_LAUNCH_CHECK();
     }

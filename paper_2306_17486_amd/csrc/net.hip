@@ -154,6 +154,8 @@ __global__ void __launch_bounds__(256) k_conv_in(const float2* __restrict__ src,
 #pragma unroll
         for (int c0 = 0; c0 < COUT; c0 += 8) {
             uint16_t o[8];
+            uint16_t sv[8];  // the skip's 8 channels in one 16-byte load
+            if (sk) *reinterpret_cast<uint4*>(sv) = *reinterpret_cast<const uint4*>(sk + c0);
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int co = c0 + u;
@@ -161,7 +163,7 @@ __global__ void __launch_bounds__(256) k_conv_in(const float2* __restrict__ src,
 #pragma unroll
                 for (int t = 0; t < 9; ++t)
                     acc += s_w[(co * 2 + 0) * 9 + t] * in[0][t] + s_w[(co * 2 + 1) * 9 + t] * in[1][t];
-                if (sk) acc += bf2f(sk[co]);
+                if (sk) acc += bf2f(sv[u]);
                 o[u] = f2bf(acc);
             }
             *reinterpret_cast<uint4*>(y + po + c0) = *reinterpret_cast<uint4*>(o);
@@ -938,10 +940,11 @@ hh_status net_precond(void* user, hh_model* md, SolveWork& W, const BatchMap& bm
     }
     HH_TRY(net_prepare_model(md));
     NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
-    float2* x0 = W.x0net.as<float2>();
-    HH_TRY(net_forward_batch(net, md, nc->acts, W.nrhs, bm, v, vstride, sig, sig_stride, x0, act));
-    const size_t nn = (size_t)md->lev[0].n * md->lev[0].n;
-    return launch_vcycle_strided(md, W.nrhs, bm, v, vstride, sig, sig_stride, x0, nn, z, zstride, W.vwork.ptr, act);
+    // the V-cycle reads the network's half-resolution output and interpolates
+    // the initial guess itself: no fine x0 is stored
+    HH_TRY(net_forward_batch(net, md, nc->acts, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, act));
+    return launch_vcycle_strided(md, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, 0, z, zstride, W.vwork.ptr, act,
+                                 nc->acts.a[L_OUT].as<float2>(), nc->acts.scales.as<float>() + W.nrhs);
 }
 
 // ===========================================================================
@@ -2068,6 +2071,26 @@ hh_status hh_net_forward(hh_model* m, int nrhs, const int* inst_host, const void
                              nullptr));
     HH_HIP(hipStreamSynchronize(m->ctx->stream));
     return HH_OK;
+}
+
+hh_status hh_apply_cnn_precond(hh_model* m, int nrhs, const int* inst_host, const void* v_dev, void* z_dev) {
+    HH_ARG(m && v_dev && z_dev, "null pointer");
+    HH_ARG(m->net, "no network attached to the model");
+    HH_ARG(nrhs >= 1, "nrhs >= 1");
+    HH_HIP(hipSetDevice(m->ctx->device));
+    HH_TRY(net_prepare_model(m));
+    Buf ib, work;
+    BatchMap bm;
+    HH_TRY(upload_inst_map(m, ib, nrhs, inst_host, &bm));
+    HH_TRY(work.ensure(m->ctx, vcycle_workspace_bytes(m, nrhs, false) + 256));
+    NetCache* nc = reinterpret_cast<NetCache*>(m->netcache);
+    const size_t nn = (size_t)m->lev[0].n * m->lev[0].n;
+    const float2* v = (const float2*)v_dev;
+    HH_TRY(net_forward_batch(m->net, m, nc->acts, nrhs, bm, v, nn, nullptr, 0, nullptr, nullptr));
+    HH_TRY(launch_vcycle_strided(m, nrhs, bm, v, nn, nullptr, 0, nullptr, 0, (float2*)z_dev, nn, work.ptr, nullptr,
+                                 nc->acts.a[L_OUT].as<float2>(), nc->acts.scales.as<float>() + nrhs));
+    HH_HIP(hipStreamSynchronize(m->ctx->stream));
+    return coarse_check_err(m);
 }
 
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,

@@ -96,6 +96,7 @@ hh_net_save = _sig("hh_net_save", _I, _P, C.c_char_p)
 hh_net_load = _sig("hh_net_load", _I, _P, C.c_char_p, C.POINTER(_P))
 hh_model_attach_net = _sig("hh_model_attach_net", _I, _P, _P)
 hh_net_forward = _sig("hh_net_forward", _I, _P, _I, _IP, _P, _P)
+hh_apply_cnn_precond = _sig("hh_apply_cnn_precond", _I, _P, _I, _IP, _P, _P)
 hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P)
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
 hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
@@ -261,6 +262,13 @@ class Model:
         check(hh_gen_training_pairs(self.ctx.handle, self.handle, x.shape[0], _ptr(x), _int_array(kiters), _ptr(e),
                                     _ptr(r)))
         return e, r
+
+    def apply_cnn_precond(self, v: torch.Tensor, inst=None) -> torch.Tensor:
+        """z = V(v; Net(v)), one application of the CNN+MG preconditioner."""
+        v = v.to(torch.complex64).contiguous()
+        z = torch.empty_like(v)
+        check(hh_apply_cnn_precond(self.handle, v.shape[0], _int_array(inst), _ptr(v), _ptr(z)))
+        return z
 
     def net_forward(self, r: torch.Tensor, inst=None) -> torch.Tensor:
         r = r.to(torch.complex64).contiguous()

@@ -6,6 +6,7 @@
 * the whole encoder-solver network (random initial weights) below and above
   n = 512, where the coarsest pair changes stride;
 * the two-phase CNN+MG FGMRES solve against the oracle's."""
+import os
 import sys
 
 import numpy as np
@@ -16,6 +17,8 @@ from oracle import cnn as C
 from oracle import helmholtz as H
 from oracle import solver as S
 from paper_2306_17486_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 
@@ -210,3 +213,25 @@ def test_cnn_mg_judge_falls_back_for_a_bad_network(hh, ctx):
         assert st["probes"] >= 1 and info["mg_cycles"][r] == st["mg_cycles"] >= 1
         assert abs(int(info["iters"][r]) - its_o) <= max(3, int(0.25 * its_o))
         assert info["iters"][r] <= its_mg + 2 * 10
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,ninst", [(128, 1), (128, 2), (1024, 1)])
+def test_cnn_precond_equals_forward_then_vcycle(hh, ctx, n, ninst):
+    # the solve's CNN+MG preconditioner interpolates the network's half-resolution
+    # output inside the V-cycle's first kernels and recomputes the relaxed guess
+    # in the up kernel; it must give what the network forward (fine x0) followed
+    # by the V-cycle with that initial guess gives
+    _say(f"cnn+mg preconditioner, fused vs forward + vcycle, n={n} media={ninst}")
+    net = hh.Net.load(ctx, os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256_512.bin"))
+    ks = np.stack([inputs.slowness(n, 60 + i, "grf" if i % 2 == 0 else "layered") for i in range(ninst)])
+    m = hh.Model(ctx, torch.from_numpy(ks), inputs.omega_for(n))
+    m.attach_net(net)
+    v = torch.from_numpy(inputs.random_complex((3, n, n), 61)).to("cuda:0", torch.complex64)
+    inst = [i % ninst for i in range(3)] if ninst > 1 else None
+    z1 = m.apply_cnn_precond(v, inst=inst)
+    e = m.net_forward(v, inst=inst)
+    z2 = m.apply_vcycle(v, e, inst=inst)
+    d = (z1 - z2).abs().max().item() / z2.abs().max().item()
+    _say(f"  max difference {d:.2e} (bitwise equal: {torch.equal(z1, z2)})")
+    assert d <= 1e-6
