@@ -47,10 +47,15 @@ struct ConvCfg {
     static constexpr int TC = 32;                                               // output tile columns
     static constexpr int TR = (MODE == CM_S2) ? (CIN >= 64 ? 2 : 4) : (CIN >= 64 ? 4 : 8);  // output tile rows
     static constexpr int NT = COUT / 16;                                        // channel tiles
-    static constexpr int WPT = 4 / NT;                                          // waves per channel tile
+    // channel tiles per wave: a pixel fragment read from LDS feeds CT MFMAs;
+    // the weights' VGPRs (CT * NCH * 4) stay within 72 so that two or more
+    // waves per SIMD remain resident
+    static constexpr int NCH = (9 * CIN + 31) / 32;                             // k chunks
+    static constexpr int CT = (NT >= 2 && 2 * NCH <= 18) ? 2 : 1;
+    static constexpr int NG = NT / CT;                                          // channel groups
+    static constexpr int WPT = 4 / NG;                                          // waves per channel group
     static constexpr int PB = TR * (TC / 16);                                   // 16-pixel blocks per tile
     static constexpr int PBW = PB / WPT;                                        // pixel blocks per wave
-    static constexpr int NCH = (9 * CIN + 31) / 32;                             // k chunks
     static constexpr int PH = (MODE == CM_S2) ? 2 * TR + 1 : TR + 2;            // staged input rows
     static constexpr int PW = (MODE == CM_S2) ? 2 * TC + 1 : TC + 2;            // staged input cols
     static constexpr int CP = CIN + 8;                                          // LDS channel pitch (bf16)
@@ -58,29 +63,32 @@ struct ConvCfg {
 };
 
 template <int CIN, int COUT, int MODE>
-__global__ void __launch_bounds__(256) k_conv_mfma(ConvArgs a) {
+__global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 waves per SIMD resident
     using C = ConvCfg<CIN, COUT, MODE>;
     __shared__ __attribute__((aligned(16))) uint16_t s_in[C::PH * C::PW * C::CP];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int ct = wave % C::NT;           // channel tile of this wave
-    const int wsub = wave / C::NT;         // which share of the pixel blocks
+    const int cg = wave % C::NG;           // channel group of this wave: tiles cg*CT .. cg*CT+CT-1
+    const int wsub = wave / C::NG;         // which share of the pixel blocks
     const int lp = lane & 15, lg = lane >> 4;
 
     // this wave's weights stay in VGPRs for all tiles
-    bf16x8 wreg[C::NCH];
+    bf16x8 wreg[C::CT][C::NCH];
     {
         const uint4* wp4 = reinterpret_cast<const uint4*>(a.wp);
 #pragma unroll
-        for (int ch = 0; ch < C::NCH; ++ch) {
-            uint4 v = wp4[((size_t)ch * COUT + ct * 16 + lp) * 4 + lg];
-            wreg[ch] = *reinterpret_cast<bf16x8*>(&v);
-        }
-    }
-    float bias4[4] = {0.f, 0.f, 0.f, 0.f};
-    if (a.bias)
+        for (int c = 0; c < C::CT; ++c)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bias4[i] = a.bias[ct * 16 + 4 * lg + i];
+            for (int ch = 0; ch < C::NCH; ++ch) {
+                uint4 v = wp4[((size_t)ch * COUT + (cg * C::CT + c) * 16 + lp) * 4 + lg];
+                wreg[c][ch] = *reinterpret_cast<bf16x8*>(&v);
+            }
+    }
+    float bias4[C::CT][4];
+#pragma unroll
+    for (int c = 0; c < C::CT; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias4[c][i] = a.bias ? a.bias[(cg * C::CT + c) * 16 + 4 * lg + i] : 0.f;
 
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         const int b = tile / (a.tiles_x * a.tiles_y);
@@ -117,9 +125,11 @@ __global__ void __launch_bounds__(256) k_conv_mfma(ConvArgs a) {
         }
         __syncthreads();
         // ---- MFMA over the k chunks ----
-        f32x4 acc[C::PBW];
+        f32x4 acc[C::PBW][C::CT];
 #pragma unroll
-        for (int q = 0; q < C::PBW; ++q) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < C::PBW; ++q)
+#pragma unroll
+            for (int c = 0; c < C::CT; ++c) acc[q][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ch = 0; ch < C::NCH; ++ch) {
             const int k0 = ch * 32 + 8 * lg;
@@ -145,14 +155,18 @@ __global__ void __launch_bounds__(256) k_conv_mfma(ConvArgs a) {
                     uint4 z = make_uint4(0, 0, 0, 0);
                     bv = *reinterpret_cast<bf16x8*>(&z);
                 }
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[ch], bv, acc[q], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < C::CT; ++c)
+                    acc[q][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[c][ch], bv, acc[q][c], 0, 0, 0);
             }
         }
-        // ---- epilogue: lane owns channels ct*16 + 4 lg .. +3 of one pixel per block ----
-        const int co = ct * 16 + 4 * lg;
+        // ---- epilogue: lane owns channels (cg*CT + c)*16 + 4 lg .. +3 of one pixel per block ----
         const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
 #pragma unroll
-        for (int q = 0; q < C::PBW; ++q) {
+        for (int q = 0; q < C::PBW; ++q)
+#pragma unroll
+        for (int c = 0; c < C::CT; ++c) {
+            const int co = (cg * C::CT + c) * 16 + 4 * lg;
             const int pbk = wsub * C::PBW + q;
             const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
             const int oy = y0 + ry, ox = x0 + rx;
@@ -160,7 +174,7 @@ __global__ void __launch_bounds__(256) k_conv_mfma(ConvArgs a) {
             const size_t po = (((size_t)b * a.Hout + oy) * a.Wout + ox) * COUT + co;
             float v[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = acc[q][i] + bias4[i];
+            for (int i = 0; i < 4; ++i) v[i] = acc[q][c][i] + bias4[c][i];
             if (a.skip) {
                 const size_t so = (((size_t)sb * a.Hout + oy) * a.Wout + ox) * COUT + co;
                 uint2 s2 = *reinterpret_cast<const uint2*>(a.skip + so);
