@@ -96,6 +96,7 @@ __device__ __forceinline__ float2 x0_from_half(const float2* s_o, int cy0, int c
 // (x0h, scale x0s per RHS), from which the up kernel recomputes x1 itself.
 // ---------------------------------------------------------------------------
 constexpr int DN_TCX = 32, DN_TCY = 8;
+constexpr int DN_TCY2 = 4;  // with the network's guess: four arrays in LDS, half-height tiles
 
 template <int X0M>
 __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, size_t bstride,
@@ -108,7 +109,8 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
                                                  const float* __restrict__ x0s) {
     constexpr bool HAS_X0 = X0M != 0;
     constexpr int HALO = HAS_X0 ? 3 : 2;
-    constexpr int PH = 2 * DN_TCY + 2 * HALO - 1;  // fine rows 2I0-HALO .. 2I0+2TCY+HALO-2
+    constexpr int TCY = X0M == 2 ? DN_TCY2 : DN_TCY;  // coarse rows per tile
+    constexpr int PH = 2 * TCY + 2 * HALO - 1;  // fine rows 2I0-HALO .. 2I0+2TCY+HALO-2
     constexpr int PW = 2 * DN_TCX + 2 * HALO - 1;
     __shared__ float2 s_b[PH][PW];   // b, later r
     __shared__ float2 s_x[PH][PW];   // x1 (relaxed)
@@ -122,7 +124,7 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
     if (active && !active[r]) return;
     const int tid = threadIdx.x;
     const int nc = n >> 1;
-    const int I0 = blockIdx.y * DN_TCY, J0 = blockIdx.x * DN_TCX;
+    const int I0 = blockIdx.y * TCY, J0 = blockIdx.x * DN_TCX;
     const int fy0 = 2 * I0 - HALO, fx0 = 2 * J0 - HALO;
     const size_t nn = (size_t)n * n;
     const float2* br = b + r * bstride;
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
         }
         __syncthreads();
         // write x1 on the fine cells this tile owns: rows 2I0 .. 2I0+2TCY-1
-        for (int e = tid; X0M == 1 && e < 4 * DN_TCY * DN_TCX; e += 256) {
+        for (int e = tid; X0M == 1 && e < 4 * TCY * DN_TCX; e += 256) {
             int ly = e / (2 * DN_TCX), lx = e - ly * (2 * DN_TCX);
             int gi = 2 * I0 + ly, gj = 2 * J0 + lx;
             if (gi < n && gj < n) x1out[r * nn + (size_t)gi * n + gj] = s_x[ly + HALO][lx + HALO];
@@ -203,7 +205,7 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
     {
         int cy = tid / DN_TCX, cx = tid - cy * DN_TCX;
         int I = I0 + cy, J = J0 + cx;
-        if (I < nc && J < nc) {
+        if (cy < TCY && I < nc && J < nc) {
             int py = 2 * cy + HALO - 1, px = 2 * cx + HALO - 1;
             const float w1[3] = {0.25f, 0.5f, 0.25f};
             float2 acc = zero;
@@ -224,6 +226,7 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
 // x1 = x0 + w (b - A_SL x0) / diag with x0 = s P(o), the down kernel's formula.
 // ---------------------------------------------------------------------------
 constexpr int UP_TX = 64, UP_TY = 16;
+constexpr int UP_TY2 = 8;  // with the network's guess: the x0 patch in LDS too, half-height tiles
 
 template <int X1M>
 __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, size_t bstride,
@@ -234,8 +237,9 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
                                                int n, float inv_h2, float beta, float wj,
                                                const int* __restrict__ active, const float2* __restrict__ x0h,
                                                const float* __restrict__ x0s) {
-    constexpr int PH = UP_TY + 2, PW = UP_TX + 2;
-    constexpr int CH = UP_TY / 2 + 2, CW = UP_TX / 2 + 2;
+    constexpr int TY = X1M == 2 ? UP_TY2 : UP_TY;  // fine rows per tile
+    constexpr int PH = TY + 2, PW = UP_TX + 2;
+    constexpr int CH = TY / 2 + 2, CW = UP_TX / 2 + 2;
     constexpr int XH = X1M == 2 ? PH + 2 : 1, XW = X1M == 2 ? PW + 2 : 1;
     __shared__ float2 s_b[PH][PW];
     __shared__ float2 s_x[PH][PW];
@@ -249,7 +253,7 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
     if (active && !active[r]) return;
     const int tid = threadIdx.x;
     const int nc = n >> 1;
-    const int y0 = blockIdx.y * UP_TY, x0 = blockIdx.x * UP_TX;
+    const int y0 = blockIdx.y * TY, x0 = blockIdx.x * UP_TX;
     const int cy0 = y0 / 2 - 1, cx0 = x0 / 2 - 1;
     const size_t nn = (size_t)n * n;
     const float2* br = b + r * bstride;
@@ -317,7 +321,7 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
         s_x[py][px] = xv;
     }
     __syncthreads();
-    for (int e = tid; e < UP_TY * UP_TX; e += 256) {
+    for (int e = tid; e < TY * UP_TX; e += 256) {
         int ly = e / UP_TX, lx = e - ly * UP_TX;
         int gi = y0 + ly, gj = x0 + lx;
         if (gi >= n || gj >= n) continue;
@@ -1692,7 +1696,8 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         const Level& lv = md->lev[l];
         const int nc = lv.n / 2;
         const size_t nl = (size_t)lv.n * lv.n;
-        dim3 grd((nc + DN_TCX - 1) / DN_TCX, (nc + DN_TCY - 1) / DN_TCY, nrhs);
+        const int tcy = (l == 0 && x0h) ? DN_TCY2 : DN_TCY;
+        dim3 grd((nc + DN_TCX - 1) / DN_TCX, (nc + tcy - 1) / tcy, nrhs);
         const float2* bin = (l == 0) ? b : bl[l];
         const size_t bs = (l == 0) ? bstride : nl;
         const double* sg = (l == 0) ? sig : nullptr;
@@ -1753,7 +1758,8 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
     for (int l = L - 2; l >= 0; --l) {
         const Level& lv = md->lev[l];
         const size_t nl = (size_t)lv.n * lv.n;
-        dim3 grd((lv.n + UP_TX - 1) / UP_TX, (lv.n + UP_TY - 1) / UP_TY, nrhs);
+        const int ty = (l == 0 && x0h) ? UP_TY2 : UP_TY;
+        dim3 grd((lv.n + UP_TX - 1) / UP_TX, (lv.n + ty - 1) / ty, nrhs);
         const float2* bin = (l == 0) ? b : bl[l];
         const size_t bs = (l == 0) ? bstride : nl;
         const double* sg = (l == 0) ? sig : nullptr;
