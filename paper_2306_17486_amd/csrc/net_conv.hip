@@ -90,17 +90,21 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
 #pragma unroll
         for (int i = 0; i < 4; ++i) bias4[c][i] = a.bias ? a.bias[(cg * C::CT + c) * 16 + 4 * lg + i] : 0.f;
 
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int b = tile / (a.tiles_x * a.tiles_y);
-        const int rem = tile - b * a.tiles_x * a.tiles_y;
+    // ---- the input patch of a tile (zero padding / zero interleaving), gathered
+    // into registers: element e = pixel * VEC + v of the PH x PW patch ----
+    constexpr int VEC = CIN / 8;
+    constexpr int NE = C::PH * C::PW * VEC;
+    constexpr int NPF = (NE + 255) / 256;  // gathers per thread
+    constexpr bool PF = NPF <= 5;           // small patches: the next tile's gather overlaps this tile's MFMAs
+    const int per_b = a.tiles_x * a.tiles_y;
+    // element e of a tile's patch (zero outside the input)
+    auto elem = [&](int tile, int e) -> uint4 {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
         const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
-        if (a.active && !a.active[b]) continue;  // uniform over the block
         const int y0 = ty * C::TR, x0 = tx * C::TC;
-        __syncthreads();  // previous tile's readers are done with s_in
-        // ---- stage the input patch (zero padding / zero interleaving) ----
         const uint16_t* xb = a.x + (size_t)b * a.Hin * a.Win * CIN;
-        constexpr int VEC = CIN / 8;
-        for (int e = tid; e < C::PH * C::PW * VEC; e += 256) {
+        {
             const int v = e % VEC, pix = e / VEC;
             const int py = pix / C::PW, px = pix - py * C::PW;
             int iy, ix;
@@ -120,10 +124,46 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
                 ix = ux >> 1;
             }
             uint4 val = make_uint4(0, 0, 0, 0);
-            if (in) val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
-            *reinterpret_cast<uint4*>(&s_in[(py * C::PW + px) * C::CP + 8 * v]) = val;
+            if (e < NE && in) val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
+            return val;
+        }
+    };
+    auto to_lds = [&](int e, uint4 val) {
+        const int v = e % VEC, pix = e / VEC;
+        *reinterpret_cast<uint4*>(&s_in[pix * C::CP + 8 * v]) = val;
+    };
+    constexpr int NPR = PF ? NPF : 1;  // registers held between tiles
+    auto gather = [&](int tile, uint4 (&g)[NPR]) {
+#pragma unroll
+        for (int j = 0; j < NPR; ++j) g[j] = elem(tile, tid + j * 256);
+    };
+    auto put = [&](const uint4 (&g)[NPR]) {
+#pragma unroll
+        for (int j = 0; j < NPR; ++j)
+            if (tid + j * 256 < NE) to_lds(tid + j * 256, g[j]);
+    };
+    // the next tile of this workgroup whose batch entry is active (uniform)
+    auto next_active = [&](int t) {
+        while (t < a.ntiles && a.active && !a.active[t / per_b]) t += gridDim.x;
+        return t;
+    };
+    uint4 pf[NPR];
+    int tile = next_active(blockIdx.x);
+    if (PF && tile < a.ntiles) gather(tile, pf);
+    while (tile < a.ntiles) {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const int y0 = ty * C::TR, x0 = tx * C::TC;
+        const int nxt = next_active(tile + gridDim.x);
+        __syncthreads();  // previous tile's readers are done with s_in
+        if (PF) {
+            put(pf);
+        } else {
+            for (int e = tid; e < NE; e += 256) to_lds(e, elem(tile, e));
         }
         __syncthreads();
+        if (PF && nxt < a.ntiles) gather(nxt, pf);  // in flight during the MFMAs below
         // ---- MFMA over the k chunks ----
         f32x4 acc[C::PBW][C::CT];
 #pragma unroll
@@ -199,6 +239,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
             *reinterpret_cast<uint2*>(a.y + po) = o2;
             if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
         }
+        tile = nxt;
     }
 }
 
