@@ -294,24 +294,76 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) bias4[i] = a.bias[ct * 16 + 4 * lg + i];
 
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int b = tile / (a.tiles_x * a.tiles_y);
-        const int rem = tile - b * a.tiles_x * a.tiles_y;
+    // the input patch, gathered into registers one active tile ahead while
+    // the current tile's MFMAs run; not for 64 -> 64, whose extra registers
+    // would cost a resident wave per SIMD
+    constexpr int VEC = CIN / 8;
+    constexpr int NE = C::PH * C::PW * VEC;
+    constexpr bool PF = !(CIN == 64 && COUT == 64);
+    constexpr int NPF = PF ? (NE + 255) / 256 : 1;
+    static_assert(!PF || NPF <= 5, "patch gathered into registers");
+    const int per_b = a.tiles_x * a.tiles_y;
+    auto gather = [&](int tile, uint4 (&g)[NPF]) {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
         const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
-        if (a.active && !a.active[b]) continue;  // uniform over the block
         const int y0 = ty * C::TR, x0 = tx * C::TC;
-        __syncthreads();
         const uint16_t* xb = a.x + (size_t)b * a.Hin * a.Win * CIN;
-        constexpr int VEC = CIN / 8;
-        for (int e = tid; e < C::PH * C::PW * VEC; e += 256) {
+#pragma unroll
+        for (int j = 0; j < NPF; ++j) {
+            const int e = tid + j * 256;
+            const int v = e % VEC, pix = e / VEC;
+            const int py = pix / C::PW, px = pix - py * C::PW;
+            const int iy = (y0 >> 1) + py, ix = (x0 >> 1) + px;
+            g[j] = make_uint4(0, 0, 0, 0);
+            if (e < NE && iy < a.Hin && ix < a.Win)
+                g[j] = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
+        }
+    };
+    // without prefetch: gather and store element by element
+    auto stage_now = [&](int tile) {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const int y0 = ty * C::TR, x0 = tx * C::TC;
+        const uint16_t* xb = a.x + (size_t)b * a.Hin * a.Win * CIN;
+        for (int e = tid; e < NE; e += 256) {
             const int v = e % VEC, pix = e / VEC;
             const int py = pix / C::PW, px = pix - py * C::PW;
             const int iy = (y0 >> 1) + py, ix = (x0 >> 1) + px;
             uint4 val = make_uint4(0, 0, 0, 0);
             if (iy < a.Hin && ix < a.Win) val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
-            *reinterpret_cast<uint4*>(&s_in[(py * C::PW + px) * C::CP + 8 * v]) = val;
+            *reinterpret_cast<uint4*>(&s_in[pix * C::CP + 8 * v]) = val;
+        }
+    };
+    auto next_active = [&](int t) {
+        while (t < a.ntiles && a.active && !a.active[t / per_b]) t += gridDim.x;
+        return t;
+    };
+    uint4 pf[NPF];
+    int tile = next_active(blockIdx.x);
+    if (PF && tile < a.ntiles) gather(tile, pf);
+    while (tile < a.ntiles) {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const int y0 = ty * C::TR, x0 = tx * C::TC;
+        const int nxt = next_active(tile + gridDim.x);
+        __syncthreads();  // previous tile's readers are done with s_in
+        if (PF) {
+#pragma unroll
+            for (int j = 0; j < NPF; ++j) {
+                const int e = tid + j * 256;
+                if (e < NE) {
+                    const int v = e % VEC, pix = e / VEC;
+                    *reinterpret_cast<uint4*>(&s_in[pix * C::CP + 8 * v]) = pf[j];
+                }
+            }
+        } else {
+            stage_now(tile);
         }
         __syncthreads();
+        if (PF && nxt < a.ntiles) gather(nxt, pf);
         f32x4 acc[C::PBW];
 #pragma unroll
         for (int q = 0; q < C::PBW; ++q) {
@@ -374,6 +426,7 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
             *reinterpret_cast<uint2*>(a.y + po) = o2;
             if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
         }
+        tile = nxt;
     }
 }
 
