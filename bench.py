@@ -136,6 +136,35 @@ def network_flops(n: int) -> float:
     return f
 
 
+def network_ceiling(n: int) -> float:
+    """Fraction of the BF16 MFMA peak the network's convolutions can reach at
+    most: every layer at the roofline min(peak, intensity x HBM bandwidth),
+    with BF16 activations read once and written once (a transposed layer also
+    reads its skip input)."""
+    from paper_2306_17486_amd import inputs
+    nc = n // 16 if n >= 512 else n // 8
+    out_size = {"s1": n // 2, "s2": n // 4, "s3": n // 8, "s4": nc, "u3": n // 8, "u2": n // 4, "u1": n // 2}
+    tin_size = {"u3": nc, "u2": n // 8, "u1": n // 4}
+    in_size = {"s1": n // 2, "s2": n // 2, "s3": n // 4, "s4": n // 8}
+    flops = t_roof = 0.0
+    for name, kind, cin, cout in inputs.net_layers((16, 32, 64, 64)):
+        lvl = name.split("_")[0]
+        if lvl.startswith("enc") or name in ("s1_d", "out"):
+            continue
+        po = out_size[lvl] ** 2
+        if kind in ("t", "t4"):
+            pi = tin_size[lvl] ** 2
+            f = 2.0 * 9 * cin * cout * pi
+            byt = 2.0 * (pi * cin + 2 * po * cout)
+        else:
+            pi = (in_size[lvl] ** 2) if kind in ("d", "d4") else po
+            f = 2.0 * 9 * cin * cout * po
+            byt = 2.0 * (pi * cin + po * cout)
+        flops += f
+        t_roof += max(f / (BF16_PEAK_TFLOPS * 1e12), byt / (HBM_PEAK_GBS * 1e9))
+    return flops / t_roof / (BF16_PEAK_TFLOPS * 1e12)
+
+
 # batched uneven-size workload: (n, slowness models), 4 point sources per model;
 # the 4096^2 models use the iterative coarsest-grid solve (10 Jacobi-GMRES steps):
 # their direct elimination would be 1024 sequential block steps per V-cycle
@@ -322,9 +351,10 @@ def main():
     per_pt = {"op_dots": 16 + 8 * mean_jp1, "ortho": 16 + 8 * mean_jp1, "vc_down": 8 + 2, "vc_up": 8 + 2 + 8,
               # coarse solve per RHS: b read twice, y written and read, x written (5 coarse vectors)
               "vc_coarse": 5 * 8 * mc * mc / N}
-    # with the network's initial guess the down kernel also reads x0 and writes the
-    # relaxed x1, and the up kernel reads x1 back
-    per_pt_cnn = dict(per_pt, vc_down=8 + 8 + 8 + 2, vc_up=8 + 2 + 8 + 8)
+    # with the network's initial guess both kernels also read the network's
+    # half-resolution output (8 B per coarse point = 2 B per fine point) and
+    # interpolate it; the relaxed guess is recomputed, not stored
+    per_pt_cnn = dict(per_pt, vc_down=8 + 2 + 2, vc_up=8 + 2 + 2 + 8)
     cnn_rhs_iters = float(res["cnn_iters"].sum())
     # per launch, shared by all RHS: coefficients; for the coarse solve the m
     # Schur inverses (m^2 complex each) streamed once per sweep
@@ -347,11 +377,16 @@ def main():
         elif kname == "conv" and cnn_apps > 0:
             total = cnn_apps * net_flops
             ach = total / (ms / 1e3) / 1e12
+            ceil = network_ceiling(n)
             classes[kname] = {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
                               "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
                               "avg_launch_us": round(ms / cnt * 1e3, 1),
                               "algorithmic_flops_per_launch": int(total / cnt), "ms": round(ms, 2),
-                              "launches": cnt}
+                              "launches": cnt,
+                              # the layers' arithmetic intensities cap the class below the MFMA
+                              # peak: the fraction attainable at the HBM roof, and ours of it
+                              "intensity_ceiling_frac": round(ceil, 4),
+                              "frac_of_ceiling": round(ach / BF16_PEAK_TFLOPS / ceil, 4)}
         else:
             classes[kname] = {"ms": round(ms, 2), "launches": cnt}
     ranked = sorted(((v[0], kname) for kname, v in prof.items()), reverse=True)

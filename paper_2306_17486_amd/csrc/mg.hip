@@ -133,19 +133,36 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
     const float dgv = 4.f * inv_h2;
     const float2 zero = make_float2(0.f, 0.f);
     const int ocy0 = fy0 >> 1, ocx0 = fx0 >> 1;  // floor halves (fy0, fx0 may be negative)
+    // this thread's b and coefficients of the patch, loaded first so that they
+    // are in flight together with the network-output tile below
+    constexpr int NPT = (PH * PW + 255) / 256;
+    float2 rb[NPT], rc[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int e = tid + j * 256;
+        const int py = e / PW, px = e - py * PW;
+        const int gi = fy0 + py, gj = fx0 + px;
+        const bool in = e < PH * PW && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        const size_t o = (size_t)gi * n + gj;
+        rb[j] = in ? br[o] : zero;
+        rc[j] = in ? cf[o] : zero;
+    }
     if (X0M == 2) {
         stage_half<OPW>(s_o, OPH, x0h + (size_t)r * (n >> 1) * (n >> 1), n >> 1, ocy0, ocx0);
         __syncthreads();
     }
 
     // stage b (scaled), the shifted mass and x0
-    for (int e = tid; e < PH * PW; e += 256) {
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int e = tid + j * 256;
+        if (e >= PH * PW) break;
         int py = e / PW, px = e - py * PW;
         int gi = fy0 + py, gj = fx0 + px;
         bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
         size_t o = (size_t)gi * n + gj;
-        float2 bv = in ? cscale(br[o], s) : zero;
-        float2 mv = in ? mass_of(cf[o], beta) : zero;
+        float2 bv = in ? cscale(rb[j], s) : zero;
+        float2 mv = in ? mass_of(rc[j], beta) : zero;
         s_b[py][px] = bv;
         s_m[py][px] = mv;
         if (X0M == 1) {
@@ -263,6 +280,20 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
     const float dg = 4.f * inv_h2;
     const float2 zero = make_float2(0.f, 0.f);
 
+    // this thread's b and coefficients of the patch, loaded first so that they
+    // are in flight together with the coarse tiles below
+    constexpr int NPT = (PH * PW + 255) / 256;
+    float2 rb[NPT], rc[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int e = tid + j * 256;
+        const int py = e / PW, px = e - py * PW;
+        const int gi = y0 - 1 + py, gj = x0 - 1 + px;
+        const bool in = e < PH * PW && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        const size_t o = (size_t)gi * n + gj;
+        rb[j] = in ? br[o] : zero;
+        rc[j] = in ? cf[o] : zero;
+    }
     for (int e = tid; e < CH * CW; e += 256) {
         int py = e / CW, px = e - py * CW;
         int I = cy0 + py, J = cx0 + px;
@@ -281,15 +312,18 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
         }
     }
     __syncthreads();
-    for (int e = tid; e < PH * PW; e += 256) {
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int e = tid + j * 256;
+        if (e >= PH * PW) break;
         int py = e / PW, px = e - py * PW;
         int gi = y0 - 1 + py, gj = x0 - 1 + px;
         bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
         float2 bv = zero, mv = zero, xv = zero;
         if (in) {
             size_t o = (size_t)gi * n + gj;
-            bv = cscale(br[o], s);
-            mv = mass_of(cf[o], beta);
+            bv = cscale(rb[j], s);
+            mv = mass_of(rc[j], beta);
             if (X1M == 1) {
                 xv = x1[r * nn + o];
             } else if (X1M == 2) {
