@@ -71,21 +71,20 @@ __device__ __forceinline__ void stage_half(float2* s_o, int rows, const float2* 
     }
 }
 
+// Bilinear value at fine parity (ey, ex) from coarse (ly, lx) of an LDS tile
+// with row pitch w, without branches: the second row / column is ly + ey /
+// lx + ex, so with a zero parity the pair averages a value with itself, which
+// is exact -- the result equals the case-by-case formula (P of eq. 8) bit for bit.
+__device__ __forceinline__ float2 interp_half(const float2* t, int w, int ly, int lx, int ey, int ex) {
+    const float2 a = t[ly * w + lx], b = t[ly * w + lx + ex];
+    const float2 c = t[(ly + ey) * w + lx], d = t[(ly + ey) * w + lx + ex];
+    const float2 h0 = cscale(cadd(a, b), 0.5f), h1 = cscale(cadd(c, d), 0.5f);
+    return cscale(cadd(h0, h1), 0.5f);
+}
+
 template <int CPW>
 __device__ __forceinline__ float2 x0_from_half(const float2* s_o, int cy0, int cx0, int i, int j, float s) {
-    auto at = [&](int I, int J) -> float2 { return s_o[(I - cy0) * CPW + (J - cx0)]; };
-    const int I = i >> 1, J = j >> 1;
-    float2 v;
-    if (!(i & 1) && !(j & 1)) {
-        v = at(I, J);
-    } else if (!(i & 1)) {
-        v = cscale(cadd(at(I, J), at(I, J + 1)), 0.5f);
-    } else if (!(j & 1)) {
-        v = cscale(cadd(at(I, J), at(I + 1, J)), 0.5f);
-    } else {
-        v = cscale(cadd(cadd(at(I, J), at(I, J + 1)), cadd(at(I + 1, J), at(I + 1, J + 1))), 0.25f);
-    }
-    return cscale(v, s);
+    return cscale(interp_half(s_o, CPW, (i >> 1) - cy0, (j >> 1) - cx0, i & 1, j & 1), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,18 +336,8 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
                 xv = cscale(cdiv_rcp(bv, make_float2(dg - mv.x, -mv.y)), wj);
             }
             // bilinear prolongation: even index -> coarse i/2; odd -> mean of (i-1)/2, (i+1)/2
-            int ly = (gi >> 1) - cy0, lx = (gj >> 1) - cx0;
-            float2 pe;
-            if (!(gi & 1) && !(gj & 1)) {
-                pe = s_e[ly][lx];
-            } else if (!(gi & 1)) {
-                pe = cscale(cadd(s_e[ly][lx], s_e[ly][lx + 1]), 0.5f);
-            } else if (!(gj & 1)) {
-                pe = cscale(cadd(s_e[ly][lx], s_e[ly + 1][lx]), 0.5f);
-            } else {
-                pe = cscale(cadd(cadd(s_e[ly][lx], s_e[ly][lx + 1]), cadd(s_e[ly + 1][lx], s_e[ly + 1][lx + 1])), 0.25f);
-            }
-            xv = cadd(xv, pe);
+            const int ly = (gi >> 1) - cy0, lx = (gj >> 1) - cx0;
+            xv = cadd(xv, interp_half(&s_e[0][0], CW, ly, lx, gi & 1, gj & 1));
         }
         s_b[py][px] = bv;
         s_m[py][px] = mv;
