@@ -247,6 +247,88 @@ __global__ void __launch_bounds__(256) k_prolong_x0(const float2* __restrict__ o
 // decimation in time inverse (all columns, then the kept rows) returns natural
 // order.  No permutation pass is needed.
 // ---------------------------------------------------------------------------
+// Radix-2 butterfly sweeps over nvec vectors of length M in LDS (vector v at
+// s[v * vstride + k * estride]), two consecutive stages fused per pass where
+// two remain (radix 2^2: the same butterflies in the same order, held in
+// registers between the stages, so one barrier instead of two).  Threads run
+// along the elements (rows) or across the vectors (vfast: columns, so that
+// neighbouring threads touch neighbouring LDS words).
+template <int M, int NT>
+__device__ __forceinline__ void impl_dif_sweep(float2* s, int nvec, int vstride, int estride, bool vfast,
+                                               const float2* tw) {
+    int len = M;
+    while (len >= 4) {  // stages len and len / 2 together
+        const int half = len >> 1, q = len >> 2, twa = M / len, twb = 2 * twa;
+        for (int t = threadIdx.x; t < nvec * (M / 4); t += NT) {
+            const int v = vfast ? t % nvec : t / (M / 4), g = vfast ? t / nvec : t % (M / 4);
+            const int blk = g / q, j = g - blk * q;
+            const int e0 = v * vstride + (blk * len + j) * estride, e1 = e0 + q * estride;
+            const int e2 = e0 + half * estride, e3 = e2 + q * estride;
+            const float2 a0 = s[e0], a1 = s[e1], a2 = s[e2], a3 = s[e3];
+            const float2 b0 = cadd(a0, a2), b2 = cmul(csub(a0, a2), tw[j * twa]);
+            const float2 b1 = cadd(a1, a3), b3 = cmul(csub(a1, a3), tw[(j + q) * twa]);
+            s[e0] = cadd(b0, b1);
+            s[e1] = cmul(csub(b0, b1), tw[j * twb]);
+            s[e2] = cadd(b2, b3);
+            s[e3] = cmul(csub(b2, b3), tw[j * twb]);
+        }
+        __syncthreads();
+        len >>= 2;
+    }
+    if (len == 2) {  // one stage left
+        for (int t = threadIdx.x; t < nvec * (M / 2); t += NT) {
+            const int v = vfast ? t % nvec : t / (M / 2), g = vfast ? t / nvec : t % (M / 2);
+            const int e0 = v * vstride + (2 * g) * estride, e1 = e0 + estride;
+            const float2 a = s[e0], bb = s[e1];
+            s[e0] = cadd(a, bb);
+            s[e1] = cmul(csub(a, bb), tw[0]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int M, int NT>
+__device__ __forceinline__ void impl_dit_sweep(float2* s, int nvec, int vstride, int estride, bool vfast,
+                                               const float2* tw) {
+    int len = 2;
+    while (2 * len <= M) {  // stages len and 2 len together
+        const int hl = len >> 1, twa = M / len, twb = M / (2 * len);
+        for (int t = threadIdx.x; t < nvec * (M / 4); t += NT) {
+            const int v = vfast ? t % nvec : t / (M / 4), g = vfast ? t / nvec : t % (M / 4);
+            const int blk = g / hl, j = g - blk * hl;
+            const int e0 = v * vstride + (blk * 2 * len + j) * estride, e1 = e0 + hl * estride;
+            const int e2 = e0 + len * estride, e3 = e2 + hl * estride;
+            float2 wa = tw[j * twa];
+            wa.y = -wa.y;
+            const float2 a0 = s[e0], a1 = cmul(s[e1], wa), a2 = s[e2], a3 = cmul(s[e3], wa);
+            const float2 c0 = cadd(a0, a1), c1 = csub(a0, a1), c2 = cadd(a2, a3), c3 = csub(a2, a3);
+            float2 w0 = tw[j * twb], w1 = tw[(j + hl) * twb];
+            w0.y = -w0.y;
+            w1.y = -w1.y;
+            const float2 d2 = cmul(c2, w0), d3 = cmul(c3, w1);
+            s[e0] = cadd(c0, d2);
+            s[e2] = csub(c0, d2);
+            s[e1] = cadd(c1, d3);
+            s[e3] = csub(c1, d3);
+        }
+        __syncthreads();
+        len <<= 2;
+    }
+    if (len == M) {  // one stage left
+        const int hl = M >> 1;
+        for (int t = threadIdx.x; t < nvec * (M / 2); t += NT) {
+            const int v = vfast ? t % nvec : t / (M / 2), j = vfast ? t / nvec : t % (M / 2);
+            const int e0 = v * vstride + j * estride, e1 = e0 + hl * estride;
+            float2 w = tw[j];
+            w.y = -w.y;
+            const float2 a = s[e0], bb = cmul(s[e1], w);
+            s[e0] = cadd(a, bb);
+            s[e1] = csub(a, bb);
+        }
+        __syncthreads();
+    }
+}
+
 template <int M, int NT>
 __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xin, uint16_t* __restrict__ yout,
                                                  const float2* __restrict__ Gbr, int nc, int nk, int conjG,
@@ -273,32 +355,9 @@ __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xi
         s[y * P + x] = make_float2(bf2f((uint16_t)(raw & 0xffff)), bf2f((uint16_t)(raw >> 16)));
     }
     __syncthreads();
-    // forward DIF along the nc data rows
-    for (int len = M; len >= 2; len >>= 1) {
-        const int half = len >> 1, tws = M / len;
-        for (int t = tid; t < nc * (M / 2); t += NT) {
-            const int row = t / (M / 2), bf = t - row * (M / 2);
-            const int blk = bf / half, j = bf - blk * half;
-            const int i0 = row * P + blk * len + j, i1 = i0 + half;
-            const float2 a = s[i0], bb = s[i1];
-            s[i0] = cadd(a, bb);
-            s[i1] = cmul(csub(a, bb), tw[j * tws]);
-        }
-        __syncthreads();
-    }
-    // forward DIF along all columns
-    for (int len = M; len >= 2; len >>= 1) {
-        const int half = len >> 1, tws = M / len;
-        for (int t = tid; t < M * (M / 2); t += NT) {
-            const int col = t % M, bf = t / M;
-            const int blk = bf / half, j = bf - blk * half;
-            const int i0 = (blk * len + j) * P + col, i1 = i0 + half * P;
-            const float2 a = s[i0], bb = s[i1];
-            s[i0] = cadd(a, bb);
-            s[i1] = cmul(csub(a, bb), tw[j * tws]);
-        }
-        __syncthreads();
-    }
+    // forward DIF along the nc data rows, then all columns (bit-reversed spectrum)
+    impl_dif_sweep<M, NT>(s, nc, P, 1, false, tw);
+    impl_dif_sweep<M, NT>(s, M, 1, P, true, tw);
     // spectrum (bit-reversed both ways) times Ghat_c
     {
         const float2* G = Gbr + (size_t)c * M * M;
@@ -310,36 +369,9 @@ __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xi
         }
     }
     __syncthreads();
-    // inverse DIT along all columns
-    for (int len = 2; len <= M; len <<= 1) {
-        const int half = len >> 1, tws = M / len;
-        for (int t = tid; t < M * (M / 2); t += NT) {
-            const int col = t % M, bf = t / M;
-            const int blk = bf / half, j = bf - blk * half;
-            const int i0 = (blk * len + j) * P + col, i1 = i0 + half * P;
-            float2 w = tw[j * tws];
-            w.y = -w.y;
-            const float2 a = s[i0], bb = cmul(s[i1], w);
-            s[i0] = cadd(a, bb);
-            s[i1] = csub(a, bb);
-        }
-        __syncthreads();
-    }
-    // inverse DIT along the nc kept rows
-    for (int len = 2; len <= M; len <<= 1) {
-        const int half = len >> 1, tws = M / len;
-        for (int t = tid; t < nc * (M / 2); t += NT) {
-            const int row = t / (M / 2), bf = t - row * (M / 2);
-            const int blk = bf / half, j = bf - blk * half;
-            const int i0 = row * P + blk * len + j, i1 = i0 + half;
-            float2 w = tw[j * tws];
-            w.y = -w.y;
-            const float2 a = s[i0], bb = cmul(s[i1], w);
-            s[i0] = cadd(a, bb);
-            s[i1] = csub(a, bb);
-        }
-        __syncthreads();
-    }
+    // inverse DIT along all columns, then the nc kept rows (natural order)
+    impl_dit_sweep<M, NT>(s, M, 1, P, true, tw);
+    impl_dit_sweep<M, NT>(s, nc, P, 1, false, tw);
     for (int e = tid; e < nc * nc; e += NT) {
         const int y = e / nc, x = e - y * nc;
         float2 v = s[y * P + x];
