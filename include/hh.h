@@ -87,11 +87,14 @@ typedef struct {
     int levels;            /* multigrid levels (Sec. 3.2), default 3, 2..HH_MAX_LEVELS */
     int nu_pre, nu_post;   /* damped-Jacobi sweeps before/after the coarse correction, 1/1 */
     double jacobi_w;       /* Jacobi damping, default 0.8 */
-    int coarse_reduce;     /* coarsest exact solve: 1 (default) eliminates the odd grid rows by
-                              their tridiagonal inverses first (one level of cyclic reduction)
-                              and runs the two-ended block elimination on the even rows (half
-                              the sequential chain, about twice the factor memory); 0 runs the
-                              two-ended elimination on all grid rows */
+    int coarse_reduce;     /* coarsest exact solve: 1 eliminates the odd grid rows by their
+                              tridiagonal inverses first (one level of cyclic reduction) and
+                              runs the two-ended block elimination on the even rows (half the
+                              sequential chain, about twice the factor memory); 2 (default) does
+                              the same and runs each elimination chain two steps at a time with
+                              precomputed two-step factors, the skipped steps following in
+                              parallel (half the sequential steps again, 5/4 of the factor
+                              memory of 1); 0 runs the two-ended elimination on all grid rows */
     int coarse_iters;      /* 0 (default): the coarsest level is solved exactly (above).  k in
                               1..16: instead k steps of GMRES on the coarsest shifted operator,
                               right-preconditioned by its diagonal (Jacobi), from zero, without

@@ -390,13 +390,18 @@ struct CoarseMV {
     // out[q] = sum_j Qk[j][row] v[q][j] for the R vectors s_v[q * m + j]; the JP
     // partial sums meet in s_part[q * CS_NT + t].  Valid in the owner threads (jp == 0).
     __device__ void apply(const float2* __restrict__ Qk, const float2* s_v, float2* s_part, float2 (&out)[R]) const {
+        float2 qa[CH], qb[CH];
+        apply(Qk, qa, qb, s_v, s_part, out);
+    }
+    // the same with the caller's chunk buffers (contents undefined on return)
+    __device__ void apply(const float2* __restrict__ Qk, float2 (&qa)[CH], float2 (&qb)[CH], const float2* s_v,
+                          float2* s_part, float2 (&out)[R]) const {
         float2 acc[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
         if (jp < JP) {
             const int j0 = jp * jlen, j1 = min(m, j0 + jlen);
             const float2* qp = Qk + row;
-            float2 qa[CH], qb[CH];
             int j = j0;
             if (j + CH <= j1) {
 #pragma unroll
@@ -449,6 +454,82 @@ struct CoarseMV {
         for (int q = 0; q < R; ++q) out[q] = acc[q];
     }
     __device__ bool owner() const { return jp == 0; }
+
+    // Cross-step prefetch for the chains: the next step's matrix does not depend
+    // on this step's result, so its first two chunks load while this step ends.
+    // Smaller chunks than apply() (the two buffers stay live across the step);
+    // needs every thread's column range to be whole chunk pairs (m = 128 .. 1024).
+    static constexpr int PCH = R == 1 ? 8 : 4;
+    __device__ bool pf_ok() const { return CS_NT % m == 0 && jlen % (2 * PCH) == 0; }
+    // buffer resource over one m x m block (the block pointer is uniform in the
+    // workgroup); loads then take the column offset from a scalar register
+    __device__ __amdgpu_buffer_rsrc_t block_rsrc(const float2* Qk) const {
+        const unsigned long long a = (unsigned long long)Qk;
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+        void* base = (void*)(((unsigned long long)hi << 32) | lo);
+        return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, m * m * (int)sizeof(float2), 0x00020000);
+    }
+    __device__ float2 bload(__amdgpu_buffer_rsrc_t rs, int vo, int col) const {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, col * m * 8, 0));
+    }
+    __device__ void preload(const float2* __restrict__ Qk, float2 (&qa)[PCH], float2 (&qb)[PCH]) const {
+        const __amdgpu_buffer_rsrc_t rs = block_rsrc(Qk);
+        const int vo = (row + jp * jlen * m) * 8;
+#pragma unroll
+        for (int u = 0; u < PCH; ++u) qa[u] = bload(rs, vo, u);
+#pragma unroll
+        for (int u = 0; u < PCH; ++u) qb[u] = bload(rs, vo, PCH + u);
+    }
+    // apply() with qa / qb holding Qk's first two chunks of this thread's columns
+    // (preload() or the previous call); on return they hold Qnext's (if not null).
+    __device__ void apply_pf(const float2* __restrict__ Qk, const float2* __restrict__ Qnext, float2 (&qa)[PCH],
+                             float2 (&qb)[PCH], const float2* s_v, float2* s_part, float2 (&out)[R]) const {
+        float2 acc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
+        const int j0 = jp * jlen, nch = jlen / PCH;
+        const int vo = (row + j0 * m) * 8;
+        const __amdgpu_buffer_rsrc_t rp = block_rsrc(Qk);
+        const __amdgpu_buffer_rsrc_t rn = block_rsrc(Qnext ? Qnext : Qk);
+        const float2* sv = s_v + j0;
+        for (int k = 0; k < nch; k += 2) {
+#pragma unroll
+            for (int u = 0; u < PCH; ++u)
+#pragma unroll
+                for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qa[u], sv[q * m + k * PCH + u]));
+            if (k + 2 < nch) {
+#pragma unroll
+                for (int u = 0; u < PCH; ++u) qa[u] = bload(rp, vo, (k + 2) * PCH + u);
+            } else if (Qnext) {
+#pragma unroll
+                for (int u = 0; u < PCH; ++u) qa[u] = bload(rn, vo, u);
+            }
+#pragma unroll
+            for (int u = 0; u < PCH; ++u)
+#pragma unroll
+                for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], cmul(qb[u], sv[q * m + (k + 1) * PCH + u]));
+            if (k + 3 < nch) {
+#pragma unroll
+                for (int u = 0; u < PCH; ++u) qb[u] = bload(rp, vo, (k + 3) * PCH + u);
+            } else if (Qnext) {
+#pragma unroll
+                for (int u = 0; u < PCH; ++u) qb[u] = bload(rn, vo, PCH + u);
+            }
+        }
+        if (JP > 1) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) s_part[q * CS_NT + threadIdx.x] = acc[q];
+            __syncthreads();
+            if (jp == 0)
+                for (int t = 1; t < JP; ++t)
+#pragma unroll
+                    for (int q = 0; q < R; ++q) acc[q] = cadd(acc[q], s_part[q * CS_NT + t * m + row]);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) out[q] = acc[q];
+    }
 };
 
 // dynamic LDS of a chain kernel: s_v [R][m], then s_part [R][CS_NT] when JP > 1
@@ -699,39 +780,90 @@ __global__ void __launch_bounds__(CS_NT) k_cr_par(const float2* __restrict__ bcs
     }
 }
 
+// The steps of one end's chains.  Plain: every chain index, factors P_j (slot
+// M + j) and R_j (slot 2M + j).  Paired (F2 given): the odd chain indices only,
+// with the two-step factors P(s) P(s-1) at F2 slot j >> 1 and R(t) R(t-1) at
+// H + (j >> 1) (built in setup.hip); forward index s sits at reduced row s (top)
+// or M-1-s (bottom), backward index t at p-1-t or p+1+t.
+struct CrSteps {
+    const float2* Fi;
+    const float2* F2i;
+    size_t mm;
+    int M, p, H, nsteps, n;
+    bool top, pair;
+    __device__ CrSteps(const float2* F, const float2* F2, int ii, int m, bool top_) {
+        M = crM(m);
+        p = M / 2;
+        H = (M + 1) / 2;
+        mm = (size_t)m * m;
+        top = top_;
+        pair = F2 != nullptr;
+        Fi = F + (size_t)ii * 4 * M * mm;
+        F2i = pair ? F2 + (size_t)ii * 2 * H * mm : nullptr;
+        nsteps = top ? p : (M - 1 - p);
+        n = pair ? nsteps / 2 : nsteps;
+    }
+    __device__ int index(int i) const { return pair ? 2 * i + 1 : i; }
+    __device__ int fwd_row(int i) const { return top ? index(i) : M - 1 - index(i); }
+    __device__ int bwd_row(int i) const { return top ? p - 1 - index(i) : p + 1 + index(i); }
+    __device__ const float2* fwd_mat(int i) const {
+        const int j = fwd_row(i);
+        return pair ? F2i + (size_t)(j >> 1) * mm : Fi + (size_t)(M + j) * mm;
+    }
+    __device__ const float2* bwd_mat(int i) const {
+        const int j = bwd_row(i);
+        return pair ? F2i + (size_t)(H + (j >> 1)) * mm : Fi + (size_t)(2 * M + j) * mm;
+    }
+};
+
 // forward chains of the reduced system: y_j = g_j + P_j y_{j -/+ 1}; y_j -> x row 2j.
-template <int R>
-__global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw, float2* __restrict__ x,
-                                                  float2* __restrict__ ends, const float2* __restrict__ F,
+// Paired: y(s) = h(s) + P(s) P(s-1) y(s-2) over the odd s, h from k_cr_pp<.,4>.
+// PF: the next step's factor is prefetched (needs CoarseMV::pf_ok(); chosen by the host).
+template <int R, bool PF>
+__global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
+                                                  float2* __restrict__ x, float2* __restrict__ ends,
+                                                  const float2* __restrict__ F, const float2* __restrict__ F2,
                                                   const int* __restrict__ inst, const int* __restrict__ slots,
                                                   int nslots, const int* __restrict__ nslots_dev, int m,
                                                   const int* __restrict__ active) {
     extern __shared__ float2 s_lds[];
     float2* s_v = s_lds;
     float2* s_part = s_lds + R * m;
-    const int M = crM(m), p = M / 2;
     const bool top = blockIdx.y == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
     if (!g.any) return;
-    const size_t mm = (size_t)m * m;
-    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const int M = cs.M;
+    const size_t mm = cs.mm;
+    const float2* src = cs.pair ? hw : gw;
     const CoarseMV<R> mv(m);
-    const int nsteps = top ? p : (M - 1 - p);
-    for (int s = 0; s < nsteps; ++s) {
-        const int j = top ? s : (M - 1 - s);
+    constexpr bool pf = PF;
+    float2 qa[CoarseMV<R>::PCH], qb[CoarseMV<R>::PCH];
+    if (pf && cs.n > 1) mv.preload(cs.fwd_mat(1), qa, qb);
+    for (int s = 0; s < cs.n; ++s) {
+        const int j = cs.fwd_row(s);
+        // g_j (h_j) does not depend on this step's product: read it first
+        float2 gv[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            gv[q] = (mv.owner() && g.on[q]) ? src[((size_t)g.rr[q] * M + j) * m + mv.row] : make_float2(0.f, 0.f);
         float2 out[R];
-        if (s > 0) mv.apply(Fi + (size_t)(M + j) * mm, s_v, s_part, out);
+        if (s > 0) {
+            if (pf) mv.apply_pf(cs.fwd_mat(s), s + 1 < cs.n ? cs.fwd_mat(s + 1) : nullptr, qa, qb, s_v, s_part, out);
+            else mv.apply(cs.fwd_mat(s), s_v, s_part, out);
+        }
         __syncthreads();
         if (mv.owner()) {
             const int i = mv.row;
+            const bool last = cs.index(s) == cs.nsteps - 1;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 float2 y = make_float2(0.f, 0.f);
                 if (g.on[q]) {
-                    y = gw[((size_t)g.rr[q] * M + j) * m + i];
+                    y = gv[q];
                     if (s > 0) y = cadd(y, out[q]);
                     x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + i] = y;
-                    if (s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + i] = y;
+                    if (last) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + i] = y;
                 }
                 s_v[q * m + i] = y;
             }
@@ -742,21 +874,24 @@ __global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw,
 
 // middle row and backward chains: x_p = g_p + P_p y_{p-1} + R_p y_{p+1};
 // x_j = y_j + R_j x_{j +/- 1} (y_j read from, x_j written to, x row 2j).
-template <int R>
-__global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw, float2* __restrict__ x,
-                                                  const float2* __restrict__ ends, const float2* __restrict__ F,
+// Paired: x(t) = k(t) + R(t) R(t-1) x(t-2) over the odd t (x(-1) = x_p), k from k_cr_pp<.,6>.
+template <int R, bool PF>
+__global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
+                                                  float2* __restrict__ x, const float2* __restrict__ ends,
+                                                  const float2* __restrict__ F, const float2* __restrict__ F2,
                                                   const int* __restrict__ inst, const int* __restrict__ slots,
                                                   int nslots, const int* __restrict__ nslots_dev, int m,
                                                   const int* __restrict__ active) {
     extern __shared__ float2 s_lds[];
     float2* s_v = s_lds;
     float2* s_part = s_lds + R * m;
-    const int M = crM(m), p = M / 2;
     const bool top = blockIdx.y == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
     if (!g.any) return;
-    const size_t mm = (size_t)m * m;
-    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const int M = cs.M, p = cs.p;
+    const size_t mm = cs.mm;
+    const float2* Fi = cs.Fi;
     const CoarseMV<R> mv(m);
     float2 acc[R];
 #pragma unroll
@@ -790,12 +925,24 @@ __global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw,
             s_v[q * m + i] = v;
         }
     }
+    constexpr bool pf = PF;
+    float2 qa[CoarseMV<R>::PCH], qb[CoarseMV<R>::PCH];
+    if (pf && cs.n > 0) mv.preload(cs.bwd_mat(0), qa, qb);
     __syncthreads();
-    const int nsteps = top ? p : (M - 1 - p);
-    for (int s = 0; s < nsteps; ++s) {
-        const int j = top ? (p - 1 - s) : (p + 1 + s);
+    for (int s = 0; s < cs.n; ++s) {
+        const int j = cs.bwd_row(s);
+        // y_j (k_j) does not depend on this step's product: read it first
+        float2 yv[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            yv[q] = make_float2(0.f, 0.f);
+            if (mv.owner() && g.on[q])
+                yv[q] = cs.pair ? hw[((size_t)g.rr[q] * M + j) * m + mv.row]
+                                : x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + mv.row];
+        }
         float2 out[R];
-        mv.apply(Fi + (size_t)(2 * M + j) * mm, s_v, s_part, out);
+        if (pf) mv.apply_pf(cs.bwd_mat(s), s + 1 < cs.n ? cs.bwd_mat(s + 1) : nullptr, qa, qb, s_v, s_part, out);
+        else mv.apply(cs.bwd_mat(s), s_v, s_part, out);
         __syncthreads();
         if (mv.owner()) {
             const int i = mv.row;
@@ -803,14 +950,85 @@ __global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw,
             for (int q = 0; q < R; ++q) {
                 float2 v = make_float2(0.f, 0.f);
                 if (g.on[q]) {
-                    const size_t o = (size_t)g.rr[q] * mm + (size_t)(2 * j) * m + i;
-                    v = cadd(x[o], out[q]);
-                    x[o] = v;
+                    v = cadd(yv[q], out[q]);
+                    x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + i] = v;
                 }
                 s_v[q * m + i] = v;
             }
         }
         __syncthreads();
+    }
+}
+
+// Row-parallel phases of the paired chains (blockIdx.y = end * H2 + i; chain
+// index 2i + 1 for PH 4 and 6, 2i for PH 5 and 7; rows as in CrSteps):
+// PH 4: h(s) = g(s) + P(s) g(s-1)                      -> hw      (odd s)
+// PH 5: y(s) = g(s) + P(s) y(s-1), y(0) = g(0)         -> x row   (even s; ends if s is the last)
+// PH 6: k(t) = y(t) + R(t) y(t-1)                      -> hw      (odd t)
+// PH 7: x(t) = y(t) + R(t) x(t-1), x(-1) = x_p         -> x row   (even t)
+template <int R, int PH>
+__global__ void __launch_bounds__(CS_NT) k_cr_pp(const float2* __restrict__ gw, float2* __restrict__ hw,
+                                                 float2* __restrict__ x, float2* __restrict__ ends,
+                                                 const float2* __restrict__ F, const int* __restrict__ inst,
+                                                 const int* __restrict__ slots, int nslots,
+                                                 const int* __restrict__ nslots_dev, int m,
+                                                 const int* __restrict__ active) {
+    extern __shared__ float2 s_lds[];
+    float2* s_v = s_lds;
+    float2* s_part = s_lds + R * m;
+    const int M = crM(m), p = M / 2;
+    const int H2 = gridDim.y / 2;
+    const int e = blockIdx.y / H2, i = blockIdx.y - e * H2;
+    const bool top = e == 0;
+    const int nsteps = top ? p : (M - 1 - p);
+    const int s = (PH == 4 || PH == 6) ? 2 * i + 1 : 2 * i;
+    if (s >= nsteps) return;
+    const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
+    if (!g.any) return;
+    const size_t mm = (size_t)m * m;
+    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const bool fwd = PH == 4 || PH == 5;
+    const int j = fwd ? (top ? s : M - 1 - s) : (top ? p - 1 - s : p + 1 + s);
+    const int jm = fwd ? (top ? s - 1 : M - s) : (top ? p - s : p + s);  // index s - 1 (x_p's row for t = 0)
+    const bool prod = !(PH == 5 && s == 0);
+    const float2* Mat = Fi + (size_t)((fwd ? M : 2 * M) + j) * mm;
+    const CoarseMV<R> mv(m);
+    float2 base[R];
+    if (mv.owner()) {
+        const int r = mv.row;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float2 w = make_float2(0.f, 0.f);
+            base[q] = make_float2(0.f, 0.f);
+            if (g.on[q]) {
+                const size_t rb = (size_t)g.rr[q] * mm;
+                if (fwd) base[q] = gw[((size_t)g.rr[q] * M + j) * m + r];
+                else base[q] = x[rb + (size_t)(2 * j) * m + r];
+                if (prod) w = PH == 4 ? gw[((size_t)g.rr[q] * M + jm) * m + r] : x[rb + (size_t)(2 * jm) * m + r];
+            }
+            s_v[q * m + r] = w;
+        }
+    }
+    float2 out[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) out[q] = make_float2(0.f, 0.f);
+    if (prod) {
+        __syncthreads();
+        mv.apply(Mat, s_v, s_part, out);
+    }
+    if (mv.owner()) {
+        const int r = mv.row;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (!g.on[q]) continue;
+            const float2 v = cadd(base[q], out[q]);
+            if (PH == 4 || PH == 6) {
+                hw[((size_t)g.rr[q] * M + j) * m + r] = v;
+            } else {
+                x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + r] = v;
+                if (PH == 5 && s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + e) * m + r] = v;
+            }
+        }
     }
 }
 
@@ -1066,8 +1284,9 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
 // first row); middle row x_p = g_p + P_p y_{p-1} + R_p y_{p+1}; backward
 // x_j = y_j + R_j x_{j +/- 1}.  Factor slots as in k_cr_fwd / k_cr_bwd.
 template <int R, int RS>
-__global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restrict__ gw, float2* __restrict__ x,
-                                                         float2* __restrict__ ends, const float2* __restrict__ F,
+__global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
+                                                         float2* __restrict__ x, float2* __restrict__ ends,
+                                                         const float2* __restrict__ F, const float2* __restrict__ F2,
                                                          const int* __restrict__ inst, const int* __restrict__ slots,
                                                          int nslots, const int* __restrict__ nslots_dev, int m,
                                                          const int* __restrict__ active, SplitGeom geo,
@@ -1081,15 +1300,16 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restric
     const bool top = (unit & 1) == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
     if (!g.any) return;  // the same for every slice of the unit
-    const int M = crM(m), p = M / 2;
-    const size_t mm = (size_t)m * m;
-    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const int M = cs.M;
+    const size_t mm = cs.mm;
+    const float2* src = cs.pair ? hw : gw;
     const int row0 = slice * RS;
     const int row = row0 + threadIdx.x;
-    const int nsteps = top ? p : (M - 1 - p);
     float2 qr[CSP_CMAX];
-    for (int s = 0; s < nsteps; ++s) {
-        const int j = top ? s : (M - 1 - s);
+    if (cs.n > 1) split_load_q<RS>(cs.fwd_mat(1), m, row0, qr);
+    for (int s = 0; s < cs.n; ++s) {
+        const int j = cs.fwd_row(s);
         float2 out[R];
         if (s > 0) {
             split_wait(cnt + unit, geo.S * s, err);
@@ -1105,22 +1325,23 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restric
             for (int q = 0; q < R; ++q) {
                 float2 y = make_float2(0.f, 0.f);
                 if (g.on[q]) {
-                    y = gw[((size_t)g.rr[q] * M + j) * m + row];
+                    y = src[((size_t)g.rr[q] * M + j) * m + row];
                     if (s > 0) y = cadd(y, out[q]);
                     x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + row] = y;
-                    if (s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + row] = y;
+                    if (cs.index(s) == cs.nsteps - 1) ends[((size_t)g.rr[q] * 2 + (top ? 0 : 1)) * m + row] = y;
                 }
                 xch_at<R>(xch, unit, s & 1, q, m)[row] = y;
             }
         }
         split_arrive(cnt + unit);
-        if (s + 1 < nsteps) split_load_q<RS>(Fi + (size_t)(M + (top ? j + 1 : j - 1)) * mm, m, row0, qr);
+        if (s > 0 && s + 1 < cs.n) split_load_q<RS>(cs.fwd_mat(s + 1), m, row0, qr);
     }
 }
 
 template <int R, int RS>
-__global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restrict__ gw, float2* __restrict__ x,
-                                                         const float2* __restrict__ ends, const float2* __restrict__ F,
+__global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
+                                                         float2* __restrict__ x, const float2* __restrict__ ends,
+                                                         const float2* __restrict__ F, const float2* __restrict__ F2,
                                                          const int* __restrict__ inst, const int* __restrict__ slots,
                                                          int nslots, const int* __restrict__ nslots_dev, int m,
                                                          const int* __restrict__ active, SplitGeom geo,
@@ -1134,12 +1355,12 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restric
     const bool top = (unit & 1) == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
     if (!g.any) return;
-    const int M = crM(m), p = M / 2;
-    const size_t mm = (size_t)m * m;
-    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
+    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const int M = cs.M, p = cs.p;
+    const size_t mm = cs.mm;
+    const float2* Fi = cs.Fi;
     const int row0 = slice * RS;
     const int row = row0 + threadIdx.x;
-    const int nsteps = top ? p : (M - 1 - p);
     float2 qr[CSP_CMAX];
     // middle row (round 0), computed by both ends
     float2 acc[R];
@@ -1172,9 +1393,9 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restric
         }
     }
     split_arrive(cnt + unit);
-    if (nsteps > 0) split_load_q<RS>(Fi + (size_t)(2 * M + (top ? p - 1 : p + 1)) * mm, m, row0, qr);
-    for (int s = 0; s < nsteps; ++s) {
-        const int j = top ? (p - 1 - s) : (p + 1 + s);
+    if (cs.n > 0) split_load_q<RS>(cs.bwd_mat(0), m, row0, qr);
+    for (int s = 0; s < cs.n; ++s) {
+        const int j = cs.bwd_row(s);
         split_wait(cnt + unit, geo.S * (s + 1), err);
         for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
             const int q = e / m, i = e - q * m;
@@ -1189,14 +1410,14 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restric
                 float2 v = make_float2(0.f, 0.f);
                 if (g.on[q]) {
                     const size_t o = (size_t)g.rr[q] * mm + (size_t)(2 * j) * m + row;
-                    v = cadd(x[o], out[q]);
+                    v = cadd(cs.pair ? hw[((size_t)g.rr[q] * M + j) * m + row] : x[o], out[q]);
                     x[o] = v;
                 }
                 xch_at<R>(xch, unit, (s + 1) & 1, q, m)[row] = v;
             }
         }
         split_arrive(cnt + unit);
-        if (s + 1 < nsteps) split_load_q<RS>(Fi + (size_t)(2 * M + (top ? j - 1 : j + 1)) * mm, m, row0, qr);
+        if (s + 1 < cs.n) split_load_q<RS>(cs.bwd_mat(s + 1), m, row0, qr);
     }
 }
 
@@ -1242,12 +1463,14 @@ struct CoarseWork {
     float2* xch;
     float2* tw;  // reduced solve: V_j b_{2j+1}, [rhs][Mo][m]
     float2* gw;  // reduced solve: g_j, [rhs][M][m]
+    float2* hw;  // paired chains: h(s), then k(t), at their reduced rows, [rhs][M][m]
 };
 static size_t coarse_work_bytes(const hh_model* md, int nrhs) {
     const size_t ns = (size_t)coarse_slot_bound(md, nrhs);
     const int m = md->lev[md->nlev - 1].n;
     return (ns + 64) * sizeof(int) + 4 * (ns + CS_RMAX) * sizeof(int) + 256 +
-           4 * (ns + CS_RMAX) * (size_t)m * sizeof(float2) + 256 + (size_t)nrhs * m * m * sizeof(float2);
+           4 * (ns + CS_RMAX) * (size_t)m * sizeof(float2) + 256 +
+           (size_t)nrhs * (m / 2 + 2 * ((m + 1) / 2)) * m * sizeof(float2);
 }
 static CoarseWork coarse_work(const hh_model* md, void* base, int nrhs) {
     const size_t ns = (size_t)coarse_slot_bound(md, nrhs);
@@ -1265,6 +1488,7 @@ static CoarseWork coarse_work(const hh_model* md, void* base, int nrhs) {
     q = (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
     w.tw = (float2*)q;
     w.gw = w.tw + (size_t)nrhs * (m / 2) * m;
+    w.hw = w.gw + (size_t)nrhs * ((m + 1) / 2) * m;
     return w;
 }
 
@@ -1430,6 +1654,53 @@ static hh_status launch_cr_par(hh_model* md, int PH, const float2* bcs, float2* 
     return HH_OK;
 }
 
+// a row-parallel phase of the paired chains (PH 4..7, k_cr_pp)
+static hh_status launch_cr_pp(hh_model* md, int PH, float2* x, float2* ends, const int* inst, const int* slots,
+                              int nslots, const int* nslots_dev, int m, const int* active, const CoarseWork& cw) {
+    constexpr int RP = CS_RMAX;
+    hh_ctx* ctx = md->ctx;
+    static unsigned attr_devices = 0;
+    if (!(attr_devices & (1u << ctx->device))) {
+        size_t mostp = 0;
+        for (int mm_ = 4; mm_ <= CS_MAXM; ++mm_) mostp = std::max(mostp, coarse_lds_bytes(RP, mm_));
+        if (mostp > 65536) {
+            const int want = (int)mostp;
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_pp<RP, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_pp<RP, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_pp<RP, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_pp<RP, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+        }
+        attr_devices |= 1u << ctx->device;
+    }
+    const int M = (m + 1) / 2, p = M / 2;
+    const int H2 = (std::max(p, M - 1 - p) + 1) / 2;
+    if (H2 == 0) return HH_OK;
+    const size_t ldsp = coarse_lds_bytes(RP, m);
+    const dim3 grd((nslots + RP - 1) / RP, 2 * H2);
+    const float2* F = md->coarseQT.as<float2>();
+    hipStream_t st = ctx->stream;
+    switch (PH) {
+        case 4:
+            hipLaunchKernelGGL((k_cr_pp<RP, 4>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
+                               nslots, nslots_dev, m, active);
+            break;
+        case 5:
+            hipLaunchKernelGGL((k_cr_pp<RP, 5>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
+                               nslots, nslots_dev, m, active);
+            break;
+        case 6:
+            hipLaunchKernelGGL((k_cr_pp<RP, 6>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
+                               nslots, nslots_dev, m, active);
+            break;
+        default:
+            hipLaunchKernelGGL((k_cr_pp<RP, 7>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
+                               nslots, nslots_dev, m, active);
+            break;
+    }
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
 template <int R>
 static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
                              const int* slots, int nslots, const int* nslots_dev, int m, float c, const int* active,
@@ -1442,8 +1713,14 @@ static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2*
         for (int mm_ = 4; mm_ <= CS_MAXM; ++mm_) most = std::max(most, coarse_lds_bytes(R, mm_));
         if (most > 65536) {
             const int want = (int)most;
-            HH_HIP(hipFuncSetAttribute((const void*)k_cr_fwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
-            HH_HIP(hipFuncSetAttribute((const void*)k_cr_bwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_fwd<R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_bwd<R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, want));
+            if (R <= 4) {
+                HH_HIP(hipFuncSetAttribute((const void*)k_cr_fwd<R, R <= 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           want));
+                HH_HIP(hipFuncSetAttribute((const void*)k_cr_bwd<R, R <= 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           want));
+            }
         }
         attr_devices |= 1u << ctx->device;
     }
@@ -1452,12 +1729,31 @@ static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2*
     hipStream_t st = ctx->stream;
     HH_TRY(launch_cr_par(md, 1, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
     HH_TRY(launch_cr_par(md, 2, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
-    hipLaunchKernelGGL((k_cr_fwd<R>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, x, ends, F, inst, slots, nslots,
-                       nslots_dev, m, active);
+    // prefetching chains where every thread's columns are whole chunk pairs
+    // (the same test as CoarseMV::pf_ok()); not for R = 8, whose registers it would spill
+    const int JP = CS_NT / m, jlen = (m + JP - 1) / JP, pch = R == 1 ? 8 : 4;
+    const bool pf = R <= 4 && CS_NT % m == 0 && jlen % (2 * pch) == 0;
+    const float2* F2 = md->cr_pair ? md->coarseP2.as<float2>() : nullptr;
+    if (F2) HH_TRY(launch_cr_pp(md, 4, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    if (pf)
+        hipLaunchKernelGGL((k_cr_fwd<R, R <= 4>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+                           inst, slots, nslots, nslots_dev, m, active);
+    else
+        hipLaunchKernelGGL((k_cr_fwd<R, false>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+                           inst, slots, nslots, nslots_dev, m, active);
     HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_cr_bwd<R>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, x, ends, F, inst, slots, nslots,
-                       nslots_dev, m, active);
+    if (F2) {
+        HH_TRY(launch_cr_pp(md, 5, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+        HH_TRY(launch_cr_pp(md, 6, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    }
+    if (pf)
+        hipLaunchKernelGGL((k_cr_bwd<R, R <= 4>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+                           inst, slots, nslots, nslots_dev, m, active);
+    else
+        hipLaunchKernelGGL((k_cr_bwd<R, false>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+                           inst, slots, nslots, nslots_dev, m, active);
     HH_LAUNCH_CHECK();
+    if (F2) HH_TRY(launch_cr_pp(md, 7, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     return launch_cr_par(md, 3, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw);
 }
 
@@ -1493,13 +1789,17 @@ static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, f
     if ((long long)std::min(per_cu_f, per_cu_b) * ctx->num_cus < grid) return HH_OK;  // not offered
     HH_TRY(launch_cr_par(md, 1, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
     HH_TRY(launch_cr_par(md, 2, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
+    const float2* F2 = md->cr_pair ? md->coarseP2.as<float2>() : nullptr;
+    if (F2) HH_TRY(launch_cr_pp(md, 4, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     hipLaunchKernelGGL(k_zero_ints, dim3((2 * geo.units + 255) / 256), dim3(256), 0, ctx->stream, cw.cnt,
                        2 * geo.units);
     HH_LAUNCH_CHECK();
     const float2* a_gw = cw.gw;
+    const float2* a_hw = cw.hw;
     float2* a_x = x;
     float2* a_ends = ends;
     const float2* a_F = md->coarseQT.as<float2>();
+    const float2* a_F2 = F2;
     const int* a_inst = inst;
     const int* a_slots = slots;
     int a_nslots = nslots;
@@ -1509,7 +1809,7 @@ static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, f
     float2* a_xch = cw.xch;
     int* a_cnt = cw.cnt;
     int* a_err = md->coarse_err.as<int>();
-    void* args[] = {&a_gw, &a_x, &a_ends, &a_F, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
+    void* args[] = {&a_gw, &a_hw, &a_x, &a_ends, &a_F, &a_F2, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
                     &geo,  &a_xch, &a_cnt, &a_err};
     const hipError_t le = hipLaunchCooperativeKernel((const void*)k_cr_split_fwd<R, RS>, dim3(grid), dim3(CSP_NT),
                                                      args, (unsigned)lds, ctx->stream);
@@ -1521,13 +1821,18 @@ static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, f
         set_error("cooperative launch failed: %s", hipGetErrorString(le));
         return HH_ERR_HIP;
     }
+    if (F2) {
+        HH_TRY(launch_cr_pp(md, 5, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+        HH_TRY(launch_cr_pp(md, 6, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    }
     const float2* b_ends = ends;
     int* b_cnt = cw.cnt + geo.units;
-    void* args_b[] = {&a_gw, &a_x, &b_ends, &a_F, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
+    void* args_b[] = {&a_gw, &a_hw, &a_x, &b_ends, &a_F, &a_F2, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
                       &geo,  &a_xch, &b_cnt, &a_err};
     HH_HIP(hipLaunchCooperativeKernel((const void*)k_cr_split_bwd<R, RS>, dim3(grid), dim3(CSP_NT), args_b,
                                       (unsigned)lds, ctx->stream));
     *fits = true;
+    if (F2) HH_TRY(launch_cr_pp(md, 7, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     return launch_cr_par(md, 3, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw);
 }
 

@@ -372,6 +372,81 @@ __global__ void __launch_bounds__(1024) k_cr_mid(const float2* __restrict__ coef
     }
 }
 
+// ---------------------------------------------------------------------------
+// Paired chains.  Both recurrences of the reduced solve, y(s) = g(s) + P(s) y(s-1)
+// forward and x(t) = y(t) + R(t) x(t-1) backward (chain index s, t from an end;
+// x(-1) = x_p), are run two steps at a time over the odd indices:
+//   y(s) = [g(s) + P(s) g(s-1)] + P(s) P(s-1) y(s-2),   y(1) = g(1) + P(1) g(0),
+//   x(t) = [y(t) + R(t) y(t-1)] + R(t) R(t-1) x(t-2),   x(-1) = x_p,
+// and the even indices follow in parallel, y(s) = g(s) + P(s) y(s-1) (y(0) = g(0))
+// and x(t) = y(t) + R(t) x(t-1): the sequential chain halves for two more
+// row-parallel products per row.  This kernel forms the two-step factors from the
+// stored single-precision P and R (FP64 accumulation).  Rows: forward index s at
+// reduced row s (top) or M-1-s (bottom); backward index t at p-1-t or p+1+t.
+// With slot(X) = X^T row-major, slot(A B) = slot(B) slot(A).
+// blockIdx.x: 32 x 32 output tile, blockIdx.y: product (kind, end, index), z: instance.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cr_pair_prod(const float2* __restrict__ F, float2* __restrict__ F2, int m) {
+    const int M = cr_M(m), p = M / 2, H = (M + 1) / 2;
+    const int H2 = gridDim.y / 4;
+    const int y = blockIdx.y;
+    const int kind = y / (2 * H2), e = (y / H2) % 2, i = y % H2;
+    const bool top = e == 0;
+    const int nsteps = top ? p : (M - 1 - p);
+    const int s = 2 * i + 1;
+    if (s >= nsteps || (kind == 0 && s < 3)) return;
+    int j, jm, a_slot, b_slot, dst;
+    if (kind == 0) {
+        j = top ? s : M - 1 - s;
+        jm = top ? s - 1 : M - s;
+        a_slot = M + j;
+        b_slot = M + jm;
+        dst = j >> 1;
+    } else {
+        j = top ? p - 1 - s : p + 1 + s;
+        jm = top ? p - s : p + s;
+        a_slot = 2 * M + j;
+        b_slot = 2 * M + jm;
+        dst = H + (j >> 1);
+    }
+    const size_t mm = (size_t)m * m;
+    const float2* Fi = F + (size_t)blockIdx.z * 4 * M * mm;
+    const float2* SA = Fi + (size_t)a_slot * mm;
+    const float2* SB = Fi + (size_t)b_slot * mm;
+    float2* SC = F2 + ((size_t)blockIdx.z * 2 * H + dst) * mm;
+    const int nt = (m + 31) / 32;
+    const int ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    __shared__ double2 sb[32][33];
+    __shared__ double2 sa[32][33];
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    double2 acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < m; k0 += 32) {
+        for (int e2 = threadIdx.x; e2 < 32 * 32; e2 += 256) {
+            const int r = e2 / 32, c = e2 % 32;
+            const int br = ti * 32 + r, bc = k0 + c, ar = k0 + r, ac = tj * 32 + c;
+            const float2 vb = (br < m && bc < m) ? SB[(size_t)br * m + bc] : make_float2(0.f, 0.f);
+            const float2 va = (ar < m && ac < m) ? SA[(size_t)ar * m + ac] : make_float2(0.f, 0.f);
+            sb[r][c] = make_double2(vb.x, vb.y);
+            sa[r][c] = make_double2(va.x, va.y);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 32; ++kk) {
+            const double2 av = sa[kk][tx];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = zadd(acc[r], zmul(sb[ty + 8 * r][kk], av));
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = ti * 32 + ty + 8 * r, col = tj * 32 + tx;
+        if (row < m && col < m) SC[(size_t)row * m + col] = make_float2((float)acc[r].x, (float)acc[r].y);
+    }
+}
+
 hh_status setup_coefficients(hh_model* md, const float* kappa_dev) {
     hipStream_t st = md->ctx->stream;
     const hh_model_desc& d = md->d;
@@ -416,6 +491,17 @@ static hh_status setup_coarse_reduced(hh_model* md) {
     hipLaunchKernelGGL(k_cr_mid, dim3(md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(), Vd.as<double2>(),
                        W.as<double2>(), Wm.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
     HH_LAUNCH_CHECK();
+    md->cr_pair = md->d.coarse_reduce >= 2;
+    if (md->cr_pair) {
+        const int p = M / 2, H = (M + 1) / 2, H2 = (std::max(p, M - 1 - p) + 1) / 2;
+        HH_TRY(md->coarseP2.ensure(ctx, (size_t)md->ninst * 2 * H * mm * sizeof(float2)));
+        if (H2 > 0) {
+            const int nt = (m + 31) / 32;
+            hipLaunchKernelGGL(k_cr_pair_prod, dim3(nt * nt, 4 * H2, md->ninst), dim3(256), 0, ctx->stream,
+                               md->coarseQT.as<float2>(), md->coarseP2.as<float2>(), m);
+            HH_LAUNCH_CHECK();
+        }
+    }
     HH_HIP(hipStreamSynchronize(ctx->stream));  // scratch released on return
     return HH_OK;
 }
@@ -424,6 +510,7 @@ hh_status setup_coarse_factors(hh_model* md) {
     if (md->d.coarse_iters > 0) {  // iterative coarsest-grid solve: nothing to factorise
         md->m = md->lev[md->nlev - 1].n;
         md->cr1 = false;
+        md->cr_pair = false;
         return HH_OK;
     }
     if (md->d.coarse_reduce) return setup_coarse_reduced(md);
@@ -433,6 +520,7 @@ hh_status setup_coarse_factors(hh_model* md) {
     const int p = m / 2;
     md->m = m;
     md->cr1 = false;
+    md->cr_pair = false;
     HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * m * m * m * sizeof(float2)));
     Buf S;
     HH_TRY(S.ensure(ctx, (size_t)md->ninst * 3 * m * m * sizeof(double2)));

@@ -68,7 +68,9 @@ def test_operator_complex_symmetry(hh, ctx):
 
 @pytest.mark.parametrize("n,family,with_x0,reduce", [(128, "grf", False, 1), (100, "layered", False, 1),
                                                      (128, "layered", True, 1), (100, "grf", True, 1),
-                                                     (100, "layered", False, 0), (128, "grf", True, 0)])
+                                                     (100, "layered", False, 0), (128, "grf", True, 0),
+                                                     (128, "grf", True, 2), (100, "layered", False, 2),
+                                                     (116, "grf", False, 2)])
 def test_vcycle_parity(hh, ctx, n, family, with_x0, reduce):
     _say(f"vcycle parity n={n} {family} x0={with_x0} reduced coarse factorisation {reduce}")
     k = inputs.slowness(n, 12, family)
@@ -177,7 +179,8 @@ def test_bad_arguments_raise(hh, ctx):
 # cyclic reduction) -- 1000 + R, and with split chains 10000 + 100 RS + R
 COARSE_VARIANTS = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 801), (0, 808), (0, 1601), (0, 1604), (0, 3202), (0, 3208),
                    (1, 1001), (1, 1002), (1, 1004), (1, 1008), (1, 10801), (1, 10808), (1, 11602), (1, 13201),
-                   (1, 13208)]
+                   (1, 13208), (2, 1001), (2, 1002), (2, 1004), (2, 1008), (2, 10801), (2, 10808), (2, 11602),
+                   (2, 13201), (2, 13208)]
 
 
 @pytest.mark.parametrize("reduce,R", COARSE_VARIANTS)
@@ -207,6 +210,24 @@ def test_coarse_group_sizes_vcycle_parity(hh, ctx, reduce, R):
         assert _rel(z2[r], H.Problem(ks[inst[r]], inputs.omega_for(64)).hier.vcycle(b2[r])) <= 2e-5
 
 
+@pytest.mark.parametrize("reduce,R", [(1, 1001), (1, 1002), (1, 1004), (2, 1001), (2, 1002), (2, 1004),
+                                     (2, 1008), (2, 13201)])
+def test_coarse_prefetching_chains_vcycle_parity(hh, ctx, reduce, R):
+    # a 128 x 128 coarsest grid: the chains with R <= 4 prefetch each step's factor
+    # during the previous step (whole chunk pairs of columns per thread)
+    n = 512
+    _say(f"coarse solve variant {R} (reduced factorisation {reduce}) at n={n}")
+    k = inputs.slowness(n, 14, "grf")
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    m = hh.Model(ctx, torch.from_numpy(k), om, coarse_reduce=reduce)
+    m.set_coarse_group(R)
+    b = inputs.random_complex((5, n, n), 19)
+    z = m.apply_vcycle(_dev(b)).cpu().numpy()
+    ref = np.stack([prob.hier.vcycle(b[i]) for i in range(5)])
+    assert _rel(z, ref) <= 2e-5, _rel(z, ref)
+
+
 def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
     # right-hand sides that converge at different iterations leave ragged active
     # sets: the packed coarse solve must still give every RHS the oracle's count.
@@ -221,7 +242,8 @@ def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
     b = np.stack([inputs.point_source(n, 60 + i) for i in range(6)] + [inputs.random_complex((n, n), 66)])
     its_o = [H.solve_mg(prob, b[r])[1] for r in range(7)]
     bad = []
-    for reduce, R in ((1, 0), (1, 1001), (1, 1008), (1, 11601), (0, 0), (0, 1), (0, 802), (0, 1608)):
+    for reduce, R in ((1, 0), (1, 1001), (1, 1008), (1, 11601), (0, 0), (0, 1), (0, 802), (0, 1608), (2, 0),
+                      (2, 1002), (2, 13201)):
         m = hh.Model(ctx, torch.from_numpy(k), om, coarse_reduce=reduce)
         m.set_coarse_group(R)
         xd, info = m.solve(_dev(b))
