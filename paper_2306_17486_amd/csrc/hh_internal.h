@@ -151,6 +151,7 @@ struct hh_model {
     hh::Buf coarse_err;                     // device int: a split-solve wait timed out
     bool cr1 = false;                       // coarseQT holds the reduced factorisation (one level of cyclic reduction)
     bool cr_pair = false;                   // cr1 with paired chains: coarseP2 holds the two-step chain factors
+    bool coarse_mm = true;                  // row-parallel phases of the reduced solve on the matrix cores
     hh::Buf coarseP2;                       // [ninst][2 ceil(ceil(m/2)/2)][m][m]: P_j P_prev at (j >> 1), R_j R_prev
                                             // at ceil(ceil(m/2)/2) + (j >> 1), transposed complex singles
 };

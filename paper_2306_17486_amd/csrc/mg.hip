@@ -1617,9 +1617,15 @@ static hh_status launch_split_t(hh_model* md, const float2* bcs, float2* x, floa
 // The row-parallel phases serve CS_RMAX right-hand sides per workgroup whatever
 // the chains use: their blocks are then read CS_RMAX times fewer (slot groups of
 // CS_RMAX never mix models: the grouping order is padded per model to CS_RMAX).
+static hh_status launch_cr_mm(hh_model* md, int PH, const float2* bcs, float2* x, float2* ends, const int* inst,
+                              const int* slots, int nslots, const int* nslots_dev, int m, float c,
+                              const int* active, const CoarseWork& cw);
+
 static hh_status launch_cr_par(hh_model* md, int PH, const float2* bcs, float2* x, const int* inst, const int* slots,
                                int nslots, const int* nslots_dev, int m, float c, const int* active,
                                const CoarseWork& cw) {
+    if (md->coarse_mm && nslots > CS_RMAX)
+        return launch_cr_mm(md, PH, bcs, x, nullptr, inst, slots, nslots, nslots_dev, m, c, active, cw);
     constexpr int RP = CS_RMAX;
     hh_ctx* ctx = md->ctx;
     static unsigned attr_devices = 0;
@@ -1654,9 +1660,240 @@ static hh_status launch_cr_par(hh_model* md, int PH, const float2* bcs, float2* 
     return HH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The row-parallel phases (PH 1..3 of k_cr_par, PH 4..7 of k_cr_pp) on the
+// matrix cores.  One workgroup takes one factor block and a tile of 16
+// right-hand sides; Y^T (16 x m) = W^T (16 x m) S (m x m), where S is the stored
+// slot ([c][r] = the factor transposed) and W the phase's gathered input
+// vectors (in LDS), as four real products on v_mfma_f32_16x16x4f32 (FP32
+// inputs and accumulation, the precision of the vector-ALU form).  Wave w
+// covers output columns 16 w + 256 u .. + 15 (sixteen waves: enough loads in
+// flight to cover the factor block's latency).  A tile whose right-hand sides
+// belong to several slowness models runs once per model, each pass with that
+// model's factors and its own rows.
+// ---------------------------------------------------------------------------
+typedef float cmm_f4 __attribute__((ext_vector_type(4)));
+constexpr int CMM_NT = 1024;
+constexpr int CMM_D = 8;  // k-steps of S fragments in flight per wave
+
+// W^T rows padded to whole groups of CMM_D k-steps (zeros beyond m), plus one
+static inline __host__ __device__ int cmm_kpad(int m) { return (m + 4 * CMM_D - 1) / (4 * CMM_D) * (4 * CMM_D); }
+static inline size_t cmm_lds_bytes(int m) { return (size_t)16 * (cmm_kpad(m) + 1) * sizeof(float2); }
+
+template <int PH>
+__global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs, float2* __restrict__ x,
+                                                  float2* __restrict__ tw, float2* __restrict__ gw,
+                                                  float2* __restrict__ hw, float2* __restrict__ ends,
+                                                  const float2* __restrict__ F, const int* __restrict__ inst,
+                                                  const int* __restrict__ slots, int nslots,
+                                                  const int* __restrict__ nslots_dev, int m, float cf,
+                                                  const int* __restrict__ active, int rows, int ntiles) {
+    extern __shared__ float2 s_w[];  // [16][ldw]: W^T, zero beyond m
+    __shared__ int s_rr[16], s_in[16];
+    const int M = crM(m), Mo = crMo(m), p = M / 2;
+    const size_t mm = (size_t)m * m;
+    const int m4 = cmm_kpad(m), ldw = m4 + 1, nks = m4 / 4;  // nks: a multiple of CMM_D
+    // workgroup -> (row, tile): all tiles of a row on one XCD (workgroup id mod 8),
+    // so that its factor block is fetched into that XCD's L2 once
+    const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
+    const int row = (kk / ntiles) * 8 + xcd, tile = kk % ntiles;
+    if (row >= rows) return;
+    // the block row (and, for the paired phases, its end and chain index)
+    int j, jm = 0, e = 0, sidx = 0, nsteps = 0;
+    bool prod = true;
+    if (PH <= 3) {
+        j = row;
+    } else {
+        const int H2 = rows / 2;
+        e = row / H2;
+        const int i = row - e * H2;
+        const bool top = e == 0;
+        nsteps = top ? p : (M - 1 - p);
+        sidx = (PH == 4 || PH == 6) ? 2 * i + 1 : 2 * i;
+        if (sidx >= nsteps) return;
+        const bool fwd = PH == 4 || PH == 5;
+        j = fwd ? (top ? sidx : M - 1 - sidx) : (top ? p - 1 - sidx : p + 1 + sidx);
+        jm = fwd ? (top ? sidx - 1 : M - sidx) : (top ? p - sidx : p + sidx);
+        prod = !(PH == 5 && sidx == 0);
+    }
+    const int slot_of = PH == 2 ? j : (PH == 1 || PH == 3) ? 3 * M + j : (PH <= 5 ? M + j : 2 * M + j);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t < 16) {
+        const int ns = nslots_dev ? *nslots_dev : nslots;
+        const int slot = tile * 16 + t;
+        const int rr = slot < ns ? (slots ? slots[slot] : slot) : -1;
+        const bool on = rr >= 0 && (!active || active[rr]);
+        s_rr[t] = on ? rr : -1;
+        s_in[t] = on ? (inst ? inst[rr] : 0) : -1;
+    }
+    __syncthreads();
+    int done = 0;
+    for (;;) {
+        // the next model of the tile (the same decision in every thread)
+        int pm = -1;
+        for (int q = 0; q < 16; ++q)
+            if (s_rr[q] >= 0 && !((done >> q) & 1)) {
+                pm = s_in[q];
+                break;
+            }
+        if (pm < 0) break;
+        int mask = 0;
+        for (int q = 0; q < 16; ++q)
+            if (s_rr[q] >= 0 && s_in[q] == pm) mask |= 1 << q;
+        done |= mask;
+        // gather W^T into LDS
+        if (prod) {
+            for (int e2 = t; e2 < 16 * m4; e2 += CMM_NT) {
+                const int n = e2 / m4, c = e2 - n * m4;
+                float2 w = make_float2(0.f, 0.f);
+                const int rr = s_rr[n];
+                if (((mask >> n) & 1) && c < m) {
+                    const size_t rb = (size_t)rr * mm;
+                    if (PH == 1) {
+                        w = bcs[rb + (size_t)(2 * j + 1) * m + c];
+                    } else if (PH == 2) {
+                        w = bcs[rb + (size_t)(2 * j) * m + c];
+                        float2 a = make_float2(0.f, 0.f);
+                        if (j >= 1) a = tw[((size_t)rr * Mo + j - 1) * m + c];
+                        if (j < Mo) a = cadd(a, tw[((size_t)rr * Mo + j) * m + c]);
+                        w = cadd(w, cscale(a, cf));
+                    } else if (PH == 3) {
+                        float2 a = x[rb + (size_t)(2 * j) * m + c];
+                        if (2 * j + 2 <= m - 1) a = cadd(a, x[rb + (size_t)(2 * j + 2) * m + c]);
+                        w = cadd(bcs[rb + (size_t)(2 * j + 1) * m + c], cscale(a, cf));
+                    } else if (PH == 4) {
+                        w = gw[((size_t)rr * M + jm) * m + c];
+                    } else {
+                        w = x[rb + (size_t)(2 * jm) * m + c];
+                    }
+                }
+                s_w[n * ldw + c] = w;
+            }
+            __syncthreads();
+        }
+        const float2* S = F + ((size_t)pm * 4 * M + slot_of) * mm;
+        const __amdgpu_buffer_rsrc_t rs = [&] {
+            const unsigned long long a = (unsigned long long)S;
+            const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+            const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+            return __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), (short)0,
+                                                     (int)(mm * sizeof(float2)), 0x00020000);
+        }();
+        const int kl = lane >> 4, cl = lane & 15;
+        for (int cb = wave * 16; cb < m; cb += CMM_NT / 4) {
+            cmm_f4 accr = (cmm_f4){0.f, 0.f, 0.f, 0.f}, acci = (cmm_f4){0.f, 0.f, 0.f, 0.f};
+            if (prod) {
+                // S fragment at k-step k: S[4 k + kl][cb + cl], row and column clamped into
+                // the block (rows >= m meet zeros of W; columns >= m are not stored)
+                const int col = min(cb + cl, m - 1);
+                auto sfrag = [&](int k) {
+                    const int off = (min(4 * k + kl, m - 1) * m + col) * (int)sizeof(float2);
+                    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+                };
+                // branch-free pipeline: every k-step refills its buffer CMM_D steps ahead
+                // (past the end the clamped row is read and not used)
+                float2 bq[CMM_D];
+#pragma unroll
+                for (int d = 0; d < CMM_D; ++d) {
+                    bq[d] = sfrag(d);
+                    __builtin_amdgcn_sched_barrier(0);  // issued in order of use
+                }
+                for (int ks = 0; ks < nks; ks += CMM_D) {
+#pragma unroll
+                    for (int d = 0; d < CMM_D; ++d) {
+                        const int k = ks + d;
+                        const float2 a = s_w[cl * ldw + 4 * k + kl];
+                        const float2 b = bq[d];
+                        bq[d] = sfrag(k + CMM_D);
+                        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accr, 0, 0, 0);
+                        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, accr, 0, 0, 0);
+                        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, acci, 0, 0, 0);
+                        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, acci, 0, 0, 0);
+                        // keep each refill in its k-step: the wait before a use is then
+                        // for the load issued CMM_D steps earlier only
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+            // lane holds rows (right-hand sides) 4 kl + v of column cb + cl
+            const int r = cb + cl;
+            if (r < m) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int n = 4 * kl + v;
+                    if (!((mask >> n) & 1)) continue;
+                    const int rr = s_rr[n];
+                    const float2 y = make_float2(accr[v], acci[v]);
+                    if (PH == 1) {
+                        tw[((size_t)rr * Mo + j) * m + r] = y;
+                    } else if (PH == 2) {
+                        gw[((size_t)rr * M + j) * m + r] = y;
+                    } else if (PH == 3) {
+                        x[(size_t)rr * mm + (size_t)(2 * j + 1) * m + r] = y;
+                    } else if (PH == 4) {
+                        hw[((size_t)rr * M + j) * m + r] = cadd(gw[((size_t)rr * M + j) * m + r], y);
+                    } else if (PH == 5) {
+                        const float2 v5 = cadd(gw[((size_t)rr * M + j) * m + r], y);
+                        x[(size_t)rr * mm + (size_t)(2 * j) * m + r] = v5;
+                        if (sidx == nsteps - 1) ends[((size_t)rr * 2 + e) * m + r] = v5;
+                    } else if (PH == 6) {
+                        hw[((size_t)rr * M + j) * m + r] = cadd(x[(size_t)rr * mm + (size_t)(2 * j) * m + r], y);
+                    } else {
+                        const size_t o = (size_t)rr * mm + (size_t)(2 * j) * m + r;
+                        x[o] = cadd(x[o], y);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // s_w is rewritten by the next pass
+    }
+}
+
+template <int PH>
+static hh_status launch_cr_mm_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
+                                const int* slots, int nslots, const int* nslots_dev, int m, float c,
+                                const int* active, const CoarseWork& cw) {
+    hh_ctx* ctx = md->ctx;
+    static unsigned attr_devices = 0;
+    if (!(attr_devices & (1u << ctx->device))) {
+        const size_t most = cmm_lds_bytes(CS_MAXM);
+        if (most > 65536)
+            HH_HIP(hipFuncSetAttribute((const void*)k_cr_mm<PH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)most));
+        attr_devices |= 1u << ctx->device;
+    }
+    const int M = (m + 1) / 2, Mo = m / 2, p = M / 2;
+    int rows;
+    if (PH <= 3) rows = PH == 2 ? M : Mo;
+    else rows = 2 * ((std::max(p, M - 1 - p) + 1) / 2);
+    if (rows == 0 || nslots == 0) return HH_OK;
+    const int ntiles = (nslots + 15) / 16;
+    hipLaunchKernelGGL(k_cr_mm<PH>, dim3(ntiles * ((rows + 7) / 8) * 8), dim3(CMM_NT), cmm_lds_bytes(m), ctx->stream,
+                       bcs, x, cw.tw, cw.gw, cw.hw, ends, md->coarseQT.as<float2>(), inst, slots, nslots, nslots_dev,
+                       m, c, active, rows, ntiles);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+static hh_status launch_cr_mm(hh_model* md, int PH, const float2* bcs, float2* x, float2* ends, const int* inst,
+                              const int* slots, int nslots, const int* nslots_dev, int m, float c,
+                              const int* active, const CoarseWork& cw) {
+    switch (PH) {
+        case 1: return launch_cr_mm_t<1>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 2: return launch_cr_mm_t<2>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 3: return launch_cr_mm_t<3>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 4: return launch_cr_mm_t<4>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 5: return launch_cr_mm_t<5>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 6: return launch_cr_mm_t<6>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        default: return launch_cr_mm_t<7>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+    }
+}
+
 // a row-parallel phase of the paired chains (PH 4..7, k_cr_pp)
 static hh_status launch_cr_pp(hh_model* md, int PH, float2* x, float2* ends, const int* inst, const int* slots,
                               int nslots, const int* nslots_dev, int m, const int* active, const CoarseWork& cw) {
+    if (md->coarse_mm && nslots > CS_RMAX)
+        return launch_cr_mm(md, PH, nullptr, x, ends, inst, slots, nslots, nslots_dev, m, 0.f, active, cw);
     constexpr int RP = CS_RMAX;
     hh_ctx* ctx = md->ctx;
     static unsigned attr_devices = 0;
