@@ -90,11 +90,13 @@ typedef struct {
     int coarse_reduce;     /* coarsest exact solve: 1 eliminates the odd grid rows by their
                               tridiagonal inverses first (one level of cyclic reduction) and
                               runs the two-ended block elimination on the even rows (half the
-                              sequential chain, about twice the factor memory); 2 (default) does
-                              the same and runs each elimination chain two steps at a time with
-                              precomputed two-step factors, the skipped steps following in
-                              parallel (half the sequential steps again, 5/4 of the factor
-                              memory of 1); 0 runs the two-ended elimination on all grid rows */
+                              sequential chain, about twice the factor memory); k = 2, 3, 4
+                              (default 4) does the same and runs each elimination chain 2^(k-1)
+                              steps at a time with precomputed multi-step factors, the skipped
+                              steps following in row-parallel phases (a chain 2^(k-1) times
+                              shorter for 4 (k-1) parallel phases; about 1/4 + 1/8 + ... more
+                              factor memory than 1); 0 runs the two-ended elimination on all
+                              grid rows */
     int coarse_iters;      /* 0 (default): the coarsest level is solved exactly (above).  k in
                               1..16: instead k steps of GMRES on the coarsest shifted operator,
                               right-preconditioned by its diagonal (Jacobi), from zero, without

@@ -146,7 +146,7 @@ void hh_model_desc_default(hh_model_desc* d) {
     d->nu_pre = 1;
     d->nu_post = 1;
     d->jacobi_w = 0.8;
-    d->coarse_reduce = 2;
+    d->coarse_reduce = 4;
     d->coarse_iters = 0;
 }
 
@@ -160,7 +160,7 @@ hh_status hh_model_create(hh_ctx* ctx, const hh_model_desc* d, int ninst, const 
     HH_ARG((d->n >> (d->levels - 1)) <= 1024, "coarsest grid at most 1024 x 1024");
     HH_ARG(d->omega >= 0.0 && d->abl_width >= 0 && d->sl_beta > 0.0, "omega >= 0, abl_width >= 0, sl_beta > 0");
     HH_ARG(d->coarse_iters >= 0 && d->coarse_iters <= coarse_gmres_max_iters(), "coarse_iters in 0..16");
-    HH_ARG(d->coarse_reduce >= 0 && d->coarse_reduce <= 2, "coarse_reduce in 0..2");
+    HH_ARG(d->coarse_reduce >= 0 && d->coarse_reduce <= 4, "coarse_reduce in 0..4");
     HH_HIP(hipSetDevice(ctx->device));
     hh_model* m = new (std::nothrow) hh_model();
     if (!m) {

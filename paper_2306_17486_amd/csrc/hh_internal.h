@@ -150,10 +150,9 @@ struct hh_model {
     int coarse_R_forced = 0;                // fixed variant (R, or 100 RS + R for the split solve); 0: autotuned
     hh::Buf coarse_err;                     // device int: a split-solve wait timed out
     bool cr1 = false;                       // coarseQT holds the reduced factorisation (one level of cyclic reduction)
-    bool cr_pair = false;                   // cr1 with paired chains: coarseP2 holds the two-step chain factors
+    int cr_depth = 0;                       // cr1 chains run 2^depth steps at a time (coarse_reduce - 1)
     bool coarse_mm = true;                  // row-parallel phases of the reduced solve on the matrix cores
-    hh::Buf coarseP2;                       // [ninst][2 ceil(ceil(m/2)/2)][m][m]: P_j P_prev at (j >> 1), R_j R_prev
-                                            // at ceil(ceil(m/2)/2) + (j >> 1), transposed complex singles
+    hh::Buf coarseFL;                       // the multi-step chain factors of levels 1..depth (hh::cr_fl_block)
 };
 
 // ---------------------------------------------------------------------------
@@ -174,6 +173,25 @@ __host__ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
 }
 // a / b with one hardware reciprocal of |b|^2 (about 1 ulp; the relaxation
 // sweeps divide by the shifted diagonal at every point and sweep)
+// ---- multi-step chains of the reduced coarse solve ----
+// The two chains of each end run over chain indices s = 0 .. nsteps-1 (top:
+// p of them, bottom: M-1-p, M = ceil(m/2), p = M/2).  Level l >= 1 keeps the
+// indices 2^l (i + 1) - 1, i < nsteps >> l, whose step factors are the products
+// A_l(i) = A_{l-1}(2i+1) A_{l-1}(2i) (forward, i >= 1) and B_l(i) = B_{l-1}(2i+1)
+// B_{l-1}(2i) (backward), stored per instance as blocks
+// [level][dir (0 fwd, 1 bwd)][end][i] with Q_l = (max(p, M-1-p) >> l) + 1 slots per end.
+__host__ __device__ __forceinline__ int cr_qlev(int M, int p, int l) {
+    return ((p > M - 1 - p ? p : M - 1 - p) >> l) + 1;
+}
+__host__ __device__ __forceinline__ size_t cr_fl_off(int M, int p, int l) {  // first block of level l
+    size_t o = 0;
+    for (int k = 1; k < l; ++k) o += 4 * (size_t)cr_qlev(M, p, k);
+    return o;
+}
+__host__ __device__ __forceinline__ size_t cr_fl_block(int M, int p, int l, int dir, int e, int i) {
+    return cr_fl_off(M, p, l) + (size_t)(dir * 2 + e) * cr_qlev(M, p, l) + i;
+}
+
 __device__ __forceinline__ float2 cdiv_rcp(float2 a, float2 b) {
     const float inv = __builtin_amdgcn_rcpf(b.x * b.x + b.y * b.y);
     return make_float2((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);

@@ -780,39 +780,69 @@ __global__ void __launch_bounds__(CS_NT) k_cr_par(const float2* __restrict__ bcs
     }
 }
 
-// The steps of one end's chains.  Plain: every chain index, factors P_j (slot
-// M + j) and R_j (slot 2M + j).  Paired (F2 given): the odd chain indices only,
-// with the two-step factors P(s) P(s-1) at F2 slot j >> 1 and R(t) R(t-1) at
-// H + (j >> 1) (built in setup.hip); forward index s sits at reduced row s (top)
-// or M-1-s (bottom), backward index t at p-1-t or p+1+t.
+// The steps of one end's chains at level lev (0: every chain index, factors P_j
+// at slot M + j and R_j at slot 2M + j; lev >= 1: the indices 2^lev (i+1) - 1
+// with the multi-step factors of FL, built in setup.hip).  Forward index s sits
+// at reduced row s (top) or M-1-s (bottom), backward index t at p-1-t or p+1+t.
 struct CrSteps {
     const float2* Fi;
-    const float2* F2i;
+    const float2* FLi;
     size_t mm;
-    int M, p, H, nsteps, n;
-    bool top, pair;
-    __device__ CrSteps(const float2* F, const float2* F2, int ii, int m, bool top_) {
+    int M, p, nsteps, n, lev, e;
+    bool top;
+    __device__ CrSteps(const float2* F, const float2* FL, int depth, int ii, int m, bool top_) {
         M = crM(m);
         p = M / 2;
-        H = (M + 1) / 2;
         mm = (size_t)m * m;
         top = top_;
-        pair = F2 != nullptr;
+        e = top ? 0 : 1;
+        lev = FL ? depth : 0;
         Fi = F + (size_t)ii * 4 * M * mm;
-        F2i = pair ? F2 + (size_t)ii * 2 * H * mm : nullptr;
+        FLi = FL ? FL + (size_t)ii * cr_fl_off(M, p, depth + 1) * mm : nullptr;
         nsteps = top ? p : (M - 1 - p);
-        n = pair ? nsteps / 2 : nsteps;
+        n = nsteps >> lev;
     }
-    __device__ int index(int i) const { return pair ? 2 * i + 1 : i; }
+    __device__ int index(int i) const { return ((i + 1) << lev) - 1; }
     __device__ int fwd_row(int i) const { return top ? index(i) : M - 1 - index(i); }
     __device__ int bwd_row(int i) const { return top ? p - 1 - index(i) : p + 1 + index(i); }
     __device__ const float2* fwd_mat(int i) const {
-        const int j = fwd_row(i);
-        return pair ? F2i + (size_t)(j >> 1) * mm : Fi + (size_t)(M + j) * mm;
+        return lev ? FLi + cr_fl_block(M, p, lev, 0, e, i) * mm : Fi + (size_t)(M + fwd_row(i)) * mm;
     }
     __device__ const float2* bwd_mat(int i) const {
-        const int j = bwd_row(i);
-        return pair ? F2i + (size_t)(H + (j >> 1)) * mm : Fi + (size_t)(2 * M + j) * mm;
+        return lev ? FLi + cr_fl_block(M, p, lev, 1, e, i) * mm : Fi + (size_t)(2 * M + bwd_row(i)) * mm;
+    }
+};
+
+// One work item of a multi-step phase at level lev >= 1 (kind 4: forward
+// combine, 5: forward fill, 6: backward combine, 7: backward fill), on chain
+// index i of level lev-1 (odd for the combines, even for the fills):
+//   combine: hw[row] = src(row) + A(i) src(prow)        (the next level's vectors)
+//   fill:    x[row]  = src(row) + A(i) x[prow]          (no product for the forward i = 0)
+// with src = g (forward) or y in x (backward) at level 0, hw above; A the level
+// lev-1 factor of index i; prow the row of i-1 (x_p's row p for the backward i = 0).
+// Item yidx = end * H + k, H = ((max(p, M-1-p) >> (lev-1)) + 1) / 2.
+struct CrItem {
+    bool valid, prod, fwd, last;
+    int e, row, prow;
+    const float2* mat;
+    __device__ CrItem(int kind, int lev, int depth, int yidx, int H, const float2* F, const float2* FL, int ii,
+                      int m) {
+        const int M = crM(m), p = M / 2;
+        const size_t mm = (size_t)m * m;
+        e = yidx / H;
+        const int k = yidx - e * H;
+        const int nsteps = e == 0 ? p : M - 1 - p;
+        const int i = (kind == 4 || kind == 6) ? 2 * k + 1 : 2 * k;
+        valid = e < 2 && i < (nsteps >> (lev - 1));
+        fwd = kind <= 5;
+        const int si = ((i + 1) << (lev - 1)) - 1, sp = (i << (lev - 1)) - 1;
+        auto rowf = [&](int s) { return fwd ? (e == 0 ? s : M - 1 - s) : (e == 0 ? p - 1 - s : p + 1 + s); };
+        row = rowf(si);
+        prow = i >= 1 ? rowf(sp) : (fwd ? 0 : p);
+        prod = !(kind == 5 && i == 0);
+        last = fwd && si == nsteps - 1;
+        if (lev == 1) mat = F + ((size_t)ii * 4 * M + (fwd ? M : 2 * M) + row) * mm;
+        else mat = FL + ((size_t)ii * cr_fl_off(M, p, depth + 1) + cr_fl_block(M, p, lev - 1, fwd ? 0 : 1, e, i)) * mm;
     }
 };
 
@@ -822,8 +852,8 @@ struct CrSteps {
 template <int R, bool PF>
 __global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
                                                   float2* __restrict__ x, float2* __restrict__ ends,
-                                                  const float2* __restrict__ F, const float2* __restrict__ F2,
-                                                  const int* __restrict__ inst, const int* __restrict__ slots,
+                                                  const float2* __restrict__ F, const float2* __restrict__ FL,
+                                                  int depth, const int* __restrict__ inst, const int* __restrict__ slots,
                                                   int nslots, const int* __restrict__ nslots_dev, int m,
                                                   const int* __restrict__ active) {
     extern __shared__ float2 s_lds[];
@@ -832,10 +862,10 @@ __global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw,
     const bool top = blockIdx.y == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
     if (!g.any) return;
-    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const CrSteps cs(F, FL, depth, inst ? inst[g.r0] : 0, m, top);
     const int M = cs.M;
     const size_t mm = cs.mm;
-    const float2* src = cs.pair ? hw : gw;
+    const float2* src = cs.lev ? hw : gw;
     const CoarseMV<R> mv(m);
     constexpr bool pf = PF;
     float2 qa[CoarseMV<R>::PCH], qb[CoarseMV<R>::PCH];
@@ -878,8 +908,8 @@ __global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw,
 template <int R, bool PF>
 __global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
                                                   float2* __restrict__ x, const float2* __restrict__ ends,
-                                                  const float2* __restrict__ F, const float2* __restrict__ F2,
-                                                  const int* __restrict__ inst, const int* __restrict__ slots,
+                                                  const float2* __restrict__ F, const float2* __restrict__ FL,
+                                                  int depth, const int* __restrict__ inst, const int* __restrict__ slots,
                                                   int nslots, const int* __restrict__ nslots_dev, int m,
                                                   const int* __restrict__ active) {
     extern __shared__ float2 s_lds[];
@@ -888,7 +918,7 @@ __global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw,
     const bool top = blockIdx.y == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
     if (!g.any) return;
-    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const CrSteps cs(F, FL, depth, inst ? inst[g.r0] : 0, m, top);
     const int M = cs.M, p = cs.p;
     const size_t mm = cs.mm;
     const float2* Fi = cs.Fi;
@@ -937,7 +967,7 @@ __global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw,
         for (int q = 0; q < R; ++q) {
             yv[q] = make_float2(0.f, 0.f);
             if (mv.owner() && g.on[q])
-                yv[q] = cs.pair ? hw[((size_t)g.rr[q] * M + j) * m + mv.row]
+                yv[q] = cs.lev ? hw[((size_t)g.rr[q] * M + j) * m + mv.row]
                                 : x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + mv.row];
         }
         float2 out[R];
@@ -960,38 +990,31 @@ __global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw,
     }
 }
 
-// Row-parallel phases of the paired chains (blockIdx.y = end * H2 + i; chain
-// index 2i + 1 for PH 4 and 6, 2i for PH 5 and 7; rows as in CrSteps):
-// PH 4: h(s) = g(s) + P(s) g(s-1)                      -> hw      (odd s)
-// PH 5: y(s) = g(s) + P(s) y(s-1), y(0) = g(0)         -> x row   (even s; ends if s is the last)
-// PH 6: k(t) = y(t) + R(t) y(t-1)                      -> hw      (odd t)
-// PH 7: x(t) = y(t) + R(t) x(t-1), x(-1) = x_p         -> x row   (even t)
+// The multi-step phases on the vector ALUs (kind PH 4..7 at level lev, as in
+// CrItem); blockIdx.x = right-hand-side group, blockIdx.y = item.
 template <int R, int PH>
 __global__ void __launch_bounds__(CS_NT) k_cr_pp(const float2* __restrict__ gw, float2* __restrict__ hw,
                                                  float2* __restrict__ x, float2* __restrict__ ends,
-                                                 const float2* __restrict__ F, const int* __restrict__ inst,
+                                                 const float2* __restrict__ F, const float2* __restrict__ FL,
+                                                 int lev, int depth, int H, const int* __restrict__ inst,
                                                  const int* __restrict__ slots, int nslots,
                                                  const int* __restrict__ nslots_dev, int m,
                                                  const int* __restrict__ active) {
     extern __shared__ float2 s_lds[];
     float2* s_v = s_lds;
     float2* s_part = s_lds + R * m;
-    const int M = crM(m), p = M / 2;
-    const int H2 = gridDim.y / 2;
-    const int e = blockIdx.y / H2, i = blockIdx.y - e * H2;
-    const bool top = e == 0;
-    const int nsteps = top ? p : (M - 1 - p);
-    const int s = (PH == 4 || PH == 6) ? 2 * i + 1 : 2 * i;
-    if (s >= nsteps) return;
+    const int M = crM(m);
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, blockIdx.x);
     if (!g.any) return;
+    const CrItem it(PH, lev, depth, blockIdx.y, H, F, FL, inst ? inst[g.r0] : 0, m);
+    if (!it.valid) return;
     const size_t mm = (size_t)m * m;
-    const float2* Fi = F + (size_t)(inst ? inst[g.r0] : 0) * 4 * M * mm;
-    const bool fwd = PH == 4 || PH == 5;
-    const int j = fwd ? (top ? s : M - 1 - s) : (top ? p - 1 - s : p + 1 + s);
-    const int jm = fwd ? (top ? s - 1 : M - s) : (top ? p - s : p + s);  // index s - 1 (x_p's row for t = 0)
-    const bool prod = !(PH == 5 && s == 0);
-    const float2* Mat = Fi + (size_t)((fwd ? M : 2 * M) + j) * mm;
+    constexpr bool combine = PH == 4 || PH == 6;
+    // the level's source vectors: g (forward) or y in x (backward) at level 0, hw above
+    auto src = [&](int rr, int row, int r) -> float2 {
+        if (lev > 1) return hw[((size_t)rr * M + row) * m + r];
+        return it.fwd ? gw[((size_t)rr * M + row) * m + r] : x[(size_t)rr * mm + (size_t)(2 * row) * m + r];
+    };
     const CoarseMV<R> mv(m);
     float2 base[R];
     if (mv.owner()) {
@@ -1001,10 +1024,9 @@ __global__ void __launch_bounds__(CS_NT) k_cr_pp(const float2* __restrict__ gw, 
             float2 w = make_float2(0.f, 0.f);
             base[q] = make_float2(0.f, 0.f);
             if (g.on[q]) {
-                const size_t rb = (size_t)g.rr[q] * mm;
-                if (fwd) base[q] = gw[((size_t)g.rr[q] * M + j) * m + r];
-                else base[q] = x[rb + (size_t)(2 * j) * m + r];
-                if (prod) w = PH == 4 ? gw[((size_t)g.rr[q] * M + jm) * m + r] : x[rb + (size_t)(2 * jm) * m + r];
+                base[q] = src(g.rr[q], it.row, r);
+                if (it.prod)
+                    w = combine ? src(g.rr[q], it.prow, r) : x[(size_t)g.rr[q] * mm + (size_t)(2 * it.prow) * m + r];
             }
             s_v[q * m + r] = w;
         }
@@ -1012,9 +1034,9 @@ __global__ void __launch_bounds__(CS_NT) k_cr_pp(const float2* __restrict__ gw, 
     float2 out[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) out[q] = make_float2(0.f, 0.f);
-    if (prod) {
+    if (it.prod) {
         __syncthreads();
-        mv.apply(Mat, s_v, s_part, out);
+        mv.apply(it.mat, s_v, s_part, out);
     }
     if (mv.owner()) {
         const int r = mv.row;
@@ -1022,11 +1044,11 @@ __global__ void __launch_bounds__(CS_NT) k_cr_pp(const float2* __restrict__ gw, 
         for (int q = 0; q < R; ++q) {
             if (!g.on[q]) continue;
             const float2 v = cadd(base[q], out[q]);
-            if (PH == 4 || PH == 6) {
-                hw[((size_t)g.rr[q] * M + j) * m + r] = v;
+            if (combine) {
+                hw[((size_t)g.rr[q] * M + it.row) * m + r] = v;
             } else {
-                x[(size_t)g.rr[q] * mm + (size_t)(2 * j) * m + r] = v;
-                if (PH == 5 && s == nsteps - 1) ends[((size_t)g.rr[q] * 2 + e) * m + r] = v;
+                x[(size_t)g.rr[q] * mm + (size_t)(2 * it.row) * m + r] = v;
+                if (it.last) ends[((size_t)g.rr[q] * 2 + it.e) * m + r] = v;
             }
         }
     }
@@ -1286,8 +1308,9 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
 template <int R, int RS>
 __global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
                                                          float2* __restrict__ x, float2* __restrict__ ends,
-                                                         const float2* __restrict__ F, const float2* __restrict__ F2,
-                                                         const int* __restrict__ inst, const int* __restrict__ slots,
+                                                         const float2* __restrict__ F, const float2* __restrict__ FL,
+                                                         int depth, const int* __restrict__ inst,
+                                                         const int* __restrict__ slots,
                                                          int nslots, const int* __restrict__ nslots_dev, int m,
                                                          const int* __restrict__ active, SplitGeom geo,
                                                          float2* __restrict__ xch, int* __restrict__ cnt,
@@ -1300,10 +1323,10 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restric
     const bool top = (unit & 1) == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
     if (!g.any) return;  // the same for every slice of the unit
-    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const CrSteps cs(F, FL, depth, inst ? inst[g.r0] : 0, m, top);
     const int M = cs.M;
     const size_t mm = cs.mm;
-    const float2* src = cs.pair ? hw : gw;
+    const float2* src = cs.lev ? hw : gw;
     const int row0 = slice * RS;
     const int row = row0 + threadIdx.x;
     float2 qr[CSP_CMAX];
@@ -1341,8 +1364,9 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_fwd(const float2* __restric
 template <int R, int RS>
 __global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
                                                          float2* __restrict__ x, const float2* __restrict__ ends,
-                                                         const float2* __restrict__ F, const float2* __restrict__ F2,
-                                                         const int* __restrict__ inst, const int* __restrict__ slots,
+                                                         const float2* __restrict__ F, const float2* __restrict__ FL,
+                                                         int depth, const int* __restrict__ inst,
+                                                         const int* __restrict__ slots,
                                                          int nslots, const int* __restrict__ nslots_dev, int m,
                                                          const int* __restrict__ active, SplitGeom geo,
                                                          float2* __restrict__ xch, int* __restrict__ cnt,
@@ -1355,7 +1379,7 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restric
     const bool top = (unit & 1) == 0;
     const CoarseSlots<R> g(slots, nslots, nslots_dev, active, unit >> 1);
     if (!g.any) return;
-    const CrSteps cs(F, F2, inst ? inst[g.r0] : 0, m, top);
+    const CrSteps cs(F, FL, depth, inst ? inst[g.r0] : 0, m, top);
     const int M = cs.M, p = cs.p;
     const size_t mm = cs.mm;
     const float2* Fi = cs.Fi;
@@ -1410,7 +1434,7 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restric
                 float2 v = make_float2(0.f, 0.f);
                 if (g.on[q]) {
                     const size_t o = (size_t)g.rr[q] * mm + (size_t)(2 * j) * m + row;
-                    v = cadd(cs.pair ? hw[((size_t)g.rr[q] * M + j) * m + row] : x[o], out[q]);
+                    v = cadd(cs.lev ? hw[((size_t)g.rr[q] * M + j) * m + row] : x[o], out[q]);
                     x[o] = v;
                 }
                 xch_at<R>(xch, unit, (s + 1) & 1, q, m)[row] = v;
@@ -1617,15 +1641,15 @@ static hh_status launch_split_t(hh_model* md, const float2* bcs, float2* x, floa
 // The row-parallel phases serve CS_RMAX right-hand sides per workgroup whatever
 // the chains use: their blocks are then read CS_RMAX times fewer (slot groups of
 // CS_RMAX never mix models: the grouping order is padded per model to CS_RMAX).
-static hh_status launch_cr_mm(hh_model* md, int PH, const float2* bcs, float2* x, float2* ends, const int* inst,
-                              const int* slots, int nslots, const int* nslots_dev, int m, float c,
+static hh_status launch_cr_mm(hh_model* md, int PH, int lev, const float2* bcs, float2* x, float2* ends,
+                              const int* inst, const int* slots, int nslots, const int* nslots_dev, int m, float c,
                               const int* active, const CoarseWork& cw);
 
 static hh_status launch_cr_par(hh_model* md, int PH, const float2* bcs, float2* x, const int* inst, const int* slots,
                                int nslots, const int* nslots_dev, int m, float c, const int* active,
                                const CoarseWork& cw) {
     if (md->coarse_mm && nslots > CS_RMAX)
-        return launch_cr_mm(md, PH, bcs, x, nullptr, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        return launch_cr_mm(md, PH, 0, bcs, x, nullptr, inst, slots, nslots, nslots_dev, m, c, active, cw);
     constexpr int RP = CS_RMAX;
     hh_ctx* ctx = md->ctx;
     static unsigned attr_devices = 0;
@@ -1684,7 +1708,8 @@ template <int PH>
 __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs, float2* __restrict__ x,
                                                   float2* __restrict__ tw, float2* __restrict__ gw,
                                                   float2* __restrict__ hw, float2* __restrict__ ends,
-                                                  const float2* __restrict__ F, const int* __restrict__ inst,
+                                                  const float2* __restrict__ F, const float2* __restrict__ FL,
+                                                  int lev, int depth, const int* __restrict__ inst,
                                                   const int* __restrict__ slots, int nslots,
                                                   const int* __restrict__ nslots_dev, int m, float cf,
                                                   const int* __restrict__ active, int rows, int ntiles) {
@@ -1698,25 +1723,19 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
     const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
     const int row = (kk / ntiles) * 8 + xcd, tile = kk % ntiles;
     if (row >= rows) return;
-    // the block row (and, for the paired phases, its end and chain index)
-    int j, jm = 0, e = 0, sidx = 0, nsteps = 0;
+    // the block row (the reduced row for PH 1..3, the multi-step item for PH 4..7)
+    int j, jm = 0;
     bool prod = true;
+    const CrItem it0(PH >= 4 ? PH : 4, lev > 0 ? lev : 1, depth, row, rows / 2, F, FL, 0, m);
     if (PH <= 3) {
         j = row;
     } else {
-        const int H2 = rows / 2;
-        e = row / H2;
-        const int i = row - e * H2;
-        const bool top = e == 0;
-        nsteps = top ? p : (M - 1 - p);
-        sidx = (PH == 4 || PH == 6) ? 2 * i + 1 : 2 * i;
-        if (sidx >= nsteps) return;
-        const bool fwd = PH == 4 || PH == 5;
-        j = fwd ? (top ? sidx : M - 1 - sidx) : (top ? p - 1 - sidx : p + 1 + sidx);
-        jm = fwd ? (top ? sidx - 1 : M - sidx) : (top ? p - sidx : p + sidx);
-        prod = !(PH == 5 && sidx == 0);
+        if (!it0.valid) return;
+        j = it0.row;
+        jm = it0.prow;
+        prod = it0.prod;
     }
-    const int slot_of = PH == 2 ? j : (PH == 1 || PH == 3) ? 3 * M + j : (PH <= 5 ? M + j : 2 * M + j);
+    const int slot_of = PH == 2 ? j : 3 * M + j;  // PH 1..3
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     if (t < 16) {
         const int ns = nslots_dev ? *nslots_dev : nslots;
@@ -1761,9 +1780,10 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
                         float2 a = x[rb + (size_t)(2 * j) * m + c];
                         if (2 * j + 2 <= m - 1) a = cadd(a, x[rb + (size_t)(2 * j + 2) * m + c]);
                         w = cadd(bcs[rb + (size_t)(2 * j + 1) * m + c], cscale(a, cf));
-                    } else if (PH == 4) {
-                        w = gw[((size_t)rr * M + jm) * m + c];
-                    } else {
+                    } else if (PH == 4 || PH == 6) {  // the previous index's source vector
+                        w = lev > 1 ? hw[((size_t)rr * M + jm) * m + c]
+                                    : (PH == 4 ? gw[((size_t)rr * M + jm) * m + c] : x[rb + (size_t)(2 * jm) * m + c]);
+                    } else {  // fills: the previous index's result
                         w = x[rb + (size_t)(2 * jm) * m + c];
                     }
                 }
@@ -1771,7 +1791,8 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
             }
             __syncthreads();
         }
-        const float2* S = F + ((size_t)pm * 4 * M + slot_of) * mm;
+        const float2* S = PH <= 3 ? F + ((size_t)pm * 4 * M + slot_of) * mm
+                                  : CrItem(PH, lev, depth, row, rows / 2, F, FL, pm, m).mat;
         const __amdgpu_buffer_rsrc_t rs = [&] {
             const unsigned long long a = (unsigned long long)S;
             const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
@@ -1830,17 +1851,18 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
                         gw[((size_t)rr * M + j) * m + r] = y;
                     } else if (PH == 3) {
                         x[(size_t)rr * mm + (size_t)(2 * j + 1) * m + r] = y;
-                    } else if (PH == 4) {
-                        hw[((size_t)rr * M + j) * m + r] = cadd(gw[((size_t)rr * M + j) * m + r], y);
-                    } else if (PH == 5) {
-                        const float2 v5 = cadd(gw[((size_t)rr * M + j) * m + r], y);
-                        x[(size_t)rr * mm + (size_t)(2 * j) * m + r] = v5;
-                        if (sidx == nsteps - 1) ends[((size_t)rr * 2 + e) * m + r] = v5;
-                    } else if (PH == 6) {
-                        hw[((size_t)rr * M + j) * m + r] = cadd(x[(size_t)rr * mm + (size_t)(2 * j) * m + r], y);
                     } else {
-                        const size_t o = (size_t)rr * mm + (size_t)(2 * j) * m + r;
-                        x[o] = cadd(x[o], y);
+                        // the source vector of this index: g / y at level 0, hw above
+                        const size_t oh = ((size_t)rr * M + j) * m + r;
+                        const size_t ox = (size_t)rr * mm + (size_t)(2 * j) * m + r;
+                        const float2 b = lev > 1 ? hw[oh] : (PH <= 5 ? gw[oh] : x[ox]);
+                        const float2 v = cadd(b, y);
+                        if (PH == 4 || PH == 6) {
+                            hw[oh] = v;
+                        } else {
+                            x[ox] = v;
+                            if (it0.last) ends[((size_t)rr * 2 + it0.e) * m + r] = v;
+                        }
                     }
                 }
             }
@@ -1849,8 +1871,14 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
     }
 }
 
+// items of a multi-step phase at level lev (per end)
+static inline int cr_phase_half(int m, int lev) {
+    const int M = (m + 1) / 2, p = M / 2;
+    return ((std::max(p, M - 1 - p) >> (lev - 1)) + 1) / 2;
+}
+
 template <int PH>
-static hh_status launch_cr_mm_t(hh_model* md, const float2* bcs, float2* x, float2* ends, const int* inst,
+static hh_status launch_cr_mm_t(hh_model* md, int lev, const float2* bcs, float2* x, float2* ends, const int* inst,
                                 const int* slots, int nslots, const int* nslots_dev, int m, float c,
                                 const int* active, const CoarseWork& cw) {
     hh_ctx* ctx = md->ctx;
@@ -1862,38 +1890,37 @@ static hh_status launch_cr_mm_t(hh_model* md, const float2* bcs, float2* x, floa
                                        (int)most));
         attr_devices |= 1u << ctx->device;
     }
-    const int M = (m + 1) / 2, Mo = m / 2, p = M / 2;
-    int rows;
-    if (PH <= 3) rows = PH == 2 ? M : Mo;
-    else rows = 2 * ((std::max(p, M - 1 - p) + 1) / 2);
+    const int M = (m + 1) / 2, Mo = m / 2;
+    const int rows = PH <= 3 ? (PH == 2 ? M : Mo) : 2 * cr_phase_half(m, lev);
     if (rows == 0 || nslots == 0) return HH_OK;
     const int ntiles = (nslots + 15) / 16;
     hipLaunchKernelGGL(k_cr_mm<PH>, dim3(ntiles * ((rows + 7) / 8) * 8), dim3(CMM_NT), cmm_lds_bytes(m), ctx->stream,
-                       bcs, x, cw.tw, cw.gw, cw.hw, ends, md->coarseQT.as<float2>(), inst, slots, nslots, nslots_dev,
-                       m, c, active, rows, ntiles);
+                       bcs, x, cw.tw, cw.gw, cw.hw, ends, md->coarseQT.as<float2>(), md->coarseFL.as<float2>(), lev,
+                       md->cr_depth, inst, slots, nslots, nslots_dev, m, c, active, rows, ntiles);
     HH_LAUNCH_CHECK();
     return HH_OK;
 }
 
-static hh_status launch_cr_mm(hh_model* md, int PH, const float2* bcs, float2* x, float2* ends, const int* inst,
-                              const int* slots, int nslots, const int* nslots_dev, int m, float c,
+static hh_status launch_cr_mm(hh_model* md, int PH, int lev, const float2* bcs, float2* x, float2* ends,
+                              const int* inst, const int* slots, int nslots, const int* nslots_dev, int m, float c,
                               const int* active, const CoarseWork& cw) {
     switch (PH) {
-        case 1: return launch_cr_mm_t<1>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
-        case 2: return launch_cr_mm_t<2>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
-        case 3: return launch_cr_mm_t<3>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
-        case 4: return launch_cr_mm_t<4>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
-        case 5: return launch_cr_mm_t<5>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
-        case 6: return launch_cr_mm_t<6>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
-        default: return launch_cr_mm_t<7>(md, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 1: return launch_cr_mm_t<1>(md, lev, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 2: return launch_cr_mm_t<2>(md, lev, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 3: return launch_cr_mm_t<3>(md, lev, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 4: return launch_cr_mm_t<4>(md, lev, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 5: return launch_cr_mm_t<5>(md, lev, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        case 6: return launch_cr_mm_t<6>(md, lev, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
+        default: return launch_cr_mm_t<7>(md, lev, bcs, x, ends, inst, slots, nslots, nslots_dev, m, c, active, cw);
     }
 }
 
-// a row-parallel phase of the paired chains (PH 4..7, k_cr_pp)
-static hh_status launch_cr_pp(hh_model* md, int PH, float2* x, float2* ends, const int* inst, const int* slots,
-                              int nslots, const int* nslots_dev, int m, const int* active, const CoarseWork& cw) {
+// a multi-step phase (PH 4..7 at level lev; k_cr_pp, or k_cr_mm above one vector group)
+static hh_status launch_cr_pp(hh_model* md, int PH, int lev, float2* x, float2* ends, const int* inst,
+                              const int* slots, int nslots, const int* nslots_dev, int m, const int* active,
+                              const CoarseWork& cw) {
     if (md->coarse_mm && nslots > CS_RMAX)
-        return launch_cr_mm(md, PH, nullptr, x, ends, inst, slots, nslots, nslots_dev, m, 0.f, active, cw);
+        return launch_cr_mm(md, PH, lev, nullptr, x, ends, inst, slots, nslots, nslots_dev, m, 0.f, active, cw);
     constexpr int RP = CS_RMAX;
     hh_ctx* ctx = md->ctx;
     static unsigned attr_devices = 0;
@@ -1909,32 +1936,44 @@ static hh_status launch_cr_pp(hh_model* md, int PH, float2* x, float2* ends, con
         }
         attr_devices |= 1u << ctx->device;
     }
-    const int M = (m + 1) / 2, p = M / 2;
-    const int H2 = (std::max(p, M - 1 - p) + 1) / 2;
-    if (H2 == 0) return HH_OK;
+    const int H = cr_phase_half(m, lev);
+    if (H == 0 || nslots == 0) return HH_OK;
     const size_t ldsp = coarse_lds_bytes(RP, m);
-    const dim3 grd((nslots + RP - 1) / RP, 2 * H2);
+    const dim3 grd((nslots + RP - 1) / RP, 2 * H);
     const float2* F = md->coarseQT.as<float2>();
+    const float2* FL = md->coarseFL.as<float2>();
+    const int D = md->cr_depth;
     hipStream_t st = ctx->stream;
     switch (PH) {
         case 4:
-            hipLaunchKernelGGL((k_cr_pp<RP, 4>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
-                               nslots, nslots_dev, m, active);
+            hipLaunchKernelGGL((k_cr_pp<RP, 4>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, FL, lev, D, H,
+                               inst, slots, nslots, nslots_dev, m, active);
             break;
         case 5:
-            hipLaunchKernelGGL((k_cr_pp<RP, 5>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
-                               nslots, nslots_dev, m, active);
+            hipLaunchKernelGGL((k_cr_pp<RP, 5>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, FL, lev, D, H,
+                               inst, slots, nslots, nslots_dev, m, active);
             break;
         case 6:
-            hipLaunchKernelGGL((k_cr_pp<RP, 6>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
-                               nslots, nslots_dev, m, active);
+            hipLaunchKernelGGL((k_cr_pp<RP, 6>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, FL, lev, D, H,
+                               inst, slots, nslots, nslots_dev, m, active);
             break;
         default:
-            hipLaunchKernelGGL((k_cr_pp<RP, 7>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, inst, slots,
-                               nslots, nslots_dev, m, active);
+            hipLaunchKernelGGL((k_cr_pp<RP, 7>), grd, dim3(CS_NT), ldsp, st, cw.gw, cw.hw, x, ends, F, FL, lev, D, H,
+                               inst, slots, nslots, nslots_dev, m, active);
             break;
     }
     HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+// the forward combines before the forward chains (levels 1 .. depth), the
+// forward fills after them (depth .. 1); likewise backward around k_cr_bwd
+static hh_status launch_cr_levels(hh_model* md, int PH, float2* x, float2* ends, const int* inst, const int* slots,
+                                  int nslots, const int* nslots_dev, int m, const int* active, const CoarseWork& cw) {
+    const int D = md->cr_depth;
+    const bool up = PH == 4 || PH == 6;
+    for (int k = 0; k < D; ++k)
+        HH_TRY(launch_cr_pp(md, PH, up ? k + 1 : D - k, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     return HH_OK;
 }
 
@@ -1970,27 +2009,26 @@ static hh_status launch_cr_t(hh_model* md, const float2* bcs, float2* x, float2*
     // (the same test as CoarseMV::pf_ok()); not for R = 8, whose registers it would spill
     const int JP = CS_NT / m, jlen = (m + JP - 1) / JP, pch = R == 1 ? 8 : 4;
     const bool pf = R <= 4 && CS_NT % m == 0 && jlen % (2 * pch) == 0;
-    const float2* F2 = md->cr_pair ? md->coarseP2.as<float2>() : nullptr;
-    if (F2) HH_TRY(launch_cr_pp(md, 4, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    const float2* FL = md->cr_depth > 0 ? md->coarseFL.as<float2>() : nullptr;
+    const int D = md->cr_depth;
+    HH_TRY(launch_cr_levels(md, 4, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     if (pf)
-        hipLaunchKernelGGL((k_cr_fwd<R, R <= 4>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+        hipLaunchKernelGGL((k_cr_fwd<R, R <= 4>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, FL, D,
                            inst, slots, nslots, nslots_dev, m, active);
     else
-        hipLaunchKernelGGL((k_cr_fwd<R, false>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+        hipLaunchKernelGGL((k_cr_fwd<R, false>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, FL, D,
                            inst, slots, nslots, nslots_dev, m, active);
     HH_LAUNCH_CHECK();
-    if (F2) {
-        HH_TRY(launch_cr_pp(md, 5, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
-        HH_TRY(launch_cr_pp(md, 6, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
-    }
+    HH_TRY(launch_cr_levels(md, 5, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    HH_TRY(launch_cr_levels(md, 6, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     if (pf)
-        hipLaunchKernelGGL((k_cr_bwd<R, R <= 4>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+        hipLaunchKernelGGL((k_cr_bwd<R, R <= 4>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, FL, D,
                            inst, slots, nslots, nslots_dev, m, active);
     else
-        hipLaunchKernelGGL((k_cr_bwd<R, false>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, F2,
+        hipLaunchKernelGGL((k_cr_bwd<R, false>), dim3(G, 2), dim3(CS_NT), lds, st, cw.gw, cw.hw, x, ends, F, FL, D,
                            inst, slots, nslots, nslots_dev, m, active);
     HH_LAUNCH_CHECK();
-    if (F2) HH_TRY(launch_cr_pp(md, 7, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    HH_TRY(launch_cr_levels(md, 7, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     return launch_cr_par(md, 3, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw);
 }
 
@@ -2026,8 +2064,8 @@ static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, f
     if ((long long)std::min(per_cu_f, per_cu_b) * ctx->num_cus < grid) return HH_OK;  // not offered
     HH_TRY(launch_cr_par(md, 1, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
     HH_TRY(launch_cr_par(md, 2, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw));
-    const float2* F2 = md->cr_pair ? md->coarseP2.as<float2>() : nullptr;
-    if (F2) HH_TRY(launch_cr_pp(md, 4, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    const float2* FL = md->cr_depth > 0 ? md->coarseFL.as<float2>() : nullptr;
+    HH_TRY(launch_cr_levels(md, 4, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     hipLaunchKernelGGL(k_zero_ints, dim3((2 * geo.units + 255) / 256), dim3(256), 0, ctx->stream, cw.cnt,
                        2 * geo.units);
     HH_LAUNCH_CHECK();
@@ -2036,7 +2074,8 @@ static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, f
     float2* a_x = x;
     float2* a_ends = ends;
     const float2* a_F = md->coarseQT.as<float2>();
-    const float2* a_F2 = F2;
+    const float2* a_FL = FL;
+    int a_depth = md->cr_depth;
     const int* a_inst = inst;
     const int* a_slots = slots;
     int a_nslots = nslots;
@@ -2046,8 +2085,8 @@ static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, f
     float2* a_xch = cw.xch;
     int* a_cnt = cw.cnt;
     int* a_err = md->coarse_err.as<int>();
-    void* args[] = {&a_gw, &a_hw, &a_x, &a_ends, &a_F, &a_F2, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
-                    &geo,  &a_xch, &a_cnt, &a_err};
+    void* args[] = {&a_gw,    &a_hw,    &a_x,      &a_ends, &a_F, &a_FL, &a_depth, &a_inst, &a_slots,
+                    &a_nslots, &a_nsd, &a_m, &a_act, &geo, &a_xch, &a_cnt, &a_err};
     const hipError_t le = hipLaunchCooperativeKernel((const void*)k_cr_split_fwd<R, RS>, dim3(grid), dim3(CSP_NT),
                                                      args, (unsigned)lds, ctx->stream);
     if (le == hipErrorCooperativeLaunchTooLarge) {  // the runtime's residency bound is tighter: not offered
@@ -2058,18 +2097,16 @@ static hh_status launch_cr_split_t(hh_model* md, const float2* bcs, float2* x, f
         set_error("cooperative launch failed: %s", hipGetErrorString(le));
         return HH_ERR_HIP;
     }
-    if (F2) {
-        HH_TRY(launch_cr_pp(md, 5, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
-        HH_TRY(launch_cr_pp(md, 6, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
-    }
+    HH_TRY(launch_cr_levels(md, 5, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    HH_TRY(launch_cr_levels(md, 6, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     const float2* b_ends = ends;
     int* b_cnt = cw.cnt + geo.units;
-    void* args_b[] = {&a_gw, &a_hw, &a_x, &b_ends, &a_F, &a_F2, &a_inst, &a_slots, &a_nslots, &a_nsd, &a_m, &a_act,
-                      &geo,  &a_xch, &b_cnt, &a_err};
+    void* args_b[] = {&a_gw,    &a_hw,    &a_x,      &b_ends, &a_F, &a_FL, &a_depth, &a_inst, &a_slots,
+                      &a_nslots, &a_nsd, &a_m, &a_act, &geo, &a_xch, &b_cnt, &a_err};
     HH_HIP(hipLaunchCooperativeKernel((const void*)k_cr_split_bwd<R, RS>, dim3(grid), dim3(CSP_NT), args_b,
                                       (unsigned)lds, ctx->stream));
     *fits = true;
-    if (F2) HH_TRY(launch_cr_pp(md, 7, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
+    HH_TRY(launch_cr_levels(md, 7, x, ends, inst, slots, nslots, nslots_dev, m, active, cw));
     return launch_cr_par(md, 3, bcs, x, inst, slots, nslots, nslots_dev, m, c, active, cw);
 }
 

@@ -373,47 +373,41 @@ __global__ void __launch_bounds__(1024) k_cr_mid(const float2* __restrict__ coef
 }
 
 // ---------------------------------------------------------------------------
-// Paired chains.  Both recurrences of the reduced solve, y(s) = g(s) + P(s) y(s-1)
-// forward and x(t) = y(t) + R(t) x(t-1) backward (chain index s, t from an end;
-// x(-1) = x_p), are run two steps at a time over the odd indices:
+// Multi-step chains.  Both recurrences of the reduced solve, y(s) = g(s) + P(s)
+// y(s-1) forward and x(t) = y(t) + R(t) x(t-1) backward (chain index s, t from an
+// end; x(-1) = x_p), keep their form when only every other index is kept:
 //   y(s) = [g(s) + P(s) g(s-1)] + P(s) P(s-1) y(s-2),   y(1) = g(1) + P(1) g(0),
 //   x(t) = [y(t) + R(t) y(t-1)] + R(t) R(t-1) x(t-2),   x(-1) = x_p,
-// and the even indices follow in parallel, y(s) = g(s) + P(s) y(s-1) (y(0) = g(0))
-// and x(t) = y(t) + R(t) x(t-1): the sequential chain halves for two more
-// row-parallel products per row.  This kernel forms the two-step factors from the
-// stored single-precision P and R (FP64 accumulation).  Rows: forward index s at
-// reduced row s (top) or M-1-s (bottom); backward index t at p-1-t or p+1+t.
-// With slot(X) = X^T row-major, slot(A B) = slot(B) slot(A).
-// blockIdx.x: 32 x 32 output tile, blockIdx.y: product (kind, end, index), z: instance.
+// while the dropped indices follow in parallel, y(s) = g(s) + P(s) y(s-1) and
+// x(t) = y(t) + R(t) x(t-1).  Applied l times, the sequential chain is 2^l times
+// shorter for 4 l row-parallel phases.  This kernel forms one level's step
+// factors from the previous level's (FP64 accumulation of the stored singles).
+// Rows: index s at reduced row s (top) or M-1-s (bottom) forward, p-1-t or p+1+t
+// backward.  With slot(X) = X^T row-major, slot(A B) = slot(B) slot(A).
+// blockIdx.x: 32 x 32 output tile, blockIdx.y: (dir, end, i), z: instance.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_cr_pair_prod(const float2* __restrict__ F, float2* __restrict__ F2, int m) {
-    const int M = cr_M(m), p = M / 2, H = (M + 1) / 2;
-    const int H2 = gridDim.y / 4;
+__global__ void __launch_bounds__(256) k_cr_level_prod(const float2* __restrict__ F, float2* __restrict__ FL,
+                                                       int m, int lev, int depth) {
+    const int M = cr_M(m), p = M / 2;
+    const int Q = cr_qlev(M, p, lev);
     const int y = blockIdx.y;
-    const int kind = y / (2 * H2), e = (y / H2) % 2, i = y % H2;
-    const bool top = e == 0;
-    const int nsteps = top ? p : (M - 1 - p);
-    const int s = 2 * i + 1;
-    if (s >= nsteps || (kind == 0 && s < 3)) return;
-    int j, jm, a_slot, b_slot, dst;
-    if (kind == 0) {
-        j = top ? s : M - 1 - s;
-        jm = top ? s - 1 : M - s;
-        a_slot = M + j;
-        b_slot = M + jm;
-        dst = j >> 1;
-    } else {
-        j = top ? p - 1 - s : p + 1 + s;
-        jm = top ? p - s : p + s;
-        a_slot = 2 * M + j;
-        b_slot = 2 * M + jm;
-        dst = H + (j >> 1);
-    }
+    const int dir = y / (2 * Q), e = (y / Q) % 2, i = y % Q;
+    const int nsteps = e == 0 ? p : M - 1 - p;
+    if (i >= (nsteps >> lev) || (dir == 0 && i < 1)) return;
     const size_t mm = (size_t)m * m;
     const float2* Fi = F + (size_t)blockIdx.z * 4 * M * mm;
-    const float2* SA = Fi + (size_t)a_slot * mm;
-    const float2* SB = Fi + (size_t)b_slot * mm;
-    float2* SC = F2 + ((size_t)blockIdx.z * 2 * H + dst) * mm;
+    float2* FLi = FL + (size_t)blockIdx.z * cr_fl_off(M, p, depth + 1) * mm;
+    // the two factors of the previous level: index 2i+1 (A) and 2i (B)
+    auto prev = [&](int k) -> const float2* {
+        if (lev == 1) {
+            const int row = dir == 0 ? (e == 0 ? k : M - 1 - k) : (e == 0 ? p - 1 - k : p + 1 + k);
+            return Fi + (size_t)((dir == 0 ? M : 2 * M) + row) * mm;
+        }
+        return FLi + cr_fl_block(M, p, lev - 1, dir, e, k) * mm;
+    };
+    const float2* SA = prev(2 * i + 1);
+    const float2* SB = prev(2 * i);
+    float2* SC = FLi + cr_fl_block(M, p, lev, dir, e, i) * mm;
     const int nt = (m + 31) / 32;
     const int ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
     __shared__ double2 sb[32][33];
@@ -491,14 +485,14 @@ static hh_status setup_coarse_reduced(hh_model* md) {
     hipLaunchKernelGGL(k_cr_mid, dim3(md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(), Vd.as<double2>(),
                        W.as<double2>(), Wm.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
     HH_LAUNCH_CHECK();
-    md->cr_pair = md->d.coarse_reduce >= 2;
-    if (md->cr_pair) {
-        const int p = M / 2, H = (M + 1) / 2, H2 = (std::max(p, M - 1 - p) + 1) / 2;
-        HH_TRY(md->coarseP2.ensure(ctx, (size_t)md->ninst * 2 * H * mm * sizeof(float2)));
-        if (H2 > 0) {
-            const int nt = (m + 31) / 32;
-            hipLaunchKernelGGL(k_cr_pair_prod, dim3(nt * nt, 4 * H2, md->ninst), dim3(256), 0, ctx->stream,
-                               md->coarseQT.as<float2>(), md->coarseP2.as<float2>(), m);
+    md->cr_depth = md->d.coarse_reduce - 1;
+    if (md->cr_depth > 0) {
+        const int p = M / 2, D = md->cr_depth;
+        HH_TRY(md->coarseFL.ensure(ctx, (size_t)md->ninst * cr_fl_off(M, p, D + 1) * mm * sizeof(float2)));
+        const int nt = (m + 31) / 32;
+        for (int l = 1; l <= D; ++l) {  // each level from the previous one
+            hipLaunchKernelGGL(k_cr_level_prod, dim3(nt * nt, 4 * cr_qlev(M, p, l), md->ninst), dim3(256), 0,
+                               ctx->stream, md->coarseQT.as<float2>(), md->coarseFL.as<float2>(), m, l, D);
             HH_LAUNCH_CHECK();
         }
     }
@@ -510,7 +504,7 @@ hh_status setup_coarse_factors(hh_model* md) {
     if (md->d.coarse_iters > 0) {  // iterative coarsest-grid solve: nothing to factorise
         md->m = md->lev[md->nlev - 1].n;
         md->cr1 = false;
-        md->cr_pair = false;
+        md->cr_depth = 0;
         return HH_OK;
     }
     if (md->d.coarse_reduce) return setup_coarse_reduced(md);
@@ -520,7 +514,7 @@ hh_status setup_coarse_factors(hh_model* md) {
     const int p = m / 2;
     md->m = m;
     md->cr1 = false;
-    md->cr_pair = false;
+    md->cr_depth = 0;
     HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * m * m * m * sizeof(float2)));
     Buf S;
     HH_TRY(S.ensure(ctx, (size_t)md->ninst * 3 * m * m * sizeof(double2)));

@@ -40,7 +40,7 @@ def test_defaults_without_gpu():
     d = hh.hh_model_desc()
     hh.hh_model_desc_default(C.byref(d))
     assert (d.abl_width, d.levels, d.nu_pre, d.nu_post) == (16, 3, 1, 1)
-    assert d.sl_beta == 0.5 and d.jacobi_w == 0.8 and d.abl_gamma_max == 1.0 and d.coarse_reduce == 2
+    assert d.sl_beta == 0.5 and d.jacobi_w == 0.8 and d.abl_gamma_max == 1.0 and d.coarse_reduce == 4
     assert d.coarse_iters == 0
     o = hh.hh_solve_opts()
     hh.hh_solve_opts_default(C.byref(o))
