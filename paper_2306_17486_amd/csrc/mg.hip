@@ -1686,26 +1686,30 @@ static hh_status launch_cr_par(hh_model* md, int PH, const float2* bcs, float2* 
 
 // ---------------------------------------------------------------------------
 // The row-parallel phases (PH 1..3 of k_cr_par, PH 4..7 of k_cr_pp) on the
-// matrix cores.  One workgroup takes one factor block and a tile of 16
-// right-hand sides; Y^T (16 x m) = W^T (16 x m) S (m x m), where S is the stored
+// matrix cores.  One workgroup takes one factor block, a tile of 16 right-hand
+// sides and a group of output columns; Y^T (16 x m) = W^T (16 x m) S (m x m), where S is the stored
 // slot ([c][r] = the factor transposed) and W the phase's gathered input
-// vectors (in LDS), as four real products on v_mfma_f32_16x16x4f32 (FP32
+// vectors (in LDS), as three real products on v_mfma_f32_16x16x4f32 (FP32
 // inputs and accumulation, the precision of the vector-ALU form).  Wave w
-// covers output columns 16 w + 256 u .. + 15 (sixteen waves: enough loads in
-// flight to cover the factor block's latency).  A tile whose right-hand sides
+// covers output columns CW cg + 16 w .. + 15 of column group cg.  A tile whose right-hand sides
 // belong to several slowness models runs once per model, each pass with that
 // model's factors and its own rows.
 // ---------------------------------------------------------------------------
 typedef float cmm_f4 __attribute__((ext_vector_type(4)));
-constexpr int CMM_NT = 1024;
 constexpr int CMM_D = 8;  // k-steps of S fragments in flight per wave
 
 // W^T rows padded to whole groups of CMM_D k-steps (zeros beyond m), plus one
 static inline __host__ __device__ int cmm_kpad(int m) { return (m + 4 * CMM_D - 1) / (4 * CMM_D) * (4 * CMM_D); }
 static inline size_t cmm_lds_bytes(int m) { return (size_t)16 * (cmm_kpad(m) + 1) * sizeof(float2); }
 
+// NW waves per workgroup (16 columns each): sixteen for the phases over every
+// factor block (PH 1..3), four for the multi-step phases, whose few blocks are
+// then spread over more compute units
 template <int PH>
-__global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs, float2* __restrict__ x,
+constexpr int cmm_waves() { return PH <= 3 ? 16 : 4; }
+
+template <int PH>
+__global__ void __launch_bounds__(64 * cmm_waves<PH>()) k_cr_mm(const float2* __restrict__ bcs, float2* __restrict__ x,
                                                   float2* __restrict__ tw, float2* __restrict__ gw,
                                                   float2* __restrict__ hw, float2* __restrict__ ends,
                                                   const float2* __restrict__ F, const float2* __restrict__ FL,
@@ -1718,10 +1722,13 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
     const int M = crM(m), Mo = crMo(m), p = M / 2;
     const size_t mm = (size_t)m * m;
     const int m4 = cmm_kpad(m), ldw = m4 + 1, nks = m4 / 4;  // nks: a multiple of CMM_D
-    // workgroup -> (row, tile): all tiles of a row on one XCD (workgroup id mod 8),
-    // so that its factor block is fetched into that XCD's L2 once
+    // workgroup -> (row, tile, column group): all workgroups of a row on one XCD
+    // (workgroup id mod 8), so that its factor block is fetched into that XCD's L2 once
+    constexpr int CMM_NT = 64 * cmm_waves<PH>(), CW = 16 * cmm_waves<PH>();  // threads, columns per workgroup
+    const int ncg = (m + CW - 1) / CW, ntc = ntiles * ncg;
     const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
-    const int row = (kk / ntiles) * 8 + xcd, tile = kk % ntiles;
+    const int row = (kk / ntc) * 8 + xcd, rem = kk % ntc;
+    const int tile = rem / ncg, cg = rem - tile * ncg;
     if (row >= rows) return;
     // the block row (the reduced row for PH 1..3, the multi-step item for PH 4..7)
     int j, jm = 0;
@@ -1760,9 +1767,9 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
         for (int q = 0; q < 16; ++q)
             if (s_rr[q] >= 0 && s_in[q] == pm) mask |= 1 << q;
         done |= mask;
-        // gather W^T into LDS
+        // gather W^T into LDS (four elements per thread in flight at a time)
         if (prod) {
-            for (int e2 = t; e2 < 16 * m4; e2 += CMM_NT) {
+            auto gather = [&](int e2) -> float2 {
                 const int n = e2 / m4, c = e2 - n * m4;
                 float2 w = make_float2(0.f, 0.f);
                 const int rr = s_rr[n];
@@ -1787,7 +1794,24 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
                         w = x[rb + (size_t)(2 * jm) * m + c];
                     }
                 }
-                s_w[n * ldw + c] = w;
+                return w;
+            };
+            const int total = 16 * m4;
+            for (int e0 = t; e0 < total; e0 += 4 * CMM_NT) {
+                float2 w[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int e2 = e0 + k * CMM_NT;
+                    w[k] = e2 < total ? gather(e2) : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int e2 = e0 + k * CMM_NT;
+                    if (e2 < total) {
+                        const int n = e2 / m4, c = e2 - n * m4;
+                        s_w[n * ldw + c] = w[k];
+                    }
+                }
             }
             __syncthreads();
         }
@@ -1801,8 +1825,9 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
                                                      (int)(mm * sizeof(float2)), 0x00020000);
         }();
         const int kl = lane >> 4, cl = lane & 15;
-        for (int cb = wave * 16; cb < m; cb += CMM_NT / 4) {
+        for (int cb = cg * CW + wave * 16; cb < m && cb < (cg + 1) * CW; cb += CW) {
             cmm_f4 accr = (cmm_f4){0.f, 0.f, 0.f, 0.f}, acci = (cmm_f4){0.f, 0.f, 0.f, 0.f};
+            cmm_f4 accq = (cmm_f4){0.f, 0.f, 0.f, 0.f};
             if (prod) {
                 // S fragment at k-step k: S[4 k + kl][cb + cl], row and column clamped into
                 // the block (rows >= m meet zeros of W; columns >= m are not stored)
@@ -1826,42 +1851,60 @@ __global__ void __launch_bounds__(CMM_NT) k_cr_mm(const float2* __restrict__ bcs
                         const float2 a = s_w[cl * ldw + 4 * k + kl];
                         const float2 b = bq[d];
                         bq[d] = sfrag(k + CMM_D);
+                        // three real products (Gauss): ar br, ai bi, (ar + ai)(br + bi)
                         accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accr, 0, 0, 0);
-                        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, accr, 0, 0, 0);
-                        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, acci, 0, 0, 0);
-                        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, acci, 0, 0, 0);
+                        accq = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, accq, 0, 0, 0);
+                        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acci, 0, 0, 0);
                         // keep each refill in its k-step: the wait before a use is then
                         // for the load issued CMM_D steps earlier only
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
+                // Re = ar br - ai bi, Im = (ar + ai)(br + bi) - ar br - ai bi
+                acci = acci - accr - accq;
+                accr = accr - accq;
             }
             // lane holds rows (right-hand sides) 4 kl + v of column cb + cl
             const int r = cb + cl;
             if (r < m) {
+                if (PH <= 3) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int n = 4 * kl + v;
-                    if (!((mask >> n) & 1)) continue;
-                    const int rr = s_rr[n];
-                    const float2 y = make_float2(accr[v], acci[v]);
-                    if (PH == 1) {
-                        tw[((size_t)rr * Mo + j) * m + r] = y;
-                    } else if (PH == 2) {
-                        gw[((size_t)rr * M + j) * m + r] = y;
-                    } else if (PH == 3) {
-                        x[(size_t)rr * mm + (size_t)(2 * j + 1) * m + r] = y;
-                    } else {
-                        // the source vector of this index: g / y at level 0, hw above
+                    for (int v = 0; v < 4; ++v) {
+                        const int n = 4 * kl + v;
+                        if (!((mask >> n) & 1)) continue;
+                        const int rr = s_rr[n];
+                        const float2 y = make_float2(accr[v], acci[v]);
+                        if (PH == 1) tw[((size_t)rr * Mo + j) * m + r] = y;
+                        else if (PH == 2) gw[((size_t)rr * M + j) * m + r] = y;
+                        else x[(size_t)rr * mm + (size_t)(2 * j + 1) * m + r] = y;
+                    }
+                } else {
+                    // this index's source vectors (g / y at level 0, hw above), all loaded first
+                    float2 b[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int n = 4 * kl + v;
+                        b[v] = make_float2(0.f, 0.f);
+                        if ((mask >> n) & 1) {
+                            const int rr = s_rr[n];
+                            const size_t oh = ((size_t)rr * M + j) * m + r;
+                            const size_t ox = (size_t)rr * mm + (size_t)(2 * j) * m + r;
+                            b[v] = lev > 1 ? hw[oh] : (PH <= 5 ? gw[oh] : x[ox]);
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int n = 4 * kl + v;
+                        if (!((mask >> n) & 1)) continue;
+                        const int rr = s_rr[n];
                         const size_t oh = ((size_t)rr * M + j) * m + r;
                         const size_t ox = (size_t)rr * mm + (size_t)(2 * j) * m + r;
-                        const float2 b = lev > 1 ? hw[oh] : (PH <= 5 ? gw[oh] : x[ox]);
-                        const float2 v = cadd(b, y);
+                        const float2 val = cadd(b[v], make_float2(accr[v], acci[v]));
                         if (PH == 4 || PH == 6) {
-                            hw[oh] = v;
+                            hw[oh] = val;
                         } else {
-                            x[ox] = v;
-                            if (it0.last) ends[((size_t)rr * 2 + it0.e) * m + r] = v;
+                            x[ox] = val;
+                            if (it0.last) ends[((size_t)rr * 2 + it0.e) * m + r] = val;
                         }
                     }
                 }
@@ -1893,8 +1936,9 @@ static hh_status launch_cr_mm_t(hh_model* md, int lev, const float2* bcs, float2
     const int M = (m + 1) / 2, Mo = m / 2;
     const int rows = PH <= 3 ? (PH == 2 ? M : Mo) : 2 * cr_phase_half(m, lev);
     if (rows == 0 || nslots == 0) return HH_OK;
-    const int ntiles = (nslots + 15) / 16;
-    hipLaunchKernelGGL(k_cr_mm<PH>, dim3(ntiles * ((rows + 7) / 8) * 8), dim3(CMM_NT), cmm_lds_bytes(m), ctx->stream,
+    const int ntiles = (nslots + 15) / 16, cw_cols = 16 * cmm_waves<PH>(), ncg = (m + cw_cols - 1) / cw_cols;
+    hipLaunchKernelGGL(k_cr_mm<PH>, dim3(ntiles * ncg * ((rows + 7) / 8) * 8), dim3(64 * cmm_waves<PH>()),
+                       cmm_lds_bytes(m), ctx->stream,
                        bcs, x, cw.tw, cw.gw, cw.hw, ends, md->coarseQT.as<float2>(), md->coarseFL.as<float2>(), lev,
                        md->cr_depth, inst, slots, nslots, nslots_dev, m, c, active, rows, ntiles);
     HH_LAUNCH_CHECK();
