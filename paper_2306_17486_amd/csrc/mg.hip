@@ -847,7 +847,8 @@ struct CrItem {
 };
 
 // forward chains of the reduced system: y_j = g_j + P_j y_{j -/+ 1}; y_j -> x row 2j.
-// Paired: y(s) = h(s) + P(s) P(s-1) y(s-2) over the odd s, h from k_cr_pp<.,4>.
+// Multi-step (level l): y(s) = h(s) + A_l y(s - 2^l) over the kept indices, h from the
+// forward combines (k_cr_pp / k_cr_mm, PH 4).
 // PF: the next step's factor is prefetched (needs CoarseMV::pf_ok(); chosen by the host).
 template <int R, bool PF>
 __global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
@@ -904,7 +905,8 @@ __global__ void __launch_bounds__(CS_NT) k_cr_fwd(const float2* __restrict__ gw,
 
 // middle row and backward chains: x_p = g_p + P_p y_{p-1} + R_p y_{p+1};
 // x_j = y_j + R_j x_{j +/- 1} (y_j read from, x_j written to, x row 2j).
-// Paired: x(t) = k(t) + R(t) R(t-1) x(t-2) over the odd t (x(-1) = x_p), k from k_cr_pp<.,6>.
+// Multi-step (level l): x(t) = k(t) + B_l x(t - 2^l) over the kept indices (x(-1) = x_p),
+// k from the backward combines (PH 6).
 template <int R, bool PF>
 __global__ void __launch_bounds__(CS_NT) k_cr_bwd(const float2* __restrict__ gw, const float2* __restrict__ hw,
                                                   float2* __restrict__ x, const float2* __restrict__ ends,
@@ -1487,7 +1489,7 @@ struct CoarseWork {
     float2* xch;
     float2* tw;  // reduced solve: V_j b_{2j+1}, [rhs][Mo][m]
     float2* gw;  // reduced solve: g_j, [rhs][M][m]
-    float2* hw;  // paired chains: h(s), then k(t), at their reduced rows, [rhs][M][m]
+    float2* hw;  // multi-step chains: the combined vectors h, then k, at their reduced rows, [rhs][M][m]
 };
 static size_t coarse_work_bytes(const hh_model* md, int nrhs) {
     const size_t ns = (size_t)coarse_slot_bound(md, nrhs);

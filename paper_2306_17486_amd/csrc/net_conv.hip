@@ -45,7 +45,7 @@ __global__ void k_pack_weights(const float* __restrict__ W, uint16_t* __restrict
 template <int CIN, int COUT, int MODE>
 struct ConvCfg {
     static constexpr int TC = 32;                                               // output tile columns
-    static constexpr int TR = (MODE == CM_S2) ? (CIN >= 64 ? 2 : 4) : (CIN >= 64 ? 4 : (CIN >= 32 ? 16 : 8));  // output tile rows
+    static constexpr int TR = (MODE == CM_S2) ? (CIN >= 64 ? 2 : 4) : (CIN >= 64 ? 2 : (CIN >= 32 ? 4 : 8));  // output tile rows
     static constexpr int NT = COUT / 16;                                        // channel tiles
     // channel tiles per wave: a pixel fragment read from LDS feeds CT MFMAs;
     // the weights' VGPRs (CT * NCH * 4) stay within 72 so that two or more
