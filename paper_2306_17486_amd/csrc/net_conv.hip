@@ -45,7 +45,7 @@ __global__ void k_pack_weights(const float* __restrict__ W, uint16_t* __restrict
 template <int CIN, int COUT, int MODE>
 struct ConvCfg {
     static constexpr int TC = 32;                                               // output tile columns
-    static constexpr int TR = (MODE == CM_S2) ? (CIN >= 64 ? 2 : 4) : (CIN >= 64 ? 2 : (CIN >= 32 ? 4 : 8));  // output tile rows
+    static constexpr int TR = (MODE == CM_S2) ? (CIN >= 32 ? 2 : 4) : (CIN >= 64 ? 2 : (CIN >= 32 ? 4 : 16));  // output tile rows
     static constexpr int NT = COUT / 16;                                        // channel tiles
     // channel tiles per wave: a pixel fragment read from LDS feeds CT MFMAs;
     // the weights' VGPRs (CT * NCH * 4) stay within 72 so that two or more
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
     constexpr int VEC = CIN / 8;
     constexpr int NE = C::PH * C::PW * VEC;
     constexpr int NPF = (NE + 255) / 256;  // gathers per thread
-    constexpr bool PF = NPF <= 5;           // small patches: the next tile's gather overlaps this tile's MFMAs
+    constexpr bool PF = NPF <= 6;           // small patches: the next tile's gather overlaps this tile's MFMAs
     const int per_b = a.tiles_x * a.tiles_y;
     // element e of a tile's patch (zero outside the input)
     auto elem = [&](int tile, int e) -> uint4 {
