@@ -1698,10 +1698,9 @@ static hh_status launch_cr_par(hh_model* md, int PH, const float2* bcs, float2* 
 // model's factors and its own rows.
 // ---------------------------------------------------------------------------
 typedef float cmm_f4 __attribute__((ext_vector_type(4)));
-constexpr int CMM_D = 8;  // k-steps of S fragments in flight per wave
 
-// W^T rows padded to whole groups of CMM_D k-steps (zeros beyond m), plus one
-static inline __host__ __device__ int cmm_kpad(int m) { return (m + 4 * CMM_D - 1) / (4 * CMM_D) * (4 * CMM_D); }
+// W^T rows padded to whole groups of 16 k-steps (any prefetch depth up to 16; zeros beyond m), plus one
+static inline __host__ __device__ int cmm_kpad(int m) { return (m + 4 * 16 - 1) / (4 * 16) * (4 * 16); }
 static inline size_t cmm_lds_bytes(int m) { return (size_t)16 * (cmm_kpad(m) + 1) * sizeof(float2); }
 
 // NW waves per workgroup (16 columns each): sixteen for the phases over every
@@ -1709,6 +1708,10 @@ static inline size_t cmm_lds_bytes(int m) { return (size_t)16 * (cmm_kpad(m) + 1
 // then spread over more compute units
 template <int PH>
 constexpr int cmm_waves() { return PH <= 3 ? 16 : 4; }
+// k-steps of factor fragments in flight per wave: deeper for the four-wave
+// workgroups, whose few waves per compute unit hide less latency
+template <int PH>
+constexpr int cmm_depth() { return PH <= 3 ? 8 : 16; }
 
 template <int PH>
 __global__ void __launch_bounds__(64 * cmm_waves<PH>()) k_cr_mm(const float2* __restrict__ bcs, float2* __restrict__ x,
@@ -1723,7 +1726,8 @@ __global__ void __launch_bounds__(64 * cmm_waves<PH>()) k_cr_mm(const float2* __
     __shared__ int s_rr[16], s_in[16];
     const int M = crM(m), Mo = crMo(m), p = M / 2;
     const size_t mm = (size_t)m * m;
-    const int m4 = cmm_kpad(m), ldw = m4 + 1, nks = m4 / 4;  // nks: a multiple of CMM_D
+    constexpr int DPF = cmm_depth<PH>();
+    const int m4 = cmm_kpad(m), ldw = m4 + 1, nks = m4 / 4;  // nks: a multiple of 16, so of DPF
     // workgroup -> (row, tile, column group): all workgroups of a row on one XCD
     // (workgroup id mod 8), so that its factor block is fetched into that XCD's L2 once
     constexpr int CMM_NT = 64 * cmm_waves<PH>(), CW = 16 * cmm_waves<PH>();  // threads, columns per workgroup
@@ -1838,27 +1842,27 @@ __global__ void __launch_bounds__(64 * cmm_waves<PH>()) k_cr_mm(const float2* __
                     const int off = (min(4 * k + kl, m - 1) * m + col) * (int)sizeof(float2);
                     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
                 };
-                // branch-free pipeline: every k-step refills its buffer CMM_D steps ahead
+                // branch-free pipeline: every k-step refills its buffer DPF steps ahead
                 // (past the end the clamped row is read and not used)
-                float2 bq[CMM_D];
+                float2 bq[DPF];
 #pragma unroll
-                for (int d = 0; d < CMM_D; ++d) {
+                for (int d = 0; d < DPF; ++d) {
                     bq[d] = sfrag(d);
                     __builtin_amdgcn_sched_barrier(0);  // issued in order of use
                 }
-                for (int ks = 0; ks < nks; ks += CMM_D) {
+                for (int ks = 0; ks < nks; ks += DPF) {
 #pragma unroll
-                    for (int d = 0; d < CMM_D; ++d) {
+                    for (int d = 0; d < DPF; ++d) {
                         const int k = ks + d;
                         const float2 a = s_w[cl * ldw + 4 * k + kl];
                         const float2 b = bq[d];
-                        bq[d] = sfrag(k + CMM_D);
+                        bq[d] = sfrag(k + DPF);
                         // three real products (Gauss): ar br, ai bi, (ar + ai)(br + bi)
                         accr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accr, 0, 0, 0);
                         accq = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, accq, 0, 0, 0);
                         acci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acci, 0, 0, 0);
                         // keep each refill in its k-step: the wait before a use is then
-                        // for the load issued CMM_D steps earlier only
+                        // for the load issued DPF steps earlier only
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
