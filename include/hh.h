@@ -319,7 +319,9 @@ hh_status hh_net_get_grads(hh_net* net, float* host);
  *   flipped = 1: w is (cin, cout, 3, 3) and the layer is a transposed convolution
  *   (mode 2 or, with mode 0, the stride-1 transposed convolution);
  *   bias (FP32, may be NULL), skip (BF16, output shape, may be NULL), relu;
- *   y_dev BF16 output, yf_dev optional FP32 output.
+ *   y_dev BF16 output, yf_dev optional FP32 output; active_host (host int[B],
+ *   may be NULL = all): batch entries with 0 are skipped (their outputs are
+ *   left untouched), as the solve skips converged right-hand sides.
  * hh_implicit_test: the implicit layer for coarsest size nc on BF16 NHWC
  *   [B][nc][nc][ch[3]] (adjoint = 1 multiplies by conj(Ghat)).
  * hh_wgrad_test: the weight-gradient kernel of the training pass,
@@ -331,7 +333,7 @@ hh_status hh_net_get_grads(hh_net* net, float* host);
  *   (64,64,1)}, otherwise HH_ERR_ARG. */
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
                        const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int relu,
-                       void* y_dev, float* yf_dev);
+                       void* y_dev, float* yf_dev, const int* active_host);
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint);
 hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, int Wo, int Hi, int Wi,
                         const void* a_dev, const void* x_dev, float* out_dev);

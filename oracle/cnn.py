@@ -49,7 +49,7 @@ def conv2d(x, w, b, stride=1):
     for a in range(3):
         for e in range(3):
             patch = xp[:, :, a:a + stride * Ho:stride, e:e + stride * Wo:stride]
-            out += np.einsum("oc,bchw->bohw", w[:, :, a, e], patch)
+            out += np.einsum("oc,bchw->bohw", w[:, :, a, e], patch, optimize=True)
     return out + b[None, :, None, None]
 
 
@@ -64,9 +64,9 @@ def conv2d_backward(x, w, gout, stride=1):
     for a in range(3):
         for e in range(3):
             patch = xp[:, :, a:a + stride * Ho:stride, e:e + stride * Wo:stride]
-            gw[:, :, a, e] = np.einsum("bohw,bchw->oc", gout, patch)
+            gw[:, :, a, e] = np.einsum("bohw,bchw->oc", gout, patch, optimize=True)
             gxp[:, :, a:a + stride * Ho:stride, e:e + stride * Wo:stride] += np.einsum(
-                "oc,bohw->bchw", w[:, :, a, e], gout)
+                "oc,bohw->bchw", w[:, :, a, e], gout, optimize=True)
     return gxp[:, :, 1:-1, 1:-1].copy(), gw, gout.sum(axis=(0, 2, 3))
 
 
@@ -79,7 +79,7 @@ def conv_transpose2d(x, w, b, stride=2):
     for a in range(3):
         for e in range(3):
             op[:, :, a:a + stride * Hh:stride, e:e + stride * W:stride] += np.einsum(
-                "co,bchw->bohw", w[:, :, a, e], x)
+                "co,bchw->bohw", w[:, :, a, e], x, optimize=True)
     return op[:, :, 1:Ho + 1, 1:Wo + 1] + b[None, :, None, None]
 
 
@@ -93,8 +93,8 @@ def conv_transpose2d_backward(x, w, gout, stride=2):
     for a in range(3):
         for e in range(3):
             sl = gp[:, :, a:a + stride * Hh:stride, e:e + stride * W:stride]
-            gx += np.einsum("co,bohw->bchw", w[:, :, a, e], sl)
-            gw[:, :, a, e] = np.einsum("bchw,bohw->co", x, sl)
+            gx += np.einsum("co,bohw->bchw", w[:, :, a, e], sl, optimize=True)
+            gw[:, :, a, e] = np.einsum("bchw,bohw->co", x, sl, optimize=True)
     return gx, gw, gout.sum(axis=(0, 2, 3))
 
 

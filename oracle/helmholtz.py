@@ -300,6 +300,12 @@ def solve_mg(prob: Problem, b, rtol=1e-6, max_iters=2000, restart=10):
 
 
 def exact_solve(prob: Problem, b):
-    """The plain definition of the result: x* = A^{-1} b by a sparse direct solve."""
+    """The plain definition of the result: x* = A^{-1} b by a sparse direct solve.
+
+    b is one n x n right-hand side or a stack (k, n, n); the matrix is
+    factorised once for the whole stack."""
     lu = spla.splu(prob.matrix(0.0).tocsc())
+    n2 = prob.n * prob.n
+    if b.ndim == 3:
+        return lu.solve(np.ascontiguousarray(b.reshape(b.shape[0], n2).T)).T.reshape(b.shape)
     return lu.solve(b.ravel()).reshape(b.shape)

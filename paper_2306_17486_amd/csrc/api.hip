@@ -180,7 +180,13 @@ hh_status hh_model_create(hh_ctx* ctx, const hh_model_desc* d, int ninst, const 
             return s;
         }
     }
-    hh_status s = setup_coefficients(m, kappa_dev);
+    hh_status s = m->kappa0.ensure(ctx, (size_t)ninst * d->n * d->n * sizeof(float));
+    if (s >= 0 && hipMemcpyAsync(m->kappa0.ptr, kappa_dev, (size_t)ninst * d->n * d->n * sizeof(float),
+                                 hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+        set_error("hipMemcpyAsync failed");
+        s = HH_ERR_HIP;
+    }
+    if (s >= 0) s = setup_coefficients(m, kappa_dev);
     if (s >= 0) s = setup_coarse_factors(m);
     if (s >= 0) s = m->coarse_err.ensure(ctx, 256);
     if (s >= 0 && hipMemsetAsync(m->coarse_err.ptr, 0, sizeof(int), ctx->stream) != hipSuccess) {

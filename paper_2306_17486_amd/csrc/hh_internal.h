@@ -140,6 +140,7 @@ struct hh_model {
     int ninst = 0;
     int nlev = 0;
     hh::Level lev[HH_MAX_LEVELS];
+    hh::Buf kappa0;        // float [ninst][n][n]: the slowness as given, for the FP64 residual
     hh::Buf coarseQT;      // coarse factors, transposed complex singles: [ninst][m][m][m] Schur inverses of the
                            // two-ended elimination, or (cr1) [ninst][4 ceil(m/2)][m][m] reduced-solve slots
     int m = 0;             // coarsest points per dimension
@@ -207,6 +208,28 @@ __host__ __device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
     return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
 }
 __host__ __device__ __forceinline__ double zabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// Attenuation gamma(i, j) of eq. 1: gamma0 plus the absorbing layer's
+// quadratic ramp, gmax ((w - d) / w)^2 at distance d < w from the nearest edge.
+__host__ __device__ __forceinline__ double abl_gamma(int i, int j, int n, int abl_w, double gmax, double gamma0) {
+    const int di = i < n - 1 - i ? i : n - 1 - i, dj = j < n - 1 - j ? j : n - 1 - j;
+    const int d = di < dj ? di : dj;
+    double g = gamma0;
+    if (d < abl_w) {
+        const double t = (double)(abl_w - d) / abl_w;
+        g += gmax * t * t;
+    }
+    return g;
+}
+
+// What the FP64 residual needs to form the operator's zeroth-order term in
+// FP64 from the FP32 slowness: omega^2 kappa^2 (1 - i gamma).
+struct Coef64 {
+    const float* kappa;  // [ninst][n][n]
+    double omega2;
+    int abl_w;
+    double gmax, gamma0;
+};
 
 // Zeroth-order term omega^2 kappa^2 (1 - i (gamma + shift)) from the stored
 // coefficient pair {omega^2 kappa^2, gamma}.

@@ -81,11 +81,13 @@ __global__ void __launch_bounds__(256) k_norm2(const float2* __restrict__ b, int
 }
 
 // r = b - A x in FP64 (x complex double); r stored single into V[r][0]; ||r||^2 partials.
+// The zeroth-order term omega^2 kappa^2 (1 - i gamma) is formed in FP64 from
+// the FP32 slowness as given, so this residual is that of eqs. 1-3 itself,
+// not of the FP32-rounded coefficients the single-precision kernels use.
 __global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ x, const float2* __restrict__ b,
-                                                    float2* __restrict__ Vbase, size_t vstride,
-                                                    const float2* __restrict__ coef, const int* __restrict__ inst,
-                                                    int n, double inv_h2, double2* __restrict__ parts,
-                                                    const int* __restrict__ done) {
+                                                    float2* __restrict__ Vbase, size_t vstride, Coef64 cf64,
+                                                    const int* __restrict__ inst, int n, double inv_h2,
+                                                    double2* __restrict__ parts, const int* __restrict__ done) {
     __shared__ double2 s_red[4];
     const int r = blockIdx.z;
     const bool skip = done && done[r];
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ 
     const int j = blockIdx.x * KT_X + threadIdx.x;
     const int i0 = blockIdx.y * KT_Y + threadIdx.y * KT_ROWS;
     const double2* xr = x + r * nn;
-    const float2* cf = coef + (size_t)(inst ? inst[r] : 0) * nn;
+    const float* kap = cf64.kappa + (size_t)(inst ? inst[r] : 0) * nn;
     double2 acc[1] = {make_double2(0.0, 0.0)};
     if (!skip && j < n) {
         const double2 z = make_double2(0.0, 0.0);
@@ -104,8 +106,9 @@ __global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ 
             double2 c = xr[o];
             double2 up = i > 0 ? xr[o - n] : z, dn = i + 1 < n ? xr[o + n] : z;
             double2 lf = j > 0 ? xr[o - 1] : z, rt = j + 1 < n ? xr[o + 1] : z;
-            float2 cc = cf[o];
-            double w2k2 = cc.x, g = cc.y;
+            const double k = kap[o];
+            const double w2k2 = cf64.omega2 * k * k;
+            const double g = abl_gamma(i, j, n, cf64.abl_w, cf64.gmax, cf64.gamma0);
             // A x = (4c - nb)/h^2 - w2k2 (1 - i g) c
             double2 m = make_double2(w2k2, -w2k2 * g);
             double2 Ax = make_double2((4.0 * c.x - up.x - dn.x - lf.x - rt.x) * inv_h2,
@@ -120,6 +123,16 @@ __global__ void __launch_bounds__(256) k_residual64(const double2* __restrict__ 
     block_sum2<1>(acc, 1, s_red);
     if (threadIdx.x == 0 && threadIdx.y == 0)
         parts[(size_t)r * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
+}
+
+static Coef64 coef64(const hh_model* md) {
+    Coef64 c;
+    c.kappa = md->kappa0.as<float>();
+    c.omega2 = md->d.omega * md->d.omega;
+    c.abl_w = md->d.abl_width;
+    c.gmax = md->d.abl_gamma_max;
+    c.gamma0 = md->d.gamma0;
+    return c;
 }
 
 // w = A z (FP32) written to V[j+1]; partial dots <v~_i, w>, i = 0..j: each
@@ -626,7 +639,7 @@ hh_status FgmresRun::begin_cycle() {
     {
         ProfScope ps(ctx, HH_K_RESTART);
         hipLaunchKernelGGL(k_residual64, grd, blk, 0, stream_, x_, b_, W_.V.as<float2>(), vstride,
-                           L0.coef.as<float2>(), bm_.inst, n, 1.0 / (L0.h * L0.h), W_.parts.as<double2>(), done);
+                           coef64(md_), bm_.inst, n, 1.0 / (L0.h * L0.h), W_.parts.as<double2>(), done);
     }
     HH_LAUNCH_CHECK();
     {
@@ -773,7 +786,7 @@ hh_status FgmresRun::run_cycle() {
     ++cycle_;
     if (fixed) {
         // one cycle only: mark everything done after the final residual
-        hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, L0.coef.as<float2>(), inst_dev, n,
+        hipLaunchKernelGGL(k_residual64, grd, blk, 0, st, x, b, V, vstride, coef64(md), inst_dev, n,
                            1.0 / (L0.h * L0.h), parts, nullptr);
         HH_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cycle_begin, dim3(nrhs), dim3(256), 0, st, parts, np, S, done, act, actc, actm, hist,
@@ -850,7 +863,7 @@ hh_status residual_norms(hh_model* md, int nrhs, const BatchMap& bm, const float
     HH_TRY(parts.ensure(ctx, (size_t)2 * nrhs * np * sizeof(double2)));
     double2* pr = parts.as<double2>();
     double2* pb = pr + (size_t)nrhs * np;
-    hipLaunchKernelGGL(k_residual64, grd, blk, 0, ctx->stream, x, b, nullptr, (size_t)0, L0.coef.as<float2>(), bm.inst,
+    hipLaunchKernelGGL(k_residual64, grd, blk, 0, ctx->stream, x, b, nullptr, (size_t)0, coef64(md), bm.inst,
                        n, 1.0 / (L0.h * L0.h), pr, nullptr);
     HH_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_norm2, grd, blk, 0, ctx->stream, b, n, pb);

@@ -2127,13 +2127,18 @@ hh_status hh_apply_cnn_precond(hh_model* m, int nrhs, const int* inst_host, cons
 
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
                        const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int relu,
-                       void* y_dev, float* yf_dev) {
+                       void* y_dev, float* yf_dev, const int* active_host) {
     HH_ARG(ctx && x_dev && w_dev && y_dev, "null pointer");
     HH_ARG(mode >= 0 && mode <= 2, "mode");
+    HH_ARG(B >= 1 && Hin >= 1 && Win >= 1, "sizes");
     HH_HIP(hipSetDevice(ctx->device));
-    Buf wp;
+    Buf wp, act;
     HH_TRY(wp.ensure(ctx, packed_weight_elems(cin, cout) * sizeof(uint16_t) + 256));
     HH_TRY(pack_weights(ctx->stream, w_dev, wp.as<uint16_t>(), cin, cout, flipped != 0));
+    if (active_host) {
+        HH_TRY(act.ensure(ctx, (size_t)B * sizeof(int)));
+        HH_HIP(hipMemcpyAsync(act.ptr, active_host, (size_t)B * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    }
     ConvArgs a{};
     a.x = (const uint16_t*)x_dev;
     a.y = (uint16_t*)y_dev;
@@ -2147,6 +2152,7 @@ hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin,
     a.Win = Win;
     a.Hout = mode == CM_S2 ? Hin / 2 : (mode == CM_T2 ? 2 * Hin : Hin);
     a.Wout = mode == CM_S2 ? Win / 2 : (mode == CM_T2 ? 2 * Win : Win);
+    a.active = act.as<int>();
     HH_TRY(launch_conv(ctx->stream, ctx->num_cus, cin, cout, mode, a));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;

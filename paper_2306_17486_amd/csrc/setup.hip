@@ -15,12 +15,7 @@ __global__ void k_coef0(const float* __restrict__ kappa, float2* __restrict__ co
     if (j >= n) return;
     const size_t off = ((size_t)inst * n + i) * n + j;
     const double k = kappa[off];
-    int d = min(min(i, n - 1 - i), min(j, n - 1 - j));
-    double g = gamma0;
-    if (d < abl_w) {
-        double t = (double)(abl_w - d) / abl_w;
-        g += gmax * t * t;
-    }
+    const double g = abl_gamma(i, j, n, abl_w, gmax, gamma0);
     coef[off] = make_float2((float)(omega * omega * k * k), (float)g);
 }
 

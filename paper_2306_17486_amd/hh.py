@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -97,7 +98,7 @@ hh_net_load = _sig("hh_net_load", _I, _P, C.c_char_p, C.POINTER(_P))
 hh_model_attach_net = _sig("hh_model_attach_net", _I, _P, _P)
 hh_net_forward = _sig("hh_net_forward", _I, _P, _I, _IP, _P, _P)
 hh_apply_cnn_precond = _sig("hh_apply_cnn_precond", _I, _P, _I, _IP, _P, _P)
-hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P)
+hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _IP)
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
 hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
 hh_gen_training_pairs = _sig("hh_gen_training_pairs", _I, _P, _P, _I, _P, _IP, _P, _P)
@@ -162,9 +163,15 @@ class Context:
         h = C.c_void_p()
         check(hh_ctx_create(device, C.c_void_p(self.stream.cuda_stream), self._alloc, self._free, None, C.byref(h)))
         self.handle = h
+        # models and networks of this context: released before the context is
+        self._children = weakref.WeakSet()
 
     def close(self):
+        """Release the context, after every model and network still open on it
+        (their workspaces go back through this context's allocator)."""
         if getattr(self, "handle", None):
+            for c in list(getattr(self, "_children", ())):
+                c.close()
             hh_ctx_destroy(self.handle)
             self.handle = None
 
@@ -207,10 +214,12 @@ class Model:
         h = C.c_void_p()
         check(hh_model_create(ctx.handle, C.byref(self.desc), self.ninst, _ptr(k), C.byref(h)))
         self.handle = h
+        ctx._children.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
-            hh_model_destroy(self.handle)
+            if self.ctx.handle:  # a closed context has already released this model
+                hh_model_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -364,6 +373,7 @@ class Net:
         self.ch = tuple(ch)
         if _handle is not None:
             self.handle = _handle
+            ctx._children.add(self)
             return
         d = hh_net_desc()
         for i in range(4):
@@ -376,6 +386,7 @@ class Net:
         check(hh_net_create(ctx.handle, C.byref(d), flat.ctypes.data_as(_FP) if flat is not None else None,
                             C.byref(h)))
         self.handle = h
+        ctx._children.add(self)
         if flat is not None:
             assert flat.size == self.num_params(), (flat.size, self.num_params())
 
@@ -432,7 +443,8 @@ class Net:
 
     def close(self):
         if getattr(self, "handle", None):
-            hh_net_destroy(self.handle)
+            if self.ctx.handle:
+                hh_net_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -443,21 +455,26 @@ class Net:
 
 
 def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, flipped: bool, bias=None, skip=None,
-              relu=False):
-    """One convolution through the library's MFMA kernel; returns (y bf16, y fp32)."""
+              relu=False, active=None, fill=None):
+    """One convolution through the library's MFMA kernel; returns (y bf16, y fp32).
+    active: optional per-batch-entry flags (0 = skipped, output left as filled);
+    fill: initial value of both outputs (default: uninitialised)."""
     B, H, W_, cin = x_bf16.shape
     cout = w.shape[1] if flipped else w.shape[0]
     Ho = H // 2 if mode == 1 else (2 * H if mode == 2 else H)
     Wo = W_ // 2 if mode == 1 else (2 * W_ if mode == 2 else W_)
     y = torch.empty((B, Ho, Wo, cout), dtype=torch.bfloat16, device=x_bf16.device)
     yf = torch.empty((B, Ho, Wo, cout), dtype=torch.float32, device=x_bf16.device)
+    if fill is not None:
+        y.fill_(fill)
+        yf.fill_(fill)
     # keep every converted tensor referenced until the call returns: the library
     # allocates through torch's caching allocator and could otherwise reuse them
     w = w.to(torch.float32).contiguous()
     bias = bias.to(torch.float32).contiguous() if bias is not None else None
     skip = skip.contiguous() if skip is not None else None
     check(hh_conv_test(ctx.handle, cin, cout, mode, B, H, W_, _ptr(x_bf16), _ptr(w), int(flipped), _ptr(bias),
-                       _ptr(skip), int(relu), _ptr(y), _ptr(yf)))
+                       _ptr(skip), int(relu), _ptr(y), _ptr(yf), _int_array(active)))
     return y, yf
 
 

@@ -31,8 +31,18 @@ def _minmax(f: np.ndarray, lo: float = KAPPA_MIN, hi: float = KAPPA_MAX) -> np.n
     return lo + (hi - lo) * (f - fmin) / (fmax - fmin)
 
 
+def _fp32_exact(k: np.ndarray) -> np.ndarray:
+    """Round to the nearest float32 and return float64.
+
+    The library takes the slowness in FP32; rounding here hands the CPU checker
+    and the library the same medium, so both assemble the same operator.
+    """
+    return np.asarray(k, dtype=np.float32).astype(np.float64)
+
+
 def grf_slowness(n: int, seed: int, corr: float = 0.1) -> np.ndarray:
-    """Gaussian random field on an n x n grid mapped to [0.25, 1] (float64).
+    """Gaussian random field on an n x n grid mapped to [0.25, 1] (float64
+    holding float32-representable values).
 
     White noise is smoothed by a periodic Gaussian filter of standard deviation
     ``corr * n`` cells (applied in Fourier space), then min-max normalised.
@@ -44,11 +54,12 @@ def grf_slowness(n: int, seed: int, corr: float = 0.1) -> np.ndarray:
     fx = np.fft.rfftfreq(n)[None, :]
     filt = np.exp(-2.0 * math.pi ** 2 * sigma ** 2 * (fx ** 2 + fy ** 2))
     field = np.fft.irfft2(np.fft.rfft2(white) * filt, s=(n, n))
-    return _minmax(field)
+    return _fp32_exact(_minmax(field))
 
 
 def layered_slowness(n: int, seed: int) -> np.ndarray:
-    """Layered / blocky slowness on an n x n grid with values in [0.25, 1].
+    """Layered / blocky slowness on an n x n grid with values in [0.25, 1]
+    (float64 holding float32-representable values).
 
     4-10 layers separated by tilted straight interfaces y = a_k + t_k (x - 1/2)
     with t_k ~ U(-0.3, 0.3); every layer gets a value ~ U[0.25, 1].  With
@@ -73,7 +84,7 @@ def layered_slowness(n: int, seed: int) -> np.ndarray:
             v = rng.uniform(KAPPA_MIN, KAPPA_MAX)
             mask = (y >= y0) & (y <= y1) & (x >= x0) & (x <= x1)
             kappa = np.where(mask, v, kappa)
-    return np.asarray(kappa, dtype=np.float64)
+    return _fp32_exact(kappa)
 
 
 def slowness(n: int, seed: int, family: str) -> np.ndarray:

@@ -54,8 +54,8 @@ def test_batch_over_the_size_classes():
     x0, info0 = res[0]
     assert info0["converged"][0]
     n = specs[0][0]
-    # the library stores the medium in FP32: the oracle takes the same rounded kappa
-    prob = H.Problem(ks[0].astype(np.float32).astype(np.float64), inputs.omega_for(n))
+    # the generators return FP32-representable slowness: both sides take the same medium
+    prob = H.Problem(ks[0], inputs.omega_for(n))
     b = inputs.point_source(n, 4200)
     x = x0.cpu().numpy()[0]
     own = models[0].residual_norms(bs[0], x0)[0]
@@ -65,6 +65,7 @@ def test_batch_over_the_size_classes():
     _say(f"512^2: FP64 residual {own:.3e} (library operator), {rel:.3e} (oracle operator), "
          f"error vs direct solve {err:.2e}")
     assert own <= 1e-6
-    # the two operators differ by the FP32 rounding of omega^2 kappa^2 in the mass term
-    assert rel <= 1e-6 + 1e-7
-    assert err <= 1e-4
+    # the library's FP64 residual forms omega^2 kappa^2 in FP64 from the same FP32
+    # slowness: the same operator, up to FP64 summation order
+    assert rel <= 1e-6 * (1 + 1e-6)
+    assert err <= 1e-5

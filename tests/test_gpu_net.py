@@ -86,6 +86,58 @@ def test_conv_kernel(hh, ctx, cin, cout, mode, flipped, Hs):
         assert np.array_equal(yb, _bf16_round(got))
 
 
+# Launches with more tiles than the grid (8 workgroups per CU): every
+# workgroup walks several tiles, prefetching the next one's patch, and skips
+# the batch entries marked inactive.  Sizes are ragged against the tiles.
+# (cin, cout, mode, flipped, Hin, Win, output tile rows, tile columns)
+LARGE_CONV_CASES = [
+    (16, 16, 0, False, 150, 170, 16, 32), (32, 32, 0, False, 62, 70, 4, 32), (64, 64, 0, False, 30, 45, 2, 32),
+    (64, 64, 0, True, 30, 45, 2, 32),
+    (16, 32, 1, False, 76, 90, 4, 32), (32, 64, 1, False, 40, 70, 2, 32), (64, 64, 1, False, 40, 70, 2, 32),
+    (64, 64, 2, True, 9, 20, 4, 32), (64, 32, 2, True, 9, 20, 4, 32), (32, 16, 2, True, 15, 20, 8, 32),
+]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("cin,cout,mode,flipped,Hin,Win,TR,TC", LARGE_CONV_CASES)
+def test_conv_kernel_many_tiles(hh, ctx, cin, cout, mode, flipped, Hin, Win, TR, TC):
+    Ho = Hin // 2 if mode == 1 else (2 * Hin if mode == 2 else Hin)
+    Wo = Win // 2 if mode == 1 else (2 * Win if mode == 2 else Win)
+    per_b = -(-Ho // TR) * -(-Wo // TC)
+    grid = 8 * torch.cuda.get_device_properties(0).multi_processor_count
+    B = grid // per_b + 2  # more tiles than workgroups, even after the skipped entries
+    active = [0 if b % 3 == 1 else 1 for b in range(B)]
+    while sum(active) * per_b <= grid:
+        B += 3
+        active = [0 if b % 3 == 1 else 1 for b in range(B)]
+    _say(f"conv many tiles cin={cin} cout={cout} mode={mode} flipped={flipped} B={B} {Hin}x{Win} "
+         f"tiles {B * per_b} (grid {grid})")
+    rng = np.random.default_rng(cin * 100 + cout + 7 * mode + 1)
+    x = _bf16_round(rng.standard_normal((B, cin, Hin, Win)))
+    wshape = (cin, cout, 3, 3) if flipped else (cout, cin, 3, 3)
+    w = _bf16_round(rng.standard_normal(wshape) / np.sqrt(9 * cin))
+    b = rng.standard_normal(cout)
+    act = np.array(active, dtype=bool)
+    if flipped:
+        ref = C.conv_transpose2d(x[act], w, b, 2 if mode == 2 else 1)
+    else:
+        ref = C.conv2d(x[act], w, b, 2 if mode == 1 else 1)
+    skip = _bf16_round(rng.standard_normal((B,) + ref.shape[1:]))
+    r = np.maximum(ref + skip[act], 0.0)
+    sentinel = 3.0
+    y, yf = hh.conv_test(ctx, _nhwc_dev(x), torch.from_numpy(w).cuda(), mode, flipped,
+                         bias=torch.from_numpy(b).cuda(), skip=_nhwc_dev(skip), relu=True, active=active,
+                         fill=sentinel)
+    got = yf.cpu().numpy().transpose(0, 3, 1, 2)
+    yb = y.to(torch.float32).cpu().numpy().transpose(0, 3, 1, 2)
+    # skipped entries are untouched
+    assert np.all(got[~act] == sentinel) and np.all(yb[~act] == sentinel)
+    # every element of every active entry, edges and ragged tails included
+    err = np.abs(got[act] - r)
+    assert np.all(err <= 2e-6 * np.abs(r).max()), err.max() / np.abs(r).max()
+    assert np.array_equal(yb[act], _bf16_round(got[act]))
+
+
 WGRAD_CASES = [
     # (ca, cx, mode, Ho): conv layers take a = output gradient, x = layer input;
     # stride-2 transposed layers take a = layer input, x = output gradient
@@ -158,8 +210,21 @@ def test_network_forward(hh, ctx, n, family):
     for i in range(nr):
         ref = netp(r[i])
         err = np.linalg.norm(e[i] - ref) / np.linalg.norm(ref)
-        _say(f"  rhs {i}: relative error {err:.3e}")
-        assert err <= 3e-2
+        emax = np.abs(e[i] - ref).max() / np.abs(ref).max()
+        # per 16 x 16 block of the output: a wrong tile of any layer shows here
+        nb = n // 16
+        d = np.abs(e[i] - ref).reshape(nb, 16, nb, 16).max(axis=(1, 3))
+        sc = np.abs(ref).reshape(nb, 16, nb, 16).max(axis=(1, 3))
+        eblk = (d / np.maximum(sc, 1e-3 * np.abs(ref).max())).max()
+        _say(f"  rhs {i}: relative error {err:.3e}, max elementwise {emax:.3e} of max|ref|, "
+             f"worst 16x16 block {eblk:.3e} of its own max")
+        # BF16 activations round at 2^-9 relative between layers (C19): the
+        # network output stays within a few of those roundings everywhere
+        # (measured: 9e-4 globally, 2.8e-3 elementwise, 3.8e-3 per block);
+        # a wrong tile in any layer shows as an O(1) error in its blocks
+        assert err <= 3e-3
+        assert emax <= 3 * 2.0 ** -9
+        assert eblk <= 1e-2
 
 
 def test_cnn_mg_two_phase_solve(hh, ctx):
@@ -181,7 +246,7 @@ def test_cnn_mg_two_phase_solve(hh, ctx):
         assert info["converged"][r] and rel <= 1e-6
         _, its_o, _, _ = S.solve_two_phase(prob, netp, b[r])
         _say(f"  rhs {r}: gpu {info['iters'][r]} oracle {its_o}")
-        assert abs(int(info["iters"][r]) - its_o) <= max(3, int(0.25 * its_o))
+        assert abs(int(info["iters"][r]) - its_o) <= 2
 
 
 def test_cnn_mg_judge_falls_back_for_a_bad_network(hh, ctx):
@@ -211,7 +276,7 @@ def test_cnn_mg_judge_falls_back_for_a_bad_network(hh, ctx):
         _say(f"  rhs {r}: gpu {info['iters'][r]} (MG cycles {info['mg_cycles'][r]}) oracle {its_o} {st} "
              f"mg-only {its_mg}")
         assert st["probes"] >= 1 and info["mg_cycles"][r] == st["mg_cycles"] >= 1
-        assert abs(int(info["iters"][r]) - its_o) <= max(3, int(0.25 * its_o))
+        assert abs(int(info["iters"][r]) - its_o) <= 2
         assert info["iters"][r] <= its_mg + 2 * 10
 
 
