@@ -222,6 +222,19 @@ int hh_model_coarse_group(const hh_model* m, int nact);
 hh_status hh_residual_norms(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
                             const void* x_dev, double* rel_host);
 
+/* hh_residual_norms without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments and results, same kernels, but the
+ * partial sums live in a fixed 1 MiB device array of the library (one per
+ * GPU, set up by hh_ctx_create on the context's device and held until the
+ * process ends) and the inst map is read on the host (one launch triple per
+ * right-hand side).  Limits: nrhs <= 256 and n <= 4096, else HH_ERR_ARG.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other threads, other streams) race and must be serialised by the caller.
+ * Calls no allocator, torch's included.  Synchronises the stream. */
+hh_status hh_residual_norms_noalloc(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host, const void* b_dev,
+                                    const void* x_dev, double* rel_host);
+
 /* ------------------------------------------------------------------------
  * Building blocks exposed for parity tests (same kernels as the solve).
  * ---------------------------------------------------------------------- */

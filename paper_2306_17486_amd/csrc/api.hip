@@ -121,6 +121,11 @@ hh_status hh_ctx_create(int device, void* stream, hh_alloc_fn alloc, hh_free_fn 
     c->dealloc = free_fn;
     c->user = user;
     c->num_cus = prop.multiProcessorCount;
+    hh_status s = noalloc_init(device);
+    if (s != HH_OK) {
+        delete c;
+        return s;
+    }
     *out = c;
     return HH_OK;
 }

@@ -318,6 +318,9 @@ int coarse_gmres_max_iters();
 // a non-blocking stream of the context for graph capture (created on first use)
 hh_status capture_stream(hh_ctx* c, hipStream_t* out);
 hh_status coarse_check_err(hh_model* md);
+// the fixed scratch of hh_residual_norms_noalloc: look up its address on
+// `device` (once per device; krylov.hip)
+hh_status noalloc_init(int device);
 // copy a host RHS -> slowness-model map to the device (api.hip)
 hh_status upload_inst_map(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out);
 

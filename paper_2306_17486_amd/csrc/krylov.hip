@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 
 #include "hh_internal.h"
 #include "krylov.h"
@@ -889,4 +890,108 @@ hh_status precond_mg_strided(hh_model* md, SolveWork& W, const BatchMap& bm, con
                                  act);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 residual norms without any allocation (hh_residual_norms_noalloc).
+// The partial sums live in a fixed device array instead of a workspace, one
+// copy per GPU; its device address is looked up once per device when a
+// context is created there and kept per device.  Every call on a device shares
+// that device's array (calls that overlap on one GPU race); each call writes
+// every word it reads, so nothing has to start at zero.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_RHS = 256;
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)1 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+hh_status noalloc_init(int device) {
+    HH_ARG(device >= 0 && device < NOALLOC_MAX_DEVICES, "device index below 64");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return HH_OK;
+    HH_HIP(hipSetDevice(device));
+    void* p = nullptr;
+    HH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+        set_error("hipGetSymbolAddress returned no address for the residual-norm scratch array");
+        return HH_ERR_HIP;
+    }
+    g_scratch_dev[device] = p;
+    return HH_OK;
+}
+
+// out[0] = sum of pr[q].x, out[1] = sum of pb[q].x over q < np (FP64; one workgroup)
+__global__ void __launch_bounds__(256) k_sum_parts(const double2* __restrict__ pr, const double2* __restrict__ pb,
+                                                   int np, double* __restrict__ out) {
+    __shared__ double s_a[4], s_b[4];
+    const int t = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int q = t; q < np; q += 256) {
+        a += pr[q].x;
+        b += pb[q].x;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((t & 63) == 0) {
+        s_a[t >> 6] = a;
+        s_b[t >> 6] = b;
+    }
+    __syncthreads();
+    if (t == 0) {
+        out[0] = (s_a[0] + s_a[1]) + (s_a[2] + s_a[3]);
+        out[1] = (s_b[0] + s_b[1]) + (s_b[2] + s_b[3]);
+    }
+}
+
 }  // namespace hh
+
+using namespace hh;
+
+extern "C" hh_status hh_residual_norms_noalloc(hh_ctx* ctx, hh_model* m, int nrhs, const int* inst_host,
+                                               const void* b_dev, const void* x_dev, double* rel_host) {
+    HH_ARG(ctx && m && b_dev && x_dev && rel_host, "null pointer");
+    HH_ARG(m->ctx == ctx, "model belongs to another context");
+    HH_ARG(nrhs >= 1 && nrhs <= NOALLOC_MAX_RHS, "nrhs in 1..256 (the fixed scratch holds 256 results)");
+    if (inst_host)
+        for (int r = 0; r < nrhs; ++r)
+            HH_ARG(inst_host[r] >= 0 && inst_host[r] < m->ninst, "instance index out of range");
+    const Level& L0 = m->lev[0];
+    const int n = L0.n, np = kblocks(n);
+    const size_t res_bytes = (size_t)2 * NOALLOC_MAX_RHS * sizeof(double);
+    HH_ARG(res_bytes + (size_t)2 * np * sizeof(double2) <= NOALLOC_SCRATCH_BYTES,
+           "grid too large for the fixed 1 MiB scratch (n <= 4096)");
+    HH_ARG(ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES, "device index below 64");
+    void* base = g_scratch_dev[ctx->device];
+    if (!base) {
+        set_error("the residual-norm scratch of device %d was not set up (hh_ctx_create does it)", ctx->device);
+        return HH_ERR_STATE;
+    }
+    HH_HIP(hipSetDevice(ctx->device));
+    double* res = reinterpret_cast<double*>(base);
+    double2* pr = reinterpret_cast<double2*>(reinterpret_cast<unsigned char*>(base) + res_bytes);
+    double2* pb = pr + np;
+    const size_t nn = (size_t)n * n;
+    const dim3 blk(KT_X, KT_Y / KT_ROWS);
+    const dim3 grd((n + KT_X - 1) / KT_X, (n + KT_Y - 1) / KT_Y, 1);
+    Coef64 cf = coef64(m);
+    const float* kappa = cf.kappa;
+    for (int r = 0; r < nrhs; ++r) {  // one right-hand side at a time: the partials are reused
+        cf.kappa = kappa + (size_t)(inst_host ? inst_host[r] : 0) * nn;
+        hipLaunchKernelGGL(k_residual64, grd, blk, 0, ctx->stream, (const double2*)x_dev + r * nn,
+                           (const float2*)b_dev + r * nn, nullptr, (size_t)0, cf, nullptr, n, 1.0 / (L0.h * L0.h),
+                           pr, nullptr);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_norm2, grd, blk, 0, ctx->stream, (const float2*)b_dev + r * nn, n, pb);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, ctx->stream, pr, pb, np, res + 2 * r);
+        HH_LAUNCH_CHECK();
+    }
+    double h[2 * NOALLOC_MAX_RHS];
+    HH_HIP(hipMemcpyAsync(h, res, (size_t)2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    for (int r = 0; r < nrhs; ++r) {
+        const double sr = h[2 * r], sb = h[2 * r + 1];
+        rel_host[r] = sb > 0.0 ? sqrt(sr / sb) : sqrt(sr);
+    }
+    return HH_OK;
+}
