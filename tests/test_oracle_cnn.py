@@ -189,6 +189,30 @@ def test_network_gradients_match_central_differences():
         assert best <= 1e-6, (k, best)
 
 
+def test_kappa_features_hand_computed():
+    # reading C13: the encoder sees [(omega h)^2 kappa^2, (omega h)^2 kappa^2 gamma].
+    # 4 x 4 grid, h = 1/4, omega = 8: (omega h)^2 = 4.  kappa = 0.5 except
+    # kappa[1, 2] = 0.25.  The 16-cell absorbing layer covers the whole grid:
+    # gamma = 1 on the edge ring (d = 0) and (15/16)^2 on the inner 2 x 2 (d = 1).
+    n, om = 4, 8.0
+    k = np.full((n, n), 0.5)
+    k[1, 2] = 0.25
+    P = H.Problem(k, om)
+    f = C.kappa_features(P.k2w2, P.gamma, P.h)
+    assert f.shape == (1, 2, n, n)
+    m = np.full((n, n), 1.0)   # 4 * 0.5^2
+    m[1, 2] = 0.25             # 4 * 0.25^2
+    g = np.ones((n, n))
+    g[1:3, 1:3] = (15.0 / 16.0) ** 2
+    assert np.allclose(f[0, 0], m, rtol=0, atol=1e-14)
+    assert np.allclose(f[0, 1], m * g, rtol=0, atol=1e-14)
+    # the same numbers are the scaled operator's diagonal (eq. 3, assembled):
+    # h^2 A_ii = 4 - (omega h)^2 kappa^2 (1 - i gamma)
+    d = P.matrix(0.0).diagonal().reshape(n, n) * P.h ** 2
+    assert np.allclose(f[0, 0], 4.0 - d.real, rtol=0, atol=1e-13)
+    assert np.allclose(f[0, 1], d.imag, rtol=0, atol=1e-13)
+
+
 def test_adam_first_step_closed_form():
     p = {"w": np.array([0.5, -1.0, 2.0]), "K": np.array([1 + 2j])}
     g = {"w": np.array([0.1, -3.0, 0.0]), "K": np.array([-0.5 + 0.25j])}

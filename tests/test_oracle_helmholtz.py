@@ -119,6 +119,23 @@ def test_coefficient_restriction_keeps_constants_at_edges():
     assert np.allclose(H.restrict_coeff(c), 0.7)
 
 
+def test_coefficient_restriction_hand_computed():
+    # reading C5: full weighting (1/16)[1 2 1; 2 4 2; 1 2 1] centred on fine
+    # (2I, 2J), the field padded by replicating its edge cells.  On c = 4i + j
+    # (4 x 4) the edge rows/columns carry weights 3/4 (edge) and 1/4 (next):
+    #   out[0,0] = (9 c00 + 3 c01 + 3 c10 + c11) / 16 = (0 + 3 + 12 + 5) / 16
+    #   out[0,1] = 3/4 (c01/4 + c02/2 + c03/4) + 1/4 (c11/4 + c12/2 + c13/4) = 3/4 * 2 + 1/4 * 6
+    #   out[1,0] = 3/4 (c10/4 + c20/2 + c30/4) + 1/4 (c11/4 + c21/2 + c31/4) = 3/4 * 8 + 1/4 * 9
+    #   out[1,1] = interior weights on a linear field: c22 = 10
+    c = np.array([[4.0 * i + j for j in range(4)] for i in range(4)])
+    assert np.allclose(H.restrict_coeff(c), [[1.25, 3.0], [8.25, 10.0]], rtol=0, atol=1e-15)
+    # injection would give [[0, 2], [8, 10]], zero padding 15/16 at (0, 0)
+    # interior weights on a quadratic: (1/4)(2I-1)^2 + (1/2)(2I)^2 + (1/4)(2I+1)^2 = 4 I^2 + 1/2
+    q = np.array([[float(i * i) for j in range(8)] for i in range(8)])
+    out = H.restrict_coeff(q)
+    assert np.allclose(out[1:, :], np.array([4.0 * I * I + 0.5 for I in range(1, 4)])[:, None], rtol=0, atol=1e-13)
+
+
 # --- relaxation -------------------------------------------------------------
 
 def test_jacobi_matches_assembled_diagonal():
