@@ -187,6 +187,33 @@ def network_flops(n: int) -> float:
     return f
 
 
+def network_bytes(n: int) -> float:
+    """HBM bytes of the convolution class per right-hand side and network
+    application when every BF16 activation is written once and read once by
+    the next layer (input layer: the complex64 residual and the first
+    encoding in, 16 channels at n/2 out; transposed layers also read their
+    skip input; the projection layer is not in the class)."""
+    from paper_2306_17486_amd import inputs
+    nc = n // 16 if n >= 512 else n // 8
+    out_size = {"s1": n // 2, "s2": n // 4, "s3": n // 8, "s4": nc, "u3": n // 8, "u2": n // 4, "u1": n // 2}
+    tin_size = {"u3": nc, "u2": n // 8, "u1": n // 4}
+    in_size = {"s1": n // 2, "s2": n // 2, "s3": n // 4, "s4": n // 8}
+    byt = 8.0 * n * n + 2.0 * 16 * (n // 2) ** 2 + 2.0 * 16 * (n // 2) ** 2  # input layer: v, E1, output
+    for name, kind, cin, cout in inputs.net_layers((16, 32, 64, 64)):
+        lvl = name.split("_")[0]
+        if lvl.startswith("enc") or name in ("s1_d", "out"):
+            continue
+        po = out_size[lvl] ** 2
+        if kind in ("t", "t4"):
+            byt += 2.0 * (tin_size[lvl] ** 2 * cin + 2 * po * cout)
+        else:
+            pi = (in_size[lvl] ** 2) if kind in ("d", "d4") else po
+            byt += 2.0 * (pi * cin + po * cout)
+            if kind in ("d", "d4") and lvl in ("s2", "s3"):
+                byt += 2.0 * po * cout  # the encoding added in
+    return byt
+
+
 def network_ceiling(n: int) -> float:
     """Fraction of the BF16 MFMA peak the network's convolutions can reach at
     most: every layer at the roofline min(peak, intensity x HBM bandwidth),
@@ -226,7 +253,6 @@ CLASS_SOURCES = {
     "ortho": ("krylov.hip", "hh_internal.h"),
     "vc_down": ("mg.hip", "hh_internal.h"),
     "vc_up": ("mg.hip", "hh_internal.h"),
-    "vc_coarse": ("mg.hip", "hh_internal.h"),
 }
 
 
@@ -242,9 +268,11 @@ def class_source_sha(cls: str) -> str | None:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cls: str):
-    """Bytes per launch of class `cls` from profiles/<cls>_cnn_mg_1024_64rhs_traffic.txt
-    (lines 'key: value'), or None when absent or taken on other kernel sources."""
+def measured_traffic(cls: str, active_rhs: float):
+    """HBM bytes per launch of class `cls` with `active_rhs` right-hand sides
+    active: the per-RHS traffic of profiles/<cls>_cnn_mg_1024_64rhs_traffic.txt
+    (lines 'key: value'; counters taken with every RHS active) times the
+    active count, or None when absent or taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{cls}_cnn_mg_1024_64rhs_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -257,7 +285,7 @@ def measured_traffic(cls: str):
     if kv.get("source_sha256_16") != class_source_sha(cls):
         return None
     try:
-        return int(float(kv["traffic_bytes_per_launch"]))
+        return int(float(kv["traffic_bytes_per_rhs"]) * active_rhs)
     except (KeyError, ValueError):
         return None
 
@@ -541,21 +569,30 @@ def main():
             total = ((rhs_iters - cnn_rhs_iters) * per_pt[kname] + cnn_rhs_iters * per_pt_cnn[kname]) * N \
                 + cnt * N * coef_pt[kname]
             ach = total / (ms / 1e3) / 1e9
+            act = rhs_iters / cnt if kname != "vc_coarse" else None
             classes[kname] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
+                              "frac": round(ach / HBM_PEAK_GBS, 4),
+                              "traffic": measured_traffic(kname, act) if act else None,
                               "avg_launch_us": round(ms / cnt * 1e3, 1),
                               "algorithmic_bytes_per_launch": int(total / cnt), "ms": round(ms, 2),
                               "launches": cnt}
         elif kname == "conv" and cnn_apps > 0:
+            # one "launch" of this class = one network application: its convolution
+            # kernels (three event scopes: input layer, down path, up path) over
+            # the right-hand sides active in it
+            apps = cnt // 3
             total = cnn_apps * net_flops
             ach = total / (ms / 1e3) / 1e12
             ceil = network_ceiling(n)
             classes[kname] = {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
                               "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4),
-                              "traffic": measured_traffic(kname),
-                              "avg_launch_us": round(ms / cnt * 1e3, 1),
-                              "algorithmic_flops_per_launch": int(total / cnt), "ms": round(ms, 2),
-                              "launches": cnt,
+                              "traffic": measured_traffic(kname, cnn_apps / apps),
+                              "algorithmic_bytes_per_launch": int(cnn_apps / apps * network_bytes(n)),
+                              "launch_unit": "network application (all its convolution kernels)",
+                              "avg_launch_us": round(ms / apps * 1e3, 1),
+                              "algorithmic_flops_per_launch": int(total / apps), "ms": round(ms, 2),
+                              "launches": apps, "event_scopes": cnt,
+                              "active_rhs_per_launch": round(cnn_apps / apps, 2),
                               # the layers' arithmetic intensities cap the class below the MFMA
                               # peak: the fraction attainable at the HBM roof, and ours of it
                               "intensity_ceiling_frac": round(ceil, 4),

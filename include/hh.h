@@ -45,7 +45,8 @@ enum {
     HH_ERR_HIP = -2,       /* a HIP runtime call or kernel launch failed */
     HH_ERR_NOMEM = -3,     /* the allocator returned NULL */
     HH_ERR_STATE = -4,     /* call not valid in the object's current state */
-    HH_ERR_BREAKDOWN = -5  /* NaN or Inf met in a solve */
+    HH_ERR_BREAKDOWN = -5  /* NaN or Inf met in a solve (outside the network: a non-finite
+                              network output switches that right-hand side to MG-only) */
 };
 
 enum { HH_MAX_LEVELS = 4, HH_MAX_RESTART = 16 };
@@ -140,7 +141,11 @@ typedef struct {
                            that one takes over if its cycle cut the residual more, otherwise
                            the previous one resumes and the wait before the next probe
                            doubles (2, 4, 8, ... cycles; a switch resets it).  0: CNN+MG
-                           in every cycle after the warm start. */
+                           in every cycle after the warm start.  Either way, a network
+                           application with a non-finite result ends its cycle: that
+                           cycle's directions are dropped (x keeps its last finite value;
+                           the applications count as iterations) and the right-hand side
+                           continues with MG-only. */
     double probe_ratio; /* default 0.5 */
     int graph;          /* 1 (default): a restart cycle's launch sequence (every kernel
                            from the first preconditioner application to the update of x)

@@ -52,17 +52,45 @@ def solve_two_phase(prob: H.Problem, netp: NetPrecond, b: np.ndarray, rtol=1e-6,
     preconditioner takes over; otherwise the previous one resumes, and the
     number of cycles before the next probe may run doubles (2, 4, 8, ...; a
     switch resets it).  ``stats`` (a dict, optional) receives ``probes`` and
-    ``mg_cycles`` (cycles after the warm start run with MG-only)."""
+    ``mg_cycles`` (cycles after the warm start run with MG-only).
+
+    A network application with a non-finite result ends its cycle at once:
+    that cycle's directions are dropped (x keeps its value from the cycle's
+    start; the applications made count as iterations) and the right-hand side
+    continues with MG-only (the failure rule of the library)."""
     x, its, hist, rel = H.fgmres(prob.A, b, prob.mg, None, restart, rtol, warm_iters)
-    cnn = lambda v: cnn_mg_precond(prob, netp, v)  # noqa: E731
+    apps = [0]
+
+    class _NonFinite(Exception):
+        pass
+
+    def cnn(v):
+        apps[0] += 1
+        z = cnn_mg_precond(prob, netp, v)
+        if not np.all(np.isfinite(z)):
+            raise _NonFinite()
+        return z
+
     cur, probing, q_base, wait, gap, probes, mg_cycles = "cnn", False, None, 0, 0, 0, 0
+    cnn_off = False
     while rel > rtol and its < max_iters:
         if cur == "mg":
             mg_cycles += 1
         rel0 = rel
-        x, its, h, rel = H.fgmres(prob.A, b, cnn if cur == "cnn" else prob.mg, x, restart, rtol, max_iters,
-                                  iters_done=its, cycles=1)
+        if cur == "cnn":
+            apps[0] = 0
+            try:
+                x, its, h, rel = H.fgmres(prob.A, b, cnn, x, restart, rtol, max_iters, iters_done=its, cycles=1)
+            except _NonFinite:
+                its += apps[0]
+                hist = hist + [rel0] * apps[0]
+                cur, cnn_off, probing = "mg", True, False
+                continue
+        else:
+            x, its, h, rel = H.fgmres(prob.A, b, prob.mg, x, restart, rtol, max_iters, iters_done=its, cycles=1)
         hist = hist + h[1:]
+        if cnn_off:
+            continue
         q = rel / rel0
         other = "mg" if cur == "cnn" else "cnn"
         if probing:

@@ -22,7 +22,7 @@ struct KState {
     int probe_wait, probe_gap;  // cycles before the next probe may run, and the next wait
     int mg_cycles;              // MG-only cycles after the warm start (probes included)
     int cnn_iters;              // iterations preconditioned by CNN+MG
-    int pad_;
+    int cnn_off;                // the network gave a non-finite result: MG-only from then on
     double res_cycle0;          // true relative residual at the start of the current cycle
     double q_base;              // residual reduction of the last cycle of the preconditioner in use
 };

@@ -329,9 +329,16 @@ __global__ void __launch_bounds__(256) k_givens(const double2* __restrict__ part
     if (S.mode == PM_CNN) S.cnn_iters += 1;
     const double est = sqrt(zabs2(S.g[j + 1])) / S.bnorm;
     S.res_est = est;
-    if (hist && S.iters < hist_len) hist[(size_t)r * hist_len + S.iters] = est;
-    bool bad = !(est == est) || !(hn == hn);
-    if (bad) S.breakdown = 1;
+    const bool bad = !isfinite(est) || !isfinite(hn);
+    if (bad && S.mode == PM_CNN) {
+        // a non-finite network output: this cycle's directions are dropped (x keeps
+        // its last finite value) and the right-hand side continues with MG-only
+        S.cnn_off = 1;
+        S.k = 0;
+    } else if (bad) {
+        S.breakdown = 1;
+    }
+    if (hist && S.iters < hist_len) hist[(size_t)r * hist_len + S.iters] = bad ? S.res_cycle0 : est;
     const bool by_est = est <= rtol * S.tol_scale;
     if (by_est) S.ended_by_est = 1;
     const int cap = caps ? min(caps[r], max_iters) : max_iters;
@@ -396,9 +403,14 @@ __global__ void k_init_state(const double2* __restrict__ parts, int npart, KStat
 // followed by one probe cycle of the other preconditioner; the probe's
 // preconditioner takes over if its cycle reduced the residual more, otherwise
 // the previous one resumes and the wait before the next probe doubles
-// (2, 4, 8, ... cycles; a switch resets it).
+// (2, 4, 8, ... cycles; a switch resets it).  A right-hand side on which the
+// network gave a non-finite result stays on MG-only.
 __device__ static int next_mode(KState& S, int warm, int judge, double probe_ratio) {
     if (warm) return PM_WARM;
+    if (S.cnn_off) {  // the network failed on this right-hand side
+        S.probing = 0;
+        return PM_MG;
+    }
     if (S.mode == PM_WARM) return PM_CNN;
     const double q = S.res_cycle0 > 0.0 ? S.res_true / S.res_cycle0 : 0.0;
     const int cur = S.mode, other = cur == PM_CNN ? PM_MG : PM_CNN;

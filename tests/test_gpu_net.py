@@ -280,6 +280,43 @@ def test_cnn_mg_judge_falls_back_for_a_bad_network(hh, ctx):
         assert info["iters"][r] <= its_mg + 2 * 10
 
 
+def test_cnn_mg_non_finite_network_falls_back_to_mg(hh, ctx):
+    # a NaN weight (forced from the host) makes every network output NaN: each
+    # right-hand side drops the cycle in which that happened, keeps its last
+    # finite iterate and goes on with MG-only; the solve succeeds and every
+    # count equals the oracle's under the same rule
+    n = 64
+    _say("cnn+mg with a NaN network weight")
+    k = inputs.grf_slowness(n, 32)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    p = inputs.init_net_params(8)
+    p["out.b"] = p["out.b"].copy()
+    p["out.b"][1] = np.nan
+    net = hh.Net(ctx, p)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.attach_net(net)
+    b = np.stack([inputs.point_source(n, 52), inputs.point_source(n, 53)])
+    x, info = m.solve(torch.from_numpy(b).to("cuda:0", torch.complex64), precond=hh.HH_PRECOND_CNN_MG)
+    assert info["status"] == hh.HH_OK
+    x = x.cpu().numpy()
+    netp = S.NetPrecond(C.Net(p), prob)
+    for r in range(2):
+        assert np.all(np.isfinite(x[r]))
+        rel = np.linalg.norm(b[r] - prob.A(x[r])) / np.linalg.norm(b[r])
+        st = {}
+        _, its_o, _, _ = S.solve_two_phase(prob, netp, b[r], stats=st)
+        _say(f"  rhs {r}: gpu {info['iters'][r]} (MG cycles {info['mg_cycles'][r]}, CNN iterations "
+             f"{info['cnn_iters'][r]}) oracle {its_o} {st}")
+        assert info["converged"][r] and rel <= 1e-6 * (1 + 1e-6)
+        assert info["cnn_iters"][r] == 1 and info["mg_cycles"][r] == st["mg_cycles"]
+        assert abs(int(info["iters"][r]) - its_o) <= 2
+    # the same model with a finite network afterwards: nothing left over
+    m.attach_net(hh.Net(ctx, inputs.init_net_params(8)))
+    _, info2 = m.solve(torch.from_numpy(b).to("cuda:0", torch.complex64), precond=hh.HH_PRECOND_CNN_MG)
+    assert info2["converged"].all() and (info2["cnn_iters"] > 1).all()
+
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("n,ninst", [(128, 1), (128, 2), (1024, 1)])
 def test_cnn_precond_equals_forward_then_vcycle(hh, ctx, n, ninst):

@@ -73,3 +73,36 @@ def test_without_the_judge_the_noisy_network_costs_far_more():
     _, its_fb, _, _ = S.solve_two_phase(prob, _Noise(1), b)
     _, its_no, _, _ = S.solve_two_phase(prob, _Noise(1), b, fallback=False, max_iters=4 * its_fb)
     assert its_no >= 2 * its_fb
+
+
+class _NaNAfter:
+    """A network whose output turns non-finite from its k-th application on."""
+
+    def __init__(self, k):
+        self.k, self.calls = k, 0
+
+    def __call__(self, r):
+        self.calls += 1
+        return np.full(r.shape, np.nan + 0j) if self.calls >= self.k else np.zeros_like(r)
+
+
+def test_non_finite_network_output_falls_back_to_mg_from_the_last_finite_iterate():
+    # the failure rule: the cycle with the non-finite application is dropped
+    # (its applications still count), x keeps the cycle's starting value and
+    # MG-only continues.  With a network that fails at once that is: 3 warm
+    # MG-only iterations, one wasted application, then MG-only FGMRES(10) from
+    # the warm iterate, counted on from 4.
+    prob = _problem()
+    b = inputs.point_source(N, 6)
+    st = {}
+    x, its, hist, rel = S.solve_two_phase(prob, _NaNAfter(1), b, stats=st)
+    xw, _, _, _ = H.fgmres(prob.A, b, prob.mg, None, 10, 1e-6, 3)
+    xe, its_e, _, rel_e = H.fgmres(prob.A, b, prob.mg, xw, 10, 1e-6, 2000, iters_done=4)
+    assert rel <= 1e-6 and np.all(np.isfinite(x))
+    assert its == its_e and np.array_equal(x, xe) and rel == rel_e
+    assert st["mg_cycles"] == -(-(its - 4) // 10) and st["probes"] == 0
+    # a network failing within a cycle: that cycle's earlier applications count too
+    st2 = {}
+    x2, its2, _, rel2 = S.solve_two_phase(prob, _NaNAfter(4), b, stats=st2)
+    xe2, its_e2, _, _ = H.fgmres(prob.A, b, prob.mg, xw, 10, 1e-6, 2000, iters_done=3 + 4)
+    assert its2 == its_e2 and np.array_equal(x2, xe2) and rel2 <= 1e-6
