@@ -271,6 +271,11 @@ hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const voi
  * ---------------------------------------------------------------------- */
 typedef struct {
     int ch[4];
+    int explicit_coarse;  /* 0 (the implicit U-Net): the coarsest level applies the Green's
+                             function of each learned kernel K_c (eqs. 16-17); 1 (the explicit
+                             U-Net of Sec. 5.2, the same network without the implicit step):
+                             it convolves with K_c itself, y = sum_{a,e} K_c[a][e]
+                             z[i - a + 1][j - e + 1].  Same parameters and layout. */
 } hh_net_desc;
 
 /* Create a network; params_host (host, nparams floats) may be NULL (zeros). */
@@ -281,7 +286,8 @@ size_t hh_net_num_params(const hh_net* net);
 /* Copy the FP32 master parameters to / from host memory (synchronous). */
 hh_status hh_net_get_params(hh_net* net, float* host);
 hh_status hh_net_set_params(hh_net* net, const float* host);
-/* Binary checkpoint: parameters, optimizer moments (when present) and step. */
+/* Binary checkpoint: the coarsest-layer kind, parameters, optimizer moments
+ * (when present) and step (files without the kind load as implicit). */
 hh_status hh_net_save(hh_net* net, const char* path);
 hh_status hh_net_load(hh_ctx* ctx, const char* path, hh_net** out);
 
@@ -340,8 +346,9 @@ hh_status hh_net_get_grads(hh_net* net, float* host);
  *   y_dev BF16 output, yf_dev optional FP32 output; active_host (host int[B],
  *   may be NULL = all): batch entries with 0 are skipped (their outputs are
  *   left untouched), as the solve skips converged right-hand sides.
- * hh_implicit_test: the implicit layer for coarsest size nc on BF16 NHWC
- *   [B][nc][nc][ch[3]] (adjoint = 1 multiplies by conj(Ghat)).
+ * hh_implicit_test: the network's coarsest layer for coarsest size nc on BF16
+ *   NHWC [B][nc][nc][ch[3]]: implicit (adjoint = 1 multiplies by conj(Ghat)) or,
+ *   for an explicit network, the convolution with K (adjoint = 1: its adjoint).
  * hh_wgrad_test: the weight-gradient kernel of the training pass,
  *   out[oo][ii][t] = sum over b and output pixels p of
  *   a[b][p][oo] * x[b][s*p + (t/3 - 1, t%3 - 1)][ii]   (zero outside x),

@@ -208,6 +208,46 @@ def implicit_direct(Gc, z):
 
 
 # ---------------------------------------------------------------------------
+# Explicit counterpart of the implicit layer (the "explicit U-Net" of Sec. 5.2:
+# the same network without the implicit step).  Reading: the coarsest step
+# multiplies by the learned kernel instead of inverting it (Sec. 4.2 contrasts
+# the inversion with a multiplication): each complex channel is convolved with
+# its own 3x3 kernel K_c, the operator whose least-squares inverse the implicit
+# layer applies, y[i, j] = sum_{a,e} K_c[a, e] z[i - a + 1, j - e + 1] (zero
+# outside the map).  Same parameters, same count.
+# ---------------------------------------------------------------------------
+
+def explicit_apply(K, z):
+    """y_c = K_c (*) z_c for z complex (B, k, m, m), K complex (k, 3, 3)."""
+    B, k, m, _ = z.shape
+    zp = np.zeros((B, k, m + 2, m + 2), dtype=np.complex128)
+    zp[:, :, 1:-1, 1:-1] = z
+    y = np.zeros((B, k, m, m), dtype=np.complex128)
+    for a in range(3):
+        for e in range(3):
+            # z[i - a + 1] = zp[i - a + 2]
+            y += K[None, :, a, e, None, None] * zp[:, :, 2 - a:2 - a + m, 2 - e:2 - e + m]
+    return y
+
+
+def explicit_backward(K, z, gy):
+    """(gz, gK) of y = explicit_apply(K, z) for the upstream gradient gy
+    (complex gradients d/dRe + i d/dIm): gz[m] = sum_d conj(K[d]) gy[m + d],
+    gK[d] = sum over the batch and the map of conj(z[i - d]) gy[i]."""
+    B, k, m, _ = z.shape
+    zp = np.zeros((B, k, m + 2, m + 2), dtype=np.complex128)
+    zp[:, :, 1:-1, 1:-1] = z
+    gzp = np.zeros_like(zp)
+    gK = np.zeros_like(K)
+    for a in range(3):
+        for e in range(3):
+            sl = (slice(None), slice(None), slice(2 - a, 2 - a + m), slice(2 - e, 2 - e + m))
+            gzp[sl] += np.conj(K[None, :, a, e, None, None]) * gy
+            gK[:, a, e] = np.sum(np.conj(zp[sl]) * gy, axis=(0, 2, 3))
+    return gzp[:, :, 1:-1, 1:-1].copy(), gK
+
+
+# ---------------------------------------------------------------------------
 # Network
 # ---------------------------------------------------------------------------
 
@@ -229,8 +269,11 @@ def kappa_features(k2w2: np.ndarray, gamma: np.ndarray, h: float) -> np.ndarray:
 class Net:
     """Encoder-solver network with its FP64 parameters ``p`` (see inputs.net_layers)."""
 
-    def __init__(self, params: dict[str, np.ndarray]):
+    def __init__(self, params: dict[str, np.ndarray], explicit: bool = False):
+        """explicit: the coarsest step multiplies by K (explicit U-Net) instead of
+        applying its Green's function (implicit U-Net)."""
         self.p = {k: np.array(v, copy=True) for k, v in params.items()}
+        self.explicit = explicit
 
     # ---- encoder --------------------------------------------------------
     def encode(self, kin):
@@ -291,8 +334,12 @@ class Net:
             downs.append(h2)
             x = h2
         z = pair(x)
-        y, Z = implicit_apply(Ghat, z)
-        c["imp"] = (Z,)
+        if self.explicit:
+            y = explicit_apply(p["implicit_K"], z)
+            c["imp"] = (z,)
+        else:
+            y, Z = implicit_apply(Ghat, z)
+            c["imp"] = (Z,)
         x = unpair(y)
         for lvl, skip in ((3, downs[2]), (2, downs[1]), (1, downs[0])):
             pre = f"u{lvl}"
@@ -327,8 +374,12 @@ class Net:
             gh0, g[pre + "_c1.w"], g[pre + "_c1.b"] = conv2d_backward(h0, p[pre + "_c1.w"], gh1p)
             gskip[lvl] = gh0
             gx, g[pre + "_t.w"], g[pre + "_t.b"] = conv_transpose2d_backward(x, p[pre + "_t.w"], gh0, st)
-        (Z,) = cache["imp"]
-        gz, gGhat = implicit_backward(Ghat, Z, pair(gx))
+        if self.explicit:
+            (z,) = cache["imp"]
+            gz, gGhat = explicit_backward(p["implicit_K"], z, pair(gx))  # here gGhat is dL/dK itself
+        else:
+            (Z,) = cache["imp"]
+            gz, gGhat = implicit_backward(Ghat, Z, pair(gx))
         gx = unpair(gz)
         gE = [None, None, None]
         for lvl in (4, 3, 2, 1):
@@ -350,7 +401,7 @@ class Net:
         """Encoder + solver on a batch (each sample with its own kappa features)."""
         n = rin.shape[2]
         nc = coarsest_size(n)
-        Ghat, gaux = green_hat(self.p["implicit_K"], nc)
+        Ghat, gaux = (None, None) if self.explicit else green_hat(self.p["implicit_K"], nc)
         enc, ecache = self.encode(kin)
         out, scache = self.solve(rin, enc, Ghat)
         return out, (Ghat, gaux, ecache, scache, nc)
@@ -359,7 +410,7 @@ class Net:
         Ghat, gaux, ecache, scache, nc = cache
         g, gGhat, gE = self.solve_backward(scache, gout, Ghat)
         g.update(self.encode_backward(ecache, gE))
-        g["implicit_K"] = green_hat_backward(self.p["implicit_K"], nc, gGhat, gaux)
+        g["implicit_K"] = gGhat if self.explicit else green_hat_backward(self.p["implicit_K"], nc, gGhat, gaux)
         return g
 
 

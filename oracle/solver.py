@@ -21,7 +21,7 @@ class NetPrecond:
         kin = C.kappa_features(prob.k2w2, prob.gamma, prob.h)
         self.enc, _ = net.encode(kin)
         self.nc = C.coarsest_size(prob.n)
-        self.Ghat, _ = C.green_hat(net.p["implicit_K"], self.nc)
+        self.Ghat = None if net.explicit else C.green_hat(net.p["implicit_K"], self.nc)[0]
 
     def __call__(self, r: np.ndarray) -> np.ndarray:
         """e = s * Net(h^2 r / s), s = rms(h^2 r) (single right-hand side)."""

@@ -46,6 +46,7 @@ struct hh_net {
     hh_ctx* ctx = nullptr;
     int ch[4] = {16, 32, 64, 64};
     int nk = 32;                            // complex channels of the implicit layer (= ch[3] / 2)
+    int explicit_coarse = 0;                // 1: the coarsest layer multiplies by K instead of inverting it
     hh::LayerInfo L[hh::NET_LAYERS];
     size_t koff = 0;                        // offset of the implicit kernels (nk x 3 x 3 complex)
     size_t nparams = 0;                     // floats
@@ -57,6 +58,8 @@ struct hh_net {
     bool packed_valid = false;
     long long step = 0;
     unsigned long long version = 1;         // bumped whenever the parameters change
+    unsigned long long uid = 0;             // unique per network of the process (caches key on it, not on
+                                            // the address, which a later network may reuse)
     void* train_work = nullptr;             // training workspace (net.hip)
     ~hh_net();
 };

@@ -8,6 +8,8 @@
 
 #include <new>
 
+#include <atomic>
+
 #include "net.h"
 
 namespace hh {
@@ -573,6 +575,108 @@ hh_status launch_implicit(hipStream_t st, int M, const uint16_t* x, uint16_t* y,
 }
 
 // ---------------------------------------------------------------------------
+// Explicit coarsest layer (the explicit U-Net of Sec. 5.2): each complex channel
+// c (real channels 2c, 2c+1) is convolved with its 3x3 kernel K_c instead of
+// being mapped through K_c's Green's function:
+//   y[i][j] = sum_{a,e} K_c[a][e] z[i - a + 1][j - e + 1]   (zero outside the map)
+// ADJ: the adjoint, gz[i][j] = sum_{a,e} conj(K_c[a][e]) gy[i + a - 1][j + e - 1],
+// zeroed where mask <= 0 (the ReLU derivative of the layer below).  One thread
+// per pixel and complex channel; BF16 NHWC in and out, FP32 arithmetic.
+// ---------------------------------------------------------------------------
+template <bool ADJ>
+__global__ void __launch_bounds__(256) k_explicit(const uint16_t* __restrict__ x, uint16_t* __restrict__ y,
+                                                  const float* __restrict__ K, int m, int nk,
+                                                  const uint16_t* __restrict__ mask, const int* __restrict__ active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= m * m * nk) return;
+    const int c = t % nk, pix = t / nk;
+    const int i = pix / m, j = pix - i * m;
+    const int C2 = 2 * nk;
+    const uint16_t* xb = x + (size_t)b * m * m * C2;
+    float yr = 0.f, yi = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int si = ADJ ? i + a - 1 : i - a + 1, sj = ADJ ? j + e - 1 : j - e + 1;
+            if (si < 0 || si >= m || sj < 0 || sj >= m) continue;
+            const uint32_t v = *reinterpret_cast<const uint32_t*>(xb + ((size_t)si * m + sj) * C2 + 2 * c);
+            const float zr = bf2f((uint16_t)(v & 0xffff)), zi = bf2f((uint16_t)(v >> 16));
+            const float kr = K[(c * 9 + a * 3 + e) * 2], ki = ADJ ? -K[(c * 9 + a * 3 + e) * 2 + 1]
+                                                                  : K[(c * 9 + a * 3 + e) * 2 + 1];
+            yr += kr * zr - ki * zi;
+            yi += kr * zi + ki * zr;
+        }
+    const size_t po = ((size_t)b * m * m + pix) * C2 + 2 * c;
+    if (mask) {
+        const uint32_t mv = *reinterpret_cast<const uint32_t*>(mask + po);
+        if (!(bf2f((uint16_t)(mv & 0xffff)) > 0.f)) yr = 0.f;
+        if (!(bf2f((uint16_t)(mv >> 16)) > 0.f)) yi = 0.f;
+    }
+    *reinterpret_cast<uint32_t*>(y + po) = (uint32_t)f2bf(yr) | ((uint32_t)f2bf(yi) << 16);
+}
+
+// Kernel gradient of the explicit layer, per block of EK_PIX pixels of one
+// sample: part[b][blk][c * 9 + tap] = sum over the block's pixels p of
+// conj(z[p - d_tap]) gy[p] (FP64), d_tap = (a - 1, e - 1).  One thread per
+// (channel, tap) pair.
+constexpr int EK_PIX = 256;
+__global__ void __launch_bounds__(320) k_explicit_kgrad(const uint16_t* __restrict__ z, const uint16_t* __restrict__ gy,
+                                                        int m, int nk, double2* __restrict__ part) {
+    const int b = blockIdx.y, blk = blockIdx.x;
+    const int t = threadIdx.x;
+    const int nblk = gridDim.x;
+    if (t >= nk * 9) return;
+    const int c = t / 9, tap = t - 9 * c, a = tap / 3, e = tap - 3 * a;
+    const int C2 = 2 * nk;
+    const uint16_t* zb = z + (size_t)b * m * m * C2;
+    const uint16_t* gb = gy + (size_t)b * m * m * C2;
+    double sr = 0.0, si = 0.0;
+    const int p0 = blk * EK_PIX, p1 = min(p0 + EK_PIX, m * m);
+    for (int p = p0; p < p1; ++p) {
+        const int i = p / m, j = p - i * m;
+        const int zi_ = i - a + 1, zj_ = j - e + 1;
+        if (zi_ < 0 || zi_ >= m || zj_ < 0 || zj_ >= m) continue;
+        const uint32_t zv = *reinterpret_cast<const uint32_t*>(zb + ((size_t)zi_ * m + zj_) * C2 + 2 * c);
+        const uint32_t gv = *reinterpret_cast<const uint32_t*>(gb + (size_t)p * C2 + 2 * c);
+        const double zr = bf2f((uint16_t)(zv & 0xffff)), zim = bf2f((uint16_t)(zv >> 16));
+        const double gr = bf2f((uint16_t)(gv & 0xffff)), gim = bf2f((uint16_t)(gv >> 16));
+        // conj(z) * gy
+        sr += zr * gr + zim * gim;
+        si += zr * gim - zim * gr;
+    }
+    part[((size_t)b * nblk + blk) * (nk * 9) + t] = make_double2(sr, si);
+}
+
+// gK[c][tap] = sum of the partials (fixed order), stored as (d/dRe, d/dIm) floats
+__global__ void k_explicit_kgrad_reduce(const double2* __restrict__ part, int nrows, int count,
+                                        float* __restrict__ gK) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    double sr = 0.0, si = 0.0;
+    for (int r = 0; r < nrows; ++r) {
+        const double2 v = part[(size_t)r * count + t];
+        sr += v.x;
+        si += v.y;
+    }
+    gK[2 * t] = (float)sr;
+    gK[2 * t + 1] = (float)si;
+}
+
+hh_status launch_explicit(hipStream_t st, const uint16_t* x, uint16_t* y, const float* K, int m, int nk, int B,
+                          bool adjoint, const int* active, const uint16_t* mask) {
+    const dim3 grd((m * m * nk + 255) / 256, B);
+    if (adjoint)
+        hipLaunchKernelGGL(k_explicit<true>, grd, dim3(256), 0, st, x, y, K, m, nk, mask, active);
+    else
+        hipLaunchKernelGGL(k_explicit<false>, grd, dim3(256), 0, st, x, y, K, m, nk, mask, active);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Green's function of the implicit kernels (eq. 17), FP64.
 //   S[c][p][q] = conj(K^)/(|K^|^2 + eps) * F(delta)[p][q],  F(delta) = (-1)^(p+q)
 //   G = IFFT_N(S) on the crop [N/2 - nc, N/2 + nc)^2 only, Ghat = FFT_M(ifftshift(G))
@@ -766,6 +870,7 @@ struct NetActs {
 // ---------------------------------------------------------------------------
 struct NetCache {
     hh_net* net = nullptr;
+    unsigned long long uid = 0;      // the network the cache was built for (0: none)
     unsigned long long version = 0;
     int n = 0, nc = 0, M = 0;
     Buf enc[9];    // BF16 outputs of the 9 encoder layers per instance (E1, E2, E3 = enc[2], enc[5], enc[8])
@@ -844,7 +949,12 @@ hh_status net_prepare_model(hh_model* md) {
         }
         md->netcache = nc;
     }
-    if (nc->net == net && nc->version == net->version && nc->n == md->lev[0].n) return HH_OK;
+    HH_TRY(net_pack(net));
+    if (nc->uid == net->uid && nc->version == net->version && nc->n == md->lev[0].n) {
+        nc->net = net;
+        return HH_OK;
+    }
+    nc->uid = 0;  // invalid until rebuilt below
     const int n = md->lev[0].n;
     if (n % 16 != 0) {
         set_error("the network needs n divisible by 16 (n = %d)", n);
@@ -855,13 +965,14 @@ hh_status net_prepare_model(hh_model* md) {
     nc->nc = coarsest_of(n);
     nc->M = 2 * nc->nc;
     HH_TRY(nc->Gbr.ensure(net->ctx, (size_t)net->nk * nc->M * nc->M * sizeof(float2)));
-    HH_TRY(green_forward(net, nc->nc, nc->Gbr.as<float2>(), 1e-5));
+    if (!net->explicit_coarse) HH_TRY(green_forward(net, nc->nc, nc->Gbr.as<float2>(), 1e-5));
     if (net->ch[0] != 16) {
         set_error("first-level channel count must be 16");
         return HH_ERR_ARG;
     }
     HH_TRY(encoder_forward(net, md, nc->enc));
     nc->net = net;
+    nc->uid = net->uid;
     nc->version = net->version;
     return HH_OK;
 }
@@ -918,8 +1029,12 @@ hh_status net_forward_core(hh_net* net, int n, double h, NetActs& A, int B, cons
     }
     {
         ProfScope ps(net->ctx, HH_K_NET_OTHER);
-        HH_TRY(launch_implicit(st, 2 * m4, act(L_S4_C2), A.imp.as<uint16_t>(), Gbr, m4, net->nk, B, false, active,
-                               nullptr, A.impw.as<float2>()));
+        if (net->explicit_coarse)
+            HH_TRY(launch_explicit(st, act(L_S4_C2), A.imp.as<uint16_t>(), P + net->koff, m4, net->nk, B, false,
+                                   active, nullptr));
+        else
+            HH_TRY(launch_implicit(st, 2 * m4, act(L_S4_C2), A.imp.as<uint16_t>(), Gbr, m4, net->nk, B, false,
+                                   active, nullptr, A.impw.as<float2>()));
     }
     {
         ProfScope ps(net->ctx, HH_K_CONV);
@@ -1626,7 +1741,7 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
     const double h = md->lev[0].h;
     const int nc = coarsest_of(n), M = 2 * nc;
     HH_TRY(T.Gbr.ensure(ctx, (size_t)net->nk * M * M * sizeof(float2)));
-    HH_TRY(green_forward(net, nc, T.Gbr.as<float2>(), 1e-5));
+    if (!net->explicit_coarse) HH_TRY(green_forward(net, nc, T.Gbr.as<float2>(), 1e-5));
     HH_TRY(encoder_forward(net, md, T.enc));
     NetActs& A = T.acts;
     HH_TRY(A.ensure(net, B, n));
@@ -1702,7 +1817,19 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
     HH_TRY(wgrad_convT(L_U3_T, s4 == 2 ? CM_S2 : CM_S1, A.imp.as<uint16_t>(), m4, m3));
     HH_TRY(dgrad_layer(net, L_U3_T, s4 == 2 ? CM_S2 : CM_S1, G(L_U3_T), B, m3, m3, T.gimp.as<uint16_t>(), m4, m4,
                        nullptr, nullptr));
-    // ---- implicit layer: input gradient (adjoint, masked) and kernel gradient
+    // ---- coarsest layer: input gradient (adjoint, masked) and kernel gradient
+    if (net->explicit_coarse) {
+        HH_TRY(launch_explicit(st, T.gimp.as<uint16_t>(), G(L_S4_C2), P + net->koff, m4, net->nk, B, true, nullptr,
+                               act(L_S4_C2)));
+        const int nblk = (m4 * m4 + EK_PIX - 1) / EK_PIX, count = net->nk * 9;
+        HH_TRY(T.gGh_part.ensure(ctx, (size_t)B * nblk * count * sizeof(double2)));
+        hipLaunchKernelGGL(k_explicit_kgrad, dim3(nblk, B), dim3(320), 0, st, act(L_S4_C2), T.gimp.as<uint16_t>(), m4,
+                           net->nk, T.gGh_part.as<double2>());
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_explicit_kgrad_reduce, dim3((count + 255) / 256), dim3(256), 0, st,
+                           T.gGh_part.as<double2>(), B * nblk, count, GR + net->koff);
+        HH_LAUNCH_CHECK();
+    } else {
     HH_TRY(launch_implicit(st, M, T.gimp.as<uint16_t>(), G(L_S4_C2), T.Gbr.as<float2>(), m4, net->nk, B, true,
                            nullptr, act(L_S4_C2)));
     {
@@ -1735,6 +1862,7 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
                            count, T.gGh.as<double2>());
         HH_LAUNCH_CHECK();
         HH_TRY(green_backward(net, nc, T.gGh.as<double2>(), GR + net->koff, 1e-5));
+    }
     }
     // ---- down path, level 4
     HH_TRY(wgrad_conv(L_S4_C2, CM_S1, act(L_S4_C1), m4, m4, m4, m4));
@@ -1938,6 +2066,7 @@ hh_status hh_net_create(hh_ctx* ctx, const hh_net_desc* d, const float* params_h
     HH_ARG(ctx && d && out, "null pointer");
     *out = nullptr;
     HH_ARG(valid_channels(d->ch), "channels must be (16, 32, 64, 64)");
+    HH_ARG(d->explicit_coarse == 0 || d->explicit_coarse == 1, "explicit_coarse is 0 or 1");
     HH_HIP(hipSetDevice(ctx->device));
     hh_net* net = new (std::nothrow) hh_net();
     if (!net) {
@@ -1945,7 +2074,12 @@ hh_status hh_net_create(hh_ctx* ctx, const hh_net_desc* d, const float* params_h
         return HH_ERR_NOMEM;
     }
     net->ctx = ctx;
+    {
+        static std::atomic<unsigned long long> next_uid{1};
+        net->uid = next_uid.fetch_add(1);
+    }
     for (int i = 0; i < 4; ++i) net->ch[i] = d->ch[i];
+    net->explicit_coarse = d->explicit_coarse ? 1 : 0;
     build_table(net);
     hh_status s = net->params.ensure(ctx, net->nparams * sizeof(float));
     if (s >= 0 && params_host) {
@@ -1989,7 +2123,9 @@ hh_status hh_net_destroy(hh_net* net) {
     return HH_OK;
 }
 
-static const char kMagic[8] = {'H', 'H', 'N', 'E', 'T', '0', '0', '1'};
+// file format 1: no coarsest-layer kind (implicit); 2: an int after the channels
+static const char kMagic[8] = {'H', 'H', 'N', 'E', 'T', '0', '0', '2'};
+static const char kMagic1[8] = {'H', 'H', 'N', 'E', 'T', '0', '0', '1'};
 
 hh_status hh_net_save(hh_net* net, const char* path) {
     HH_ARG(net && path, "null pointer");
@@ -2009,7 +2145,7 @@ hh_status hh_net_save(hh_net* net, const char* path) {
     }
     const long long np = (long long)net->nparams, step = net->step;
     bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(net->ch, sizeof(int), 4, f) == 4 &&
-              fwrite(&np, sizeof(np), 1, f) == 1 && fwrite(&step, sizeof(step), 1, f) == 1 &&
+              fwrite(&net->explicit_coarse, sizeof(int), 1, f) == 1 && fwrite(&np, sizeof(np), 1, f) == 1 && fwrite(&step, sizeof(step), 1, f) == 1 &&
               fwrite(&have_adam, sizeof(int), 1, f) == 1 && fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
     if (ok && have_adam)
         ok = fwrite(m.data(), sizeof(float), m.size(), f) == m.size() &&
@@ -2034,9 +2170,12 @@ hh_status hh_net_load(hh_ctx* ctx, const char* path, hh_net** out) {
     hh_net_desc d;
     long long np = 0, step = 0;
     int have_adam = 0;
-    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMagic, 8) == 0 && fread(d.ch, sizeof(int), 4, f) == 4 &&
-              fread(&np, sizeof(np), 1, f) == 1 && fread(&step, sizeof(step), 1, f) == 1 &&
-              fread(&have_adam, sizeof(int), 1, f) == 1;
+    d.explicit_coarse = 0;
+    bool ok = fread(magic, 1, 8, f) == 8 && (memcmp(magic, kMagic, 8) == 0 || memcmp(magic, kMagic1, 8) == 0) &&
+              fread(d.ch, sizeof(int), 4, f) == 4;
+    if (ok && memcmp(magic, kMagic, 8) == 0) ok = fread(&d.explicit_coarse, sizeof(int), 1, f) == 1;
+    ok = ok && fread(&np, sizeof(np), 1, f) == 1 && fread(&step, sizeof(step), 1, f) == 1 &&
+         fread(&have_adam, sizeof(int), 1, f) == 1;
     std::vector<float> p, m, v;
     if (ok && np > 0 && np < (1LL << 30)) {
         p.resize((size_t)np);
@@ -2175,6 +2314,12 @@ hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, in
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint) {
     HH_ARG(net && x_dev && y_dev, "null pointer");
     HH_HIP(hipSetDevice(net->ctx->device));
+    if (net->explicit_coarse) {
+        HH_TRY(launch_explicit(net->ctx->stream, (const uint16_t*)x_dev, (uint16_t*)y_dev,
+                               net->params.as<float>() + net->koff, nc, net->nk, B, adjoint != 0, nullptr, nullptr));
+        HH_HIP(hipStreamSynchronize(net->ctx->stream));
+        return HH_OK;
+    }
     Buf G, Wk;
     const int M = 2 * nc;
     HH_TRY(G.ensure(net->ctx, (size_t)net->nk * M * M * sizeof(float2)));

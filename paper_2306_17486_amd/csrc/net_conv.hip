@@ -244,6 +244,176 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
 }
 
 // ---------------------------------------------------------------------------
+// The same convolution (S1 / S2) with the input patch copied from HBM straight
+// into LDS by buffer loads (buffer_load_dwordx4 ... lds: 16 bytes per lane,
+// no VGPR staging), so that tiles can be taller without the registers the
+// prefetch above needs.  Out-of-range offsets read as zero (the buffer's
+// range check), which gives the zero padding.
+//
+// LDS layout: slot q = 16 bytes; pixel P of the patch owns slots P*S .. P*S+S-1
+// (S = CIN/8 vectors of 8 channels), vector j stored in slot P*S + (j ^ f(P)),
+// f(P) = (P / (16/S)) mod S.  A B-operand read takes vector j of 16
+// consecutive pixels; P mod 16 decides both the 256-byte bank row offset and
+// the swizzle, so those 16 reads hit 16 distinct 16-byte bank groups.
+// Each wave's buffer load fills 64 consecutive slots (lane l -> slot base + l);
+// the lane loads whatever vector that slot holds under the swizzle.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int MODE, int TR_>
+struct DmaCfg {
+    static constexpr int TC = 32;                                   // output tile columns
+    static constexpr int TR = TR_;                                  // output tile rows
+    static constexpr int NT = COUT / 16;                            // channel tiles
+    static constexpr int NCH = (9 * CIN + 31) / 32;                 // k chunks
+    static constexpr int CT = (NT >= 2 && 2 * NCH <= 18) ? 2 : 1;   // channel tiles per wave
+    static constexpr int NG = NT / CT;                              // channel groups
+    static constexpr int WPT = 4 / NG;                              // waves per channel group
+    static constexpr int PB = TR * (TC / 16);                       // 16-pixel blocks per tile
+    static constexpr int PBW = PB / WPT;                            // pixel blocks per wave
+    static constexpr int PH = (MODE == CM_S2) ? 2 * TR + 1 : TR + 2;
+    static constexpr int PW = (MODE == CM_S2) ? 2 * TC + 1 : TC + 2;
+    static constexpr int S = CIN / 8;                               // 16-byte vectors per pixel
+    static constexpr int SH = S == 2 ? 3 : (S == 4 ? 2 : 1);        // log2(16 / S)
+    static constexpr int NSLOT = PH * PW * S;
+    static constexpr int NROUND = (NSLOT + 255) / 256;
+    static_assert(S == 2 || S == 4 || S == 8, "16, 32 or 64 input channels");
+    static_assert(PB % WPT == 0, "pixel blocks shared evenly");
+    static_assert(NROUND <= 15, "buffer loads per thread fit the vmcnt wait immediate");
+};
+
+__device__ __forceinline__ int dma_slot(int P, int j, int S, int SH) { return P * S + (j ^ ((P >> SH) & (S - 1))); }
+
+template <int CIN, int COUT, int MODE, int TR>
+__global__ void __launch_bounds__(256) k_conv_dma(ConvArgs a) {
+    using C = DmaCfg<CIN, COUT, MODE, TR>;
+    __shared__ __attribute__((aligned(16))) uint4 s_in[C::NROUND * 256];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int cg = wave % C::NG;
+    const int wsub = wave / C::NG;
+    const int lp = lane & 15, lg = lane >> 4;
+
+    bf16x8 wreg[C::CT][C::NCH];
+    {
+        const uint4* wp4 = reinterpret_cast<const uint4*>(a.wp);
+#pragma unroll
+        for (int c = 0; c < C::CT; ++c)
+#pragma unroll
+            for (int ch = 0; ch < C::NCH; ++ch) {
+                uint4 v = wp4[((size_t)ch * COUT + (cg * C::CT + c) * 16 + lp) * 4 + lg];
+                wreg[c][ch] = *reinterpret_cast<bf16x8*>(&v);
+            }
+    }
+    float bias4[C::CT][4];
+#pragma unroll
+    for (int c = 0; c < C::CT; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias4[c][i] = a.bias ? a.bias[(cg * C::CT + c) * 16 + 4 * lg + i] : 0.f;
+
+    const int per_b = a.tiles_x * a.tiles_y;
+    const uint32_t bytes_b = (uint32_t)a.Hin * a.Win * CIN * 2;
+    auto next_active = [&](int t) {
+        while (t < a.ntiles && a.active && !a.active[t / per_b]) t += gridDim.x;
+        return t;
+    };
+    int tile = next_active(blockIdx.x);
+    while (tile < a.ntiles) {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const int y0 = ty * C::TR, x0 = tx * C::TC;
+        const int nxt = next_active(tile + gridDim.x);
+        __syncthreads();  // the previous tile's readers are done with s_in
+        {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(a.x + (size_t)b * a.Hin * a.Win * CIN), (short)0, (int)bytes_b, 0x00020000);
+#pragma unroll
+            for (int r = 0; r < C::NROUND; ++r) {
+                const int q = r * 256 + tid;
+                const int P = q / C::S, jp = q - P * C::S;
+                const int j = jp ^ ((P >> C::SH) & (C::S - 1));
+                const int py = P / C::PW, px = P - py * C::PW;
+                const int iy = (MODE == CM_S2 ? 2 * y0 : y0) - 1 + py;
+                const int ix = (MODE == CM_S2 ? 2 * x0 : x0) - 1 + px;
+                const bool in = q < C::NSLOT && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+                const int off = in ? ((iy * a.Win + ix) * CIN + 8 * j) * 2 : 0x7ffffff0;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void*)(s_in + r * 256 + wave * 64), 16, off, 0, 0, 0);
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+        __syncthreads();
+        f32x4 acc[C::PBW][C::CT];
+#pragma unroll
+        for (int q = 0; q < C::PBW; ++q)
+#pragma unroll
+            for (int c = 0; c < C::CT; ++c) acc[q][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < C::NCH; ++ch) {
+            const int k0 = ch * 32 + 8 * lg;
+            const int tap = k0 / CIN, ci = k0 % CIN;
+            const int ky = tap / 3, kx = tap - 3 * ky;
+#pragma unroll
+            for (int q = 0; q < C::PBW; ++q) {
+                const int pbk = wsub * C::PBW + q;
+                const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
+                bf16x8 bv;
+                if (tap < 9) {
+                    const int sy = (MODE == CM_S2 ? 2 * ry : ry) + ky;
+                    const int sx = (MODE == CM_S2 ? 2 * rx : rx) + kx;
+                    const uint4 raw = s_in[dma_slot(sy * C::PW + sx, ci >> 3, C::S, C::SH)];
+                    bv = *reinterpret_cast<const bf16x8*>(&raw);
+                } else {
+                    const uint4 z = make_uint4(0, 0, 0, 0);
+                    bv = *reinterpret_cast<const bf16x8*>(&z);
+                }
+#pragma unroll
+                for (int c = 0; c < C::CT; ++c)
+                    acc[q][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[c][ch], bv, acc[q][c], 0, 0, 0);
+            }
+        }
+        const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
+#pragma unroll
+        for (int q = 0; q < C::PBW; ++q)
+#pragma unroll
+            for (int c = 0; c < C::CT; ++c) {
+                const int co = (cg * C::CT + c) * 16 + 4 * lg;
+                const int pbk = wsub * C::PBW + q;
+                const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
+                const int oy = y0 + ry, ox = x0 + rx;
+                if (oy >= a.Hout || ox >= a.Wout) continue;
+                const size_t po = (((size_t)b * a.Hout + oy) * a.Wout + ox) * COUT + co;
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = acc[q][c][i] + bias4[c][i];
+                if (a.skip) {
+                    const size_t so = (((size_t)sb * a.Hout + oy) * a.Wout + ox) * COUT + co;
+                    uint2 s2 = *reinterpret_cast<const uint2*>(a.skip + so);
+                    v[0] += bf2f((uint16_t)(s2.x & 0xffff));
+                    v[1] += bf2f((uint16_t)(s2.x >> 16));
+                    v[2] += bf2f((uint16_t)(s2.y & 0xffff));
+                    v[3] += bf2f((uint16_t)(s2.y >> 16));
+                }
+                if (a.relu)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
+                if (a.mask) {
+                    uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
+                    if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
+                    if (!(bf2f((uint16_t)(m2.x >> 16)) > 0.f)) v[1] = 0.f;
+                    if (!(bf2f((uint16_t)(m2.y & 0xffff)) > 0.f)) v[2] = 0.f;
+                    if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
+                }
+                uint2 o2;
+                o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+                o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+                *reinterpret_cast<uint2*>(a.y + po) = o2;
+                if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        tile = nxt;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Stride-2 transposed convolution by output parity.  With u the zero-interleaved
 // input (u[2i][2j] = x[i][j]), out[oy][ox] = sum_t Wg[t] u[oy + ky - 1][ox + kx - 1]
 // only meets nonzero u where oy + ky - 1 and ox + kx - 1 are even: an even output
@@ -443,17 +613,40 @@ static hh_status launch_t2_t(hipStream_t st, ConvArgs a, int num_cus) {
     return HH_OK;
 }
 
-template <int CIN, int COUT, int MODE>
-static hh_status launch_conv_t(hipStream_t st, ConvArgs a, int num_cus) {
-    using C = ConvCfg<CIN, COUT, MODE>;
+// stride-2 layers: the direct-to-LDS kernel (measured at the 1024^2 network's
+// shapes, 42 right-hand sides: 16 -> 32 121 -> 112 us, 32 -> 64 74 -> 68 us,
+// 64 -> 64 48 -> 34 us); the stride-1 layers keep the register-prefetch
+// kernel, which overlaps the next tile's loads with the MFMAs and was faster
+// there (16 -> 16 181 against 185-224 us, 32 -> 32 113 against 122-131 us).
+template <int CIN, int COUT>
+static hh_status launch_conv_s2_dma(hipStream_t st, ConvArgs a, int num_cus) {
+    constexpr int TR = CIN >= 32 ? 2 : 4;
+    using C = DmaCfg<CIN, COUT, CM_S2, TR>;
     a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
     a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
     a.ntiles = a.B * a.tiles_x * a.tiles_y;
     if (a.ntiles == 0) return HH_OK;
     const int grid = std::min(a.ntiles, 8 * num_cus);
-    hipLaunchKernelGGL((k_conv_mfma<CIN, COUT, MODE>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_conv_dma<CIN, COUT, CM_S2, TR>), dim3(grid), dim3(256), 0, st, a);
     HH_LAUNCH_CHECK();
     return HH_OK;
+}
+
+template <int CIN, int COUT, int MODE>
+static hh_status launch_conv_t(hipStream_t st, ConvArgs a, int num_cus) {
+    if constexpr (MODE == CM_S2) {
+        return launch_conv_s2_dma<CIN, COUT>(st, a, num_cus);
+    } else {
+        using C = ConvCfg<CIN, COUT, MODE>;
+        a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
+        a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
+        a.ntiles = a.B * a.tiles_x * a.tiles_y;
+        if (a.ntiles == 0) return HH_OK;
+        const int grid = std::min(a.ntiles, 8 * num_cus);
+        hipLaunchKernelGGL((k_conv_mfma<CIN, COUT, MODE>), dim3(grid), dim3(256), 0, st, a);
+        HH_LAUNCH_CHECK();
+        return HH_OK;
+    }
 }
 
 hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a) {

@@ -84,7 +84,7 @@ hh_solve_batch = _sig("hh_solve_batch", _I, _P, _I, _P, _IP, _P, _P, _P, C.POINT
 hh_apply_operator = _sig("hh_apply_operator", _I, _P, _I, _D, _I, _IP, _P, _P)
 hh_apply_vcycle = _sig("hh_apply_vcycle", _I, _P, _I, _IP, _P, _P, _P)
 class hh_net_desc(C.Structure):
-    _fields_ = [("ch", C.c_int * 4)]
+    _fields_ = [("ch", C.c_int * 4), ("explicit_coarse", C.c_int)]
 
 
 _FP = C.POINTER(C.c_float)
@@ -373,15 +373,19 @@ def solve_batch(ctx: Context, models, bs, insts=None, restart=10, max_iters=2000
 # network
 # ---------------------------------------------------------------------------
 
-from .netfile import NET_LAYER_NAMES, flatten_params, read_params, unflatten_params  # noqa: E402,F401
+from .netfile import NET_LAYER_NAMES, flatten_params, read_header, read_params, unflatten_params  # noqa: E402,F401
 
 
 class Net:
     """Encoder-solver network on the device (FP32 master parameters)."""
 
-    def __init__(self, ctx: Context, params: dict | np.ndarray | None = None, ch=(16, 32, 64, 64), _handle=None):
+    def __init__(self, ctx: Context, params: dict | np.ndarray | None = None, ch=(16, 32, 64, 64), _handle=None,
+                 explicit: bool = False):
+        """explicit: the explicit U-Net (the coarsest level convolves with the
+        learned kernels instead of applying their Green's functions)."""
         self.ctx = ctx
         self.ch = tuple(ch)
+        self.explicit = bool(explicit)
         if _handle is not None:
             self.handle = _handle
             ctx._children.add(self)
@@ -389,6 +393,7 @@ class Net:
         d = hh_net_desc()
         for i in range(4):
             d.ch[i] = ch[i]
+        d.explicit_coarse = int(self.explicit)
         flat = None
         if params is not None:
             flat = params if isinstance(params, np.ndarray) else flatten_params(params, ch)
@@ -405,7 +410,8 @@ class Net:
     def load(cls, ctx: Context, path: str) -> "Net":
         h = C.c_void_p()
         check(hh_net_load(ctx.handle, path.encode(), C.byref(h)))
-        return cls(ctx, _handle=h)
+        hd = read_header(path)
+        return cls(ctx, ch=hd["ch"], _handle=h, explicit=hd["explicit"])
 
     def save(self, path: str):
         check(hh_net_save(self.handle, path.encode()))

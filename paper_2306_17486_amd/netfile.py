@@ -6,16 +6,18 @@ inputs.net_layers in order, the weights ((cout, cin, 3, 3) for convolutions,
 (cin, cout, 3, 3) for transposed convolutions) then the biases; then the
 complex 3x3 implicit-layer kernels as (re, im) pairs.
 
-File: 8-byte magic "HHNET001", int32 channels[4], int64 parameter count,
-int64 optimiser step, int32 has_optimiser_state, FP32 parameters, then (when
-present) the FP32 Adam first and second moments."""
+File: 8-byte magic "HHNET002", int32 channels[4], int32 coarsest-layer kind
+(0 implicit, 1 explicit), int64 parameter count, int64 optimiser step, int32
+has_optimiser_state, FP32 parameters, then (when present) the FP32 Adam first
+and second moments.  Files with magic "HHNET001" have no kind field (implicit)."""
 from __future__ import annotations
 
 import numpy as np
 
 from . import inputs
 
-MAGIC = b"HHNET001"
+MAGIC = b"HHNET002"
+MAGIC1 = b"HHNET001"
 
 NET_LAYER_NAMES = [name for name, _, _, _ in inputs.net_layers((16, 32, 64, 64))]
 
@@ -48,12 +50,26 @@ def unflatten_params(flat: np.ndarray, ch=(16, 32, 64, 64)) -> dict:
     return out
 
 
+def read_header(path: str) -> dict:
+    """{'ch': channels, 'explicit': bool} of a network file."""
+    with open(path, "rb") as f:
+        magic = f.read(8)
+        if magic not in (MAGIC, MAGIC1):
+            raise ValueError(f"{path} is not a network file")
+        ch = tuple(int(c) for c in np.frombuffer(f.read(16), dtype=np.int32))
+        explicit = bool(np.frombuffer(f.read(4), dtype=np.int32)[0]) if magic == MAGIC else False
+    return {"ch": ch, "explicit": explicit}
+
+
 def read_params(path: str) -> tuple[np.ndarray, tuple[int, ...]]:
     """(flat FP32 parameters, channels) of a network file."""
     with open(path, "rb") as f:
-        if f.read(8) != MAGIC:
+        magic = f.read(8)
+        if magic not in (MAGIC, MAGIC1):
             raise ValueError(f"{path} is not a network file")
         ch = tuple(int(c) for c in np.frombuffer(f.read(16), dtype=np.int32))
+        if magic == MAGIC:
+            f.read(4)  # coarsest-layer kind
         npar = int(np.frombuffer(f.read(8), dtype=np.int64)[0])
         f.read(8 + 4)  # optimiser step, has_optimiser_state
         flat = np.frombuffer(f.read(4 * npar), dtype=np.float32)

@@ -78,15 +78,15 @@ class KappaPrefetch:
     """Draws the next batches of slowness models on a host thread while the GPU
     trains on the current one."""
 
-    def __init__(self, plan, batch: int, depth: int = 3):
+    def __init__(self, plan, batch: int, depth: int = 3, step0: int = 0):
         self.q: queue.Queue = queue.Queue(maxsize=depth)
-        self.plan, self.batch = plan, batch
+        self.plan, self.batch, self.step0 = plan, batch, step0
         self.t = threading.Thread(target=self._run, daemon=True)
         self.t.start()
 
     def _run(self):
         for step, n in enumerate(self.plan):
-            seeds = TRAIN_SEED0 + step * self.batch + np.arange(self.batch)
+            seeds = TRAIN_SEED0 + (self.step0 + step) * self.batch + np.arange(self.batch)
             self.q.put((step, n, kappa_batch(n, seeds)))
 
     def get(self):
@@ -132,7 +132,9 @@ class GradClip:
 
 
 def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: int, nval: int, seed: int,
-          sizes=(128, 256), clip: float = 2.0):
+          sizes=(128, 256), clip: float = 2.0, step0: int = 0):
+    """`steps` steps; with `step0` > 0 (a continued run) the training stream's
+    media are those of steps step0 .. step0 + steps - 1, so no sample repeats."""
     dev = f"cuda:{ctx.device}"
     plan_blocks = schedule(steps, block, sizes)
     plan = [plan_blocks[s // block] for s in range(steps)]
@@ -158,7 +160,7 @@ def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: in
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
     rng = np.random.default_rng(seed)
-    pre = KappaPrefetch(plan, batch)
+    pre = KappaPrefetch(plan, batch, step0=step0)
     t0 = time.time()
     run = {n: [] for n in sizes}
     for step in range(steps):
@@ -241,21 +243,29 @@ def main(argv=None):
     ap.add_argument("--eval-large-max-iters", type=int, default=8000)
     ap.add_argument("--out", type=str, default=os.path.join(os.path.dirname(__file__), "weights",
                                                           "net_ms128_256.bin"))
+    ap.add_argument("--init-from", type=str, default="",
+                    help="continue from this network file (parameters and Adam moments)")
+    ap.add_argument("--step0", type=int, default=0,
+                    help="steps already taken by --init-from: the training stream continues after them")
+    ap.add_argument("--gen-seed", type=int, default=None, help="seed of the random vectors (default: --seed)")
+    ap.add_argument("--explicit", action="store_true",
+                    help="train the explicit U-Net (the coarsest level convolves with the kernels, Sec. 5.2)")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("training runs on the GPU")
     ctx = hh.Context(0)
     init = inputs.init_net_params(args.init_seed)
-    net = hh.Net(ctx, init)
+    net = hh.Net.load(ctx, args.init_from) if args.init_from else hh.Net(ctx, init, explicit=args.explicit)
     sizes = tuple(int(s) for s in args.sizes.split(","))
     if any(s not in SIZE_WEIGHT for s in sizes):
         sys.exit(f"training sizes must be among {sorted(SIZE_WEIGHT)}")
-    hist = train(ctx, net, args.steps, args.batch, args.lr, args.block, args.val_every, args.nval, args.seed,
-                 sizes=sizes, clip=args.clip)
+    seed = args.seed + args.step0 if args.gen_seed is None else args.gen_seed
+    hist = train(ctx, net, args.steps, args.batch, args.lr, args.block, args.val_every, args.nval, seed,
+                 sizes=sizes, clip=args.clip, step0=args.step0)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
     _log(f"[train] saved {args.out} after {hist['seconds']:.0f} s ({hist['steps_per_s']:.2f} steps/s)")
-    untrained = hh.Net(ctx, init)
+    untrained = hh.Net(ctx, init, explicit=net.explicit)
     nets = {"cnn_untrained": untrained, "cnn_trained": net}
     ev = evaluate(ctx, nets, sizes=tuple(int(s) for s in args.eval_sizes.split(",") if s), nk=args.eval_media)
     ev.update(evaluate(ctx, nets, sizes=tuple(int(s) for s in args.eval_large.split(",") if s),

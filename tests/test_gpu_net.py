@@ -192,6 +192,85 @@ def test_implicit_layer(hh, ctx, nc):
         assert np.all(np.abs(y - ref) <= tol), (adjoint, np.abs(y - ref).max() / np.abs(ref).max())
 
 
+@pytest.mark.parametrize("nc", [8, 32, 64])
+def test_explicit_coarsest_layer(hh, ctx, nc):
+    # the explicit U-Net's coarsest layer (convolution with K) and its adjoint
+    _say(f"explicit layer nc={nc}")
+    rng = np.random.default_rng(nc + 1)
+    p = inputs.init_net_params(3)
+    K = p["implicit_K"] + 0.3 * (rng.standard_normal((32, 3, 3)) + 1j * rng.standard_normal((32, 3, 3)))
+    p["implicit_K"] = K
+    net = hh.Net(ctx, p, explicit=True)
+    Kf = K.astype(np.complex64).astype(np.complex128)  # the library holds K in FP32
+    x = _bf16_round(rng.standard_normal((3, 64, nc, nc)))
+    mask = None
+    for adjoint in (False, True):
+        y = net.implicit_test(_nhwc_dev(x), nc, adjoint=adjoint).to(torch.float32).cpu().numpy().transpose(0, 3, 1, 2)
+        z = C.pair(x)
+        ref = C.unpair(C.explicit_backward(Kf, np.zeros_like(z), z)[0] if adjoint else C.explicit_apply(Kf, z))
+        # FP32 sums of exact products, then one BF16 rounding (2^-9 relative)
+        tol = 2.0 ** -8 * np.abs(ref) + 1e-6 * np.abs(ref).max()
+        assert np.all(np.abs(y - ref) <= tol), (adjoint, np.abs(y - ref).max() / np.abs(ref).max())
+
+
+def test_cnn_mg_two_phase_solve_explicit_network(hh, ctx):
+    n = 64
+    _say("cnn+mg two-phase solve, explicit network")
+    k = inputs.grf_slowness(n, 33)
+    om = inputs.omega_for(n, k)
+    prob = H.Problem(k, om)
+    p = inputs.init_net_params(9)
+    net = hh.Net(ctx, p, explicit=True)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.attach_net(net)
+    b = np.stack([inputs.point_source(n, 54), inputs.point_source(n, 55)])
+    x, info = m.solve(torch.from_numpy(b).to("cuda:0", torch.complex64), precond=hh.HH_PRECOND_CNN_MG)
+    x = x.cpu().numpy()
+    netp = S.NetPrecond(C.Net(p, explicit=True), prob)
+    for r in range(2):
+        rel = np.linalg.norm(b[r] - prob.A(x[r])) / np.linalg.norm(b[r])
+        assert info["converged"][r] and rel <= 1e-6 * (1 + 1e-6)
+        _, its_o, _, _ = S.solve_two_phase(prob, netp, b[r])
+        _say(f"  rhs {r}: gpu {info['iters'][r]} oracle {its_o}")
+        assert abs(int(info["iters"][r]) - its_o) <= 2
+    # the network forward itself against the oracle's
+    e = m.net_forward(torch.from_numpy(b).to("cuda:0", torch.complex64)).cpu().numpy()
+    for r in range(2):
+        ref = netp(b[r])
+        assert np.linalg.norm(e[r] - ref) / np.linalg.norm(ref) <= 3e-3
+
+
+def test_model_cache_follows_a_new_network_at_a_reused_address(hh, ctx):
+    # regression: the model's network cache (encodings, packed weights) was keyed
+    # on the network's address; a network created after another was destroyed
+    # can get the same address, and then ran with the old cache and no packed
+    # weights of its own.  The cache now keys on a unique id per network.
+    n = 64
+    _say("network cache after destroy + create")
+    k = inputs.grf_slowness(n, 34)
+    om = inputs.omega_for(n, k)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    v = torch.from_numpy(inputs.random_complex((2, n, n), 35)).to("cuda:0", torch.complex64)
+    net1 = hh.Net(ctx, inputs.init_net_params(21))
+    m.attach_net(net1)
+    e1 = m.net_forward(v)
+    m.attach_net(None)
+    net1.close()
+    p2 = inputs.init_net_params(22)
+    net2 = hh.Net(ctx, p2)
+    m.attach_net(net2)
+    e2 = m.net_forward(v)
+    # the same network on a model that never saw another one
+    m2 = hh.Model(ctx, torch.from_numpy(k), om)
+    m2.attach_net(net2)
+    ref = m2.net_forward(v)
+    assert torch.equal(e2, ref)
+    assert not torch.equal(e1, e2)
+    m.attach_net(None)
+    m2.attach_net(None)
+    net2.close()
+
+
 @pytest.mark.timeout(400)
 @pytest.mark.parametrize("n,family", [(64, "grf"), (128, "layered"), (512, "grf"), (1024, "layered")])
 def test_network_forward(hh, ctx, n, family):

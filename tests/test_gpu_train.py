@@ -61,9 +61,9 @@ def test_training_pairs_match_oracle(hh, ctx):
         assert np.linalg.norm(r[b] - ro) / np.linalg.norm(ro) <= 1e-3
 
 
-def _oracle_loss_grads(p, ks, om, r, e, n):
+def _oracle_loss_grads(p, ks, om, r, e, n, explicit=False):
     h = 1.0 / n
-    net = C.Net(p)
+    net = C.Net(p, explicit=explicit)
     rms = np.sqrt(np.mean(np.abs(r) ** 2, axis=(1, 2)))
     rin = C.to_channels(r / rms[:, None, None])
     # the GPU rounds the network input to BF16
@@ -91,6 +91,7 @@ def _bf16_storage(monkeypatch):
     conv, convt = C.conv2d, C.conv_transpose2d
     convb, convtb = C.conv2d_backward, C.conv_transpose2d_backward
     imp, impb = C.implicit_apply, C.implicit_backward
+    exp_, expb = C.explicit_apply, C.explicit_backward
 
     def cb(*a, **k):
         gx, gw, gb = convb(*a, **k)
@@ -115,8 +116,18 @@ def _bf16_storage(monkeypatch):
     monkeypatch.setattr(C, "implicit_apply", ia)
     monkeypatch.setattr(C, "implicit_backward", ib)
 
+    def ea(K, z):
+        return C.pair(_bf16(C.unpair(exp_(K, z))))
 
-def _check_loss_and_grads(hh, ctx, monkeypatch, n, kseed, xseed, kiters):
+    def eb(K, z, gy):
+        gz, gK = expb(K, z, gy)
+        return C.pair(_bf16(C.unpair(gz))), gK
+
+    monkeypatch.setattr(C, "explicit_apply", ea)
+    monkeypatch.setattr(C, "explicit_backward", eb)
+
+
+def _check_loss_and_grads(hh, ctx, monkeypatch, n, kseed, xseed, kiters, explicit=False):
     B = len(kiters)
     ks = _kappas(n, B, kseed)
     om = inputs.omega_for(n)
@@ -128,17 +139,19 @@ def _check_loss_and_grads(hh, ctx, monkeypatch, n, kseed, xseed, kiters):
     x = inputs.random_complex((B, n, n), xseed)
     e, r = m.training_pairs(_dev(x), kiters)
     e64, r64 = e.cpu().numpy().astype(np.complex128), r.cpu().numpy().astype(np.complex128)
-    net = hh.Net(ctx, p)
+    net = hh.Net(ctx, p, explicit=explicit)
     loss = net.train_step(m, r, e, lr=0.0)
     g = hh.unflatten_params(net.get_grads())
-    L, go = _oracle_loss_grads(p, ks, om, r64, e64, n)
+    if explicit:  # the library's kernel is the FP32 parameter itself
+        p = dict(p, implicit_K=p["implicit_K"].astype(np.complex64).astype(np.complex128))
+    L, go = _oracle_loss_grads(p, ks, om, r64, e64, n, explicit)
     # the MFMA layers compute with BF16 copies of their weights; the input
     # layers and the projection layer keep FP32 weights
     pq = {k: (_bf16(v) if k.endswith(".w") and k not in ("enc1_d.w", "s1_d.w", "out.w") else v)
           for k, v in p.items()}
     with monkeypatch.context() as mp:
         _bf16_storage(mp)
-        _, gq = _oracle_loss_grads(pq, ks, om, r64, e64, n)
+        _, gq = _oracle_loss_grads(pq, ks, om, r64, e64, n, explicit)
     _say(f"  loss gpu {loss:.6e} oracle {L:.6e}")
     assert abs(loss - L) <= 1e-3 * L
     bad = []
@@ -154,17 +167,19 @@ def _check_loss_and_grads(hh, ctx, monkeypatch, n, kseed, xseed, kiters):
     assert not bad, bad
 
 
-def test_loss_and_gradients_match_oracle(hh, ctx, monkeypatch):
-    _say("loss and gradients, n = 64 (stride-1 coarsest level)")
-    _check_loss_and_grads(hh, ctx, monkeypatch, 64, 70, 80, [3, 6])
+@pytest.mark.parametrize("explicit", [False, True])
+def test_loss_and_gradients_match_oracle(hh, ctx, monkeypatch, explicit):
+    _say(f"loss and gradients, n = 64 (stride-1 coarsest level), explicit={explicit}")
+    _check_loss_and_grads(hh, ctx, monkeypatch, 64, 70, 80, [3, 6], explicit)
 
 
 @pytest.mark.timeout(400)
-def test_loss_and_gradients_match_oracle_strided_coarsest_level(hh, ctx, monkeypatch):
+@pytest.mark.parametrize("explicit", [False, True])
+def test_loss_and_gradients_match_oracle_strided_coarsest_level(hh, ctx, monkeypatch, explicit):
     # from n = 512 on, the coarsest level is reached by a stride-2 convolution
     # and left by a stride-2 transposed one
-    _say("loss and gradients, n = 512 (stride-2 coarsest level)")
-    _check_loss_and_grads(hh, ctx, monkeypatch, 512, 75, 85, [4])
+    _say(f"loss and gradients, n = 512 (stride-2 coarsest level), explicit={explicit}")
+    _check_loss_and_grads(hh, ctx, monkeypatch, 512, 75, 85, [4], explicit)
 
 
 def test_adam_first_step_closed_form(hh, ctx):

@@ -132,6 +132,55 @@ def test_green_function_matches_sparse_direct_solve():
     assert np.abs(conv[2:-2, 2:-2] - dl[2:-2, 2:-2]).max() <= 2e-5
 
 
+def test_explicit_layer_undoes_the_implicit_layer():
+    # the explicit U-Net's coarsest step multiplies by the kernel whose Green's
+    # function the implicit step applies: explicit(implicit(z)) = z / (1 + eps)
+    # wherever the Green's function's support around z stays inside the map.
+    # A random non-symmetric kernel (damped so that G decays fast) makes the
+    # check sensitive to the kernel's orientation.
+    nc = 24
+    K = inputs.random_complex((2, 3, 3), 11) * 0.3
+    K[:, 1, 1] += 4.0 + 2.0j
+    Ghat, aux = C.green_hat(K, nc)
+    z = np.zeros((1, 2, nc, nc), dtype=complex)
+    z[0, :, 10:14, 9:15] = inputs.random_complex((2, 4, 6), 12)
+    y, _ = C.implicit_apply(Ghat, z)
+    back = C.explicit_apply(K, y)
+    # K (*) G has the symbol |F|^2 / (|F|^2 + eps): the defect's symbol is at most
+    # eps / min |F|^2, so the defect is at most that times the l1 norm of z
+    bound = 2 * C.EPS_GREEN / (np.abs(aux["Khat"]) ** 2).min() * np.abs(z).sum()
+    assert bound < 1e-3 * np.abs(z).max()
+    assert np.abs(back - z).max() <= bound
+    # the kernel's other orientations do not undo it
+    for Kf in (K[:, ::-1, ::-1], K[:, ::-1, :], K[:, :, ::-1], K.transpose(0, 2, 1)):
+        assert np.abs(C.explicit_apply(Kf, y) - z).max() > 0.1 * np.abs(z).max()
+    # identity kernel: identity
+    I3 = np.zeros((2, 3, 3), dtype=complex)
+    I3[:, 1, 1] = 1.0
+    assert np.array_equal(C.explicit_apply(I3, z), z)
+
+
+def test_explicit_layer_adjoint_and_kernel_gradient():
+    m = 6
+    K = inputs.random_complex((2, 3, 3), 13)
+    z = inputs.random_complex((3, 2, m, m), 14)
+    gy = inputs.random_complex((3, 2, m, m), 15)
+    y = C.explicit_apply(K, z)
+    gz, gK = C.explicit_backward(K, z, gy)
+    # L = Re <gy, y> is linear in z: its gradient is the adjoint applied to gy
+    assert np.real(np.vdot(gy, y)) == pytest.approx(np.real(np.vdot(gz, z)), rel=1e-12)
+    # and in K: d L / d Re K + i d L / d Im K, by central differences
+    for c, a, e in ((0, 0, 2), (1, 1, 1), (1, 2, 0)):
+        for unit in (1.0, 1j):
+            h = 1e-6
+            Kp, Km = K.copy(), K.copy()
+            Kp[c, a, e] += h * unit
+            Km[c, a, e] -= h * unit
+            fd = (np.real(np.vdot(gy, C.explicit_apply(Kp, z))) - np.real(np.vdot(gy, C.explicit_apply(Km, z)))) / (2 * h)
+            an = gK[c, a, e].real if unit == 1.0 else gK[c, a, e].imag
+            assert fd == pytest.approx(an, rel=1e-7, abs=1e-9)
+
+
 def test_implicit_adjoint_dot_product():
     nc = 4
     K = inputs.random_complex((2, 3, 3), 5)
@@ -147,13 +196,14 @@ def test_implicit_adjoint_dot_product():
 
 # --- network gradients ------------------------------------------------------
 
-def test_network_gradients_match_central_differences():
+@pytest.mark.parametrize("explicit", [False, True])
+def test_network_gradients_match_central_differences(explicit):
     ch = (4, 4, 8, 8)
     p = inputs.init_net_params(0, ch)
     for k in p:
         if k.endswith(".w"):
             p[k] = 2.0 * p[k]  # keeps every layer's gradient well above round-off
-    net = C.Net(p)
+    net = C.Net(p, explicit=explicit)
     n = 32
     r = _rng(1)
     rin = r.standard_normal((2, 2, n, n))
