@@ -23,8 +23,16 @@ struct ConvArgs {
     int B, Hin, Win, Hout, Wout;
     int tiles_x, tiles_y, ntiles;  // filled by the launcher
     const int* active;     // per batch entry: skipped when 0 (null: all active)
+    // projection layer (16 -> 2, FP32 weights as a BF16 high part wp plus a BF16
+    // low part wp_lo, output channels 2..15 zero): FP32 (re, im) output [B][H][W]
+    const uint16_t* wp_lo;
+    float2* yproj;
 };
 hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a);
+// the 16 -> 2 projection (stride 1) on the convolution kernel, weights split into BF16 high + low parts
+hh_status launch_conv_proj(hipStream_t st, int num_cus, const ConvArgs& a);
+hh_status pack_weights_split(hipStream_t st, const float* W, uint16_t* Wp_hi, uint16_t* Wp_lo, int cin, int cout_real,
+                             int cout);
 hh_status pack_weights(hipStream_t st, const float* W, uint16_t* Wp, int cin, int cout, bool flipped);
 size_t packed_weight_elems(int cin, int cout);
 
@@ -55,6 +63,7 @@ struct hh_net {
     hh::Buf adam_m, adam_v;                 // Adam moments
     hh::Buf packed;                         // BF16 packed weights (forward + input-gradient forms)
     size_t pk_fwd[hh::NET_LAYERS] = {0}, pk_bwd[hh::NET_LAYERS] = {0};
+    size_t pk_proj_hi = 0, pk_proj_lo = 0;  // the projection layer's split weights in `packed`
     bool packed_valid = false;
     long long step = 0;
     unsigned long long version = 1;         // bumped whenever the parameters change

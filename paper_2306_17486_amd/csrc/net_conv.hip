@@ -39,8 +39,28 @@ __global__ void k_pack_weights(const float* __restrict__ W, uint16_t* __restrict
     Wp[e] = f2bf(v);
 }
 
+// Split packing for a layer with cout_real < cout output channels kept in FP32
+// precision: Wp_hi = BF16(W), Wp_lo = BF16(W - Wp_hi) (together 16 significant
+// bits), output channels cout_real .. cout-1 zero.
+__global__ void k_pack_weights_split(const float* __restrict__ W, uint16_t* __restrict__ Wp_hi,
+                                     uint16_t* __restrict__ Wp_lo, int cin, int cout_real, int cout, int nch) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = nch * cout * 32;
+    if (e >= total) return;
+    const int kk = e % 32, o = (e / 32) % cout, ch = e / (32 * cout);
+    const int k = ch * 32 + kk;
+    const int t = k / cin, i = k % cin;
+    const float v = (t < 9 && o < cout_real) ? W[((size_t)o * cin + i) * 9 + t] : 0.f;
+    const uint16_t hi = f2bf(v);
+    Wp_hi[e] = hi;
+    Wp_lo[e] = f2bf(v - bf2f(hi));
+}
+
 // ---------------------------------------------------------------------------
-// The MFMA convolution.
+// The MFMA convolution.  PROJ: the projection layer (16 -> 2 channels): the
+// weights as a BF16 high and low part (two MFMAs per k chunk, products of the
+// BF16 activations exact, so the layer keeps its FP32 weights to 2^-17), and
+// the output as FP32 (re, im) pairs.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, int MODE>
 struct ConvCfg {
@@ -62,9 +82,11 @@ struct ConvCfg {
     static constexpr int LDS_BYTES = PH * PW * CP * 2;
 };
 
-template <int CIN, int COUT, int MODE>
+template <int CIN, int COUT, int MODE, bool PROJ = false>
 __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 waves per SIMD resident
     using C = ConvCfg<CIN, COUT, MODE>;
+    static_assert(!PROJ || (CIN == 16 && COUT == 16 && MODE == CM_S1 && C::CT == 1 && C::NG == 1),
+                  "projection: one 16-channel tile, stride 1");
     __shared__ __attribute__((aligned(16))) uint16_t s_in[C::PH * C::PW * C::CP];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -74,6 +96,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
 
     // this wave's weights stay in VGPRs for all tiles
     bf16x8 wreg[C::CT][C::NCH];
+    bf16x8 wlo[PROJ ? C::NCH : 1];
     {
         const uint4* wp4 = reinterpret_cast<const uint4*>(a.wp);
 #pragma unroll
@@ -83,12 +106,23 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
                 uint4 v = wp4[((size_t)ch * COUT + (cg * C::CT + c) * 16 + lp) * 4 + lg];
                 wreg[c][ch] = *reinterpret_cast<bf16x8*>(&v);
             }
+        if (PROJ) {
+            const uint4* wl4 = reinterpret_cast<const uint4*>(a.wp_lo);
+#pragma unroll
+            for (int ch = 0; ch < C::NCH; ++ch) {
+                uint4 v = wl4[((size_t)ch * COUT + lp) * 4 + lg];
+                wlo[ch] = *reinterpret_cast<bf16x8*>(&v);
+            }
+        }
     }
     float bias4[C::CT][4];
 #pragma unroll
     for (int c = 0; c < C::CT; ++c)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bias4[c][i] = a.bias ? a.bias[(cg * C::CT + c) * 16 + 4 * lg + i] : 0.f;
+        for (int i = 0; i < 4; ++i) {
+            const int co = (cg * C::CT + c) * 16 + 4 * lg + i;
+            bias4[c][i] = (a.bias && (!PROJ || co < 2)) ? a.bias[co] : 0.f;
+        }
 
     // ---- the input patch of a tile (zero padding / zero interleaving), gathered
     // into registers: element e = pixel * VEC + v of the PH x PW patch ----
@@ -198,7 +232,22 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
 #pragma unroll
                 for (int c = 0; c < C::CT; ++c)
                     acc[q][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[c][ch], bv, acc[q][c], 0, 0, 0);
+                if (PROJ) acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[ch], bv, acc[q][0], 0, 0, 0);
             }
+        }
+        if constexpr (PROJ) {
+            // lanes with lg == 0 hold output channels 0 (re) and 1 (im)
+#pragma unroll
+            for (int q = 0; q < C::PBW; ++q) {
+                const int pbk = wsub * C::PBW + q;
+                const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
+                const int oy = y0 + ry, ox = x0 + rx;
+                if (lg != 0 || oy >= a.Hout || ox >= a.Wout) continue;
+                a.yproj[((size_t)b * a.Hout + oy) * a.Wout + ox] =
+                    make_float2(acc[q][0][0] + bias4[0][0], acc[q][0][1] + bias4[0][1]);
+            }
+            tile = nxt;
+            continue;
         }
         // ---- epilogue: lane owns channels (cg*CT + c)*16 + 4 lg .. +3 of one pixel per block ----
         const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
@@ -666,6 +715,29 @@ hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, 
     }
     set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
     return HH_ERR_ARG;
+}
+
+hh_status launch_conv_proj(hipStream_t st, int num_cus, const ConvArgs& a0) {
+    using C = ConvCfg<16, 16, CM_S1>;
+    ConvArgs a = a0;
+    a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
+    a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
+    a.ntiles = a.B * a.tiles_x * a.tiles_y;
+    if (a.ntiles == 0) return HH_OK;
+    const int grid = std::min(a.ntiles, 8 * num_cus);
+    hipLaunchKernelGGL((k_conv_mfma<16, 16, CM_S1, true>), dim3(grid), dim3(256), 0, st, a);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+hh_status pack_weights_split(hipStream_t st, const float* W, uint16_t* Wp_hi, uint16_t* Wp_lo, int cin, int cout_real,
+                             int cout) {
+    const int nch = (9 * cin + 31) / 32;
+    const int total = nch * cout * 32;
+    hipLaunchKernelGGL(k_pack_weights_split, dim3((total + 255) / 256), dim3(256), 0, st, W, Wp_hi, Wp_lo, cin,
+                       cout_real, cout, nch);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
 }
 
 hh_status pack_weights(hipStream_t st, const float* W, uint16_t* Wp, int cin, int cout, bool flipped) {

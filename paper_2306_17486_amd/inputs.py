@@ -183,3 +183,82 @@ def init_net_params(seed: int, ch=(16, 32, 64, 64)) -> dict[str, np.ndarray]:
     p["implicit_K"] = np.broadcast_to(lap + 1j * np.array([[0, 0, 0], [0, 1.0, 0], [0, 0, 0]]),
                                       (nk, 3, 3)).astype(np.complex128).copy()
     return p
+
+
+# ---------------------------------------------------------------------------
+# Out-of-distribution media (stand-ins for the paper's Marmousi, SEG/EAGE salt
+# dome and Overthrust velocity models, which are not available here).  Each
+# builds a velocity model v (km/s) and returns kappa = 1/v normalised to a
+# largest value of 1 (the normalisation of Sec. 5.4), on a square n x n grid.
+# ---------------------------------------------------------------------------
+
+def _kappa_from_velocity(v: np.ndarray) -> np.ndarray:
+    k = 1.0 / v
+    return _fp32_exact(k / k.max())
+
+
+def salt_slowness(n: int, seed: int) -> np.ndarray:
+    """Sediments whose velocity grows with depth (1.5 -> 4 km/s, mild layering)
+    around a salt body (4.5 km/s) with a rough dome-shaped top and steep flanks."""
+    rng = np.random.default_rng(seed)
+    c = (np.arange(n) + 0.5) / n
+    y, x = c[:, None], c[None, :]
+    nl = int(rng.integers(12, 20))
+    tops = np.sort(rng.uniform(0.0, 1.0, nl))
+    dips = rng.uniform(-0.08, 0.08, nl)
+    layer = np.zeros((n, n), dtype=np.int64)
+    for a, t in zip(tops, dips):
+        layer += (y > a + t * (x - 0.5)).astype(np.int64)
+    v = 1.5 + 2.5 * (layer / nl) ** 0.8 + rng.uniform(-0.15, 0.15, nl + 1)[layer]
+    # salt: top y = y0 - h exp(-((x - xc)/w)^2) + small roughness, flanks down to the bottom
+    xc, w, y0, h = rng.uniform(0.35, 0.65), rng.uniform(0.12, 0.22), rng.uniform(0.55, 0.7), rng.uniform(0.2, 0.35)
+    kx = np.arange(1, 6)
+    rough = (rng.uniform(-0.02, 0.02, 5)[:, None] * np.sin(2 * np.pi * kx[:, None] * x[0][None, :])).sum(0)
+    top = y0 - h * np.exp(-((x[0] - xc) / w) ** 2) + rough
+    inside = (y > top[None, :]) & (np.abs(x - xc) < 1.6 * w * np.sqrt(np.maximum(0.0, 1.0 - (y - top[None, :]) * 0.3)))
+    v = np.where(inside, 4.5, v)
+    return _kappa_from_velocity(v)
+
+
+def faulted_slowness(n: int, seed: int) -> np.ndarray:
+    """Many thin dipping layers (velocity 1.5 -> 4.5 km/s with depth and random
+    contrasts) cut by two normal faults that offset them (a Marmousi-like
+    structure)."""
+    rng = np.random.default_rng(seed)
+    c = (np.arange(n) + 0.5) / n
+    y, x = c[:, None], c[None, :]
+    nl = int(rng.integers(25, 40))
+    tops = np.sort(rng.uniform(0.0, 1.0, nl))
+    vals = 1.5 + 3.0 * np.sort(rng.uniform(0.0, 1.0, nl + 1)) + rng.uniform(-0.3, 0.3, nl + 1)
+    vals = np.clip(vals, 1.5, 4.5)
+    yy = y + 0.15 * (x - 0.5)  # regional dip
+    for _ in range(2):  # faults: x = x0 + s (y - 0.5); the hanging wall drops by d
+        x0, s, d = rng.uniform(0.25, 0.75), rng.uniform(-0.4, 0.4), rng.uniform(0.03, 0.08)
+        yy = yy - d * (x > x0 + s * (y - 0.5))
+    layer = np.zeros((n, n), dtype=np.int64)
+    for a in tops:
+        layer += (yy > a).astype(np.int64)
+    return _kappa_from_velocity(vals[layer])
+
+
+def folded_slowness(n: int, seed: int) -> np.ndarray:
+    """Folded layers (an anticline and a syncline) with a thrust fault that
+    repeats part of the sequence (an Overthrust-like structure)."""
+    rng = np.random.default_rng(seed)
+    c = (np.arange(n) + 0.5) / n
+    y, x = c[:, None], c[None, :]
+    nl = int(rng.integers(10, 18))
+    tops = np.sort(rng.uniform(0.05, 1.0, nl))
+    vals = np.clip(2.0 + 4.0 * np.sort(rng.uniform(0.0, 1.0, nl + 1)) + rng.uniform(-0.4, 0.4, nl + 1), 2.0, 6.0)
+    amp, per, ph = rng.uniform(0.05, 0.12), rng.uniform(0.6, 1.2), rng.uniform(0.0, 2 * np.pi)
+    yy = y - amp * np.sin(2 * np.pi * x / per + ph) * (1.0 - 0.5 * y)
+    # thrust: above the plane y = y0 + s (x - 0.5) the block is pushed up by d
+    y0, s, d = rng.uniform(0.35, 0.6), rng.uniform(0.5, 1.0), rng.uniform(0.08, 0.15)
+    yy = np.where(y < y0 + s * (x - 0.5), yy + d, yy)
+    layer = np.zeros((n, n), dtype=np.int64)
+    for a in tops:
+        layer += (yy > a).astype(np.int64)
+    return _kappa_from_velocity(vals[layer])
+
+
+OOD_FAMILIES = {"salt": salt_slowness, "faulted": faulted_slowness, "folded": folded_slowness}

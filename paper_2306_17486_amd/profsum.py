@@ -47,6 +47,8 @@ CLASS_SOURCES = {
 
 
 def class_of(name: str) -> str:
+    if name.startswith("k_conv_mfma") and name.rstrip().endswith("true>"):
+        return "net_other"  # the projection layer (launched in the library's network-other scope)
     for p, c in CLASS_OF:
         if name.startswith(p):
             return c

@@ -338,3 +338,14 @@ def test_vcycle_with_iterative_coarse_solve():
     zd = direct.mg(b)
     assert np.linalg.norm(it_full.mg(b) - zd) / np.linalg.norm(zd) <= 1e-8
     assert np.linalg.norm(it_few.mg(b) - zd) / np.linalg.norm(zd) > 1e-4
+
+
+def test_out_of_distribution_media_generators():
+    # inputs only: seeded, FP32-representable, normalised like the paper's
+    # out-of-distribution media (largest slowness 1), values inside [0.25, 1]
+    for name, f in inputs.OOD_FAMILIES.items():
+        a, b = f(128, 11), f(128, 11)
+        assert np.array_equal(a, b), name
+        assert a.max() == 1.0 and a.min() >= 0.25, name
+        assert np.array_equal(a, a.astype(np.float32).astype(np.float64)), name
+        assert len(np.unique(a)) >= 5, name
