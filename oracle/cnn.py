@@ -486,3 +486,273 @@ class Adam:
                 vh = self.v[k] / (1 - self.b2 ** self.t)
                 params[k] = params[k] - self.lr * mh / (np.sqrt(vh) + self.eps)
         return params
+
+
+# ---------------------------------------------------------------------------
+# The paper's lightweight network (Sec. 4.4, Sec. 5.3): convolution + batch
+# normalisation + softplus modules, inverted bottlenecks (1x1 expansion,
+# depthwise 3x3, 1x1 shrink) on the first three solver levels.  Layer list:
+# paper_2306_17486_amd.inputs.net_layers_light.  Readings: the bottleneck's
+# shrink output is batch-normalised without activation and added to the
+# module's input (the residual form of Sec. 4.1, as in MobileNetV2); layers
+# followed by batch normalisation carry no bias; batch normalisation in
+# training uses the batch's statistics over (sample, row, column) with the
+# biased variance and eps 1e-5, and updates running statistics with momentum
+# 0.1 (unbiased variance), which inference uses.
+# ---------------------------------------------------------------------------
+BN_EPS = 1e-5
+BN_MOMENTUM = 0.1
+
+
+def conv1x1(x, w):
+    """out[b,o] = sum_c w[o,c] x[b,c]."""
+    return np.einsum("oc,bchw->bohw", w, x, optimize=True)
+
+
+def conv1x1_backward(x, w, gout):
+    return (np.einsum("oc,bohw->bchw", w, gout, optimize=True),
+            np.einsum("bohw,bchw->oc", gout, x, optimize=True))
+
+
+def depthwise(x, w):
+    """out[b,c,i,j] = sum_{a,e} w[c,a,e] x[b,c,i+a-1,j+e-1] (zero outside)."""
+    B, Cc, Hh, W = x.shape
+    xp = np.zeros((B, Cc, Hh + 2, W + 2))
+    xp[:, :, 1:-1, 1:-1] = x
+    out = np.zeros_like(x)
+    for a in range(3):
+        for e in range(3):
+            out += w[None, :, a, e, None, None] * xp[:, :, a:a + Hh, e:e + W]
+    return out
+
+
+def depthwise_backward(x, w, gout):
+    B, Cc, Hh, W = x.shape
+    xp = np.zeros((B, Cc, Hh + 2, W + 2))
+    xp[:, :, 1:-1, 1:-1] = x
+    gxp = np.zeros_like(xp)
+    gw = np.zeros_like(w)
+    for a in range(3):
+        for e in range(3):
+            gxp[:, :, a:a + Hh, e:e + W] += w[None, :, a, e, None, None] * gout
+            gw[:, a, e] = np.sum(gout * xp[:, :, a:a + Hh, e:e + W], axis=(0, 2, 3))
+    return gxp[:, :, 1:-1, 1:-1].copy(), gw
+
+
+def batchnorm(x, g, be, rm=None, rv=None):
+    """Batch normalisation over (sample, row, column) per channel.  With rm / rv
+    (running statistics) it is the inference form; otherwise the batch's own
+    mean and biased variance.  Returns (y, cache)."""
+    if rm is not None:
+        mu, var = rm, rv
+    else:
+        mu = x.mean(axis=(0, 2, 3))
+        var = x.var(axis=(0, 2, 3))
+    sd = np.sqrt(var + BN_EPS)
+    xh = (x - mu[None, :, None, None]) / sd[None, :, None, None]
+    return g[None, :, None, None] * xh + be[None, :, None, None], (xh, sd, mu, var)
+
+
+def batchnorm_backward(cache, g, gy):
+    """(gx, gg, gbe) of the training form."""
+    xh, sd, _, _ = cache
+    gg = np.sum(gy * xh, axis=(0, 2, 3))
+    gbe = np.sum(gy, axis=(0, 2, 3))
+    m = gy.shape[0] * gy.shape[2] * gy.shape[3]
+    gxh = gy * g[None, :, None, None]
+    gx = (gxh - gxh.sum(axis=(0, 2, 3))[None, :, None, None] / m
+          - xh * (gxh * xh).sum(axis=(0, 2, 3))[None, :, None, None] / m) / sd[None, :, None, None]
+    return gx, gg, gbe
+
+
+def softplus(x):
+    return np.logaddexp(0.0, x)
+
+
+def softplus_grad(x):
+    return 0.5 * (1.0 + np.tanh(0.5 * x))  # the logistic function, overflow-free
+
+
+class LightNet:
+    """The lightweight encoder-solver network with FP64 parameters ``p``
+    (inputs.init_light_params).  ``train`` selects batch statistics in the batch
+    normalisations (and records them for the running averages); otherwise the
+    running statistics are used."""
+
+    def __init__(self, params: dict[str, np.ndarray], explicit: bool = False, t: int = 6):
+        self.p = {k: np.array(v, copy=True) for k, v in params.items()}
+        self.explicit = explicit
+        self.t = t
+        self.train = False
+        self.batch_stats = {}
+
+    # one layer: its pre-normalisation output, then normalisation and activation
+    def _bn(self, name, z, act):
+        p = self.p
+        if self.train:
+            y, cache = batchnorm(z, p[name + ".g"], p[name + ".be"])
+            self.batch_stats[name] = (cache[2], cache[3], z.shape[0] * z.shape[2] * z.shape[3])
+        else:
+            y, cache = batchnorm(z, p[name + ".g"], p[name + ".be"], p[name + ".rm"], p[name + ".rv"])
+        return (softplus(y) if act else y), (z, y, cache, act)
+
+    def _bn_back(self, name, c, gout, g):
+        z, y, cache, act = c
+        gy = gout * softplus_grad(y) if act else gout
+        gz, g[name + ".g"], g[name + ".be"] = batchnorm_backward(cache, self.p[name + ".g"], gy)
+        return gz
+
+    def _cb(self, name, x, stride=1):
+        z = conv2d(x, self.p[name + ".w"], np.zeros(self.p[name + ".w"].shape[0]), stride)
+        out, c = self._bn(name, z, True)
+        return out, (x, stride, c)
+
+    def _cb_back(self, name, cache, gout, g):
+        x, stride, c = cache
+        gz = self._bn_back(name, c, gout, g)
+        gx, g[name + ".w"], _ = conv2d_backward(x, self.p[name + ".w"], gz, stride)
+        return gx
+
+    def _ib(self, pre, x):
+        p = self.p
+        ze = conv1x1(x, p[pre + "_e.w"])
+        he, ce = self._bn(pre + "_e", ze, True)
+        zw = depthwise(he, p[pre + "_w.w"])
+        hw, cw = self._bn(pre + "_w", zw, True)
+        zs = conv1x1(hw, p[pre + "_s.w"])
+        hs, cs = self._bn(pre + "_s", zs, False)
+        return x + hs, (x, he, ce, hw, cw, cs)
+
+    def _ib_back(self, pre, cache, gout, g):
+        p = self.p
+        x, he, ce, hw, cw, cs = cache
+        gzs = self._bn_back(pre + "_s", cs, gout, g)
+        ghw, g[pre + "_s.w"] = conv1x1_backward(hw, p[pre + "_s.w"], gzs)
+        gzw = self._bn_back(pre + "_w", cw, ghw, g)
+        ghe, g[pre + "_w.w"] = depthwise_backward(he, p[pre + "_w.w"], gzw)
+        gze = self._bn_back(pre + "_e", ce, ghe, g)
+        gx, g[pre + "_e.w"] = conv1x1_backward(x, p[pre + "_e.w"], gze)
+        return gout + gx
+
+    def encode(self, kin):
+        p = self.p
+        c, acts, x = {}, [], kin
+        for lvl in (1, 2, 3):
+            pre = f"enc{lvl}"
+            h0 = conv2d(x, p[pre + "_d.w"], p[pre + "_d.b"], 2)
+            h1, c1 = self._cb(pre + "_c1", h0)
+            h2, c2 = self._cb(pre + "_c2", h1)
+            c[lvl] = (x, c1, c2)
+            acts.append(h2)
+            x = h2
+        return tuple(acts), c
+
+    def encode_backward(self, cache, gE):
+        p = self.p
+        g = {}
+        gx_next = None
+        for lvl in (3, 2, 1):
+            pre = f"enc{lvl}"
+            x, c1, c2 = cache[lvl]
+            gh2 = gE[lvl - 1] + (gx_next if gx_next is not None else 0.0)
+            gh1 = self._cb_back(pre + "_c2", c2, gh2, g)
+            gh0 = self._cb_back(pre + "_c1", c1, gh1, g)
+            gx_next, g[pre + "_d.w"], g[pre + "_d.b"] = conv2d_backward(x, p[pre + "_d.w"], gh0, 2)
+        return g
+
+    def solve(self, rin, enc, Ghat):
+        p = self.p
+        n = rin.shape[2]
+        s4 = coarse_stride(n)
+        c = {}
+        x = rin
+        downs = []
+        for lvl in (1, 2, 3):
+            pre = f"s{lvl}"
+            h0 = conv2d(x, p[pre + "_d.w"], p[pre + "_d.b"], 2) + enc[lvl - 1]
+            h1, cib = self._ib(pre, h0)
+            c[pre] = (x, cib)
+            downs.append(h1)
+            x = h1
+        h0 = conv2d(x, p["s4_d.w"], p["s4_d.b"], s4)
+        h1, c1 = self._cb("s4_c1", h0)
+        h2, c2 = self._cb("s4_c2", h1)
+        c["s4"] = (x, s4, c1, c2)
+        z = pair(h2)
+        if self.explicit:
+            y = explicit_apply(p["implicit_K"], z)
+            c["imp"] = (z,)
+        else:
+            y, Z = implicit_apply(Ghat, z)
+            c["imp"] = (Z,)
+        x = unpair(y)
+        for lvl, skip in ((3, downs[2]), (2, downs[1]), (1, downs[0])):
+            pre = f"u{lvl}"
+            st = s4 if lvl == 3 else 2
+            h0 = conv_transpose2d(x, p[pre + "_t.w"], p[pre + "_t.b"], st) + skip
+            h1, c1 = self._cb(pre + "_c1", h0)
+            h2, c2 = self._cb(pre + "_c2", h1)
+            c[pre] = (x, st, c1, c2)
+            x = h2
+        o = conv2d(x, p["out.w"], p["out.b"])
+        c["out"] = x
+        up = np.stack([np.stack([H.prolong(o[b, ch]) for ch in range(2)]) for b in range(o.shape[0])])
+        return up, c
+
+    def solve_backward(self, cache, gup, Ghat):
+        p = self.p
+        g = {}
+        B = gup.shape[0]
+        go = np.stack([np.stack([4.0 * H.restrict_fw(gup[b, ch]) for ch in range(2)]) for b in range(B)])
+        gx, g["out.w"], g["out.b"] = conv2d_backward(cache["out"], p["out.w"], go)
+        gskip = {}
+        for lvl in (1, 2, 3):
+            pre = f"u{lvl}"
+            x, st, c1, c2 = cache[pre]
+            gh1 = self._cb_back(pre + "_c2", c2, gx, g)
+            gh0 = self._cb_back(pre + "_c1", c1, gh1, g)
+            gskip[lvl] = gh0
+            gx, g[pre + "_t.w"], g[pre + "_t.b"] = conv_transpose2d_backward(x, p[pre + "_t.w"], gh0, st)
+        if self.explicit:
+            (z,) = cache["imp"]
+            gz, gK = explicit_backward(p["implicit_K"], z, pair(gx))
+        else:
+            (Z,) = cache["imp"]
+            gz, gK = implicit_backward(Ghat, Z, pair(gx))
+        gx = unpair(gz)
+        x, s4, c1, c2 = cache["s4"]
+        gh1 = self._cb_back("s4_c2", c2, gx, g)
+        gh0 = self._cb_back("s4_c1", c1, gh1, g)
+        gx, g["s4_d.w"], g["s4_d.b"] = conv2d_backward(x, p["s4_d.w"], gh0, s4)
+        gE = [None, None, None]
+        for lvl in (3, 2, 1):
+            pre = f"s{lvl}"
+            x, cib = cache[pre]
+            gh1 = gx + gskip[lvl]
+            gh0 = self._ib_back(pre, cib, gh1, g)
+            gE[lvl - 1] = gh0
+            gx, g[pre + "_d.w"], g[pre + "_d.b"] = conv2d_backward(x, p[pre + "_d.w"], gh0, 2)
+        return g, gK, gE
+
+    def forward(self, rin, kin):
+        n = rin.shape[2]
+        nc = coarsest_size(n)
+        Ghat, gaux = (None, None) if self.explicit else green_hat(self.p["implicit_K"], nc)
+        self.batch_stats = {}
+        enc, ecache = self.encode(kin)
+        out, scache = self.solve(rin, enc, Ghat)
+        return out, (Ghat, gaux, ecache, scache, nc)
+
+    def backward(self, cache, gout):
+        Ghat, gaux, ecache, scache, nc = cache
+        g, gK, gE = self.solve_backward(scache, gout, Ghat)
+        g.update(self.encode_backward(ecache, gE))
+        g["implicit_K"] = gK if self.explicit else green_hat_backward(self.p["implicit_K"], nc, gK, gaux)
+        return g
+
+    def update_running_stats(self):
+        """Running averages after a training forward pass (momentum 0.1, the
+        unbiased batch variance)."""
+        for name, (mu, var, m) in self.batch_stats.items():
+            self.p[name + ".rm"] = (1 - BN_MOMENTUM) * self.p[name + ".rm"] + BN_MOMENTUM * mu
+            self.p[name + ".rv"] = (1 - BN_MOMENTUM) * self.p[name + ".rv"] + BN_MOMENTUM * var * m / (m - 1)

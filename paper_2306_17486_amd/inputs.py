@@ -262,3 +262,73 @@ def folded_slowness(n: int, seed: int) -> np.ndarray:
 
 
 OOD_FAMILIES = {"salt": salt_slowness, "faulted": faulted_slowness, "folded": folded_slowness}
+
+
+# ---------------------------------------------------------------------------
+# The paper's lightweight network (Sec. 4.4, Sec. 5.3): modules of a 3x3
+# convolution, batch normalisation and softplus; inverted bottlenecks (1x1
+# expansion by LIGHT_EXPAND, depthwise 3x3, 1x1 shrink, sum with the module's
+# input) on the first three solver levels.
+# ---------------------------------------------------------------------------
+LIGHT_EXPAND = 6
+
+
+def net_layers_light(ch=(16, 32, 64, 64), t: int = LIGHT_EXPAND):
+    """Layer list of the lightweight encoder-solver network (name, kind, cin, cout).
+
+    kinds: 'd' 3x3 stride-2 conv, 'd4' the coarsest down conv (stride 2 from
+    n = 512, else 1), 'cb' 3x3 conv + batch norm + softplus, 'e' 1x1 expansion
+    + batch norm + softplus, 'w' depthwise 3x3 + batch norm + softplus (cin =
+    cout channels), 's' 1x1 shrink + batch norm (added to the bottleneck's
+    input), 't' / 't4' 3x3 stride-2 transposed conv, 'c' the 3x3 projection.
+    Layers followed by batch norm have no bias (the normalisation removes it).
+    """
+    c1, c2, c3, c4 = ch
+    L = []
+    for lvl, (ci, co) in enumerate(((2, c1), (c1, c2), (c2, c3)), start=1):
+        L += [(f"enc{lvl}_d", "d", ci, co), (f"enc{lvl}_c1", "cb", co, co), (f"enc{lvl}_c2", "cb", co, co)]
+    for lvl, (ci, co) in enumerate(((2, c1), (c1, c2), (c2, c3)), start=1):
+        L += [(f"s{lvl}_d", "d", ci, co), (f"s{lvl}_e", "e", co, t * co), (f"s{lvl}_w", "w", t * co, t * co),
+              (f"s{lvl}_s", "s", t * co, co)]
+    L += [("s4_d", "d4", c3, c4), ("s4_c1", "cb", c4, c4), ("s4_c2", "cb", c4, c4)]
+    L += [("u3_t", "t4", c4, c3), ("u3_c1", "cb", c3, c3), ("u3_c2", "cb", c3, c3)]
+    L += [("u2_t", "t", c3, c2), ("u2_c1", "cb", c2, c2), ("u2_c2", "cb", c2, c2)]
+    L += [("u1_t", "t", c2, c1), ("u1_c1", "cb", c1, c1), ("u1_c2", "cb", c1, c1)]
+    L += [("out", "c", c1, 2)]
+    return L
+
+
+def light_has_bn(kind: str) -> bool:
+    return kind in ("cb", "e", "w", "s")
+
+
+def init_light_params(seed: int, ch=(16, 32, 64, 64), t: int = LIGHT_EXPAND) -> dict[str, np.ndarray]:
+    """Seeded initial parameters of the lightweight network (float64): Kaiming-
+    uniform weights (bound 1/sqrt(fan_in)), biases likewise where the layer has
+    one, batch-norm scale 1 and shift 0 with running mean 0 and variance 1, and
+    the implicit kernels L + iI."""
+    rng = np.random.default_rng(seed)
+    p: dict[str, np.ndarray] = {}
+    for name, kind, cin, cout in net_layers_light(ch, t):
+        if kind in ("t", "t4"):
+            shape, fan_in = (cin, cout, 3, 3), cout * 9
+        elif kind in ("e", "s"):
+            shape, fan_in = (cout, cin), cin
+        elif kind == "w":
+            shape, fan_in = (cout, 3, 3), 9
+        else:
+            shape, fan_in = (cout, cin, 3, 3), cin * 9
+        bound = 1.0 / math.sqrt(fan_in)
+        p[name + ".w"] = rng.uniform(-bound, bound, shape)
+        if light_has_bn(kind):
+            p[name + ".g"] = np.ones(cout)
+            p[name + ".be"] = np.zeros(cout)
+            p[name + ".rm"] = np.zeros(cout)
+            p[name + ".rv"] = np.ones(cout)
+        else:
+            p[name + ".b"] = rng.uniform(-bound, bound, (cout,))
+    lap = np.array([[0.0, -1.0, 0.0], [-1.0, 4.0, -1.0], [0.0, -1.0, 0.0]])
+    nk = ch[3] // 2
+    p["implicit_K"] = np.broadcast_to(lap + 1j * np.array([[0, 0, 0], [0, 1.0, 0], [0, 0, 0]]),
+                                      (nk, 3, 3)).astype(np.complex128).copy()
+    return p

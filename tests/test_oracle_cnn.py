@@ -312,3 +312,132 @@ def test_net_preconditioner_scale_invariance():
     e1 = netp(v)
     e2 = netp(7.5 * v)
     assert np.abs(e2 - 7.5 * e1).max() <= 1e-12 * np.abs(e2).max()
+
+
+# --- the lightweight network (Sec. 4.4, Sec. 5.3) ----------------------------
+
+def test_depthwise_brute_force_and_adjoint():
+    r = _rng(30)
+    x = r.standard_normal((2, 3, 5, 6))
+    w = r.standard_normal((3, 3, 3))
+    y = C.depthwise(x, w)
+    ref = np.zeros_like(x)
+    for b in range(2):
+        for c in range(3):
+            for i in range(5):
+                for j in range(6):
+                    for a in range(3):
+                        for e in range(3):
+                            ii, jj = i + a - 1, j + e - 1
+                            if 0 <= ii < 5 and 0 <= jj < 6:
+                                ref[b, c, i, j] += w[c, a, e] * x[b, c, ii, jj]
+    assert np.allclose(y, ref, rtol=0, atol=1e-13)
+    gy = r.standard_normal(y.shape)
+    gx, gw = C.depthwise_backward(x, w, gy)
+    assert np.sum(gy * y) == pytest.approx(np.sum(gx * x), rel=1e-12)   # adjoint in x
+    assert np.sum(gy * y) == pytest.approx(np.sum(gw * w), rel=1e-12)   # linear in w too
+
+
+def test_conv1x1_is_a_matrix_product_per_pixel():
+    r = _rng(31)
+    x = r.standard_normal((2, 5, 4, 3))
+    w = r.standard_normal((7, 5))
+    y = C.conv1x1(x, w)
+    ref = np.matmul(w, x.transpose(0, 2, 3, 1)[..., None])[..., 0].transpose(0, 3, 1, 2)
+    assert np.allclose(y, ref, rtol=0, atol=1e-13)
+    gy = r.standard_normal(y.shape)
+    gx, gw = C.conv1x1_backward(x, w, gy)
+    assert np.sum(gy * y) == pytest.approx(np.sum(gx * x), rel=1e-12)
+    assert np.sum(gy * y) == pytest.approx(np.sum(gw * w), rel=1e-12)
+
+
+def test_batchnorm_closed_forms():
+    r = _rng(32)
+    x = 3.0 + 2.0 * r.standard_normal((4, 3, 5, 5))
+    g, be = np.array([1.0, 2.0, 0.5]), np.array([0.0, -1.0, 3.0])
+    y, (xh, sd, mu, var) = C.batchnorm(x, g, be)
+    # per channel the output has mean beta and variance gamma^2 var / (var + eps)
+    assert np.allclose(y.mean(axis=(0, 2, 3)), be, atol=1e-12)
+    assert np.allclose(y.var(axis=(0, 2, 3)), g ** 2 * var / (var + C.BN_EPS), rtol=1e-12)
+    # the inference form with the batch's own statistics is the training form
+    y2, _ = C.batchnorm(x, g, be, mu, var)
+    assert np.allclose(y, y2, rtol=0, atol=1e-12)
+    # the gradient of the training form is orthogonal to constants (a shift of x
+    # does not change y) and, against x-hat, leaves only the eps part: scaling x
+    # by (1 + t) changes y through var / (var + eps) alone
+    gy = r.standard_normal(y.shape)
+    gx, _, _ = C.batchnorm_backward((xh, sd, mu, var), g, gy)
+    assert np.allclose(gx.sum(axis=(0, 2, 3)), 0.0, atol=1e-10)
+    dy_dt = g[None, :, None, None] * xh * (C.BN_EPS / (var + C.BN_EPS))[None, :, None, None]
+    assert np.allclose((gx * (x - mu[None, :, None, None])).sum(axis=(0, 2, 3)), (gy * dy_dt).sum(axis=(0, 2, 3)),
+                       rtol=1e-8, atol=1e-12)
+
+
+def test_softplus_closed_forms():
+    x = np.array([-30.0, -1.0, 0.0, 2.0, 40.0])
+    assert C.softplus(np.array(0.0)) == pytest.approx(math.log(2.0), rel=1e-15)
+    assert np.allclose(C.softplus(x) - C.softplus(-x), x, atol=1e-13)
+    assert C.softplus_grad(np.array(0.0)) == pytest.approx(0.5, rel=1e-15)
+    assert np.allclose(C.softplus_grad(x), 1.0 / (1.0 + np.exp(-x)), rtol=1e-12)
+
+
+@pytest.mark.parametrize("explicit", [False, True])
+def test_light_network_gradients_match_central_differences(explicit):
+    ch, t = (4, 4, 8, 8), 2
+    p = inputs.init_light_params(1, ch, t)
+    for k in p:
+        if k.endswith(".w") and not k.startswith("implicit"):
+            p[k] = 2.0 * p[k]
+    net = C.LightNet(p, explicit=explicit, t=t)
+    net.train = True
+    n = 32
+    r = _rng(33)
+    rin = r.standard_normal((3, 2, n, n))
+    kin = r.standard_normal((3, 2, n, n))
+    tgt = r.standard_normal((3, 2, n, n))
+
+    def loss(params):
+        net.p = params
+        return C.mse_loss(net.forward(rin, kin)[0], tgt)[0]
+
+    net.p = {k: v.copy() for k, v in p.items()}
+    out, cache = net.forward(rin, kin)
+    _, gout = C.mse_loss(out, tgt)
+    g = net.backward(cache, gout)
+    learn = [k for k in p if not (k.endswith(".rm") or k.endswith(".rv"))]
+    assert set(g) == set(learn)
+    for k in sorted(learn):
+        v = p[k]
+        d = r.standard_normal(v.shape) + (1j * r.standard_normal(v.shape) if np.iscomplexobj(v) else 0)
+        d = d / np.linalg.norm(d) * max(np.linalg.norm(v), 1.0)
+        an = np.sum(g[k].real * d.real) + (np.sum(g[k].imag * d.imag) if np.iscomplexobj(v) else 0.0)
+
+        def at(s):
+            q = {kk: vv.copy() for kk, vv in p.items()}
+            q[k] = q[k] + s * d
+            return loss(q)
+
+        best = np.inf
+        # batch normalisation makes the loss nearly invariant to the scale of the
+        # weights before it, so a random direction can be nearly orthogonal to the
+        # gradient: the error is measured against |g| |d| (Cauchy-Schwarz), with
+        # steps large enough for the loss's rounding (fourth-order scheme)
+        scale = np.linalg.norm(g[k]) * np.linalg.norm(d)
+        for h in (1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5):
+            fd = (8.0 * (at(h) - at(-h)) - (at(2 * h) - at(-2 * h))) / (12.0 * h)
+            best = min(best, abs(fd - an) / scale)
+        assert best <= 1e-7, (k, best)
+
+
+def test_light_network_running_statistics():
+    p = inputs.init_light_params(2, (4, 4, 8, 8), 2)
+    net = C.LightNet(p, t=2)
+    net.train = True
+    r = _rng(34)
+    rin, kin = r.standard_normal((2, 2, 32, 32)), r.standard_normal((2, 2, 32, 32))
+    _, cache = net.forward(rin, kin)
+    z = cache[3]["u1"][3][2][0]  # the pre-normalisation map of u1_c2
+    net.update_running_stats()
+    m = z.shape[0] * z.shape[2] * z.shape[3]
+    assert np.allclose(net.p["u1_c2.rm"], 0.1 * z.mean(axis=(0, 2, 3)), rtol=1e-12)
+    assert np.allclose(net.p["u1_c2.rv"], 0.9 + 0.1 * z.var(axis=(0, 2, 3)) * m / (m - 1), rtol=1e-12)
