@@ -269,6 +269,25 @@ hh_status hh_apply_vcycle(hh_model* m, int nrhs, const int* inst_host, const voi
  * convolutions (s4_d stride 1 when n < 512), *_t stride-2 transposed
  * convolutions (u3_t stride 1 when n < 512); ReLU follows every *_c* layer.
  * ---------------------------------------------------------------------- */
+/* The lightweight network (HH_ARCH_LIGHT; Sec. 4.4, Sec. 5.3), same channels:
+ *   encoder  enc1_d enc1_c1 enc1_c2 enc2_d enc2_c1 enc2_c2 enc3_d enc3_c1 enc3_c2
+ *   solver   s1_d s1_e s1_w s1_s s2_d s2_e s2_w s2_s s3_d s3_e s3_w s3_s
+ *            s4_d s4_c1 s4_c2 u3_t u3_c1 u3_c2 u2_t u2_c1 u2_c2 u1_t u1_c1 u1_c2 out
+ * *_c* are 3x3 convolutions followed by batch normalisation and softplus;
+ * sK_e (1x1, c -> 6c), sK_w (depthwise 3x3 on 6c channels) and sK_s (1x1,
+ * 6c -> c) form an inverted bottleneck: softplus after the first two
+ * normalisations, none after the third, whose output is added to the
+ * bottleneck's input (the output of sK_d).  *_d, *_t and out are as above,
+ * with biases and no activation.  Parameters per layer: the weights ((cout,
+ * cin, 3, 3) for convolutions, (cin, cout, 3, 3) for *_t, (cout, cin) for 1x1,
+ * (cout, 3, 3) for depthwise), then for batch-normalised layers the scale,
+ * shift, running mean and running variance (cout each; such layers have no
+ * bias), otherwise the biases; then the implicit kernels.  Training uses the
+ * batch's statistics over (sample, row, column), biased variance, eps 1e-5,
+ * and a training step with lr > 0 updates the running statistics with
+ * momentum 0.1 (the unbiased variance); every other use (solves, hh_net_forward, hh_eval_loss)
+ * applies the running statistics, folded into the weights. */
+enum { HH_ARCH_UNET = 0, HH_ARCH_LIGHT = 1 };
 typedef struct {
     int ch[4];
     int explicit_coarse;  /* 0 (the implicit U-Net): the coarsest level applies the Green's
@@ -276,6 +295,8 @@ typedef struct {
                              U-Net of Sec. 5.2, the same network without the implicit step):
                              it convolves with K_c itself, y = sum_{a,e} K_c[a][e]
                              z[i - a + 1][j - e + 1].  Same parameters and layout. */
+    int arch;             /* HH_ARCH_UNET: the network above.  HH_ARCH_LIGHT: the lightweight
+                             network of Sec. 4.4 / 5.3 (layer list and parameter layout below). */
 } hh_net_desc;
 
 /* Create a network; params_host (host, nparams floats) may be NULL (zeros). */
@@ -286,8 +307,9 @@ size_t hh_net_num_params(const hh_net* net);
 /* Copy the FP32 master parameters to / from host memory (synchronous). */
 hh_status hh_net_get_params(hh_net* net, float* host);
 hh_status hh_net_set_params(hh_net* net, const float* host);
-/* Binary checkpoint: the coarsest-layer kind, parameters, optimizer moments
- * (when present) and step (files without the kind load as implicit). */
+/* Binary checkpoint: the architecture and coarsest-layer kind, parameters,
+ * optimizer moments (when present) and step (files without the kind load as
+ * the implicit U-Net). */
 hh_status hh_net_save(hh_net* net, const char* path);
 hh_status hh_net_load(hh_ctx* ctx, const char* path, hh_net** out);
 
@@ -342,7 +364,8 @@ hh_status hh_net_get_grads(hh_net* net, float* host);
  *   flipped = 0: w is (cout, cin, 3, 3) and the layer is a convolution;
  *   flipped = 1: w is (cin, cout, 3, 3) and the layer is a transposed convolution
  *   (mode 2 or, with mode 0, the stride-1 transposed convolution);
- *   bias (FP32, may be NULL), skip (BF16, output shape, may be NULL), relu;
+ *   bias (FP32, may be NULL), skip (BF16, output shape, may be NULL), act
+ *   (0 none, 1 ReLU, 2 softplus, after bias and skip);
  *   y_dev BF16 output, yf_dev optional FP32 output; active_host (host int[B],
  *   may be NULL = all): batch entries with 0 are skipped (their outputs are
  *   left untouched), as the solve skips converged right-hand sides.
@@ -357,9 +380,23 @@ hh_status hh_net_get_grads(hh_net* net, float* host);
  *   (ca, cx, mode) in {(16,16,0), (32,32,0), (64,64,0), (32,16,1), (64,32,1),
  *   (64,64,1)}, otherwise HH_ERR_ARG. */
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
-                       const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int relu,
+                       const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int act,
                        void* y_dev, float* yf_dev, const int* active_host);
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint);
+/* hh_pointwise_test: the lightweight network's 1x1 convolution (Sec. 4.4) on
+ *   BF16 x [npix][cin] with FP32 weights w [cout][cin]:
+ *   y[p][o] = act(sum_c w[o][c] x[p][c] + bias[o]) + res[p][o]; bias (FP32) and
+ *   res (BF16 [npix][cout]) may be NULL; act 0 none, 2 softplus; y BF16, yf
+ *   optional FP32.  (cin, cout) in {(16,96), (96,16), (32,192), (192,32),
+ *   (64,384), (384,64)}, otherwise HH_ERR_ARG.
+ * hh_depthwise_test: its depthwise 3x3 convolution (stride 1, zero padding) on
+ *   BF16 NHWC x [B][H][W][C] with FP32 w [C][3][3]:
+ *   y[b][i][j][c] = act(sum_{a,e} w[c][a][e] x[b][i+a-1][j+e-1][c] + bias[c]),
+ *   flip = 1 uses w[c][2-a][2-e]; C in {96, 192, 384}. */
+hh_status hh_pointwise_test(hh_ctx* ctx, int cin, int cout, size_t npix, const void* x_dev, const float* w_dev,
+                            const float* bias_dev, const void* res_dev, int act, void* y_dev, float* yf_dev);
+hh_status hh_depthwise_test(hh_ctx* ctx, int C, int B, int H, int W, const void* x_dev, const float* w_dev,
+                            const float* bias_dev, int act, int flip, void* y_dev, float* yf_dev);
 hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, int Wo, int Hi, int Wi,
                         const void* a_dev, const void* x_dev, float* out_dev);
 

@@ -50,8 +50,78 @@ static void build_table(hh_net* net) {
     net->nparams = off + (size_t)net->nk * 9 * 2;
 }
 
+// The lightweight network (Sec. 4.4, Sec. 5.3): the same encoder, down and up
+// paths, with batch normalisation + softplus after every 3x3 convolution of a
+// level (no bias there), and on the first three solver levels one inverted
+// bottleneck in place of the two convolutions: 1x1 expansion by 6, depthwise
+// 3x3, 1x1 shrink, each batch-normalised (softplus after the first two), the
+// shrink's output added to the bottleneck's input.  Parameters per layer: the
+// weights, then (batch-norm layers) scale, shift, running mean and running
+// variance, or (the others) the biases.
+enum {
+    LL_ENC1_D = 0, LL_ENC1_C1, LL_ENC1_C2, LL_ENC2_D, LL_ENC2_C1, LL_ENC2_C2, LL_ENC3_D, LL_ENC3_C1, LL_ENC3_C2,
+    LL_S1_D, LL_S1_E, LL_S1_W, LL_S1_S, LL_S2_D, LL_S2_E, LL_S2_W, LL_S2_S, LL_S3_D, LL_S3_E, LL_S3_W, LL_S3_S,
+    LL_S4_D, LL_S4_C1, LL_S4_C2, LL_U3_T, LL_U3_C1, LL_U3_C2, LL_U2_T, LL_U2_C1, LL_U2_C2, LL_U1_T, LL_U1_C1,
+    LL_U1_C2, LL_OUT
+};
+constexpr int LIGHT_EXPAND = 6;
+
+static void build_light_table(hh_net* net) {
+    const int c1 = net->ch[0], c2 = net->ch[1], c3 = net->ch[2], c4 = net->ch[3], t = LIGHT_EXPAND;
+    const int tab[LIGHT_LAYERS][4] = {
+        {LK_DOWN, 2, c1, 0},    {LK_CONV, c1, c1, 1},      {LK_CONV, c1, c1, 1},        // encoder level 1
+        {LK_DOWN, c1, c2, 0},   {LK_CONV, c2, c2, 1},      {LK_CONV, c2, c2, 1},        // encoder level 2
+        {LK_DOWN, c2, c3, 0},   {LK_CONV, c3, c3, 1},      {LK_CONV, c3, c3, 1},        // encoder level 3
+        {LK_DOWN, 2, c1, 0},    {LK_PW, c1, t * c1, 1},    {LK_DW, t * c1, t * c1, 1},  // solver level 1
+        {LK_PW, t * c1, c1, 1},
+        {LK_DOWN, c1, c2, 0},   {LK_PW, c2, t * c2, 1},    {LK_DW, t * c2, t * c2, 1},  // solver level 2
+        {LK_PW, t * c2, c2, 1},
+        {LK_DOWN, c2, c3, 0},   {LK_PW, c3, t * c3, 1},    {LK_DW, t * c3, t * c3, 1},  // solver level 3
+        {LK_PW, t * c3, c3, 1},
+        {LK_DOWN4, c3, c4, 0},  {LK_CONV, c4, c4, 1},      {LK_CONV, c4, c4, 1},        // solver level 4
+        {LK_UP4, c4, c3, 0},    {LK_CONV, c3, c3, 1},      {LK_CONV, c3, c3, 1},        // up to level 3
+        {LK_UP, c3, c2, 0},     {LK_CONV, c2, c2, 1},      {LK_CONV, c2, c2, 1},        // up to level 2
+        {LK_UP, c2, c1, 0},     {LK_CONV, c1, c1, 1},      {LK_CONV, c1, c1, 1},        // up to level 1
+        {LK_CONV, c1, 2, 0}};                                                           // projection
+    size_t off = 0;
+    for (int l = 0; l < LIGHT_LAYERS; ++l) {
+        LayerInfo& L = net->L[l];
+        L.kind = tab[l][0];
+        L.cin = tab[l][1];
+        L.cout = tab[l][2];
+        L.bn = tab[l][3];
+        L.woff = off;
+        off += L.kind == LK_PW ? (size_t)L.cin * L.cout
+                               : (L.kind == LK_DW ? (size_t)L.cout * 9 : (size_t)L.cin * L.cout * 9);
+        if (L.bn) {
+            L.boff = (size_t)-1;
+            L.goff = off;
+            L.beoff = off + L.cout;
+            L.rmoff = off + 2 * (size_t)L.cout;
+            L.rvoff = off + 3 * (size_t)L.cout;
+            off += 4 * (size_t)L.cout;
+        } else {
+            L.boff = off;
+            off += L.cout;
+        }
+    }
+    net->nlayers = LIGHT_LAYERS;
+    net->nk = c4 / 2;
+    net->koff = off;
+    net->nparams = off + (size_t)net->nk * 9 * 2;
+}
+
 static inline int coarse_stride_of(int n) { return n >= 512 ? 2 : 1; }
 static inline int coarsest_of(int n) { return n >= 512 ? n / 16 : n / 8; }
+
+// map size of light layer l for fine size n
+static int light_res(int l, int n) {
+    if (l <= LL_ENC3_C2) return n >> (l / 3 + 1);
+    if (l <= LL_S1_S || l >= LL_U1_T) return n / 2;
+    if (l <= LL_S2_S || (l >= LL_U2_T && l <= LL_U2_C2)) return n / 4;
+    if (l <= LL_S3_S || (l >= LL_U3_T && l <= LL_U3_C2)) return n / 8;
+    return coarsest_of(n);
+}
 static inline int nextpow2(int v) {
     int p = 1;
     while (p < v) p <<= 1;
@@ -784,8 +854,69 @@ hh_status green_forward(hh_net* net, int nc, float2* Gbr, double eps) {
 // ---------------------------------------------------------------------------
 // parameters / packing
 // ---------------------------------------------------------------------------
+// the lightweight network: BN folded into `folded` (inference); BF16 packs of
+// every 3x3 and pointwise layer in training (unfolded), input-gradient and
+// (batch-norm layers) folded inference forms
+static hh_status light_pack(hh_net* net) {
+    hipStream_t st = net->ctx->stream;
+    const float* P = net->params.as<float>();
+    HH_TRY(net->folded.ensure(net->ctx, net->nparams * sizeof(float)));
+    float* F = net->folded.as<float>();
+    HH_HIP(hipMemcpyAsync(F, P, net->nparams * sizeof(float), hipMemcpyDeviceToDevice, st));
+    size_t off = 0;
+    for (int l = 0; l < LIGHT_LAYERS; ++l) {
+        const LayerInfo& L = net->L[l];
+        net->pk_fwd[l] = net->pk_bwd[l] = net->pk_inf[l] = (size_t)-1;
+        if (L.bn) {
+            const int per = L.kind == LK_PW ? L.cin : (L.kind == LK_DW ? 9 : L.cin * 9);
+            HH_TRY(bn_fold(st, P + L.woff, P + L.goff, P + L.beoff, P + L.rmoff, P + L.rvoff, L.cout, per,
+                           F + L.woff, F + L.beoff));
+        }
+        if (L.kind == LK_PW) {
+            const size_t e = (size_t)L.cin * L.cout;
+            net->pk_fwd[l] = off;
+            net->pk_bwd[l] = off + e;
+            net->pk_inf[l] = off + 2 * e;
+            off += 3 * e;
+        } else if (L.kind != LK_DW && L.cin >= 16 && L.cout >= 16) {
+            net->pk_fwd[l] = off;
+            off += packed_weight_elems(L.cin, L.cout);
+            net->pk_bwd[l] = off;
+            off += packed_weight_elems(L.cout, L.cin);
+            if (L.bn) {
+                net->pk_inf[l] = off;
+                off += packed_weight_elems(L.cin, L.cout);
+            }
+        }
+        off = (off + 7) & ~(size_t)7;  // 16-byte aligned blocks
+    }
+    net->pk_proj_hi = off;
+    off += packed_weight_elems(16, 16);
+    net->pk_proj_lo = off;
+    off += packed_weight_elems(16, 16);
+    HH_TRY(net->packed.ensure(net->ctx, off * sizeof(uint16_t) + 256));
+    uint16_t* pk = net->packed.as<uint16_t>();
+    for (int l = 0; l < LIGHT_LAYERS; ++l) {
+        const LayerInfo& L = net->L[l];
+        if (L.kind == LK_PW) {
+            HH_TRY(pack_pointwise(st, P + L.woff, pk + net->pk_fwd[l], L.cout, L.cin, false));
+            HH_TRY(pack_pointwise(st, P + L.woff, pk + net->pk_bwd[l], L.cout, L.cin, true));
+            HH_TRY(pack_pointwise(st, F + L.woff, pk + net->pk_inf[l], L.cout, L.cin, false));
+        } else if (net->pk_fwd[l] != (size_t)-1) {
+            const bool up = L.kind == LK_UP || L.kind == LK_UP4;
+            HH_TRY(pack_weights(st, P + L.woff, pk + net->pk_fwd[l], L.cin, L.cout, up));
+            HH_TRY(pack_weights(st, P + L.woff, pk + net->pk_bwd[l], L.cout, L.cin, !up));
+            if (L.bn) HH_TRY(pack_weights(st, F + L.woff, pk + net->pk_inf[l], L.cin, L.cout, up));
+        }
+    }
+    HH_TRY(pack_weights_split(st, P + net->L[LL_OUT].woff, pk + net->pk_proj_hi, pk + net->pk_proj_lo, 16, 2, 16));
+    net->packed_valid = true;
+    return HH_OK;
+}
+
 hh_status net_pack(hh_net* net) {
     if (net->packed_valid) return HH_OK;
+    if (net->light) return light_pack(net);
     hipStream_t st = net->ctx->stream;
     size_t off = 0;
     for (int l = 0; l < NET_LAYERS; ++l) {
@@ -864,6 +995,64 @@ struct NetActs {
     }
 };
 
+// activations of the lightweight network: encoder layers (EB batch entries,
+// one per slowness model) and solver layers (B right-hand sides); in training
+// also the pre-normalisation outputs and batch statistics of the batch-norm layers
+struct LightActs {
+    int B = 0, n = 0, EB = 0, En = 0;
+    bool train = false, etrain = false;
+    Buf a[LIGHT_LAYERS];     // layer outputs (BF16 NHWC); a[LL_OUT]: FP32 (re, im) at n/2
+    Buf z[LIGHT_LAYERS];     // training: pre-normalisation outputs
+    Buf stat;                // training: float4 (mean, sd, scale, shift) per channel of every batch-norm layer
+    size_t stat_off[LIGHT_LAYERS] = {0};
+    Buf imp, impw, parts, scales, zeros, bnpart;
+    hh_status ensure_stat(hh_net* net) {
+        size_t off = 0;
+        for (int l = 0; l < LIGHT_LAYERS; ++l) {
+            stat_off[l] = off;
+            if (net->L[l].bn) off += net->L[l].cout;
+        }
+        return stat.ensure(net->ctx, off * sizeof(float4));
+    }
+    hh_status ensure_layers(hh_net* net, int l0, int l1, int Bn, int nn, bool tr) {
+        for (int l = l0; l <= l1; ++l) {
+            const int m = light_res(l, nn);
+            const size_t px = (size_t)Bn * m * m;
+            const size_t esz = (l == LL_OUT) ? sizeof(float) : sizeof(uint16_t);
+            HH_TRY(a[l].ensure(net->ctx, px * net->L[l].cout * esz));
+            if (tr && net->L[l].bn) HH_TRY(z[l].ensure(net->ctx, px * net->L[l].cout * sizeof(uint16_t)));
+        }
+        return HH_OK;
+    }
+    hh_status ensure_enc(hh_net* net, int EB_, int n_, bool tr) {
+        if (EB_ <= EB && n_ == En && (!tr || etrain)) return HH_OK;
+        EB = std::max(EB_, EB);
+        En = n_;
+        etrain = etrain || tr;
+        HH_TRY(ensure_stat(net));
+        return ensure_layers(net, LL_ENC1_D, LL_ENC3_C2, EB, En, etrain);
+    }
+    hh_status ensure(hh_net* net, int B_, int n_, bool tr) {
+        if (B_ <= B && n_ == n && (!tr || train)) return HH_OK;
+        B = std::max(B_, B);
+        n = n_;
+        train = train || tr;
+        HH_TRY(ensure_stat(net));
+        HH_TRY(ensure_layers(net, LL_S1_D, LL_OUT, B, n, train));
+        const int ncs = coarsest_of(n);
+        HH_TRY(imp.ensure(net->ctx, (size_t)B * ncs * ncs * net->ch[3] * sizeof(uint16_t)));
+        if (implicit_work_bytes(2 * ncs, ncs, net->nk, B) > 0)
+            HH_TRY(impw.ensure(net->ctx, implicit_work_bytes(2 * ncs, ncs, net->nk, B)));
+        HH_TRY(parts.ensure(net->ctx, (size_t)B * 64 * sizeof(double)));
+        HH_TRY(scales.ensure(net->ctx, (size_t)2 * B * sizeof(float)));
+        HH_TRY(zeros.ensure(net->ctx, (size_t)B * sizeof(int)));
+        HH_HIP(hipMemsetAsync(zeros.ptr, 0, (size_t)B * sizeof(int), net->ctx->stream));
+        return HH_OK;
+    }
+    uint16_t* out(int l) const { return a[l].as<uint16_t>(); }
+    float4* st(int l) const { return stat.as<float4>() + stat_off[l]; }
+};
+
 // ---------------------------------------------------------------------------
 // per-model network state: encodings and Ghat
 // ---------------------------------------------------------------------------
@@ -875,6 +1064,7 @@ struct NetCache {
     Buf enc[9];    // BF16 outputs of the 9 encoder layers per instance (E1, E2, E3 = enc[2], enc[5], enc[8])
     Buf Gbr;       // bit-reversed, scaled Ghat [nk][M][M]
     NetActs acts;  // forward activations of the solves on this model
+    LightActs lacts;  // the same for the lightweight network (encoder outputs in lacts.a[0..8])
 };
 
 void net_model_release(hh_model* m) {
@@ -895,7 +1085,7 @@ static hh_status conv_layer(hh_net* net, int l, int mode, const uint16_t* x, int
     a.skip = skip;
     a.skip_map = skip_map;
     a.mask = nullptr;
-    a.relu = relu ? 1 : 0;
+    a.act = relu ? ACT_RELU : ACT_NONE;
     a.B = B;
     a.Hin = Hin;
     a.Win = Win;
@@ -936,6 +1126,232 @@ hh_status encoder_forward(hh_net* net, hh_model* md, Buf* enc) {
     return HH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// lightweight network, forward (inference: batch norm folded into the weights;
+// training: batch statistics over the batch, running averages updated when
+// `update`)
+// ---------------------------------------------------------------------------
+// batch-norm + activation of layer l from its pre-normalisation output A.z[l]
+static hh_status light_bn(hh_net* net, LightActs& A, int l, size_t npix, int act, const uint16_t* res, bool update) {
+    const LayerInfo& L = net->L[l];
+    float* P = net->params.as<float>();
+    const BnParams bp{P + L.goff, P + L.beoff, P + L.rmoff, P + L.rvoff};
+    return bn_train_forward(net->ctx->stream, net->ctx, A.bnpart, L.cout, A.z[l].as<uint16_t>(), npix, bp, update,
+                            A.st(l), act, res, A.out(l));
+}
+
+// 3x3 layer l (convolution, stride-2 or transposed) into A.a[l]: with batch
+// norm either the folded form with softplus fused, or (training) the raw
+// convolution into A.z[l] and the normalisation; otherwise bias and skip
+static hh_status light_conv(hh_net* net, LightActs& A, int l, int mode, const uint16_t* x, int B, int Hin, int Win,
+                            int Hout, int Wout, const uint16_t* skip, const int* smap, const int* active, bool train,
+                            bool update) {
+    const LayerInfo& L = net->L[l];
+    const uint16_t* pk = net->packed.as<uint16_t>();
+    ConvArgs a{};
+    a.x = x;
+    a.B = B;
+    a.Hin = Hin;
+    a.Win = Win;
+    a.Hout = Hout;
+    a.Wout = Wout;
+    a.active = active;
+    a.skip = skip;
+    a.skip_map = skip ? smap : nullptr;
+    if (!L.bn) {
+        a.y = A.out(l);
+        a.wp = pk + net->pk_fwd[l];
+        a.bias = net->params.as<float>() + L.boff;
+        a.act = ACT_NONE;
+        return launch_conv(net->ctx->stream, net->ctx->num_cus, L.cin, L.cout, mode, a);
+    }
+    if (!train) {
+        a.y = A.out(l);
+        a.wp = pk + net->pk_inf[l];
+        a.bias = net->folded.as<float>() + L.beoff;
+        a.act = ACT_SOFTPLUS;
+        return launch_conv(net->ctx->stream, net->ctx->num_cus, L.cin, L.cout, mode, a);
+    }
+    a.y = A.z[l].as<uint16_t>();
+    a.wp = pk + net->pk_fwd[l];
+    a.bias = nullptr;
+    a.act = ACT_NONE;
+    a.active = nullptr;
+    HH_TRY(launch_conv(net->ctx->stream, net->ctx->num_cus, L.cin, L.cout, mode, a));
+    return light_bn(net, A, l, (size_t)B * Hout * Wout, ACT_SOFTPLUS, nullptr, update);
+}
+
+// inverted bottleneck of the layers le (expansion), le + 1 (depthwise), le + 2
+// (shrink) on x [B][m][m][c]: A.a[le + 2] = x + BN(shrink(...))
+static hh_status light_ib(hh_net* net, LightActs& A, int le, const uint16_t* x, int B, int m, const int* active,
+                          bool train, bool update) {
+    const int lw = le + 1, ls = le + 2;
+    const LayerInfo &E = net->L[le], &Dw = net->L[lw], &S = net->L[ls];
+    hipStream_t st = net->ctx->stream;
+    const int cus = net->ctx->num_cus;
+    const size_t npix = (size_t)B * m * m;
+    const float* P = net->params.as<float>();
+    const float* F = net->folded.as<float>();
+    const uint16_t* pk = net->packed.as<uint16_t>();
+    PwArgs pa{};
+    pa.npix = npix;
+    pa.pix_per_b = m * m;
+    DwArgs da{};
+    da.B = B;
+    da.H = da.W = m;
+    if (!train) {
+        pa.active = da.active = active;
+        pa.x = x;
+        pa.y = A.out(le);
+        pa.w = pk + net->pk_inf[le];
+        pa.bias = F + E.beoff;
+        pa.act = ACT_SOFTPLUS;
+        HH_TRY(launch_pointwise(st, cus, E.cin, E.cout, pa));
+        da.x = A.out(le);
+        da.y = A.out(lw);
+        da.w = F + Dw.woff;
+        da.bias = F + Dw.beoff;
+        da.act = ACT_SOFTPLUS;
+        HH_TRY(launch_depthwise(st, cus, Dw.cout, da));
+        pa.x = A.out(lw);
+        pa.y = A.out(ls);
+        pa.w = pk + net->pk_inf[ls];
+        pa.bias = F + S.beoff;
+        pa.act = ACT_NONE;
+        pa.res = x;
+        return launch_pointwise(st, cus, S.cin, S.cout, pa);
+    }
+    pa.x = x;
+    pa.y = A.z[le].as<uint16_t>();
+    pa.w = pk + net->pk_fwd[le];
+    HH_TRY(launch_pointwise(st, cus, E.cin, E.cout, pa));
+    HH_TRY(light_bn(net, A, le, npix, ACT_SOFTPLUS, nullptr, update));
+    da.x = A.out(le);
+    da.y = A.z[lw].as<uint16_t>();
+    da.w = P + Dw.woff;
+    HH_TRY(launch_depthwise(st, cus, Dw.cout, da));
+    HH_TRY(light_bn(net, A, lw, npix, ACT_SOFTPLUS, nullptr, update));
+    pa.x = A.out(lw);
+    pa.y = A.z[ls].as<uint16_t>();
+    pa.w = pk + net->pk_fwd[ls];
+    HH_TRY(launch_pointwise(st, cus, S.cin, S.cout, pa));
+    return light_bn(net, A, ls, npix, ACT_NONE, x, update);
+}
+
+// encoder of the lightweight network on every slowness model of md (A.a[0..8])
+static hh_status light_encoder_forward(hh_net* net, hh_model* md, LightActs& A, bool train, bool update) {
+    hipStream_t st = net->ctx->stream;
+    const int n = md->lev[0].n, B = md->ninst;
+    const double h = md->lev[0].h;
+    HH_TRY(A.ensure_enc(net, B, n, train));
+    const float* P = net->params.as<float>();
+    hipLaunchKernelGGL((k_conv_in_mfma<1>), conv_in_grid(n, B), dim3(256), 0, st, md->lev[0].coef.as<float2>(),
+                       (size_t)n * n, nullptr, nullptr, (float)(h * h), P + net->L[LL_ENC1_D].woff,
+                       P + net->L[LL_ENC1_D].boff, nullptr, nullptr, A.out(LL_ENC1_D), n, nullptr);
+    HH_LAUNCH_CHECK();
+    for (int k = 0; k < 3; ++k) {
+        const int l = 3 * k, m = n >> (k + 1);
+        if (k > 0)
+            HH_TRY(light_conv(net, A, l, CM_S2, A.out(l - 1), B, 2 * m, 2 * m, m, m, nullptr, nullptr, nullptr, train,
+                              update));
+        HH_TRY(light_conv(net, A, l + 1, CM_S1, A.out(l), B, m, m, m, m, nullptr, nullptr, nullptr, train, update));
+        HH_TRY(light_conv(net, A, l + 2, CM_S1, A.out(l + 1), B, m, m, m, m, nullptr, nullptr, nullptr, train,
+                          update));
+    }
+    return HH_OK;
+}
+
+// solver part of the lightweight network on B vectors v (see net_forward_core)
+static hh_status light_forward(hh_net* net, int n, double h, LightActs& A, int B, const int* smap, const uint16_t* E1,
+                               const uint16_t* E2, const uint16_t* E3, const float2* Gbr, const float2* v,
+                               size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active,
+                               bool train, bool update) {
+    hipStream_t st = net->ctx->stream;
+    HH_TRY(A.ensure(net, B, n, train));
+    if (train) active = nullptr;
+    float* in_scale = A.scales.as<float>();
+    float* out_scale = in_scale + B;
+    {
+        const int nblk = 64;
+        hipLaunchKernelGGL(k_sumsq, dim3(nblk, B), dim3(256), 0, st, v, vstride, (size_t)n * n, A.parts.as<double>(),
+                           active);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scales, dim3((B + 63) / 64), dim3(64), 0, st, A.parts.as<double>(), nblk, (size_t)n * n,
+                           sig, sig_stride, h * h, in_scale, out_scale, B);
+        HH_LAUNCH_CHECK();
+    }
+    const float* P = net->params.as<float>();
+    const int m1 = n / 2, m2 = n / 4, m3 = n / 8, m4 = coarsest_of(n), s4 = coarse_stride_of(n);
+    auto o = [&](int l) { return A.out(l); };
+    uint16_t* imp = A.imp.as<uint16_t>();
+    {
+        ProfScope ps(net->ctx, HH_K_CONV);
+        hipLaunchKernelGGL((k_conv_in_mfma<0>), conv_in_grid(n, B), dim3(256), 0, st, v, vstride, in_scale, nullptr,
+                           0.f, P + net->L[LL_S1_D].woff, P + net->L[LL_S1_D].boff, E1, smap, o(LL_S1_D), n, active);
+        HH_LAUNCH_CHECK();
+        HH_TRY(light_ib(net, A, LL_S1_E, o(LL_S1_D), B, m1, active, train, update));
+        HH_TRY(light_conv(net, A, LL_S2_D, CM_S2, o(LL_S1_S), B, m1, m1, m2, m2, E2, smap, active, train, update));
+        HH_TRY(light_ib(net, A, LL_S2_E, o(LL_S2_D), B, m2, active, train, update));
+        HH_TRY(light_conv(net, A, LL_S3_D, CM_S2, o(LL_S2_S), B, m2, m2, m3, m3, E3, smap, active, train, update));
+        HH_TRY(light_ib(net, A, LL_S3_E, o(LL_S3_D), B, m3, active, train, update));
+        HH_TRY(light_conv(net, A, LL_S4_D, s4 == 2 ? CM_S2 : CM_S1, o(LL_S3_S), B, m3, m3, m4, m4, nullptr, nullptr,
+                          active, train, update));
+        HH_TRY(light_conv(net, A, LL_S4_C1, CM_S1, o(LL_S4_D), B, m4, m4, m4, m4, nullptr, nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_S4_C2, CM_S1, o(LL_S4_C1), B, m4, m4, m4, m4, nullptr, nullptr, active, train,
+                          update));
+    }
+    {
+        ProfScope ps(net->ctx, HH_K_NET_OTHER);
+        if (net->explicit_coarse)
+            HH_TRY(launch_explicit(st, o(LL_S4_C2), imp, P + net->koff, m4, net->nk, B, false, active, nullptr));
+        else
+            HH_TRY(launch_implicit(st, 2 * m4, o(LL_S4_C2), imp, Gbr, m4, net->nk, B, false, active, nullptr,
+                                   A.impw.ptr ? A.impw.as<float2>() : nullptr));
+    }
+    {
+        ProfScope ps(net->ctx, HH_K_CONV);
+        HH_TRY(light_conv(net, A, LL_U3_T, s4 == 2 ? CM_T2 : CM_S1, imp, B, m4, m4, m3, m3, o(LL_S3_S), nullptr,
+                          active, train, update));
+        HH_TRY(light_conv(net, A, LL_U3_C1, CM_S1, o(LL_U3_T), B, m3, m3, m3, m3, nullptr, nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_U3_C2, CM_S1, o(LL_U3_C1), B, m3, m3, m3, m3, nullptr, nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_U2_T, CM_T2, o(LL_U3_C2), B, m3, m3, m2, m2, o(LL_S2_S), nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_U2_C1, CM_S1, o(LL_U2_T), B, m2, m2, m2, m2, nullptr, nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_U2_C2, CM_S1, o(LL_U2_C1), B, m2, m2, m2, m2, nullptr, nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_U1_T, CM_T2, o(LL_U2_C2), B, m2, m2, m1, m1, o(LL_S1_S), nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_U1_C1, CM_S1, o(LL_U1_T), B, m1, m1, m1, m1, nullptr, nullptr, active, train,
+                          update));
+        HH_TRY(light_conv(net, A, LL_U1_C2, CM_S1, o(LL_U1_C1), B, m1, m1, m1, m1, nullptr, nullptr, active, train,
+                          update));
+    }
+    {
+        ProfScope ps(net->ctx, HH_K_NET_OTHER);
+        float2* out = A.a[LL_OUT].as<float2>();
+        ConvArgs pa{};
+        pa.x = o(LL_U1_C2);
+        pa.wp = net->packed.as<uint16_t>() + net->pk_proj_hi;
+        pa.wp_lo = net->packed.as<uint16_t>() + net->pk_proj_lo;
+        pa.bias = P + net->L[LL_OUT].boff;
+        pa.yproj = out;
+        pa.B = B;
+        pa.Hin = pa.Win = pa.Hout = pa.Wout = m1;
+        pa.active = active;
+        HH_TRY(launch_conv_proj(st, net->ctx->num_cus, pa));
+        if (x0) {
+            hipLaunchKernelGGL(k_prolong_x0, dim3((n * n + 255) / 256, B), dim3(256), 0, st, out, out_scale, x0, n,
+                               active);
+            HH_LAUNCH_CHECK();
+        }
+    }
+    return HH_OK;
+}
+
 hh_status net_prepare_model(hh_model* md) {
     hh_net* net = md->net;
     if (!net) return HH_ERR_STATE;
@@ -969,7 +1385,10 @@ hh_status net_prepare_model(hh_model* md) {
         set_error("first-level channel count must be 16");
         return HH_ERR_ARG;
     }
-    HH_TRY(encoder_forward(net, md, nc->enc));
+    if (net->light)
+        HH_TRY(light_encoder_forward(net, md, nc->lacts, false, false));
+    else
+        HH_TRY(encoder_forward(net, md, nc->enc));
     nc->net = net;
     nc->uid = net->uid;
     nc->version = net->version;
@@ -1110,6 +1529,26 @@ hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const 
                             nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active);
 }
 
+// either network's forward pass on B vectors of model md (encodings and Ghat from
+// the model cache), and where its half-resolution output and scales are kept
+static hh_status net_forward_model(hh_net* net, hh_model* md, int B, const BatchMap& bm, const float2* v,
+                                   size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active) {
+    NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
+    if (!net->light) return net_forward_batch(net, md, nc->acts, B, bm, v, vstride, sig, sig_stride, x0, active);
+    LightActs& A = nc->lacts;
+    HH_TRY(A.ensure(net, B, md->lev[0].n, false));
+    const int* smap = md->ninst > 1 ? bm.inst : A.zeros.as<int>();
+    return light_forward(net, md->lev[0].n, md->lev[0].h, A, B, smap, A.out(LL_ENC1_C2), A.out(LL_ENC2_C2),
+                         A.out(LL_ENC3_C2), nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active, false,
+                         false);
+}
+static const float2* net_out_of(const NetCache* nc, const hh_net* net) {
+    return net->light ? nc->lacts.a[LL_OUT].as<float2>() : nc->acts.a[L_OUT].as<float2>();
+}
+static const float* net_out_scale_of(const NetCache* nc, const hh_net* net, int B) {
+    return (net->light ? nc->lacts.scales.as<float>() : nc->acts.scales.as<float>()) + B;
+}
+
 // ---------------------------------------------------------------------------
 // CNN+MG preconditioner used by the solve
 // ---------------------------------------------------------------------------
@@ -1125,9 +1564,9 @@ hh_status net_precond(void* user, hh_model* md, SolveWork& W, const BatchMap& bm
     NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
     // the V-cycle reads the network's half-resolution output and interpolates
     // the initial guess itself: no fine x0 is stored
-    HH_TRY(net_forward_batch(net, md, nc->acts, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, act));
+    HH_TRY(net_forward_model(net, md, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, act));
     return launch_vcycle_strided(md, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, 0, z, zstride, W.vwork.ptr, act,
-                                 nc->acts.a[L_OUT].as<float2>(), nc->acts.scales.as<float>() + W.nrhs);
+                                 net_out_of(nc, net), net_out_scale_of(nc, net, W.nrhs));
 }
 
 // ===========================================================================
@@ -1295,7 +1734,7 @@ static hh_status launch_bgrad(hipStream_t st, int C, const uint16_t* A, size_t n
 }
 
 // ---- projection layer (CIN -> 2) backward --------------------------------
-// input gradient: g[q][c] = sum_{o,t} W[o][c][t] go[q - off(t)][o], masked by (x > 0)
+// input gradient: g[q][c] = sum_{o,t} W[o][c][t] go[q - off(t)][o], masked by (x > 0) unless mask is null
 template <int CIN>
 __global__ void __launch_bounds__(256) k_out_dgrad(const float2* __restrict__ go, const float* __restrict__ W,
                                                    const uint16_t* __restrict__ mask, uint16_t* __restrict__ g, int m) {
@@ -1319,11 +1758,11 @@ __global__ void __launch_bounds__(256) k_out_dgrad(const float2* __restrict__ go
     const size_t o = ((size_t)b * m * m + q) * CIN;
 #pragma unroll
     for (int c0 = 0; c0 < CIN; c0 += 8) {
-        uint4 mr = *reinterpret_cast<const uint4*>(mask + o + c0);
+        uint4 mr = mask ? *reinterpret_cast<const uint4*>(mask + o + c0) : make_uint4(0, 0, 0, 0);
         const uint16_t* mh = reinterpret_cast<const uint16_t*>(&mr);
         uint16_t out[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) out[u] = f2bf(bf2f(mh[u]) > 0.f ? acc[c0 + u] : 0.f);
+        for (int u = 0; u < 8; ++u) out[u] = f2bf((!mask || bf2f(mh[u]) > 0.f) ? acc[c0 + u] : 0.f);
         *reinterpret_cast<uint4*>(g + o + c0) = *reinterpret_cast<uint4*>(out);
     }
 }
@@ -1691,6 +2130,11 @@ struct TrainWork {
     Buf part, part2;      // reduction scratch
     Buf gGh_part, gGh;    // implicit-layer kernel gradients
     Buf Gbr;              // transformed Green's functions of this step
+    // the lightweight network
+    LightActs lacts;
+    Buf LG[LIGHT_LAYERS];   // gradients w.r.t. each layer's output
+    Buf LGZ[LIGHT_LAYERS];  // ... and w.r.t. the pre-normalisation output of batch-norm layers
+    Buf coef;               // batch-norm backward coefficients
 };
 
 static hh_status ensure_grads(hh_net* net, TrainWork& T, int B, int n) {
@@ -1723,7 +2167,7 @@ static hh_status dgrad_layer(hh_net* net, int l, int mode, const uint16_t* gout,
     a.bias = nullptr;
     a.skip = add;
     a.mask = mask;
-    a.relu = 0;
+    a.act = ACT_NONE;
     a.B = B;
     a.Hin = Hout;
     a.Win = Wout;
@@ -1752,6 +2196,276 @@ static hh_status read_loss(hh_ctx* ctx, const Buf& lparts, int B, int n, const B
     return HH_OK;
 }
 
+// coarsest layer backward: gin = adjoint(T.gimp) masked by `mask` (null: none),
+// and the gradient of its kernels from its input z (B maps of m4 x m4) into GR
+static hh_status coarse_backward(hh_ctx* ctx, hh_net* net, TrainWork& T, int B, int m4, const uint16_t* z,
+                                 const uint16_t* mask, uint16_t* gin, float* GR) {
+    hipStream_t st = ctx->stream;
+    const float* P = net->params.as<float>();
+    const int nc = m4, M = 2 * m4;
+    if (net->explicit_coarse) {
+        HH_TRY(launch_explicit(st, T.gimp.as<uint16_t>(), gin, P + net->koff, m4, net->nk, B, true, nullptr,
+                               mask));
+        const int nblk = (m4 * m4 + EK_PIX - 1) / EK_PIX, count = net->nk * 9;
+        HH_TRY(T.gGh_part.ensure(ctx, (size_t)B * nblk * count * sizeof(double2)));
+        hipLaunchKernelGGL(k_explicit_kgrad, dim3(nblk, B), dim3(320), 0, st, z, T.gimp.as<uint16_t>(), m4,
+                           net->nk, T.gGh_part.as<double2>());
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_explicit_kgrad_reduce, dim3((count + 255) / 256), dim3(256), 0, st,
+                           T.gGh_part.as<double2>(), B * nblk, count, GR + net->koff);
+        HH_LAUNCH_CHECK();
+    } else {
+    HH_TRY(launch_implicit(st, M, T.gimp.as<uint16_t>(), gin, T.Gbr.as<float2>(), m4, net->nk, B, true,
+                           nullptr, mask));
+    {
+        HH_TRY(T.gGh_part.ensure(ctx, (size_t)B * net->nk * M * M * sizeof(float2)));
+        HH_TRY(T.gGh.ensure(ctx, (size_t)net->nk * M * M * sizeof(double2)));
+        const size_t lds = ((size_t)2 * M * (M + 1) + M / 2) * sizeof(float2);
+        dim3 grd(net->nk, B);
+        if (M == 32) {
+            hipLaunchKernelGGL((k_implicit_ggrad<32, 256>), grd, dim3(256), lds, st, z, T.gimp.as<uint16_t>(),
+                               T.gGh_part.as<float2>(), m4, net->nk);
+        } else if (M == 64) {
+            static bool attr = false;
+            if (!attr) {
+                HH_HIP(hipFuncSetAttribute((const void*)k_implicit_ggrad<64, 512>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                attr = true;
+            }
+            hipLaunchKernelGGL((k_implicit_ggrad<64, 512>), grd, dim3(512), lds, st, z,
+                               T.gimp.as<uint16_t>(), T.gGh_part.as<float2>(), m4, net->nk);
+        } else if (M == 16) {
+            hipLaunchKernelGGL((k_implicit_ggrad<16, 256>), grd, dim3(256), lds, st, z, T.gimp.as<uint16_t>(),
+                               T.gGh_part.as<float2>(), m4, net->nk);
+        } else {
+            set_error("implicit-layer gradient: transform size %d not supported", M);
+            return HH_ERR_ARG;
+        }
+        HH_LAUNCH_CHECK();
+        const int count = net->nk * M * M;
+        hipLaunchKernelGGL(k_reduce_ggrad, dim3((count + 255) / 256), dim3(256), 0, st, T.gGh_part.as<float2>(), B,
+                           count, T.gGh.as<double2>());
+        HH_LAUNCH_CHECK();
+        HH_TRY(green_backward(net, nc, T.gGh.as<double2>(), GR + net->koff, 1e-5));
+    }
+    }
+    return HH_OK;
+}
+
+// gradient norm and clip factor (on the device), Adam when lr > 0, and the loss
+static hh_status finish_train_step(hh_ctx* ctx, hh_net* net, TrainWork& T, int B, int n, double lr,
+                                   double max_grad_norm, double* loss_out, double* grad_norm_out) {
+    hipStream_t st = ctx->stream;
+    float* GR = net->grads.as<float>();
+    HH_TRY(T.gn.ensure(ctx, (GN_BLOCKS + 2) * sizeof(double)));
+    hipLaunchKernelGGL(k_grad_norm_parts, dim3(GN_BLOCKS), dim3(256), 0, st, GR, net->nparams,
+                       T.gn.as<double>() + 2);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_grad_norm, dim3(1), dim3(256), 0, st, T.gn.as<double>(), max_grad_norm);
+    HH_LAUNCH_CHECK();
+    // ---- Adam
+    if (lr > 0.0) {
+        if (!net->adam_m.ptr) {
+            HH_TRY(net->adam_m.ensure(ctx, net->nparams * sizeof(float)));
+            HH_TRY(net->adam_v.ensure(ctx, net->nparams * sizeof(float)));
+            HH_HIP(hipMemsetAsync(net->adam_m.ptr, 0, net->nparams * sizeof(float), st));
+            HH_HIP(hipMemsetAsync(net->adam_v.ptr, 0, net->nparams * sizeof(float), st));
+        }
+        net->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float bc1 = (float)(1.0 - pow(0.9, (double)net->step)), bc2 = (float)(1.0 - pow(0.999, (double)net->step));
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->nparams + 255) / 256)), dim3(256), 0, st,
+                           net->params.as<float>(), GR, T.gn.as<double>(), net->adam_m.as<float>(),
+                           net->adam_v.as<float>(), net->nparams, (float)lr, b1, b2, 1e-8f, bc1, bc2);
+        HH_LAUNCH_CHECK();
+        net->packed_valid = false;
+        net->version++;
+    }
+    return read_loss(ctx, T.lparts, B, n, &T.gn, loss_out, grad_norm_out);
+}
+
+// The lightweight network's training step (see train_core): forward with batch
+// statistics (running averages updated when lr > 0), loss, backward through
+// batch norm, softplus, the inverted bottlenecks and every convolution.
+static hh_status light_train_core(hh_ctx* ctx, hh_net* net, hh_model* md, TrainWork& T, int B, const void* r_dev,
+                                  const void* e_dev, double lr, double max_grad_norm, double* loss_out,
+                                  double* grad_norm_out, bool backward) {
+    hipStream_t st = ctx->stream;
+    const int n = md->lev[0].n;
+    const double h = md->lev[0].h;
+    const int m1 = n / 2, m2 = n / 4, m3 = n / 8, m4 = coarsest_of(n), s4 = coarse_stride_of(n);
+    LightActs& A = T.lacts;
+    const bool train = backward;  // the validation loss (no backward) applies the running statistics
+    const bool update = backward && lr > 0.0;
+    HH_TRY(light_encoder_forward(net, md, A, train, update));
+    HH_TRY(A.ensure(net, B, n, train));
+    const int* smap = md->ninst == 1 ? A.zeros.as<int>() : nullptr;  // sample b uses slowness model b
+    HH_TRY(light_forward(net, n, h, A, B, smap, A.out(LL_ENC1_C2), A.out(LL_ENC2_C2), A.out(LL_ENC3_C2),
+                         T.Gbr.as<float2>(), (const float2*)r_dev, (size_t)n * n, nullptr, 0, nullptr, nullptr,
+                         train, update));
+    HH_TRY(T.gfull.ensure(ctx, (size_t)B * n * n * sizeof(float2)));
+    HH_TRY(T.go.ensure(ctx, (size_t)B * m1 * m1 * sizeof(float2)));
+    HH_TRY(T.lparts.ensure(ctx, (size_t)B * 64 * sizeof(double)));
+    const float* out_scale = A.scales.as<float>() + B;
+    hipLaunchKernelGGL(k_loss, dim3(64, B), dim3(256), 0, st, A.a[LL_OUT].as<float2>(), (const float2*)e_dev,
+                       out_scale, T.gfull.as<float2>(), T.lparts.as<double>(), n, (float)(1.0 / ((double)B * n * n)));
+    HH_LAUNCH_CHECK();
+    if (!backward) return read_loss(ctx, T.lparts, B, n, nullptr, loss_out, nullptr);
+    if (md->ninst != B) {
+        set_error("training with one slowness model shared by the batch is not supported");
+        return HH_ERR_ARG;
+    }
+    if (update) {  // the running statistics changed: the folded weights are stale
+        net->packed_valid = false;
+        net->version++;
+    }
+    hipLaunchKernelGGL(k_restrict4, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.gfull.as<float2>(),
+                       T.go.as<float2>(), n);
+    HH_LAUNCH_CHECK();
+    // gradient buffers
+    for (int l = 0; l < LL_OUT; ++l) {
+        const int m = light_res(l, n);
+        const size_t bytes = (size_t)B * m * m * net->L[l].cout * sizeof(uint16_t);
+        HH_TRY(T.LG[l].ensure(ctx, bytes));
+        if (net->L[l].bn) HH_TRY(T.LGZ[l].ensure(ctx, bytes));
+    }
+    HH_TRY(T.gimp.ensure(ctx, (size_t)B * m4 * m4 * net->ch[3] * sizeof(uint16_t)));
+    HH_TRY(net->grads.ensure(ctx, net->nparams * sizeof(float)));
+    float* GR = net->grads.as<float>();
+    const float* P = net->params.as<float>();
+    auto o = [&](int l) { return A.out(l); };
+    auto G = [&](int l) { return T.LG[l].as<uint16_t>(); };
+    auto GZ = [&](int l) { return T.LGZ[l].as<uint16_t>(); };
+    // ---- projection layer (its weights and 2 biases are contiguous)
+    {
+        const int chunk = 1024;
+        const int nb = (m1 * m1 + chunk - 1) / chunk;
+        const int count = 2 * 16 * 9 + 2;
+        HH_TRY(T.part.ensure(ctx, (size_t)B * nb * count * sizeof(float)));
+        hipLaunchKernelGGL(k_out_wgrad<16>, dim3(nb, B), dim3(256), 0, st, T.go.as<float2>(), o(LL_U1_C2),
+                           T.part.as<float>(), m1, chunk);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
+                           count, GR + net->L[LL_OUT].woff, 1.f);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_out_dgrad<16>, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.go.as<float2>(),
+                           P + net->L[LL_OUT].woff, nullptr, G(LL_U1_C2), m1);
+        HH_LAUNCH_CHECK();
+    }
+    // batch norm (+ activation) backward of layer l from the gradient gout of its output, into GZ(l)
+    auto bn_back = [&](int l, const uint16_t* gout, size_t npix, int act) -> hh_status {
+        const LayerInfo& L = net->L[l];
+        const BnGrads gr{GR + L.goff, GR + L.beoff, GR + L.rmoff, GR + L.rvoff};
+        return bn_train_backward(st, ctx, T.part2, T.coef, L.cout, gout, A.z[l].as<uint16_t>(), npix, P + L.goff,
+                                 A.st(l), act, gr, GZ(l));
+    };
+    // 3x3 conv + batch norm + softplus layer l (stride 1, size m) from the gradient gout
+    // of its output: weight gradient from its input x, input gradient into gin
+    auto cb_back = [&](int l, const uint16_t* gout, const uint16_t* x, int m, uint16_t* gin) -> hh_status {
+        const LayerInfo& L = net->L[l];
+        HH_TRY(bn_back(l, gout, (size_t)B * m * m, ACT_SOFTPLUS));
+        HH_TRY(launch_wgrad(st, L.cout, L.cin, CM_S1, GZ(l), x, B, m, m, m, m, T.part, ctx, GR + L.woff));
+        return dgrad_layer(net, l, CM_S1, GZ(l), B, m, m, gin, m, m, nullptr, nullptr);
+    };
+    // strided convolution l (bias, no normalisation; input x at mi, output at mo, gradient G(l))
+    auto down_back = [&](int l, int wmode, int dmode, const uint16_t* x, int mi, int mo, uint16_t* gin,
+                         const uint16_t* add) -> hh_status {
+        const LayerInfo& L = net->L[l];
+        HH_TRY(launch_wgrad(st, L.cout, L.cin, wmode, G(l), x, B, mo, mo, mi, mi, T.part, ctx, GR + L.woff));
+        HH_TRY(launch_bgrad(st, L.cout, G(l), (size_t)B * mo * mo, T.part2, ctx, GR + L.boff));
+        return dgrad_layer(net, l, dmode, G(l), B, mo, mo, gin, mi, mi, add, nullptr);
+    };
+    // transposed convolution l (input x at mi, output at mo)
+    auto up_back = [&](int l, int mode, const uint16_t* x, int mi, int mo, uint16_t* gin) -> hh_status {
+        const LayerInfo& L = net->L[l];
+        HH_TRY(launch_wgrad(st, L.cin, L.cout, mode, x, G(l), B, mi, mi, mo, mo, T.part, ctx, GR + L.woff));
+        HH_TRY(launch_bgrad(st, L.cout, G(l), (size_t)B * mo * mo, T.part2, ctx, GR + L.boff));
+        return dgrad_layer(net, l, mode, G(l), B, mo, mo, gin, mi, mi, nullptr, nullptr);
+    };
+    // inverted bottleneck le .. le + 2 on input x (size m): gradient gout of its output,
+    // input gradient into gin (the skip path's gout included)
+    auto ib_back = [&](int le, const uint16_t* x, int m, const uint16_t* gout, uint16_t* gin) -> hh_status {
+        const int lw = le + 1, ls = le + 2;
+        const LayerInfo &E = net->L[le], &Dw = net->L[lw], &S = net->L[ls];
+        const size_t npix = (size_t)B * m * m;
+        const uint16_t* pk = net->packed.as<uint16_t>();
+        HH_TRY(bn_back(ls, gout, npix, ACT_NONE));
+        HH_TRY(launch_pw_wgrad(st, ctx, T.part, S.cin, S.cout, GZ(ls), o(lw), npix, GR + S.woff));
+        PwArgs pa{};
+        pa.npix = npix;
+        pa.pix_per_b = m * m;
+        pa.x = GZ(ls);
+        pa.y = G(lw);
+        pa.w = pk + net->pk_bwd[ls];
+        HH_TRY(launch_pointwise(st, ctx->num_cus, S.cout, S.cin, pa));
+        HH_TRY(bn_back(lw, G(lw), npix, ACT_SOFTPLUS));
+        HH_TRY(launch_dw_wgrad(st, ctx, T.part, Dw.cout, GZ(lw), o(le), B, m, m, GR + Dw.woff));
+        DwArgs da{};
+        da.x = GZ(lw);
+        da.y = G(le);
+        da.w = P + Dw.woff;
+        da.flip = 1;
+        da.B = B;
+        da.H = da.W = m;
+        HH_TRY(launch_depthwise(st, ctx->num_cus, Dw.cout, da));
+        HH_TRY(bn_back(le, G(le), npix, ACT_SOFTPLUS));
+        HH_TRY(launch_pw_wgrad(st, ctx, T.part, E.cin, E.cout, GZ(le), x, npix, GR + E.woff));
+        pa.x = GZ(le);
+        pa.y = gin;
+        pa.w = pk + net->pk_bwd[le];
+        pa.res = gout;
+        return launch_pointwise(st, ctx->num_cus, E.cout, E.cin, pa);
+    };
+    // ---- up path
+    HH_TRY(cb_back(LL_U1_C2, G(LL_U1_C2), o(LL_U1_C1), m1, G(LL_U1_C1)));
+    HH_TRY(cb_back(LL_U1_C1, G(LL_U1_C1), o(LL_U1_T), m1, G(LL_U1_T)));
+    HH_TRY(up_back(LL_U1_T, CM_S2, o(LL_U2_C2), m2, m1, G(LL_U2_C2)));
+    HH_TRY(cb_back(LL_U2_C2, G(LL_U2_C2), o(LL_U2_C1), m2, G(LL_U2_C1)));
+    HH_TRY(cb_back(LL_U2_C1, G(LL_U2_C1), o(LL_U2_T), m2, G(LL_U2_T)));
+    HH_TRY(up_back(LL_U2_T, CM_S2, o(LL_U3_C2), m3, m2, G(LL_U3_C2)));
+    HH_TRY(cb_back(LL_U3_C2, G(LL_U3_C2), o(LL_U3_C1), m3, G(LL_U3_C1)));
+    HH_TRY(cb_back(LL_U3_C1, G(LL_U3_C1), o(LL_U3_T), m3, G(LL_U3_T)));
+    HH_TRY(up_back(LL_U3_T, s4 == 2 ? CM_S2 : CM_S1, A.imp.as<uint16_t>(), m4, m3, T.gimp.as<uint16_t>()));
+    // ---- coarsest layer (no mask: softplus derivatives sit in the batch-norm backward)
+    HH_TRY(coarse_backward(ctx, net, T, B, m4, o(LL_S4_C2), nullptr, G(LL_S4_C2), GR));
+    // ---- level 4 and the down path (G of each strided layer's output is also its encoding's gradient)
+    HH_TRY(cb_back(LL_S4_C2, G(LL_S4_C2), o(LL_S4_C1), m4, G(LL_S4_C1)));
+    HH_TRY(cb_back(LL_S4_C1, G(LL_S4_C1), o(LL_S4_D), m4, G(LL_S4_D)));
+    HH_TRY(down_back(LL_S4_D, s4 == 2 ? CM_S2 : CM_S1, s4 == 2 ? CM_T2 : CM_S1, o(LL_S3_S), m3, m4, G(LL_S3_S),
+                     G(LL_U3_T)));
+    HH_TRY(ib_back(LL_S3_E, o(LL_S3_D), m3, G(LL_S3_S), G(LL_S3_D)));
+    HH_TRY(down_back(LL_S3_D, CM_S2, CM_T2, o(LL_S2_S), m2, m3, G(LL_S2_S), G(LL_U2_T)));
+    HH_TRY(ib_back(LL_S2_E, o(LL_S2_D), m2, G(LL_S2_S), G(LL_S2_D)));
+    HH_TRY(down_back(LL_S2_D, CM_S2, CM_T2, o(LL_S1_S), m1, m2, G(LL_S1_S), G(LL_U1_T)));
+    HH_TRY(ib_back(LL_S1_E, o(LL_S1_D), m1, G(LL_S1_S), G(LL_S1_D)));
+    const int chunk = 1024;
+    const int nb = (m1 * m1 + chunk - 1) / chunk;
+    const int count = 16 * 18 + 16;  // weights and biases of the 2 -> 16 layer
+    HH_TRY(T.part.ensure(ctx, (size_t)B * nb * count * sizeof(float)));
+    hipLaunchKernelGGL((k_in_wgrad<0, 16>), dim3(nb, B), dim3(256), 0, st, G(LL_S1_D), (const float2*)r_dev,
+                       (size_t)n * n, A.scales.as<float>(), 0.f, T.part.as<float>(), n, chunk);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb, count,
+                       GR + net->L[LL_S1_D].woff, 1.f);
+    HH_LAUNCH_CHECK();
+    // ---- encoder: the encodings' gradients are G(LL_S3_D), G(LL_S2_D), G(LL_S1_D)
+    HH_TRY(cb_back(LL_ENC3_C2, G(LL_S3_D), o(LL_ENC3_C1), m3, G(LL_ENC3_C1)));
+    HH_TRY(cb_back(LL_ENC3_C1, G(LL_ENC3_C1), o(LL_ENC3_D), m3, G(LL_ENC3_D)));
+    HH_TRY(down_back(LL_ENC3_D, CM_S2, CM_T2, o(LL_ENC2_C2), m2, m3, G(LL_ENC2_C2), G(LL_S2_D)));
+    HH_TRY(cb_back(LL_ENC2_C2, G(LL_ENC2_C2), o(LL_ENC2_C1), m2, G(LL_ENC2_C1)));
+    HH_TRY(cb_back(LL_ENC2_C1, G(LL_ENC2_C1), o(LL_ENC2_D), m2, G(LL_ENC2_D)));
+    HH_TRY(down_back(LL_ENC2_D, CM_S2, CM_T2, o(LL_ENC1_C2), m1, m2, G(LL_ENC1_C2), G(LL_S1_D)));
+    HH_TRY(cb_back(LL_ENC1_C2, G(LL_ENC1_C2), o(LL_ENC1_C1), m1, G(LL_ENC1_C1)));
+    HH_TRY(cb_back(LL_ENC1_C1, G(LL_ENC1_C1), o(LL_ENC1_D), m1, G(LL_ENC1_D)));
+    hipLaunchKernelGGL((k_in_wgrad<1, 16>), dim3(nb, B), dim3(256), 0, st, G(LL_ENC1_D), md->lev[0].coef.as<float2>(),
+                       (size_t)n * n, nullptr, (float)(h * h), T.part.as<float>(), n, chunk);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb, count,
+                       GR + net->L[LL_ENC1_D].woff, 1.f);
+    HH_LAUNCH_CHECK();
+    return finish_train_step(ctx, net, T, B, n, lr, max_grad_norm, loss_out, grad_norm_out);
+}
+
 // forward pass and loss on B pairs; with backward set, also every gradient and
 // (lr > 0) one Adam step on the gradient clipped to max_grad_norm (0 = no clip)
 static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev, const void* e_dev,
@@ -1778,6 +2492,9 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
     const int nc = coarsest_of(n), M = 2 * nc;
     HH_TRY(T.Gbr.ensure(ctx, (size_t)net->nk * M * M * sizeof(float2)));
     if (!net->explicit_coarse) HH_TRY(green_forward(net, nc, T.Gbr.as<float2>(), 1e-5));
+    if (net->light)
+        return light_train_core(ctx, net, md, T, B, r_dev, e_dev, lr, max_grad_norm, loss_out, grad_norm_out,
+                                backward);
     HH_TRY(encoder_forward(net, md, T.enc));
     NetActs& A = T.acts;
     HH_TRY(A.ensure(net, B, n));
@@ -1853,53 +2570,7 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
     HH_TRY(wgrad_convT(L_U3_T, s4 == 2 ? CM_S2 : CM_S1, A.imp.as<uint16_t>(), m4, m3));
     HH_TRY(dgrad_layer(net, L_U3_T, s4 == 2 ? CM_S2 : CM_S1, G(L_U3_T), B, m3, m3, T.gimp.as<uint16_t>(), m4, m4,
                        nullptr, nullptr));
-    // ---- coarsest layer: input gradient (adjoint, masked) and kernel gradient
-    if (net->explicit_coarse) {
-        HH_TRY(launch_explicit(st, T.gimp.as<uint16_t>(), G(L_S4_C2), P + net->koff, m4, net->nk, B, true, nullptr,
-                               act(L_S4_C2)));
-        const int nblk = (m4 * m4 + EK_PIX - 1) / EK_PIX, count = net->nk * 9;
-        HH_TRY(T.gGh_part.ensure(ctx, (size_t)B * nblk * count * sizeof(double2)));
-        hipLaunchKernelGGL(k_explicit_kgrad, dim3(nblk, B), dim3(320), 0, st, act(L_S4_C2), T.gimp.as<uint16_t>(), m4,
-                           net->nk, T.gGh_part.as<double2>());
-        HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_explicit_kgrad_reduce, dim3((count + 255) / 256), dim3(256), 0, st,
-                           T.gGh_part.as<double2>(), B * nblk, count, GR + net->koff);
-        HH_LAUNCH_CHECK();
-    } else {
-    HH_TRY(launch_implicit(st, M, T.gimp.as<uint16_t>(), G(L_S4_C2), T.Gbr.as<float2>(), m4, net->nk, B, true,
-                           nullptr, act(L_S4_C2)));
-    {
-        HH_TRY(T.gGh_part.ensure(ctx, (size_t)B * net->nk * M * M * sizeof(float2)));
-        HH_TRY(T.gGh.ensure(ctx, (size_t)net->nk * M * M * sizeof(double2)));
-        const size_t lds = ((size_t)2 * M * (M + 1) + M / 2) * sizeof(float2);
-        dim3 grd(net->nk, B);
-        if (M == 32) {
-            hipLaunchKernelGGL((k_implicit_ggrad<32, 256>), grd, dim3(256), lds, st, act(L_S4_C2), T.gimp.as<uint16_t>(),
-                               T.gGh_part.as<float2>(), m4, net->nk);
-        } else if (M == 64) {
-            static bool attr = false;
-            if (!attr) {
-                HH_HIP(hipFuncSetAttribute((const void*)k_implicit_ggrad<64, 512>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-                attr = true;
-            }
-            hipLaunchKernelGGL((k_implicit_ggrad<64, 512>), grd, dim3(512), lds, st, act(L_S4_C2),
-                               T.gimp.as<uint16_t>(), T.gGh_part.as<float2>(), m4, net->nk);
-        } else if (M == 16) {
-            hipLaunchKernelGGL((k_implicit_ggrad<16, 256>), grd, dim3(256), lds, st, act(L_S4_C2), T.gimp.as<uint16_t>(),
-                               T.gGh_part.as<float2>(), m4, net->nk);
-        } else {
-            set_error("implicit-layer gradient: transform size %d not supported", M);
-            return HH_ERR_ARG;
-        }
-        HH_LAUNCH_CHECK();
-        const int count = net->nk * M * M;
-        hipLaunchKernelGGL(k_reduce_ggrad, dim3((count + 255) / 256), dim3(256), 0, st, T.gGh_part.as<float2>(), B,
-                           count, T.gGh.as<double2>());
-        HH_LAUNCH_CHECK();
-        HH_TRY(green_backward(net, nc, T.gGh.as<double2>(), GR + net->koff, 1e-5));
-    }
-    }
+    HH_TRY(coarse_backward(ctx, net, T, B, m4, act(L_S4_C2), act(L_S4_C2), G(L_S4_C2), GR));
     // ---- down path, level 4
     HH_TRY(wgrad_conv(L_S4_C2, CM_S1, act(L_S4_C1), m4, m4, m4, m4));
     HH_TRY(dgrad_layer(net, L_S4_C2, CM_S1, G(L_S4_C2), B, m4, m4, G(L_S4_C1), m4, m4, nullptr, act(L_S4_C1)));
@@ -1976,32 +2647,7 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
                            count, GR + net->L[L_ENC1_D].woff, 1.f);
         HH_LAUNCH_CHECK();
     }
-    // ---- gradient norm and clip factor (device side, no host round trip)
-    HH_TRY(T.gn.ensure(ctx, (GN_BLOCKS + 2) * sizeof(double)));
-    hipLaunchKernelGGL(k_grad_norm_parts, dim3(GN_BLOCKS), dim3(256), 0, st, GR, net->nparams,
-                       T.gn.as<double>() + 2);
-    HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_grad_norm, dim3(1), dim3(256), 0, st, T.gn.as<double>(), max_grad_norm);
-    HH_LAUNCH_CHECK();
-    // ---- Adam
-    if (lr > 0.0) {
-        if (!net->adam_m.ptr) {
-            HH_TRY(net->adam_m.ensure(ctx, net->nparams * sizeof(float)));
-            HH_TRY(net->adam_v.ensure(ctx, net->nparams * sizeof(float)));
-            HH_HIP(hipMemsetAsync(net->adam_m.ptr, 0, net->nparams * sizeof(float), st));
-            HH_HIP(hipMemsetAsync(net->adam_v.ptr, 0, net->nparams * sizeof(float), st));
-        }
-        net->step += 1;
-        const float b1 = 0.9f, b2 = 0.999f;
-        const float bc1 = (float)(1.0 - pow(0.9, (double)net->step)), bc2 = (float)(1.0 - pow(0.999, (double)net->step));
-        hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->nparams + 255) / 256)), dim3(256), 0, st,
-                           net->params.as<float>(), GR, T.gn.as<double>(), net->adam_m.as<float>(),
-                           net->adam_v.as<float>(), net->nparams, (float)lr, b1, b2, 1e-8f, bc1, bc2);
-        HH_LAUNCH_CHECK();
-        net->packed_valid = false;
-        net->version++;
-    }
-    return read_loss(ctx, T.lparts, B, n, &T.gn, loss_out, grad_norm_out);
+    return finish_train_step(ctx, net, T, B, n, lr, max_grad_norm, loss_out, grad_norm_out);
 }
 
 extern "C" hh_status hh_train_step(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const void* r_dev,
@@ -2103,6 +2749,7 @@ hh_status hh_net_create(hh_ctx* ctx, const hh_net_desc* d, const float* params_h
     *out = nullptr;
     HH_ARG(valid_channels(d->ch), "channels must be (16, 32, 64, 64)");
     HH_ARG(d->explicit_coarse == 0 || d->explicit_coarse == 1, "explicit_coarse is 0 or 1");
+    HH_ARG(d->arch == HH_ARCH_UNET || d->arch == HH_ARCH_LIGHT, "arch is HH_ARCH_UNET or HH_ARCH_LIGHT");
     HH_HIP(hipSetDevice(ctx->device));
     hh_net* net = new (std::nothrow) hh_net();
     if (!net) {
@@ -2116,7 +2763,11 @@ hh_status hh_net_create(hh_ctx* ctx, const hh_net_desc* d, const float* params_h
     }
     for (int i = 0; i < 4; ++i) net->ch[i] = d->ch[i];
     net->explicit_coarse = d->explicit_coarse ? 1 : 0;
-    build_table(net);
+    net->light = d->arch == HH_ARCH_LIGHT ? 1 : 0;
+    if (net->light)
+        build_light_table(net);
+    else
+        build_table(net);
     hh_status s = net->params.ensure(ctx, net->nparams * sizeof(float));
     if (s >= 0 && params_host) {
         if (hipMemcpy(net->params.ptr, params_host, net->nparams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
@@ -2159,7 +2810,8 @@ hh_status hh_net_destroy(hh_net* net) {
     return HH_OK;
 }
 
-// file format 1: no coarsest-layer kind (implicit); 2: an int after the channels
+// file format 1: no coarsest-layer kind (implicit); 2: an int of flags after the
+// channels, bit 0 the explicit coarsest layer, bit 1 the lightweight network
 static const char kMagic[8] = {'H', 'H', 'N', 'E', 'T', '0', '0', '2'};
 static const char kMagic1[8] = {'H', 'H', 'N', 'E', 'T', '0', '0', '1'};
 
@@ -2180,8 +2832,9 @@ hh_status hh_net_save(hh_net* net, const char* path) {
         return HH_ERR_ARG;
     }
     const long long np = (long long)net->nparams, step = net->step;
+    const int flags = net->explicit_coarse | (net->light << 1);
     bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(net->ch, sizeof(int), 4, f) == 4 &&
-              fwrite(&net->explicit_coarse, sizeof(int), 1, f) == 1 && fwrite(&np, sizeof(np), 1, f) == 1 && fwrite(&step, sizeof(step), 1, f) == 1 &&
+              fwrite(&flags, sizeof(int), 1, f) == 1 && fwrite(&np, sizeof(np), 1, f) == 1 && fwrite(&step, sizeof(step), 1, f) == 1 &&
               fwrite(&have_adam, sizeof(int), 1, f) == 1 && fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
     if (ok && have_adam)
         ok = fwrite(m.data(), sizeof(float), m.size(), f) == m.size() &&
@@ -2206,10 +2859,12 @@ hh_status hh_net_load(hh_ctx* ctx, const char* path, hh_net** out) {
     hh_net_desc d;
     long long np = 0, step = 0;
     int have_adam = 0;
-    d.explicit_coarse = 0;
+    int flags = 0;
     bool ok = fread(magic, 1, 8, f) == 8 && (memcmp(magic, kMagic, 8) == 0 || memcmp(magic, kMagic1, 8) == 0) &&
               fread(d.ch, sizeof(int), 4, f) == 4;
-    if (ok && memcmp(magic, kMagic, 8) == 0) ok = fread(&d.explicit_coarse, sizeof(int), 1, f) == 1;
+    if (ok && memcmp(magic, kMagic, 8) == 0) ok = fread(&flags, sizeof(int), 1, f) == 1 && flags >= 0 && flags <= 3;
+    d.explicit_coarse = flags & 1;
+    d.arch = (flags >> 1) & 1 ? HH_ARCH_LIGHT : HH_ARCH_UNET;
     ok = ok && fread(&np, sizeof(np), 1, f) == 1 && fread(&step, sizeof(step), 1, f) == 1 &&
          fread(&have_adam, sizeof(int), 1, f) == 1;
     std::vector<float> p, m, v;
@@ -2272,10 +2927,8 @@ hh_status hh_net_forward(hh_model* m, int nrhs, const int* inst_host, const void
     Buf ib;
     BatchMap bm;
     HH_TRY(upload_inst_map(m, ib, nrhs, inst_host, &bm));
-    NetCache* nc = reinterpret_cast<NetCache*>(m->netcache);
     const size_t nn = (size_t)m->lev[0].n * m->lev[0].n;
-    HH_TRY(net_forward_batch(m->net, m, nc->acts, nrhs, bm, (const float2*)r_dev, nn, nullptr, 0, (float2*)e_dev,
-                             nullptr));
+    HH_TRY(net_forward_model(m->net, m, nrhs, bm, (const float2*)r_dev, nn, nullptr, 0, (float2*)e_dev, nullptr));
     HH_HIP(hipStreamSynchronize(m->ctx->stream));
     return HH_OK;
 }
@@ -2293,26 +2946,26 @@ hh_status hh_apply_cnn_precond(hh_model* m, int nrhs, const int* inst_host, cons
     NetCache* nc = reinterpret_cast<NetCache*>(m->netcache);
     const size_t nn = (size_t)m->lev[0].n * m->lev[0].n;
     const float2* v = (const float2*)v_dev;
-    HH_TRY(net_forward_batch(m->net, m, nc->acts, nrhs, bm, v, nn, nullptr, 0, nullptr, nullptr));
+    HH_TRY(net_forward_model(m->net, m, nrhs, bm, v, nn, nullptr, 0, nullptr, nullptr));
     HH_TRY(launch_vcycle_strided(m, nrhs, bm, v, nn, nullptr, 0, nullptr, 0, (float2*)z_dev, nn, work.ptr, nullptr,
-                                 nc->acts.a[L_OUT].as<float2>(), nc->acts.scales.as<float>() + nrhs));
+                                 net_out_of(nc, m->net), net_out_scale_of(nc, m->net, nrhs)));
     HH_HIP(hipStreamSynchronize(m->ctx->stream));
     return coarse_check_err(m);
 }
 
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
-                       const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int relu,
+                       const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int act,
                        void* y_dev, float* yf_dev, const int* active_host) {
     HH_ARG(ctx && x_dev && w_dev && y_dev, "null pointer");
     HH_ARG(mode >= 0 && mode <= 2, "mode");
     HH_ARG(B >= 1 && Hin >= 1 && Win >= 1, "sizes");
     HH_HIP(hipSetDevice(ctx->device));
-    Buf wp, act;
+    Buf wp, actb;
     HH_TRY(wp.ensure(ctx, packed_weight_elems(cin, cout) * sizeof(uint16_t) + 256));
     HH_TRY(pack_weights(ctx->stream, w_dev, wp.as<uint16_t>(), cin, cout, flipped != 0));
     if (active_host) {
-        HH_TRY(act.ensure(ctx, (size_t)B * sizeof(int)));
-        HH_HIP(hipMemcpyAsync(act.ptr, active_host, (size_t)B * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        HH_TRY(actb.ensure(ctx, (size_t)B * sizeof(int)));
+        HH_HIP(hipMemcpyAsync(actb.ptr, active_host, (size_t)B * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     }
     ConvArgs a{};
     a.x = (const uint16_t*)x_dev;
@@ -2321,13 +2974,13 @@ hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin,
     a.wp = wp.as<uint16_t>();
     a.bias = bias_dev;
     a.skip = (const uint16_t*)skip_dev;
-    a.relu = relu;
+    a.act = act;
     a.B = B;
     a.Hin = Hin;
     a.Win = Win;
     a.Hout = mode == CM_S2 ? Hin / 2 : (mode == CM_T2 ? 2 * Hin : Hin);
     a.Wout = mode == CM_S2 ? Win / 2 : (mode == CM_T2 ? 2 * Win : Win);
-    a.active = act.as<int>();
+    a.active = actb.as<int>();
     HH_TRY(launch_conv(ctx->stream, ctx->num_cus, cin, cout, mode, a));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
@@ -2343,6 +2996,50 @@ hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, in
     Buf part;
     HH_TRY(launch_wgrad(ctx->stream, ca, cx, mode, (const uint16_t*)a_dev, (const uint16_t*)x_dev, B, Ho, Wo, Hi, Wi,
                         part, ctx, out_dev));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+}
+
+hh_status hh_pointwise_test(hh_ctx* ctx, int cin, int cout, size_t npix, const void* x_dev, const float* w_dev,
+                            const float* bias_dev, const void* res_dev, int act, void* y_dev, float* yf_dev) {
+    HH_ARG(ctx && x_dev && w_dev && y_dev, "null pointer");
+    HH_ARG(act == ACT_NONE || act == ACT_SOFTPLUS, "act is 0 or 2");
+    HH_HIP(hipSetDevice(ctx->device));
+    Buf wp;
+    HH_TRY(wp.ensure(ctx, (size_t)cin * cout * sizeof(uint16_t)));
+    HH_TRY(pack_pointwise(ctx->stream, w_dev, wp.as<uint16_t>(), cout, cin, false));
+    PwArgs a{};
+    a.x = (const uint16_t*)x_dev;
+    a.y = (uint16_t*)y_dev;
+    a.yf = yf_dev;
+    a.w = wp.as<uint16_t>();
+    a.bias = bias_dev;
+    a.res = (const uint16_t*)res_dev;
+    a.act = act;
+    a.npix = npix;
+    HH_TRY(launch_pointwise(ctx->stream, ctx->num_cus, cin, cout, a));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+}
+
+hh_status hh_depthwise_test(hh_ctx* ctx, int C, int B, int H, int W, const void* x_dev, const float* w_dev,
+                            const float* bias_dev, int act, int flip, void* y_dev, float* yf_dev) {
+    HH_ARG(ctx && x_dev && w_dev && y_dev, "null pointer");
+    HH_ARG(act == ACT_NONE || act == ACT_SOFTPLUS, "act is 0 or 2");
+    HH_ARG(B >= 1 && H >= 1 && W >= 1, "sizes");
+    HH_HIP(hipSetDevice(ctx->device));
+    DwArgs a{};
+    a.x = (const uint16_t*)x_dev;
+    a.y = (uint16_t*)y_dev;
+    a.yf = yf_dev;
+    a.w = w_dev;
+    a.bias = bias_dev;
+    a.act = act;
+    a.flip = flip ? 1 : 0;
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    HH_TRY(launch_depthwise(ctx->stream, ctx->num_cus, C, a));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
 }

@@ -11,8 +11,9 @@
 // transposed convolution, evaluated as a stride-1 convolution over the
 // zero-interleaved input with flipped weights).  The input gradients of the
 // three layer kinds are again S1/S2/T2 convolutions with repacked weights.
-// The epilogue fuses bias, a sum skip connection, ReLU, and (backward) the
-// ReLU mask of the tensor whose gradient is produced.
+// The epilogue fuses bias, a sum skip connection, the activation (ReLU, or
+// softplus for the lightweight network), and (backward) the ReLU mask of the
+// tensor whose gradient is produced.
 #include "net.h"
 
 namespace hh {
@@ -272,9 +273,13 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
                 v[2] += bf2f((uint16_t)(s2.y & 0xffff));
                 v[3] += bf2f((uint16_t)(s2.y >> 16));
             }
-            if (a.relu)
+            if (a.act == ACT_RELU) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
+            } else if (a.act == ACT_SOFTPLUS) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = softplus_f(v[i]);
+            }
             if (a.mask) {
                 uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
                 if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
@@ -442,9 +447,13 @@ __global__ void __launch_bounds__(256) k_conv_dma(ConvArgs a) {
                     v[2] += bf2f((uint16_t)(s2.y & 0xffff));
                     v[3] += bf2f((uint16_t)(s2.y >> 16));
                 }
-                if (a.relu)
+                if (a.act == ACT_RELU) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
+                } else if (a.act == ACT_SOFTPLUS) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = softplus_f(v[i]);
+                }
                 if (a.mask) {
                     uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
                     if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
@@ -629,9 +638,13 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
                 v[2] += bf2f((uint16_t)(s2.y & 0xffff));
                 v[3] += bf2f((uint16_t)(s2.y >> 16));
             }
-            if (a.relu)
+            if (a.act == ACT_RELU) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
+            } else if (a.act == ACT_SOFTPLUS) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = softplus_f(v[i]);
+            }
             if (a.mask) {
                 uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
                 if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;

@@ -84,7 +84,10 @@ hh_solve_batch = _sig("hh_solve_batch", _I, _P, _I, _P, _IP, _P, _P, _P, C.POINT
 hh_apply_operator = _sig("hh_apply_operator", _I, _P, _I, _D, _I, _IP, _P, _P)
 hh_apply_vcycle = _sig("hh_apply_vcycle", _I, _P, _I, _IP, _P, _P, _P)
 class hh_net_desc(C.Structure):
-    _fields_ = [("ch", C.c_int * 4), ("explicit_coarse", C.c_int)]
+    _fields_ = [("ch", C.c_int * 4), ("explicit_coarse", C.c_int), ("arch", C.c_int)]
+
+
+HH_ARCH_UNET, HH_ARCH_LIGHT = 0, 1
 
 
 _FP = C.POINTER(C.c_float)
@@ -100,6 +103,8 @@ hh_net_forward = _sig("hh_net_forward", _I, _P, _I, _IP, _P, _P)
 hh_apply_cnn_precond = _sig("hh_apply_cnn_precond", _I, _P, _I, _IP, _P, _P)
 hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _IP)
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
+hh_pointwise_test = _sig("hh_pointwise_test", _I, _P, _I, _I, C.c_size_t, _P, _P, _P, _P, _I, _P, _P)
+hh_depthwise_test = _sig("hh_depthwise_test", _I, _P, _I, _I, _I, _I, _P, _P, _P, _I, _I, _P, _P)
 hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
 hh_gen_training_pairs = _sig("hh_gen_training_pairs", _I, _P, _P, _I, _P, _IP, _P, _P)
 hh_residual_norms = _sig("hh_residual_norms", _I, _P, _P, _I, _IP, _P, _P, _DP)
@@ -373,19 +378,22 @@ def solve_batch(ctx: Context, models, bs, insts=None, restart=10, max_iters=2000
 # network
 # ---------------------------------------------------------------------------
 
-from .netfile import NET_LAYER_NAMES, flatten_params, read_header, read_params, unflatten_params  # noqa: E402,F401
+from .netfile import (NET_LAYER_NAMES, flatten_light_params, flatten_params, read_header, read_params,  # noqa: E402,F401
+                      unflatten_light_params, unflatten_params)
 
 
 class Net:
     """Encoder-solver network on the device (FP32 master parameters)."""
 
     def __init__(self, ctx: Context, params: dict | np.ndarray | None = None, ch=(16, 32, 64, 64), _handle=None,
-                 explicit: bool = False):
-        """explicit: the explicit U-Net (the coarsest level convolves with the
-        learned kernels instead of applying their Green's functions)."""
+                 explicit: bool = False, light: bool = False):
+        """explicit: the coarsest level convolves with the learned kernels
+        instead of applying their Green's functions; light: the lightweight
+        network (inverted bottlenecks, batch normalisation, softplus)."""
         self.ctx = ctx
         self.ch = tuple(ch)
         self.explicit = bool(explicit)
+        self.light = bool(light)
         if _handle is not None:
             self.handle = _handle
             ctx._children.add(self)
@@ -394,9 +402,13 @@ class Net:
         for i in range(4):
             d.ch[i] = ch[i]
         d.explicit_coarse = int(self.explicit)
+        d.arch = HH_ARCH_LIGHT if self.light else HH_ARCH_UNET
         flat = None
         if params is not None:
-            flat = params if isinstance(params, np.ndarray) else flatten_params(params, ch)
+            if isinstance(params, np.ndarray):
+                flat = params
+            else:
+                flat = flatten_light_params(params, ch) if self.light else flatten_params(params, ch)
             flat = np.ascontiguousarray(flat, dtype=np.float32)
         h = C.c_void_p()
         check(hh_net_create(ctx.handle, C.byref(d), flat.ctypes.data_as(_FP) if flat is not None else None,
@@ -411,7 +423,7 @@ class Net:
         h = C.c_void_p()
         check(hh_net_load(ctx.handle, path.encode(), C.byref(h)))
         hd = read_header(path)
-        return cls(ctx, ch=hd["ch"], _handle=h, explicit=hd["explicit"])
+        return cls(ctx, ch=hd["ch"], _handle=h, explicit=hd["explicit"], light=hd["light"])
 
     def save(self, path: str):
         check(hh_net_save(self.handle, path.encode()))
@@ -433,6 +445,10 @@ class Net:
         a = np.zeros(self.num_params(), dtype=np.float32)
         check(hh_net_get_grads(self.handle, a.ctypes.data_as(_FP)))
         return a
+
+    def unflatten(self, flat: np.ndarray) -> dict:
+        """Named FP64 parameters (or gradients) of a flat vector of this network."""
+        return unflatten_light_params(flat, self.ch) if self.light else unflatten_params(flat, self.ch)
 
     def train_step(self, model: "Model", r: torch.Tensor, e: torch.Tensor, lr: float,
                    max_grad_norm: float = 0.0) -> float:
@@ -472,8 +488,9 @@ class Net:
 
 
 def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, flipped: bool, bias=None, skip=None,
-              relu=False, active=None, fill=None):
+              relu=False, active=None, fill=None, act=None):
     """One convolution through the library's MFMA kernel; returns (y bf16, y fp32).
+    act: 0 none, 1 ReLU, 2 softplus (default: 1 if relu else 0).
     active: optional per-batch-entry flags (0 = skipped, output left as filled);
     fill: initial value of both outputs (default: uninitialised)."""
     B, H, W_, cin = x_bf16.shape
@@ -491,7 +508,8 @@ def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, fl
     bias = bias.to(torch.float32).contiguous() if bias is not None else None
     skip = skip.contiguous() if skip is not None else None
     check(hh_conv_test(ctx.handle, cin, cout, mode, B, H, W_, _ptr(x_bf16), _ptr(w), int(flipped), _ptr(bias),
-                       _ptr(skip), int(relu), _ptr(y), _ptr(yf), _int_array(active)))
+                       _ptr(skip), int(act if act is not None else (1 if relu else 0)), _ptr(y), _ptr(yf),
+                       _int_array(active)))
     return y, yf
 
 
@@ -503,3 +521,32 @@ def wgrad_test(ctx: Context, a_bf16: torch.Tensor, x_bf16: torch.Tensor, mode: i
     out = torch.empty((ca, cx, 3, 3), dtype=torch.float32, device=a_bf16.device)
     check(hh_wgrad_test(ctx.handle, ca, cx, mode, B, Ho, Wo, Hi, Wi, _ptr(a_bf16), _ptr(x_bf16), _ptr(out)))
     return out
+
+
+def pointwise_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, bias=None, res=None, act: int = 0):
+    """The lightweight network's 1x1 convolution: x [..., cin] BF16, w (cout, cin); returns (y bf16, y fp32)."""
+    cin = x_bf16.shape[-1]
+    cout = w.shape[0]
+    npix = x_bf16.numel() // cin
+    y = torch.empty(x_bf16.shape[:-1] + (cout,), dtype=torch.bfloat16, device=x_bf16.device)
+    yf = torch.empty(y.shape, dtype=torch.float32, device=x_bf16.device)
+    w = w.to(torch.float32).contiguous()
+    bias = bias.to(torch.float32).contiguous() if bias is not None else None
+    res = res.contiguous() if res is not None else None
+    x_bf16 = x_bf16.contiguous()
+    check(hh_pointwise_test(ctx.handle, cin, cout, npix, _ptr(x_bf16), _ptr(w), _ptr(bias), _ptr(res), int(act),
+                            _ptr(y), _ptr(yf)))
+    return y, yf
+
+
+def depthwise_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, bias=None, act: int = 0, flip=False):
+    """The lightweight network's depthwise 3x3 convolution: x [B][H][W][C] BF16, w (C, 3, 3)."""
+    B, H, W_, Cc = x_bf16.shape
+    y = torch.empty_like(x_bf16)
+    yf = torch.empty(x_bf16.shape, dtype=torch.float32, device=x_bf16.device)
+    w = w.to(torch.float32).contiguous()
+    bias = bias.to(torch.float32).contiguous() if bias is not None else None
+    x_bf16 = x_bf16.contiguous()
+    check(hh_depthwise_test(ctx.handle, Cc, B, H, W_, _ptr(x_bf16), _ptr(w), _ptr(bias), int(act), int(flip),
+                            _ptr(y), _ptr(yf)))
+    return y, yf

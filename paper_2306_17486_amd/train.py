@@ -250,12 +250,15 @@ def main(argv=None):
     ap.add_argument("--gen-seed", type=int, default=None, help="seed of the random vectors (default: --seed)")
     ap.add_argument("--explicit", action="store_true",
                     help="train the explicit U-Net (the coarsest level convolves with the kernels, Sec. 5.2)")
+    ap.add_argument("--light", action="store_true",
+                    help="train the lightweight network (inverted bottlenecks, batch norm, softplus; Sec. 4.4)")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("training runs on the GPU")
     ctx = hh.Context(0)
-    init = inputs.init_net_params(args.init_seed)
-    net = hh.Net.load(ctx, args.init_from) if args.init_from else hh.Net(ctx, init, explicit=args.explicit)
+    init = inputs.init_light_params(args.init_seed) if args.light else inputs.init_net_params(args.init_seed)
+    net = (hh.Net.load(ctx, args.init_from) if args.init_from
+           else hh.Net(ctx, init, explicit=args.explicit, light=args.light))
     sizes = tuple(int(s) for s in args.sizes.split(","))
     if any(s not in SIZE_WEIGHT for s in sizes):
         sys.exit(f"training sizes must be among {sorted(SIZE_WEIGHT)}")
@@ -265,7 +268,9 @@ def main(argv=None):
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
     _log(f"[train] saved {args.out} after {hist['seconds']:.0f} s ({hist['steps_per_s']:.2f} steps/s)")
-    untrained = hh.Net(ctx, init, explicit=net.explicit)
+    if net.light != args.light:
+        init = inputs.init_light_params(args.init_seed) if net.light else inputs.init_net_params(args.init_seed)
+    untrained = hh.Net(ctx, init, explicit=net.explicit, light=net.light)
     nets = {"cnn_untrained": untrained, "cnn_trained": net}
     ev = evaluate(ctx, nets, sizes=tuple(int(s) for s in args.eval_sizes.split(",") if s), nk=args.eval_media)
     ev.update(evaluate(ctx, nets, sizes=tuple(int(s) for s in args.eval_large.split(",") if s),
