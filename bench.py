@@ -37,7 +37,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Helmholtz solves/s to rel. residual 1e-6 at 1024², CNN+MG vs MG-only FGMRES"
-NET_FILE = os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256_512.bin")
+NET_FILES = {  # the shipped networks (trained on 128/256/512 GRF and layered media)
+    "unet": os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_ms128_256_512.bin"),
+    "light": os.path.join(ROOT, "paper_2306_17486_amd", "weights", "net_light_ms128_256_512.bin"),
+}
+NET_FILE = NET_FILES["unet"]
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix, published
@@ -74,7 +78,11 @@ def _cpu_worker(args):
     s_cnn = None
     if net_file:
         flat, ch = netfile.read_params(net_file)
-        netp = S.NetPrecond(C.Net(netfile.unflatten_params(flat, ch)), prob)  # encoder: once per medium
+        if netfile.read_header(net_file)["light"]:
+            onet = C.LightNet(netfile.unflatten_light_params(flat, ch))
+        else:
+            onet = C.Net(netfile.unflatten_params(flat, ch))
+        netp = S.NetPrecond(onet, prob)  # encoder: once per medium
         t = time.perf_counter()
         H.fgmres(prob.A, b, lambda v: S.cnn_mg_precond(prob, netp, v), x, 10, 1e-6, mg_iters + 1,
                  iters_done=mg_iters)
@@ -168,76 +176,70 @@ def cpu_baseline(sample, n, mg_iters, iters_mg, iters_cnn):
                         f"solve (the GPU run's means); wall {wall:.1f} s"}
 
 
-def network_flops(n: int) -> float:
-    """FLOPs of the BF16 MFMA convolutions of one solver-network application
-    (encoder excluded: it runs once per slowness model).  A convolution costs
-    2 * 9 * cin * cout per output pixel, a transposed one per input pixel; the
-    FP32 input (2 -> 16) and projection (16 -> 2) layers are not counted."""
+def _net_layers(light: bool):
+    """(name, kind, cin, cout) of the solver's layers whose kernels form the
+    "conv" class: the encoder, the FP32 input layer and the projection are not
+    in it."""
     from paper_2306_17486_amd import inputs
+    layers = inputs.net_layers_light() if light else inputs.net_layers((16, 32, 64, 64))
+    return [(nm, k, ci, co) for nm, k, ci, co in layers if not nm.startswith("enc") and nm not in ("s1_d", "out")]
+
+
+def _layer_cost(n: int, name: str, kind: str, cin: int, cout: int):
+    """(FLOPs, HBM bytes) of one layer per right-hand side: a 3x3 convolution
+    costs 2 * 9 * cin * cout per output pixel (a transposed one per input
+    pixel), a 1x1 one 2 * cin * cout, a depthwise one 2 * 9 * cout (vector
+    ALU); BF16 activations are written once and read once by the next layer,
+    transposed layers also read their skip input, the strided layers of levels
+    2 and 3 the encoding added in.  The lightweight network's bottleneck runs
+    as one kernel: only its input and output touch HBM (counted at the shrink)."""
     nc = n // 16 if n >= 512 else n // 8
     out_size = {"s1": n // 2, "s2": n // 4, "s3": n // 8, "s4": nc, "u3": n // 8, "u2": n // 4, "u1": n // 2}
     tin_size = {"u3": nc, "u2": n // 8, "u1": n // 4}
-    f = 0.0
-    for name, kind, cin, cout in inputs.net_layers((16, 32, 64, 64)):
-        lvl = name.split("_")[0]
-        if lvl.startswith("enc") or name in ("s1_d", "out"):
-            continue
-        pix = tin_size[lvl] ** 2 if kind in ("t", "t4") else out_size[lvl] ** 2
-        f += 2.0 * 9 * cin * cout * pix
-    return f
+    in_size = {"s1": n // 2, "s2": n // 2, "s3": n // 4, "s4": n // 8}
+    lvl = name.split("_")[0]
+    po = out_size[lvl] ** 2
+    if kind in ("t", "t4"):
+        pi = tin_size[lvl] ** 2
+        return 2.0 * 9 * cin * cout * pi, 2.0 * (pi * cin + 2 * po * cout)
+    if kind in ("e", "s"):
+        return 2.0 * cin * cout * po, (2.0 * (po * cout + po * cout) if kind == "s" else 0.0)
+    if kind == "w":
+        return 2.0 * 9 * cout * po, 0.0
+    pi = (in_size[lvl] ** 2) if kind in ("d", "d4") else po
+    byt = 2.0 * (pi * cin + po * cout)
+    if kind in ("d", "d4") and lvl in ("s2", "s3"):
+        byt += 2.0 * po * cout
+    return 2.0 * 9 * cin * cout * po, byt
 
 
-def network_bytes(n: int) -> float:
+def network_flops(n: int, light: bool = False) -> float:
+    """FLOPs of the convolutions of one solver-network application per
+    right-hand side (encoder, FP32 input and projection layers excluded)."""
+    return sum(_layer_cost(n, *L)[0] for L in _net_layers(light))
+
+
+def network_bytes(n: int, light: bool = False) -> float:
     """HBM bytes of the convolution class per right-hand side and network
-    application when every BF16 activation is written once and read once by
-    the next layer (input layer: the complex64 residual and the first
-    encoding in, 16 channels at n/2 out; transposed layers also read their
-    skip input; the projection layer is not in the class)."""
-    from paper_2306_17486_amd import inputs
-    nc = n // 16 if n >= 512 else n // 8
-    out_size = {"s1": n // 2, "s2": n // 4, "s3": n // 8, "s4": nc, "u3": n // 8, "u2": n // 4, "u1": n // 2}
-    tin_size = {"u3": nc, "u2": n // 8, "u1": n // 4}
-    in_size = {"s1": n // 2, "s2": n // 2, "s3": n // 4, "s4": n // 8}
-    byt = 8.0 * n * n + 2.0 * 16 * (n // 2) ** 2 + 2.0 * 16 * (n // 2) ** 2  # input layer: v, E1, output
-    for name, kind, cin, cout in inputs.net_layers((16, 32, 64, 64)):
-        lvl = name.split("_")[0]
-        if lvl.startswith("enc") or name in ("s1_d", "out"):
-            continue
-        po = out_size[lvl] ** 2
-        if kind in ("t", "t4"):
-            byt += 2.0 * (tin_size[lvl] ** 2 * cin + 2 * po * cout)
-        else:
-            pi = (in_size[lvl] ** 2) if kind in ("d", "d4") else po
-            byt += 2.0 * (pi * cin + po * cout)
-            if kind in ("d", "d4") and lvl in ("s2", "s3"):
-                byt += 2.0 * po * cout  # the encoding added in
-    return byt
+    application (input layer: the complex64 residual and the first encoding
+    in, 16 channels at n/2 out; then every layer of _layer_cost)."""
+    byt = 8.0 * n * n + 2.0 * 16 * (n // 2) ** 2 + 2.0 * 16 * (n // 2) ** 2
+    return byt + sum(_layer_cost(n, *L)[1] for L in _net_layers(light))
 
 
-def network_ceiling(n: int) -> float:
+def network_ceiling(n: int, light: bool = False) -> float:
     """Fraction of the BF16 MFMA peak the network's convolutions can reach at
-    most: every layer at the roofline min(peak, intensity x HBM bandwidth),
-    with BF16 activations read once and written once (a transposed layer also
-    reads its skip input)."""
-    from paper_2306_17486_amd import inputs
-    nc = n // 16 if n >= 512 else n // 8
-    out_size = {"s1": n // 2, "s2": n // 4, "s3": n // 8, "s4": nc, "u3": n // 8, "u2": n // 4, "u1": n // 2}
-    tin_size = {"u3": nc, "u2": n // 8, "u1": n // 4}
-    in_size = {"s1": n // 2, "s2": n // 2, "s3": n // 4, "s4": n // 8}
+    most: every layer at the roofline min(peak, intensity x HBM bandwidth)
+    (a fused bottleneck as one unit)."""
     flops = t_roof = 0.0
-    for name, kind, cin, cout in inputs.net_layers((16, 32, 64, 64)):
-        lvl = name.split("_")[0]
-        if lvl.startswith("enc") or name in ("s1_d", "out"):
+    pend_f = 0.0
+    for L in _net_layers(light):
+        f, byt = _layer_cost(n, *L)
+        if L[1] in ("e", "w"):  # fused with the following shrink
+            pend_f += f
             continue
-        po = out_size[lvl] ** 2
-        if kind in ("t", "t4"):
-            pi = tin_size[lvl] ** 2
-            f = 2.0 * 9 * cin * cout * pi
-            byt = 2.0 * (pi * cin + 2 * po * cout)
-        else:
-            pi = (in_size[lvl] ** 2) if kind in ("d", "d4") else po
-            f = 2.0 * 9 * cin * cout * po
-            byt = 2.0 * (pi * cin + po * cout)
+        f += pend_f
+        pend_f = 0.0
         flops += f
         t_roof += max(f / (BF16_PEAK_TFLOPS * 1e12), byt / (HBM_PEAK_GBS * 1e9))
     return flops / t_roof / (BF16_PEAK_TFLOPS * 1e12)
@@ -248,7 +250,7 @@ def network_ceiling(n: int) -> float:
 # counters' reading of a plain copy of known size.  Reported only while the
 # class's kernel sources are unchanged since the counters were taken.
 CLASS_SOURCES = {
-    "conv": ("net_conv.hip", "hh_internal.h"),
+    "conv": ("net_conv.hip", "net_light.hip", "net.h", "hh_internal.h"),
     "op_dots": ("krylov.hip", "hh_internal.h"),
     "ortho": ("krylov.hip", "hh_internal.h"),
     "vc_down": ("mg.hip", "hh_internal.h"),
@@ -268,12 +270,12 @@ def class_source_sha(cls: str) -> str | None:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cls: str, active_rhs: float):
+def measured_traffic(cls: str, active_rhs: float, workload: str = "cnn_mg_1024_64rhs"):
     """HBM bytes per launch of class `cls` with `active_rhs` right-hand sides
-    active: the per-RHS traffic of profiles/<cls>_cnn_mg_1024_64rhs_traffic.txt
+    active: the per-RHS traffic of profiles/<cls>_<workload>_traffic.txt
     (lines 'key: value'; counters taken with every RHS active) times the
     active count, or None when absent or taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"{cls}_cnn_mg_1024_64rhs_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{cls}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -440,6 +442,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--no-exact", action="store_true", help="skip the error against the exact solutions")
     ap.add_argument("--workload", choices=["single", "batch"], default="single")
+    ap.add_argument("--net", choices=sorted(NET_FILES), default="unet",
+                    help="the network of CNN+MG: the U-Net (default) or the lightweight network")
     ap.add_argument("--batch-max-iters", type=int, default=2000)
     a = ap.parse_args()
     if a.gpus != 1:
@@ -450,11 +454,13 @@ def main():
         run_batch(a)
         return
 
-    use_cnn = a.precond == "cnn_mg" or (a.precond == "auto" and os.path.exists(NET_FILE))
+    net_file = NET_FILES[a.net]
+    light = a.net == "light"
+    use_cnn = a.precond == "cnn_mg" or (a.precond == "auto" and os.path.exists(net_file))
     sample = None
     if not a.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        sample = cpu_sample(a.n, a.nrhs, a.cpu_iters, NET_FILE if use_cnn else None)
+        sample = cpu_sample(a.n, a.nrhs, a.cpu_iters, net_file if use_cnn else None)
     exact = None
     if not a.no_cpu_baseline and not a.no_exact:
         # the oracle's exact solutions of a few right-hand sides, computed on one
@@ -476,7 +482,7 @@ def main():
     b = torch.from_numpy(np.stack([inputs.point_source(n, 3000 + i) for i in range(nrhs)])).to(dev, torch.complex64)
     precond = hh.HH_PRECOND_MG
     if use_cnn:
-        net = hh.Net.load(ctx, NET_FILE)
+        net = hh.Net.load(ctx, net_file)
         model.attach_net(net)
         precond = hh.HH_PRECOND_CNN_MG
 
@@ -560,7 +566,8 @@ def main():
     # Schur inverses (m^2 complex each) streamed once per sweep
     coef_pt = {"op_dots": 8, "ortho": 0, "vc_down": 8, "vc_up": 8, "vc_coarse": 2 * mc ** 3 * 8 / N}
     cnn_apps = float(pinfo["cnn_iters"].sum())
-    net_flops = network_flops(n)
+    net_flops = network_flops(n, light)
+    traffic_tag = f"cnn_mg{'_light' if light else ''}_{n}_{nrhs}rhs"
     classes = {}
     for kname, (ms, cnt) in prof.items():
         if cnt == 0 or ms <= 0:
@@ -572,7 +579,7 @@ def main():
             act = rhs_iters / cnt if kname != "vc_coarse" else None
             classes[kname] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(ach / HBM_PEAK_GBS, 4),
-                              "traffic": measured_traffic(kname, act) if act else None,
+                              "traffic": measured_traffic(kname, act, traffic_tag) if act else None,
                               "avg_launch_us": round(ms / cnt * 1e3, 1),
                               "algorithmic_bytes_per_launch": int(total / cnt), "ms": round(ms, 2),
                               "launches": cnt}
@@ -583,11 +590,11 @@ def main():
             apps = cnt // 3
             total = cnn_apps * net_flops
             ach = total / (ms / 1e3) / 1e12
-            ceil = network_ceiling(n)
+            ceil = network_ceiling(n, light)
             classes[kname] = {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
                               "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4),
-                              "traffic": measured_traffic(kname, cnn_apps / apps),
-                              "algorithmic_bytes_per_launch": int(cnn_apps / apps * network_bytes(n)),
+                              "traffic": measured_traffic(kname, cnn_apps / apps, traffic_tag),
+                              "algorithmic_bytes_per_launch": int(cnn_apps / apps * network_bytes(n, light)),
                               "launch_unit": "network application (all its convolution kernels)",
                               "avg_launch_us": round(ms / apps * 1e3, 1),
                               "algorithmic_flops_per_launch": int(total / apps), "ms": round(ms, 2),
@@ -620,8 +627,11 @@ def main():
         "dtype": "c64+f64" if not use_cnn else "bf16+c64+f64",
         "data": "synthetic",
         "config": {"workload": f"{n}^2 layered slowness (seed 2000), {nrhs} unit point sources (seeds 3000..), "
-                               f"FGMRES(10) rtol 1e-6, " + ("CNN+MG" if use_cnn else "MG-only") + " preconditioner",
-                   "n": n, "nrhs": nrhs, "precond": "cnn_mg" if use_cnn else "mg"},
+                               f"FGMRES(10) rtol 1e-6, "
+                               + (("CNN+MG (lightweight network)" if light else "CNN+MG") if use_cnn else "MG-only")
+                               + " preconditioner",
+                   "n": n, "nrhs": nrhs, "precond": "cnn_mg" if use_cnn else "mg",
+                   "network": (a.net if use_cnn else None)},
         "iterations": {"mean": mean_it, "min": int(iters.min()), "max": int(iters.max())},
         "all_converged": bool(conv.all()),
         "converged": f"{int(conv.sum())}/{conv.size}",

@@ -237,12 +237,14 @@ __device__ __forceinline__ float2 mass_of(float2 c, float shift) {
     return make_float2(c.x, -c.x * (c.y + shift));
 }
 
-// FP32 <-> BF16 (round to nearest even; NaN stays NaN)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// FP32 <-> BF16 (round to nearest even; NaN stays NaN): the conversion is
+// gfx950's v_cvt_pk_bf16_f32, which the compiler pairs for two values
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+typedef __bf16 hh_bf16x2 __attribute__((ext_vector_type(2)));
+// two values packed (a in the low half): one conversion instruction
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+    const hh_bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 

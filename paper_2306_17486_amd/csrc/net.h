@@ -11,7 +11,7 @@ enum { CM_S1 = 0, CM_S2 = 1, CM_T2 = 2 };  // stride 1, stride 2, transposed str
 enum { ACT_NONE = 0, ACT_RELU = 1, ACT_SOFTPLUS = 2 };
 
 // softplus log(1 + e^v) without overflow, and its derivative (the logistic function)
-__device__ __forceinline__ float softplus_f(float v) { return fmaxf(v, 0.f) + log1pf(__expf(-fabsf(v))); }
+__device__ __forceinline__ float softplus_f(float v) { return fmaxf(v, 0.f) + __logf(1.f + __expf(-fabsf(v))); }
 __device__ __forceinline__ float logistic_f(float v) { return 1.f / (1.f + __expf(-v)); }
 
 // ---- convolution kernels (net_conv.hip) ----
@@ -90,6 +90,22 @@ hh_status bn_train_forward(hipStream_t st, hh_ctx* ctx, Buf& part, int C, const 
 hh_status bn_train_backward(hipStream_t st, hh_ctx* ctx, Buf& part, Buf& coef, int C, const uint16_t* gout,
                             const uint16_t* z, size_t npix, const float* g, const float4* stat, int act,
                             const BnGrads& gr, uint16_t* gz);
+// the inverted bottleneck in one kernel (inference, batch norm folded):
+// y = x + Ws (softplus(dw(softplus(We x + be)) + bw)) + bs on x [B][m][m][c]
+struct IbArgs {
+    const uint16_t* x;     // input [B][m][m][c] BF16 (also the residual)
+    uint16_t* y;           // output, same shape
+    const uint16_t* we;    // expansion weights BF16 [6c][c]
+    const float* be;       // its bias [6c]
+    const float* wd;       // depthwise weights FP32 [6c][3][3]
+    const float* bd;       // its bias [6c]
+    const uint16_t* ws;    // shrink weights BF16 [c][6c]
+    const float* bs;       // its bias [c]
+    int B, m;
+    const int* active;     // per batch entry: skipped when 0 (null: all active)
+    int tiles_x, tiles_y, ntiles;  // filled by the launcher
+};
+hh_status launch_ib_fused(hipStream_t st, int num_cus, int c, IbArgs a);
 hh_status launch_pw_wgrad(hipStream_t st, hh_ctx* ctx, Buf& part, int cin, int cout, const uint16_t* g,
                           const uint16_t* x, size_t npix, float* out);
 hh_status launch_dw_wgrad(hipStream_t st, hh_ctx* ctx, Buf& part, int C, const uint16_t* g, const uint16_t* x,

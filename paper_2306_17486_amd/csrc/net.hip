@@ -255,8 +255,8 @@ __global__ void __launch_bounds__(256) k_conv_in_mfma(const float2* __restrict__
             v[3] += bf2f((uint16_t)(s2.y >> 16));
         }
         uint2 o2;
-        o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-        o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+        o2.x = f2bf2(v[0], v[1]);
+        o2.y = f2bf2(v[2], v[3]);
         *reinterpret_cast<uint2*>(y + ((size_t)b * m * m + pix) * COUT + 4 * kl) = o2;
     }
 }
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xi
             if (!(bf2f((uint16_t)(mr & 0xffff)) > 0.f)) v.x = 0.f;
             if (!(bf2f((uint16_t)(mr >> 16)) > 0.f)) v.y = 0.f;
         }
-        *reinterpret_cast<uint32_t*>(yout + o) = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+        *reinterpret_cast<uint32_t*>(yout + o) = f2bf2(v.x, v.y);
     }
 }
 
@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(256) k_implicit_rows_inv(const float2* __restr
         const int v = e / nc, x = e - v * nc;
         const float2 val = s[v * M + x];
         *reinterpret_cast<uint32_t*>(yout + (((size_t)b * nc + r0 + v) * nc + x) * CH + 2 * c) =
-            (uint32_t)f2bf(val.x) | ((uint32_t)f2bf(val.y) << 16);
+            f2bf2(val.x, val.y);
     }
 }
 
@@ -669,7 +669,7 @@ __global__ void __launch_bounds__(256) k_explicit(const uint16_t* __restrict__ x
         if (!(bf2f((uint16_t)(mv & 0xffff)) > 0.f)) yr = 0.f;
         if (!(bf2f((uint16_t)(mv >> 16)) > 0.f)) yi = 0.f;
     }
-    *reinterpret_cast<uint32_t*>(y + po) = (uint32_t)f2bf(yr) | ((uint32_t)f2bf(yi) << 16);
+    *reinterpret_cast<uint32_t*>(y + po) = f2bf2(yr, yi);
 }
 
 // Kernel gradient of the explicit layer, per block of EK_PIX pixels of one
@@ -1016,6 +1016,9 @@ struct LightActs {
     }
     hh_status ensure_layers(hh_net* net, int l0, int l1, int Bn, int nn, bool tr) {
         for (int l = l0; l <= l1; ++l) {
+            // the expanded tensors of the bottlenecks exist in HBM only in training
+            const LayerInfo& L = net->L[l];
+            if (!tr && (L.kind == LK_DW || (L.kind == LK_PW && L.cout > L.cin))) continue;
             const int m = light_res(l, nn);
             const size_t px = (size_t)Bn * m * m;
             const size_t esz = (l == LL_OUT) ? sizeof(float) : sizeof(uint16_t);
@@ -1199,27 +1202,20 @@ static hh_status light_ib(hh_net* net, LightActs& A, int le, const uint16_t* x, 
     DwArgs da{};
     da.B = B;
     da.H = da.W = m;
-    if (!train) {
-        pa.active = da.active = active;
-        pa.x = x;
-        pa.y = A.out(le);
-        pa.w = pk + net->pk_inf[le];
-        pa.bias = F + E.beoff;
-        pa.act = ACT_SOFTPLUS;
-        HH_TRY(launch_pointwise(st, cus, E.cin, E.cout, pa));
-        da.x = A.out(le);
-        da.y = A.out(lw);
-        da.w = F + Dw.woff;
-        da.bias = F + Dw.beoff;
-        da.act = ACT_SOFTPLUS;
-        HH_TRY(launch_depthwise(st, cus, Dw.cout, da));
-        pa.x = A.out(lw);
-        pa.y = A.out(ls);
-        pa.w = pk + net->pk_inf[ls];
-        pa.bias = F + S.beoff;
-        pa.act = ACT_NONE;
-        pa.res = x;
-        return launch_pointwise(st, cus, S.cin, S.cout, pa);
+    if (!train) {  // one fused kernel: the expanded channels stay in LDS
+        IbArgs ia{};
+        ia.x = x;
+        ia.y = A.out(ls);
+        ia.we = pk + net->pk_inf[le];
+        ia.be = F + E.beoff;
+        ia.wd = F + Dw.woff;
+        ia.bd = F + Dw.beoff;
+        ia.ws = pk + net->pk_inf[ls];
+        ia.bs = F + S.beoff;
+        ia.B = B;
+        ia.m = m;
+        ia.active = active;
+        return launch_ib_fused(st, cus, E.cin, ia);
     }
     pa.x = x;
     pa.y = A.z[le].as<uint16_t>();

@@ -288,8 +288,8 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
                 if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
             }
             uint2 o2;
-            o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-            o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+            o2.x = f2bf2(v[0], v[1]);
+            o2.y = f2bf2(v[2], v[3]);
             *reinterpret_cast<uint2*>(a.y + po) = o2;
             if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
         }
@@ -462,8 +462,8 @@ __global__ void __launch_bounds__(256) k_conv_dma(ConvArgs a) {
                     if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
                 }
                 uint2 o2;
-                o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-                o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+                o2.x = f2bf2(v[0], v[1]);
+                o2.y = f2bf2(v[2], v[3]);
                 *reinterpret_cast<uint2*>(a.y + po) = o2;
                 if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
             }
@@ -653,8 +653,8 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
                 if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
             }
             uint2 o2;
-            o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-            o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+            o2.x = f2bf2(v[0], v[1]);
+            o2.y = f2bf2(v[2], v[3]);
             *reinterpret_cast<uint2*>(a.y + po) = o2;
             if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
         }

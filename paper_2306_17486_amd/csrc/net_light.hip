@@ -35,7 +35,7 @@ __device__ __forceinline__ void unpack8(uint4 r, float (&f)[8]) {
 __device__ __forceinline__ uint4 pack8(const float (&f)[8]) {
     uint32_t w[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+    for (int i = 0; i < 4; ++i) w[i] = f2bf2(f[2 * i], f[2 * i + 1]);
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
@@ -168,8 +168,8 @@ __global__ void __launch_bounds__(256) k_pointwise(PwArgs a) {
                     v[3] += bf2f((uint16_t)(r2.y >> 16));
                 }
                 uint2 o2;
-                o2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-                o2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+                o2.x = f2bf2(v[0], v[1]);
+                o2.y = f2bf2(v[2], v[3]);
                 *reinterpret_cast<uint2*>(a.y + po) = o2;
                 if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
             }
@@ -695,6 +695,254 @@ hh_status launch_dw_wgrad(hipStream_t st, hh_ctx* ctx, Buf& part, int C, const u
     hipLaunchKernelGGL(k_sum_blocks, dim3((count + 255) / 256), dim3(256), 0, st, part.as<float>(), nblk, count, out);
     HH_LAUNCH_CHECK();
     return HH_OK;
+}
+
+}  // namespace hh
+
+namespace hh {
+
+// ---------------------------------------------------------------------------
+// The inverted bottleneck fused into one kernel (inference): the 6c expanded
+// channels never leave LDS.  Per output tile of TH x TW pixels the input
+// patch with a one-pixel halo is staged in LDS once; then for every chunk of
+// EC = 32 expanded channels:
+//   expansion  he = softplus(We x + be) on the halo patch   (MFMA: A = 16 expanded
+//              channels x c, B = c x 16 halo pixels), zero outside the image
+//              (the depthwise layer's zero padding), BF16 in LDS;
+//   depthwise  hw = softplus(dw(he) + bd) on the matrix cores as well: per 16
+//              channels, K = 9 taps x 16 channels (5 steps of 32, the last half
+//              empty) with a block-diagonal A (the weight w[r][t] where the
+//              k index's channel equals the row) and B = the tap-shifted he
+//              rows, one 16-byte LDS read per lane and step;
+//   shrink     acc += Ws[:, chunk] hw   (MFMA, K = 32): the depthwise result
+//              is already in the lane layout of a B operand, with the chunk's
+//              channels in the order (4 lg .. 4 lg + 3, 16 + 4 lg .. 16 + 4 lg + 3),
+//              which the shrink weights' A fragment follows;
+// and finally y = acc + bs + x.  HBM traffic: x once (plus the halo) and y.
+// ---------------------------------------------------------------------------
+template <int C>
+struct IbCfg {
+    static constexpr int E = 6 * C;                         // expanded channels
+    static constexpr int EC = 32;                           // expanded channels per chunk
+    static constexpr int NCH = E / EC;                      // chunks
+    static constexpr int TW = C >= 64 ? 16 : 32;            // output tile columns
+    static constexpr int TH = 8;                            // output tile rows
+    static constexpr int HW_ = TW + 2, HH_ = TH + 2;        // halo patch
+    static constexpr int HPX = HW_ * HH_;                   // halo pixels
+    static constexpr int HPB = (HPX + 15) / 16;             // 16-pixel blocks of the halo patch
+    static constexpr int OPB = TH * TW / 16;                // 16-pixel blocks of the output tile
+    static constexpr int PBW = OPB / 4;                     // output blocks per wave
+    static constexpr int CT = C / 16;                       // output channel tiles
+    static constexpr int XP = C + 8;                        // LDS pitch of a halo pixel (BF16)
+    static constexpr int EP = EC + 8;                       // LDS pitch of an expanded pixel / shrink row
+    static constexpr int KE = C % 32 == 0 ? 32 : 16;        // k per expansion MFMA
+    static constexpr int DS = 5;                            // depthwise k steps (9 taps x 16 channels, padded)
+    static_assert(OPB % 4 == 0, "output blocks shared by 4 waves");
+};
+
+template <int C>
+__global__ void __launch_bounds__(256, 2) k_ib_fused(IbArgs a) {
+    using G = IbCfg<C>;
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[G::HPB * 16 * G::XP];
+    __shared__ __attribute__((aligned(16))) uint16_t s_he[G::HPB * 16 * G::EP];
+    __shared__ __attribute__((aligned(16))) uint16_t s_we[G::EC * G::XP];
+    __shared__ __attribute__((aligned(16))) uint16_t s_ws[C * G::EP];
+    __shared__ float s_wd[G::EC * 9];  // [channel][tap]
+    __shared__ float s_be[G::EC], s_bd[G::EC];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lp = lane & 15, lg = lane >> 4;
+    const int per_b = a.tiles_x * a.tiles_y;
+    auto next_active = [&](int t) {
+        while (t < a.ntiles && a.active && !a.active[t / per_b]) t += gridDim.x;
+        return t;
+    };
+    float bsv[G::CT][4];
+#pragma unroll
+    for (int ct = 0; ct < G::CT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bsv[ct][i] = a.bs[ct * 16 + 4 * lg + i];
+    // this lane's slot in the depthwise A fragments: the k index 8 lg + j of step s
+    // is tap 2 s + (lg >> 1), channel 8 (lg & 1) + j; only j = lp - 8 (lg & 1) can
+    // meet the row lp
+    const int dj = lp - 8 * (lg & 1);
+    for (int tile = next_active(blockIdx.x); tile < a.ntiles; tile = next_active(tile + gridDim.x)) {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const int y0 = ty * G::TH, x0 = tx * G::TW;
+        const uint16_t* xb = a.x + (size_t)b * a.m * a.m * C;
+        __syncthreads();  // the previous tile's readers are done with s_x
+        // ---- the halo patch (zero outside the image and beyond the patch)
+        for (int e = tid; e < G::HPB * 16 * (C / 8); e += 256) {
+            const int px = e / (C / 8), v = e - px * (C / 8);
+            const int py = px / G::HW_, pxx = px - py * G::HW_;
+            const int iy = y0 - 1 + py, ix = x0 - 1 + pxx;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (px < G::HPX && iy >= 0 && iy < a.m && ix >= 0 && ix < a.m)
+                val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.m + ix) * C + 8 * v);
+            *reinterpret_cast<uint4*>(&s_x[px * G::XP + 8 * v]) = val;
+        }
+        f32x4 acc[G::CT][G::PBW];
+#pragma unroll
+        for (int ct = 0; ct < G::CT; ++ct)
+#pragma unroll
+            for (int q = 0; q < G::PBW; ++q) acc[ct][q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int ch = 0; ch < G::NCH; ++ch) {
+            __syncthreads();  // s_he, s_we, s_ws, s_wd of the previous chunk are free
+            const int e0 = ch * G::EC;
+            for (int e = tid; e < G::EC * (C / 8); e += 256) {
+                const int r = e / (C / 8), v = e - r * (C / 8);
+                *reinterpret_cast<uint4*>(&s_we[r * G::XP + 8 * v]) =
+                    *reinterpret_cast<const uint4*>(a.we + (size_t)(e0 + r) * C + 8 * v);
+            }
+            for (int e = tid; e < C * (G::EC / 8); e += 256) {
+                const int r = e / (G::EC / 8), v = e - r * (G::EC / 8);
+                *reinterpret_cast<uint4*>(&s_ws[r * G::EP + 8 * v]) =
+                    *reinterpret_cast<const uint4*>(a.ws + (size_t)r * G::E + e0 + 8 * v);
+            }
+            for (int e = tid; e < 9 * G::EC; e += 256) s_wd[e] = a.wd[(size_t)e0 * 9 + e];
+            if (tid < G::EC) {
+                s_be[tid] = a.be[e0 + tid];
+                s_bd[tid] = a.bd[e0 + tid];
+            }
+            __syncthreads();
+            // ---- expansion on the halo patch: (EC / 16) x HPB MFMA tiles over the 4 waves
+#pragma unroll 1
+            for (int pr = wave; pr < (G::EC / 16) * G::HPB; pr += 4) {
+                const int et = pr / G::HPB, pb = pr - et * G::HPB;
+                f32x4 d = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k0 = 0; k0 < C; k0 += G::KE) {
+                    if constexpr (G::KE == 32) {
+                        const uint4 av = *reinterpret_cast<const uint4*>(&s_we[(et * 16 + lp) * G::XP + k0 + 8 * lg]);
+                        const uint4 bv = *reinterpret_cast<const uint4*>(&s_x[(pb * 16 + lp) * G::XP + k0 + 8 * lg]);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(&av),
+                                                                    *reinterpret_cast<const bf16x8*>(&bv), d, 0, 0, 0);
+                    } else {
+                        const uint2 av = *reinterpret_cast<const uint2*>(&s_we[(et * 16 + lp) * G::XP + k0 + 4 * lg]);
+                        const uint2 bv = *reinterpret_cast<const uint2*>(&s_x[(pb * 16 + lp) * G::XP + k0 + 4 * lg]);
+                        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(*reinterpret_cast<const s16x4*>(&av),
+                                                                      *reinterpret_cast<const s16x4*>(&bv), d, 0, 0, 0);
+                    }
+                }
+                // lane: expanded channels et*16 + 4 lg .. +3 of halo pixel pb*16 + lp
+                const int px = pb * 16 + lp;
+                const int py = px / G::HW_, pxx = px - py * G::HW_;
+                const int iy = y0 - 1 + py, ix = x0 - 1 + pxx;
+                const bool inside = px < G::HPX && iy >= 0 && iy < a.m && ix >= 0 && ix < a.m;
+                float o[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = inside ? softplus_f(d[i] + s_be[et * 16 + 4 * lg + i]) : 0.f;
+                *reinterpret_cast<uint2*>(&s_he[px * G::EP + et * 16 + 4 * lg]) =
+                    make_uint2(f2bf2(o[0], o[1]), f2bf2(o[2], o[3]));
+            }
+            // depthwise A fragments of this chunk (block-diagonal, BF16 weights)
+            bf16x8 dA[2][G::DS];
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int st = 0; st < G::DS; ++st) {
+                    const int t = 2 * st + (lg >> 1);
+                    const float w = (t < 9 && dj >= 0 && dj < 8) ? s_wd[(g * 16 + lp) * 9 + t] : 0.f;
+                    uint32_t wv[4];
+#pragma unroll
+                    for (int h = 0; h < 4; ++h)
+                        wv[h] = f2bf2(2 * h == dj ? w : 0.f, 2 * h + 1 == dj ? w : 0.f);
+                    const uint4 u4 = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+                    dA[g][st] = *reinterpret_cast<const bf16x8*>(&u4);
+                }
+            // shrink A fragments with the k order (4 lg .. +3, 16 + 4 lg .. +3) of the chunk
+            bf16x8 wsA[G::CT];
+#pragma unroll
+            for (int ct = 0; ct < G::CT; ++ct) {
+                const uint2 lo = *reinterpret_cast<const uint2*>(&s_ws[(ct * 16 + lp) * G::EP + 4 * lg]);
+                const uint2 hi = *reinterpret_cast<const uint2*>(&s_ws[(ct * 16 + lp) * G::EP + 16 + 4 * lg]);
+                const uint4 u4 = make_uint4(lo.x, lo.y, hi.x, hi.y);
+                wsA[ct] = *reinterpret_cast<const bf16x8*>(&u4);
+            }
+            float bd8[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bd8[i] = s_bd[4 * lg + i];
+                bd8[4 + i] = s_bd[16 + 4 * lg + i];
+            }
+            __syncthreads();  // s_he complete
+#pragma unroll
+            for (int q = 0; q < G::PBW; ++q) {
+                const int p = (wave * G::PBW + q) * 16 + lp;  // output pixel of the tile
+                const int oy = p / G::TW, ox = p - oy * G::TW;
+                f32x4 d0 = (f32x4){0.f, 0.f, 0.f, 0.f}, d1 = d0;
+#pragma unroll
+                for (int st = 0; st < G::DS; ++st) {
+                    const int t = 2 * st + (lg >> 1);
+                    uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0;
+                    if (t < 9) {
+                        const int hp = (oy + t / 3) * G::HW_ + ox + t % 3;
+                        r0 = *reinterpret_cast<const uint4*>(&s_he[hp * G::EP + 8 * (lg & 1)]);
+                        r1 = *reinterpret_cast<const uint4*>(&s_he[hp * G::EP + 16 + 8 * (lg & 1)]);
+                    }
+                    d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[0][st], *reinterpret_cast<const bf16x8*>(&r0),
+                                                                 d0, 0, 0, 0);
+                    d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[1][st], *reinterpret_cast<const bf16x8*>(&r1),
+                                                                 d1, 0, 0, 0);
+                }
+                float hv[8];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    hv[i] = softplus_f(d0[i] + bd8[i]);
+                    hv[4 + i] = softplus_f(d1[i] + bd8[4 + i]);
+                }
+                const uint4 hb = pack8(hv);
+#pragma unroll
+                for (int ct = 0; ct < G::CT; ++ct)
+                    acc[ct][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        wsA[ct], *reinterpret_cast<const bf16x8*>(&hb), acc[ct][q], 0, 0, 0);
+            }
+        }
+        // ---- y = acc + bs + x: lane holds channels ct*16 + 4 lg .. +3 of pixel p
+#pragma unroll
+        for (int q = 0; q < G::PBW; ++q) {
+            const int p = (wave * G::PBW + q) * 16 + lp;
+            const int oy = p / G::TW, ox = p - oy * G::TW;
+            const int iy = y0 + oy, ix = x0 + ox;
+            if (iy >= a.m || ix >= a.m) continue;
+            const int hp = (oy + 1) * G::HW_ + ox + 1;
+#pragma unroll
+            for (int ct = 0; ct < G::CT; ++ct) {
+                const int co = ct * 16 + 4 * lg;
+                const uint2 r2 = *reinterpret_cast<const uint2*>(&s_x[hp * G::XP + co]);
+                const float v0 = acc[ct][q][0] + bsv[ct][0] + bf2f((uint16_t)(r2.x & 0xffff));
+                const float v1 = acc[ct][q][1] + bsv[ct][1] + bf2f((uint16_t)(r2.x >> 16));
+                const float v2 = acc[ct][q][2] + bsv[ct][2] + bf2f((uint16_t)(r2.y & 0xffff));
+                const float v3 = acc[ct][q][3] + bsv[ct][3] + bf2f((uint16_t)(r2.y >> 16));
+                *reinterpret_cast<uint2*>(a.y + (((size_t)b * a.m + iy) * a.m + ix) * C + co) =
+                    make_uint2(f2bf2(v0, v1), f2bf2(v2, v3));
+            }
+        }
+    }
+}
+
+template <int C>
+static hh_status launch_ib_t(hipStream_t st, int num_cus, IbArgs a) {
+    using G = IbCfg<C>;
+    a.tiles_x = (a.m + G::TW - 1) / G::TW;
+    a.tiles_y = (a.m + G::TH - 1) / G::TH;
+    a.ntiles = a.B * a.tiles_x * a.tiles_y;
+    if (a.ntiles == 0) return HH_OK;
+    const int grid = std::min(a.ntiles, num_cus * 2);
+    hipLaunchKernelGGL(k_ib_fused<C>, dim3(grid), dim3(256), 0, st, a);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+hh_status launch_ib_fused(hipStream_t st, int num_cus, int c, IbArgs a) {
+    if (c == 16) return launch_ib_t<16>(st, num_cus, a);
+    if (c == 32) return launch_ib_t<32>(st, num_cus, a);
+    if (c == 64) return launch_ib_t<64>(st, num_cus, a);
+    set_error("no fused bottleneck kernel for %d channels", c);
+    return HH_ERR_ARG;
 }
 
 }  // namespace hh

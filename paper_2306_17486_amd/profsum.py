@@ -26,7 +26,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # kernel name prefix -> class (the library's kernel classes)
 CLASS_OF = [
-    ("k_conv_mfma", "conv"), ("k_conv_t2", "conv"), ("k_conv_in", "conv"),
+    ("k_conv_mfma", "conv"), ("k_conv_t2", "conv"), ("k_conv_in", "conv"), ("k_conv_dma", "conv"),
+    ("k_ib_fused", "conv"), ("k_pointwise", "conv"), ("k_depthwise", "conv"), ("k_explicit", "net_other"),
     ("k_conv_out", "net_other"), ("k_implicit", "net_other"), ("k_sumsq", "net_other"),
     ("k_scales", "net_other"), ("k_prolong_x0", "net_other"),
     ("k_op_dots", "op_dots"), ("k_ortho", "ortho"),
@@ -38,7 +39,7 @@ CLASS_OF = [
 
 # kernel sources of each class (their hash marks which build the counters saw)
 CLASS_SOURCES = {
-    "conv": ("net_conv.hip", "hh_internal.h"),
+    "conv": ("net_conv.hip", "net_light.hip", "net.h", "hh_internal.h"),
     "op_dots": ("krylov.hip", "hh_internal.h"),
     "ortho": ("krylov.hip", "hh_internal.h"),
     "vc_down": ("mg.hip", "hh_internal.h"),
