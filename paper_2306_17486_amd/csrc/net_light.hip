@@ -745,10 +745,6 @@ __global__ void __launch_bounds__(256, 2) k_ib_fused(IbArgs a) {
     using G = IbCfg<C>;
     __shared__ __attribute__((aligned(16))) uint16_t s_x[G::HPB * 16 * G::XP];
     __shared__ __attribute__((aligned(16))) uint16_t s_he[G::HPB * 16 * G::EP];
-    __shared__ __attribute__((aligned(16))) uint16_t s_we[G::EC * G::XP];
-    __shared__ __attribute__((aligned(16))) uint16_t s_ws[C * G::EP];
-    __shared__ float s_wd[G::EC * 9];  // [channel][tap]
-    __shared__ float s_be[G::EC], s_bd[G::EC];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int lp = lane & 15, lg = lane >> 4;
@@ -766,22 +762,68 @@ __global__ void __launch_bounds__(256, 2) k_ib_fused(IbArgs a) {
     // is tap 2 s + (lg >> 1), channel 8 (lg & 1) + j; only j = lp - 8 (lg & 1) can
     // meet the row lp
     const int dj = lp - 8 * (lg & 1);
-    for (int tile = next_active(blockIdx.x); tile < a.ntiles; tile = next_active(tile + gridDim.x)) {
+    // the halo patch of a tile, gathered into registers (zero outside the image):
+    // element e = pixel * (C / 8) + vector; the next tile's is in flight while
+    // this one is computed
+    constexpr int NV = C / 8;
+    constexpr int NPF = (G::HPB * 16 * NV + 255) / 256;
+    auto gather = [&](int tile, uint4 (&g)[NPF <= 3 ? NPF : 1]) {
+        constexpr int NG = NPF <= 3 ? NPF : 1;
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const uint16_t* xb = a.x + (size_t)b * a.m * a.m * C;
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            const int e = tid + j * 256;
+            const int px = e / NV, v = e - px * NV;
+            const int py = px / G::HW_, pxx = px - py * G::HW_;
+            const int iy = ty * G::TH - 1 + py, ix = tx * G::TW - 1 + pxx;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (px < G::HPX && iy >= 0 && iy < a.m && ix >= 0 && ix < a.m)
+                val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.m + ix) * C + 8 * v);
+            g[j] = val;
+        }
+    };
+    constexpr bool PF = NPF <= 3;         // small patches: prefetch the next tile's in registers
+    constexpr int NPR = PF ? NPF : 1;
+    uint4 pf[NPR];
+    int tile = next_active(blockIdx.x);
+    if (PF && tile < a.ntiles) gather(tile, pf);
+    while (tile < a.ntiles) {
         const int b = tile / per_b;
         const int rem = tile - b * per_b;
         const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
         const int y0 = ty * G::TH, x0 = tx * G::TW;
-        const uint16_t* xb = a.x + (size_t)b * a.m * a.m * C;
-        __syncthreads();  // the previous tile's readers are done with s_x
-        // ---- the halo patch (zero outside the image and beyond the patch)
-        for (int e = tid; e < G::HPB * 16 * (C / 8); e += 256) {
-            const int px = e / (C / 8), v = e - px * (C / 8);
+        const int nxt = next_active(tile + gridDim.x);
+        __syncthreads();  // the previous tile's readers are done with s_x and s_he
+        if constexpr (PF) {
+#pragma unroll
+            for (int j = 0; j < NPF; ++j) {
+                const int e = tid + j * 256;
+                if (e < G::HPB * 16 * NV) *reinterpret_cast<uint4*>(&s_x[(e / NV) * G::XP + 8 * (e % NV)]) = pf[j];
+            }
+            if (nxt < a.ntiles) gather(nxt, pf);
+        } else {
+            const uint16_t* xb = a.x + (size_t)b * a.m * a.m * C;
+            for (int e = tid; e < G::HPB * 16 * NV; e += 256) {
+                const int px = e / NV, v = e - px * NV;
+                const int py = px / G::HW_, pxx = px - py * G::HW_;
+                const int iy = y0 - 1 + py, ix = x0 - 1 + pxx;
+                uint4 val = make_uint4(0, 0, 0, 0);
+                if (px < G::HPX && iy >= 0 && iy < a.m && ix >= 0 && ix < a.m)
+                    val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.m + ix) * C + 8 * v);
+                *reinterpret_cast<uint4*>(&s_x[px * G::XP + 8 * v]) = val;
+            }
+        }
+        // halo pixels pb * 16 + lp of this lane inside the image (the expanded map is zero elsewhere)
+        uint32_t imask = 0;
+#pragma unroll
+        for (int pb = 0; pb < G::HPB; ++pb) {
+            const int px = pb * 16 + lp;
             const int py = px / G::HW_, pxx = px - py * G::HW_;
             const int iy = y0 - 1 + py, ix = x0 - 1 + pxx;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (px < G::HPX && iy >= 0 && iy < a.m && ix >= 0 && ix < a.m)
-                val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.m + ix) * C + 8 * v);
-            *reinterpret_cast<uint4*>(&s_x[px * G::XP + 8 * v]) = val;
+            if (px < G::HPX && iy >= 0 && iy < a.m && ix >= 0 && ix < a.m) imask |= 1u << pb;
         }
         f32x4 acc[G::CT][G::PBW];
 #pragma unroll
@@ -790,52 +832,75 @@ __global__ void __launch_bounds__(256, 2) k_ib_fused(IbArgs a) {
             for (int q = 0; q < G::PBW; ++q) acc[ct][q] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
         for (int ch = 0; ch < G::NCH; ++ch) {
-            __syncthreads();  // s_he, s_we, s_ws, s_wd of the previous chunk are free
             const int e0 = ch * G::EC;
-            for (int e = tid; e < G::EC * (C / 8); e += 256) {
-                const int r = e / (C / 8), v = e - r * (C / 8);
-                *reinterpret_cast<uint4*>(&s_we[r * G::XP + 8 * v]) =
-                    *reinterpret_cast<const uint4*>(a.we + (size_t)(e0 + r) * C + 8 * v);
+            // this chunk's weight fragments and biases, straight from global memory (cached)
+            uint4 weA[2][C / G::KE];
+            float be8[8];
+#pragma unroll
+            for (int et = 0; et < 2; ++et) {
+#pragma unroll
+                for (int kk = 0; kk < C / G::KE; ++kk) {
+                    const uint16_t* wr = a.we + (size_t)(e0 + et * 16 + lp) * C + kk * G::KE;
+                    if constexpr (G::KE == 32) {
+                        weA[et][kk] = *reinterpret_cast<const uint4*>(wr + 8 * lg);
+                    } else {
+                        const uint2 h = *reinterpret_cast<const uint2*>(wr + 4 * lg);
+                        weA[et][kk] = make_uint4(h.x, h.y, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) be8[4 * et + i] = a.be[e0 + et * 16 + 4 * lg + i];
             }
-            for (int e = tid; e < C * (G::EC / 8); e += 256) {
-                const int r = e / (G::EC / 8), v = e - r * (G::EC / 8);
-                *reinterpret_cast<uint4*>(&s_ws[r * G::EP + 8 * v]) =
-                    *reinterpret_cast<const uint4*>(a.ws + (size_t)r * G::E + e0 + 8 * v);
+            float wdv[2][G::DS];
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int st = 0; st < G::DS; ++st) {
+                    const int t = 2 * st + (lg >> 1);
+                    wdv[g][st] = (t < 9 && dj >= 0 && dj < 8) ? a.wd[(size_t)(e0 + g * 16 + lp) * 9 + t] : 0.f;
+                }
+            bf16x8 wsA[G::CT];
+#pragma unroll
+            for (int ct = 0; ct < G::CT; ++ct) {
+                const uint16_t* wr = a.ws + (size_t)(ct * 16 + lp) * G::E + e0;
+                const uint2 lo = *reinterpret_cast<const uint2*>(wr + 4 * lg);
+                const uint2 hi = *reinterpret_cast<const uint2*>(wr + 16 + 4 * lg);
+                const uint4 u4 = make_uint4(lo.x, lo.y, hi.x, hi.y);
+                wsA[ct] = *reinterpret_cast<const bf16x8*>(&u4);
             }
-            for (int e = tid; e < 9 * G::EC; e += 256) s_wd[e] = a.wd[(size_t)e0 * 9 + e];
-            if (tid < G::EC) {
-                s_be[tid] = a.be[e0 + tid];
-                s_bd[tid] = a.bd[e0 + tid];
+            float bd8[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bd8[i] = a.bd[e0 + 4 * lg + i];
+                bd8[4 + i] = a.bd[e0 + 16 + 4 * lg + i];
             }
-            __syncthreads();
+            if (ch > 0) __syncthreads();  // the previous chunk's depthwise is done with s_he
             // ---- expansion on the halo patch: (EC / 16) x HPB MFMA tiles over the 4 waves
-#pragma unroll 1
-            for (int pr = wave; pr < (G::EC / 16) * G::HPB; pr += 4) {
-                const int et = pr / G::HPB, pb = pr - et * G::HPB;
+#pragma unroll 2
+            for (int pr = wave; pr < 2 * G::HPB; pr += 4) {
+                const int et = pr >= G::HPB ? 1 : 0;
+                const int pb = pr - et * G::HPB;
                 f32x4 d = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int k0 = 0; k0 < C; k0 += G::KE) {
+                for (int kk = 0; kk < C / G::KE; ++kk) {
+                    const uint4 A = et ? weA[1][kk] : weA[0][kk];
                     if constexpr (G::KE == 32) {
-                        const uint4 av = *reinterpret_cast<const uint4*>(&s_we[(et * 16 + lp) * G::XP + k0 + 8 * lg]);
-                        const uint4 bv = *reinterpret_cast<const uint4*>(&s_x[(pb * 16 + lp) * G::XP + k0 + 8 * lg]);
-                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(&av),
+                        const uint4 bv = *reinterpret_cast<const uint4*>(&s_x[(pb * 16 + lp) * G::XP + kk * 32 + 8 * lg]);
+                        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(&A),
                                                                     *reinterpret_cast<const bf16x8*>(&bv), d, 0, 0, 0);
                     } else {
-                        const uint2 av = *reinterpret_cast<const uint2*>(&s_we[(et * 16 + lp) * G::XP + k0 + 4 * lg]);
-                        const uint2 bv = *reinterpret_cast<const uint2*>(&s_x[(pb * 16 + lp) * G::XP + k0 + 4 * lg]);
+                        const uint2 av = make_uint2(A.x, A.y);
+                        const uint2 bv = *reinterpret_cast<const uint2*>(&s_x[(pb * 16 + lp) * G::XP + 4 * lg]);
                         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(*reinterpret_cast<const s16x4*>(&av),
                                                                       *reinterpret_cast<const s16x4*>(&bv), d, 0, 0, 0);
                     }
                 }
                 // lane: expanded channels et*16 + 4 lg .. +3 of halo pixel pb*16 + lp
-                const int px = pb * 16 + lp;
-                const int py = px / G::HW_, pxx = px - py * G::HW_;
-                const int iy = y0 - 1 + py, ix = x0 - 1 + pxx;
-                const bool inside = px < G::HPX && iy >= 0 && iy < a.m && ix >= 0 && ix < a.m;
+                const bool inside = (imask >> pb) & 1u;
                 float o[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = inside ? softplus_f(d[i] + s_be[et * 16 + 4 * lg + i]) : 0.f;
-                *reinterpret_cast<uint2*>(&s_he[px * G::EP + et * 16 + 4 * lg]) =
+                for (int i = 0; i < 4; ++i) o[i] = inside ? softplus_f(d[i] + (et ? be8[4 + i] : be8[i])) : 0.f;
+                *reinterpret_cast<uint2*>(&s_he[(pb * 16 + lp) * G::EP + et * 16 + 4 * lg]) =
                     make_uint2(f2bf2(o[0], o[1]), f2bf2(o[2], o[3]));
             }
             // depthwise A fragments of this chunk (block-diagonal, BF16 weights)
@@ -844,8 +909,7 @@ __global__ void __launch_bounds__(256, 2) k_ib_fused(IbArgs a) {
             for (int g = 0; g < 2; ++g)
 #pragma unroll
                 for (int st = 0; st < G::DS; ++st) {
-                    const int t = 2 * st + (lg >> 1);
-                    const float w = (t < 9 && dj >= 0 && dj < 8) ? s_wd[(g * 16 + lp) * 9 + t] : 0.f;
+                    const float w = wdv[g][st];
                     uint32_t wv[4];
 #pragma unroll
                     for (int h = 0; h < 4; ++h)
@@ -853,46 +917,43 @@ __global__ void __launch_bounds__(256, 2) k_ib_fused(IbArgs a) {
                     const uint4 u4 = make_uint4(wv[0], wv[1], wv[2], wv[3]);
                     dA[g][st] = *reinterpret_cast<const bf16x8*>(&u4);
                 }
-            // shrink A fragments with the k order (4 lg .. +3, 16 + 4 lg .. +3) of the chunk
-            bf16x8 wsA[G::CT];
-#pragma unroll
-            for (int ct = 0; ct < G::CT; ++ct) {
-                const uint2 lo = *reinterpret_cast<const uint2*>(&s_ws[(ct * 16 + lp) * G::EP + 4 * lg]);
-                const uint2 hi = *reinterpret_cast<const uint2*>(&s_ws[(ct * 16 + lp) * G::EP + 16 + 4 * lg]);
-                const uint4 u4 = make_uint4(lo.x, lo.y, hi.x, hi.y);
-                wsA[ct] = *reinterpret_cast<const bf16x8*>(&u4);
-            }
-            float bd8[8];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                bd8[i] = s_bd[4 * lg + i];
-                bd8[4 + i] = s_bd[16 + 4 * lg + i];
-            }
             __syncthreads();  // s_he complete
+            // all of this wave's pixel blocks advance together through the 5 steps:
+            // 2 PBW independent accumulation chains keep the matrix cores fed
+            f32x4 dd[G::PBW][2];
+#pragma unroll
+            for (int q = 0; q < G::PBW; ++q) dd[q][0] = dd[q][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            // tap offset of this lane's k slots in each step (tap 2 st + (lg >> 1))
+#pragma unroll
+            for (int st = 0; st < G::DS; ++st) {
+                const int t = 2 * st + (lg >> 1);
+                const int toff = (t / 3) * G::HW_ + t % 3;
+                uint4 r[G::PBW][2];
+#pragma unroll
+                for (int q = 0; q < G::PBW; ++q) {
+                    const int p = (wave * G::PBW + q) * 16 + lp;  // output pixel of the tile
+                    const int oy = p / G::TW, ox = p - oy * G::TW;
+                    const int hp = oy * G::HW_ + ox + toff;
+                    r[q][0] = r[q][1] = make_uint4(0, 0, 0, 0);
+                    if (t < 9) {
+                        r[q][0] = *reinterpret_cast<const uint4*>(&s_he[hp * G::EP + 8 * (lg & 1)]);
+                        r[q][1] = *reinterpret_cast<const uint4*>(&s_he[hp * G::EP + 16 + 8 * (lg & 1)]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < G::PBW; ++q)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        dd[q][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            dA[g][st], *reinterpret_cast<const bf16x8*>(&r[q][g]), dd[q][g], 0, 0, 0);
+            }
 #pragma unroll
             for (int q = 0; q < G::PBW; ++q) {
-                const int p = (wave * G::PBW + q) * 16 + lp;  // output pixel of the tile
-                const int oy = p / G::TW, ox = p - oy * G::TW;
-                f32x4 d0 = (f32x4){0.f, 0.f, 0.f, 0.f}, d1 = d0;
-#pragma unroll
-                for (int st = 0; st < G::DS; ++st) {
-                    const int t = 2 * st + (lg >> 1);
-                    uint4 r0 = make_uint4(0, 0, 0, 0), r1 = r0;
-                    if (t < 9) {
-                        const int hp = (oy + t / 3) * G::HW_ + ox + t % 3;
-                        r0 = *reinterpret_cast<const uint4*>(&s_he[hp * G::EP + 8 * (lg & 1)]);
-                        r1 = *reinterpret_cast<const uint4*>(&s_he[hp * G::EP + 16 + 8 * (lg & 1)]);
-                    }
-                    d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[0][st], *reinterpret_cast<const bf16x8*>(&r0),
-                                                                 d0, 0, 0, 0);
-                    d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[1][st], *reinterpret_cast<const bf16x8*>(&r1),
-                                                                 d1, 0, 0, 0);
-                }
                 float hv[8];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    hv[i] = softplus_f(d0[i] + bd8[i]);
-                    hv[4 + i] = softplus_f(d1[i] + bd8[4 + i]);
+                    hv[i] = softplus_f(dd[q][0][i] + bd8[i]);
+                    hv[4 + i] = softplus_f(dd[q][1][i] + bd8[4 + i]);
                 }
                 const uint4 hb = pack8(hv);
 #pragma unroll
@@ -921,6 +982,7 @@ __global__ void __launch_bounds__(256, 2) k_ib_fused(IbArgs a) {
                     make_uint2(f2bf2(v0, v1), f2bf2(v2, v3));
             }
         }
+        tile = nxt;
     }
 }
 
