@@ -427,6 +427,175 @@ def run_batch(a):
     ctx.close()
 
 
+# the network-inference workload at 256^2 and 512^2: the held-out GRF media of
+# train.py's evaluation (seeds 1000 + i) with one point source each (3000 + i)
+GRF_SIZES = (256, 512)
+GRF_MEDIA = 16
+GRF_EXACT = 4  # media per size whose solutions are compared with the exact solve
+
+
+def run_grf(a):
+    exact = None
+    if not a.no_exact:
+        jobs = [(n, 1000 + i, [3000 + i], "grf") for n in GRF_SIZES for i in range(GRF_EXACT)]
+        print("bench grf: starting the oracle's sparse direct solves of the sampled media", file=sys.stderr,
+              flush=True)
+        exact = start_exact(jobs)
+    import numpy as np
+    import torch
+    from paper_2306_17486_amd import hh, inputs
+
+    def say(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    light = a.net == "light"
+    ctx = hh.Context(0)
+    net = hh.Net.load(ctx, NET_FILES[a.net])
+    per_size, xs = {}, {}
+    for n in GRF_SIZES:
+        kap = np.stack([inputs.grf_slowness(n, 1000 + i) for i in range(GRF_MEDIA)]).astype(np.float32)
+        m = hh.Model(ctx, torch.from_numpy(kap), inputs.omega_for(n))
+        m.attach_net(net)
+        b = torch.from_numpy(np.stack([inputs.point_source(n, 3000 + i) for i in range(GRF_MEDIA)])).to(
+            "cuda:0", torch.complex64)
+        inst = list(range(GRF_MEDIA))
+        row = {}
+        for label, prec in (("mg", hh.HH_PRECOND_MG), ("cnn_mg", hh.HH_PRECOND_CNN_MG)):
+            m.solve(b, inst=inst, precond=prec, max_iters=a.max_iters, want_hist=False)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            conv = 0
+            for _ in range(a.steps):
+                x, info = m.solve(b, inst=inst, precond=prec, max_iters=a.max_iters, want_hist=False)
+                conv += int(info["converged"].sum())
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            row[label] = {"solves_per_s": round(conv / dt, 3), "ms_per_step": round(1e3 * dt / a.steps, 2),
+                          "iterations_mean": round(float(info["iters"].mean()), 2),
+                          "iterations_max": int(info["iters"].max()),
+                          "converged": f"{int(info['converged'].sum())}/{GRF_MEDIA}",
+                          "max_final_rel_residual": float(info["final_res"].max())}
+            if label == "cnn_mg":
+                xs[n] = x.cpu().numpy()
+            say(f"bench grf: {n}^2 {label} {row[label]['solves_per_s']} solves/s, "
+                f"{row[label]['iterations_mean']} iterations")
+        torch.cuda.synchronize()
+        ctx.profile_begin()
+        _, pinfo = m.solve(b, inst=inst, precond=hh.HH_PRECOND_CNN_MG, max_iters=a.max_iters, want_hist=False)
+        prof = ctx.profile_end()
+        classes, roof = class_report(prof, pinfo, n, GRF_MEDIA, light, n_models=GRF_MEDIA)
+        row["kernels"] = classes
+        row["roofline"] = roof
+        row["cnn_mg_over_mg_only"] = round(row["cnn_mg"]["solves_per_s"] / row["mg"]["solves_per_s"], 3)
+        per_size[n] = row
+        m.attach_net(None)
+        m.close()
+    if exact is not None:
+        pool, jobs = exact
+        say("bench grf: waiting for the oracle's exact solutions")
+        k = 0
+        for n in GRF_SIZES:
+            errs = []
+            for i in range(GRF_EXACT):
+                X, _ = jobs[k].get()
+                k += 1
+                errs.append(rel_err(xs[n][i], X[0]))
+            per_size[n]["cnn_mg"]["max_error_vs_exact"] = max(errs)
+            per_size[n]["cnn_mg"]["error_sample"] = f"media 0..{GRF_EXACT - 1} (CNN+MG solutions)"
+        pool.close()
+        pool.join()
+    head = per_size[GRF_SIZES[-1]]
+    line = {"metric": "Helmholtz solves/s to rel. residual 1e-6, CNN+MG, 16 GRF media with one point source each",
+            "value": head["cnn_mg"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": 1, "ms_per_step": head["cnn_mg"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16+c64+f64", "data": "synthetic",
+            "config": {"workload": "network inference at 256^2 and 512^2: 16 Gaussian-random-field slowness media "
+                                   "(held-out seeds 1000..1015) per size, one unit point source each (seeds "
+                                   "3000..3015), omega = 2 pi n / 10, FGMRES(10) rtol 1e-6, all media of a size in "
+                                   "one solve; value: 512^2", "sizes": list(GRF_SIZES), "media": GRF_MEDIA,
+                       "network": a.net},
+            "per_size": {str(n): r for n, r in per_size.items()},
+            "roofline": head["roofline"]}
+    print(json.dumps(line), flush=True)
+    net.close()
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def class_report(prof: dict, pinfo: dict, n: int, nrhs: int, light: bool, n_models: int = 1):
+    """Per kernel class: algorithmic bytes (HBM-bound classes) or FLOPs (MFMA
+    convolutions) over the class's summed HIP-event time of one profiled solve
+    (`prof`, `pinfo`).  Bytes = (sum over RHS of their iterations) x N x bytes
+    per point and RHS, plus the coefficients of the n_models media once per
+    launch; inactive right-hand sides exit at once and are not counted.
+    Returns (classes, roofline object of the dominant class)."""
+    N = n * n
+    # the class times come from the profiled solve: count its own iterations
+    rhs_iters = float(pinfo["iters"].sum())
+    mean_jp1 = (10 + 1) / 2.0  # mean (j + 1) over full FGMRES(10) cycles
+    mc = n // 4  # coarsest grid of the 3-level hierarchy
+    per_pt = {"op_dots": 16 + 8 * mean_jp1, "ortho": 16 + 8 * mean_jp1, "vc_down": 8 + 2, "vc_up": 8 + 2 + 8,
+              # coarse solve per RHS: b read twice, y written and read, x written (5 coarse vectors)
+              "vc_coarse": 5 * 8 * mc * mc / N}
+    # with the network's initial guess both kernels also read the network's
+    # half-resolution output (8 B per coarse point = 2 B per fine point) and
+    # interpolate it; the relaxed guess is recomputed, not stored
+    per_pt_cnn = dict(per_pt, vc_down=8 + 2 + 2, vc_up=8 + 2 + 2 + 8)
+    cnn_rhs_iters = float(pinfo["cnn_iters"].sum())
+    # per launch, shared by all RHS: coefficients; for the coarse solve the m
+    # Schur inverses (m^2 complex each) streamed once per sweep
+    coef_pt = {k: v * n_models for k, v in
+               {"op_dots": 8, "ortho": 0, "vc_down": 8, "vc_up": 8, "vc_coarse": 2 * mc ** 3 * 8 / N}.items()}
+    cnn_apps = float(pinfo["cnn_iters"].sum())
+    net_flops = network_flops(n, light)
+    traffic_tag = f"cnn_mg{'_light' if light else ''}_{n}_{nrhs}rhs"
+    classes = {}
+    for kname, (ms, cnt) in prof.items():
+        if cnt == 0 or ms <= 0:
+            continue
+        if kname in per_pt:
+            total = ((rhs_iters - cnn_rhs_iters) * per_pt[kname] + cnn_rhs_iters * per_pt_cnn[kname]) * N \
+                + cnt * N * coef_pt[kname]
+            ach = total / (ms / 1e3) / 1e9
+            act = rhs_iters / cnt if kname != "vc_coarse" else None
+            classes[kname] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4),
+                              "traffic": measured_traffic(kname, act, traffic_tag) if act else None,
+                              "avg_launch_us": round(ms / cnt * 1e3, 1),
+                              "algorithmic_bytes_per_launch": int(total / cnt), "ms": round(ms, 2),
+                              "launches": cnt}
+        elif kname == "conv" and cnn_apps > 0:
+            # one "launch" of this class = one network application: its convolution
+            # kernels (three event scopes: input layer, down path, up path) over
+            # the right-hand sides active in it
+            apps = cnt // 3
+            total = cnn_apps * net_flops
+            ach = total / (ms / 1e3) / 1e12
+            ceil = network_ceiling(n, light)
+            classes[kname] = {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4),
+                              "traffic": measured_traffic(kname, cnn_apps / apps, traffic_tag),
+                              "algorithmic_bytes_per_launch": int(cnn_apps / apps * network_bytes(n, light)),
+                              "launch_unit": "network application (all its convolution kernels)",
+                              "avg_launch_us": round(ms / apps * 1e3, 1),
+                              "algorithmic_flops_per_launch": int(total / apps), "ms": round(ms, 2),
+                              "launches": apps, "event_scopes": cnt,
+                              "active_rhs_per_launch": round(cnn_apps / apps, 2),
+                              # the layers' arithmetic intensities cap the class below the MFMA
+                              # peak: the fraction attainable at the HBM roof, and ours of it
+                              "intensity_ceiling_frac": round(ceil, 4),
+                              "frac_of_ceiling": round(ach / BF16_PEAK_TFLOPS / ceil, 4)}
+        else:
+            classes[kname] = {"ms": round(ms, 2), "launches": cnt}
+    ranked = sorted(((v[0], kname) for kname, v in prof.items()), reverse=True)
+    dom = next((kname for _, kname in ranked if "bound" in classes.get(kname, {})), None)
+    roof = dict(classes[dom], kernel=dom,
+                measured="HIP events around every launch of the class on the library's stream, in one "
+                         "profiled solve after the timed steps (same kernels; cycles eager while profiling)") \
+        if dom else None
+    return classes, roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,7 +610,9 @@ def main():
     ap.add_argument("--mg-steps", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--no-exact", action="store_true", help="skip the error against the exact solutions")
-    ap.add_argument("--workload", choices=["single", "batch"], default="single")
+    ap.add_argument("--workload", choices=["single", "batch", "grf"], default="single",
+                    help="single: 1024^2, 64 sources (the headline); batch: uneven sizes; grf: 16 GRF media at "
+                         "256^2 and 512^2")
     ap.add_argument("--net", choices=sorted(NET_FILES), default="unet",
                     help="the network of CNN+MG: the U-Net (default) or the lightweight network")
     ap.add_argument("--batch-max-iters", type=int, default=2000)
@@ -452,6 +623,9 @@ def main():
         sys.exit(2)
     if a.workload == "batch":
         run_batch(a)
+        return
+    if a.workload == "grf":
+        run_grf(a)
         return
 
     net_file = NET_FILES[a.net]
@@ -543,75 +717,8 @@ def main():
     # only right-hand sides whose FP64 residual reached 1e-6 count as solves
     value = float(conv.sum()) / elapsed
 
-    # per kernel class: algorithmic bytes (HBM-bound classes) or FLOPs (MFMA
-    # convolutions) over the class's summed HIP-event time.  Bytes = (sum over
-    # RHS of their iterations) x N x bytes per point and RHS, plus the shared
-    # coefficients once per launch; inactive right-hand sides exit at once and
-    # are not counted.
-    N = n * n
     mean_it = float(iters.mean())
-    # the class times come from the profiled solve: count its own iterations
-    rhs_iters = float(pinfo["iters"].sum())
-    mean_jp1 = (10 + 1) / 2.0  # mean (j + 1) over full FGMRES(10) cycles
-    mc = n // 4  # coarsest grid of the 3-level hierarchy
-    per_pt = {"op_dots": 16 + 8 * mean_jp1, "ortho": 16 + 8 * mean_jp1, "vc_down": 8 + 2, "vc_up": 8 + 2 + 8,
-              # coarse solve per RHS: b read twice, y written and read, x written (5 coarse vectors)
-              "vc_coarse": 5 * 8 * mc * mc / N}
-    # with the network's initial guess both kernels also read the network's
-    # half-resolution output (8 B per coarse point = 2 B per fine point) and
-    # interpolate it; the relaxed guess is recomputed, not stored
-    per_pt_cnn = dict(per_pt, vc_down=8 + 2 + 2, vc_up=8 + 2 + 2 + 8)
-    cnn_rhs_iters = float(pinfo["cnn_iters"].sum())
-    # per launch, shared by all RHS: coefficients; for the coarse solve the m
-    # Schur inverses (m^2 complex each) streamed once per sweep
-    coef_pt = {"op_dots": 8, "ortho": 0, "vc_down": 8, "vc_up": 8, "vc_coarse": 2 * mc ** 3 * 8 / N}
-    cnn_apps = float(pinfo["cnn_iters"].sum())
-    net_flops = network_flops(n, light)
-    traffic_tag = f"cnn_mg{'_light' if light else ''}_{n}_{nrhs}rhs"
-    classes = {}
-    for kname, (ms, cnt) in prof.items():
-        if cnt == 0 or ms <= 0:
-            continue
-        if kname in per_pt:
-            total = ((rhs_iters - cnn_rhs_iters) * per_pt[kname] + cnn_rhs_iters * per_pt_cnn[kname]) * N \
-                + cnt * N * coef_pt[kname]
-            ach = total / (ms / 1e3) / 1e9
-            act = rhs_iters / cnt if kname != "vc_coarse" else None
-            classes[kname] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(ach / HBM_PEAK_GBS, 4),
-                              "traffic": measured_traffic(kname, act, traffic_tag) if act else None,
-                              "avg_launch_us": round(ms / cnt * 1e3, 1),
-                              "algorithmic_bytes_per_launch": int(total / cnt), "ms": round(ms, 2),
-                              "launches": cnt}
-        elif kname == "conv" and cnn_apps > 0:
-            # one "launch" of this class = one network application: its convolution
-            # kernels (three event scopes: input layer, down path, up path) over
-            # the right-hand sides active in it
-            apps = cnt // 3
-            total = cnn_apps * net_flops
-            ach = total / (ms / 1e3) / 1e12
-            ceil = network_ceiling(n, light)
-            classes[kname] = {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
-                              "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4),
-                              "traffic": measured_traffic(kname, cnn_apps / apps, traffic_tag),
-                              "algorithmic_bytes_per_launch": int(cnn_apps / apps * network_bytes(n, light)),
-                              "launch_unit": "network application (all its convolution kernels)",
-                              "avg_launch_us": round(ms / apps * 1e3, 1),
-                              "algorithmic_flops_per_launch": int(total / apps), "ms": round(ms, 2),
-                              "launches": apps, "event_scopes": cnt,
-                              "active_rhs_per_launch": round(cnn_apps / apps, 2),
-                              # the layers' arithmetic intensities cap the class below the MFMA
-                              # peak: the fraction attainable at the HBM roof, and ours of it
-                              "intensity_ceiling_frac": round(ceil, 4),
-                              "frac_of_ceiling": round(ach / BF16_PEAK_TFLOPS / ceil, 4)}
-        else:
-            classes[kname] = {"ms": round(ms, 2), "launches": cnt}
-    ranked = sorted(((v[0], kname) for kname, v in prof.items()), reverse=True)
-    dom = next((kname for _, kname in ranked if "bound" in classes.get(kname, {})), None)
-    roof = dict(classes[dom], kernel=dom,
-                measured="HIP events around every launch of the class on the library's stream, in one "
-                         "profiled solve after the timed steps (same kernels; cycles eager while profiling)") \
-        if dom else None
+    classes, roof = class_report(prof, pinfo, n, nrhs, light)
 
     out = {
         "metric": METRIC,

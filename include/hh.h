@@ -381,7 +381,23 @@ hh_status hh_net_get_grads(hh_net* net, float* host);
  *   (64,64,1)}, otherwise HH_ERR_ARG. */
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
                        const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int act,
-                       void* y_dev, float* yf_dev, const int* active_host);
+                       void* y_dev, float* yf_dev, const int* active_host, int variant);
+
+/* Tile autotuning of the 3x3 convolutions (stride 1 and 2; the transposed
+ * layers have one kernel).  Each layer shape has several kernel variants
+ * (tile heights, staging through registers or direct to LDS; code TR or
+ * 100 + TR): on the first launch of a (shape, output size, batch) on a device,
+ * outside graph capture, each variant is timed on that call's data and the
+ * fastest is kept for the process.  All variants give bit-identical results.
+ * hh_conv_variants: the variant codes of a shape (codes may be NULL; returns
+ *   their count, 0 for an unknown shape; the first is the untuned default).
+ * hh_conv_tuned_variant: the choice made for a key, 0 if not tuned yet.
+ * hh_conv_force_variant: use `code` for every launch of the shape (0: autotune
+ *   again); HH_ERR_ARG for a code the shape does not have.
+ * hh_conv_test's `variant` (0: the autotuned choice) selects one variant. */
+int hh_conv_variants(int cin, int cout, int mode, int* codes, int max);
+int hh_conv_tuned_variant(int device, int cin, int cout, int mode, int Hout, int Wout, int B);
+hh_status hh_conv_force_variant(int cin, int cout, int mode, int code);
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint);
 /* hh_pointwise_test: the lightweight network's 1x1 convolution (Sec. 4.4) on
  *   BF16 x [npix][cin] with FP32 weights w [cout][cin]:

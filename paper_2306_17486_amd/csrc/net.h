@@ -33,7 +33,12 @@ struct ConvArgs {
     const uint16_t* wp_lo;
     float2* yproj;
 };
-hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a);
+// variant 0: the autotuned choice for this (shape, output size, batch) key (tuned
+// on the first launch outside graph capture); otherwise a variant code of the shape
+hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a, int variant = 0);
+int conv_tuned_variant(int device, int cin, int cout, int mode, int Hout, int Wout, int B);  // 0: not tuned
+hh_status conv_force_variant(int cin, int cout, int mode, int code);                         // 0: autotune
+int conv_variant_list(int cin, int cout, int mode, int* codes, int max);
 // the 16 -> 2 projection (stride 1) on the convolution kernel, weights split into BF16 high + low parts
 hh_status launch_conv_proj(hipStream_t st, int num_cus, const ConvArgs& a);
 hh_status pack_weights_split(hipStream_t st, const float* W, uint16_t* Wp_hi, uint16_t* Wp_lo, int cin, int cout_real,

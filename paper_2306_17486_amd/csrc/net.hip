@@ -2951,7 +2951,7 @@ hh_status hh_apply_cnn_precond(hh_model* m, int nrhs, const int* inst_host, cons
 
 hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin, int Win, const void* x_dev,
                        const float* w_dev, int flipped, const float* bias_dev, const void* skip_dev, int act,
-                       void* y_dev, float* yf_dev, const int* active_host) {
+                       void* y_dev, float* yf_dev, const int* active_host, int variant) {
     HH_ARG(ctx && x_dev && w_dev && y_dev, "null pointer");
     HH_ARG(mode >= 0 && mode <= 2, "mode");
     HH_ARG(B >= 1 && Hin >= 1 && Win >= 1, "sizes");
@@ -2977,7 +2977,7 @@ hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin,
     a.Hout = mode == CM_S2 ? Hin / 2 : (mode == CM_T2 ? 2 * Hin : Hin);
     a.Wout = mode == CM_S2 ? Win / 2 : (mode == CM_T2 ? 2 * Win : Win);
     a.active = actb.as<int>();
-    HH_TRY(launch_conv(ctx->stream, ctx->num_cus, cin, cout, mode, a));
+    HH_TRY(launch_conv(ctx->stream, ctx->num_cus, cin, cout, mode, a, variant));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
 }
@@ -2994,6 +2994,18 @@ hh_status hh_wgrad_test(hh_ctx* ctx, int ca, int cx, int mode, int B, int Ho, in
                         part, ctx, out_dev));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
+}
+
+int hh_conv_variants(int cin, int cout, int mode, int* codes, int max) {
+    return codes ? conv_variant_list(cin, cout, mode, codes, max) : conv_variant_list(cin, cout, mode, nullptr, 0);
+}
+
+int hh_conv_tuned_variant(int device, int cin, int cout, int mode, int Hout, int Wout, int B) {
+    return conv_tuned_variant(device, cin, cout, mode, Hout, Wout, B);
+}
+
+hh_status hh_conv_force_variant(int cin, int cout, int mode, int code) {
+    return conv_force_variant(cin, cout, mode, code);
 }
 
 hh_status hh_pointwise_test(hh_ctx* ctx, int cin, int cout, size_t npix, const void* x_dev, const float* w_dev,

@@ -14,6 +14,9 @@
 // The epilogue fuses bias, a sum skip connection, the activation (ReLU, or
 // softplus for the lightweight network), and (backward) the ReLU mask of the
 // tensor whose gradient is produced.
+#include <map>
+#include <mutex>
+
 #include "net.h"
 
 namespace hh {
@@ -63,10 +66,12 @@ __global__ void k_pack_weights_split(const float* __restrict__ W, uint16_t* __re
 // BF16 activations exact, so the layer keeps its FP32 weights to 2^-17), and
 // the output as FP32 (re, im) pairs.
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, int MODE>
+template <int CIN, int COUT, int MODE, int TR_ = 0>
 struct ConvCfg {
     static constexpr int TC = 32;                                               // output tile columns
-    static constexpr int TR = (MODE == CM_S2) ? (CIN >= 32 ? 2 : 4) : (CIN >= 64 ? 2 : (CIN >= 32 ? 4 : 16));  // output tile rows
+    // output tile rows (TR_ = 0: the default of the shape)
+    static constexpr int TR = TR_ > 0 ? TR_
+                                      : (MODE == CM_S2) ? (CIN >= 32 ? 2 : 4) : (CIN >= 64 ? 2 : (CIN >= 32 ? 4 : 16));
     static constexpr int NT = COUT / 16;                                        // channel tiles
     // channel tiles per wave: a pixel fragment read from LDS feeds CT MFMAs;
     // the weights' VGPRs (CT * NCH * 4) stay within 72 so that two or more
@@ -83,9 +88,9 @@ struct ConvCfg {
     static constexpr int LDS_BYTES = PH * PW * CP * 2;
 };
 
-template <int CIN, int COUT, int MODE, bool PROJ = false>
+template <int CIN, int COUT, int MODE, bool PROJ = false, int TR_ = 0>
 __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 waves per SIMD resident
-    using C = ConvCfg<CIN, COUT, MODE>;
+    using C = ConvCfg<CIN, COUT, MODE, TR_>;
     static_assert(!PROJ || (CIN == 16 && COUT == 16 && MODE == CM_S1 && C::CT == 1 && C::NG == 1),
                   "projection: one 16-channel tile, stride 1");
     __shared__ __attribute__((aligned(16))) uint16_t s_in[C::PH * C::PW * C::CP];
@@ -675,59 +680,214 @@ static hh_status launch_t2_t(hipStream_t st, ConvArgs a, int num_cus) {
     return HH_OK;
 }
 
-// stride-2 layers: the direct-to-LDS kernel (measured at the 1024^2 network's
-// shapes, 42 right-hand sides: 16 -> 32 121 -> 112 us, 32 -> 64 74 -> 68 us,
-// 64 -> 64 48 -> 34 us); the stride-1 layers keep the register-prefetch
-// kernel, which overlaps the next tile's loads with the MFMAs and was faster
-// there (16 -> 16 181 against 185-224 us, 32 -> 32 113 against 122-131 us).
-template <int CIN, int COUT>
-static hh_status launch_conv_s2_dma(hipStream_t st, ConvArgs a, int num_cus) {
-    constexpr int TR = CIN >= 32 ? 2 : 4;
-    using C = DmaCfg<CIN, COUT, CM_S2, TR>;
+// ---------------------------------------------------------------------------
+// Tile autotuner.  Every stride-1 and stride-2 layer shape has several
+// variants: the register-prefetch kernel (k_conv_mfma) and the direct-to-LDS
+// kernel (k_conv_dma) at several tile heights.  Variant code: TR for the
+// register kernel, 100 + TR for the direct-to-LDS one.  On the first launch of
+// a (shape, output size, batch) key on a device, outside graph capture, every
+// variant runs twice on the call's own data (HIP events on the launch stream,
+// the second run counts) and the fastest is kept for the process; then the
+// chosen variant runs once more (each run rewrites the same output, so the
+// result does not depend on which ran last).  All variants take the same k
+// chunks in the same order for every output pixel: their results are
+// bit-identical.  Defaults (before tuning, or while a stream captures): the
+// direct-to-LDS kernel for the strided layers (measured at the 1024^2
+// network's shapes, 42 right-hand sides: 16 -> 32 121 -> 112 us, 32 -> 64
+// 74 -> 68, 64 -> 64 48 -> 34), the register kernel for stride 1 (16 -> 16
+// 181 against 185-224 us, 32 -> 32 113 against 122-131 us).
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int MODE, int TR>
+static hh_status launch_reg(hipStream_t st, ConvArgs a, int num_cus) {
+    using C = ConvCfg<CIN, COUT, MODE, TR>;
     a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
     a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
     a.ntiles = a.B * a.tiles_x * a.tiles_y;
     if (a.ntiles == 0) return HH_OK;
     const int grid = std::min(a.ntiles, 8 * num_cus);
-    hipLaunchKernelGGL((k_conv_dma<CIN, COUT, CM_S2, TR>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_conv_mfma<CIN, COUT, MODE, false, TR>), dim3(grid), dim3(256), 0, st, a);
     HH_LAUNCH_CHECK();
     return HH_OK;
 }
 
-template <int CIN, int COUT, int MODE>
-static hh_status launch_conv_t(hipStream_t st, ConvArgs a, int num_cus) {
-    if constexpr (MODE == CM_S2) {
-        return launch_conv_s2_dma<CIN, COUT>(st, a, num_cus);
-    } else {
-        using C = ConvCfg<CIN, COUT, MODE>;
-        a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
-        a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
-        a.ntiles = a.B * a.tiles_x * a.tiles_y;
-        if (a.ntiles == 0) return HH_OK;
-        const int grid = std::min(a.ntiles, 8 * num_cus);
-        hipLaunchKernelGGL((k_conv_mfma<CIN, COUT, MODE>), dim3(grid), dim3(256), 0, st, a);
-        HH_LAUNCH_CHECK();
-        return HH_OK;
-    }
+template <int CIN, int COUT, int MODE, int TR>
+static hh_status launch_dma(hipStream_t st, ConvArgs a, int num_cus) {
+    using C = DmaCfg<CIN, COUT, MODE, TR>;
+    a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
+    a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
+    a.ntiles = a.B * a.tiles_x * a.tiles_y;
+    if (a.ntiles == 0) return HH_OK;
+    const int grid = std::min(a.ntiles, 8 * num_cus);
+    hipLaunchKernelGGL((k_conv_dma<CIN, COUT, MODE, TR>), dim3(grid), dim3(256), 0, st, a);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
 }
 
-hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a) {
-#define HH_CONV_CASE(CI, CO, MD) \
-    if (cin == CI && cout == CO && mode == MD) return launch_conv_t<CI, CO, MD>(st, a, num_cus);
-    HH_CONV_CASE(16, 16, CM_S1)
-    HH_CONV_CASE(32, 32, CM_S1)
-    HH_CONV_CASE(64, 64, CM_S1)
-    HH_CONV_CASE(16, 32, CM_S2)
-    HH_CONV_CASE(32, 64, CM_S2)
-    HH_CONV_CASE(64, 64, CM_S2)
-#undef HH_CONV_CASE
+// the variants of a shape (first: the default)
+static int conv_variants(int cin, int cout, int mode, int* codes) {
+    static const int v16[] = {16, 8, 4, 108, 116};
+    static const int v32[] = {4, 2, 8, 104, 108};
+    static const int v64[] = {2, 1, 4, 102, 104};
+    static const int s16[] = {104, 102, 108, 4};
+    static const int s32[] = {102, 104, 2, 4};
+    static const int s64[] = {102, 101, 2};
+    const int* v = nullptr;
+    int nv = 0;
+    if (mode == CM_S1 && cin == 16 && cout == 16) { v = v16; nv = 5; }
+    if (mode == CM_S1 && cin == 32 && cout == 32) { v = v32; nv = 5; }
+    if (mode == CM_S1 && cin == 64 && cout == 64) { v = v64; nv = 5; }
+    if (mode == CM_S2 && cin == 16 && cout == 32) { v = s16; nv = 4; }
+    if (mode == CM_S2 && cin == 32 && cout == 64) { v = s32; nv = 4; }
+    if (mode == CM_S2 && cin == 64 && cout == 64) { v = s64; nv = 3; }
+    for (int i = 0; i < nv; ++i) codes[i] = v[i];
+    return nv;
+}
+
+static hh_status launch_variant(hipStream_t st, int num_cus, int cin, int cout, int mode, int code,
+                                const ConvArgs& a) {
+#define HH_V(CI, CO, MD, CODE, CALL) \
+    if (cin == CI && cout == CO && mode == MD && code == CODE) return CALL(st, a, num_cus);
+    HH_V(16, 16, CM_S1, 16, (launch_reg<16, 16, CM_S1, 16>))
+    HH_V(16, 16, CM_S1, 8, (launch_reg<16, 16, CM_S1, 8>))
+    HH_V(16, 16, CM_S1, 4, (launch_reg<16, 16, CM_S1, 4>))
+    HH_V(16, 16, CM_S1, 108, (launch_dma<16, 16, CM_S1, 8>))
+    HH_V(16, 16, CM_S1, 116, (launch_dma<16, 16, CM_S1, 16>))
+    HH_V(32, 32, CM_S1, 4, (launch_reg<32, 32, CM_S1, 4>))
+    HH_V(32, 32, CM_S1, 2, (launch_reg<32, 32, CM_S1, 2>))
+    HH_V(32, 32, CM_S1, 8, (launch_reg<32, 32, CM_S1, 8>))
+    HH_V(32, 32, CM_S1, 104, (launch_dma<32, 32, CM_S1, 4>))
+    HH_V(32, 32, CM_S1, 108, (launch_dma<32, 32, CM_S1, 8>))
+    HH_V(64, 64, CM_S1, 2, (launch_reg<64, 64, CM_S1, 2>))
+    HH_V(64, 64, CM_S1, 1, (launch_reg<64, 64, CM_S1, 1>))
+    HH_V(64, 64, CM_S1, 4, (launch_reg<64, 64, CM_S1, 4>))
+    HH_V(64, 64, CM_S1, 102, (launch_dma<64, 64, CM_S1, 2>))
+    HH_V(64, 64, CM_S1, 104, (launch_dma<64, 64, CM_S1, 4>))
+    HH_V(16, 32, CM_S2, 104, (launch_dma<16, 32, CM_S2, 4>))
+    HH_V(16, 32, CM_S2, 102, (launch_dma<16, 32, CM_S2, 2>))
+    HH_V(16, 32, CM_S2, 108, (launch_dma<16, 32, CM_S2, 8>))
+    HH_V(16, 32, CM_S2, 4, (launch_reg<16, 32, CM_S2, 4>))
+    HH_V(32, 64, CM_S2, 102, (launch_dma<32, 64, CM_S2, 2>))
+    HH_V(32, 64, CM_S2, 104, (launch_dma<32, 64, CM_S2, 4>))
+    HH_V(32, 64, CM_S2, 2, (launch_reg<32, 64, CM_S2, 2>))
+    HH_V(32, 64, CM_S2, 4, (launch_reg<32, 64, CM_S2, 4>))
+    HH_V(64, 64, CM_S2, 102, (launch_dma<64, 64, CM_S2, 2>))
+    HH_V(64, 64, CM_S2, 101, (launch_dma<64, 64, CM_S2, 1>))
+    HH_V(64, 64, CM_S2, 2, (launch_reg<64, 64, CM_S2, 2>))
+#undef HH_V
+    set_error("no convolution variant %d for cin=%d cout=%d mode=%d", code, cin, cout, mode);
+    return HH_ERR_ARG;
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::pair<int, uint64_t>, int> g_tune;  // (device, key) -> chosen variant
+std::map<uint64_t, int> g_forced;                // (cin, cout, mode) -> forced variant
+uint64_t tune_key(int cin, int cout, int mode, const ConvArgs& a) {
+    return ((uint64_t)cin << 56) | ((uint64_t)cout << 48) | ((uint64_t)mode << 44) | ((uint64_t)a.Hout << 30) |
+           ((uint64_t)a.Wout << 16) | (uint64_t)a.B;
+}
+uint64_t shape_key(int cin, int cout, int mode) { return ((uint64_t)cin << 16) | ((uint64_t)cout << 4) | mode; }
+}  // namespace
+
+// times the variants of a key on the call's data; returns the fastest
+static hh_status conv_tune(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a,
+                           const int* codes, int nv, int* best) {
+    hipEvent_t e0, e1;
+    HH_HIP(hipEventCreate(&e0));
+    HH_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    *best = codes[0];
+    hh_status s = HH_OK;
+    for (int v = 0; v < nv && s == HH_OK; ++v) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && s == HH_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) s = HH_ERR_HIP;
+            if (s == HH_OK) s = launch_variant(st, num_cus, cin, cout, mode, codes[v], a);
+            if (s == HH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                s = HH_ERR_HIP;
+        }
+        if (s == HH_OK && ms < best_ms) {
+            best_ms = ms;
+            *best = codes[v];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != HH_OK && !hh_last_error()[0]) set_error("convolution autotuning failed");
+    return s;
+}
+
+hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a, int variant) {
     if (mode == CM_T2) {
         if (cin == 64 && cout == 64) return launch_t2_t<64, 64>(st, a, num_cus);
         if (cin == 64 && cout == 32) return launch_t2_t<64, 32>(st, a, num_cus);
         if (cin == 32 && cout == 16) return launch_t2_t<32, 16>(st, a, num_cus);
+        set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
+        return HH_ERR_ARG;
     }
-    set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
-    return HH_ERR_ARG;
+    int codes[8];
+    const int nv = conv_variants(cin, cout, mode, codes);
+    if (nv == 0) {
+        set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
+        return HH_ERR_ARG;
+    }
+    if (variant != 0) return launch_variant(st, num_cus, cin, cout, mode, variant, a);
+    int dev = 0;
+    HH_HIP(hipGetDevice(&dev));
+    const uint64_t key = tune_key(cin, cout, mode, a);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto f = g_forced.find(shape_key(cin, cout, mode));
+        if (f != g_forced.end()) return launch_variant(st, num_cus, cin, cout, mode, f->second, a);
+        auto it = g_tune.find({dev, key});
+        if (it != g_tune.end()) return launch_variant(st, num_cus, cin, cout, mode, it->second, a);
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HH_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone || a.B * a.Hout * a.Wout == 0)
+        return launch_variant(st, num_cus, cin, cout, mode, codes[0], a);
+    int best = codes[0];
+    HH_TRY(conv_tune(st, num_cus, cin, cout, mode, a, codes, nv, &best));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[{dev, key}] = best;
+    }
+    return launch_variant(st, num_cus, cin, cout, mode, best, a);
+}
+
+int conv_tuned_variant(int device, int cin, int cout, int mode, int Hout, int Wout, int B) {
+    ConvArgs a{};
+    a.Hout = Hout;
+    a.Wout = Wout;
+    a.B = B;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({device, tune_key(cin, cout, mode, a)});
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+hh_status conv_force_variant(int cin, int cout, int mode, int code) {
+    int codes[8];
+    const int nv = conv_variants(cin, cout, mode, codes);
+    bool ok = code == 0;
+    for (int i = 0; i < nv; ++i) ok = ok || codes[i] == code;
+    if (!ok) {
+        set_error("variant %d is not one of the layer shape's", code);
+        return HH_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (code == 0)
+        g_forced.erase(shape_key(cin, cout, mode));
+    else
+        g_forced[shape_key(cin, cout, mode)] = code;
+    return HH_OK;
+}
+
+int conv_variant_list(int cin, int cout, int mode, int* codes, int max) {
+    int tmp[8];
+    const int nv = mode == CM_T2 ? 0 : conv_variants(cin, cout, mode, tmp);
+    for (int i = 0; codes && i < nv && i < max; ++i) codes[i] = tmp[i];
+    return nv;
 }
 
 hh_status launch_conv_proj(hipStream_t st, int num_cus, const ConvArgs& a0) {

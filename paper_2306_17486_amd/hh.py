@@ -101,7 +101,10 @@ hh_net_load = _sig("hh_net_load", _I, _P, C.c_char_p, C.POINTER(_P))
 hh_model_attach_net = _sig("hh_model_attach_net", _I, _P, _P)
 hh_net_forward = _sig("hh_net_forward", _I, _P, _I, _IP, _P, _P)
 hh_apply_cnn_precond = _sig("hh_apply_cnn_precond", _I, _P, _I, _IP, _P, _P)
-hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _IP)
+hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _IP, _I)
+hh_conv_variants = _sig("hh_conv_variants", _I, _I, _I, _I, _IP, _I)
+hh_conv_tuned_variant = _sig("hh_conv_tuned_variant", _I, _I, _I, _I, _I, _I, _I, _I)
+hh_conv_force_variant = _sig("hh_conv_force_variant", _I, _I, _I, _I, _I)
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
 hh_pointwise_test = _sig("hh_pointwise_test", _I, _P, _I, _I, C.c_size_t, _P, _P, _P, _P, _I, _P, _P)
 hh_depthwise_test = _sig("hh_depthwise_test", _I, _P, _I, _I, _I, _I, _P, _P, _P, _I, _I, _P, _P)
@@ -487,10 +490,28 @@ class Net:
             pass
 
 
+def conv_variants(cin: int, cout: int, mode: int) -> list[int]:
+    """Kernel variant codes of a convolution shape (the first is the untuned default)."""
+    codes = (C.c_int * 16)()
+    nv = hh_conv_variants(cin, cout, mode, codes, 16)
+    return [int(codes[i]) for i in range(nv)]
+
+
+def conv_tuned_variant(device: int, cin: int, cout: int, mode: int, Hout: int, Wout: int, B: int) -> int:
+    """The autotuner's choice for a key (0: not tuned yet)."""
+    return int(hh_conv_tuned_variant(device, cin, cout, mode, Hout, Wout, B))
+
+
+def conv_force_variant(cin: int, cout: int, mode: int, code: int):
+    """Use one variant for every launch of a shape (0: autotune again)."""
+    check(hh_conv_force_variant(cin, cout, mode, code))
+
+
 def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, flipped: bool, bias=None, skip=None,
-              relu=False, active=None, fill=None, act=None):
+              relu=False, active=None, fill=None, act=None, variant: int = 0):
     """One convolution through the library's MFMA kernel; returns (y bf16, y fp32).
-    act: 0 none, 1 ReLU, 2 softplus (default: 1 if relu else 0).
+    act: 0 none, 1 ReLU, 2 softplus (default: 1 if relu else 0); variant: a
+    kernel variant code (0: the autotuned choice).
     active: optional per-batch-entry flags (0 = skipped, output left as filled);
     fill: initial value of both outputs (default: uninitialised)."""
     B, H, W_, cin = x_bf16.shape
@@ -509,7 +530,7 @@ def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, fl
     skip = skip.contiguous() if skip is not None else None
     check(hh_conv_test(ctx.handle, cin, cout, mode, B, H, W_, _ptr(x_bf16), _ptr(w), int(flipped), _ptr(bias),
                        _ptr(skip), int(act if act is not None else (1 if relu else 0)), _ptr(y), _ptr(yf),
-                       _int_array(active)))
+                       _int_array(active), int(variant)))
     return y, yf
 
 

@@ -416,3 +416,64 @@ def test_cnn_precond_equals_forward_then_vcycle(hh, ctx, n, ninst):
     d = (z1 - z2).abs().max().item() / z2.abs().max().item()
     _say(f"  max difference {d:.2e} (bitwise equal: {torch.equal(z1, z2)})")
     assert d <= 1e-6
+
+
+VARIANT_SHAPES = [(16, 16, 0, 40), (32, 32, 0, 36), (64, 64, 0, 20), (16, 32, 1, 80), (32, 64, 1, 72),
+                  (64, 64, 1, 40)]
+
+
+@pytest.mark.parametrize("cin,cout,mode,Hin", VARIANT_SHAPES)
+def test_conv_tile_variants_bit_identical(hh, ctx, cin, cout, mode, Hin):
+    # every tile variant the autotuner can pick takes the same k chunks in the
+    # same order per output pixel: bit-identical outputs, skipped batch entries
+    # untouched (ragged sizes, more tiles than one row of workgroups)
+    codes = hh.conv_variants(cin, cout, mode)
+    _say(f"conv variants {cin}->{cout} mode {mode}: {codes}")
+    assert len(codes) >= 3
+    rng = np.random.default_rng(cin * 7 + mode)
+    B, W = 3, Hin + 6
+    x = _bf16_round(rng.standard_normal((B, cin, Hin, W)))
+    w = _bf16_round(rng.uniform(-1, 1, (cout, cin, 3, 3)) / np.sqrt(9 * cin))
+    b = torch.from_numpy(rng.uniform(-0.5, 0.5, cout)).to("cuda:0", torch.float32)
+    xd = _nhwc_dev(x)
+    wd = torch.from_numpy(w).to("cuda:0", torch.float32)
+    active = [1, 0, 1]
+    ref = hh.conv_test(ctx, xd, wd, mode, False, bias=b, relu=True, active=active, fill=7.0, variant=codes[0])
+    for c in codes[1:]:
+        y, yf = hh.conv_test(ctx, xd, wd, mode, False, bias=b, relu=True, active=active, fill=7.0, variant=c)
+        assert torch.equal(y, ref[0]) and torch.equal(yf, ref[1]), c
+    # against the oracle (the default variant), and the skipped entry untouched
+    o = np.maximum(C.conv2d(x, w, b.cpu().numpy().astype(np.float64), 2 if mode == 1 else 1), 0.0)
+    yf = ref[1].cpu().numpy().astype(np.float64).transpose(0, 3, 1, 2)
+    for bb in (0, 2):
+        assert np.abs(yf[bb] - o[bb]).max() <= 2e-6 * max(np.abs(o[bb]).max(), 1.0)
+    assert (yf[1] == 7.0).all()
+
+
+def test_conv_autotuner_records_and_forces(hh, ctx):
+    n = 128
+    _say("conv autotuner")
+    k = inputs.grf_slowness(n, 44)
+    om = inputs.omega_for(n, k)
+    net = hh.Net(ctx, inputs.init_net_params(19))
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.attach_net(net)
+    r = torch.from_numpy(inputs.random_complex((2, n, n), 45)).to("cuda:0", torch.complex64)
+    e0 = m.net_forward(r)
+    # the level-1 stride-1 layer (16 -> 16 at n/2, batch 2) and a strided one were tuned
+    c11 = hh.conv_tuned_variant(0, 16, 16, 0, n // 2, n // 2, 2)
+    c12 = hh.conv_tuned_variant(0, 16, 32, 1, n // 4, n // 4, 2)
+    _say(f"  tuned: 16->16 {c11}, 16->32 strided {c12}")
+    assert c11 in hh.conv_variants(16, 16, 0)
+    assert c12 in hh.conv_variants(16, 32, 1)
+    # forcing any other variant changes nothing in the result
+    for code in hh.conv_variants(16, 16, 0):
+        hh.conv_force_variant(16, 16, 0, code)
+        assert torch.equal(m.net_forward(r), e0), code
+    hh.conv_force_variant(16, 16, 0, 0)
+    with pytest.raises(hh.HHError):
+        hh.conv_force_variant(16, 16, 0, 3)
+    assert torch.equal(m.net_forward(r), e0)
+    m.attach_net(None)
+    net.close()
+    m.close()
