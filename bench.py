@@ -748,6 +748,16 @@ def main():
         "kernels": classes,
     }
     if use_cnn:
+        # the convolution tiles the autotuner picked for this workload's solver layers
+        nc4 = n // 16 if n >= 512 else n // 8
+        tiles = {}
+        for (ci, co, md, ho) in ((16, 16, 0, n // 2), (32, 32, 0, n // 4), (64, 64, 0, n // 8), (64, 64, 0, nc4),
+                                 (16, 32, 1, n // 4), (32, 64, 1, n // 8), (64, 64, 1 if n >= 512 else 0, nc4)):
+            code = hh.conv_tuned_variant(0, ci, co, md, ho, ho, nrhs)
+            tiles[f"{ci}->{co} {'stride 2' if md else 'stride 1'} at {ho}^2"] = (
+                None if code == 0 else (f"direct-to-LDS, {code - 100}-row tiles" if code > 100
+                                        else f"register-staged, {code}-row tiles"))
+        out["conv_tiles_autotuned"] = tiles
         out["cnn_iterations_mean"] = float(res["cnn_iters"].mean())
         out["mg_only_cycles_mean"] = float(res["mg_cycles"].mean())
         if a.mg_steps > 0:
