@@ -399,6 +399,13 @@ int hh_conv_variants(int cin, int cout, int mode, int* codes, int max);
 int hh_conv_tuned_variant(int device, int cin, int cout, int mode, int Hout, int Wout, int B);
 hh_status hh_conv_force_variant(int cin, int cout, int mode, int code);
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint);
+/* hh_implicit_ggrad_test: the training pass's gradient of the implicit layer's
+ *   transformed Green's functions (eqs. 16-17): for BF16 NHWC z and gy
+ *   [B][nc][nc][2 nk] (complex channel c = channels 2c, 2c+1), out (complex128
+ *   [nk][2nc][2nc], natural frequency order, overwritten) =
+ *   sum_b conj(FFT(pad z_b)) FFT(pad gy_b) / (2nc)^2; 2nc in {16, 32, 64, 128}. */
+hh_status hh_implicit_ggrad_test(hh_ctx* ctx, int nk, int nc, int B, const void* z_dev, const void* gy_dev,
+                                 void* out_dev);
 /* hh_pointwise_test: the lightweight network's 1x1 convolution (Sec. 4.4) on
  *   BF16 x [npix][cin] with FP32 weights w [cout][cin]:
  *   y[p][o] = act(sum_c w[o][c] x[p][c] + bias[o]) + res[p][o]; bias (FP32) and

@@ -1904,6 +1904,79 @@ __global__ void __launch_bounds__(NT) k_implicit_ggrad(const uint16_t* __restric
     }
 }
 
+// the same for transforms too large for two maps in LDS (M = 128, the 1024^2
+// network): FFT(pad z) goes through a scratch map in global memory (written
+// and read back by the same threads), FFT(pad gy) stays in LDS
+template <int M, int NT>
+__global__ void __launch_bounds__(NT) k_implicit_ggrad_big(const uint16_t* __restrict__ z,
+                                                           const uint16_t* __restrict__ gy, float2* __restrict__ scratch,
+                                                           float2* __restrict__ part, int nc, int nk) {
+    extern __shared__ float2 s_dyn[];
+    constexpr int P = M + 1;
+    float2* s = s_dyn;
+    float2* tw = s_dyn + M * P;
+    const int c = blockIdx.x, b = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int CH = 2 * nk;
+    float2* zs = scratch + ((size_t)b * nk + c) * M * M;
+    for (int t = tid; t < M / 2; t += NT) {
+        float sn, cs;
+        sincospif(-2.0f * (float)t / (float)M, &sn, &cs);
+        tw[t] = make_float2(cs, sn);
+    }
+    int bits = 0;
+    while ((1 << bits) < M) ++bits;
+    const float sc = 1.f / ((float)M * M);
+    for (int pass = 0; pass < 2; ++pass) {
+        const uint16_t* src = pass == 0 ? z : gy;
+        __syncthreads();  // the previous pass is done with s
+        for (int e = tid; e < M * P; e += NT) s[e] = make_float2(0.f, 0.f);
+        __syncthreads();
+        for (int e = tid; e < nc * nc; e += NT) {
+            const int y = e / nc, x = e - y * nc;
+            const uint32_t r0 = *reinterpret_cast<const uint32_t*>(src + (((size_t)b * nc + y) * nc + x) * CH + 2 * c);
+            s[y * P + x] = make_float2(bf2f((uint16_t)(r0 & 0xffff)), bf2f((uint16_t)(r0 >> 16)));
+        }
+        __syncthreads();
+        for (int len = M; len >= 2; len >>= 1) {  // rows holding data
+            const int half = len >> 1, tws = M / len;
+            for (int t = tid; t < nc * (M / 2); t += NT) {
+                const int row = t / (M / 2), bf = t - row * (M / 2);
+                const int blk = bf / half, j = bf - blk * half;
+                const int i0 = row * P + blk * len + j, i1 = i0 + half;
+                const float2 a = s[i0], bb = s[i1];
+                s[i0] = cadd(a, bb);
+                s[i1] = cmul(csub(a, bb), tw[j * tws]);
+            }
+            __syncthreads();
+        }
+        for (int len = M; len >= 2; len >>= 1) {  // all columns
+            const int half = len >> 1, tws = M / len;
+            for (int t = tid; t < M * (M / 2); t += NT) {
+                const int col = t % M, bf = t / M;
+                const int blk = bf / half, j = bf - blk * half;
+                const int i0 = (blk * len + j) * P + col, i1 = i0 + half * P;
+                const float2 a = s[i0], bb = s[i1];
+                s[i0] = cadd(a, bb);
+                s[i1] = cmul(csub(a, bb), tw[j * tws]);
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < M * M; e += NT) {
+            const int r = e / M, col = e - r * M;
+            if (pass == 0) {
+                zs[e] = s[r * P + col];
+            } else {
+                const float2 a = zs[e], g = s[r * P + col];  // written by this thread in pass 0
+                const float2 pr = make_float2((a.x * g.x + a.y * g.y) * sc, (a.x * g.y - a.y * g.x) * sc);
+                const int k1 = (int)(__brev((unsigned)r) >> (32 - bits));
+                const int k2 = (int)(__brev((unsigned)col) >> (32 - bits));
+                part[(((size_t)b * nk + c) * M + k1) * M + k2] = pr;
+            }
+        }
+    }
+}
+
 // gG[c][e] = sum_b part[b][c][e]  (FP64)
 __global__ void k_reduce_ggrad(const float2* __restrict__ part, int B, int count, double2* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2125,6 +2198,7 @@ struct TrainWork {
     Buf lparts;           // loss partials
     Buf part, part2;      // reduction scratch
     Buf gGh_part, gGh;    // implicit-layer kernel gradients
+    Buf ggscratch;        // implicit-layer gradient scratch maps (transform size 128)
     Buf Gbr;              // transformed Green's functions of this step
     // the lightweight network
     LightActs lacts;
@@ -2192,6 +2266,52 @@ static hh_status read_loss(hh_ctx* ctx, const Buf& lparts, int B, int n, const B
     return HH_OK;
 }
 
+// gradient of the transformed Green's functions (natural order, FP64):
+// gGh[c][k] = sum_b conj(FFT(pad z_b))[k] FFT(pad gy_b)[k] / M^2, M = 2 nc,
+// through per-sample partials (and, for M = 128, a scratch map per sample and channel)
+static hh_status implicit_ggrad(hh_ctx* ctx, int nk, int nc, int B, const uint16_t* z, const uint16_t* gy, Buf& part,
+                                Buf& scratch, double2* gGh) {
+    hipStream_t st = ctx->stream;
+    const int M = 2 * nc;
+    HH_TRY(part.ensure(ctx, (size_t)B * nk * M * M * sizeof(float2)));
+    dim3 grd(nk, B);
+    if (M == 128) {
+        const size_t lds = ((size_t)M * (M + 1) + M / 2) * sizeof(float2);
+        HH_TRY(scratch.ensure(ctx, (size_t)B * nk * M * M * sizeof(float2)));
+        static bool attr = false;
+        if (!attr) {
+            HH_HIP(hipFuncSetAttribute((const void*)k_implicit_ggrad_big<128, 1024>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_implicit_ggrad_big<128, 1024>), grd, dim3(1024), lds, st, z, gy,
+                           scratch.as<float2>(), part.as<float2>(), nc, nk);
+    } else {
+        const size_t lds = ((size_t)2 * M * (M + 1) + M / 2) * sizeof(float2);
+        if (M == 32) {
+            hipLaunchKernelGGL((k_implicit_ggrad<32, 256>), grd, dim3(256), lds, st, z, gy, part.as<float2>(), nc, nk);
+        } else if (M == 64) {
+            static bool attr = false;
+            if (!attr) {
+                HH_HIP(hipFuncSetAttribute((const void*)k_implicit_ggrad<64, 512>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                attr = true;
+            }
+            hipLaunchKernelGGL((k_implicit_ggrad<64, 512>), grd, dim3(512), lds, st, z, gy, part.as<float2>(), nc, nk);
+        } else if (M == 16) {
+            hipLaunchKernelGGL((k_implicit_ggrad<16, 256>), grd, dim3(256), lds, st, z, gy, part.as<float2>(), nc, nk);
+        } else {
+            set_error("implicit-layer gradient: transform size %d not supported (16 .. 128)", M);
+            return HH_ERR_ARG;
+        }
+    }
+    HH_LAUNCH_CHECK();
+    const int count = nk * M * M;
+    hipLaunchKernelGGL(k_reduce_ggrad, dim3((count + 255) / 256), dim3(256), 0, st, part.as<float2>(), B, count, gGh);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
 // coarsest layer backward: gin = adjoint(T.gimp) masked by `mask` (null: none),
 // and the gradient of its kernels from its input z (B maps of m4 x m4) into GR
 static hh_status coarse_backward(hh_ctx* ctx, hh_net* net, TrainWork& T, int B, int m4, const uint16_t* z,
@@ -2211,39 +2331,12 @@ static hh_status coarse_backward(hh_ctx* ctx, hh_net* net, TrainWork& T, int B, 
                            T.gGh_part.as<double2>(), B * nblk, count, GR + net->koff);
         HH_LAUNCH_CHECK();
     } else {
-    HH_TRY(launch_implicit(st, M, T.gimp.as<uint16_t>(), gin, T.Gbr.as<float2>(), m4, net->nk, B, true,
-                           nullptr, mask));
-    {
-        HH_TRY(T.gGh_part.ensure(ctx, (size_t)B * net->nk * M * M * sizeof(float2)));
+        HH_TRY(launch_implicit(st, M, T.gimp.as<uint16_t>(), gin, T.Gbr.as<float2>(), m4, net->nk, B, true,
+                               nullptr, mask));
         HH_TRY(T.gGh.ensure(ctx, (size_t)net->nk * M * M * sizeof(double2)));
-        const size_t lds = ((size_t)2 * M * (M + 1) + M / 2) * sizeof(float2);
-        dim3 grd(net->nk, B);
-        if (M == 32) {
-            hipLaunchKernelGGL((k_implicit_ggrad<32, 256>), grd, dim3(256), lds, st, z, T.gimp.as<uint16_t>(),
-                               T.gGh_part.as<float2>(), m4, net->nk);
-        } else if (M == 64) {
-            static bool attr = false;
-            if (!attr) {
-                HH_HIP(hipFuncSetAttribute((const void*)k_implicit_ggrad<64, 512>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-                attr = true;
-            }
-            hipLaunchKernelGGL((k_implicit_ggrad<64, 512>), grd, dim3(512), lds, st, z,
-                               T.gimp.as<uint16_t>(), T.gGh_part.as<float2>(), m4, net->nk);
-        } else if (M == 16) {
-            hipLaunchKernelGGL((k_implicit_ggrad<16, 256>), grd, dim3(256), lds, st, z, T.gimp.as<uint16_t>(),
-                               T.gGh_part.as<float2>(), m4, net->nk);
-        } else {
-            set_error("implicit-layer gradient: transform size %d not supported", M);
-            return HH_ERR_ARG;
-        }
-        HH_LAUNCH_CHECK();
-        const int count = net->nk * M * M;
-        hipLaunchKernelGGL(k_reduce_ggrad, dim3((count + 255) / 256), dim3(256), 0, st, T.gGh_part.as<float2>(), B,
-                           count, T.gGh.as<double2>());
-        HH_LAUNCH_CHECK();
+        HH_TRY(implicit_ggrad(ctx, net->nk, nc, B, z, T.gimp.as<uint16_t>(), T.gGh_part, T.ggscratch,
+                              T.gGh.as<double2>()));
         HH_TRY(green_backward(net, nc, T.gGh.as<double2>(), GR + net->koff, 1e-5));
-    }
     }
     return HH_OK;
 }
@@ -2471,8 +2564,8 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
     HH_ARG(net->ctx == ctx && md->ctx == ctx, "objects of another context");
     HH_ARG(B >= 1 && (md->ninst == B || md->ninst == 1), "model must hold one slowness model per sample (or one)");
     const int n = md->lev[0].n;
-    HH_ARG(n % 16 == 0 && n >= 64 && n <= 512 && (n & (n - 1)) == 0,
-           "training sizes: n a power of two from 64 to 512 (implicit-layer gradient transforms up to 64)");
+    HH_ARG(n % 16 == 0 && n >= 64 && n <= 1024 && (n & (n - 1)) == 0,
+           "training sizes: n a power of two from 64 to 1024 (implicit-layer gradient transforms up to 128)");
     HH_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     if (!net->train_work) {
@@ -3048,6 +3141,18 @@ hh_status hh_depthwise_test(hh_ctx* ctx, int C, int B, int H, int W, const void*
     a.H = H;
     a.W = W;
     HH_TRY(launch_depthwise(ctx->stream, ctx->num_cus, C, a));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+}
+
+hh_status hh_implicit_ggrad_test(hh_ctx* ctx, int nk, int nc, int B, const void* z_dev, const void* gy_dev,
+                                 void* out_dev) {
+    HH_ARG(ctx && z_dev && gy_dev && out_dev, "null pointer");
+    HH_ARG(nk >= 1 && B >= 1, "sizes");
+    HH_HIP(hipSetDevice(ctx->device));
+    Buf part, scratch;
+    HH_TRY(implicit_ggrad(ctx, nk, nc, B, (const uint16_t*)z_dev, (const uint16_t*)gy_dev, part, scratch,
+                          (double2*)out_dev));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
 }

@@ -106,6 +106,7 @@ hh_conv_variants = _sig("hh_conv_variants", _I, _I, _I, _I, _IP, _I)
 hh_conv_tuned_variant = _sig("hh_conv_tuned_variant", _I, _I, _I, _I, _I, _I, _I, _I)
 hh_conv_force_variant = _sig("hh_conv_force_variant", _I, _I, _I, _I, _I)
 hh_implicit_test = _sig("hh_implicit_test", _I, _P, _I, _I, _P, _P, _I)
+hh_implicit_ggrad_test = _sig("hh_implicit_ggrad_test", _I, _P, _I, _I, _I, _P, _P, _P)
 hh_pointwise_test = _sig("hh_pointwise_test", _I, _P, _I, _I, C.c_size_t, _P, _P, _P, _P, _I, _P, _P)
 hh_depthwise_test = _sig("hh_depthwise_test", _I, _P, _I, _I, _I, _I, _P, _P, _P, _I, _I, _P, _P)
 hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P)
@@ -571,3 +572,13 @@ def depthwise_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, bias=Non
     check(hh_depthwise_test(ctx.handle, Cc, B, H, W_, _ptr(x_bf16), _ptr(w), _ptr(bias), int(act), int(flip),
                             _ptr(y), _ptr(yf)))
     return y, yf
+
+
+def implicit_ggrad_test(ctx: Context, z_bf16: torch.Tensor, gy_bf16: torch.Tensor) -> torch.Tensor:
+    """Gradient of the implicit layer's transformed Green's functions for BF16
+    NHWC z, gy [B][nc][nc][2 nk]: complex128 [nk][2nc][2nc]."""
+    B, nc, _, ch = z_bf16.shape
+    out = torch.empty((ch // 2, 2 * nc, 2 * nc), dtype=torch.complex128, device=z_bf16.device)
+    z_bf16, gy_bf16 = z_bf16.contiguous(), gy_bf16.contiguous()
+    check(hh_implicit_ggrad_test(ctx.handle, ch // 2, nc, B, _ptr(z_bf16), _ptr(gy_bf16), _ptr(out)))
+    return out

@@ -38,7 +38,7 @@ import torch
 
 from . import hh, inputs
 
-SIZE_WEIGHT = {128: 16, 256: 10, 512: 4}  # relative number of steps per grid size (Sec. 5.3 epoch lengths)
+SIZE_WEIGHT = {128: 16, 256: 10, 512: 4, 1024: 2}  # relative number of steps per grid size (Sec. 5.3 epoch lengths; 1024 optional)
 GAMMA0 = 0.05                     # global damping of the training operators (Sec. 5.1)
 TRAIN_SEED0 = 100_000             # slowness seeds of the training stream: TRAIN_SEED0 + step * batch + j
 VAL_SEED0 = 9000                  # held-out validation media and vectors
@@ -235,7 +235,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=4000)
     ap.add_argument("--clip", type=float, default=2.0, help="clip at this multiple of the median gradient norm")
     ap.add_argument("--init-seed", type=int, default=0, help="seed of the initial parameters")
-    ap.add_argument("--sizes", type=str, default="128,256", help="training grid sizes (128, 256, 512)")
+    ap.add_argument("--sizes", type=str, default="128,256", help="training grid sizes (128, 256, 512, 1024)")
     ap.add_argument("--eval-sizes", type=str, default="128,256,512")
     ap.add_argument("--eval-media", type=int, default=16)
     ap.add_argument("--eval-large", type=str, default="1024", help="sizes evaluated on fewer media")

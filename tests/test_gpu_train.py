@@ -263,3 +263,48 @@ def test_gradient_norm_and_clipped_adam_step(hh, ctx):
     unclipped = p1 - lr * (m2u / (1 - b1 ** 2)) / (np.sqrt(v2u / (1 - b2 ** 2)) + eps)
     assert np.abs(unclipped - expect).max() > 1e-4
     assert np.abs(p1 - p0).max() > 0
+
+
+@pytest.mark.parametrize("nc", [8, 16, 32, 64])
+def test_implicit_green_gradient_matches_oracle(hh, ctx, nc):
+    # the Ghat gradient of the implicit layer (LDS transforms up to 2nc = 64,
+    # a scratch map per sample and channel at 2nc = 128: the 1024^2 network)
+    _say(f"implicit-layer Ghat gradient, nc = {nc}")
+    rng = np.random.default_rng(nc)
+    B, nk = 3, 32
+    z = _bf16(rng.standard_normal((B, nc, nc, 2 * nk)))
+    gy = _bf16(rng.standard_normal((B, nc, nc, 2 * nk)))
+    zd = torch.from_numpy(z).to("cuda:0", torch.bfloat16)
+    gd = torch.from_numpy(gy).to("cuda:0", torch.bfloat16)
+    out = hh.implicit_ggrad_test(ctx, zd, gd).cpu().numpy()
+    zc = z[..., 0::2] + 1j * z[..., 1::2]      # [B][nc][nc][nk]
+    gc = gy[..., 0::2] + 1j * gy[..., 1::2]
+    m = 2 * nc
+    zp = np.zeros((B, nk, m, m), dtype=np.complex128)
+    gp = np.zeros((B, nk, m, m), dtype=np.complex128)
+    zp[:, :, :nc, :nc] = zc.transpose(0, 3, 1, 2)
+    gp[:, :, :nc, :nc] = gc.transpose(0, 3, 1, 2)
+    ref = np.sum(np.conj(np.fft.fft2(zp)) * np.fft.fft2(gp), axis=0) / (m * m)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    _say(f"  max error {err:.2e} of max|ref|")
+    # FP32 radix-2 transforms of BF16 data, FP64 sum over the batch (measured 1.3-2.6e-7)
+    assert err <= 2e-6
+
+
+@pytest.mark.timeout(300)
+def test_training_step_at_1024(hh, ctx):
+    # the coarsest map of the 1024^2 network is 64 x 64 (transform size 128)
+    n, B = 1024, 2
+    _say("training step at 1024^2")
+    ks = _kappas(n, B, 150)
+    om = inputs.omega_for(n)
+    m = hh.Model(ctx, torch.from_numpy(np.stack(ks)), om, gamma0=0.05)
+    e, r = m.training_pairs(_dev(inputs.random_complex((B, n, n), 151)), [3, 5])
+    net = hh.Net(ctx, inputs.init_net_params(20))
+    losses = [net.train_step(m, r, e, lr=1e-3) for _ in range(4)]
+    g = hh.unflatten_params(net.get_grads())
+    _say(f"  losses {losses}")
+    assert np.isfinite(losses).all() and losses[-1] < losses[0]
+    assert np.isfinite(g["implicit_K"]).all() and np.abs(g["implicit_K"]).max() > 0
+    net.close()
+    m.close()
