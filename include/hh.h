@@ -220,6 +220,20 @@ hh_status hh_solve_batch(hh_ctx* ctx, int nmodels, hh_model* const* models, cons
 hh_status hh_model_set_coarse_group(hh_model* m, int R);
 int hh_model_coarse_group(const hh_model* m, int nact);
 
+/* Tile heights of the V-cycle's fused kernels (kernel 0: pre-relaxation,
+ * residual and restriction; 1: prolongation, correction and post-relaxation;
+ * mode 0: zero initial guess, 1: a stored fine guess, 2: the network's
+ * half-resolution output), autotuned per (kernel, mode, level size, batch)
+ * on the first launch outside graph capture (each height timed on the call's
+ * data, the fastest kept per device for the process).  Heights give
+ * bit-identical results.  down: 2, 4 or 8 coarse rows (mode 2), 4 or 8 (mode 1),
+ * 4, 8 or 16 (mode 0); up: 4, 8 or 16 fine rows (mode 2), 8, 16 or 32.
+ * hh_vcycle_tuned_height: the choice for a key, 0 if not tuned yet;
+ * hh_vcycle_force_height: use `height` for every launch of (kernel, mode), 0 to
+ * autotune again; HH_ERR_ARG for a height the kernel does not have. */
+int hh_vcycle_tuned_height(int device, int kernel, int mode, int n, int nrhs);
+hh_status hh_vcycle_force_height(int kernel, int mode, int height);
+
 /* rel_host[r] = ||b_r - A x_r|| / ||b_r|| in FP64 (A of eqs. 1-3 with the
  * model's coefficients) for solutions x_dev (c128 [nrhs][n][n], e.g. those
  * hh_solve returned) and right-hand sides b_dev (c64 [nrhs][n][n]); inst_host

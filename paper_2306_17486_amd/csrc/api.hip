@@ -431,6 +431,12 @@ int hh_model_coarse_group(const hh_model* m, int nact) {
     return m->coarse_R[b];
 }
 
+int hh_vcycle_tuned_height(int device, int kernel, int mode, int n, int nrhs) {
+    return vc_tuned_height(device, kernel, mode, n, nrhs);
+}
+
+hh_status hh_vcycle_force_height(int kernel, int mode, int height) { return vc_force_height(kernel, mode, height); }
+
 hh_status hh_profile_begin(hh_ctx* ctx, int cls) {
     HH_ARG(ctx, "null pointer");
     HH_ARG(cls >= 0 && cls <= HH_K_NUM_CLASSES, "kernel class");

@@ -323,6 +323,9 @@ hh_status coarse_check_err(hh_model* md);
 // the fixed scratch of hh_residual_norms_noalloc: look up its address on
 // `device` (once per device; krylov.hip)
 hh_status noalloc_init(int device);
+// V-cycle tile autotuner (mg.hip): the height chosen for a key (0: not tuned), forcing one
+int vc_tuned_height(int device, int kernel, int mode, int n, int nrhs);
+hh_status vc_force_height(int kernel, int mode, int height);
 // copy a host RHS -> slowness-model map to the device (api.hip)
 hh_status upload_inst_map(hh_model* m, Buf& buf, int nrhs, const int* inst_host, BatchMap* out);
 

@@ -9,6 +9,9 @@
 // so the level reads b once in each direction and writes only the coarse
 // right-hand side and the level's result.  The tiles are staged in LDS with the
 // halo the stencil chain needs (2 fine cells for down, 1 for up).
+#include <map>
+#include <mutex>
+
 #include "hh_internal.h"
 
 namespace hh {
@@ -97,7 +100,7 @@ __device__ __forceinline__ float2 x0_from_half(const float2* s_o, int cy0, int c
 constexpr int DN_TCX = 32, DN_TCY = 8;
 constexpr int DN_TCY2 = 4;  // with the network's guess: four arrays in LDS, half-height tiles
 
-template <int X0M>
+template <int X0M, int TCY>
 __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, size_t bstride,
                                                  const double* __restrict__ sig, int sig_stride,
                                                  const float2* __restrict__ x0, size_t x0stride,
@@ -108,8 +111,7 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
                                                  const float* __restrict__ x0s) {
     constexpr bool HAS_X0 = X0M != 0;
     constexpr int HALO = HAS_X0 ? 3 : 2;
-    constexpr int TCY = X0M == 2 ? DN_TCY2 : DN_TCY;  // coarse rows per tile
-    constexpr int PH = 2 * TCY + 2 * HALO - 1;  // fine rows 2I0-HALO .. 2I0+2TCY+HALO-2
+    constexpr int PH = 2 * TCY + 2 * HALO - 1;  // fine rows 2I0-HALO .. 2I0+2TCY+HALO-2 (TCY coarse rows per tile)
     constexpr int PW = 2 * DN_TCX + 2 * HALO - 1;
     __shared__ float2 s_b[PH][PW];   // b, later r
     __shared__ float2 s_x[PH][PW];   // x1 (relaxed)
@@ -244,7 +246,7 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
 constexpr int UP_TX = 64, UP_TY = 16;
 constexpr int UP_TY2 = 8;  // with the network's guess: the x0 patch in LDS too, half-height tiles
 
-template <int X1M>
+template <int X1M, int TY>
 __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, size_t bstride,
                                                const double* __restrict__ sig, int sig_stride,
                                                const float2* __restrict__ x1, const float2* __restrict__ ec,
@@ -253,8 +255,7 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
                                                int n, float inv_h2, float beta, float wj,
                                                const int* __restrict__ active, const float2* __restrict__ x0h,
                                                const float* __restrict__ x0s) {
-    constexpr int TY = X1M == 2 ? UP_TY2 : UP_TY;  // fine rows per tile
-    constexpr int PH = TY + 2, PW = UP_TX + 2;
+    constexpr int PH = TY + 2, PW = UP_TX + 2;  // TY fine rows per tile
     constexpr int CH = TY / 2 + 2, CW = UP_TX / 2 + 2;
     constexpr int XH = X1M == 2 ? PH + 2 : 1, XW = X1M == 2 ? PW + 2 : 1;
     __shared__ float2 s_b[PH][PW];
@@ -2321,6 +2322,192 @@ static hh_status coarse_pick(hh_model* md, int nact, const float2* bcs, float2* 
     return HH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tile heights of the V-cycle's fused kernels, autotuned like the convolution
+// tiles: for each (kernel, initial-guess mode, level size, batch) key, on its
+// first launch outside graph capture, every height runs twice on the call's own
+// data (HIP events, the second run counts; each run rewrites the same outputs)
+// and the fastest is kept per device for the process.  Defaults: 8 coarse rows
+// (4 with the network's guess, whose fourth LDS array halves them) for the down
+// kernel, 16 fine rows (8 with the guess) for the up kernel.
+// ---------------------------------------------------------------------------
+struct VcDownArgs {
+    const float2* b;
+    size_t bstride;
+    const double* sig;
+    int sig_stride;
+    const float2* x0;
+    size_t x0stride;
+    float2* x1out;
+    float2* bc;
+    const float2* coef;
+    const int* inst;
+    int n;
+    float inv_h2, beta, wj;
+    const int* active;
+    const float2* x0h;
+    const float* x0s;
+    int nrhs;
+};
+struct VcUpArgs {
+    const float2* b;
+    size_t bstride;
+    const double* sig;
+    int sig_stride;
+    const float2* x1;
+    const float2* ec;
+    float2* z;
+    size_t zstride;
+    const float2* coef;
+    const int* inst;
+    int n;
+    float inv_h2, beta, wj;
+    const int* active;
+    const float2* x0h;
+    const float* x0s;
+    int nrhs;
+};
+
+// tile heights per kernel (0 down, 1 up) and mode; the first is the default
+static int vc_heights(int kernel, int mode, int* h) {
+    if (kernel == 0) {
+        if (mode == 2) { h[0] = 4; h[1] = 2; h[2] = 8; return 3; }
+        if (mode == 1) { h[0] = 8; h[1] = 4; return 2; }
+        h[0] = 8; h[1] = 4; h[2] = 16; return 3;
+    }
+    if (mode == 2) { h[0] = 8; h[1] = 4; h[2] = 16; return 3; }
+    h[0] = 16; h[1] = 8; h[2] = 32; return 3;
+}
+
+template <int X0M, int TCY>
+static hh_status vc_down_t(hipStream_t st, const VcDownArgs& a) {
+    const int nc = a.n / 2;
+    dim3 grd((nc + DN_TCX - 1) / DN_TCX, (nc + TCY - 1) / TCY, a.nrhs);
+    hipLaunchKernelGGL((k_vc_down<X0M, TCY>), grd, dim3(256), 0, st, a.b, a.bstride, a.sig, a.sig_stride, a.x0,
+                       a.x0stride, a.x1out, a.bc, a.coef, a.inst, a.n, a.inv_h2, a.beta, a.wj, a.active, a.x0h,
+                       a.x0s);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+static hh_status launch_vc_down(hipStream_t st, int mode, int tcy, const VcDownArgs& a) {
+    if (mode == 2 && tcy == 4) return vc_down_t<2, 4>(st, a);
+    if (mode == 2 && tcy == 2) return vc_down_t<2, 2>(st, a);
+    if (mode == 2 && tcy == 8) return vc_down_t<2, 8>(st, a);
+    if (mode == 1 && tcy == 8) return vc_down_t<1, 8>(st, a);
+    if (mode == 1 && tcy == 4) return vc_down_t<1, 4>(st, a);
+    if (mode == 0 && tcy == 8) return vc_down_t<0, 8>(st, a);
+    if (mode == 0 && tcy == 4) return vc_down_t<0, 4>(st, a);
+    if (mode == 0 && tcy == 16) return vc_down_t<0, 16>(st, a);
+    set_error("no V-cycle down kernel for mode %d, %d rows", mode, tcy);
+    return HH_ERR_ARG;
+}
+
+template <int X1M, int TY>
+static hh_status vc_up_t(hipStream_t st, const VcUpArgs& a) {
+    dim3 grd((a.n + UP_TX - 1) / UP_TX, (a.n + TY - 1) / TY, a.nrhs);
+    hipLaunchKernelGGL((k_vc_up<X1M, TY>), grd, dim3(256), 0, st, a.b, a.bstride, a.sig, a.sig_stride, a.x1, a.ec,
+                       a.z, a.zstride, a.coef, a.inst, a.n, a.inv_h2, a.beta, a.wj, a.active, a.x0h, a.x0s);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+static hh_status launch_vc_up(hipStream_t st, int mode, int ty, const VcUpArgs& a) {
+    if (mode == 2 && ty == 8) return vc_up_t<2, 8>(st, a);
+    if (mode == 2 && ty == 4) return vc_up_t<2, 4>(st, a);
+    if (mode == 2 && ty == 16) return vc_up_t<2, 16>(st, a);
+    if (mode == 1 && ty == 16) return vc_up_t<1, 16>(st, a);
+    if (mode == 1 && ty == 8) return vc_up_t<1, 8>(st, a);
+    if (mode == 1 && ty == 32) return vc_up_t<1, 32>(st, a);
+    if (mode == 0 && ty == 16) return vc_up_t<0, 16>(st, a);
+    if (mode == 0 && ty == 8) return vc_up_t<0, 8>(st, a);
+    if (mode == 0 && ty == 32) return vc_up_t<0, 32>(st, a);
+    set_error("no V-cycle up kernel for mode %d, %d rows", mode, ty);
+    return HH_ERR_ARG;
+}
+
+namespace {
+std::mutex g_vc_mu;
+std::map<std::pair<int, uint64_t>, int> g_vc_tune;  // (device, key) -> height
+int g_vc_forced[2][3] = {{0, 0, 0}, {0, 0, 0}};     // forced height per kernel and mode (0: autotune)
+uint64_t vc_key(int kernel, int mode, int n, int nrhs) {
+    return ((uint64_t)kernel << 60) | ((uint64_t)mode << 56) | ((uint64_t)n << 24) | (uint64_t)nrhs;
+}
+}  // namespace
+
+template <class F>
+static hh_status vc_tuned_launch(hipStream_t st, int kernel, int mode, int n, int nrhs, F launch) {
+    int h[4];
+    const int nh = vc_heights(kernel, mode, h);
+    int dev = 0;
+    HH_HIP(hipGetDevice(&dev));
+    const uint64_t key = vc_key(kernel, mode, n, nrhs);
+    {
+        std::lock_guard<std::mutex> lk(g_vc_mu);
+        if (g_vc_forced[kernel][mode] > 0) return launch(g_vc_forced[kernel][mode]);
+        auto it = g_vc_tune.find({dev, key});
+        if (it != g_vc_tune.end()) return launch(it->second);
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HH_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return launch(h[0]);
+    hipEvent_t e0, e1;
+    HH_HIP(hipEventCreate(&e0));
+    HH_HIP(hipEventCreate(&e1));
+    int best = h[0];
+    float best_ms = 1e30f;
+    hh_status s = HH_OK;
+    for (int v = 0; v < nh && s == HH_OK; ++v) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && s == HH_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) s = HH_ERR_HIP;
+            if (s == HH_OK) s = launch(h[v]);
+            if (s == HH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                s = HH_ERR_HIP;
+        }
+        if (s == HH_OK && ms < best_ms) {
+            best_ms = ms;
+            best = h[v];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != HH_OK) {
+        if (!hh_last_error()[0]) set_error("V-cycle tile autotuning failed");
+        return s;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_vc_mu);
+        g_vc_tune[{dev, key}] = best;
+    }
+    return launch(best);
+}
+
+int vc_tuned_height(int device, int kernel, int mode, int n, int nrhs) {
+    std::lock_guard<std::mutex> lk(g_vc_mu);
+    auto it = g_vc_tune.find({device, vc_key(kernel, mode, n, nrhs)});
+    return it == g_vc_tune.end() ? 0 : it->second;
+}
+
+hh_status vc_force_height(int kernel, int mode, int height) {
+    if (kernel < 0 || kernel > 1 || mode < 0 || mode > 2) {
+        set_error("kernel is 0 (down) or 1 (up), mode 0..2");
+        return HH_ERR_ARG;
+    }
+    int h[4];
+    const int nh = vc_heights(kernel, mode, h);
+    bool ok = height == 0;
+    for (int i = 0; i < nh; ++i) ok = ok || h[i] == height;
+    if (!ok) {
+        set_error("%d rows is not a tile height of this kernel and mode", height);
+        return HH_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_vc_mu);
+    g_vc_forced[kernel][mode] = height;
+    return HH_OK;
+}
+
 hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, const float2* b, size_t bstride,
                                 const double* sig, int sig_stride, const float2* x0, size_t x0stride, float2* z,
                                 size_t zstride, void* work, const int* active, const float2* x0h,
@@ -2348,27 +2535,17 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         const Level& lv = md->lev[l];
         const int nc = lv.n / 2;
         const size_t nl = (size_t)lv.n * lv.n;
-        const int tcy = (l == 0 && x0h) ? DN_TCY2 : DN_TCY;
-        dim3 grd((nc + DN_TCX - 1) / DN_TCX, (nc + tcy - 1) / tcy, nrhs);
         const float2* bin = (l == 0) ? b : bl[l];
         const size_t bs = (l == 0) ? bstride : nl;
         const double* sg = (l == 0) ? sig : nullptr;
         const float ih2 = (float)(1.0 / (lv.h * lv.h));
         ProfScope ps(md->ctx, l == 0 ? HH_K_VC_DOWN : HH_K_VC_MID);
-        if (l == 0 && x0h) {
-            hipLaunchKernelGGL(k_vc_down<2>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr, (size_t)0,
-                               nullptr, bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, x0h,
-                               x0s);
-        } else if (l == 0 && x0) {
-            hipLaunchKernelGGL(k_vc_down<1>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x0, x0stride, x1,
-                               bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, nullptr,
-                               nullptr);
-        } else {
-            hipLaunchKernelGGL(k_vc_down<0>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
-                               (size_t)0, nullptr, bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta,
-                               wj, active, nullptr, nullptr);
-        }
-        HH_LAUNCH_CHECK();
+        const int mode = (l == 0 && x0h) ? 2 : ((l == 0 && x0) ? 1 : 0);
+        VcDownArgs da{bin, bs, sg, sig_stride, mode == 1 ? x0 : nullptr, mode == 1 ? x0stride : (size_t)0,
+                      mode == 1 ? x1 : nullptr, bl[l + 1], lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj,
+                      active, mode == 2 ? x0h : nullptr, mode == 2 ? x0s : nullptr, nrhs};
+        HH_TRY(vc_tuned_launch(st, 0, mode, lv.n, nrhs, [&](int t) { return launch_vc_down(st, mode, t, da); }));
+        (void)nc;
     }
     // coarsest exact solve
     {
@@ -2410,8 +2587,6 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
     for (int l = L - 2; l >= 0; --l) {
         const Level& lv = md->lev[l];
         const size_t nl = (size_t)lv.n * lv.n;
-        const int ty = (l == 0 && x0h) ? UP_TY2 : UP_TY;
-        dim3 grd((lv.n + UP_TX - 1) / UP_TX, (lv.n + ty - 1) / ty, nrhs);
         const float2* bin = (l == 0) ? b : bl[l];
         const size_t bs = (l == 0) ? bstride : nl;
         const double* sg = (l == 0) ? sig : nullptr;
@@ -2419,18 +2594,11 @@ hh_status launch_vcycle_strided(hh_model* md, int nrhs, const BatchMap& bm, cons
         const size_t os = (l == 0) ? zstride : nl;
         const float ih2 = (float)(1.0 / (lv.h * lv.h));
         ProfScope ps(md->ctx, l == 0 ? HH_K_VC_UP : HH_K_VC_MID);
-        if (l == 0 && x0h) {
-            hipLaunchKernelGGL(k_vc_up<2>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr, el[l + 1], out,
-                               os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, x0h, x0s);
-        } else if (l == 0 && x0) {
-            hipLaunchKernelGGL(k_vc_up<1>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, x1, el[l + 1], out,
-                               os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active, nullptr, nullptr);
-        } else {
-            hipLaunchKernelGGL(k_vc_up<0>, grd, dim3(256), 0, st, bin, bs, sg, sig_stride, nullptr,
-                               el[l + 1], out, os, lv.coef.as<float2>(), inst_dev, lv.n, ih2, beta, wj, active,
-                               nullptr, nullptr);
-        }
-        HH_LAUNCH_CHECK();
+        const int mode = (l == 0 && x0h) ? 2 : ((l == 0 && x0) ? 1 : 0);
+        VcUpArgs ua{bin, bs, sg, sig_stride, mode == 1 ? x1 : nullptr, el[l + 1], out, os, lv.coef.as<float2>(),
+                    inst_dev, lv.n, ih2, beta, wj, active, mode == 2 ? x0h : nullptr, mode == 2 ? x0s : nullptr,
+                    nrhs};
+        HH_TRY(vc_tuned_launch(st, 1, mode, lv.n, nrhs, [&](int t) { return launch_vc_up(st, mode, t, ua); }));
     }
     return HH_OK;
 }

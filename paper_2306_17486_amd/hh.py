@@ -113,6 +113,8 @@ hh_wgrad_test = _sig("hh_wgrad_test", _I, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P
 hh_gen_training_pairs = _sig("hh_gen_training_pairs", _I, _P, _P, _I, _P, _IP, _P, _P)
 hh_residual_norms = _sig("hh_residual_norms", _I, _P, _P, _I, _IP, _P, _P, _DP)
 hh_residual_norms_noalloc = _sig("hh_residual_norms_noalloc", _I, _P, _P, _I, _IP, _P, _P, _DP)
+hh_vcycle_tuned_height = _sig("hh_vcycle_tuned_height", _I, _I, _I, _I, _I, _I)
+hh_vcycle_force_height = _sig("hh_vcycle_force_height", _I, _I, _I, _I)
 hh_model_set_coarse_group = _sig("hh_model_set_coarse_group", _I, _P, _I)
 hh_model_coarse_group = _sig("hh_model_coarse_group", _I, _P, _I)
 hh_train_step = _sig("hh_train_step", _I, _P, _P, _P, _I, _P, _P, _D, _D, _DP, _DP)
@@ -582,3 +584,13 @@ def implicit_ggrad_test(ctx: Context, z_bf16: torch.Tensor, gy_bf16: torch.Tenso
     z_bf16, gy_bf16 = z_bf16.contiguous(), gy_bf16.contiguous()
     check(hh_implicit_ggrad_test(ctx.handle, ch // 2, nc, B, _ptr(z_bf16), _ptr(gy_bf16), _ptr(out)))
     return out
+
+
+def vcycle_tuned_height(device: int, kernel: int, mode: int, n: int, nrhs: int) -> int:
+    """The V-cycle tile height the autotuner chose for a key (0: not tuned yet)."""
+    return int(hh_vcycle_tuned_height(device, kernel, mode, n, nrhs))
+
+
+def vcycle_force_height(kernel: int, mode: int, height: int):
+    """Use one tile height for a V-cycle kernel and mode (0: autotune again)."""
+    check(hh_vcycle_force_height(kernel, mode, height))

@@ -122,3 +122,39 @@ def test_solution_error_vs_exact_1024(problem, precond):
     errs8 = _check(prob, B, X, x8, info8, 1e-8, precond)
     assert max(errs8) <= 1e-5, errs8
     assert all(e8 <= e / 10 for e8, e in zip(errs8, errs)), (errs8, errs)
+
+
+GOLDEN_STAGNANT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "oracle_1024_layered2000_mg_rhs1.json")
+
+
+@pytest.mark.timeout(300)
+def test_mg_only_hardest_source_no_worse_than_oracle():
+    # Source 1 is one of the six of the benchmark's 64 that MG-only FGMRES(10)
+    # leaves at the 10000-iteration cap when all 64 are solved together (the
+    # bench's configuration; residual plateau about 2e-2).  The FP64 oracle's
+    # own MG-only solve of it stagnates as well (tests/golden: 2.3e-2 after
+    # 12000 iterations), so the cap is the method's behaviour in this regime
+    # and not an artefact of single-precision Krylov storage.  In such a
+    # plateau rounding decides when (and whether) a restart escapes -- solved
+    # alone, source 1 converges on the GPU after 8665 iterations -- so the test
+    # asserts only that the GPU ends no worse than the oracle.
+    from paper_2306_17486_amd import hh
+    with open(GOLDEN_STAGNANT) as f:
+        g = json.load(f)["rhs"]["1"]["mg"]
+    k = inputs.layered_slowness(N, 2000)
+    om = inputs.omega_for(N, k)
+    ctx = hh.Context(0)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    b = torch.from_numpy(np.stack([inputs.point_source(N, 3000 + i) for i in range(64)])).to(
+        "cuda:0", torch.complex64)
+    _say("accuracy: MG-only on the benchmark's 64 sources, cap 10000")
+    x, info = m.solve(b, precond=hh.HH_PRECOND_MG, max_iters=10000, want_hist=False)
+    capped = [i for i in range(64) if not info["converged"][i]]
+    res = float(info["final_res"][1])
+    _say(f"accuracy: MG-only capped sources {capped}; source 1: gpu residual {res:.3e} after "
+         f"{int(info['iters'][1])} iterations, oracle {g['rel_residual']:.3e} after {g['iterations']}")
+    assert res <= 3 * g["rel_residual"]
+    assert len(capped) <= 8
+    m.close()
+    ctx.close()

@@ -268,3 +268,49 @@ def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
                                          (1, 2, 4, 8, 801, 802, 804, 808, 1601, 1602, 1604, 1608, 3201, 3202, 3204,
                                           3208))
     assert not bad, bad
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_vcycle_tile_heights_bit_identical(hh, ctx, mode):
+    # every tile height the V-cycle autotuner can pick computes each point the
+    # same way: bit-identical outputs (ragged size 100: partial tiles), and the
+    # default against the oracle
+    n = 100 if mode != 2 else 128
+    heights = {0: ([4, 8, 16], [8, 16, 32]), 1: ([4, 8], [8, 16, 32]), 2: ([2, 4, 8], [4, 8, 16])}[mode]
+    _say(f"vcycle tile heights, mode {mode}: down {heights[0]}, up {heights[1]}")
+    k = inputs.slowness(n, 13, "layered")
+    om = inputs.omega_for(n, k)
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    b = _dev(inputs.random_complex((3, n, n), 8))
+    net = None
+    if mode == 2:
+        net = hh.Net(ctx, inputs.init_net_params(21))
+        m.attach_net(net)
+        run = lambda: m.apply_cnn_precond(b)  # noqa: E731
+    else:
+        x0 = _dev(inputs.random_complex((3, n, n), 9) * 1e-4) if mode == 1 else None
+        run = lambda: m.apply_vcycle(b, x0)  # noqa: E731
+    ref = run()
+    try:
+        for hd in heights[0]:
+            for hu in heights[1]:
+                hh.vcycle_force_height(0, mode, hd)
+                hh.vcycle_force_height(1, mode, hu)
+                assert torch.equal(run(), ref), (hd, hu)
+    finally:
+        hh.vcycle_force_height(0, mode, 0)
+        hh.vcycle_force_height(1, mode, 0)
+    with pytest.raises(hh.HHError):
+        hh.vcycle_force_height(0, mode, 3)
+    # the first launch of each key was tuned
+    assert hh.vcycle_tuned_height(0, 0, mode, n, 3) in heights[0]
+    assert hh.vcycle_tuned_height(0, 1, mode, n, 3) in heights[1]
+    if mode == 0:
+        prob = H.Problem(k, om)
+        bb = b.cpu().numpy()
+        refo = np.stack([prob.hier.vcycle(bb[i]) for i in range(3)])
+        assert _rel(ref.cpu().numpy(), refo) <= 2e-5
+    if net is not None:
+        m.attach_net(None)
+        net.close()
+    m.close()
