@@ -1648,14 +1648,46 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ A, c
     }
 }
 
-// out[e] = scale * sum_b part[b][e]   (deterministic two-stage reduction)
-__global__ void k_reduce_part(const float* __restrict__ part, int nblk, int count, float* __restrict__ out,
-                              float scale) {
+// Deterministic reduction of per-block partial sums, out[e] = scale * sum_b part[b][e], in two
+// stages so that thousands of partial rows are read by many workgroups: stage one sums the rows
+// of each slice of `chunk` consecutive blocks into the slice's first row (in place: the thread
+// for column e of a slice is the only one that reads or writes that column of the slice), stage
+// two sums those first rows in slice order.
+__global__ void k_reduce_slices(float* __restrict__ part, int nblk, int count, int chunk) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const int b0 = blockIdx.y * chunk, b1 = min(b0 + chunk, nblk);
+    float acc = 0.f;
+    for (int b = b0; b < b1; ++b) acc += part[(size_t)b * count + e];
+    part[(size_t)b0 * count + e] = acc;
+}
+
+__global__ void k_reduce_part(const float* __restrict__ part, int nrow, int rstride, int count,
+                              float* __restrict__ out, float scale) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
     float acc = 0.f;
-    for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * count + e];
+    for (int b = 0; b < nrow; ++b) acc += part[(size_t)b * rstride * count + e];
     out[e] = acc * scale;
+}
+
+static hh_status reduce_partials(hipStream_t st, float* part, int nblk, int count, float* out, float scale) {
+    const int gx = (count + 255) / 256;
+    int chunk = nblk, nslice = 1;
+    if (nblk >= 64) {  // aim at about 2048 workgroups for the first stage
+        const int want = std::max(1, std::min(nblk / 8, (2048 + gx - 1) / gx));
+        chunk = (nblk + want - 1) / want;
+        nslice = (nblk + chunk - 1) / chunk;
+    }
+    if (nslice > 1) {
+        hipLaunchKernelGGL(k_reduce_slices, dim3(gx, nslice), dim3(256), 0, st, part, nblk, count, chunk);
+        HH_LAUNCH_CHECK();
+    }
+    // without the first stage every block's row is summed directly
+    hipLaunchKernelGGL(k_reduce_part, dim3(gx), dim3(256), 0, st, part, nslice > 1 ? nslice : nblk,
+                       nslice > 1 ? chunk : 1, count, out, scale);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
 }
 
 template <int CA, int CX, int MODE>
@@ -1669,9 +1701,7 @@ static hh_status launch_wgrad_t(hipStream_t st, const uint16_t* A, const uint16_
     hipLaunchKernelGGL((k_wgrad<CA, CX, MODE>), dim3(nblk), dim3(256), 0, st, A, X, part.as<float>(), Ho, Wo, Hi, Wi,
                        tx, ty);
     HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, part.as<float>(), nblk, count, out,
-                       1.f);
-    HH_LAUNCH_CHECK();
+    HH_TRY(reduce_partials(st, part.as<float>(), nblk, count, out, 1.f));
     return HH_OK;
 }
 
@@ -1724,8 +1754,7 @@ static hh_status launch_bgrad(hipStream_t st, int C, const uint16_t* A, size_t n
         return HH_ERR_ARG;
     }
     HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_reduce_part, dim3((C + 255) / 256), dim3(256), 0, st, part.as<float>(), nblk, C, out, 1.f);
-    HH_LAUNCH_CHECK();
+    HH_TRY(reduce_partials(st, part.as<float>(), nblk, C, out, 1.f));
     return HH_OK;
 }
 
@@ -2434,9 +2463,7 @@ static hh_status light_train_core(hh_ctx* ctx, hh_net* net, hh_model* md, TrainW
         hipLaunchKernelGGL(k_out_wgrad<16>, dim3(nb, B), dim3(256), 0, st, T.go.as<float2>(), o(LL_U1_C2),
                            T.part.as<float>(), m1, chunk);
         HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
-                           count, GR + net->L[LL_OUT].woff, 1.f);
-        HH_LAUNCH_CHECK();
+        HH_TRY(reduce_partials(st, T.part.as<float>(), B * nb, count, GR + net->L[LL_OUT].woff, 1.f));
         hipLaunchKernelGGL(k_out_dgrad<16>, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.go.as<float2>(),
                            P + net->L[LL_OUT].woff, nullptr, G(LL_U1_C2), m1);
         HH_LAUNCH_CHECK();
@@ -2534,9 +2561,7 @@ static hh_status light_train_core(hh_ctx* ctx, hh_net* net, hh_model* md, TrainW
     hipLaunchKernelGGL((k_in_wgrad<0, 16>), dim3(nb, B), dim3(256), 0, st, G(LL_S1_D), (const float2*)r_dev,
                        (size_t)n * n, A.scales.as<float>(), 0.f, T.part.as<float>(), n, chunk);
     HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb, count,
-                       GR + net->L[LL_S1_D].woff, 1.f);
-    HH_LAUNCH_CHECK();
+    HH_TRY(reduce_partials(st, T.part.as<float>(), B * nb, count, GR + net->L[LL_S1_D].woff, 1.f));
     // ---- encoder: the encodings' gradients are G(LL_S3_D), G(LL_S2_D), G(LL_S1_D)
     HH_TRY(cb_back(LL_ENC3_C2, G(LL_S3_D), o(LL_ENC3_C1), m3, G(LL_ENC3_C1)));
     HH_TRY(cb_back(LL_ENC3_C1, G(LL_ENC3_C1), o(LL_ENC3_D), m3, G(LL_ENC3_D)));
@@ -2549,9 +2574,7 @@ static hh_status light_train_core(hh_ctx* ctx, hh_net* net, hh_model* md, TrainW
     hipLaunchKernelGGL((k_in_wgrad<1, 16>), dim3(nb, B), dim3(256), 0, st, G(LL_ENC1_D), md->lev[0].coef.as<float2>(),
                        (size_t)n * n, nullptr, (float)(h * h), T.part.as<float>(), n, chunk);
     HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb, count,
-                       GR + net->L[LL_ENC1_D].woff, 1.f);
-    HH_LAUNCH_CHECK();
+    HH_TRY(reduce_partials(st, T.part.as<float>(), B * nb, count, GR + net->L[LL_ENC1_D].woff, 1.f));
     return finish_train_step(ctx, net, T, B, n, lr, max_grad_norm, loss_out, grad_norm_out);
 }
 
@@ -2617,9 +2640,8 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
         hipLaunchKernelGGL(k_out_wgrad<16>, dim3(nb, B), dim3(256), 0, st, T.go.as<float2>(), act(L_U1_C2),
                            T.part.as<float>(), m1, chunk);
         HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
-                           count, GR + net->L[L_OUT].woff, 1.f);  // weights and the 2 biases are contiguous
-        HH_LAUNCH_CHECK();
+        // the weights and the 2 biases are contiguous
+        HH_TRY(reduce_partials(st, T.part.as<float>(), B * nb, count, GR + net->L[L_OUT].woff, 1.f));
         hipLaunchKernelGGL(k_out_dgrad<16>, dim3((m1 * m1 + 255) / 256, B), dim3(256), 0, st, T.go.as<float2>(),
                            P + net->L[L_OUT].woff, act(L_U1_C2), G(L_U1_C2), m1);
         HH_LAUNCH_CHECK();
@@ -2692,9 +2714,7 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
         hipLaunchKernelGGL((k_in_wgrad<0, 16>), dim3(nb, B), dim3(256), 0, st, G(L_S1_D), (const float2*)r_dev,
                            (size_t)n * n, A.scales.as<float>(), 0.f, T.part.as<float>(), n, chunk);
         HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
-                           count, GR + net->L[L_S1_D].woff, 1.f);
-        HH_LAUNCH_CHECK();
+        HH_TRY(reduce_partials(st, T.part.as<float>(), B * nb, count, GR + net->L[L_S1_D].woff, 1.f));
     }
     // ---- encoder (the encodings' gradients are G(L_S1_D), G(L_S2_D), G(L_S3_D))
     {
@@ -2732,9 +2752,7 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
                            md->lev[0].coef.as<float2>(), (size_t)n * n, nullptr, (float)(h * h), T.part.as<float>(), n,
                            chunk);
         HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce_part, dim3((count + 255) / 256), dim3(256), 0, st, T.part.as<float>(), B * nb,
-                           count, GR + net->L[L_ENC1_D].woff, 1.f);
-        HH_LAUNCH_CHECK();
+        HH_TRY(reduce_partials(st, T.part.as<float>(), B * nb, count, GR + net->L[L_ENC1_D].woff, 1.f));
     }
     return finish_train_step(ctx, net, T, B, n, lr, max_grad_norm, loss_out, grad_norm_out);
 }

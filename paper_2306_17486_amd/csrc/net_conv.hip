@@ -486,10 +486,10 @@ __global__ void __launch_bounds__(256) k_conv_dma(ConvArgs a) {
 // four outputs instead of 36.  Every chunk is one tap x 32 input channels, so
 // the weights are the same packed chunks as the interleaved form's.
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT>
+template <int CIN, int COUT, int TR_ = 0>
 struct T2Cfg {
     static constexpr int TC = 32;                        // output tile columns
-    static constexpr int TR = CIN >= 64 ? 4 : 8;         // output tile rows (even)
+    static constexpr int TR = TR_ > 0 ? TR_ : (CIN >= 64 ? 4 : 8);  // output tile rows (even; TR_ = 0: default)
     static constexpr int NT = COUT / 16;                 // channel tiles
     static constexpr int WPT = 4 / NT;                   // waves per channel tile
     static constexpr int PB = TR * 2;                    // (row, column parity) blocks
@@ -503,9 +503,9 @@ struct T2Cfg {
     static_assert(PBW % 4 == 0, "row and column parity of a block fixed at compile time");
 };
 
-template <int CIN, int COUT>
+template <int CIN, int COUT, int TR_ = 0>
 __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
-    using C = T2Cfg<CIN, COUT>;
+    using C = T2Cfg<CIN, COUT, TR_>;
     __shared__ __attribute__((aligned(16))) uint16_t s_in[C::PH * C::PW * C::CP];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -667,15 +667,15 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
     }
 }
 
-template <int CIN, int COUT>
+template <int CIN, int COUT, int TR = 0>
 static hh_status launch_t2_t(hipStream_t st, ConvArgs a, int num_cus) {
-    using C = T2Cfg<CIN, COUT>;
+    using C = T2Cfg<CIN, COUT, TR>;
     a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
     a.tiles_y = (a.Hout + C::TR - 1) / C::TR;
     a.ntiles = a.B * a.tiles_x * a.tiles_y;
     if (a.ntiles == 0) return HH_OK;
     const int grid = std::min(a.ntiles, 8 * num_cus);
-    hipLaunchKernelGGL((k_conv_t2<CIN, COUT>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_conv_t2<CIN, COUT, TR>), dim3(grid), dim3(256), 0, st, a);
     HH_LAUNCH_CHECK();
     return HH_OK;
 }
@@ -683,8 +683,9 @@ static hh_status launch_t2_t(hipStream_t st, ConvArgs a, int num_cus) {
 // ---------------------------------------------------------------------------
 // Tile autotuner.  Every stride-1 and stride-2 layer shape has several
 // variants: the register-prefetch kernel (k_conv_mfma) and the direct-to-LDS
-// kernel (k_conv_dma) at several tile heights.  Variant code: TR for the
-// register kernel, 100 + TR for the direct-to-LDS one.  On the first launch of
+// kernel (k_conv_dma) at several tile heights; the transposed layers their one
+// kernel (k_conv_t2) at several heights.  Variant code: TR for the register and
+// transposed kernels, 100 + TR for the direct-to-LDS one.  On the first launch of
 // a (shape, output size, batch) key on a device, outside graph capture, every
 // variant runs twice on the call's own data (HIP events on the launch stream,
 // the second run counts) and the fastest is kept for the process; then the
@@ -731,8 +732,14 @@ static int conv_variants(int cin, int cout, int mode, int* codes) {
     static const int s16[] = {104, 102, 108, 4};
     static const int s32[] = {102, 104, 2, 4};
     static const int s64[] = {102, 101, 2};
+    static const int t16[] = {8, 16};
+    static const int t32[] = {4, 8, 16};
+    static const int t64[] = {4, 2, 8};
     const int* v = nullptr;
     int nv = 0;
+    if (mode == CM_T2 && cin == 32 && cout == 16) { v = t16; nv = 2; }
+    if (mode == CM_T2 && cin == 64 && cout == 32) { v = t32; nv = 3; }
+    if (mode == CM_T2 && cin == 64 && cout == 64) { v = t64; nv = 3; }
     if (mode == CM_S1 && cin == 16 && cout == 16) { v = v16; nv = 5; }
     if (mode == CM_S1 && cin == 32 && cout == 32) { v = v32; nv = 5; }
     if (mode == CM_S1 && cin == 64 && cout == 64) { v = v64; nv = 5; }
@@ -773,6 +780,14 @@ static hh_status launch_variant(hipStream_t st, int num_cus, int cin, int cout, 
     HH_V(64, 64, CM_S2, 102, (launch_dma<64, 64, CM_S2, 2>))
     HH_V(64, 64, CM_S2, 101, (launch_dma<64, 64, CM_S2, 1>))
     HH_V(64, 64, CM_S2, 2, (launch_reg<64, 64, CM_S2, 2>))
+    HH_V(32, 16, CM_T2, 8, (launch_t2_t<32, 16, 8>))
+    HH_V(32, 16, CM_T2, 16, (launch_t2_t<32, 16, 16>))
+    HH_V(64, 32, CM_T2, 8, (launch_t2_t<64, 32, 8>))
+    HH_V(64, 32, CM_T2, 4, (launch_t2_t<64, 32, 4>))
+    HH_V(64, 32, CM_T2, 16, (launch_t2_t<64, 32, 16>))
+    HH_V(64, 64, CM_T2, 4, (launch_t2_t<64, 64, 4>))
+    HH_V(64, 64, CM_T2, 2, (launch_t2_t<64, 64, 2>))
+    HH_V(64, 64, CM_T2, 8, (launch_t2_t<64, 64, 8>))
 #undef HH_V
     set_error("no convolution variant %d for cin=%d cout=%d mode=%d", code, cin, cout, mode);
     return HH_ERR_ARG;
@@ -819,13 +834,6 @@ static hh_status conv_tune(hipStream_t st, int num_cus, int cin, int cout, int m
 }
 
 hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, const ConvArgs& a, int variant) {
-    if (mode == CM_T2) {
-        if (cin == 64 && cout == 64) return launch_t2_t<64, 64>(st, a, num_cus);
-        if (cin == 64 && cout == 32) return launch_t2_t<64, 32>(st, a, num_cus);
-        if (cin == 32 && cout == 16) return launch_t2_t<32, 16>(st, a, num_cus);
-        set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
-        return HH_ERR_ARG;
-    }
     int codes[8];
     const int nv = conv_variants(cin, cout, mode, codes);
     if (nv == 0) {
@@ -885,7 +893,7 @@ hh_status conv_force_variant(int cin, int cout, int mode, int code) {
 
 int conv_variant_list(int cin, int cout, int mode, int* codes, int max) {
     int tmp[8];
-    const int nv = mode == CM_T2 ? 0 : conv_variants(cin, cout, mode, tmp);
+    const int nv = conv_variants(cin, cout, mode, tmp);
     for (int i = 0; codes && i < nv && i < max; ++i) codes[i] = tmp[i];
     return nv;
 }

@@ -78,14 +78,18 @@ class KappaPrefetch:
     """Draws the next batches of slowness models on a host thread while the GPU
     trains on the current one."""
 
-    def __init__(self, plan, batch: int, depth: int = 3, step0: int = 0):
+    def __init__(self, plan, batch: int, depth: int = 3, step0: int = 0, fresh=None):
         self.q: queue.Queue = queue.Queue(maxsize=depth)
         self.plan, self.batch, self.step0 = plan, batch, step0
+        self.fresh = fresh if fresh is not None else [True] * len(plan)
         self.t = threading.Thread(target=self._run, daemon=True)
         self.t.start()
 
     def _run(self):
         for step, n in enumerate(self.plan):
+            if not self.fresh[step]:  # the previous step's media are used again
+                self.q.put((step, n, None))
+                continue
             seeds = TRAIN_SEED0 + (self.step0 + step) * self.batch + np.arange(self.batch)
             self.q.put((step, n, kappa_batch(n, seeds)))
 
@@ -132,12 +136,17 @@ class GradClip:
 
 
 def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: int, nval: int, seed: int,
-          sizes=(128, 256), clip: float = 2.0, step0: int = 0):
+          sizes=(128, 256), clip: float = 2.0, step0: int = 0, reuse: int = 1, reuse_from: int = 1024):
     """`steps` steps; with `step0` > 0 (a continued run) the training stream's
-    media are those of steps step0 .. step0 + steps - 1, so no sample repeats."""
+    media are those of steps step0 .. step0 + steps - 1, so no sample repeats.
+    At grid sizes >= `reuse_from` one batch of media (and its factorised
+    coarsest operators) serves `reuse` consecutive steps of a block, each with
+    fresh random vectors: setting up 32 media at 1024^2 costs several training
+    steps."""
     dev = f"cuda:{ctx.device}"
     plan_blocks = schedule(steps, block, sizes)
     plan = [plan_blocks[s // block] for s in range(steps)]
+    fresh = [plan[s] < reuse_from or (s % block) % max(1, reuse) == 0 for s in range(steps)]
     omegas = {n: inputs.omega_for(n) for n in sizes}
     _log(f"[train] {steps} steps, batch {batch}, blocks of {block}: " +
          ", ".join(f"{n}^2 x {plan.count(n)}" for n in sizes))
@@ -160,20 +169,23 @@ def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: in
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
     rng = np.random.default_rng(seed)
-    pre = KappaPrefetch(plan, batch, step0=step0)
+    pre = KappaPrefetch(plan, batch, step0=step0, fresh=fresh)
     t0 = time.time()
     run = {n: [] for n in sizes}
+    m = None
     for step in range(steps):
         s, n, kap = pre.get()
         assert s == step and n == plan[step]
-        m = hh.Model(ctx, torch.from_numpy(kap), omegas[n], gamma0=GAMMA0)
+        if kap is not None:
+            if m is not None:
+                m.close()
+            m = hh.Model(ctx, torch.from_numpy(kap), omegas[n], gamma0=GAMMA0)
         x = torch.view_as_complex(torch.randn((batch, n, n, 2), generator=gen, device=dev))
         e, r = m.training_pairs(x, rng.integers(2, 9, batch).tolist())
         cur_lr = learning_rate(step, steps, lr)
         thr = clipper.threshold()
         loss = net.train_step(m, r, e, lr=cur_lr, max_grad_norm=thr)
         clipper.record(net.last_grad_norm)
-        m.close()
         if not np.isfinite(loss):
             raise RuntimeError(f"training loss is not finite at step {step}")
         hist["step"].append(step)
@@ -190,6 +202,8 @@ def train(ctx, net, steps: int, batch: int, lr: float, block: int, val_every: in
                  f"clipped {sum(hist['clipped'][-50:])}  {el:.0f} s ({el / (step + 1) * 1e3:.0f} ms/step)")
         if (step + 1) % val_every == 0 or step + 1 == steps:
             do_val(step + 1)
+    if m is not None:
+        m.close()
     hist["seconds"] = time.time() - t0
     hist["steps_per_s"] = steps / hist["seconds"]
     return hist
@@ -250,6 +264,9 @@ def main(argv=None):
     ap.add_argument("--gen-seed", type=int, default=None, help="seed of the random vectors (default: --seed)")
     ap.add_argument("--explicit", action="store_true",
                     help="train the explicit U-Net (the coarsest level convolves with the kernels, Sec. 5.2)")
+    ap.add_argument("--reuse", type=int, default=1,
+                    help="steps that share one batch of media at sizes >= --reuse-from")
+    ap.add_argument("--reuse-from", type=int, default=1024)
     ap.add_argument("--light", action="store_true",
                     help="train the lightweight network (inverted bottlenecks, batch norm, softplus; Sec. 4.4)")
     args = ap.parse_args(argv)
@@ -264,7 +281,7 @@ def main(argv=None):
         sys.exit(f"training sizes must be among {sorted(SIZE_WEIGHT)}")
     seed = args.seed + args.step0 if args.gen_seed is None else args.gen_seed
     hist = train(ctx, net, args.steps, args.batch, args.lr, args.block, args.val_every, args.nval, seed,
-                 sizes=sizes, clip=args.clip, step0=args.step0)
+                 sizes=sizes, clip=args.clip, step0=args.step0, reuse=args.reuse, reuse_from=args.reuse_from)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
     _log(f"[train] saved {args.out} after {hist['seconds']:.0f} s ({hist['steps_per_s']:.2f} steps/s)")
