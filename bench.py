@@ -615,8 +615,12 @@ def main():
                          "256^2 and 512^2")
     ap.add_argument("--net", choices=sorted(NET_FILES), default="unet",
                     help="the network of CNN+MG: the U-Net (default) or the lightweight network")
+    ap.add_argument("--net-file", type=str, default="",
+                    help="a network file to use instead of the shipped one of --net")
     ap.add_argument("--batch-max-iters", type=int, default=2000)
     a = ap.parse_args()
+    if a.net_file:
+        NET_FILES[a.net] = os.path.abspath(a.net_file)
     if a.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {a.gpus} is not supported "
               f"(the right-hand sides shard across GPUs with no communication, see DESIGN.md)", file=sys.stderr)

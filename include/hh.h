@@ -410,6 +410,19 @@ hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin,
  *   again); HH_ERR_ARG for a code the shape does not have.
  * hh_conv_test's `variant` (0: the autotuned choice) selects one variant. */
 int hh_conv_variants(int cin, int cout, int mode, int* codes, int max);
+/* Fused layer pair (mode 3 of the autotuner calls, cin = cout = 16): two
+ * stride-1 3x3 convolutions with ReLU, y = relu(conv(w2, relu(conv(w1, x) + b1))
+ * + b2), as the network's 16-channel levels apply them at inference (Sec. 5.3).
+ * Variants: 16 and 8 (rows per tile of the fused kernel, the first layer's
+ * output kept in LDS) and 1 (the two layers launched separately through mid).
+ * All three give bit-identical y.
+ * hh_conv_pair_test: x BF16 NHWC [B][H][W][16], w1/w2 FP32 (16, 16, 3, 3),
+ *   b1/b2 FP32 [16] (may be NULL), mid and y BF16 NHWC [B][H][W][16] (mid is
+ *   written by variant 1 only), active_host as for hh_conv_test, variant 0:
+ *   the autotuned choice.  Synchronises the stream. */
+hh_status hh_conv_pair_test(hh_ctx* ctx, int B, int H, int W, const void* x_dev, const float* w1_dev,
+                            const float* b1_dev, const float* w2_dev, const float* b2_dev, void* mid_dev, void* y_dev,
+                            const int* active_host, int variant);
 int hh_conv_tuned_variant(int device, int cin, int cout, int mode, int Hout, int Wout, int B);
 hh_status hh_conv_force_variant(int cin, int cout, int mode, int code);
 hh_status hh_implicit_test(hh_net* net, int nc, int B, const void* x_dev, void* y_dev, int adjoint);

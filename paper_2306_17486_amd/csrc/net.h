@@ -7,7 +7,8 @@
 
 namespace hh {
 
-enum { CM_S1 = 0, CM_S2 = 1, CM_T2 = 2 };  // stride 1, stride 2, transposed stride 2
+// stride 1, stride 2, transposed stride 2; two stride-1 layers with ReLU fused (16 channels, inference)
+enum { CM_S1 = 0, CM_S2 = 1, CM_T2 = 2, CM_PAIR = 3 };
 enum { ACT_NONE = 0, ACT_RELU = 1, ACT_SOFTPLUS = 2 };
 
 // softplus log(1 + e^v) without overflow, and its derivative (the logistic function)
@@ -32,6 +33,11 @@ struct ConvArgs {
     // low part wp_lo, output channels 2..15 zero): FP32 (re, im) output [B][H][W]
     const uint16_t* wp_lo;
     float2* yproj;
+    // fused pair (CM_PAIR): the second layer's packed weights and bias (wp, bias are
+    // the first layer's), and the intermediate tensor that the unfused variant writes
+    const uint16_t* wp2;
+    const float* bias2;
+    uint16_t* ymid;
 };
 // variant 0: the autotuned choice for this (shape, output size, batch) key (tuned
 // on the first launch outside graph capture); otherwise a variant code of the shape

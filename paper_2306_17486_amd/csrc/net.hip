@@ -1399,11 +1399,11 @@ hh_status net_prepare_model(hh_model* md) {
 static hh_status net_forward_chunk(hh_net* net, int n, NetActs& A, int b0, int Bc, const float* in_scale0,
                                    const float* out_scale0, const int* smap0, const uint16_t* E1, const uint16_t* E2,
                                    const uint16_t* E3, const float2* Gbr, const float2* v0, size_t vstride,
-                                   float2* x00, const int* active0);
+                                   float2* x00, const int* active0, bool keep);
 
 hh_status net_forward_core(hh_net* net, int n, double h, NetActs& A, int B, const int* smap, const uint16_t* E1,
                            const uint16_t* E2, const uint16_t* E3, const float2* Gbr, const float2* v, size_t vstride,
-                           const double* sig, int sig_stride, float2* x0, const int* active) {
+                           const double* sig, int sig_stride, float2* x0, const int* active, bool keep) {
     hipStream_t st = net->ctx->stream;
     HH_TRY(A.ensure(net, B, n));
     float* in_scale = A.scales.as<float>();
@@ -1421,14 +1421,15 @@ hh_status net_forward_core(hh_net* net, int n, double h, NetActs& A, int B, cons
     // The whole batch in every launch.  (Running it through the network in
     // chunks of 8 or 16 samples, so that a layer's output could still sit in
     // the last-level cache for the next layer, measured 16% and 7% slower.)
-    return net_forward_chunk(net, n, A, 0, B, in_scale, out_scale, smap, E1, E2, E3, Gbr, v, vstride, x0, active);
+    return net_forward_chunk(net, n, A, 0, B, in_scale, out_scale, smap, E1, E2, E3, Gbr, v, vstride, x0, active,
+                             keep);
 }
 
 // samples b0 .. b0 + Bc - 1 of net_forward_core (scales already computed)
 static hh_status net_forward_chunk(hh_net* net, int n, NetActs& A, int b0, int Bc, const float* in_scale0,
                                    const float* out_scale0, const int* smap0, const uint16_t* E1, const uint16_t* E2,
                                    const uint16_t* E3, const float2* Gbr, const float2* v0, size_t vstride,
-                                   float2* x00, const int* active0) {
+                                   float2* x00, const int* active0, bool keep) {
     hipStream_t st = net->ctx->stream;
     const float* P = net->params.as<float>();
     const int m1 = n / 2, m2 = n / 4, m3 = n / 8, m4 = coarsest_of(n), s4 = coarse_stride_of(n);
@@ -1447,6 +1448,28 @@ static hh_status net_forward_chunk(hh_net* net, int n, NetActs& A, int b0, int B
     auto act = [&](int l) { return A.a[l].as<uint16_t>() + (size_t)b0 * A.sample_elems(net, l); };
     uint16_t* imp = A.imp.as<uint16_t>() + (size_t)b0 * m4 * m4 * net->ch[3];
     float2* impw = A.impw.ptr ? A.impw.as<float2>() + (size_t)b0 * net->nk * m4 * (2 * m4) : nullptr;
+    // layers l and l + 1 (stride 1, ReLU): fused for inference when both have 16
+    // channels; the training pass keeps the intermediate output for its backward
+    auto conv_pair = [&](int l, const uint16_t* x, uint16_t* mid, uint16_t* y, int m) -> hh_status {
+        const LayerInfo &L1 = net->L[l], &L2 = net->L[l + 1];
+        if (keep || L1.cin != 16 || L1.cout != 16 || L2.cout != 16) {
+            HH_TRY(conv_layer(net, l, CM_S1, x, B, m, m, mid, m, m, nullptr, nullptr, true, active));
+            return conv_layer(net, l + 1, CM_S1, mid, B, m, m, y, m, m, nullptr, nullptr, true, active);
+        }
+        ConvArgs a{};
+        a.x = x;
+        a.y = y;
+        a.ymid = mid;
+        a.wp = net->packed.as<uint16_t>() + net->pk_fwd[l];
+        a.bias = P + L1.boff;
+        a.wp2 = net->packed.as<uint16_t>() + net->pk_fwd[l + 1];
+        a.bias2 = P + L2.boff;
+        a.act = ACT_RELU;
+        a.B = B;
+        a.Hin = a.Win = a.Hout = a.Wout = m;
+        a.active = active;
+        return launch_conv(st, net->ctx->num_cus, 16, 16, CM_PAIR, a);
+    };
     {
         ProfScope ps(net->ctx, HH_K_CONV);
         hipLaunchKernelGGL((k_conv_in_mfma<0>), conv_in_grid(n, B), dim3(256), 0, st, v, vstride, in_scale,
@@ -1457,8 +1480,7 @@ static hh_status net_forward_chunk(hh_net* net, int n, NetActs& A, int b0, int B
     {
         ProfScope ps(net->ctx, HH_K_CONV);
         // level 1
-        HH_TRY(conv_layer(net, L_S1_C1, CM_S1, act(L_S1_D), B, m1, m1, act(L_S1_C1), m1, m1, nullptr, nullptr, true, active));
-        HH_TRY(conv_layer(net, L_S1_C2, CM_S1, act(L_S1_C1), B, m1, m1, act(L_S1_C2), m1, m1, nullptr, nullptr, true, active));
+        HH_TRY(conv_pair(L_S1_C1, act(L_S1_D), act(L_S1_C1), act(L_S1_C2), m1));
         // level 2
         HH_TRY(conv_layer(net, L_S2_D, CM_S2, act(L_S1_C2), B, m1, m1, act(L_S2_D), m2, m2, E2, smap, false, active));
         HH_TRY(conv_layer(net, L_S2_C1, CM_S1, act(L_S2_D), B, m2, m2, act(L_S2_C1), m2, m2, nullptr, nullptr, true, active));
@@ -1490,8 +1512,7 @@ static hh_status net_forward_chunk(hh_net* net, int n, NetActs& A, int b0, int B
         HH_TRY(conv_layer(net, L_U2_C1, CM_S1, act(L_U2_T), B, m2, m2, act(L_U2_C1), m2, m2, nullptr, nullptr, true, active));
         HH_TRY(conv_layer(net, L_U2_C2, CM_S1, act(L_U2_C1), B, m2, m2, act(L_U2_C2), m2, m2, nullptr, nullptr, true, active));
         HH_TRY(conv_layer(net, L_U1_T, CM_T2, act(L_U2_C2), B, m2, m2, act(L_U1_T), m1, m1, act(L_S1_C2), nullptr, false, active));
-        HH_TRY(conv_layer(net, L_U1_C1, CM_S1, act(L_U1_T), B, m1, m1, act(L_U1_C1), m1, m1, nullptr, nullptr, true, active));
-        HH_TRY(conv_layer(net, L_U1_C2, CM_S1, act(L_U1_C1), B, m1, m1, act(L_U1_C2), m1, m1, nullptr, nullptr, true, active));
+        HH_TRY(conv_pair(L_U1_C1, act(L_U1_T), act(L_U1_C1), act(L_U1_C2), m1));
     }
     {
         ProfScope ps(net->ctx, HH_K_NET_OTHER);
@@ -1522,7 +1543,7 @@ hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const 
     const int* smap = md->ninst > 1 ? bm.inst : A.zeros.as<int>();
     return net_forward_core(net, md->lev[0].n, md->lev[0].h, A, B, smap, nc->enc[L_ENC1_C2].as<uint16_t>(),
                             nc->enc[L_ENC2_C2].as<uint16_t>(), nc->enc[L_ENC3_C2].as<uint16_t>(),
-                            nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active);
+                            nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active, false);
 }
 
 // either network's forward pass on B vectors of model md (encodings and Ghat from
@@ -2613,7 +2634,7 @@ static hh_status train_core(hh_ctx* ctx, hh_net* net, hh_model* md, int B, const
     const int* smap = md->ninst == 1 ? A.zeros.as<int>() : nullptr;  // sample b uses slowness model b
     HH_TRY(net_forward_core(net, n, h, A, B, smap, T.enc[L_ENC1_C2].as<uint16_t>(), T.enc[L_ENC2_C2].as<uint16_t>(),
                             T.enc[L_ENC3_C2].as<uint16_t>(), T.Gbr.as<float2>(), (const float2*)r_dev, (size_t)n * n,
-                            nullptr, 0, nullptr, nullptr));
+                            nullptr, 0, nullptr, nullptr, true));
     HH_TRY(ensure_grads(net, T, B, n));
     float* out_scale = A.scales.as<float>() + B;
     // ---- loss and gradient at the projection layer
@@ -3089,6 +3110,39 @@ hh_status hh_conv_test(hh_ctx* ctx, int cin, int cout, int mode, int B, int Hin,
     a.Wout = mode == CM_S2 ? Win / 2 : (mode == CM_T2 ? 2 * Win : Win);
     a.active = actb.as<int>();
     HH_TRY(launch_conv(ctx->stream, ctx->num_cus, cin, cout, mode, a, variant));
+    HH_HIP(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+}
+
+hh_status hh_conv_pair_test(hh_ctx* ctx, int B, int H, int W, const void* x_dev, const float* w1_dev,
+                            const float* b1_dev, const float* w2_dev, const float* b2_dev, void* mid_dev, void* y_dev,
+                            const int* active_host, int variant) {
+    HH_ARG(ctx && x_dev && w1_dev && w2_dev && mid_dev && y_dev, "null pointer");
+    HH_ARG(B >= 1 && H >= 1 && W >= 1, "sizes");
+    HH_HIP(hipSetDevice(ctx->device));
+    const size_t pe = packed_weight_elems(16, 16);
+    Buf wp, actb;
+    HH_TRY(wp.ensure(ctx, 2 * pe * sizeof(uint16_t) + 256));
+    HH_TRY(pack_weights(ctx->stream, w1_dev, wp.as<uint16_t>(), 16, 16, false));
+    HH_TRY(pack_weights(ctx->stream, w2_dev, wp.as<uint16_t>() + pe, 16, 16, false));
+    if (active_host) {
+        HH_TRY(actb.ensure(ctx, (size_t)B * sizeof(int)));
+        HH_HIP(hipMemcpyAsync(actb.ptr, active_host, (size_t)B * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    }
+    ConvArgs a{};
+    a.x = (const uint16_t*)x_dev;
+    a.y = (uint16_t*)y_dev;
+    a.ymid = (uint16_t*)mid_dev;
+    a.wp = wp.as<uint16_t>();
+    a.bias = b1_dev;
+    a.wp2 = wp.as<uint16_t>() + pe;
+    a.bias2 = b2_dev;
+    a.act = ACT_RELU;
+    a.B = B;
+    a.Hin = a.Hout = H;
+    a.Win = a.Wout = W;
+    a.active = actb.as<int>();
+    HH_TRY(launch_conv(ctx->stream, ctx->num_cus, 16, 16, CM_PAIR, a, variant));
     HH_HIP(hipStreamSynchronize(ctx->stream));
     return HH_OK;
 }

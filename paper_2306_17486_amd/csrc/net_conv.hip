@@ -681,6 +681,201 @@ static hh_status launch_t2_t(hipStream_t st, ConvArgs a, int num_cus) {
 }
 
 // ---------------------------------------------------------------------------
+// Two stride-1 16-channel layers with ReLU, fused (inference):
+//   y = relu(conv(W2, relu(conv(W1, x) + b1)) + b2).
+// Per TR x 32 output tile the (TR + 4) x 36 input patch is staged in LDS; the
+// first layer is evaluated over the tile and a one-pixel ring around it,
+// (TR + 2) x 34 pixels, into LDS as BF16 (zero outside the image, which is the
+// second layer's zero padding); the second layer reads it from there, so the
+// intermediate tensor never goes through HBM.  The first layer's 16-pixel
+// blocks run over the flattened ring region (a block may wrap a row end).
+// Every output takes the same k chunks in the same order as k_conv_mfma and
+// the intermediate is rounded to BF16 as that kernel stores it, so the result
+// is bit-identical to the two layers launched separately.
+// ---------------------------------------------------------------------------
+template <int TR>
+struct PairCfg {
+    static constexpr int C = 16, TC = 32, CP = C + 8;          // channels, tile columns, LDS pitch (bf16)
+    static constexpr int MH = TR + 2, MW = TC + 2;             // ring region (first layer's outputs)
+    static constexpr int IH = TR + 4, IW = TC + 4;             // input patch
+    static constexpr int P1 = MH * MW, NB1 = (P1 + 15) / 16;   // ring pixels, their 16-pixel blocks
+    static constexpr int NB2 = TR * TC / 16;                   // output blocks
+    static constexpr int NCH = (9 * C + 31) / 32;              // k chunks per layer
+    static constexpr int J1 = (NB1 + 3) / 4;                   // first-layer blocks per wave (at most)
+    static constexpr int G1 = 2;                               // of which accumulated together
+    static constexpr int J2 = NB2 / 4;                         // output blocks per wave
+    static constexpr int G2 = 2;                               // of which accumulated together
+    static constexpr int NE = IH * IW * (C / 8);               // 16-byte vectors of the patch
+    static constexpr int NPF = (NE + 255) / 256;               // gathers per thread
+    static_assert(NB2 % 4 == 0 && J2 % G2 == 0, "output blocks split evenly over the four waves");
+};
+
+template <int TR>
+__global__ void __launch_bounds__(256, 4) k_conv_pair16(ConvArgs a) {
+    using C = PairCfg<TR>;
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[C::IH * C::IW * C::CP];
+    __shared__ __attribute__((aligned(16))) uint16_t s_mid[C::P1 * C::CP];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lp = lane & 15, lg = lane >> 4;
+
+    // both layers' weights stay in VGPRs for all tiles
+    bf16x8 w1[C::NCH], w2[C::NCH];
+    {
+        const uint4* p1 = reinterpret_cast<const uint4*>(a.wp);
+        const uint4* p2 = reinterpret_cast<const uint4*>(a.wp2);
+#pragma unroll
+        for (int ch = 0; ch < C::NCH; ++ch) {
+            uint4 v1 = p1[((size_t)ch * 16 + lp) * 4 + lg];
+            uint4 v2 = p2[((size_t)ch * 16 + lp) * 4 + lg];
+            w1[ch] = *reinterpret_cast<bf16x8*>(&v1);
+            w2[ch] = *reinterpret_cast<bf16x8*>(&v2);
+        }
+    }
+    float b1[4], b2[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        b1[i] = a.bias ? a.bias[4 * lg + i] : 0.f;
+        b2[i] = a.bias2 ? a.bias2[4 * lg + i] : 0.f;
+    }
+
+    const int per_b = a.tiles_x * a.tiles_y;
+    // input vector e of a tile's patch (zero outside the image)
+    auto elem = [&](int tile, int e) -> uint4 {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const int v = e & 1, pix = e >> 1;
+        const int py = pix / C::IW, px = pix - py * C::IW;
+        const int iy = ty * TR - 2 + py, ix = tx * C::TC - 2 + px;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (e < C::NE && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win)
+            val = *reinterpret_cast<const uint4*>(a.x + (((size_t)b * a.Hin + iy) * a.Win + ix) * 16 + 8 * v);
+        return val;
+    };
+    auto next_active = [&](int t) {
+        while (t < a.ntiles && a.active && !a.active[t / per_b]) t += gridDim.x;
+        return t;
+    };
+    // B operand of chunk ch for a pixel whose 3x3 window starts at (sy, sx) of a
+    // region of width W held in buf (tap 9 of the last chunk is zero)
+    auto bfrag = [&](const uint16_t* buf, int W, int sy, int sx, int ch) -> bf16x8 {
+        const int k0 = ch * 32 + 8 * lg;
+        const int tap = k0 >> 4, ci = k0 & 15;
+        uint4 raw = make_uint4(0, 0, 0, 0);
+        if (tap < 9) {
+            const int ky = tap / 3, kx = tap - 3 * ky;
+            raw = *reinterpret_cast<const uint4*>(&buf[((sy + ky) * W + sx + kx) * C::CP + ci]);
+        }
+        return *reinterpret_cast<bf16x8*>(&raw);
+    };
+
+    uint4 pf[C::NPF];
+    int tile = next_active(blockIdx.x);
+    if (tile < a.ntiles) {
+#pragma unroll
+        for (int j = 0; j < C::NPF; ++j) pf[j] = elem(tile, tid + j * 256);
+    }
+    while (tile < a.ntiles) {
+        const int b = tile / per_b;
+        const int rem = tile - b * per_b;
+        const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+        const int y0 = ty * TR, x0 = tx * C::TC;
+        const int nxt = next_active(tile + gridDim.x);
+        __syncthreads();  // the previous tile's readers of s_in and s_mid are done
+#pragma unroll
+        for (int j = 0; j < C::NPF; ++j) {
+            const int e = tid + j * 256;
+            if (e < C::NE) *reinterpret_cast<uint4*>(&s_in[(e >> 1) * C::CP + 8 * (e & 1)]) = pf[j];
+        }
+        __syncthreads();
+        if (nxt < a.ntiles) {  // the next tile's patch is in flight during both layers
+#pragma unroll
+            for (int j = 0; j < C::NPF; ++j) pf[j] = elem(nxt, tid + j * 256);
+        }
+        // ---- first layer over the ring region: blocks wave, wave + 4, ... ----
+#pragma unroll 1
+        for (int g0 = 0; g0 < C::J1; g0 += C::G1) {
+            f32x4 acc[C::G1];
+#pragma unroll
+            for (int q = 0; q < C::G1; ++q) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ch = 0; ch < C::NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < C::G1; ++q) {
+                    const int blk = wave + 4 * (g0 + q);
+                    if (g0 + q >= C::J1 || blk >= C::NB1) continue;  // uniform per wave
+                    const int p = min(blk * 16 + lp, C::P1 - 1);     // lanes past the region: discarded
+                    const int my = p / C::MW, mx = p - my * C::MW;
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[ch], bfrag(s_in, C::IW, my, mx, ch), acc[q],
+                                                                     0, 0, 0);
+                }
+#pragma unroll
+            for (int q = 0; q < C::G1; ++q) {
+                const int blk = wave + 4 * (g0 + q);
+                if (g0 + q >= C::J1 || blk >= C::NB1) continue;
+                const int p = blk * 16 + lp;
+                if (p >= C::P1) continue;
+                const int my = p / C::MW, mx = p - my * C::MW;
+                const int gy = y0 - 1 + my, gx = x0 - 1 + mx;
+                const bool in = gy >= 0 && gy < a.Hin && gx >= 0 && gx < a.Win;
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = in ? fmaxf(acc[q][i] + b1[i], 0.f) : 0.f;
+                uint2 o2;
+                o2.x = f2bf2(v[0], v[1]);
+                o2.y = f2bf2(v[2], v[3]);
+                *reinterpret_cast<uint2*>(&s_mid[p * C::CP + 4 * lg]) = o2;
+            }
+        }
+        __syncthreads();  // s_mid complete
+        // ---- second layer over the tile: blocks wave * J2 .. + J2 - 1, G2 at a time ----
+#pragma unroll 1
+        for (int g0 = 0; g0 < C::J2; g0 += C::G2) {
+            f32x4 acc2[C::G2];
+#pragma unroll
+            for (int q = 0; q < C::G2; ++q) acc2[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ch = 0; ch < C::NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < C::G2; ++q) {
+                    const int pbk = wave * C::J2 + g0 + q;
+                    const int ry = pbk >> 1, rx = (pbk & 1) * 16 + lp;
+                    acc2[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[ch], bfrag(s_mid, C::MW, ry, rx, ch),
+                                                                      acc2[q], 0, 0, 0);
+                }
+#pragma unroll
+            for (int q = 0; q < C::G2; ++q) {
+                const int pbk = wave * C::J2 + g0 + q;
+                const int oy = y0 + (pbk >> 1), ox = x0 + (pbk & 1) * 16 + lp;
+                if (oy >= a.Hout || ox >= a.Wout) continue;
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc2[q][i] + b2[i], 0.f);
+                uint2 o2;
+                o2.x = f2bf2(v[0], v[1]);
+                o2.y = f2bf2(v[2], v[3]);
+                *reinterpret_cast<uint2*>(a.y + (((size_t)b * a.Hout + oy) * a.Wout + ox) * 16 + 4 * lg) = o2;
+            }
+        }
+        tile = nxt;
+    }
+}
+
+template <int TR>
+static hh_status launch_pair_t(hipStream_t st, ConvArgs a, int num_cus) {
+    using C = PairCfg<TR>;
+    a.tiles_x = (a.Wout + C::TC - 1) / C::TC;
+    a.tiles_y = (a.Hout + TR - 1) / TR;
+    a.ntiles = a.B * a.tiles_x * a.tiles_y;
+    if (a.ntiles == 0) return HH_OK;
+    const int grid = std::min(a.ntiles, 8 * num_cus);
+    hipLaunchKernelGGL((k_conv_pair16<TR>), dim3(grid), dim3(256), 0, st, a);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Tile autotuner.  Every stride-1 and stride-2 layer shape has several
 // variants: the register-prefetch kernel (k_conv_mfma) and the direct-to-LDS
 // kernel (k_conv_dma) at several tile heights; the transposed layers their one
@@ -735,6 +930,7 @@ static int conv_variants(int cin, int cout, int mode, int* codes) {
     static const int t16[] = {8, 16};
     static const int t32[] = {4, 8, 16};
     static const int t64[] = {4, 2, 8};
+    static const int p16[] = {8, 16, 4, 1};  // fused at 8, 16 or 4 rows; 1: the two layers launched separately
     const int* v = nullptr;
     int nv = 0;
     if (mode == CM_T2 && cin == 32 && cout == 16) { v = t16; nv = 2; }
@@ -746,6 +942,7 @@ static int conv_variants(int cin, int cout, int mode, int* codes) {
     if (mode == CM_S2 && cin == 16 && cout == 32) { v = s16; nv = 4; }
     if (mode == CM_S2 && cin == 32 && cout == 64) { v = s32; nv = 4; }
     if (mode == CM_S2 && cin == 64 && cout == 64) { v = s64; nv = 3; }
+    if (mode == CM_PAIR && cin == 16 && cout == 16) { v = p16; nv = 4; }
     for (int i = 0; i < nv; ++i) codes[i] = v[i];
     return nv;
 }
@@ -788,7 +985,20 @@ static hh_status launch_variant(hipStream_t st, int num_cus, int cin, int cout, 
     HH_V(64, 64, CM_T2, 4, (launch_t2_t<64, 64, 4>))
     HH_V(64, 64, CM_T2, 2, (launch_t2_t<64, 64, 2>))
     HH_V(64, 64, CM_T2, 8, (launch_t2_t<64, 64, 8>))
+    HH_V(16, 16, CM_PAIR, 16, (launch_pair_t<16>))
+    HH_V(16, 16, CM_PAIR, 8, (launch_pair_t<8>))
+    HH_V(16, 16, CM_PAIR, 4, (launch_pair_t<4>))
 #undef HH_V
+    if (cin == 16 && cout == 16 && mode == CM_PAIR && code == 1) {  // unfused: through the intermediate tensor
+        ConvArgs a1 = a;
+        a1.y = a.ymid;
+        HH_TRY(launch_conv(st, num_cus, 16, 16, CM_S1, a1));
+        ConvArgs a2 = a;
+        a2.x = a.ymid;
+        a2.wp = a.wp2;
+        a2.bias = a.bias2;
+        return launch_conv(st, num_cus, 16, 16, CM_S1, a2);
+    }
     set_error("no convolution variant %d for cin=%d cout=%d mode=%d", code, cin, cout, mode);
     return HH_ERR_ARG;
 }
@@ -840,17 +1050,28 @@ hh_status launch_conv(hipStream_t st, int num_cus, int cin, int cout, int mode, 
         set_error("no convolution kernel for cin=%d cout=%d mode=%d", cin, cout, mode);
         return HH_ERR_ARG;
     }
+    if (mode == CM_PAIR && (a.act != ACT_RELU || a.skip || a.mask || a.yf || !a.ymid || !a.wp2 ||
+                            a.Hin != a.Hout || a.Win != a.Wout)) {
+        set_error("fused layer pair: two stride-1 ReLU layers without skip, mask or FP32 copy, with an "
+                  "intermediate buffer");
+        return HH_ERR_ARG;
+    }
     if (variant != 0) return launch_variant(st, num_cus, cin, cout, mode, variant, a);
     int dev = 0;
     HH_HIP(hipGetDevice(&dev));
     const uint64_t key = tune_key(cin, cout, mode, a);
-    {
+    int chosen = 0;
+    {  // looked up under the lock, launched after it (the unfused pair launches its layers through here)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto f = g_forced.find(shape_key(cin, cout, mode));
-        if (f != g_forced.end()) return launch_variant(st, num_cus, cin, cout, mode, f->second, a);
-        auto it = g_tune.find({dev, key});
-        if (it != g_tune.end()) return launch_variant(st, num_cus, cin, cout, mode, it->second, a);
+        if (f != g_forced.end()) {
+            chosen = f->second;
+        } else {
+            auto it = g_tune.find({dev, key});
+            if (it != g_tune.end()) chosen = it->second;
+        }
     }
+    if (chosen != 0) return launch_variant(st, num_cus, cin, cout, mode, chosen, a);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HH_HIP(hipStreamIsCapturing(st, &cs));
     if (cs != hipStreamCaptureStatusNone || a.B * a.Hout * a.Wout == 0)

@@ -102,6 +102,7 @@ hh_model_attach_net = _sig("hh_model_attach_net", _I, _P, _P)
 hh_net_forward = _sig("hh_net_forward", _I, _P, _I, _IP, _P, _P)
 hh_apply_cnn_precond = _sig("hh_apply_cnn_precond", _I, _P, _I, _IP, _P, _P)
 hh_conv_test = _sig("hh_conv_test", _I, _P, _I, _I, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _IP, _I)
+hh_conv_pair_test = _sig("hh_conv_pair_test", _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _IP, _I)
 hh_conv_variants = _sig("hh_conv_variants", _I, _I, _I, _I, _IP, _I)
 hh_conv_tuned_variant = _sig("hh_conv_tuned_variant", _I, _I, _I, _I, _I, _I, _I, _I)
 hh_conv_force_variant = _sig("hh_conv_force_variant", _I, _I, _I, _I, _I)
@@ -535,6 +536,25 @@ def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, fl
                        _ptr(skip), int(act if act is not None else (1 if relu else 0)), _ptr(y), _ptr(yf),
                        _int_array(active), int(variant)))
     return y, yf
+
+
+def conv_pair_test(ctx: Context, x_bf16: torch.Tensor, w1: torch.Tensor, b1, w2: torch.Tensor, b2, active=None,
+                   fill=None, variant: int = 0):
+    """Two fused stride-1 16-channel ReLU layers (mode 3); returns (y, mid) BF16,
+    mid written by the unfused variant 1 only.  fill: initial value of both."""
+    B, H, W_, _ = x_bf16.shape
+    y = torch.empty((B, H, W_, 16), dtype=torch.bfloat16, device=x_bf16.device)
+    mid = torch.empty_like(y)
+    if fill is not None:
+        y.fill_(fill)
+        mid.fill_(fill)
+    x_bf16 = x_bf16.contiguous()
+    w1, w2 = w1.to(torch.float32).contiguous(), w2.to(torch.float32).contiguous()
+    b1 = b1.to(torch.float32).contiguous() if b1 is not None else None
+    b2 = b2.to(torch.float32).contiguous() if b2 is not None else None
+    check(hh_conv_pair_test(ctx.handle, B, H, W_, _ptr(x_bf16), _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2), _ptr(mid),
+                            _ptr(y), _int_array(active), int(variant)))
+    return y, mid
 
 
 def wgrad_test(ctx: Context, a_bf16: torch.Tensor, x_bf16: torch.Tensor, mode: int) -> torch.Tensor:

@@ -32,6 +32,7 @@ import queue
 import sys
 import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import torch
@@ -54,8 +55,12 @@ def family_of(j: int) -> str:
     return "grf" if j % 2 == 0 else "layered"
 
 
-def kappa_batch(n: int, seeds) -> np.ndarray:
-    return np.stack([inputs.slowness(n, int(s), family_of(int(s))) for s in seeds]).astype(np.float32)
+def kappa_batch(n: int, seeds, pool=None) -> np.ndarray:
+    """Slowness models of the given seeds; `pool` (an executor) draws them in
+    parallel (NumPy's FFTs and generators release the GIL)."""
+    one = lambda s: inputs.slowness(n, int(s), family_of(int(s)))
+    ks = list(pool.map(one, seeds)) if pool is not None else [one(s) for s in seeds]
+    return np.stack(ks).astype(np.float32)
 
 
 def schedule(steps: int, block: int, sizes=(128, 256)) -> list[int]:
@@ -75,7 +80,7 @@ def learning_rate(step: int, steps: int, lr: float, drop_frac: float = 0.75) -> 
 
 
 class KappaPrefetch:
-    """Draws the next batches of slowness models on a host thread while the GPU
+    """Draws the next batches of slowness models on host threads while the GPU
     trains on the current one."""
 
     def __init__(self, plan, batch: int, depth: int = 3, step0: int = 0, fresh=None):
@@ -86,12 +91,13 @@ class KappaPrefetch:
         self.t.start()
 
     def _run(self):
-        for step, n in enumerate(self.plan):
-            if not self.fresh[step]:  # the previous step's media are used again
-                self.q.put((step, n, None))
-                continue
-            seeds = TRAIN_SEED0 + (self.step0 + step) * self.batch + np.arange(self.batch)
-            self.q.put((step, n, kappa_batch(n, seeds)))
+        with ThreadPoolExecutor(8) as pool:
+            for step, n in enumerate(self.plan):
+                if not self.fresh[step]:  # the previous step's media are used again
+                    self.q.put((step, n, None))
+                    continue
+                seeds = TRAIN_SEED0 + (self.step0 + step) * self.batch + np.arange(self.batch)
+                self.q.put((step, n, kappa_batch(n, seeds, pool)))
 
     def get(self):
         return self.q.get()

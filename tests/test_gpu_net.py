@@ -479,3 +479,61 @@ def test_conv_autotuner_records_and_forces(hh, ctx):
     m.attach_net(None)
     net.close()
     m.close()
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 37, 45), (6, 360, 400)])
+def test_fused_layer_pair_bit_identical(hh, ctx, B, H, W):
+    # the fused 16-channel pair (first layer's output kept in LDS, at 16, 8 and
+    # 4 rows per tile) against the two layers launched separately: bit-identical,
+    # skipped batch entries untouched, ragged tiles on both edges, and (the
+    # large case) more tiles than one pass of the grid
+    codes = hh.conv_variants(16, 16, 3)
+    _say(f"fused pair B={B} {H}x{W}: variants {codes}")
+    assert sorted(codes) == [1, 4, 8, 16]
+    rng = np.random.default_rng(H + W)
+    x = _bf16_round(rng.standard_normal((B, 16, H, W)))
+    w1 = _bf16_round(rng.uniform(-1, 1, (16, 16, 3, 3)) / np.sqrt(9 * 16) * 1.5)
+    w2 = _bf16_round(rng.uniform(-1, 1, (16, 16, 3, 3)) / np.sqrt(9 * 16) * 1.5)
+    b1, b2 = rng.uniform(-0.3, 0.3, 16), rng.uniform(-0.3, 0.3, 16)
+    dev = lambda a: torch.from_numpy(a).to("cuda:0", torch.float32)
+    xd = _nhwc_dev(x)
+    active = [1 if i % 3 != 1 else 0 for i in range(B)]
+    y1, mid = hh.conv_pair_test(ctx, xd, dev(w1), dev(b1), dev(w2), dev(b2), active=active, fill=5.0, variant=1)
+    for c in (16, 8, 4):
+        y, _ = hh.conv_pair_test(ctx, xd, dev(w1), dev(b1), dev(w2), dev(b2), active=active, fill=5.0, variant=c)
+        assert torch.equal(y, y1), c
+    yn = y1.float().cpu().numpy().transpose(0, 3, 1, 2)
+    for bb in range(B):
+        if not active[bb]:
+            assert (yn[bb] == 5.0).all()
+    if B * H * W > 10000:
+        return
+    # against the oracle, the intermediate rounded to BF16 as the library stores it
+    h = C.relu(C.conv2d(x, w1, b1, 1))
+    ref = C.relu(C.conv2d(_bf16_round(h), w2, b2, 1))
+    for bb in range(B):
+        if active[bb]:
+            assert np.abs(yn[bb] - ref[bb]).max() <= 1e-2 * np.abs(ref[bb]).max()
+
+
+def test_fused_layer_pair_in_the_network(hh, ctx):
+    # the network's inference forward with the 16-channel level pairs fused (both
+    # tile heights) or launched separately: bit-identical outputs
+    n = 256
+    k = inputs.grf_slowness(n, 61)
+    om = inputs.omega_for(n, k)
+    net = hh.Net(ctx, inputs.init_net_params(23))
+    m = hh.Model(ctx, torch.from_numpy(k), om)
+    m.attach_net(net)
+    r = torch.from_numpy(inputs.random_complex((3, n, n), 62)).to("cuda:0", torch.complex64)
+    outs = {}
+    for code in (1, 16, 8, 4):
+        hh.conv_force_variant(16, 16, 3, code)
+        outs[code] = m.net_forward(r)
+    hh.conv_force_variant(16, 16, 3, 0)
+    _say(f"  fused pair in the network at {n}^2: tuned {hh.conv_tuned_variant(0, 16, 16, 3, n // 2, n // 2, 3)}")
+    assert all(torch.equal(outs[c], outs[1]) for c in (16, 8, 4))
+    assert torch.equal(m.net_forward(r), outs[1])
+    m.attach_net(None)
+    net.close()
+    m.close()
