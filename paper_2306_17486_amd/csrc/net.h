@@ -11,6 +11,14 @@ namespace hh {
 enum { CM_S1 = 0, CM_S2 = 1, CM_T2 = 2, CM_PAIR = 3 };
 enum { ACT_NONE = 0, ACT_RELU = 1, ACT_SOFTPLUS = 2 };
 
+// Waits until every outstanding memory operation of the wave has completed.
+// Called after a persistent kernel has loaded its weights and biases into
+// registers, before its tile loop: otherwise the compiler's wait insertion,
+// merging the loop's entry with its back edge, keeps those loads pending
+// inside the loop and waits for them with counts that also cover the next
+// tile's prefetch, so the prefetch no longer overlaps the MFMAs.
+__device__ __forceinline__ void wait_all_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
 // softplus log(1 + e^v) without overflow, and its derivative (the logistic function)
 __device__ __forceinline__ float softplus_f(float v) { return fmaxf(v, 0.f) + __logf(1.f + __expf(-fabsf(v))); }
 __device__ __forceinline__ float logistic_f(float v) { return 1.f / (1.f + __expf(-v)); }

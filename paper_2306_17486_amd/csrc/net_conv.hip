@@ -88,6 +88,59 @@ struct ConvCfg {
     static constexpr int LDS_BYTES = PH * PW * CP * 2;
 };
 
+// One lane's epilogue: four consecutive output channels of one pixel at element
+// offset off of its batch entry (one entry holds fewer than 2^31 elements):
+// bias, sum skip, activation, ReLU-derivative mask, BF16 store and the optional
+// FP32 copy.  yb / yfb / kb / mb: the entry's output, FP32 copy, skip and mask
+// tensors (uniform per tile; the last three may be null).
+__device__ __forceinline__ void conv_epilogue4(const f32x4& acc, const float (&bias)[4], int act, uint16_t* yb,
+                                               float* yfb, const uint16_t* kb, const uint16_t* mb, int off) {
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = acc[i] + bias[i];
+    if (kb) {
+        const uint2 s2 = *reinterpret_cast<const uint2*>(kb + off);
+        v[0] += bf2f((uint16_t)(s2.x & 0xffff));
+        v[1] += bf2f((uint16_t)(s2.x >> 16));
+        v[2] += bf2f((uint16_t)(s2.y & 0xffff));
+        v[3] += bf2f((uint16_t)(s2.y >> 16));
+    }
+    if (act == ACT_RELU) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
+    } else if (act == ACT_SOFTPLUS) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = softplus_f(v[i]);
+    }
+    if (mb) {
+        const uint2 m2 = *reinterpret_cast<const uint2*>(mb + off);
+        if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
+        if (!(bf2f((uint16_t)(m2.x >> 16)) > 0.f)) v[1] = 0.f;
+        if (!(bf2f((uint16_t)(m2.y & 0xffff)) > 0.f)) v[2] = 0.f;
+        if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
+    }
+    uint2 o2;
+    o2.x = f2bf2(v[0], v[1]);
+    o2.y = f2bf2(v[2], v[3]);
+    *reinterpret_cast<uint2*>(yb + off) = o2;
+    if (yfb) *reinterpret_cast<float4*>(yfb + off) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// a tile's per-entry tensor bases for conv_epilogue4
+struct EpiBases {
+    uint16_t* yb;
+    float* yfb;
+    const uint16_t* kb;
+    const uint16_t* mb;
+};
+template <int COUT>
+__device__ __forceinline__ EpiBases epi_bases(const ConvArgs& a, int b) {
+    const size_t per = (size_t)a.Hout * a.Wout * COUT;
+    const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
+    return EpiBases{a.y + b * per, a.yf ? a.yf + b * per : nullptr, a.skip ? a.skip + sb * per : nullptr,
+                    a.mask ? a.mask + b * per : nullptr};
+}
+
 template <int CIN, int COUT, int MODE, bool PROJ = false, int TR_ = 0>
 __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 waves per SIMD resident
     using C = ConvCfg<CIN, COUT, MODE, TR_>;
@@ -129,6 +182,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
             const int co = (cg * C::CT + c) * 16 + 4 * lg + i;
             bias4[c][i] = (a.bias && (!PROJ || co < 2)) ? a.bias[co] : 0.f;
         }
+    wait_all_memory();
 
     // ---- the input patch of a tile (zero padding / zero interleaving), gathered
     // into registers: element e = pixel * VEC + v of the PH x PW patch ----
@@ -164,7 +218,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
                 ix = ux >> 1;
             }
             uint4 val = make_uint4(0, 0, 0, 0);
-            if (e < NE && in) val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
+            if (e < NE && in) val = *reinterpret_cast<const uint4*>(xb + (iy * a.Win + ix) * CIN + 8 * v);
             return val;
         }
     };
@@ -256,7 +310,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
             continue;
         }
         // ---- epilogue: lane owns channels (cg*CT + c)*16 + 4 lg .. +3 of one pixel per block ----
-        const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
+        const EpiBases eb = epi_bases<COUT>(a, b);
 #pragma unroll
         for (int q = 0; q < C::PBW; ++q)
 #pragma unroll
@@ -266,37 +320,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
             const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
             const int oy = y0 + ry, ox = x0 + rx;
             if (oy >= a.Hout || ox >= a.Wout) continue;
-            const size_t po = (((size_t)b * a.Hout + oy) * a.Wout + ox) * COUT + co;
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = acc[q][c][i] + bias4[c][i];
-            if (a.skip) {
-                const size_t so = (((size_t)sb * a.Hout + oy) * a.Wout + ox) * COUT + co;
-                uint2 s2 = *reinterpret_cast<const uint2*>(a.skip + so);
-                v[0] += bf2f((uint16_t)(s2.x & 0xffff));
-                v[1] += bf2f((uint16_t)(s2.x >> 16));
-                v[2] += bf2f((uint16_t)(s2.y & 0xffff));
-                v[3] += bf2f((uint16_t)(s2.y >> 16));
-            }
-            if (a.act == ACT_RELU) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
-            } else if (a.act == ACT_SOFTPLUS) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = softplus_f(v[i]);
-            }
-            if (a.mask) {
-                uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
-                if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
-                if (!(bf2f((uint16_t)(m2.x >> 16)) > 0.f)) v[1] = 0.f;
-                if (!(bf2f((uint16_t)(m2.y & 0xffff)) > 0.f)) v[2] = 0.f;
-                if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
-            }
-            uint2 o2;
-            o2.x = f2bf2(v[0], v[1]);
-            o2.y = f2bf2(v[2], v[3]);
-            *reinterpret_cast<uint2*>(a.y + po) = o2;
-            if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
+            conv_epilogue4(acc[q][c], bias4[c], a.act, eb.yb, eb.yfb, eb.kb, eb.mb, (oy * a.Wout + ox) * COUT + co);
         }
         tile = nxt;
     }
@@ -367,6 +391,7 @@ __global__ void __launch_bounds__(256) k_conv_dma(ConvArgs a) {
     for (int c = 0; c < C::CT; ++c)
 #pragma unroll
         for (int i = 0; i < 4; ++i) bias4[c][i] = a.bias ? a.bias[(cg * C::CT + c) * 16 + 4 * lg + i] : 0.f;
+    wait_all_memory();
 
     const int per_b = a.tiles_x * a.tiles_y;
     const uint32_t bytes_b = (uint32_t)a.Hin * a.Win * CIN * 2;
@@ -430,7 +455,7 @@ __global__ void __launch_bounds__(256) k_conv_dma(ConvArgs a) {
                     acc[q][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[c][ch], bv, acc[q][c], 0, 0, 0);
             }
         }
-        const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
+        const EpiBases eb = epi_bases<COUT>(a, b);
 #pragma unroll
         for (int q = 0; q < C::PBW; ++q)
 #pragma unroll
@@ -440,37 +465,8 @@ __global__ void __launch_bounds__(256) k_conv_dma(ConvArgs a) {
                 const int ry = pbk / (C::TC / 16), rx = (pbk % (C::TC / 16)) * 16 + lp;
                 const int oy = y0 + ry, ox = x0 + rx;
                 if (oy >= a.Hout || ox >= a.Wout) continue;
-                const size_t po = (((size_t)b * a.Hout + oy) * a.Wout + ox) * COUT + co;
-                float v[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = acc[q][c][i] + bias4[c][i];
-                if (a.skip) {
-                    const size_t so = (((size_t)sb * a.Hout + oy) * a.Wout + ox) * COUT + co;
-                    uint2 s2 = *reinterpret_cast<const uint2*>(a.skip + so);
-                    v[0] += bf2f((uint16_t)(s2.x & 0xffff));
-                    v[1] += bf2f((uint16_t)(s2.x >> 16));
-                    v[2] += bf2f((uint16_t)(s2.y & 0xffff));
-                    v[3] += bf2f((uint16_t)(s2.y >> 16));
-                }
-                if (a.act == ACT_RELU) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
-                } else if (a.act == ACT_SOFTPLUS) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = softplus_f(v[i]);
-                }
-                if (a.mask) {
-                    uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
-                    if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
-                    if (!(bf2f((uint16_t)(m2.x >> 16)) > 0.f)) v[1] = 0.f;
-                    if (!(bf2f((uint16_t)(m2.y & 0xffff)) > 0.f)) v[2] = 0.f;
-                    if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
-                }
-                uint2 o2;
-                o2.x = f2bf2(v[0], v[1]);
-                o2.y = f2bf2(v[2], v[3]);
-                *reinterpret_cast<uint2*>(a.y + po) = o2;
-                if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
+                conv_epilogue4(acc[q][c], bias4[c], a.act, eb.yb, eb.yfb, eb.kb, eb.mb,
+                               (oy * a.Wout + ox) * COUT + co);
             }
         tile = nxt;
     }
@@ -526,6 +522,7 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
     if (a.bias)
 #pragma unroll
         for (int i = 0; i < 4; ++i) bias4[i] = a.bias[ct * 16 + 4 * lg + i];
+    wait_all_memory();
 
     // the input patch, gathered into registers one active tile ahead while
     // the current tile's MFMAs run; not for 64 -> 64, whose extra registers
@@ -550,7 +547,7 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
             const int iy = (y0 >> 1) + py, ix = (x0 >> 1) + px;
             g[j] = make_uint4(0, 0, 0, 0);
             if (e < NE && iy < a.Hin && ix < a.Win)
-                g[j] = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
+                g[j] = *reinterpret_cast<const uint4*>(xb + (iy * a.Win + ix) * CIN + 8 * v);
         }
     };
     // without prefetch: gather and store element by element
@@ -565,7 +562,7 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
             const int py = pix / C::PW, px = pix - py * C::PW;
             const int iy = (y0 >> 1) + py, ix = (x0 >> 1) + px;
             uint4 val = make_uint4(0, 0, 0, 0);
-            if (iy < a.Hin && ix < a.Win) val = *reinterpret_cast<const uint4*>(xb + ((size_t)iy * a.Win + ix) * CIN + 8 * v);
+            if (iy < a.Hin && ix < a.Win) val = *reinterpret_cast<const uint4*>(xb + (iy * a.Win + ix) * CIN + 8 * v);
             *reinterpret_cast<uint4*>(&s_in[pix * C::CP + 8 * v]) = val;
         }
     };
@@ -625,43 +622,13 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
             }
         }
         const int co = ct * 16 + 4 * lg;
-        const int sb = a.skip ? (a.skip_map ? a.skip_map[b] : b) : 0;
+        const EpiBases eb = epi_bases<COUT>(a, b);
 #pragma unroll
         for (int q = 0; q < C::PBW; ++q) {
             const int ry = (wsub * C::PBW + q) >> 1;
             const int oy = y0 + ry, ox = x0 + (q & 1) + 2 * lp;
             if (oy >= a.Hout || ox >= a.Wout) continue;
-            const size_t po = (((size_t)b * a.Hout + oy) * a.Wout + ox) * COUT + co;
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = acc[q][i] + bias4[i];
-            if (a.skip) {
-                const size_t so = (((size_t)sb * a.Hout + oy) * a.Wout + ox) * COUT + co;
-                uint2 s2 = *reinterpret_cast<const uint2*>(a.skip + so);
-                v[0] += bf2f((uint16_t)(s2.x & 0xffff));
-                v[1] += bf2f((uint16_t)(s2.x >> 16));
-                v[2] += bf2f((uint16_t)(s2.y & 0xffff));
-                v[3] += bf2f((uint16_t)(s2.y >> 16));
-            }
-            if (a.act == ACT_RELU) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = fmaxf(v[i], 0.f);
-            } else if (a.act == ACT_SOFTPLUS) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = softplus_f(v[i]);
-            }
-            if (a.mask) {
-                uint2 m2 = *reinterpret_cast<const uint2*>(a.mask + po);
-                if (!(bf2f((uint16_t)(m2.x & 0xffff)) > 0.f)) v[0] = 0.f;
-                if (!(bf2f((uint16_t)(m2.x >> 16)) > 0.f)) v[1] = 0.f;
-                if (!(bf2f((uint16_t)(m2.y & 0xffff)) > 0.f)) v[2] = 0.f;
-                if (!(bf2f((uint16_t)(m2.y >> 16)) > 0.f)) v[3] = 0.f;
-            }
-            uint2 o2;
-            o2.x = f2bf2(v[0], v[1]);
-            o2.y = f2bf2(v[2], v[3]);
-            *reinterpret_cast<uint2*>(a.y + po) = o2;
-            if (a.yf) *reinterpret_cast<float4*>(a.yf + po) = make_float4(v[0], v[1], v[2], v[3]);
+            conv_epilogue4(acc[q], bias4, a.act, eb.yb, eb.yfb, eb.kb, eb.mb, (oy * a.Wout + ox) * COUT + co);
         }
         tile = nxt;
     }
@@ -711,7 +678,7 @@ struct PairCfg {
 };
 
 template <int TR>
-__global__ void __launch_bounds__(256, 4) k_conv_pair16(ConvArgs a) {
+__global__ void __launch_bounds__(256, TR >= 16 ? 2 : 4) k_conv_pair16(ConvArgs a) {
     using C = PairCfg<TR>;
     __shared__ __attribute__((aligned(16))) uint16_t s_in[C::IH * C::IW * C::CP];
     __shared__ __attribute__((aligned(16))) uint16_t s_mid[C::P1 * C::CP];
@@ -738,6 +705,7 @@ __global__ void __launch_bounds__(256, 4) k_conv_pair16(ConvArgs a) {
         b1[i] = a.bias ? a.bias[4 * lg + i] : 0.f;
         b2[i] = a.bias2 ? a.bias2[4 * lg + i] : 0.f;
     }
+    wait_all_memory();
 
     const int per_b = a.tiles_x * a.tiles_y;
     // input vector e of a tile's patch (zero outside the image)
@@ -750,7 +718,7 @@ __global__ void __launch_bounds__(256, 4) k_conv_pair16(ConvArgs a) {
         const int iy = ty * TR - 2 + py, ix = tx * C::TC - 2 + px;
         uint4 val = make_uint4(0, 0, 0, 0);
         if (e < C::NE && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win)
-            val = *reinterpret_cast<const uint4*>(a.x + (((size_t)b * a.Hin + iy) * a.Win + ix) * 16 + 8 * v);
+            val = *reinterpret_cast<const uint4*>(a.x + (size_t)b * a.Hin * a.Win * 16 + ((iy * a.Win + ix) * 16 + 8 * v));
         return val;
     };
     auto next_active = [&](int t) {
@@ -830,6 +798,7 @@ __global__ void __launch_bounds__(256, 4) k_conv_pair16(ConvArgs a) {
         }
         __syncthreads();  // s_mid complete
         // ---- second layer over the tile: blocks wave * J2 .. + J2 - 1, G2 at a time ----
+        uint16_t* yb = a.y + (size_t)b * a.Hout * a.Wout * 16;
 #pragma unroll 1
         for (int g0 = 0; g0 < C::J2; g0 += C::G2) {
             f32x4 acc2[C::G2];
@@ -855,7 +824,7 @@ __global__ void __launch_bounds__(256, 4) k_conv_pair16(ConvArgs a) {
                 uint2 o2;
                 o2.x = f2bf2(v[0], v[1]);
                 o2.y = f2bf2(v[2], v[3]);
-                *reinterpret_cast<uint2*>(a.y + (((size_t)b * a.Hout + oy) * a.Wout + ox) * 16 + 4 * lg) = o2;
+                *reinterpret_cast<uint2*>(yb + ((oy * a.Wout + ox) * 16 + 4 * lg)) = o2;
             }
         }
         tile = nxt;
