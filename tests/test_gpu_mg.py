@@ -51,6 +51,11 @@ def test_operator_all_levels(hh, ctx, n, family):
             y = m.apply_operator(_dev(x), level=lvl, shift=shift).cpu().numpy()
             ref = np.stack([H.apply_op(x[i], L.k2w2, L.gamma, L.h, shift) for i in range(2)])
             assert _rel(y, ref) <= 2e-6, (lvl, shift, _rel(y, ref))
+            # elementwise, so that one wrong edge row or absorbing-layer band cannot
+            # hide in the global norm
+            emax = float(np.abs(y - ref).max() / np.abs(ref).max())
+            _say(f"  level {lvl} shift {shift}: global {_rel(y, ref):.2e}, elementwise {emax:.2e}")
+            assert emax <= 2e-5, (lvl, shift, emax)
 
 
 def test_operator_complex_symmetry(hh, ctx):
@@ -84,6 +89,9 @@ def test_vcycle_parity(hh, ctx, n, family, with_x0, reduce):
     z = m.apply_vcycle(_dev(b), None if x0 is None else _dev(x0)).cpu().numpy()
     ref = np.stack([prob.hier.vcycle(b[i], None if x0 is None else x0[i]) for i in range(3)])
     assert _rel(z, ref) <= 2e-5, _rel(z, ref)
+    emax = float(np.abs(z - ref).max() / np.abs(ref).max())
+    _say(f"  global {_rel(z, ref):.2e}, elementwise {emax:.2e}")
+    assert emax <= 2e-4, emax
 
 
 def test_vcycle_multi_instance(hh, ctx):
