@@ -48,7 +48,7 @@ CLASS_SOURCES = {
 
 
 def class_of(name: str) -> str:
-    if name.startswith("k_conv_mfma") and name.rstrip().endswith("true>"):
+    if name.startswith("k_conv_mfma") and re.search(r", true(, \d+)?>$", name.rstrip()):
         return "net_other"  # the projection layer (launched in the library's network-other scope)
     for p, c in CLASS_OF:
         if name.startswith(p):
