@@ -165,6 +165,40 @@ __global__ void k_scales(const double* __restrict__ parts, int nblk, size_t N, c
     out_scale[b] = rms > 0.0 ? (float)(h2 * sg * rms) : 0.f;
 }
 
+// the same scales from a known norm: the vectors are FGMRES's lazily normalised
+// basis vectors, whose norm is 1/sig as the orthogonalisation measured it, so
+// rms = 1/(sqrt(N) sig), in_scale = sqrt(N) sig and out_scale = h^2 / sqrt(N)
+__global__ void k_scales_known(const double* __restrict__ sig, int sig_stride, size_t N, double h2,
+                               float* __restrict__ in_scale, float* __restrict__ out_scale, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double sg = sig[(size_t)b * sig_stride];
+    const double rn = sqrt((double)N);
+    in_scale[b] = sg > 0.0 ? (float)(rn * sg) : 0.f;
+    out_scale[b] = sg > 0.0 ? (float)(h2 / rn) : 0.f;
+}
+
+// The network's input and output scales per sample (C9 reading of Sec. 4.3: the
+// network works on a unit-rms residual): in_scale = 1/rms(v), out_scale =
+// h^2 sig rms(v); with known_norm (sig given) from sig alone, without a pass over v.
+static hh_status launch_scales(hipStream_t st, const float2* v, size_t vstride, size_t N, double* parts,
+                               const int* active, const double* sig, int sig_stride, double h2, float* in_scale,
+                               float* out_scale, int B, bool known_norm) {
+    if (known_norm && sig) {
+        hipLaunchKernelGGL(k_scales_known, dim3((B + 63) / 64), dim3(64), 0, st, sig, sig_stride, N, h2, in_scale,
+                           out_scale, B);
+        HH_LAUNCH_CHECK();
+        return HH_OK;
+    }
+    const int nblk = 64;
+    hipLaunchKernelGGL(k_sumsq, dim3(nblk, B), dim3(256), 0, st, v, vstride, N, parts, active);
+    HH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scales, dim3((B + 63) / 64), dim3(64), 0, st, parts, nblk, N, sig, sig_stride, h2, in_scale,
+                       out_scale, B);
+    HH_LAUNCH_CHECK();
+    return HH_OK;
+}
+
 // First layer of the encoder / solver: 3x3 stride-2 convolution from 2 input
 // channels (BF16-rounded) to 16 channels, + bias, + optional skip.  The input
 // is either a complex vector scaled per RHS (solver: v / rms(v)) or the
@@ -1261,21 +1295,14 @@ static hh_status light_encoder_forward(hh_net* net, hh_model* md, LightActs& A, 
 static hh_status light_forward(hh_net* net, int n, double h, LightActs& A, int B, const int* smap, const uint16_t* E1,
                                const uint16_t* E2, const uint16_t* E3, const float2* Gbr, const float2* v,
                                size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active,
-                               bool train, bool update) {
+                               bool train, bool update, bool known_norm = false) {
     hipStream_t st = net->ctx->stream;
     HH_TRY(A.ensure(net, B, n, train));
     if (train) active = nullptr;
     float* in_scale = A.scales.as<float>();
     float* out_scale = in_scale + B;
-    {
-        const int nblk = 64;
-        hipLaunchKernelGGL(k_sumsq, dim3(nblk, B), dim3(256), 0, st, v, vstride, (size_t)n * n, A.parts.as<double>(),
-                           active);
-        HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_scales, dim3((B + 63) / 64), dim3(64), 0, st, A.parts.as<double>(), nblk, (size_t)n * n,
-                           sig, sig_stride, h * h, in_scale, out_scale, B);
-        HH_LAUNCH_CHECK();
-    }
+    HH_TRY(launch_scales(st, v, vstride, (size_t)n * n, A.parts.as<double>(), active, sig, sig_stride, h * h, in_scale,
+                         out_scale, B, known_norm));
     const float* P = net->params.as<float>();
     const int m1 = n / 2, m2 = n / 4, m3 = n / 8, m4 = coarsest_of(n), s4 = coarse_stride_of(n);
     auto o = [&](int l) { return A.out(l); };
@@ -1403,21 +1430,14 @@ static hh_status net_forward_chunk(hh_net* net, int n, NetActs& A, int b0, int B
 
 hh_status net_forward_core(hh_net* net, int n, double h, NetActs& A, int B, const int* smap, const uint16_t* E1,
                            const uint16_t* E2, const uint16_t* E3, const float2* Gbr, const float2* v, size_t vstride,
-                           const double* sig, int sig_stride, float2* x0, const int* active, bool keep) {
+                           const double* sig, int sig_stride, float2* x0, const int* active, bool keep,
+                           bool known_norm = false) {
     hipStream_t st = net->ctx->stream;
     HH_TRY(A.ensure(net, B, n));
     float* in_scale = A.scales.as<float>();
     float* out_scale = in_scale + B;
-    // rms scaling (C9 reading of Sec. 4.3: the network works on a unit-rms residual)
-    {
-        const int nblk = 64;
-        hipLaunchKernelGGL(k_sumsq, dim3(nblk, B), dim3(256), 0, st, v, vstride, (size_t)n * n, A.parts.as<double>(),
-                           active);
-        HH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_scales, dim3((B + 63) / 64), dim3(64), 0, st, A.parts.as<double>(), nblk, (size_t)n * n,
-                           sig, sig_stride, h * h, in_scale, out_scale, B);
-        HH_LAUNCH_CHECK();
-    }
+    HH_TRY(launch_scales(st, v, vstride, (size_t)n * n, A.parts.as<double>(), active, sig, sig_stride, h * h, in_scale,
+                         out_scale, B, known_norm));
     // The whole batch in every launch.  (Running it through the network in
     // chunks of 8 or 16 samples, so that a layer's output could still sit in
     // the last-level cache for the next layer, measured 16% and 7% slower.)
@@ -1537,27 +1557,31 @@ static hh_status net_forward_chunk(hh_net* net, int n, NetActs& A, int b0, int B
 }
 
 hh_status net_forward_batch(hh_net* net, hh_model* md, NetActs& A, int B, const BatchMap& bm, const float2* v,
-                            size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active) {
+                            size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active,
+                            bool known_norm) {
     NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
     HH_TRY(A.ensure(net, B, md->lev[0].n));
     const int* smap = md->ninst > 1 ? bm.inst : A.zeros.as<int>();
     return net_forward_core(net, md->lev[0].n, md->lev[0].h, A, B, smap, nc->enc[L_ENC1_C2].as<uint16_t>(),
                             nc->enc[L_ENC2_C2].as<uint16_t>(), nc->enc[L_ENC3_C2].as<uint16_t>(),
-                            nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active, false);
+                            nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active, false, known_norm);
 }
 
 // either network's forward pass on B vectors of model md (encodings and Ghat from
 // the model cache), and where its half-resolution output and scales are kept
+// (known_norm: v are FGMRES basis vectors of norm 1/sig, see launch_scales)
 static hh_status net_forward_model(hh_net* net, hh_model* md, int B, const BatchMap& bm, const float2* v,
-                                   size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active) {
+                                   size_t vstride, const double* sig, int sig_stride, float2* x0, const int* active,
+                                   bool known_norm = false) {
     NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
-    if (!net->light) return net_forward_batch(net, md, nc->acts, B, bm, v, vstride, sig, sig_stride, x0, active);
+    if (!net->light)
+        return net_forward_batch(net, md, nc->acts, B, bm, v, vstride, sig, sig_stride, x0, active, known_norm);
     LightActs& A = nc->lacts;
     HH_TRY(A.ensure(net, B, md->lev[0].n, false));
     const int* smap = md->ninst > 1 ? bm.inst : A.zeros.as<int>();
     return light_forward(net, md->lev[0].n, md->lev[0].h, A, B, smap, A.out(LL_ENC1_C2), A.out(LL_ENC2_C2),
                          A.out(LL_ENC3_C2), nc->Gbr.as<float2>(), v, vstride, sig, sig_stride, x0, active, false,
-                         false);
+                         false, known_norm);
 }
 static const float2* net_out_of(const NetCache* nc, const hh_net* net) {
     return net->light ? nc->lacts.a[LL_OUT].as<float2>() : nc->acts.a[L_OUT].as<float2>();
@@ -1581,7 +1605,8 @@ hh_status net_precond(void* user, hh_model* md, SolveWork& W, const BatchMap& bm
     NetCache* nc = reinterpret_cast<NetCache*>(md->netcache);
     // the V-cycle reads the network's half-resolution output and interpolates
     // the initial guess itself: no fine x0 is stored
-    HH_TRY(net_forward_model(net, md, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, act));
+    // v are the solve's lazily normalised basis vectors: their norms are 1/sig
+    HH_TRY(net_forward_model(net, md, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, act, true));
     return launch_vcycle_strided(md, W.nrhs, bm, v, vstride, sig, sig_stride, nullptr, 0, z, zstride, W.vwork.ptr, act,
                                  net_out_of(nc, net), net_out_scale_of(nc, net, W.nrhs));
 }
