@@ -64,13 +64,23 @@ __global__ void __launch_bounds__(256) k_apply_op(const float2* __restrict__ x, 
 // The blocks stage the coarse tile they need, s_o[I - cy0][J - cx0] (zero
 // outside the grid), and interpolate from LDS; i, j >= 0 are fine indices
 // inside the grid.
-template <int CPW>
-__device__ __forceinline__ void stage_half(float2* s_o, int rows, const float2* __restrict__ ob, int m, int cy0,
-                                           int cx0) {
-    for (int e = threadIdx.x; e < rows * CPW; e += blockDim.x) {
+// (256 threads; every load of a thread is issued before its first store, so that
+// they are in flight together)
+template <int CPW, int ROWS>
+__device__ __forceinline__ void stage_half(float2* s_o, const float2* __restrict__ ob, int m, int cy0, int cx0) {
+    constexpr int NE = ROWS * CPW, NJ = (NE + 255) / 256;
+    float2 v[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int e = threadIdx.x + 256 * j;
         const int py = e / CPW, px = e - py * CPW;
         const int I = cy0 + py, J = cx0 + px;
-        s_o[e] = (I >= 0 && I < m && J >= 0 && J < m) ? ob[(size_t)I * m + J] : make_float2(0.f, 0.f);
+        v[j] = (e < NE && I >= 0 && I < m && J >= 0 && J < m) ? ob[(size_t)I * m + J] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        if (e < NE) s_o[e] = v[j];
     }
 }
 
@@ -149,7 +159,7 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
         rc[j] = in ? cf[o] : zero;
     }
     if (X0M == 2) {
-        stage_half<OPW>(s_o, OPH, x0h + (size_t)r * (n >> 1) * (n >> 1), n >> 1, ocy0, ocx0);
+        stage_half<OPW, OPH>(s_o, x0h + (size_t)r * (n >> 1) * (n >> 1), n >> 1, ocy0, ocx0);
         __syncthreads();
     }
 
@@ -294,14 +304,10 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
         rb[j] = in ? br[o] : zero;
         rc[j] = in ? cf[o] : zero;
     }
-    for (int e = tid; e < CH * CW; e += 256) {
-        int py = e / CW, px = e - py * CW;
-        int I = cy0 + py, J = cx0 + px;
-        s_e[py][px] = (I >= 0 && I < nc && J >= 0 && J < nc) ? er[(size_t)I * nc + J] : zero;
-    }
+    stage_half<CW, CH>(&s_e[0][0], er, nc, cy0, cx0);  // the coarse correction's tile
     const int ocy0 = (y0 - 2) >> 1, ocx0 = (x0 - 2) >> 1;
     if (X1M == 2) {
-        stage_half<OPW>(s_o, OPH, x0h + (size_t)r * nc * nc, nc, ocy0, ocx0);
+        stage_half<OPW, OPH>(s_o, x0h + (size_t)r * nc * nc, nc, ocy0, ocx0);
         __syncthreads();
         const float os = x0s[r];
         for (int e = tid; e < XH * XW; e += 256) {

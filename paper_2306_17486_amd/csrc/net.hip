@@ -242,18 +242,31 @@ __global__ void __launch_bounds__(256) k_conv_in_mfma(const float2* __restrict__
     for (int i = 0; i < 4; ++i) bv[i] = bias[4 * kl + i];
     const float2* sb = src + (size_t)(src_map ? src_map[b] : b) * src_bstride;
     const float sc = (SRC == 0) ? in_scale[b] : 1.f;
-    for (int e = tid; e < PH * PW; e += 256) {
+    // the patch: every load of this thread issued before the first store, so
+    // that they are in flight together
+    constexpr int NST = (PH * PW + 255) / 256;
+    float2 pv[NST];
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+        const int e = tid + j * 256;
+        const int py = e / PW, px = e - py * PW;
+        const int iy = 2 * oy0 - 1 + py, ix = 2 * ox0 - 1 + px;
+        pv[j] = (e < PH * PW && iy >= 0 && iy < n && ix >= 0 && ix < n) ? sb[iy * n + ix] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+        const int e = tid + j * 256;
+        if (e >= PH * PW) break;
         const int py = e / PW, px = e - py * PW;
         const int iy = 2 * oy0 - 1 + py, ix = 2 * ox0 - 1 + px;
         float a0 = 0.f, a1 = 0.f;
-        if (iy >= 0 && iy < n && ix >= 0 && ix < n) {
-            const float2 v = sb[(size_t)iy * n + ix];
+        if (iy >= 0 && iy < n && ix >= 0 && ix < n) {  // zero padding stays zero whatever the scale
             if (SRC == 0) {
-                a0 = v.x * sc;
-                a1 = v.y * sc;
+                a0 = pv[j].x * sc;
+                a1 = pv[j].y * sc;
             } else {
-                a0 = v.x * h2;
-                a1 = a0 * v.y;
+                a0 = pv[j].x * h2;
+                a1 = a0 * pv[j].y;
             }
         }
         s_a[0][py][px] = bf2f(f2bf(a0));
