@@ -449,27 +449,47 @@ __global__ void __launch_bounds__(NT) k_implicit(const uint16_t* __restrict__ xi
         sincospif(-2.0f * (float)t / (float)M, &sn, &cs);
         tw[t] = make_float2(cs, sn);
     }
+    // the input map (nc <= M / 2) and this thread's share of Ghat_c: every load
+    // issued before the first is used, Ghat's in flight during the forward sweeps
+    constexpr int NI = (M / 2 * (M / 2) + NT - 1) / NT, NG = (M * M + NT - 1) / NT;
+    uint32_t raw[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = tid + i * NT;
+        const int y = e / nc, x = e - y * nc;
+        raw[i] = e < nc * nc ? *reinterpret_cast<const uint32_t*>(xin + (((size_t)b * nc + y) * nc + x) * CH + 2 * c)
+                             : 0u;
+    }
+    float2 g[NG];
+    {
+        const float2* G = Gbr + (size_t)c * M * M;
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int e = tid + i * NT;
+            g[i] = e < M * M ? G[e] : make_float2(0.f, 0.f);
+        }
+    }
     for (int e = tid; e < M * P; e += NT) s[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    for (int e = tid; e < nc * nc; e += NT) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = tid + i * NT;
         const int y = e / nc, x = e - y * nc;
-        const uint16_t* px = xin + (((size_t)b * nc + y) * nc + x) * CH + 2 * c;
-        const uint32_t raw = *reinterpret_cast<const uint32_t*>(px);
-        s[y * P + x] = make_float2(bf2f((uint16_t)(raw & 0xffff)), bf2f((uint16_t)(raw >> 16)));
+        if (e < nc * nc) s[y * P + x] = make_float2(bf2f((uint16_t)(raw[i] & 0xffff)), bf2f((uint16_t)(raw[i] >> 16)));
     }
     __syncthreads();
     // forward DIF along the nc data rows, then all columns (bit-reversed spectrum)
     impl_dif_sweep<M, NT>(s, nc, P, 1, false, tw);
     impl_dif_sweep<M, NT>(s, M, 1, P, true, tw);
     // spectrum (bit-reversed both ways) times Ghat_c
-    {
-        const float2* G = Gbr + (size_t)c * M * M;
-        for (int e = tid; e < M * M; e += NT) {
-            float2 g = G[e];
-            if (conjG) g.y = -g.y;
-            const int r = e / M, col = e - r * M;
-            s[r * P + col] = cmul(s[r * P + col], g);
-        }
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+        const int e = tid + i * NT;
+        if (e >= M * M) break;
+        float2 gv = g[i];
+        if (conjG) gv.y = -gv.y;
+        const int r = e / M, col = e - r * M;
+        s[r * P + col] = cmul(s[r * P + col], gv);
     }
     __syncthreads();
     // inverse DIT along all columns, then the nc kept rows (natural order)
@@ -652,6 +672,10 @@ hh_status launch_implicit(hipStream_t st, int M, const uint16_t* x, uint16_t* y,
                         : launch_implicit_large_t<512>(st, x, y, Gbr, nc, nk, B, work, active);
     }
     const size_t lds = implicit_lds_bytes(M);
+    if (2 * nc > M) {  // the in-LDS kernel stages at most (M/2)^2 input points per map
+        set_error("implicit layer: map %d x %d does not fit a transform of %d points", nc, nc, M);
+        return HH_ERR_ARG;
+    }
     dim3 grd(nk, B);
 #define HH_IMP(MM, NTT)                                                                                  \
     if (M == MM) {                                                                                       \
