@@ -254,7 +254,15 @@ __global__ void __launch_bounds__(256, 2) k_conv_mfma(ConvArgs a) {  // >= 2 wav
         if (PF) {
             put(pf);
         } else {
-            for (int e = tid; e < NE; e += 256) to_lds(e, elem(tile, e));
+            // four loads of this thread in flight at a time
+            for (int e0 = tid; e0 < NE; e0 += 4 * 256) {
+                uint4 v4[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v4[k] = elem(tile, e0 + k * 256);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (e0 + k * 256 < NE) to_lds(e0 + k * 256, v4[k]);
+            }
         }
         __syncthreads();
         if (PF && nxt < a.ntiles) gather(nxt, pf);  // in flight during the MFMAs below
@@ -557,13 +565,23 @@ __global__ void __launch_bounds__(256) k_conv_t2(ConvArgs a) {
         const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
         const int y0 = ty * C::TR, x0 = tx * C::TC;
         const uint16_t* xb = a.x + (size_t)b * a.Hin * a.Win * CIN;
-        for (int e = tid; e < NE; e += 256) {
+        // all of this thread's loads issued before its first store
+        constexpr int NJ = (NE + 255) / 256;
+        uint4 val[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int e = tid + j * 256;
             const int v = e % VEC, pix = e / VEC;
             const int py = pix / C::PW, px = pix - py * C::PW;
             const int iy = (y0 >> 1) + py, ix = (x0 >> 1) + px;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (iy < a.Hin && ix < a.Win) val = *reinterpret_cast<const uint4*>(xb + (iy * a.Win + ix) * CIN + 8 * v);
-            *reinterpret_cast<uint4*>(&s_in[pix * C::CP + 8 * v]) = val;
+            val[j] = make_uint4(0, 0, 0, 0);
+            if (e < NE && iy < a.Hin && ix < a.Win)
+                val[j] = *reinterpret_cast<const uint4*>(xb + (iy * a.Win + ix) * CIN + 8 * v);
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int e = tid + j * 256;
+            if (e < NE) *reinterpret_cast<uint4*>(&s_in[(e / VEC) * C::CP + 8 * (e % VEC)]) = val[j];
         }
     };
     auto next_active = [&](int t) {
