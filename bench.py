@@ -112,21 +112,58 @@ def _exact_worker(args):
     return X, time.perf_counter() - t
 
 
+def _exact_server(conn):
+    """Child process: waits for the list of jobs, then sends each result in order."""
+    jobs = conn.recv()
+    for j in jobs:
+        conn.send(_exact_worker(j))
+    conn.close()
+
+
+class _PipeResult:
+    """The next result from the exact-solve process (results arrive in job order)."""
+
+    def __init__(self, owner, k):
+        self.owner, self.k = owner, k
+
+    def get(self):
+        return self.owner.result(self.k)
+
+
 class ExactSolves:
     """The oracle's exact solves in a separate single-threaded process, spawned
-    before this process touches the GPU.  The jobs are submitted by `start()`,
-    after the timed region: a host core busy with a sparse factorisation slowed
-    the launch-bound 256^2 solves by half when it ran beside them."""
+    before this process touches the GPU and fed through a pipe.  The jobs are
+    sent by `start()`, after the timed region.  No pool: a process pool keeps
+    handler threads in this process, whose wake-ups compete for the GIL with
+    the library's allocator callbacks and slowed the launch-bound 256^2 solves
+    by 40%; a factorisation running beside the timed solves halved them."""
 
     def __init__(self, jobs):
-        self.pool = mp.get_context("spawn").Pool(1)
+        ctx = mp.get_context("spawn")
+        self.conn, child = ctx.Pipe()
+        self.proc = ctx.Process(target=_exact_server, args=(child,), daemon=True)
+        self.proc.start()
+        child.close()
         self.jobs = jobs
-        self.results = None
+        self.got = []
+        self.pool = self  # close() / join() as the callers expect
 
     def start(self):
-        if self.results is None:
-            self.results = [self.pool.apply_async(_exact_worker, (j,)) for j in self.jobs]
-        return self.results
+        if not hasattr(self, "sent"):
+            self.conn.send(self.jobs)
+            self.sent = True
+        return [_PipeResult(self, k) for k in range(len(self.jobs))]
+
+    def result(self, k):
+        while len(self.got) <= k:
+            self.got.append(self.conn.recv())
+        return self.got[k]
+
+    def close(self):
+        self.conn.close()
+
+    def join(self):
+        self.proc.join(timeout=60)
 
 
 def start_exact(jobs):
