@@ -1258,7 +1258,7 @@ __global__ void __launch_bounds__(CSP_NT) k_coarse_split_bwd(const float2* __res
     const int nsteps = top ? p : (m - 1 - p);
     float2 qr[CSP_CMAX];
     split_load_q<RS>(Q + (size_t)p * mm, m, row0, qr);
-    // middle row (step 0 of the sweep): x_p = Q_p (b_p + c y_{p-1} + c y_{p+1}); both ends compute it
+    // middle row (round 0): x_p = Q_p (b_p + c y_{p-1} + c y_{p+1}); both ends compute it
     for (int e = threadIdx.x; e < R * m; e += CSP_NT) {
         const int q = e / m, j = e - q * m;
         float2 w = make_float2(0.f, 0.f);
@@ -1395,7 +1395,7 @@ __global__ void __launch_bounds__(CSP_NT) k_cr_split_bwd(const float2* __restric
     const int row0 = slice * RS;
     const int row = row0 + threadIdx.x;
     float2 qr[CSP_CMAX];
-    // middle row (step 0 of the sweep), computed by both ends
+    // middle row (round 0), computed by both ends
     float2 acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
