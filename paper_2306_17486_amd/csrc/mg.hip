@@ -100,6 +100,37 @@ __device__ __forceinline__ float2 x0_from_half(const float2* s_o, int cy0, int c
     return cscale(interp_half(s_o, CPW, (i >> 1) - cy0, (j >> 1) - cx0, i & 1, j & 1), s);
 }
 
+// The guess x0 = s P(o) on a fine LDS patch dst[PH][PW] whose first row and
+// column are the fine cells (fy0, fx0), from the coarse tile s_o (pitch CPW,
+// origin (fy0 >> 1, fx0 >> 1)), zero outside the n x n grid.  Each thread forms
+// the four fine cells of one coarse cell, (2I + a, 2J + c), from its four
+// corners, with interp_half's operations for each parity: (0, 0) gives the
+// corner itself, (0, 1) and (1, 0) the midpoints, (1, 1) the mean of the two
+// row midpoints -- bit for bit what interp_half returns, with one quarter of
+// its index work.  256 threads.
+template <int CPW, int PH, int PW>
+__device__ __forceinline__ void x0_patch_from_half(float2 (*dst)[PW], const float2* s_o, int fy0, int fx0, int n,
+                                                   float s) {
+    const int by0 = fy0 >> 1, bx0 = fx0 >> 1;  // floor: fy0, fx0 may be negative
+    constexpr int BH = PH / 2 + 1, BW = PW / 2 + 1;  // coarse cells touching the patch (at most)
+    for (int e = threadIdx.x; e < BH * BW; e += 256) {
+        const int by = e / BW, bx = e - by * BW;
+        const float2* t = s_o + by * CPW + bx;
+        const float2 a = t[0], b = t[1], c = t[CPW], d = t[CPW + 1];
+        const float2 ab = cscale(cadd(a, b), 0.5f), cd = cscale(cadd(c, d), 0.5f);
+        const float2 v[2][2] = {{a, ab}, {cscale(cadd(a, c), 0.5f), cscale(cadd(ab, cd), 0.5f)}};
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int gi = 2 * (by0 + by) + dy, gj = 2 * (bx0 + bx) + dx;
+                const int py = gi - fy0, px = gj - fx0;
+                if (py < 0 || py >= PH || px < 0 || px >= PW) continue;
+                dst[py][px] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? cscale(v[dy][dx], s) : make_float2(0.f, 0.f);
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle down kernel on one level.
 // Block = 256 threads computes a TCY x TCX tile of the coarse right-hand side.
@@ -179,13 +210,14 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
         if (X0M == 1) {
             s_x0[py][px] = in ? x0[r * x0stride + o] : zero;
         } else if (X0M == 2) {
-            s_x0[py][px] = in ? x0_from_half<OPW>(s_o, ocy0, ocx0, gi, gj, x0s[r]) : zero;
+            // staged below, four fine cells per thread
         } else {
             // x1 = w b / diag with diag = 4/h^2 - mass
             float2 d = make_float2(dgv - mv.x, -mv.y);
             s_x[py][px] = in ? cscale(cdiv_rcp(bv, d), wj) : zero;
         }
     }
+    if constexpr (X0M == 2) x0_patch_from_half<OPW, PH, PW>(s_x0, s_o, fy0, fx0, n, x0s[r]);
     __syncthreads();
     if (HAS_X0) {
         // x1 = x0 + w (b - A_SL x0)/diag on rows/cols 1..P-2
@@ -306,16 +338,10 @@ __global__ void __launch_bounds__(256) k_vc_up(const float2* __restrict__ b, siz
     }
     stage_half<CW, CH>(&s_e[0][0], er, nc, cy0, cx0);  // the coarse correction's tile
     const int ocy0 = (y0 - 2) >> 1, ocx0 = (x0 - 2) >> 1;
-    if (X1M == 2) {
+    if constexpr (X1M == 2) {
         stage_half<OPW, OPH>(s_o, x0h + (size_t)r * nc * nc, nc, ocy0, ocx0);
         __syncthreads();
-        const float os = x0s[r];
-        for (int e = tid; e < XH * XW; e += 256) {
-            int py = e / XW, px = e - py * XW;
-            int gi = y0 - 2 + py, gj = x0 - 2 + px;
-            s_x0[py][px] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? x0_from_half<OPW>(s_o, ocy0, ocx0, gi, gj, os)
-                                                                   : zero;
-        }
+        x0_patch_from_half<OPW, XH, XW>(s_x0, s_o, y0 - 2, x0 - 2, n, x0s[r]);
     }
     __syncthreads();
 #pragma unroll
