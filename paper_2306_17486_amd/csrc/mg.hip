@@ -220,8 +220,12 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
     if constexpr (X0M == 2) x0_patch_from_half<OPW, PH, PW>(s_x0, s_o, fy0, fx0, n, x0s[r]);
     __syncthreads();
     if (HAS_X0) {
-        // x1 = x0 + w (b - A_SL x0)/diag on rows/cols 1..P-2
-        for (int e = tid; e < PH * PW; e += 256) {
+        // x1 = x0 + w (b - A_SL x0)/diag on rows/cols 1..P-2 (the staging's
+        // thread-to-cell map, so its index work is reused)
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int e = tid + j * 256;
+            if (e >= PH * PW) break;
             int py = e / PW, px = e - py * PW;
             int gi = fy0 + py, gj = fx0 + px;
             bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
@@ -246,7 +250,10 @@ __global__ void __launch_bounds__(256) k_vc_down(const float2* __restrict__ b, s
     }
     // residual r = b - A_SL x1 on rows/cols R0 .. P-1-R0 (the FW support)
     constexpr int R0 = HALO - 1;
-    for (int e = tid; e < PH * PW; e += 256) {
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int e = tid + j * 256;
+        if (e >= PH * PW) break;
         int py = e / PW, px = e - py * PW;
         if (py < R0 || py > PH - 1 - R0 || px < R0 || px > PW - 1 - R0) continue;
         int gi = fy0 + py, gj = fx0 + px;
