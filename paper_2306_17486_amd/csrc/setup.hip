@@ -201,37 +201,6 @@ __device__ void build_tblock(double2* A, const float2* cf, int k, int m, double 
     __syncthreads();
 }
 
-// C (+)= alpha A B for m x m FP64 complex matrices (row-major), one workgroup,
-// 32 x 32 output tiles through LDS.  C must not alias A or B.
-__device__ void zgemm_wg(double2* C, const double2* A, const double2* B, int m, double alpha, bool accumulate) {
-    constexpr int T = 32;
-    __shared__ double2 sa[T][T + 1];
-    __shared__ double2 sb[T][T + 1];
-    const int tid = threadIdx.x;  // blockDim.x == 1024: one output entry of the tile per thread
-    const int ty = tid / T, tx = tid % T;
-    const int nt = (m + T - 1) / T;
-    for (int bi = 0; bi < nt; ++bi)
-        for (int bj = 0; bj < nt; ++bj) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int bk = 0; bk < nt; ++bk) {
-                const int ar = bi * T + ty, ac = bk * T + tx;
-                const int br = bk * T + ty, bc = bj * T + tx;
-                sa[ty][tx] = (ar < m && ac < m) ? A[(size_t)ar * m + ac] : make_double2(0.0, 0.0);
-                sb[ty][tx] = (br < m && bc < m) ? B[(size_t)br * m + bc] : make_double2(0.0, 0.0);
-                __syncthreads();
-#pragma unroll 8
-                for (int k = 0; k < T; ++k) acc = zadd(acc, zmul(sa[ty][k], sb[k][tx]));
-                __syncthreads();
-            }
-            const int r = bi * T + ty, cc = bj * T + tx;
-            if (r < m && cc < m) {
-                const double2 v = make_double2(alpha * acc.x, alpha * acc.y);
-                C[(size_t)r * m + cc] = accumulate ? zadd(C[(size_t)r * m + cc], v) : v;
-            }
-        }
-    __syncthreads();
-}
-
 // store alpha * A (FP64, row-major) transposed in single precision
 __device__ void store_slot(const double2* A, float2* slot, int m, double alpha) {
     for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
@@ -257,113 +226,340 @@ __global__ void __launch_bounds__(1024) k_cr_vinv(const float2* __restrict__ coe
     store_slot(V, F + ((size_t)inst * 4 * M + 3 * M + j) * mm, m, 1.0);
 }
 
-// A <- D_j = T_{2j} - c^2 ([j >= 1] V_{j-1} + [j < Mo] V_j)
-__device__ void build_dblock(double2* A, const float2* cf, const double2* Vinst, int j, int m, double c,
-                             double beta) {
-    const int Mo = cr_Mo(m);
-    const size_t mm = (size_t)m * m;
-    build_tblock(A, cf, 2 * j, m, c, beta);
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        double2 v = A[e];
-        if (j >= 1) {
-            const double2 a = Vinst[(size_t)(j - 1) * mm + e];
-            v.x -= c * c * a.x;
-            v.y -= c * c * a.y;
+// ---------------------------------------------------------------------------
+// Tile-parallel factorisation of the reduced chains.  A chain step (one row j)
+// is a handful of m x m FP64 products and one inversion; each of these is
+// spread over 32 x 32 output tiles, one workgroup per tile, chain and medium,
+// and the step's phases are separate launches:
+//   couple: T = Q_prev V_c                       (V_c: the block coupling j to the previous row)
+//   schur:  A = D_j - c^4 V_c T                  (middle row: both ends' terms)
+//   invert: A <- A^{-1}, blocked Gauss-Jordan over 32-wide panels (below)
+//   store:  slots Q_j, P_j = c^2 Q_j V_c, R_j = c^2 Q_j V_n (complex single, transposed)
+// Q_j stays in one of two FP64 buffers per chain (alternating with the step's
+// parity) for the next step's coupling.
+// Scratch per medium: three chain blocks (top, bottom, middle) of
+// cf_chain_len(m) FP64 complex: A[2] (m x m), T (m x m), C (m x 32), P (32 x 32).
+// ---------------------------------------------------------------------------
+static inline __device__ __host__ size_t cf_chain_len(int m) { return 3 * (size_t)m * m + 32 * (size_t)m + 1024; }
+
+// acc[r] += X[r0 + ty + 8 r][k] Y[k][c0 + tx] over k < kn (X rows < xr, Y columns < yc; the rest reads
+// as zero).  256 threads, tx = tid % 32, ty = tid / 32.
+__device__ void tile_mac(double2 (&acc)[4], const double2* __restrict__ X, int ldx, int xr,
+                         const double2* __restrict__ Y, int ldy, int yc, int kn, int r0, int c0) {
+    __shared__ double2 sx[32][33];
+    __shared__ double2 sy[32][33];
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    const double2 z = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < kn; k0 += 32) {
+        double2 vx[4], vy[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ty + 8 * q;
+            vx[q] = (r0 + r < xr && k0 + tx < kn) ? X[(size_t)(r0 + r) * ldx + k0 + tx] : z;
+            vy[q] = (k0 + r < kn && c0 + tx < yc) ? Y[(size_t)(k0 + r) * ldy + c0 + tx] : z;
         }
-        if (j < Mo) {
-            const double2 a = Vinst[(size_t)j * mm + e];
-            v.x -= c * c * a.x;
-            v.y -= c * c * a.y;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sx[ty + 8 * q][tx] = vx[q];
+            sy[ty + 8 * q][tx] = vy[q];
         }
-        A[e] = v;
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) {
+            const double2 b = sy[kk][tx];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = zadd(acc[q], zmul(sx[ty + 8 * q][kk], b));
+        }
+        __syncthreads();
+    }
+}
+
+// Blocked Gauss-Jordan inversion without pivoting of m x m FP64 matrices, one
+// panel K (columns and rows [32 K, 32 K + 32)) per three launches; with the
+// panel's pivot block P = A_KK:
+//   1: A_KJ <- P^{-1} A_KJ  (J != K)                    one workgroup per column tile J
+//   2: A_IJ <- A_IJ - A_IK A_KJ,  C_I = -A_IK P^{-1}    one workgroup per tile (I != K)
+//   3: A_IK <- C_I,  A_KK <- P^{-1}                     one workgroup per row tile I
+// which is the scalar in-place elimination applied to 32 x 32 blocks (every
+// pivot block is a principal block of a Schur complement, nonsingular for the
+// same reason as the scalar pivots).  P^{-1} is formed in LDS by the scalar
+// elimination, the ragged last panel padded with the identity.  Matrices:
+// X + inst * xi + z * xz for z = blockIdx.y (skipped where bit z of skip is set,
+// z < 32), inst = blockIdx.z; scratch C (m x 32) and P^{-1} (32 x 32) at
+// S + inst * si + z * sz.
+struct BlkInv {
+    double2* X;
+    size_t xz, xi;
+    double2* S;
+    size_t sz, si;
+    unsigned skip;
+};
+
+__global__ void __launch_bounds__(256) k_blkinv_row(BlkInv b, int m, int K) {
+    const int z = blockIdx.y, inst = blockIdx.z;
+    if (z < 32 && ((b.skip >> z) & 1u)) return;
+    double2* A = b.X + inst * b.xi + z * b.xz;
+    double2* Pv = b.S + inst * b.si + z * b.sz + 32 * (size_t)m;
+    const int k0 = 32 * K, bk = min(32, m - k0), J = blockIdx.x, j0 = 32 * J, bj = min(32, m - j0);
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    __shared__ double2 P[32][33];
+    __shared__ double2 Y[32][33];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        P[r][tx] = (r < bk && tx < bk) ? A[(size_t)(k0 + r) * m + k0 + tx]
+                                       : make_double2(r == tx ? 1.0 : 0.0, 0.0);
+        if (J != K) Y[r][tx] = (r < bk && tx < bj) ? A[(size_t)(k0 + r) * m + j0 + tx] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-}
-
-// The two chains of the reduced system: blockIdx.x = instance, blockIdx.y = 0 (top) / 1 (bottom).
-// Scratch W per instance: [6][m][m] FP64: A, Qprev (top), A, Qprev (bottom), T1, T2 (temporaries
-// of the top chain; the bottom chain uses the next two) -- laid out as [chain][3][m][m].
-__global__ void __launch_bounds__(1024) k_cr_chain(const float2* __restrict__ coef, const double2* __restrict__ Vd,
-                                                   double2* __restrict__ W, float2* __restrict__ F, int m,
-                                                   double H, double beta) {
-    const int inst = blockIdx.x;
-    const bool top = blockIdx.y == 0;
-    const int M = cr_M(m), Mo = cr_Mo(m), p = M / 2;
-    const size_t mm = (size_t)m * m;
-    const double c = 1.0 / (H * H), c2 = c * c;
-    const float2* cf = coef + (size_t)inst * mm;
-    const double2* Vi = Vd + (size_t)inst * Mo * mm;
-    double2* base = W + ((size_t)inst * 2 + (top ? 0 : 1)) * 4 * mm;
-    double2* A = base;            // S_j, then Q_j
-    double2* Qp = base + mm;      // Q of the previous step
-    double2* T1 = base + 2 * mm;  // temporaries
-    double2* T2 = base + 3 * mm;
-    float2* Fi = F + (size_t)inst * 4 * M * mm;
-    const int first = top ? 0 : M - 1, last = top ? p - 1 : p + 1, dir = top ? 1 : -1;
-    if (top ? (p < 1) : (M - 1 <= p)) return;  // empty chain
-    for (int j = first;; j += dir) {
-        build_dblock(A, cf, Vi, j, m, c, beta);
-        if (j != first) {
-            // the coupling block between j and the previous row: V_{j-1} (top) or V_j (bottom)
-            const double2* Vc = Vi + (size_t)(top ? j - 1 : j) * mm;
-            zgemm_wg(T1, Qp, Vc, m, 1.0, false);      // Q_prev V
-            zgemm_wg(A, Vc, T1, m, -c2 * c2, true);    // S_j -= c^4 V Q_prev V
-        }
-        invert_inplace(A, m);                          // A = Q_j
-        store_slot(A, Fi + (size_t)j * mm, m, 1.0);
-        // P_j: couples to the previous row (exists unless j is the first of the chain)
-        if (j != first) {
-            const double2* Vc = Vi + (size_t)(top ? j - 1 : j) * mm;
-            zgemm_wg(T2, A, Vc, m, c2, false);
-            store_slot(T2, Fi + (size_t)(M + j) * mm, m, 1.0);
-        }
-        // R_j: couples to the next row towards the middle: V_j (top) or V_{j-1} (bottom)
-        {
-            const double2* Vn = Vi + (size_t)(top ? j : j - 1) * mm;
-            zgemm_wg(T2, A, Vn, m, c2, false);
-            store_slot(T2, Fi + (size_t)(2 * M + j) * mm, m, 1.0);
-        }
-        // keep Q_j for the next step (and for the middle row)
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) Qp[e] = A[e];
+    for (int q0 = 0; q0 < 32; ++q0) {
+        const double2 a = P[q0][q0];
+        const double den = a.x * a.x + a.y * a.y;
+        const double2 piv = make_double2(a.x / den, -a.y / den);
+        const double2 rq = zmul(P[q0][tx], piv);  // the pivot row, scaled
+        double2 f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) f[q] = P[ty + 8 * q][q0];
         __syncthreads();
-        if (j == last) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ty + 8 * q;
+            if (r == q0) P[r][tx] = tx == q0 ? piv : rq;
+            else if (tx == q0) P[r][tx] = zmul(make_double2(-f[q].x, -f[q].y), piv);
+            else P[r][tx] = zsub(P[r][tx], zmul(f[q], rq));
+        }
+        __syncthreads();
+    }
+    if (J == K) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Pv[(ty + 8 * q) * 32 + tx] = P[ty + 8 * q][tx];
+        return;
+    }
+    double2 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+        const double2 y = Y[kk][tx];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = zadd(acc[q], zmul(P[ty + 8 * q][kk], y));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        if (r < bk && tx < bj) A[(size_t)(k0 + r) * m + j0 + tx] = acc[q];
     }
 }
 
-// middle row: blockIdx.x = instance; uses the chains' last Q (W[.][0|1][1]).
-__global__ void __launch_bounds__(1024) k_cr_mid(const float2* __restrict__ coef, const double2* __restrict__ Vd,
-                                                 double2* __restrict__ W, double2* __restrict__ Wm,
-                                                 float2* __restrict__ F, int m, double H, double beta) {
-    const int inst = blockIdx.x;
+__global__ void __launch_bounds__(256) k_blkinv_update(BlkInv b, int m, int K) {
+    const int z = blockIdx.y, inst = blockIdx.z;
+    if (z < 32 && ((b.skip >> z) & 1u)) return;
+    const int nt = (m + 31) / 32, I = blockIdx.x / nt, J = blockIdx.x - I * nt;
+    if (I == K) return;
+    double2* A = b.X + inst * b.xi + z * b.xz;
+    double2* C = b.S + inst * b.si + z * b.sz;
+    const double2* Pv = C + 32 * (size_t)m;
+    const int k0 = 32 * K, bk = min(32, m - k0), i0 = 32 * I, j0 = 32 * J;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    double2 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+    if (J != K) {
+        tile_mac(acc, A + k0, m, m, A + (size_t)k0 * m, m, m, bk, i0, j0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = i0 + ty + 8 * q, c = j0 + tx;
+            if (r < m && c < m) A[(size_t)r * m + c] = zsub(A[(size_t)r * m + c], acc[q]);
+        }
+    } else {
+        tile_mac(acc, A + k0, m, m, Pv, 32, bk, bk, i0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = i0 + ty + 8 * q;
+            if (r < m) C[(size_t)r * 32 + tx] = make_double2(-acc[q].x, -acc[q].y);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_blkinv_col(BlkInv b, int m, int K) {
+    const int z = blockIdx.y, inst = blockIdx.z;
+    if (z < 32 && ((b.skip >> z) & 1u)) return;
+    double2* A = b.X + inst * b.xi + z * b.xz;
+    const double2* C = b.S + inst * b.si + z * b.sz;
+    const double2* Pv = C + 32 * (size_t)m;
+    const int k0 = 32 * K, bk = min(32, m - k0), I = blockIdx.x, i0 = 32 * I;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    if (tx >= bk) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        if (i0 + r >= m) break;
+        A[(size_t)(i0 + r) * m + k0 + tx] = I == K ? Pv[r * 32 + tx] : C[(size_t)(i0 + r) * 32 + tx];
+    }
+}
+
+static hh_status blk_invert(hipStream_t st, const BlkInv& b, int nz, int ninst, int m) {
+    const int nt = (m + 31) / 32;
+    for (int K = 0; K < nt; ++K) {
+        hipLaunchKernelGGL(k_blkinv_row, dim3(nt, nz, ninst), dim3(256), 0, st, b, m, K);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_blkinv_update, dim3(nt * nt, nz, ninst), dim3(256), 0, st, b, m, K);
+        HH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_blkinv_col, dim3(nt, nz, ninst), dim3(256), 0, st, b, m, K);
+        HH_LAUNCH_CHECK();
+    }
+    return HH_OK;
+}
+
+// Chain bookkeeping: chain e = 0 (top) takes rows j = s for steps s < p, chain
+// e = 1 (bottom) rows j = M - 1 - s for s < M - 1 - p; the middle row p is
+// their common next row.  Coupling block to the previous row: V_{j-1} (top),
+// V_j (bottom); to the next row: V_j (top), V_{j-1} (bottom).
+static inline __device__ __host__ int cf_nsteps(int m, int e) {
+    const int M = cr_M(m), p = M / 2;
+    return e == 0 ? p : M - 1 - p;
+}
+
+// couple: T_e = Q_prev V_c for step s of chain e (mid: the step onto row p).
+// grid: (tiles, 2, instances)
+__global__ void __launch_bounds__(256) k_cf_couple(const double2* __restrict__ Vd, double2* __restrict__ W, int m,
+                                                   int s, int mid) {
+    const int e = blockIdx.y, inst = blockIdx.z;
+    const int n = cf_nsteps(m, e);
+    const int se = mid ? n : s;
+    if (se < 1 || (!mid && se >= n)) return;
+    const int M = cr_M(m), Mo = cr_Mo(m), j = e == 0 ? se : M - 1 - se;
+    const size_t mm = (size_t)m * m, CH = cf_chain_len(m);
+    const double2* Vc = Vd + ((size_t)inst * Mo + (e == 0 ? j - 1 : j)) * mm;
+    double2* Wc = W + ((size_t)inst * 3 + e) * CH;
+    const int nt = (m + 31) / 32, ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    double2 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+    tile_mac(acc, Wc + ((se - 1) & 1) * mm, m, m, Vc, m, m, m, 32 * ti, 32 * tj);
+    double2* T = Wc + 2 * mm;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 32 * ti + ty + 8 * q, c = 32 * tj + tx;
+        if (r < m && c < m) T[(size_t)r * m + c] = acc[q];
+    }
+}
+
+// schur: A = D_j - c^4 sum V_c T with D_j = T_{2j} - c^2 ([j >= 1] V_{j-1} + [j < Mo] V_j).
+// grid: (tiles, 2 (chains) or 1 (mid), instances)
+__global__ void __launch_bounds__(256) k_cf_schur(const float2* __restrict__ coef, const double2* __restrict__ Vd,
+                                                  double2* __restrict__ W, int m, double H, double beta, int s,
+                                                  int mid) {
+    const int inst = blockIdx.z;
     const int M = cr_M(m), Mo = cr_Mo(m), p = M / 2;
-    const size_t mm = (size_t)m * m;
-    const double c = 1.0 / (H * H), c2 = c * c;
+    const size_t mm = (size_t)m * m, CH = cf_chain_len(m);
     const double2* Vi = Vd + (size_t)inst * Mo * mm;
-    const double2* Qtop = W + ((size_t)inst * 2 + 0) * 4 * mm + mm;
-    const double2* Qbot = W + ((size_t)inst * 2 + 1) * 4 * mm + mm;
-    double2* A = Wm + (size_t)inst * 2 * mm;
-    double2* T1 = A + mm;
-    float2* Fi = F + (size_t)inst * 4 * M * mm;
-    build_dblock(A, coef + (size_t)inst * mm, Vi, p, m, c, beta);
-    if (p >= 1) {
-        const double2* Vc = Vi + (size_t)(p - 1) * mm;
-        zgemm_wg(T1, Qtop, Vc, m, 1.0, false);
-        zgemm_wg(A, Vc, T1, m, -c2 * c2, true);
+    double2* Wi = W + (size_t)inst * 3 * CH;
+    const int nt = (m + 31) / 32, ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    double2 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+    int j;
+    double2* A;
+    if (mid) {
+        j = p;
+        A = Wi + 2 * CH;
+        if (cf_nsteps(m, 0) >= 1) tile_mac(acc, Vi + (size_t)(p - 1) * mm, m, m, Wi + 2 * mm, m, m, m, 32 * ti, 32 * tj);
+        if (cf_nsteps(m, 1) >= 1)
+            tile_mac(acc, Vi + (size_t)p * mm, m, m, Wi + CH + 2 * mm, m, m, m, 32 * ti, 32 * tj);
+    } else {
+        const int e = blockIdx.y;
+        if (s >= cf_nsteps(m, e)) return;
+        j = e == 0 ? s : M - 1 - s;
+        double2* Wc = Wi + e * CH;
+        A = Wc + (s & 1) * mm;
+        if (s >= 1) tile_mac(acc, Vi + (size_t)(e == 0 ? j - 1 : j) * mm, m, m, Wc + 2 * mm, m, m, m, 32 * ti, 32 * tj);
     }
-    if (p + 1 <= M - 1) {
-        const double2* Vc = Vi + (size_t)p * mm;
-        zgemm_wg(T1, Qbot, Vc, m, 1.0, false);
-        zgemm_wg(A, Vc, T1, m, -c2 * c2, true);
+    const double c = 1.0 / (H * H), c2 = c * c, c4 = c2 * c2;
+    const float2* cf = coef + (size_t)inst * mm + (size_t)(2 * j) * m;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 32 * ti + ty + 8 * q, col = 32 * tj + tx;
+        if (r >= m || col >= m) continue;
+        const size_t o = (size_t)r * m + col;
+        double2 v = make_double2(-c4 * acc[q].x, -c4 * acc[q].y);
+        if (r == col) {
+            const float2 cc = cf[r];
+            const double w2k2 = cc.x, g = cc.y;
+            v.x += 4.0 * c - w2k2;
+            v.y += w2k2 * (g + beta);
+        } else if (col == r - 1 || col == r + 1) {
+            v.x -= c;
+        }
+        if (j >= 1) {
+            const double2 a = Vi[(size_t)(j - 1) * mm + o];
+            v.x -= c2 * a.x;
+            v.y -= c2 * a.y;
+        }
+        if (j < Mo) {
+            const double2 a = Vi[(size_t)j * mm + o];
+            v.x -= c2 * a.x;
+            v.y -= c2 * a.y;
+        }
+        A[o] = v;
     }
-    invert_inplace(A, m);
-    store_slot(A, Fi + (size_t)p * mm, m, 1.0);
-    if (p >= 1) {
-        zgemm_wg(T1, A, Vi + (size_t)(p - 1) * mm, m, c2, false);
-        store_slot(T1, Fi + (size_t)(M + p) * mm, m, 1.0);
+}
+
+// store: slots Q_j (role 0), P_j = c^2 Q_j V_c (role 1), R_j = c^2 Q_j V_n (role 2), transposed through LDS.
+// grid: (3 * tiles, 2 (chains) or 1 (mid), instances)
+__global__ void __launch_bounds__(256) k_cf_store(const double2* __restrict__ Vd, const double2* __restrict__ W,
+                                                  float2* __restrict__ F, int m, double H, int s, int mid) {
+    const int inst = blockIdx.z;
+    const int M = cr_M(m), Mo = cr_Mo(m), p = M / 2;
+    const size_t mm = (size_t)m * m, CH = cf_chain_len(m);
+    const double2* Vi = Vd + (size_t)inst * Mo * mm;
+    const double2* Wi = W + (size_t)inst * 3 * CH;
+    const int nt = (m + 31) / 32, role = blockIdx.x / (nt * nt), t = blockIdx.x - role * nt * nt;
+    const int ti = t / nt, tj = t - ti * nt;
+    int j;
+    const double2 *Q, *Vc, *Vn;
+    if (mid) {
+        j = p;
+        Q = Wi + 2 * CH;
+        Vc = p >= 1 ? Vi + (size_t)(p - 1) * mm : nullptr;
+        Vn = p + 1 <= M - 1 ? Vi + (size_t)p * mm : nullptr;
+    } else {
+        const int e = blockIdx.y;
+        if (s >= cf_nsteps(m, e)) return;
+        j = e == 0 ? s : M - 1 - s;
+        Q = Wi + e * CH + (s & 1) * mm;
+        Vc = s >= 1 ? Vi + (size_t)(e == 0 ? j - 1 : j) * mm : nullptr;
+        Vn = Vi + (size_t)(e == 0 ? j : j - 1) * mm;
     }
-    if (p + 1 <= M - 1) {
-        zgemm_wg(T1, A, Vi + (size_t)p * mm, m, c2, false);
-        store_slot(T1, Fi + (size_t)(2 * M + p) * mm, m, 1.0);
+    const double2* Vr = role == 1 ? Vc : Vn;
+    if (role > 0 && !Vr) return;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    double2 acc[4];
+    double alpha = 1.0;
+    if (role == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 32 * ti + ty + 8 * q, c = 32 * tj + tx;
+            acc[q] = (r < m && c < m) ? Q[(size_t)r * m + c] : make_double2(0.0, 0.0);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+        tile_mac(acc, Q, m, m, Vr, m, m, m, 32 * ti, 32 * tj);
+        const double c = 1.0 / (H * H);
+        alpha = c * c;
+    }
+    __shared__ float2 so[32][33];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) so[ty + 8 * q][tx] = make_float2((float)(alpha * acc[q].x), (float)(alpha * acc[q].y));
+    __syncthreads();
+    float2* slot = F + ((size_t)inst * 4 * M + (size_t)role * M + j) * mm;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = 32 * tj + ty + 8 * q, r = 32 * ti + tx;  // slot[c][r] = M[r][c]
+        if (r < m && c < m) slot[(size_t)c * m + r] = so[tx][ty + 8 * q];
     }
 }
 
@@ -465,21 +661,49 @@ static hh_status setup_coarse_reduced(hh_model* md) {
     md->m = m;
     md->cr1 = true;
     HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * 4 * M * mm * sizeof(float2)));
-    Buf Vd, W, Wm;
+    Buf Vd, W;
+    const size_t CH = cf_chain_len(m);
     HH_TRY(Vd.ensure(ctx, (size_t)md->ninst * std::max(Mo, 1) * mm * sizeof(double2)));
-    HH_TRY(W.ensure(ctx, (size_t)md->ninst * 8 * mm * sizeof(double2)));
-    HH_TRY(Wm.ensure(ctx, (size_t)md->ninst * 2 * mm * sizeof(double2)));
+    HH_TRY(W.ensure(ctx, (size_t)md->ninst * 3 * CH * sizeof(double2)));
+    hipStream_t st = ctx->stream;
     if (Mo > 0) {
-        hipLaunchKernelGGL(k_cr_vinv, dim3(Mo, md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
+        hipLaunchKernelGGL(k_cr_vinv, dim3(Mo, md->ninst), dim3(1024), 0, st, C.coef.as<float2>(),
                            Vd.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
         HH_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_cr_chain, dim3(md->ninst, 2), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
-                       Vd.as<double2>(), W.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
-    HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cr_mid, dim3(md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(), Vd.as<double2>(),
-                       W.as<double2>(), Wm.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
-    HH_LAUNCH_CHECK();
+    {
+        const int nt = (m + 31) / 32, ntop = cf_nsteps(m, 0), nbot = cf_nsteps(m, 1), ni = md->ninst;
+        const double beta = md->d.sl_beta;
+        double2* Wd = W.as<double2>();
+        const double2* Vp = Vd.as<double2>();
+        float2* F = md->coarseQT.as<float2>();
+        for (int s = 0; s < std::max(ntop, nbot); ++s) {  // both chains, one row each per step
+            if (s >= 1) {
+                hipLaunchKernelGGL(k_cf_couple, dim3(nt * nt, 2, ni), dim3(256), 0, st, Vp, Wd, m, s, 0);
+                HH_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_cf_schur, dim3(nt * nt, 2, ni), dim3(256), 0, st, C.coef.as<float2>(), Vp, Wd, m,
+                               C.h, beta, s, 0);
+            HH_LAUNCH_CHECK();
+            const BlkInv b{Wd + (s & 1) * mm, CH, 3 * CH, Wd + 3 * mm, CH, 3 * CH,
+                           (s >= ntop ? 1u : 0u) | (s >= nbot ? 2u : 0u)};
+            HH_TRY(blk_invert(st, b, 2, ni, m));
+            hipLaunchKernelGGL(k_cf_store, dim3(3 * nt * nt, 2, ni), dim3(256), 0, st, Vp, Wd, F, m, C.h, s, 0);
+            HH_LAUNCH_CHECK();
+        }
+        // the middle row, coupled to both chains' last rows
+        if (ntop >= 1 || nbot >= 1) {
+            hipLaunchKernelGGL(k_cf_couple, dim3(nt * nt, 2, ni), dim3(256), 0, st, Vp, Wd, m, 0, 1);
+            HH_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_cf_schur, dim3(nt * nt, 1, ni), dim3(256), 0, st, C.coef.as<float2>(), Vp, Wd, m, C.h,
+                           beta, 0, 1);
+        HH_LAUNCH_CHECK();
+        const BlkInv bm{Wd + 2 * CH, 0, 3 * CH, Wd + 2 * CH + 3 * mm, 0, 3 * CH, 0u};
+        HH_TRY(blk_invert(st, bm, 1, ni, m));
+        hipLaunchKernelGGL(k_cf_store, dim3(3 * nt * nt, 1, ni), dim3(256), 0, st, Vp, Wd, F, m, C.h, 0, 1);
+        HH_LAUNCH_CHECK();
+    }
     md->cr_depth = md->d.coarse_reduce - 1;
     if (md->cr_depth > 0) {
         const int p = M / 2, D = md->cr_depth;

@@ -77,7 +77,8 @@ def test_operator_complex_symmetry(hh, ctx):
                                                      (128, "grf", True, 2), (100, "layered", False, 2),
                                                      (116, "grf", False, 2), (128, "layered", False, 3),
                                                      (116, "grf", True, 3), (100, "grf", False, 4),
-                                                     (128, "grf", False, 4)])
+                                                     (128, "grf", False, 4), (200, "grf", False, 1),
+                                                     (232, "layered", True, 4)])
 def test_vcycle_parity(hh, ctx, n, family, with_x0, reduce):
     _say(f"vcycle parity n={n} {family} x0={with_x0} reduced coarse factorisation {reduce}")
     k = inputs.slowness(n, 12, family)
