@@ -43,204 +43,13 @@ __global__ void k_coef_restrict(const float2* __restrict__ fine, float2* __restr
     coarse[((size_t)inst * nc + I) * nc + J] = make_float2(sx, sy);
 }
 
-// ---------------------------------------------------------------------------
-// Coarsest-level direct solver.  The shifted operator on an m x m grid is block
-// tridiagonal in grid rows: diagonal blocks T_k (tridiagonal, 4/H^2 - mass on
-// the diagonal, -1/H^2 off it) and off-diagonal blocks -c I with c = 1/H^2.
-// The rows are eliminated from both ends towards the middle row p = m/2
-// ("burn at both ends"), which halves the sequential chain:
-//   top:    S_0 = T_0,         S_k = T_k - c^2 S_{k-1}^{-1}   (k = 0 .. p-1)
-//   bottom: S_{m-1} = T_{m-1}, S_k = T_k - c^2 S_{k+1}^{-1}   (k = m-1 .. p+1)
-//   middle: S_p = T_p - c^2 S_{p-1}^{-1} - c^2 S_{p+1}^{-1}
-// The inverses Q_k = S_k^{-1} are formed in FP64 (in-place Gauss-Jordan without
-// pivoting) and stored transposed in complex single precision:
-// QT[k][j][i] = Q_k[i][j].  -i A_SL has a positive definite Hermitian part
-// (omega^2 kappa^2 (gamma + beta) > 0 on the diagonal), which keeps every Schur
-// complement nonsingular without pivoting.
-// ---------------------------------------------------------------------------
-
-// A <- T_k - c^2 (P1 + P2)   (P1, P2 may be null)
-__device__ void build_schur(double2* A, const double2* P1, const double2* P2, const float2* cf, int k, int m,
-                            double c, double beta) {
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        int i = e / m, j = e - i * m;
-        double2 v = make_double2(0.0, 0.0);
-        if (P1) v = zadd(v, P1[e]);
-        if (P2) v = zadd(v, P2[e]);
-        v = make_double2(-c * c * v.x, -c * c * v.y);
-        if (i == j) {
-            float2 cc = cf[(size_t)k * m + i];
-            double w2k2 = cc.x, g = cc.y;
-            // diagonal: 4c - omega^2 kappa^2 (1 - i (gamma + beta))
-            v.x += 4.0 * c - w2k2;
-            v.y += w2k2 * (g + beta);
-        } else if (j == i - 1 || j == i + 1) {
-            v.x += -c;
-        }
-        A[e] = v;
-    }
-    __syncthreads();
-}
-
-// In-place Gauss-Jordan inversion without pivoting (one workgroup).
-__device__ void invert_inplace(double2* A, int m) {
-    __shared__ double2 piv_s;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int p = 0; p < m; ++p) {
-        if (tid == 0) {
-            double2 a = A[(size_t)p * m + p];
-            double den = a.x * a.x + a.y * a.y;
-            piv_s = make_double2(a.x / den, -a.y / den);
-        }
-        __syncthreads();
-        const double2 piv = piv_s;
-        for (int j = tid; j < m; j += nt)
-            if (j != p) A[(size_t)p * m + j] = zmul(A[(size_t)p * m + j], piv);
-        __syncthreads();
-        for (int e = tid; e < m * m; e += nt) {
-            int i = e / m, j = e - i * m;
-            if (i == p || j == p) continue;
-            A[e] = zsub(A[e], zmul(A[(size_t)i * m + p], A[(size_t)p * m + j]));
-        }
-        __syncthreads();
-        for (int i = tid; i < m; i += nt) {
-            if (i != p) {
-                double2 a = A[(size_t)i * m + p];
-                A[(size_t)i * m + p] = zmul(make_double2(-a.x, -a.y), piv);
-            }
-        }
-        if (tid == 0) A[(size_t)p * m + p] = piv;
-        __syncthreads();
-    }
-}
-
-// ... then store the transpose in single precision
-__device__ void invert_store(double2* A, float2* Qk, int m) {
-    invert_inplace(A, m);
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        int i = e / m, j = e - i * m;
-        double2 v = A[e];
-        Qk[(size_t)j * m + i] = make_float2((float)v.x, (float)v.y);
-    }
-    __syncthreads();
-}
-
-// blockIdx.x = instance, blockIdx.y = 0 (top chain) or 1 (bottom chain).
-// Scratch S per instance: [3][m][m] FP64 (top, bottom, middle).
-__global__ void __launch_bounds__(1024) k_coarse_factor_ends(const float2* __restrict__ coef, double2* __restrict__ S,
-                                                             float2* __restrict__ QT, int m, int p, double H,
-                                                             double beta) {
-    const int inst = blockIdx.x;
-    const bool top = blockIdx.y == 0;
-    const double c = 1.0 / (H * H);
-    const size_t mm = (size_t)m * m;
-    const float2* cf = coef + (size_t)inst * mm;
-    double2* A = S + (size_t)inst * 3 * mm + (top ? 0 : mm);
-    float2* Q = QT + (size_t)inst * mm * m;
-    if (top) {
-        for (int k = 0; k < p; ++k) {
-            build_schur(A, k > 0 ? A : nullptr, nullptr, cf, k, m, c, beta);
-            invert_store(A, Q + (size_t)k * mm, m);
-        }
-    } else {
-        for (int k = m - 1; k > p; --k) {
-            build_schur(A, k < m - 1 ? A : nullptr, nullptr, cf, k, m, c, beta);
-            invert_store(A, Q + (size_t)k * mm, m);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(1024) k_coarse_factor_mid(const float2* __restrict__ coef, double2* __restrict__ S,
-                                                            float2* __restrict__ QT, int m, int p, double H,
-                                                            double beta) {
-    const int inst = blockIdx.x;
-    const double c = 1.0 / (H * H);
-    const size_t mm = (size_t)m * m;
-    double2* base = S + (size_t)inst * 3 * mm;
-    double2* A = base + 2 * mm;
-    build_schur(A, p > 0 ? base : nullptr, p < m - 1 ? base + mm : nullptr, coef + (size_t)inst * mm, p, m, c, beta);
-    invert_store(A, QT + (size_t)inst * mm * m + (size_t)p * mm, m);
-}
 
 // ---------------------------------------------------------------------------
-// One level of cyclic reduction before the two-ended elimination.  With V_j =
-// T_{2j+1}^{-1} (odd grid rows, j < Mo = floor(m/2)), eliminating the odd rows
-// leaves a block-tridiagonal system on the even rows 2j, j < M = ceil(m/2):
-//   D_j = T_{2j} - c^2 ([j >= 1] V_{j-1} + [j < Mo] V_j),  L_j = -c^2 V_{j-1},  U_j = -c^2 V_j,
-//   b'_j = b_{2j} + c ([j >= 1] V_{j-1} b_{2j-1} + [j < Mo] V_j b_{2j+1}),
-// and the odd rows follow from x_{2j+1} = V_j (b_{2j+1} + c x_{2j} + c x_{2j+2}).
-// The reduced system is eliminated from both ends towards p = M/2:
-//   top (j < p):      S_j = D_j - c^4 V_{j-1} Q_{j-1} V_{j-1},  P_j = c^2 Q_j V_{j-1},  R_j = c^2 Q_j V_j
-//   bottom (j > p):   S_j = D_j - c^4 V_j Q_{j+1} V_j,          P_j = c^2 Q_j V_j,      R_j = c^2 Q_j V_{j-1}
-//   middle:           S_p = D_p - c^4 V_{p-1} Q_{p-1} V_{p-1} - c^4 V_p Q_{p+1} V_p,
-//                     P_p = c^2 Q_p V_{p-1},  R_p = c^2 Q_p V_p
-// with Q_j = S_j^{-1}, so that the solve is
-//   g_j = Q_j b'_j;  y_j = g_j + P_j y_{j-/+1} (forward from each end);
-//   x_p = g_p + P_p y_{p-1} + R_p y_{p+1};  x_j = y_j + R_j x_{j+/-1} (backward).
-// Factors per instance, complex single, transposed (slot[c][r] = M[r][c]):
-// slots j (Q_j), M + j (P_j), 2M + j (R_j), 3M + j (V_j).
+// Building blocks of the coarsest-level factorisations: 32 x 32 tile products
+// and a blocked in-place inversion in FP64, one workgroup per output tile (and
+// per matrix and medium), so that every sequential step of an elimination is
+// spread over the whole chip.
 // ---------------------------------------------------------------------------
-static inline __device__ __host__ int cr_M(int m) { return (m + 1) / 2; }
-static inline __device__ __host__ int cr_Mo(int m) { return m / 2; }
-
-// A <- T_k (the shifted operator's grid-row block), dense FP64
-__device__ void build_tblock(double2* A, const float2* cf, int k, int m, double c, double beta) {
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        const int i = e / m, j = e - i * m;
-        double2 v = make_double2(0.0, 0.0);
-        if (i == j) {
-            const float2 cc = cf[(size_t)k * m + i];
-            const double w2k2 = cc.x, g = cc.y;
-            v.x = 4.0 * c - w2k2;
-            v.y = w2k2 * (g + beta);
-        } else if (j == i - 1 || j == i + 1) {
-            v.x = -c;
-        }
-        A[e] = v;
-    }
-    __syncthreads();
-}
-
-// store alpha * A (FP64, row-major) transposed in single precision
-__device__ void store_slot(const double2* A, float2* slot, int m, double alpha) {
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        const int i = e / m, j = e - i * m;
-        const double2 v = A[e];
-        slot[(size_t)j * m + i] = make_float2((float)(alpha * v.x), (float)(alpha * v.y));
-    }
-    __syncthreads();
-}
-
-
-// V_j = T_{2j+1}^{-1}: blockIdx.x = j (< Mo), blockIdx.y = instance.
-// Vd: FP64 copies [inst][Mo][m][m] (kept for the chain factorisation).
-__global__ void __launch_bounds__(1024) k_cr_vinv(const float2* __restrict__ coef, double2* __restrict__ Vd,
-                                                  float2* __restrict__ F, int m, double H, double beta) {
-    const int j = blockIdx.x, inst = blockIdx.y;
-    const int M = cr_M(m), Mo = cr_Mo(m);
-    const size_t mm = (size_t)m * m;
-    const double c = 1.0 / (H * H);
-    double2* V = Vd + ((size_t)inst * Mo + j) * mm;
-    build_tblock(V, coef + (size_t)inst * mm, 2 * j + 1, m, c, beta);
-    invert_inplace(V, m);
-    store_slot(V, F + ((size_t)inst * 4 * M + 3 * M + j) * mm, m, 1.0);
-}
-
-// ---------------------------------------------------------------------------
-// Tile-parallel factorisation of the reduced chains.  A chain step (one row j)
-// is a handful of m x m FP64 products and one inversion; each of these is
-// spread over 32 x 32 output tiles, one workgroup per tile, chain and medium,
-// and the step's phases are separate launches:
-//   couple: T = Q_prev V_c                       (V_c: the block coupling j to the previous row)
-//   schur:  A = D_j - c^4 V_c T                  (middle row: both ends' terms)
-//   invert: A <- A^{-1}, blocked Gauss-Jordan over 32-wide panels (below)
-//   store:  slots Q_j, P_j = c^2 Q_j V_c, R_j = c^2 Q_j V_n (complex single, transposed)
-// Q_j stays in one of two FP64 buffers per chain (alternating with the step's
-// parity) for the next step's coupling.
-// Scratch per medium: three chain blocks (top, bottom, middle) of
-// cf_chain_len(m) FP64 complex: A[2] (m x m), T (m x m), C (m x 32), P (32 x 32).
-// ---------------------------------------------------------------------------
-static inline __device__ __host__ size_t cf_chain_len(int m) { return 3 * (size_t)m * m + 32 * (size_t)m + 1024; }
 
 // acc[r] += X[r0 + ty + 8 r][k] Y[k][c0 + tx] over k < kn (X rows < xr, Y columns < yc; the rest reads
 // as zero).  256 threads, tx = tid % 32, ty = tid / 32.
@@ -302,37 +111,41 @@ __global__ void __launch_bounds__(256) k_blkinv_row(BlkInv b, int m, int K) {
     double2* Pv = b.S + inst * b.si + z * b.sz + 32 * (size_t)m;
     const int k0 = 32 * K, bk = min(32, m - k0), J = blockIdx.x, j0 = 32 * J, bj = min(32, m - j0);
     const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
-    __shared__ double2 P[32][33];
+    __shared__ double2 P[2][32][33];  // the elimination alternates between two copies: one barrier per pivot
     __shared__ double2 Y[32][33];
+    double2 vp[4], vy[4];  // all loads in flight before the first LDS store
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int r = ty + 8 * q;
-        P[r][tx] = (r < bk && tx < bk) ? A[(size_t)(k0 + r) * m + k0 + tx]
-                                       : make_double2(r == tx ? 1.0 : 0.0, 0.0);
-        if (J != K) Y[r][tx] = (r < bk && tx < bj) ? A[(size_t)(k0 + r) * m + j0 + tx] : make_double2(0.0, 0.0);
+        vp[q] = (r < bk && tx < bk) ? A[(size_t)(k0 + r) * m + k0 + tx] : make_double2(r == tx ? 1.0 : 0.0, 0.0);
+        vy[q] = (J != K && r < bk && tx < bj) ? A[(size_t)(k0 + r) * m + j0 + tx] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        P[0][ty + 8 * q][tx] = vp[q];
+        Y[ty + 8 * q][tx] = vy[q];
     }
     __syncthreads();
     for (int q0 = 0; q0 < 32; ++q0) {
-        const double2 a = P[q0][q0];
-        const double den = a.x * a.x + a.y * a.y;
-        const double2 piv = make_double2(a.x / den, -a.y / den);
-        const double2 rq = zmul(P[q0][tx], piv);  // the pivot row, scaled
-        double2 f[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) f[q] = P[ty + 8 * q][q0];
-        __syncthreads();
+        const double2(*Pc)[33] = P[q0 & 1];
+        double2(*Pn)[33] = P[(q0 & 1) ^ 1];
+        const double2 a = Pc[q0][q0];
+        const double rden = 1.0 / (a.x * a.x + a.y * a.y);
+        const double2 piv = make_double2(a.x * rden, -a.y * rden);
+        const double2 rq = zmul(Pc[q0][tx], piv);  // the pivot row, scaled
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = ty + 8 * q;
-            if (r == q0) P[r][tx] = tx == q0 ? piv : rq;
-            else if (tx == q0) P[r][tx] = zmul(make_double2(-f[q].x, -f[q].y), piv);
-            else P[r][tx] = zsub(P[r][tx], zmul(f[q], rq));
+            const double2 f = Pc[r][q0];
+            if (r == q0) Pn[r][tx] = tx == q0 ? piv : rq;
+            else if (tx == q0) Pn[r][tx] = zmul(make_double2(-f.x, -f.y), piv);
+            else Pn[r][tx] = zsub(Pc[r][tx], zmul(f, rq));
         }
         __syncthreads();
     }
     if (J == K) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Pv[(ty + 8 * q) * 32 + tx] = P[ty + 8 * q][tx];
+        for (int q = 0; q < 4; ++q) Pv[(ty + 8 * q) * 32 + tx] = P[0][ty + 8 * q][tx];
         return;
     }
     double2 acc[4];
@@ -342,7 +155,7 @@ __global__ void __launch_bounds__(256) k_blkinv_row(BlkInv b, int m, int K) {
     for (int kk = 0; kk < 32; ++kk) {
         const double2 y = Y[kk][tx];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = zadd(acc[q], zmul(P[ty + 8 * q][kk], y));
+        for (int q = 0; q < 4; ++q) acc[q] = zadd(acc[q], zmul(P[0][ty + 8 * q][kk], y));
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -410,6 +223,166 @@ static hh_status blk_invert(hipStream_t st, const BlkInv& b, int nz, int ninst, 
     }
     return HH_OK;
 }
+
+// slot(z, inst)[c][r] = X(z, inst)[r][c] in complex single precision, through LDS:
+// X(z, inst) = X + inst * xi + z * xz, slot(z, inst) = F + inst * fi + z * fz for
+// z = blockIdx.y (skipped where bit z of skip is set, z < 32), inst = blockIdx.z.
+// grid: (tiles, matrices, instances)
+__global__ void __launch_bounds__(256) k_tstore(const double2* __restrict__ X, size_t xz, size_t xi,
+                                                float2* __restrict__ F, long long fz, size_t fi, unsigned skip, int m) {
+    const int z = blockIdx.y, inst = blockIdx.z;
+    if (z < 32 && ((skip >> z) & 1u)) return;
+    const double2* A = X + inst * xi + z * xz;
+    float2* slot = F + inst * fi + (long long)z * fz;
+    const int nt = (m + 31) / 32, ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    __shared__ float2 so[32][33];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 32 * ti + ty + 8 * q, c = 32 * tj + tx;
+        const double2 v = (r < m && c < m) ? A[(size_t)r * m + c] : make_double2(0.0, 0.0);
+        so[ty + 8 * q][tx] = make_float2((float)v.x, (float)v.y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = 32 * tj + ty + 8 * q, r = 32 * ti + tx;
+        if (r < m && c < m) slot[(size_t)c * m + r] = so[tx][ty + 8 * q];
+    }
+}
+
+// Entry (r, col) of T_k, the shifted operator's block of grid row k (cf: that
+// row's coefficients): 4c - omega^2 kappa^2 (1 - i (gamma + beta)) on the
+// diagonal, -c beside it.
+__device__ __forceinline__ double2 tblock_entry(const float2* __restrict__ cf, int r, int col, double c, double beta) {
+    if (r == col) {
+        const float2 cc = cf[r];
+        const double w2k2 = cc.x, g = cc.y;
+        return make_double2(4.0 * c - w2k2, w2k2 * (g + beta));
+    }
+    return make_double2(col == r - 1 || col == r + 1 ? -c : 0.0, 0.0);
+}
+
+
+// ---------------------------------------------------------------------------
+// Coarsest-level direct solver.  The shifted operator on an m x m grid is block
+// tridiagonal in grid rows: diagonal blocks T_k (tridiagonal, 4/H^2 - mass on
+// the diagonal, -1/H^2 off it) and off-diagonal blocks -c I with c = 1/H^2.
+// The rows are eliminated from both ends towards the middle row p = m/2
+// ("burn at both ends"), which halves the sequential chain:
+//   top:    S_0 = T_0,         S_k = T_k - c^2 S_{k-1}^{-1}   (k = 0 .. p-1)
+//   bottom: S_{m-1} = T_{m-1}, S_k = T_k - c^2 S_{k+1}^{-1}   (k = m-1 .. p+1)
+//   middle: S_p = T_p - c^2 S_{p-1}^{-1} - c^2 S_{p+1}^{-1}
+// The inverses Q_k = S_k^{-1} are formed in FP64 (blocked Gauss-Jordan without
+// pivoting, above) and stored transposed in complex single precision:
+// QT[k][j][i] = Q_k[i][j].  -i A_SL has a positive definite Hermitian part
+// (omega^2 kappa^2 (gamma + beta) > 0 on the diagonal), which keeps every Schur
+// complement nonsingular without pivoting.
+// ---------------------------------------------------------------------------
+
+// Chains of the plain elimination: e = 0 takes rows k = s (s < p), e = 1 rows
+// k = m - 1 - s (s < m - 1 - p).  Scratch per medium: three blocks (top, bottom,
+// middle) of pf_chain_len(m) FP64 complex: A[2] (m x m, alternating with the
+// step's parity), C (m x 32) and P (32 x 32) of the blocked inversion.
+static inline __device__ __host__ int pf_nsteps(int m, int e) { return e == 0 ? m / 2 : m - 1 - m / 2; }
+static inline __device__ __host__ size_t pf_chain_len(int m) { return 2 * (size_t)m * m + 32 * (size_t)m + 1024; }
+
+// A = T_k - c^2 (the neighbouring rows' inverses): the previous step's (chains)
+// or both chains' last (middle row).  grid: (tiles, 2 (chains) or 1 (mid), instances)
+__global__ void __launch_bounds__(256) k_pf_schur(const float2* __restrict__ coef, double2* __restrict__ W, int m,
+                                                  double H, double beta, int s, int mid) {
+    const int inst = blockIdx.z;
+    const size_t mm = (size_t)m * m, CH = pf_chain_len(m);
+    double2* Wi = W + (size_t)inst * 3 * CH;
+    int k;
+    double2* A;
+    const double2 *P1 = nullptr, *P2 = nullptr;
+    if (mid) {
+        const int n0 = pf_nsteps(m, 0), n1 = pf_nsteps(m, 1);
+        k = m / 2;
+        A = Wi + 2 * CH;
+        if (n0 >= 1) P1 = Wi + ((n0 - 1) & 1) * mm;
+        if (n1 >= 1) P2 = Wi + CH + ((n1 - 1) & 1) * mm;
+    } else {
+        const int e = blockIdx.y;
+        if (s >= pf_nsteps(m, e)) return;
+        k = e == 0 ? s : m - 1 - s;
+        A = Wi + e * CH + (s & 1) * mm;
+        if (s >= 1) P1 = Wi + e * CH + ((s - 1) & 1) * mm;
+    }
+    const double c = 1.0 / (H * H), c2 = c * c;
+    const float2* cf = coef + (size_t)inst * mm + (size_t)k * m;
+    const int nt = (m + 31) / 32, ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 32 * ti + ty + 8 * q, col = 32 * tj + tx;
+        if (r >= m || col >= m) continue;
+        const size_t o = (size_t)r * m + col;
+        double2 v = make_double2(0.0, 0.0);
+        if (P1) v = zadd(v, P1[o]);
+        if (P2) v = zadd(v, P2[o]);
+        v = make_double2(-c2 * v.x, -c2 * v.y);
+        A[o] = zadd(v, tblock_entry(cf, r, col, c, beta));
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// One level of cyclic reduction before the two-ended elimination.  With V_j =
+// T_{2j+1}^{-1} (odd grid rows, j < Mo = floor(m/2)), eliminating the odd rows
+// leaves a block-tridiagonal system on the even rows 2j, j < M = ceil(m/2):
+//   D_j = T_{2j} - c^2 ([j >= 1] V_{j-1} + [j < Mo] V_j),  L_j = -c^2 V_{j-1},  U_j = -c^2 V_j,
+//   b'_j = b_{2j} + c ([j >= 1] V_{j-1} b_{2j-1} + [j < Mo] V_j b_{2j+1}),
+// and the odd rows follow from x_{2j+1} = V_j (b_{2j+1} + c x_{2j} + c x_{2j+2}).
+// The reduced system is eliminated from both ends towards p = M/2:
+//   top (j < p):      S_j = D_j - c^4 V_{j-1} Q_{j-1} V_{j-1},  P_j = c^2 Q_j V_{j-1},  R_j = c^2 Q_j V_j
+//   bottom (j > p):   S_j = D_j - c^4 V_j Q_{j+1} V_j,          P_j = c^2 Q_j V_j,      R_j = c^2 Q_j V_{j-1}
+//   middle:           S_p = D_p - c^4 V_{p-1} Q_{p-1} V_{p-1} - c^4 V_p Q_{p+1} V_p,
+//                     P_p = c^2 Q_p V_{p-1},  R_p = c^2 Q_p V_p
+// with Q_j = S_j^{-1}, so that the solve is
+//   g_j = Q_j b'_j;  y_j = g_j + P_j y_{j-/+1} (forward from each end);
+//   x_p = g_p + P_p y_{p-1} + R_p y_{p+1};  x_j = y_j + R_j x_{j+/-1} (backward).
+// Factors per instance, complex single, transposed (slot[c][r] = M[r][c]):
+// slots j (Q_j), M + j (P_j), 2M + j (R_j), 3M + j (V_j).
+// ---------------------------------------------------------------------------
+static inline __device__ __host__ int cr_M(int m) { return (m + 1) / 2; }
+static inline __device__ __host__ int cr_Mo(int m) { return m / 2; }
+
+// V_j <- T_{2j+1} (dense FP64; inverted in place afterwards).  Vd: [inst][Mo][m][m],
+// kept for the chain factorisation.  grid: (tiles, Mo, instances)
+__global__ void __launch_bounds__(256) k_cr_tfill(const float2* __restrict__ coef, double2* __restrict__ Vd, int m,
+                                                  double H, double beta) {
+    const int j = blockIdx.y, inst = blockIdx.z, Mo = cr_Mo(m);
+    const size_t mm = (size_t)m * m;
+    double2* V = Vd + ((size_t)inst * Mo + j) * mm;
+    const float2* cf = coef + (size_t)inst * mm + (size_t)(2 * j + 1) * m;
+    const double c = 1.0 / (H * H);
+    const int nt = (m + 31) / 32, ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 32 * ti + ty + 8 * q, col = 32 * tj + tx;
+        if (r < m && col < m) V[(size_t)r * m + col] = tblock_entry(cf, r, col, c, beta);
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Tile-parallel factorisation of the reduced chains.  A chain step (one row j)
+// is a handful of m x m FP64 products and one inversion; each of these is
+// spread over 32 x 32 output tiles, one workgroup per tile, chain and medium,
+// and the step's phases are separate launches:
+//   couple: T = Q_prev V_c                       (V_c: the block coupling j to the previous row)
+//   schur:  A = D_j - c^4 V_c T                  (middle row: both ends' terms)
+//   invert: A <- A^{-1}, blocked Gauss-Jordan over 32-wide panels (below)
+//   store:  slots Q_j, P_j = c^2 Q_j V_c, R_j = c^2 Q_j V_n (complex single, transposed)
+// Q_j stays in one of two FP64 buffers per chain (alternating with the step's
+// parity) for the next step's coupling.
+// Scratch per medium: three chain blocks (top, bottom, middle) of
+// cf_chain_len(m) FP64 complex: A[2] (m x m), T (m x m), C (m x 32), P (32 x 32).
+// ---------------------------------------------------------------------------
+static inline __device__ __host__ size_t cf_chain_len(int m) { return 3 * (size_t)m * m + 32 * (size_t)m + 1024; }
 
 // Chain bookkeeping: chain e = 0 (top) takes rows j = s for steps s < p, chain
 // e = 1 (bottom) rows j = M - 1 - s for s < M - 1 - p; the middle row p is
@@ -484,15 +457,7 @@ __global__ void __launch_bounds__(256) k_cf_schur(const float2* __restrict__ coe
         const int r = 32 * ti + ty + 8 * q, col = 32 * tj + tx;
         if (r >= m || col >= m) continue;
         const size_t o = (size_t)r * m + col;
-        double2 v = make_double2(-c4 * acc[q].x, -c4 * acc[q].y);
-        if (r == col) {
-            const float2 cc = cf[r];
-            const double w2k2 = cc.x, g = cc.y;
-            v.x += 4.0 * c - w2k2;
-            v.y += w2k2 * (g + beta);
-        } else if (col == r - 1 || col == r + 1) {
-            v.x -= c;
-        }
+        double2 v = zadd(make_double2(-c4 * acc[q].x, -c4 * acc[q].y), tblock_entry(cf, r, col, c, beta));
         if (j >= 1) {
             const double2 a = Vi[(size_t)(j - 1) * mm + o];
             v.x -= c2 * a.x;
@@ -661,14 +626,21 @@ static hh_status setup_coarse_reduced(hh_model* md) {
     md->m = m;
     md->cr1 = true;
     HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * 4 * M * mm * sizeof(float2)));
-    Buf Vd, W;
-    const size_t CH = cf_chain_len(m);
+    Buf Vd, W, Sv;
+    const size_t CH = cf_chain_len(m), SL = 32 * (size_t)m + 1024;
     HH_TRY(Vd.ensure(ctx, (size_t)md->ninst * std::max(Mo, 1) * mm * sizeof(double2)));
     HH_TRY(W.ensure(ctx, (size_t)md->ninst * 3 * CH * sizeof(double2)));
     hipStream_t st = ctx->stream;
-    if (Mo > 0) {
-        hipLaunchKernelGGL(k_cr_vinv, dim3(Mo, md->ninst), dim3(1024), 0, st, C.coef.as<float2>(),
-                           Vd.as<double2>(), md->coarseQT.as<float2>(), m, C.h, md->d.sl_beta);
+    if (Mo > 0) {  // V_j = T_{2j+1}^{-1}, all j at once
+        const int nt = (m + 31) / 32, ni = md->ninst;
+        HH_TRY(Sv.ensure(ctx, (size_t)ni * Mo * SL * sizeof(double2)));
+        hipLaunchKernelGGL(k_cr_tfill, dim3(nt * nt, Mo, ni), dim3(256), 0, st, C.coef.as<float2>(),
+                           Vd.as<double2>(), m, C.h, md->d.sl_beta);
+        HH_LAUNCH_CHECK();
+        const BlkInv bv{Vd.as<double2>(), mm, Mo * mm, Sv.as<double2>(), SL, Mo * SL, 0u};
+        HH_TRY(blk_invert(st, bv, Mo, ni, m));
+        hipLaunchKernelGGL(k_tstore, dim3(nt * nt, Mo, ni), dim3(256), 0, st, Vd.as<double2>(), mm, Mo * mm,
+                           md->coarseQT.as<float2>() + 3 * M * mm, (long long)mm, 4 * M * mm, 0u, m);
         HH_LAUNCH_CHECK();
     }
     {
@@ -735,13 +707,32 @@ hh_status setup_coarse_factors(hh_model* md) {
     md->cr1 = false;
     md->cr_depth = 0;
     HH_TRY(md->coarseQT.ensure(ctx, (size_t)md->ninst * m * m * m * sizeof(float2)));
+    const size_t mm = (size_t)m * m, CP = pf_chain_len(m);
     Buf S;
-    HH_TRY(S.ensure(ctx, (size_t)md->ninst * 3 * m * m * sizeof(double2)));
-    hipLaunchKernelGGL(k_coarse_factor_ends, dim3(md->ninst, 2), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
-                       S.as<double2>(), md->coarseQT.as<float2>(), m, p, C.h, md->d.sl_beta);
+    HH_TRY(S.ensure(ctx, (size_t)md->ninst * 3 * CP * sizeof(double2)));
+    hipStream_t st = ctx->stream;
+    const int nt = (m + 31) / 32, ntop = pf_nsteps(m, 0), nbot = pf_nsteps(m, 1), ni = md->ninst;
+    const double beta = md->d.sl_beta;
+    double2* Wd = S.as<double2>();
+    float2* QT = md->coarseQT.as<float2>();
+    for (int s = 0; s < std::max(ntop, nbot); ++s) {  // both chains, one row each per step
+        const unsigned skip = (s >= ntop ? 1u : 0u) | (s >= nbot ? 2u : 0u);
+        hipLaunchKernelGGL(k_pf_schur, dim3(nt * nt, 2, ni), dim3(256), 0, st, C.coef.as<float2>(), Wd, m, C.h, beta,
+                           s, 0);
+        HH_LAUNCH_CHECK();
+        const BlkInv b{Wd + (s & 1) * mm, CP, 3 * CP, Wd + 2 * mm, CP, 3 * CP, skip};
+        HH_TRY(blk_invert(st, b, 2, ni, m));
+        // slots s (top) and m - 1 - s (bottom)
+        hipLaunchKernelGGL(k_tstore, dim3(nt * nt, 2, ni), dim3(256), 0, st, Wd + (s & 1) * mm, CP, 3 * CP,
+                           QT + (size_t)s * mm, (long long)(m - 1 - 2 * s) * (long long)mm, (size_t)m * mm, skip, m);
+        HH_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_pf_schur, dim3(nt * nt, 1, ni), dim3(256), 0, st, C.coef.as<float2>(), Wd, m, C.h, beta, 0, 1);
     HH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_coarse_factor_mid, dim3(md->ninst), dim3(1024), 0, ctx->stream, C.coef.as<float2>(),
-                       S.as<double2>(), md->coarseQT.as<float2>(), m, p, C.h, md->d.sl_beta);
+    const BlkInv bm{Wd + 2 * CP, 0, 3 * CP, Wd + 2 * CP + 2 * mm, 0, 3 * CP, 0u};
+    HH_TRY(blk_invert(st, bm, 1, ni, m));
+    hipLaunchKernelGGL(k_tstore, dim3(nt * nt, 1, ni), dim3(256), 0, st, Wd + 2 * CP, (size_t)0, 3 * CP,
+                       QT + (size_t)p * mm, 0LL, (size_t)m * mm, 0u, m);
     HH_LAUNCH_CHECK();
     // S is released when this function returns: order the free after the kernels.
     HH_HIP(hipStreamSynchronize(ctx->stream));
