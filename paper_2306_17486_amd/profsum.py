@@ -34,6 +34,9 @@ CLASS_OF = [
     ("k_arnoldi_col", "small"), ("k_givens", "small"), ("k_cycle_begin", "small"),
     ("k_residual64", "restart"), ("k_xupdate", "restart"),
     ("k_vc_down", "vc_down"), ("k_vc_up", "vc_up"),
+    # once per medium: coefficients and the coarsest operator's factorisation
+    ("k_coef", "setup"), ("k_blkinv", "setup"), ("k_cf_", "setup"), ("k_pf_", "setup"), ("k_tstore", "setup"),
+    ("k_cr_tfill", "setup"), ("k_cr_level_prod", "setup"),
     ("k_cr_", "vc_coarse"), ("k_coarse", "vc_coarse"), ("k_cg_", "vc_coarse"),
 ]
 
