@@ -97,15 +97,17 @@ EXACT_RHS = (0, 21, 42, 63)
 
 def _exact_worker(args):
     """The oracle's exact discrete solutions x* = A^{-1} b (sparse direct, FP64)
-    of the sampled right-hand sides: one factorisation, one solve per RHS."""
-    n, seed_k, seeds_b, family = args
+    of the sampled right-hand sides: one factorisation, one solve per RHS.
+    omega is the model's own (None: ten points per wavelength at this medium's
+    largest slowness, the single-medium workloads' rule)."""
+    n, seed_k, seeds_b, family, omega = args
     for v in _THREAD_VARS:
         os.environ[v] = "1"
     import numpy as np
     from oracle import helmholtz as H
     from paper_2306_17486_amd import inputs
     k = inputs.slowness(n, seed_k, family)
-    prob = H.Problem(k, inputs.omega_for(n, k))
+    prob = H.Problem(k, inputs.omega_for(n, k) if omega is None else omega)
     B = np.stack([inputs.point_source(n, s) for s in seeds_b])
     t = time.perf_counter()
     X = H.exact_solve(prob, B)
@@ -362,11 +364,15 @@ def _batch_instance(si, i):
 def run_batch(a):
     exact = None
     if not a.no_exact:
+        from paper_2306_17486_amd import inputs  # NumPy only: nothing touches the GPU before the spawn
+
         jobs = []
         for si, i in BATCH_EXACT:
             n = BATCH_SIZES[si][0]
             fam, seed = _batch_instance(si, i)
-            jobs.append((n, seed, [3000 + 1000 * si + q for q in range(4 * i, 4 * i + BATCH_RHS_PER_MODEL)], fam))
+            # the batch's models share one omega per size (the slowness range's maximum)
+            jobs.append((n, seed, [3000 + 1000 * si + q for q in range(4 * i, 4 * i + BATCH_RHS_PER_MODEL)], fam,
+                         inputs.omega_for(n)))
         print("bench batch: spawning the process for the oracle's sparse direct solves (run after the timed solves)",
               file=sys.stderr, flush=True)
         exact = start_exact(jobs)
@@ -487,7 +493,9 @@ GRF_EXACT = 4  # media per size whose solutions are compared with the exact solv
 def run_grf(a):
     exact = None
     if not a.no_exact:
-        jobs = [(n, 1000 + i, [3000 + i], "grf") for n in GRF_SIZES for i in range(GRF_EXACT)]
+        from paper_2306_17486_amd import inputs  # NumPy only: nothing touches the GPU before the spawn
+
+        jobs = [(n, 1000 + i, [3000 + i], "grf", inputs.omega_for(n)) for n in GRF_SIZES for i in range(GRF_EXACT)]
         print("bench grf: spawning the process for the oracle's sparse direct solves (run after the timed solves)",
               file=sys.stderr,
               flush=True)
@@ -697,7 +705,7 @@ def main():
         # process touches the GPU)
         print("bench: spawning the process for the oracle's sparse direct solve of the sampled right-hand sides",
               file=sys.stderr, flush=True)
-        exact = start_exact([(a.n, 2000, [3000 + r for r in EXACT_RHS if r < a.nrhs], "layered")])
+        exact = start_exact([(a.n, 2000, [3000 + r for r in EXACT_RHS if r < a.nrhs], "layered", None)])
 
     import numpy as np
     import torch
