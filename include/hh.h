@@ -91,7 +91,7 @@ typedef struct {
     int coarse_reduce;     /* coarsest exact solve: 1 eliminates the odd grid rows by their
                               tridiagonal inverses first (one level of cyclic reduction) and
                               runs the two-ended block elimination on the even rows (half the
-                              sequential chain, about twice the factor memory); k = 2, 3, 4
+                              sequential chain, about twice the factor memory); k = 2 .. 5
                               (default 4) does the same and runs each elimination chain 2^(k-1)
                               steps at a time with precomputed multi-step factors, the skipped
                               steps following in row-parallel phases (a chain 2^(k-1) times

@@ -165,7 +165,7 @@ hh_status hh_model_create(hh_ctx* ctx, const hh_model_desc* d, int ninst, const 
     HH_ARG((d->n >> (d->levels - 1)) <= 1024, "coarsest grid at most 1024 x 1024");
     HH_ARG(d->omega >= 0.0 && d->abl_width >= 0 && d->sl_beta > 0.0, "omega >= 0, abl_width >= 0, sl_beta > 0");
     HH_ARG(d->coarse_iters >= 0 && d->coarse_iters <= coarse_gmres_max_iters(), "coarse_iters in 0..16");
-    HH_ARG(d->coarse_reduce >= 0 && d->coarse_reduce <= 4, "coarse_reduce in 0..4");
+    HH_ARG(d->coarse_reduce >= 0 && d->coarse_reduce <= 5, "coarse_reduce in 0..5");
     HH_HIP(hipSetDevice(ctx->device));
     hh_model* m = new (std::nothrow) hh_model();
     if (!m) {

@@ -78,7 +78,8 @@ def test_operator_complex_symmetry(hh, ctx):
                                                      (116, "grf", False, 2), (128, "layered", False, 3),
                                                      (116, "grf", True, 3), (100, "grf", False, 4),
                                                      (128, "grf", False, 4), (200, "grf", False, 1),
-                                                     (232, "layered", True, 4)])
+                                                     (232, "layered", True, 4), (128, "grf", False, 5),
+                                                     (232, "layered", True, 5), (512, "grf", True, 5)])
 def test_vcycle_parity(hh, ctx, n, family, with_x0, reduce):
     _say(f"vcycle parity n={n} {family} x0={with_x0} reduced coarse factorisation {reduce}")
     k = inputs.slowness(n, 12, family)
@@ -197,7 +198,7 @@ COARSE_VARIANTS = [(0, 1), (0, 2), (0, 4), (0, 8), (0, 801), (0, 808), (0, 1601)
                    (1, 1001), (1, 1002), (1, 1004), (1, 1008), (1, 10801), (1, 10808), (1, 11602), (1, 13201),
                    (1, 13208), (2, 1001), (2, 1002), (2, 1004), (2, 1008), (2, 10801), (2, 10808), (2, 11602),
                    (2, 13201), (2, 13208), (3, 1001), (3, 1004), (3, 1008), (3, 10808), (3, 13201), (4, 1002),
-                   (4, 1008), (4, 11602)]
+                   (4, 1008), (4, 11602), (5, 1001), (5, 13201)]
 
 
 @pytest.mark.parametrize("reduce,R", COARSE_VARIANTS)
@@ -228,7 +229,8 @@ def test_coarse_group_sizes_vcycle_parity(hh, ctx, reduce, R):
 
 
 @pytest.mark.parametrize("reduce,R", [(1, 1001), (1, 1002), (1, 1004), (2, 1001), (2, 1002), (2, 1004),
-                                     (2, 1008), (2, 13201), (3, 1001), (3, 1002), (3, 13201), (4, 1001)])
+                                     (2, 1008), (2, 13201), (3, 1001), (3, 1002), (3, 13201), (4, 1001),
+                                     (5, 1001), (5, 1004), (5, 13201)])
 def test_coarse_prefetching_chains_vcycle_parity(hh, ctx, reduce, R):
     # a 128 x 128 coarsest grid: the chains with R <= 4 prefetch each step's factor
     # during the previous step (whole chunk pairs of columns per thread)
@@ -260,7 +262,7 @@ def test_coarse_autotuner_and_compaction_in_solves(hh, ctx):
     its_o = [H.solve_mg(prob, b[r])[1] for r in range(7)]
     bad = []
     for reduce, R in ((1, 0), (1, 1001), (1, 1008), (1, 11601), (0, 0), (0, 1), (0, 802), (0, 1608), (2, 0),
-                      (2, 1002), (2, 13201), (3, 0), (3, 1001), (4, 0)):
+                      (2, 1002), (2, 13201), (3, 0), (3, 1001), (4, 0), (5, 0), (5, 1002)):
         m = hh.Model(ctx, torch.from_numpy(k), om, coarse_reduce=reduce)
         m.set_coarse_group(R)
         xd, info = m.solve(_dev(b))
