@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(256) k_cr_tfill(const float2* __restrict__ coe
 // and the step's phases are separate launches:
 //   couple: T = Q_prev V_c                       (V_c: the block coupling j to the previous row)
 //   schur:  A = D_j - c^4 V_c T                  (middle row: both ends' terms)
-//   invert: A <- A^{-1}, blocked Gauss-Jordan over 32-wide panels (below)
+//   invert: A <- A^{-1}, blocked Gauss-Jordan over 32-wide panels (above)
 //   store:  slots Q_j, P_j = c^2 Q_j V_c, R_j = c^2 Q_j V_n (complex single, transposed)
 // Q_j stays in one of two FP64 buffers per chain (alternating with the step's
 // parity) for the next step's coupling.
