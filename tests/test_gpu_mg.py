@@ -79,7 +79,8 @@ def test_operator_complex_symmetry(hh, ctx):
                                                      (116, "grf", True, 3), (100, "grf", False, 4),
                                                      (128, "grf", False, 4), (200, "grf", False, 1),
                                                      (232, "layered", True, 4), (128, "grf", False, 5),
-                                                     (232, "layered", True, 5), (512, "grf", True, 5)])
+                                                     (232, "layered", True, 5), (512, "grf", True, 5),
+                                                     (400, "layered", False, 4), (400, "grf", True, 0)])
 def test_vcycle_parity(hh, ctx, n, family, with_x0, reduce):
     _say(f"vcycle parity n={n} {family} x0={with_x0} reduced coarse factorisation {reduce}")
     k = inputs.slowness(n, 12, family)
