@@ -512,8 +512,9 @@ def conv_force_variant(cin: int, cout: int, mode: int, code: int):
 
 
 def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, flipped: bool, bias=None, skip=None,
-              relu=False, active=None, fill=None, act=None, variant: int = 0):
-    """One convolution through the library's MFMA kernel; returns (y bf16, y fp32).
+              relu=False, active=None, fill=None, act=None, variant: int = 0, fp32_out: bool = True):
+    """One convolution through the library's MFMA kernel; returns (y bf16, y fp32),
+    y fp32 None with fp32_out=False (the FP32 copy not written, as in the network).
     act: 0 none, 1 ReLU, 2 softplus (default: 1 if relu else 0); variant: a
     kernel variant code (0: the autotuned choice).
     active: optional per-batch-entry flags (0 = skipped, output left as filled);
@@ -523,10 +524,11 @@ def conv_test(ctx: Context, x_bf16: torch.Tensor, w: torch.Tensor, mode: int, fl
     Ho = H // 2 if mode == 1 else (2 * H if mode == 2 else H)
     Wo = W_ // 2 if mode == 1 else (2 * W_ if mode == 2 else W_)
     y = torch.empty((B, Ho, Wo, cout), dtype=torch.bfloat16, device=x_bf16.device)
-    yf = torch.empty((B, Ho, Wo, cout), dtype=torch.float32, device=x_bf16.device)
+    yf = torch.empty((B, Ho, Wo, cout), dtype=torch.float32, device=x_bf16.device) if fp32_out else None
     if fill is not None:
         y.fill_(fill)
-        yf.fill_(fill)
+        if yf is not None:
+            yf.fill_(fill)
     # keep every converted tensor referenced until the call returns: the library
     # allocates through torch's caching allocator and could otherwise reuse them
     w = w.to(torch.float32).contiguous()
